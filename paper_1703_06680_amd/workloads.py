@@ -1,0 +1,173 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module only draws numbers: it holds none of the matching arithmetic, and
+it is the one piece of code that both the GPU path's tests/benchmarks and the
+CPU oracle's tests consume.
+
+The experimental setup of the paper (Sec. 5, "Experimental setup") places
+N = n + m extents uniformly on a routing space of length L = 1e6, all of the
+same length l chosen from the overlapping degree alpha = N * l / L, i.e.
+l = alpha * L / N.  Here the same recipe is applied on every axis of a
+d-dimensional routing space [0, L)^d:
+
+* generator: numpy PCG64 seeded with SeedSequence([seed, stream]); stream 0 =
+  updates, 1 = subscriptions, 1000 + i = batched instance i, 2000 + j =
+  serving simulation j;
+* lower corner: float32(U[0,1) * L) per axis, clamped to the largest float32
+  below L;
+* side: l32 = float32(alpha * L / (n + m)) (computed in float64, rounded
+  once);
+* upper corner: hi = lo + l32 in float32 (IEEE round-to-nearest-even), so
+  tiny alpha produces many empty intervals (lo == hi), as float rounding
+  dictates.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+L_SPACE = 1.0e6
+LO_MAX = np.float32(999999.9375)  # largest float32 strictly below 1e6
+
+UPD_STREAM = 0
+SUB_STREAM = 1
+BATCH_STREAM_BASE = 1000
+SIM_STREAM_BASE = 2000
+
+
+def generator(seed: int, stream: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, stream])))
+
+
+def side_length(alpha: float, n_total: int, L: float = L_SPACE) -> np.float32:
+    """l = alpha * L / N, rounded once to float32."""
+    return np.float32(alpha * L / max(n_total, 1))
+
+
+def uniform_regions(rng: np.random.Generator, count: int, d: int, side: np.float32,
+                    L: float = L_SPACE):
+    """``count`` boxes with float32 lower corners uniform on [0, L)^d and all
+    sides equal to ``side``.  Returns (lo, hi), float32 [count, d]."""
+    lo = (rng.random((count, d)) * L).astype(np.float32)
+    np.minimum(lo, np.nextafter(np.float32(L), np.float32(0)), out=lo)
+    hi = (lo + np.float32(side)).astype(np.float32)
+    return lo, hi
+
+
+@dataclass
+class Instance:
+    upd_lo: np.ndarray
+    upd_hi: np.ndarray
+    sub_lo: np.ndarray
+    sub_hi: np.ndarray
+    alpha: float
+    name: str = ""
+
+    @property
+    def n(self):
+        return self.upd_lo.shape[0]
+
+    @property
+    def m(self):
+        return self.sub_lo.shape[0]
+
+    @property
+    def d(self):
+        return self.upd_lo.shape[1]
+
+
+def uniform_instance(n: int, m: int, d: int, alpha: float, seed: int = 0,
+                     upd_stream: int = UPD_STREAM, sub_stream: int = SUB_STREAM,
+                     name: str = "") -> Instance:
+    side = side_length(alpha, n + m)
+    ulo, uhi = uniform_regions(generator(seed, upd_stream), n, d, side)
+    slo, shi = uniform_regions(generator(seed, sub_stream), m, d, side)
+    return Instance(ulo, uhi, slo, shi, alpha, name or f"uniform_d{d}_n{n}_m{m}_a{alpha:g}")
+
+
+# The paper-shaped configurations (d, n = m, alphas).
+CONFIGS = {
+    "cfg1": dict(d=1, n=10_000, alphas=(1.0,)),
+    "cfg2": dict(d=2, n=500_000, alphas=(0.01, 1.0, 100.0)),
+    "cfg3": dict(d=3, n=5_000_000, alphas=(1.0, 10.0, 100.0)),
+}
+
+
+def config_instance(cfg: str, alpha: float | None = None, seed: int = 0) -> Instance:
+    c = CONFIGS[cfg]
+    a = c["alphas"][0] if alpha is None else alpha
+    return uniform_instance(c["n"], c["n"], c["d"], a, seed, name=f"{cfg}_a{a:g}")
+
+
+def correlated_d3(n: int, alpha: float, seed: int = 0) -> Instance:
+    """Stress variant with many true 3-D matches: axis-0 lower corners are
+    uniform as above; on axes 1 and 2 the lower corner is the axis-0 lower
+    corner plus U[0, 2l), in float32."""
+    side = side_length(alpha, 2 * n)
+    out = []
+    for stream in (UPD_STREAM, SUB_STREAM):
+        rng = generator(seed, 100 + stream)
+        lo0 = np.minimum((rng.random(n) * L_SPACE).astype(np.float32), LO_MAX)
+        lo = np.empty((n, 3), dtype=np.float32)
+        lo[:, 0] = lo0
+        for k in (1, 2):
+            lo[:, k] = (lo0 + (rng.random(n) * (2.0 * float(side))).astype(np.float32)).astype(np.float32)
+        hi = (lo + side).astype(np.float32)
+        out.append((lo, hi))
+    (ulo, uhi), (slo, shi) = out
+    return Instance(ulo, uhi, slo, shi, alpha, f"correlated_d3_n{n}_a{alpha:g}")
+
+
+def tie_heavy(n: int, m: int, d: int, grid: int = 12, max_len: int = 4, seed: int = 0) -> Instance:
+    """Small integer-grid boxes: lower corners in {0..grid}, side lengths in
+    {0..max_len}.  Touching, nested, identical and empty intervals are all
+    frequent."""
+    rng = generator(seed, 7)
+    out = []
+    for cnt in (n, m):
+        lo = rng.integers(0, grid + 1, size=(cnt, d)).astype(np.float32)
+        ln = rng.integers(0, max_len + 1, size=(cnt, d)).astype(np.float32)
+        out.append((lo, (lo + ln).astype(np.float32)))
+    (ulo, uhi), (slo, shi) = out
+    return Instance(ulo, uhi, slo, shi, float("nan"), f"ties_d{d}_n{n}_m{m}_g{grid}")
+
+
+def random_float_boxes(n: int, m: int, d: int, seed: int = 0, extent: float = 100.0,
+                       max_side: float = 20.0) -> Instance:
+    """Small boxes with random float corners and random (per-box, per-axis)
+    sides; some sides are forced to zero."""
+    rng = generator(seed, 8)
+    out = []
+    for cnt in (n, m):
+        lo = (rng.random((cnt, d)) * extent).astype(np.float32)
+        side = (rng.random((cnt, d)) * max_side).astype(np.float32)
+        side[rng.random((cnt, d)) < 0.05] = 0
+        out.append((lo, (lo + side).astype(np.float32)))
+    (ulo, uhi), (slo, shi) = out
+    return Instance(ulo, uhi, slo, shi, float("nan"), f"float_d{d}_n{n}_m{m}")
+
+
+def batched_sizes(count: int = 512, lo: int = 1_000, hi: int = 200_000,
+                  alphas=(0.01, 1.0, 10.0), seed: int = 0):
+    """Per-instance (n = m, alpha) for the batched workload: n log-uniform on
+    [lo, hi], alpha a uniform choice from ``alphas``."""
+    rng = generator(seed, BATCH_STREAM_BASE - 1)
+    sizes = np.rint(np.exp(rng.uniform(math.log(lo), math.log(hi), size=count))).astype(np.int64)
+    al = np.asarray(alphas, dtype=np.float64)[rng.integers(0, len(alphas), size=count)]
+    return sizes, al
+
+
+def batched_instances(count: int = 512, d: int = 2, seed: int = 0, lo: int = 1_000,
+                      hi: int = 200_000, alphas=(0.01, 1.0, 10.0)):
+    sizes, al = batched_sizes(count, lo, hi, alphas, seed)
+    insts = []
+    for i in range(count):
+        n = int(sizes[i])
+        side = side_length(float(al[i]), 2 * n)
+        rng = generator(seed, BATCH_STREAM_BASE + i)
+        ulo, uhi = uniform_regions(rng, n, d, side)
+        slo, shi = uniform_regions(rng, n, d, side)
+        insts.append(Instance(ulo, uhi, slo, shi, float(al[i]), f"batch{i}"))
+    return insts
