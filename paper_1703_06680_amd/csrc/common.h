@@ -1,0 +1,104 @@
+// Device-side helpers shared by the libddm kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ddm {
+
+constexpr int kWave = 64;
+// Key of an empty region's lower endpoint: above every encoded coordinate
+// (only a NaN could encode to it, and NaN is rejected).
+constexpr uint32_t kSentinel = 0xFFFFFFFFu;
+
+// Device-detected input errors (bit flags in Header::err).
+constexpr uint32_t kErrNaN = 1u;
+constexpr uint32_t kErrOrder = 2u;
+
+// Small device-resident header at the start of every workspace.
+struct Header {
+  uint32_t err;        // OR of kErr* flags
+  uint32_t nonempty;   // regions that are non-empty on every axis
+  uint32_t kmin;       // min encoded lower key over non-empty regions
+  uint32_t kmax;       // max encoded lower key over non-empty regions
+  unsigned long long total;  // number of intersecting pairs
+  unsigned long long aux[3];
+};
+
+// Order-preserving map of a non-NaN float32 onto uint32: a < b (IEEE)
+// iff enc(a) < enc(b) (unsigned), and enc(-0) == enc(+0).
+__device__ __forceinline__ uint32_t encode_coord(float x) {
+  uint32_t b = __float_as_uint(x);
+  if ((b << 1) == 0u) b = 0u;  // -0.0 -> +0.0
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  return (uint64_t(1) << lane_id()) - 1;
+}
+
+// Sum over the 64 lanes of a wave (result in every lane).
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    T w = __shfl_xor(v, o, kWave);
+    v = w < v ? w : v;
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    T w = __shfl_xor(v, o, kWave);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
+// Inclusive prefix sum over the lanes of a wave.
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T v) {
+  const int lane = lane_id();
+  for (int o = 1; o < kWave; o <<= 1) {
+    T y = __shfl_up(v, o, kWave);
+    if (lane >= o) v += y;
+  }
+  return v;
+}
+
+// Exclusive prefix sum over a block of THREADS threads.  ``lds`` must hold
+// THREADS/64 + 1 elements.  Returns the exclusive prefix of ``v`` and writes
+// the block total to ``*total``.  Contains barriers: every thread must call.
+template <typename T, int THREADS>
+__device__ __forceinline__ T block_exclusive_scan(T v, T *lds, T *total) {
+  constexpr int W = THREADS / kWave;
+  const int w = threadIdx.x / kWave;
+  T x = wave_inclusive_scan(v);
+  if (lane_id() == kWave - 1) lds[w] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T acc = 0;
+    for (int i = 0; i < W; ++i) {
+      T t = lds[i];
+      lds[i] = acc;
+      acc += t;
+    }
+    lds[W] = acc;
+  }
+  __syncthreads();
+  T res = lds[w] + x - v;
+  *total = lds[W];
+  __syncthreads();
+  return res;
+}
+
+}  // namespace ddm

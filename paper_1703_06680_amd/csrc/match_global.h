@@ -1,0 +1,40 @@
+// Launchers of the device-wide sort-based matching kernels
+// (match_global.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace ddm {
+
+struct SweepArgs {
+  const uint32_t *skey;    // sorted lower keys [count]
+  const uint32_t *sidx;    // region index of each sorted lower endpoint
+  const uint32_t *s_khi;   // upper key of each sorted region
+  const float *s_other;    // [2*dm1][stride] other-axis lo/hi in sorted order
+  size_t stride;
+  uint32_t count;          // non-empty regions
+  uint32_t n;              // number of updates (regions < n are updates)
+  int dm1;                 // number of other axes (d - 1)
+  int32_t *per_update;     // mode 1: per-update counts (zeroed beforehand)
+  const unsigned long long *offsets;  // mode 2: first pair slot of each update
+  uint32_t *cursor;        // mode 2: per-update running slot (zeroed)
+  uint32_t *out_u, *out_s; // mode 2: pair staging
+  unsigned long long *total;
+};
+
+void launch_keys(const float *ulo, const float *uhi, uint32_t n, const float *slo,
+                 const float *shi, uint32_t m, int d, int axis, uint32_t *klo, uint32_t *khi,
+                 Header *hdr, hipStream_t s);
+void launch_gather(const uint32_t *sidx, uint32_t count, const uint32_t *khi, const float *ulo,
+                   const float *uhi, uint32_t n, const float *slo, const float *shi, int d,
+                   int axis, uint32_t *s_khi, float *s_other, size_t stride, hipStream_t s);
+void launch_sweep(int mode, const SweepArgs &a, hipStream_t s);
+void launch_interleave(const uint32_t *u, const uint32_t *sidx, int32_t *out, size_t count,
+                       hipStream_t s);
+void launch_widen(const int32_t *in, unsigned long long *out, size_t count, hipStream_t s);
+
+}  // namespace ddm

@@ -1,0 +1,80 @@
+"""The C interface: the built library loads on the host and exports every
+function that include/*.h declares (no compute call is made here)."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1703_06680_amd", "libddm.so")
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w\s\*]*?\b(ddm_\w+)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_1703_06680_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    assert {"ddm_match", "ddm_workspace_bytes", "ddm_strerror"} <= set(names)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_host_only_queries(lib):
+    lib.ddm_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_int64]
+    lib.ddm_workspace_bytes.restype = ctypes.c_size_t
+    assert lib.ddm_workspace_bytes(1000, 1000, 2, 0, 0) > 0
+    assert lib.ddm_workspace_bytes(-1, 10, 2, 0, 0) == 0
+    assert lib.ddm_workspace_bytes(10, 10, 0, 0, 0) == 0
+    assert lib.ddm_workspace_bytes(10, 10, 17, 0, 0) == 0
+    assert lib.ddm_workspace_bytes(10, 10, 2, 7, 0) == 0
+    assert lib.ddm_workspace_bytes(2**30, 2**30, 1, 0, 0) == 0
+    # pair capacity grows the pair workspace only in pair mode
+    assert lib.ddm_workspace_bytes(10, 10, 2, 2, 10**6) > lib.ddm_workspace_bytes(10, 10, 2, 2, 0)
+    assert lib.ddm_workspace_bytes(10, 10, 2, 0, 10**6) == lib.ddm_workspace_bytes(10, 10, 2, 0, 0)
+    lib.ddm_strerror.restype = ctypes.c_char_p
+    assert b"workspace" in lib.ddm_strerror(-3)
+
+
+def test_host_side_argument_errors_return_before_any_launch(lib):
+    """Calls that fail host-side checks never touch the device, so they can
+    run without a GPU."""
+    vp, i64 = ctypes.c_void_p, ctypes.c_int64
+    lib.ddm_match.argtypes = [vp, vp, i64, vp, vp, i64, ctypes.c_int, ctypes.c_int, vp,
+                              ctypes.c_size_t, vp, ctypes.POINTER(ctypes.c_uint64), vp, vp, i64]
+    lib.ddm_match.restype = ctypes.c_int
+    cnt = ctypes.c_uint64(7)
+    fake = ctypes.c_void_p(0x1000)
+    # negative n, bad d, bad mode, missing count pointer, NULL data
+    assert lib.ddm_match(fake, fake, -1, fake, fake, 1, 1, 0, fake, 1 << 30, None, ctypes.byref(cnt), None, None, 0) == -1
+    assert lib.ddm_match(fake, fake, 1, fake, fake, 1, 0, 0, fake, 1 << 30, None, ctypes.byref(cnt), None, None, 0) == -1
+    assert lib.ddm_match(fake, fake, 1, fake, fake, 1, 1, 9, fake, 1 << 30, None, ctypes.byref(cnt), None, None, 0) == -1
+    assert lib.ddm_match(fake, fake, 1, fake, fake, 1, 1, 0, fake, 1 << 30, None, None, None, None, 0) == -1
+    assert lib.ddm_match(None, fake, 1, fake, fake, 1, 1, 0, fake, 1 << 30, None, ctypes.byref(cnt), None, None, 0) == -1
+    # per-update mode without the output, pair mode without the pair buffer
+    assert lib.ddm_match(fake, fake, 1, fake, fake, 1, 1, 1, fake, 1 << 30, None, ctypes.byref(cnt), None, None, 0) == -1
+    assert lib.ddm_match(fake, fake, 1, fake, fake, 1, 1, 2, fake, 1 << 30, None, ctypes.byref(cnt), None, None, 5) == -1
+    # workspace one byte short
+    need = lib.ddm_workspace_bytes(5, 5, 2, 0, 0)
+    assert lib.ddm_match(fake, fake, 5, fake, fake, 5, 2, 0, fake, need - 1, None, ctypes.byref(cnt), None, None, 0) == -3
+    assert lib.ddm_match(fake, fake, 5, fake, fake, 5, 2, 0, None, need, None, ctypes.byref(cnt), None, None, 0) == -3

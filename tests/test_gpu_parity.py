@@ -1,0 +1,212 @@
+"""GPU parity: the HIP path (through the C interface) against the CPU oracle.
+
+Every comparison is exact: counts, per-update counts and the lexicographically
+ordered pair list must be identical element by element.  Inputs come from the
+seeded generators shared with the oracle tests.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1703_06680_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _note(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ddm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1703_06680_amd import ddm as D
+    D.library()
+    return D
+
+
+def _dev(inst):
+    return [torch.from_numpy(np.ascontiguousarray(a)).cuda()
+            for a in (inst.upd_lo, inst.upd_hi, inst.sub_lo, inst.sub_hi)]
+
+
+def _host(inst):
+    return (inst.upd_lo, inst.upd_hi, inst.sub_lo, inst.sub_hi)
+
+
+def check_all_modes(ddm, oracle, inst, pairs=True):
+    _note(f"{inst.name} n={inst.n} m={inst.m} d={inst.d}")
+    g = _dev(inst)
+    k_ref, per_ref, pairs_ref = oracle.sbm(*_host(inst), pairs=pairs)
+    k = ddm.match(*g, mode="count")
+    assert k == k_ref, (inst.name, k, k_ref)
+    k1, per = ddm.match(*g, mode="per_update")
+    assert k1 == k_ref
+    assert np.array_equal(per.cpu().numpy(), per_ref), inst.name
+    if pairs:
+        k2, pr, per2 = ddm.match(*g, mode="pairs")
+        assert k2 == k_ref
+        assert np.array_equal(pr.cpu().numpy(), pairs_ref), inst.name
+        assert np.array_equal(per2.cpu().numpy(), per_ref)
+
+
+def test_worked_example(ddm, oracle):
+    import json, os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "ddm_example_fig.json")))
+    arrs = [torch.tensor(g[k], dtype=torch.float32).cuda() for k in ("upd_lo", "upd_hi", "sub_lo", "sub_hi")]
+    k, pairs, per = ddm.match(*arrs, mode="pairs")
+    assert k == 4 and pairs.cpu().tolist() == g["expected_pairs"]
+    assert per.cpu().tolist() == [2, 2]
+
+
+def test_cfg1_full(ddm, oracle):
+    check_all_modes(ddm, oracle, W.config_instance("cfg1"))
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_tie_heavy_small(ddm, oracle, d):
+    rng = np.random.default_rng(77 + d)
+    for seed in range(40):
+        n, m = int(rng.integers(0, 60)), int(rng.integers(0, 60))
+        inst = W.tie_heavy(n, m, d, grid=int(rng.integers(2, 20)), max_len=int(rng.integers(0, 6)),
+                           seed=seed)
+        check_all_modes(ddm, oracle, inst)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 5])
+def test_random_float_boxes(ddm, oracle, d):
+    for seed in range(6):
+        check_all_modes(ddm, oracle, W.random_float_boxes(700, 900, d, seed=seed, extent=300.0))
+
+
+@pytest.mark.parametrize("d,alpha", [(1, 100.0), (2, 1.0), (3, 100.0)])
+def test_multi_tile_with_ragged_tail(ddm, oracle, d, alpha):
+    # sizes that span many sort tiles and sweep blocks, none a multiple of a tile
+    check_all_modes(ddm, oracle, W.uniform_instance(20_011, 17_389, d, alpha, seed=4))
+
+
+@pytest.mark.parametrize("alpha", [0.01, 1.0, 100.0])
+def test_cfg2_full(ddm, oracle, alpha):
+    """d=2, n = m = 5e5 at every alpha of the configuration."""
+    check_all_modes(ddm, oracle, W.config_instance("cfg2", alpha))
+
+
+@pytest.mark.parametrize("alpha", [1.0, 10.0, 100.0])
+def test_cfg3_full_counts(ddm, oracle, alpha):
+    """d=3, n = m = 5e6: exact total and per-update counts."""
+    inst = W.config_instance("cfg3", alpha)
+    _note(inst.name)
+    g = _dev(inst)
+    k_ref, per_ref, _ = oracle.sbm(*_host(inst), pairs=False)
+    k, per = ddm.match(*g, mode="per_update")
+    assert k == k_ref
+    assert np.array_equal(per.cpu().numpy(), per_ref)
+
+
+@pytest.mark.parametrize("alpha", [1.0, 100.0])
+def test_correlated_d3_stress(ddm, oracle, alpha):
+    """Many true 3-D matches, so per-update counts and pairs are exercised."""
+    inst = W.correlated_d3(400_000, alpha, seed=2)
+    check_all_modes(ddm, oracle, inst)
+
+
+# ------------------------------------------------------------- edge cases
+
+def _t(a, d=1):
+    return torch.tensor(np.asarray(a, dtype=np.float32).reshape(-1, d)).cuda()
+
+
+def test_empty_sets(ddm):
+    _note("empty sets")
+    z = torch.zeros((0, 2), dtype=torch.float32, device="cuda")
+    one = torch.ones((5, 2), dtype=torch.float32, device="cuda")
+    assert ddm.match(z, z, one * 0, one) == 0
+    assert ddm.match(one * 0, one, z, z) == 0
+    k, per = ddm.match(one * 0, one, z, z, mode="per_update")
+    assert k == 0 and per.cpu().tolist() == [0] * 5
+    k, pairs, _ = ddm.match(z, z, z, z, mode="pairs")
+    assert k == 0 and pairs.shape == (0, 2)
+
+
+def test_all_identical_gives_n_times_m(ddm):
+    _note("all identical")
+    lo = torch.full((300, 3), 2.0, device="cuda")
+    hi = torch.full((300, 3), 9.0, device="cuda")
+    slo = torch.full((200, 3), 2.0, device="cuda")
+    shi = torch.full((200, 3), 9.0, device="cuda")
+    k, pairs, per = ddm.match(lo, hi, slo, shi, mode="pairs")
+    assert k == 60_000
+    exp = np.stack(np.meshgrid(np.arange(300), np.arange(200), indexing="ij"), -1).reshape(-1, 2)
+    assert np.array_equal(pairs.cpu().numpy(), exp)
+    assert per.cpu().tolist() == [200] * 300
+
+
+def test_touching_nested_signed_zero_infinity(ddm):
+    _note("touching / nested / signed zero / inf")
+    assert ddm.match(_t([0, 2, 4]), _t([1, 3, 5]), _t([1, 3, 5]), _t([2, 4, 6])) == 0
+    assert ddm.match(_t([2.0]), _t([3.0]), _t([0.0]), _t([10.0])) == 1
+    assert ddm.match(_t([-0.0]), _t([1.0]), _t([0.0]), _t([1.0])) == 1
+    assert ddm.match(_t([-1.0]), _t([-0.0]), _t([0.0]), _t([1.0])) == 0
+    inf = float("inf")
+    assert ddm.match(_t([-inf]), _t([inf]), _t([0.0]), _t([1.0])) == 1
+    assert ddm.match(_t([inf]), _t([inf]), _t([0.0]), _t([inf])) == 0
+    assert ddm.match(_t([5.0]), _t([5.0]), _t([0.0]), _t([10.0])) == 0
+
+
+def test_invalid_input_is_reported(ddm):
+    _note("invalid input")
+    nan = float("nan")
+    for args in ((_t([nan]), _t([1.0]), _t([0.0]), _t([1.0])),
+                 (_t([2.0]), _t([1.0]), _t([0.0]), _t([1.0])),
+                 (_t([[0, 2]], 2), _t([[1, 1]], 2), _t([[0, 0]], 2), _t([[1, 1]], 2))):
+        with pytest.raises(ddm.DDMError) as e:
+            ddm.match(*args)
+        assert e.value.code == ddm.DDM_E_INVAL
+
+
+def test_capacity_retry(ddm, oracle):
+    _note("capacity retry")
+    inst = W.tie_heavy(50, 50, 2, grid=5, seed=1)
+    g = _dev(inst)
+    k_ref, _, pairs_ref = oracle.sbm(*_host(inst))
+    assert k_ref > 10
+    with pytest.raises(ddm.DDMError) as e:
+        ddm.match(*g, mode="pairs", pair_capacity=k_ref - 1)
+    assert e.value.code == ddm.DDM_E_CAPACITY
+    k, pairs, _ = ddm.match(*g, mode="pairs", pair_capacity=k_ref)
+    assert k == k_ref and np.array_equal(pairs.cpu().numpy(), pairs_ref)
+
+
+def test_deterministic_and_permutation_invariant(ddm, oracle):
+    _note("determinism / permutation")
+    inst = W.correlated_d3(50_000, 100.0, seed=5)
+    g = _dev(inst)
+    k1, p1, c1 = ddm.match(*g, mode="pairs")
+    k2, p2, c2 = ddm.match(*g, mode="pairs")
+    assert k1 == k2 and torch.equal(p1, p2) and torch.equal(c1, c2)
+    rng = np.random.default_rng(0)
+    pu, ps = rng.permutation(inst.n), rng.permutation(inst.m)
+    gp = [g[0][pu], g[1][pu], g[2][ps], g[3][ps]]
+    k3, p3, _ = ddm.match(*gp, mode="pairs")
+    assert k3 == k1
+    mapped = np.stack([pu[p3[:, 0].cpu().numpy()], ps[p3[:, 1].cpu().numpy()]], 1)
+    mapped = mapped[np.lexsort((mapped[:, 1], mapped[:, 0]))]
+    assert np.array_equal(mapped, p1.cpu().numpy())
+
+
+def test_role_swap_transposes(ddm):
+    _note("role swap")
+    inst = W.random_float_boxes(2000, 1500, 2, seed=3, extent=200.0)
+    g = _dev(inst)
+    k, p, _ = ddm.match(*g, mode="pairs")
+    k2, p2, _ = ddm.match(g[2], g[3], g[0], g[1], mode="pairs")
+    assert k == k2
+    t = p2.cpu().numpy()[:, ::-1]
+    t = t[np.lexsort((t[:, 1], t[:, 0]))]
+    assert np.array_equal(t, p.cpu().numpy())
