@@ -104,6 +104,23 @@ int ddm_match(const float *upd_lo, const float *upd_hi, int64_t n,
 /* Human-readable text for a DDM_* return code (static storage). */
 const char *ddm_strerror(int code);
 
+/*
+ * Per-phase GPU timing (diagnostic; not part of the method).
+ *
+ * ddm_profile(1) clears the totals and starts recording: every later call of
+ * this library brackets each kernel phase with HIP events on the caller's
+ * stream and, once the call has synchronised, adds the elapsed time of each
+ * phase to a running total.  ddm_profile(0) stops recording.  The recorder is
+ * process-global and not thread-safe; it adds one event record per phase.
+ *
+ * ddm_profile_report() writes the totals as a JSON object
+ * {"phase": {"ms": total_milliseconds, "launches": n}, ...} into buf (host,
+ * len bytes, NUL-terminated).  Returns DDM_OK, or, if buf is NULL or too
+ * small, the number of bytes needed.
+ */
+int ddm_profile(int enable);
+int ddm_profile_report(char *buf, size_t len);
+
 #ifdef __cplusplus
 }
 #endif

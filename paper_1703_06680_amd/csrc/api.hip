@@ -11,6 +11,7 @@
 #include "common.h"
 #include "match_global.h"
 #include "primitives.h"
+#include "profile.h"
 
 namespace ddm {
 namespace {
@@ -19,7 +20,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Byte offsets of every workspace buffer; size 0 means "not used".
 struct Layout {
-  size_t hdr, klo, khi, vals_a, keys_b, vals_b, sort_tmp, s_khi, s_other;
+  size_t hdr, partial, klo, khi, vals_a, keys_b, vals_b, sort_tmp, s_khi, s_other;
   size_t cnt, off, cur, pu, ps, pu2, ps2, scan_tmp, pair_sort_tmp;
   size_t total;
 };
@@ -35,6 +36,7 @@ Layout make_layout(int64_t n, int64_t m, int d, int mode, int64_t cap) {
   const size_t N = (size_t)(n + m);
   const size_t u4 = N * sizeof(uint32_t);
   L.hdr = take(sizeof(Header));
+  L.partial = take(kKeysMaxBlocks * sizeof(uint4));
   L.klo = take(u4);
   L.khi = take(u4);
   L.vals_a = take(u4);
@@ -152,11 +154,14 @@ extern "C" int ddm_match(const float *upd_lo, const float *upd_hi, int64_t n, co
   uint32_t *klo = at<uint32_t>(workspace, L.klo);
   uint32_t *khi = at<uint32_t>(workspace, L.khi);
   const int axis = 0;
-  launch_keys(upd_lo, upd_hi, un, sub_lo, sub_hi, um, d, axis, klo, khi, hdr, s);
+  launch_keys(upd_lo, upd_hi, un, sub_lo, sub_hi, um, d, axis, klo, khi,
+              at<uint4>(workspace, L.partial), hdr, s);
   DDM_HIP(hipGetLastError());
   Header h{};
+  prof::end(s);
   DDM_HIP(hipMemcpyAsync(&h, hdr, sizeof(Header), hipMemcpyDeviceToHost, s));
   DDM_HIP(hipStreamSynchronize(s));
+  prof::flush();
   if (h.err) return DDM_E_INVAL;
   const uint32_t nne = h.nonempty;
   if (nne == 0 || n == 0 || m == 0) return DDM_OK;  // counts already zeroed
@@ -196,8 +201,10 @@ extern "C" int ddm_match(const float *upd_lo, const float *upd_hi, int64_t n, co
   launch_sweep(want_counts ? 1 : 0, a, s);
   DDM_HIP(hipGetLastError());
   unsigned long long K = 0;
+  prof::end(s);
   DDM_HIP(hipMemcpyAsync(&K, &hdr->total, sizeof(K), hipMemcpyDeviceToHost, s));
   DDM_HIP(hipStreamSynchronize(s));
+  prof::flush();
   *count_host = K;
   if (mode != DDM_PAIRS || K == 0) return DDM_OK;
   if ((int64_t)K > pair_capacity) return DDM_E_CAPACITY;
@@ -210,6 +217,7 @@ extern "C" int ddm_match(const float *upd_lo, const float *upd_hi, int64_t n, co
   uint32_t *pu2 = at<uint32_t>(workspace, L.pu2), *ps2 = at<uint32_t>(workspace, L.ps2);
   launch_widen(cnt, off, (size_t)n, s);
   DDM_HIP(exclusive_scan_u64(off, off, (size_t)n, at<void>(workspace, L.scan_tmp), s));
+  prof::mark(s, "pairs.memset");
   DDM_HIP(hipMemsetAsync(cur, 0, (size_t)n * sizeof(uint32_t), s));
   a.offsets = off;
   a.cursor = cur;
@@ -223,6 +231,8 @@ extern "C" int ddm_match(const float *upd_lo, const float *upd_hi, int64_t n, co
                       &ru, &rs));
   launch_interleave(ru, rs, pairs, (size_t)K, s);
   DDM_HIP(hipGetLastError());
+  prof::end(s);
   DDM_HIP(hipStreamSynchronize(s));
+  prof::flush();
   return DDM_OK;
 }

@@ -26,9 +26,13 @@ struct SweepArgs {
   unsigned long long *total;
 };
 
+constexpr unsigned kKeysMaxBlocks = 8192;
+unsigned keys_grid(size_t regions);
+// Validates and encodes; per-block partials (<= kKeysMaxBlocks uint4) are
+// folded into hdr->err / nonempty / kmin / kmax by a one-block kernel.
 void launch_keys(const float *ulo, const float *uhi, uint32_t n, const float *slo,
                  const float *shi, uint32_t m, int d, int axis, uint32_t *klo, uint32_t *khi,
-                 Header *hdr, hipStream_t s);
+                 uint4 *partial, Header *hdr, hipStream_t s);
 void launch_gather(const uint32_t *sidx, uint32_t count, const uint32_t *khi, const float *ulo,
                    const float *uhi, uint32_t n, const float *slo, const float *shi, int d,
                    int axis, uint32_t *s_khi, float *s_other, size_t stride, hipStream_t s);

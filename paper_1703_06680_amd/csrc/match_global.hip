@@ -25,6 +25,7 @@
 // over axes of Sec. 3).
 #include "common.h"
 #include "match_global.h"
+#include "profile.h"
 
 namespace ddm {
 
@@ -35,7 +36,7 @@ constexpr int kThreads = 256;
 __global__ __launch_bounds__(kThreads) void keys_kernel(
     const float *__restrict__ ulo, const float *__restrict__ uhi, uint32_t n,
     const float *__restrict__ slo, const float *__restrict__ shi, uint32_t m, int d, int axis,
-    uint32_t *__restrict__ klo, uint32_t *__restrict__ khi, Header *__restrict__ hdr) {
+    uint32_t *__restrict__ klo, uint32_t *__restrict__ khi, uint4 *__restrict__ partial) {
   __shared__ uint32_t red[4][kThreads / kWave];
   const uint32_t N = n + m;
   uint32_t err = 0, nonempty = 0, kmin = 0xFFFFFFFFu, kmax = 0u;
@@ -85,12 +86,48 @@ __global__ __launch_bounds__(kThreads) void keys_kernel(
       kmin = red[2][i] < kmin ? red[2][i] : kmin;
       kmax = red[3][i] > kmax ? red[3][i] : kmax;
     }
-    if (err) atomicOr(&hdr->err, err);
-    if (nonempty) {
-      atomicAdd(&hdr->nonempty, nonempty);
-      atomicMin(&hdr->kmin, kmin);
-      atomicMax(&hdr->kmax, kmax);
+    partial[blockIdx.x] = make_uint4(err, nonempty, kmin, kmax);
+  }
+}
+
+// One block folds the per-block partials of keys_kernel into the header.
+__global__ __launch_bounds__(kThreads) void keys_finalize_kernel(const uint4 *__restrict__ partial,
+                                                                 unsigned nparts,
+                                                                 Header *__restrict__ hdr) {
+  __shared__ uint32_t red[4][kThreads / kWave];
+  uint32_t err = 0, nonempty = 0, kmin = 0xFFFFFFFFu, kmax = 0u;
+  for (unsigned i = threadIdx.x; i < nparts; i += kThreads) {
+    const uint4 p = partial[i];
+    err |= p.x;
+    nonempty += p.y;
+    if (p.y) {
+      kmin = p.z < kmin ? p.z : kmin;
+      kmax = p.w > kmax ? p.w : kmax;
     }
+  }
+  err = (__ballot(err & kErrNaN) ? kErrNaN : 0u) | (__ballot(err & kErrOrder) ? kErrOrder : 0u);
+  nonempty = wave_sum(nonempty);
+  kmin = wave_min(kmin);
+  kmax = wave_max(kmax);
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == 0) {
+    red[0][w] = err;
+    red[1][w] = nonempty;
+    red[2][w] = kmin;
+    red[3][w] = kmax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < kThreads / kWave; ++i) {
+      err |= red[0][i];
+      nonempty += red[1][i];
+      kmin = red[2][i] < kmin ? red[2][i] : kmin;
+      kmax = red[3][i] > kmax ? red[3][i] : kmax;
+    }
+    hdr->err = err;
+    hdr->nonempty = nonempty;
+    hdr->kmin = kmin;
+    hdr->kmax = kmax;
   }
 }
 
@@ -229,23 +266,30 @@ void launch_sweep(const SweepArgs &a, hipStream_t s) {
 
 }  // namespace
 
+unsigned keys_grid(size_t regions) { return grid_for(regions, kKeysMaxBlocks); }
+
 void launch_keys(const float *ulo, const float *uhi, uint32_t n, const float *slo,
                  const float *shi, uint32_t m, int d, int axis, uint32_t *klo, uint32_t *khi,
-                 Header *hdr, hipStream_t s) {
-  keys_kernel<<<grid_for((size_t)n + m), kThreads, 0, s>>>(ulo, uhi, n, slo, shi, m, d, axis, klo,
-                                                           khi, hdr);
+                 uint4 *partial, Header *hdr, hipStream_t s) {
+  const unsigned grid = keys_grid((size_t)n + m);
+  prof::mark(s, "keys");
+  keys_kernel<<<grid, kThreads, 0, s>>>(ulo, uhi, n, slo, shi, m, d, axis, klo, khi, partial);
+  prof::mark(s, "keys.finalize");
+  keys_finalize_kernel<<<1, kThreads, 0, s>>>(partial, grid, hdr);
 }
 
 void launch_gather(const uint32_t *sidx, uint32_t count, const uint32_t *khi, const float *ulo,
                    const float *uhi, uint32_t n, const float *slo, const float *shi, int d,
                    int axis, uint32_t *s_khi, float *s_other, size_t stride, hipStream_t s) {
   if (!count) return;
+  prof::mark(s, "gather");
   gather_kernel<<<grid_for(count), kThreads, 0, s>>>(sidx, count, khi, ulo, uhi, n, slo, shi, d,
                                                      axis, s_khi, s_other, stride);
 }
 
 void launch_sweep(int mode, const SweepArgs &a, hipStream_t s) {
   if (!a.count) return;
+  prof::mark(s, mode == 2 ? "sweep.emit" : "sweep.count");
   if (mode == 0)
     launch_sweep<0>(a, s);
   else if (mode == 1)
@@ -257,11 +301,13 @@ void launch_sweep(int mode, const SweepArgs &a, hipStream_t s) {
 void launch_interleave(const uint32_t *u, const uint32_t *sidx, int32_t *out, size_t count,
                        hipStream_t s) {
   if (!count) return;
+  prof::mark(s, "pairs.interleave");
   interleave_kernel<<<grid_for(count), kThreads, 0, s>>>(u, sidx, out, count);
 }
 
 void launch_widen(const int32_t *in, unsigned long long *out, size_t count, hipStream_t s) {
   if (!count) return;
+  prof::mark(s, "pairs.widen");
   widen_kernel<<<grid_for(count), kThreads, 0, s>>>(in, out, count);
 }
 

@@ -12,6 +12,7 @@
 // and tiles follow input order within a digit, so every pass is stable.
 #include "common.h"
 #include "primitives.h"
+#include "profile.h"
 
 namespace ddm {
 
@@ -102,6 +103,7 @@ hipError_t exclusive_scan_impl(const T *in, T *out, size_t count, void *temp, hi
   if (count == 0) return hipSuccess;
   size_t nb = div_up(count, kScanChunk);
   T *sums = static_cast<T *>(temp);
+  prof::mark(s, "scan");
   scan_reduce_kernel<T><<<dim3((unsigned)nb), dim3(kScanThreads), 0, s>>>(in, count, sums);
   scan_block_sums_kernel<T><<<dim3(1), dim3(kScanThreads), 0, s>>>(sums, nb);
   scan_apply_kernel<T><<<dim3((unsigned)nb), dim3(kScanThreads), 0, s>>>(in, out, count, sums);
@@ -232,6 +234,7 @@ hipError_t radix_sort_pairs(uint32_t *keys_a, uint32_t *vals_a, uint32_t *keys_b
   if (count == 0) return hipSuccess;
   const int passes = (bits + kRadixBits - 1) / kRadixBits;
   if (passes == 0) {
+    prof::mark(s, "sort.iota");
     if (vals_iota) iota_kernel<<<dim3(1024), dim3(256), 0, s>>>(vals_a, count);
     return hipGetLastError();
   }
@@ -243,10 +246,12 @@ hipError_t radix_sort_pairs(uint32_t *keys_a, uint32_t *vals_a, uint32_t *keys_b
   bool iota = vals_iota;
   for (int p = 0; p < passes; ++p) {
     const int shift = p * kRadixBits;
+    prof::mark(s, "sort.upsweep");
     radix_upsweep_kernel<<<dim3(ntiles), dim3(kSortThreads), 0, s>>>(ck, count, xf, shift, counts,
                                                                      ntiles);
     hipError_t e = exclusive_scan_u32(counts, counts, hist, scan_tmp, s);
     if (e != hipSuccess) return e;
+    prof::mark(s, "sort.downsweep");
     if (iota)
       radix_downsweep_kernel<true><<<dim3(ntiles), dim3(kSortThreads), 0, s>>>(
           ck, cv, ok, ov, count, xf, shift, counts, ntiles);

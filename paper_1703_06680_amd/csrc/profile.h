@@ -1,0 +1,24 @@
+// Optional per-phase GPU timing with HIP events (diagnostic).
+//
+// When enabled, every launch site calls mark(stream, "phase") just before it
+// enqueues work; consecutive marks on a stream delimit one phase, whose
+// duration (hipEventElapsedTime between the two events) is added to the
+// phase's running total once the call has synchronised.  Disabled, mark() is
+// a branch.  The recorder is process-global and not thread-safe: profile from
+// one host thread.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+namespace ddm {
+namespace prof {
+
+bool enabled();
+void mark(hipStream_t s, const char *phase);
+void end(hipStream_t s);
+// Resolve the recorded events (the stream must have been synchronised).
+void flush();
+
+}  // namespace prof
+}  // namespace ddm

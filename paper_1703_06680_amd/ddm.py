@@ -53,6 +53,10 @@ def library() -> ctypes.CDLL:
         lib.ddm_match.restype = ctypes.c_int
         lib.ddm_strerror.argtypes = [ctypes.c_int]
         lib.ddm_strerror.restype = ctypes.c_char_p
+        lib.ddm_profile.argtypes = [ctypes.c_int]
+        lib.ddm_profile.restype = ctypes.c_int
+        lib.ddm_profile_report.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+        lib.ddm_profile_report.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -62,6 +66,44 @@ def strerror(code: int) -> str:
         return library().ddm_strerror(code).decode()
     except Exception:  # library missing: still produce a message
         return "unknown"
+
+
+def profile(enable: bool) -> None:
+    """Start (clearing the totals) or stop per-phase GPU timing."""
+    library().ddm_profile(1 if enable else 0)
+
+
+def profile_report() -> dict:
+    """Per-phase totals recorded since profile(True): {phase: {"ms", "launches"}}."""
+    import json
+    lib = library()
+    need = lib.ddm_profile_report(None, 0)
+    buf = ctypes.create_string_buffer(max(need, 2) + 64)
+    rc = lib.ddm_profile_report(buf, len(buf))
+    if rc != DDM_OK:
+        raise DDMError(rc, "ddm_profile_report")
+    return json.loads(buf.value.decode())
+
+
+def match_into(upd_lo, upd_hi, sub_lo, sub_hi, mode: str, workspace: torch.Tensor,
+               per_update: torch.Tensor | None = None, pairs: torch.Tensor | None = None,
+               stream=None) -> int:
+    """Low-level call with caller-provided workspace and outputs (no
+    allocation); returns the number of pairs, raises DDMError on failure."""
+    n, d = upd_lo.shape
+    m = sub_lo.shape[0]
+    if stream is None:
+        stream = torch.cuda.current_stream(upd_lo.device)
+    cnt = ctypes.c_uint64(0)
+    cap = pairs.shape[0] if pairs is not None else 0
+    rc = library().ddm_match(_ptr(upd_lo), _ptr(upd_hi), n, _ptr(sub_lo), _ptr(sub_hi), m, d,
+                             MODES[mode], ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                             ctypes.c_void_p(stream.cuda_stream), ctypes.byref(cnt),
+                             _ptr(per_update) if per_update is not None else None,
+                             _ptr(pairs) if pairs is not None else None, cap)
+    if rc != DDM_OK:
+        raise DDMError(rc)
+    return int(cnt.value)
 
 
 def workspace_bytes(n: int, m: int, d: int, mode: str = "count", pair_capacity: int = 0) -> int:
