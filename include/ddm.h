@@ -105,6 +105,32 @@ int ddm_match(const float *upd_lo, const float *upd_hi, int64_t n,
 const char *ddm_strerror(int code);
 
 /*
+ * Implementation selection (process-global, for tests and benchmarks).
+ * Both implementations compute the same result (the pairs of Sec. 3, swept
+ * as in Algorithm 4):
+ *   DDM_PATH_BUCKETED  regions are partitioned by their axis-0 lower
+ *                      coordinate into buckets (consecutive segments of the
+ *                      sorted endpoint list, as in Algorithm 5); each bucket
+ *                      is sorted and swept in on-chip memory, starting from
+ *                      the regions of earlier buckets still active at its
+ *                      start (the boundary state of Algorithm 6); available
+ *                      for d <= 3;
+ *   DDM_PATH_GLOBAL    a device-wide sort of the lower endpoints and a sweep
+ *                      over device memory; any d.
+ * DDM_PATH_AUTO (default) uses the bucketed path where available and falls
+ * back to the global one when a bucket or the boundary state does not fit.
+ * A forced DDM_PATH_BUCKETED call returns DDM_E_UNSUPPORTED instead of
+ * falling back.  ddm_set_path() returns DDM_E_INVAL for an unknown value;
+ * ddm_last_path() reports the path that produced the last successful result
+ * of ddm_match() on any thread (0 if none).
+ */
+#define DDM_PATH_AUTO 0
+#define DDM_PATH_BUCKETED 1
+#define DDM_PATH_GLOBAL 2
+int ddm_set_path(int path);
+int ddm_last_path(void);
+
+/*
  * Per-phase GPU timing (diagnostic; not part of the method).
  *
  * ddm_profile(1) clears the totals and starts recording: every later call of

@@ -1,13 +1,20 @@
 // C interface of libddm (declared in include/ddm.h).
 //
-// ddm_match() enqueues the whole matching pipeline on the caller's stream and
-// synchronises once to learn how many regions are non-empty and the key range
-// (which fixes the number of radix passes), and once more at the end to return
-// the total; in pair mode it also synchronises after the counting sweep to
-// size the pair list.
+// Two implementations of the same matching sit behind ddm_match():
+//   - the bucketed path (bucket_path.hip): regions are partitioned by their
+//     swept-axis lower coordinate into buckets that are sorted and swept in
+//     LDS, with each bucket's boundary state delivered from the earlier ones;
+//     used when d <= 3 and the bucket count fits, and every bucket and the
+//     boundary state fit their buffers;
+//   - the device-wide path (match_global.hip): a global radix sort of the
+//     lower keys, a gather of the other axes into sorted order and a forward
+//     sweep over device memory; it has no size limit beyond 2^31 regions and
+//     is the fallback when a bucket overflows.
+// Both produce identical results; ddm_set_path() can force one of them.
 #include <string.h>
 
 #include "../../include/ddm.h"
+#include "bucket_path.h"
 #include "common.h"
 #include "match_global.h"
 #include "primitives.h"
@@ -18,10 +25,19 @@ namespace {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Byte offsets of every workspace buffer; size 0 means "not used".
+int g_path_request = DDM_PATH_AUTO;
+int g_last_path = 0;
+
+// Byte offsets of every workspace buffer.  The buffers of the two paths share
+// one region (only one path runs at a time).
 struct Layout {
-  size_t hdr, partial, klo, khi, vals_a, keys_b, vals_b, sort_tmp, s_khi, s_other;
-  size_t cnt, off, cur, pu, ps, pu2, ps2, scan_tmp, pair_sort_tmp;
+  size_t hdr, partial;
+  size_t cnt, off, cur, pu, ps, pu2, ps2, scan_tmp, pair_sort_tmp;  // pair mode
+  size_t region;
+  // device-wide path, relative to region
+  size_t klo, khi, vals_a, keys_b, vals_b, sort_tmp, s_khi, s_other, global_bytes;
+  bool bucket_ok;
+  BucketLayout B;
   size_t total;
 };
 
@@ -33,18 +49,8 @@ Layout make_layout(int64_t n, int64_t m, int d, int mode, int64_t cap) {
     at += align256(bytes);
     return o;
   };
-  const size_t N = (size_t)(n + m);
-  const size_t u4 = N * sizeof(uint32_t);
   L.hdr = take(sizeof(Header));
   L.partial = take(kKeysMaxBlocks * sizeof(uint4));
-  L.klo = take(u4);
-  L.khi = take(u4);
-  L.vals_a = take(u4);
-  L.keys_b = take(u4);
-  L.vals_b = take(u4);
-  L.sort_tmp = take(radix_sort_temp_bytes((uint32_t)N));
-  L.s_khi = take(u4);
-  L.s_other = take((size_t)2 * (d - 1) * u4);
   if (mode == DDM_PAIRS) {
     const size_t c = (size_t)(cap > 0 ? cap : 0);
     L.cnt = take((size_t)n * sizeof(int32_t));
@@ -57,7 +63,33 @@ Layout make_layout(int64_t n, int64_t m, int d, int mode, int64_t cap) {
     L.scan_tmp = take(scan_temp_bytes((size_t)n));
     L.pair_sort_tmp = take(radix_sort_temp_bytes((uint32_t)(c ? c : 1)));
   }
-  L.total = at;
+  L.region = at;
+  // device-wide path
+  size_t g = 0;
+  auto gtake = [&](size_t bytes) {
+    size_t o = g;
+    g += align256(bytes);
+    return o;
+  };
+  const size_t N = (size_t)(n + m);
+  const size_t u4 = N * sizeof(uint32_t);
+  L.klo = gtake(u4);
+  L.khi = gtake(u4);
+  L.vals_a = gtake(u4);
+  L.keys_b = gtake(u4);
+  L.vals_b = gtake(u4);
+  L.sort_tmp = gtake(radix_sort_temp_bytes((uint32_t)N));
+  L.s_khi = gtake(u4);
+  L.s_other = gtake((size_t)2 * (d - 1) * u4);
+  L.global_bytes = g;
+  // bucketed path
+  L.bucket_ok = bucket_path_supported(d, n, m);
+  size_t region_bytes = g;
+  if (L.bucket_ok) {
+    L.B = bucket_layout(n, m, d);
+    if (L.B.bytes > region_bytes) region_bytes = L.B.bytes;
+  }
+  L.total = L.region + align256(region_bytes);
   return L;
 }
 
@@ -71,10 +103,12 @@ bool sizes_ok(int64_t n, int64_t m, int d, int mode) {
 
 int bit_length(uint32_t x) { return x ? 32 - __builtin_clz(x) : 0; }
 
-#define DDM_HIP(call)                          \
-  do {                                         \
+#define DDM_HIP(call)                              \
+  do {                                             \
     if ((call) != hipSuccess) return DDM_E_DEVICE; \
   } while (0)
+
+constexpr int kFallback = 1;  // internal: the bucketed path asks for the other one
 
 template <typename T>
 T *at(void *ws, size_t off) {
@@ -101,6 +135,168 @@ hipError_t order_pairs(uint32_t *pu, uint32_t *ps, uint32_t *pu2, uint32_t *ps2,
   return hipSuccess;
 }
 
+struct Call {
+  const float *ulo, *uhi, *slo, *shi;
+  int64_t n, m;
+  int d, mode;
+  void *ws;
+  Layout L;
+  hipStream_t s;
+  uint64_t *count_host;
+  int32_t *per_update;
+  int32_t *pairs;
+  int64_t cap;
+  Header *hdr;
+  int32_t *cnt;  // per-update counts (caller's or workspace), pair/per-update modes
+};
+
+int reset_outputs(const Call &c) {
+  DDM_HIP(hipMemsetAsync(c.hdr, 0, sizeof(Header), c.s));
+  DDM_HIP(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(&c.hdr->kmin), 0xFFFFFFFFu, 1, c.s));
+  if (c.mode != DDM_COUNT && c.n > 0)
+    DDM_HIP(hipMemsetAsync(c.cnt, 0, (size_t)c.n * sizeof(int32_t), c.s));
+  return DDM_OK;
+}
+
+// Pair list from per-update counts already in c.cnt and K pairs: offsets,
+// the emitting sweep (``emit``), lexicographic ordering into c.pairs.
+template <typename Emit>
+int finish_pairs(const Call &c, unsigned long long K, Emit emit) {
+  if ((int64_t)K > c.cap) return DDM_E_CAPACITY;
+  if (K >= (1ull << 32)) return DDM_E_UNSUPPORTED;  // pair staging uses 32-bit positions
+  const Layout &L = c.L;
+  unsigned long long *off = at<unsigned long long>(c.ws, L.off);
+  uint32_t *cur = at<uint32_t>(c.ws, L.cur);
+  uint32_t *pu = at<uint32_t>(c.ws, L.pu), *ps = at<uint32_t>(c.ws, L.ps);
+  uint32_t *pu2 = at<uint32_t>(c.ws, L.pu2), *ps2 = at<uint32_t>(c.ws, L.ps2);
+  launch_widen(c.cnt, off, (size_t)c.n, c.s);
+  DDM_HIP(exclusive_scan_u64(off, off, (size_t)c.n, at<void>(c.ws, L.scan_tmp), c.s));
+  prof::mark(c.s, "pairs.memset");
+  DDM_HIP(hipMemsetAsync(cur, 0, (size_t)c.n * sizeof(uint32_t), c.s));
+  DDM_HIP(emit(off, cur, pu, ps));
+  uint32_t *ru = nullptr, *rs = nullptr;
+  DDM_HIP(order_pairs(pu, ps, pu2, ps2, (uint32_t)K, c.n, c.m, at<void>(c.ws, L.pair_sort_tmp),
+                      c.s, &ru, &rs));
+  launch_interleave(ru, rs, c.pairs, (size_t)K, c.s);
+  DDM_HIP(hipGetLastError());
+  prof::end(c.s);
+  DDM_HIP(hipStreamSynchronize(c.s));
+  prof::flush();
+  return DDM_OK;
+}
+
+// ------------------------------------------------------- bucketed path
+int run_bucketed(const Call &c) {
+  BucketArgs a{};
+  a.ulo = c.ulo;
+  a.uhi = c.uhi;
+  a.slo = c.slo;
+  a.shi = c.shi;
+  a.n = (uint32_t)c.n;
+  a.m = (uint32_t)c.m;
+  a.d = c.d;
+  a.ws = at<void>(c.ws, c.L.region);
+  a.L = c.L.B;
+  a.hdr = c.hdr;
+  int rc = reset_outputs(c);
+  if (rc != DDM_OK) return rc;
+  DDM_HIP(bucket_prepare(a, c.s));
+  const int count_mode = c.mode == DDM_COUNT ? 0 : 1;
+  DDM_HIP(bucket_sweep(a, count_mode, c.cnt, nullptr, nullptr, nullptr, nullptr, &c.hdr->total,
+                       c.s));
+  Header h{};
+  prof::end(c.s);
+  DDM_HIP(hipMemcpyAsync(&h, c.hdr, sizeof(Header), hipMemcpyDeviceToHost, c.s));
+  DDM_HIP(hipStreamSynchronize(c.s));
+  prof::flush();
+  if (h.err) return DDM_E_INVAL;
+  if (h.overflow || h.pad[0]) return kFallback;
+  *c.count_host = h.total;
+  if (c.mode != DDM_PAIRS || h.total == 0) return DDM_OK;
+  return finish_pairs(c, h.total, [&](unsigned long long *off, uint32_t *cur, uint32_t *pu,
+                                      uint32_t *ps) {
+    return bucket_sweep(a, 2, nullptr, off, cur, pu, ps, &c.hdr->aux[0], c.s);
+  });
+}
+
+// ---------------------------------------------------- device-wide path
+int run_global(const Call &c) {
+  const Layout &L = c.L;
+  const uint32_t un = (uint32_t)c.n, um = (uint32_t)c.m, N = un + um;
+  void *R = at<void>(c.ws, L.region);
+  int rc = reset_outputs(c);
+  if (rc != DDM_OK) return rc;
+
+  // 1. validate, encode, empties
+  uint32_t *klo = at<uint32_t>(R, L.klo);
+  uint32_t *khi = at<uint32_t>(R, L.khi);
+  const int axis = 0;
+  launch_keys(c.ulo, c.uhi, un, c.slo, c.shi, um, c.d, axis, klo, khi,
+              at<uint4>(c.ws, L.partial), c.hdr, c.s);
+  DDM_HIP(hipGetLastError());
+  Header h{};
+  prof::end(c.s);
+  DDM_HIP(hipMemcpyAsync(&h, c.hdr, sizeof(Header), hipMemcpyDeviceToHost, c.s));
+  DDM_HIP(hipStreamSynchronize(c.s));
+  prof::flush();
+  if (h.err) return DDM_E_INVAL;
+  const uint32_t nne = h.nonempty;
+  if (nne == 0 || c.n == 0 || c.m == 0) return DDM_OK;  // counts already zeroed
+
+  // 2. radix sort of the lower keys (range-reduced; empties last)
+  const bool has_empty = nne < N;
+  const uint32_t range = h.kmax - h.kmin;
+  KeyTransform xf{1u, h.kmin, range + 1u};
+  const int bits = bit_length(has_empty ? range + 1u : range);
+  uint32_t *vals_a = at<uint32_t>(R, L.vals_a);
+  uint32_t *keys_b = at<uint32_t>(R, L.keys_b);
+  uint32_t *vals_b = at<uint32_t>(R, L.vals_b);
+  int in_b = 0;
+  DDM_HIP(radix_sort_pairs(klo, vals_a, keys_b, vals_b, N, bits, true, xf,
+                           at<void>(R, L.sort_tmp), c.s, &in_b));
+  const uint32_t *skey = in_b ? keys_b : klo;
+  const uint32_t *sidx = in_b ? vals_b : vals_a;
+
+  // 3. other axes in sorted order
+  uint32_t *s_khi = at<uint32_t>(R, L.s_khi);
+  float *s_other = at<float>(R, L.s_other);
+  launch_gather(sidx, nne, khi, c.ulo, c.uhi, un, c.slo, c.shi, c.d, axis, s_khi, s_other, N, c.s);
+  DDM_HIP(hipGetLastError());
+
+  // 4. the sweep
+  SweepArgs a{};
+  a.skey = skey;
+  a.sidx = sidx;
+  a.s_khi = s_khi;
+  a.s_other = s_other;
+  a.stride = N;
+  a.count = nne;
+  a.n = un;
+  a.dm1 = c.d - 1;
+  a.per_update = c.cnt;
+  a.total = &c.hdr->total;
+  launch_sweep(c.mode != DDM_COUNT ? 1 : 0, a, c.s);
+  DDM_HIP(hipGetLastError());
+  unsigned long long K = 0;
+  prof::end(c.s);
+  DDM_HIP(hipMemcpyAsync(&K, &c.hdr->total, sizeof(K), hipMemcpyDeviceToHost, c.s));
+  DDM_HIP(hipStreamSynchronize(c.s));
+  prof::flush();
+  *c.count_host = K;
+  if (c.mode != DDM_PAIRS || K == 0) return DDM_OK;
+  return finish_pairs(c, K, [&](unsigned long long *off, uint32_t *cur, uint32_t *pu,
+                                uint32_t *ps) {
+    SweepArgs e = a;
+    e.offsets = off;
+    e.cursor = cur;
+    e.out_u = pu;
+    e.out_s = ps;
+    e.total = &c.hdr->aux[0];
+    launch_sweep(2, e, c.s);
+    return hipGetLastError();
+  });
+}
+
 }  // namespace
 }  // namespace ddm
 
@@ -124,115 +320,63 @@ extern "C" const char *ddm_strerror(int code) {
   }
 }
 
+extern "C" int ddm_set_path(int path) {
+  if (path != DDM_PATH_AUTO && path != DDM_PATH_BUCKETED && path != DDM_PATH_GLOBAL)
+    return DDM_E_INVAL;
+  g_path_request = path;
+  return DDM_OK;
+}
+
+extern "C" int ddm_last_path(void) { return g_last_path; }
+
 extern "C" int ddm_match(const float *upd_lo, const float *upd_hi, int64_t n, const float *sub_lo,
                          const float *sub_hi, int64_t m, int d, int mode, void *workspace,
                          size_t ws_bytes, void *stream, uint64_t *count_host, int32_t *per_update,
                          int32_t *pairs, int64_t pair_capacity) {
-  // ---------------------------------------------------- host-side checks
+  // host-side checks: nothing is launched when one fails
   if (!sizes_ok(n, m, d, mode) || !count_host || pair_capacity < 0) return DDM_E_INVAL;
   if ((n > 0 && (!upd_lo || !upd_hi)) || (m > 0 && (!sub_lo || !sub_hi))) return DDM_E_INVAL;
   if (mode == DDM_PER_UPDATE && n > 0 && !per_update) return DDM_E_INVAL;
   if (mode == DDM_PAIRS && pair_capacity > 0 && !pairs) return DDM_E_INVAL;
-  const Layout L = make_layout(n, m, d, mode, pair_capacity);
-  if (!workspace || ws_bytes < L.total) return DDM_E_WORKSPACE;
+  Call c{};
+  c.L = make_layout(n, m, d, mode, pair_capacity);
+  if (!workspace || ws_bytes < c.L.total) return DDM_E_WORKSPACE;
   if (reinterpret_cast<uintptr_t>(workspace) & 255) return DDM_E_INVAL;
   *count_host = 0;
-
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const uint32_t un = (uint32_t)n, um = (uint32_t)m, N = un + um;
-  Header *hdr = at<Header>(workspace, L.hdr);
-  int32_t *cnt = mode == DDM_PAIRS ? (per_update ? per_update : at<int32_t>(workspace, L.cnt))
-                                   : per_update;
-  const bool want_counts = mode != DDM_COUNT;
-
-  DDM_HIP(hipMemsetAsync(hdr, 0, sizeof(Header), s));
-  DDM_HIP(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(&hdr->kmin), 0xFFFFFFFFu, 1, s));
-  if (want_counts && n > 0) DDM_HIP(hipMemsetAsync(cnt, 0, (size_t)n * sizeof(int32_t), s));
-  if (N == 0) return DDM_OK;
-
-  // ---------------------------------------- 1. validate, encode, empties
-  uint32_t *klo = at<uint32_t>(workspace, L.klo);
-  uint32_t *khi = at<uint32_t>(workspace, L.khi);
-  const int axis = 0;
-  launch_keys(upd_lo, upd_hi, un, sub_lo, sub_hi, um, d, axis, klo, khi,
-              at<uint4>(workspace, L.partial), hdr, s);
-  DDM_HIP(hipGetLastError());
-  Header h{};
-  prof::end(s);
-  DDM_HIP(hipMemcpyAsync(&h, hdr, sizeof(Header), hipMemcpyDeviceToHost, s));
-  DDM_HIP(hipStreamSynchronize(s));
-  prof::flush();
-  if (h.err) return DDM_E_INVAL;
-  const uint32_t nne = h.nonempty;
-  if (nne == 0 || n == 0 || m == 0) return DDM_OK;  // counts already zeroed
-
-  // ---------------------------------------------------- 2. radix sort
-  const bool has_empty = nne < N;
-  const uint32_t range = h.kmax - h.kmin;
-  KeyTransform xf{1u, h.kmin, range + 1u};
-  const int bits = bit_length(has_empty ? range + 1u : range);
-  uint32_t *vals_a = at<uint32_t>(workspace, L.vals_a);
-  uint32_t *keys_b = at<uint32_t>(workspace, L.keys_b);
-  uint32_t *vals_b = at<uint32_t>(workspace, L.vals_b);
-  int in_b = 0;
-  DDM_HIP(radix_sort_pairs(klo, vals_a, keys_b, vals_b, N, bits, true, xf,
-                           at<void>(workspace, L.sort_tmp), s, &in_b));
-  const uint32_t *skey = in_b ? keys_b : klo;
-  const uint32_t *sidx = in_b ? vals_b : vals_a;
-
-  // --------------------------------------- 3. other axes in sorted order
-  uint32_t *s_khi = at<uint32_t>(workspace, L.s_khi);
-  float *s_other = at<float>(workspace, L.s_other);
-  launch_gather(sidx, nne, khi, upd_lo, upd_hi, un, sub_lo, sub_hi, d, axis, s_khi, s_other, N, s);
-  DDM_HIP(hipGetLastError());
-
-  // ------------------------------------------------------- 4. the sweep
-  SweepArgs a{};
-  a.skey = skey;
-  a.sidx = sidx;
-  a.s_khi = s_khi;
-  a.s_other = s_other;
-  a.stride = N;
-  a.count = nne;
-  a.n = un;
-  a.dm1 = d - 1;
-  a.per_update = cnt;
-  a.total = &hdr->total;
-  launch_sweep(want_counts ? 1 : 0, a, s);
-  DDM_HIP(hipGetLastError());
-  unsigned long long K = 0;
-  prof::end(s);
-  DDM_HIP(hipMemcpyAsync(&K, &hdr->total, sizeof(K), hipMemcpyDeviceToHost, s));
-  DDM_HIP(hipStreamSynchronize(s));
-  prof::flush();
-  *count_host = K;
-  if (mode != DDM_PAIRS || K == 0) return DDM_OK;
-  if ((int64_t)K > pair_capacity) return DDM_E_CAPACITY;
-  if (K >= (1ull << 32)) return DDM_E_UNSUPPORTED;  // pair staging uses 32-bit positions
-
-  // -------------------------------------- 5. pairs: two-pass compaction
-  unsigned long long *off = at<unsigned long long>(workspace, L.off);
-  uint32_t *cur = at<uint32_t>(workspace, L.cur);
-  uint32_t *pu = at<uint32_t>(workspace, L.pu), *ps = at<uint32_t>(workspace, L.ps);
-  uint32_t *pu2 = at<uint32_t>(workspace, L.pu2), *ps2 = at<uint32_t>(workspace, L.ps2);
-  launch_widen(cnt, off, (size_t)n, s);
-  DDM_HIP(exclusive_scan_u64(off, off, (size_t)n, at<void>(workspace, L.scan_tmp), s));
-  prof::mark(s, "pairs.memset");
-  DDM_HIP(hipMemsetAsync(cur, 0, (size_t)n * sizeof(uint32_t), s));
-  a.offsets = off;
-  a.cursor = cur;
-  a.out_u = pu;
-  a.out_s = ps;
-  a.total = &hdr->aux[0];
-  launch_sweep(2, a, s);
-  DDM_HIP(hipGetLastError());
-  uint32_t *ru = nullptr, *rs = nullptr;
-  DDM_HIP(order_pairs(pu, ps, pu2, ps2, (uint32_t)K, n, m, at<void>(workspace, L.pair_sort_tmp), s,
-                      &ru, &rs));
-  launch_interleave(ru, rs, pairs, (size_t)K, s);
-  DDM_HIP(hipGetLastError());
-  prof::end(s);
-  DDM_HIP(hipStreamSynchronize(s));
-  prof::flush();
-  return DDM_OK;
+  c.ulo = upd_lo;
+  c.uhi = upd_hi;
+  c.slo = sub_lo;
+  c.shi = sub_hi;
+  c.n = n;
+  c.m = m;
+  c.d = d;
+  c.mode = mode;
+  c.ws = workspace;
+  c.s = static_cast<hipStream_t>(stream);
+  c.count_host = count_host;
+  c.per_update = per_update;
+  c.pairs = pairs;
+  c.cap = pair_capacity;
+  c.hdr = at<Header>(workspace, c.L.hdr);
+  c.cnt = mode == DDM_PAIRS ? (per_update ? per_update : at<int32_t>(workspace, c.L.cnt))
+                            : per_update;
+  g_last_path = 0;
+  if (n + m == 0) {
+    const int rc = reset_outputs(c);
+    if (rc == DDM_OK && hipStreamSynchronize(c.s) != hipSuccess) return DDM_E_DEVICE;
+    return rc;
+  }
+  if (g_path_request == DDM_PATH_BUCKETED && !c.L.bucket_ok) return DDM_E_UNSUPPORTED;
+  int rc;
+  if (g_path_request != DDM_PATH_GLOBAL && c.L.bucket_ok) {
+    rc = run_bucketed(c);
+    if (rc != kFallback) {
+      if (rc == DDM_OK || rc == DDM_E_CAPACITY) g_last_path = DDM_PATH_BUCKETED;
+      return rc;
+    }
+    if (g_path_request == DDM_PATH_BUCKETED) return DDM_E_UNSUPPORTED;
+  }
+  rc = run_global(c);
+  if (rc == DDM_OK || rc == DDM_E_CAPACITY) g_last_path = DDM_PATH_GLOBAL;
+  return rc;
 }

@@ -21,6 +21,9 @@ struct Header {
   uint32_t nonempty;   // regions that are non-empty on every axis
   uint32_t kmin;       // min encoded lower key over non-empty regions
   uint32_t kmax;       // max encoded lower key over non-empty regions
+  uint32_t overflow;   // bucketed path: a bucket or the boundary state did not fit
+  uint32_t bs_total;   // bucketed path: boundary-state entries over all buckets
+  uint32_t pad[2];
   unsigned long long total;  // number of intersecting pairs
   unsigned long long aux[3];
 };

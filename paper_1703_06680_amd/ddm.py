@@ -24,6 +24,7 @@ DDM_E_DEVICE = -4
 DDM_E_UNSUPPORTED = -5
 
 MODES = {"count": 0, "per_update": 1, "pairs": 2}
+PATHS = {"auto": 0, "bucketed": 1, "global": 2}
 MAX_DIMS = 16
 
 
@@ -53,6 +54,10 @@ def library() -> ctypes.CDLL:
         lib.ddm_match.restype = ctypes.c_int
         lib.ddm_strerror.argtypes = [ctypes.c_int]
         lib.ddm_strerror.restype = ctypes.c_char_p
+        lib.ddm_set_path.argtypes = [ctypes.c_int]
+        lib.ddm_set_path.restype = ctypes.c_int
+        lib.ddm_last_path.argtypes = []
+        lib.ddm_last_path.restype = ctypes.c_int
         lib.ddm_profile.argtypes = [ctypes.c_int]
         lib.ddm_profile.restype = ctypes.c_int
         lib.ddm_profile_report.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
@@ -66,6 +71,20 @@ def strerror(code: int) -> str:
         return library().ddm_strerror(code).decode()
     except Exception:  # library missing: still produce a message
         return "unknown"
+
+
+def set_path(name: str) -> None:
+    """Select the implementation for later calls (process-global): "auto"
+    (bucketed where available, global otherwise or on overflow), "bucketed"
+    (error instead of falling back) or "global"."""
+    rc = library().ddm_set_path(PATHS[name])
+    if rc != DDM_OK:
+        raise DDMError(rc, "ddm_set_path")
+
+
+def last_path():
+    """Implementation that produced the last successful result."""
+    return {0: None, 1: "bucketed", 2: "global"}[library().ddm_last_path()]
 
 
 def profile(enable: bool) -> None:

@@ -40,20 +40,43 @@ def _host(inst):
     return (inst.upd_lo, inst.upd_hi, inst.sub_lo, inst.sub_hi)
 
 
-def check_all_modes(ddm, oracle, inst, pairs=True):
-    _note(f"{inst.name} n={inst.n} m={inst.m} d={inst.d}")
-    g = _dev(inst)
+PATHS = ("auto", "global")
+
+
+@pytest.fixture(autouse=True)
+def _reset_path(ddm):
+    ddm.set_path("auto")
+    yield
+    ddm.set_path("auto")
+
+
+def check_all_modes(ddm, oracle, inst, pairs=True, expect_bucketed=None):
+    """Every output mode, on both implementations, equal to the oracle.
+    Returns the implementation that served the "auto" calls."""
     k_ref, per_ref, pairs_ref = oracle.sbm(*_host(inst), pairs=pairs)
-    k = ddm.match(*g, mode="count")
-    assert k == k_ref, (inst.name, k, k_ref)
-    k1, per = ddm.match(*g, mode="per_update")
-    assert k1 == k_ref
-    assert np.array_equal(per.cpu().numpy(), per_ref), inst.name
-    if pairs:
-        k2, pr, per2 = ddm.match(*g, mode="pairs")
-        assert k2 == k_ref
-        assert np.array_equal(pr.cpu().numpy(), pairs_ref), inst.name
-        assert np.array_equal(per2.cpu().numpy(), per_ref)
+    g = _dev(inst)
+    served = None
+    for path in PATHS:
+        _note(f"{inst.name} n={inst.n} m={inst.m} d={inst.d} path={path}")
+        ddm.set_path(path)
+        k = ddm.match(*g, mode="count")
+        assert k == k_ref, (inst.name, path, k, k_ref)
+        if path == "auto":
+            served = ddm.last_path()
+        k1, per = ddm.match(*g, mode="per_update")
+        assert k1 == k_ref, (inst.name, path)
+        assert np.array_equal(per.cpu().numpy(), per_ref), (inst.name, path)
+        if pairs:
+            k2, pr, per2 = ddm.match(*g, mode="pairs")
+            assert k2 == k_ref, (inst.name, path)
+            assert np.array_equal(pr.cpu().numpy(), pairs_ref), (inst.name, path)
+            assert np.array_equal(per2.cpu().numpy(), per_ref), (inst.name, path)
+    ddm.set_path("auto")
+    if expect_bucketed is None:
+        expect_bucketed = inst.d <= 3 and inst.n + inst.m > 0
+    if expect_bucketed:
+        assert served == "bucketed", (inst.name, served)
+    return served
 
 
 def test_worked_example(ddm, oracle):
@@ -76,13 +99,23 @@ def test_tie_heavy_small(ddm, oracle, d):
         n, m = int(rng.integers(0, 60)), int(rng.integers(0, 60))
         inst = W.tie_heavy(n, m, d, grid=int(rng.integers(2, 20)), max_len=int(rng.integers(0, 6)),
                            seed=seed)
-        check_all_modes(ddm, oracle, inst)
+        # tiny inputs with many empty boxes may legitimately have nothing to bucket
+        check_all_modes(ddm, oracle, inst, expect_bucketed=False)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_tie_heavy_many_buckets(ddm, oracle, d):
+    """Integer grid with heavy ties, large enough for thousands of buckets and
+    long boundary-state lists."""
+    inst = W.tie_heavy(30_000, 25_000, d, grid=4000, max_len=40, seed=11)
+    check_all_modes(ddm, oracle, inst)
 
 
 @pytest.mark.parametrize("d", [1, 2, 3, 5])
 def test_random_float_boxes(ddm, oracle, d):
     for seed in range(6):
-        check_all_modes(ddm, oracle, W.random_float_boxes(700, 900, d, seed=seed, extent=300.0))
+        check_all_modes(ddm, oracle, W.random_float_boxes(700, 900, d, seed=seed, extent=300.0),
+                        expect_bucketed=d <= 3)
 
 
 @pytest.mark.parametrize("d,alpha", [(1, 100.0), (2, 1.0), (3, 100.0)])
@@ -99,14 +132,18 @@ def test_cfg2_full(ddm, oracle, alpha):
 
 @pytest.mark.parametrize("alpha", [1.0, 10.0, 100.0])
 def test_cfg3_full_counts(ddm, oracle, alpha):
-    """d=3, n = m = 5e6: exact total and per-update counts."""
+    """d=3, n = m = 5e6: exact total and per-update counts on both paths."""
     inst = W.config_instance("cfg3", alpha)
-    _note(inst.name)
     g = _dev(inst)
     k_ref, per_ref, _ = oracle.sbm(*_host(inst), pairs=False)
-    k, per = ddm.match(*g, mode="per_update")
-    assert k == k_ref
-    assert np.array_equal(per.cpu().numpy(), per_ref)
+    for path in PATHS:
+        _note(f"{inst.name} path={path}")
+        ddm.set_path(path)
+        k, per = ddm.match(*g, mode="per_update")
+        assert k == k_ref
+        assert np.array_equal(per.cpu().numpy(), per_ref)
+        if path == "auto":
+            assert ddm.last_path() == "bucketed"
 
 
 @pytest.mark.parametrize("alpha", [1.0, 100.0])
@@ -210,3 +247,33 @@ def test_role_swap_transposes(ddm):
     t = p2.cpu().numpy()[:, ::-1]
     t = t[np.lexsort((t[:, 1], t[:, 0]))]
     assert np.array_equal(t, p.cpu().numpy())
+
+
+def test_overflowing_bucket_falls_back(ddm, oracle):
+    """3000 identical boxes per side land in one bucket, larger than a
+    workgroup can hold: "auto" must fall back to the device-wide path, and
+    forcing the bucketed path must refuse rather than answer."""
+    _note("overflowing bucket")
+    lo = np.full((3000, 2), 1.0, np.float32)
+    hi = np.full((3000, 2), 4.0, np.float32)
+    g = [torch.from_numpy(a).cuda() for a in (lo, hi, lo.copy(), hi.copy())]
+    k, per = ddm.match(*g, mode="per_update")
+    assert k == 9_000_000 and ddm.last_path() == "global"
+    assert per.cpu().tolist() == [3000] * 3000
+    ddm.set_path("bucketed")
+    with pytest.raises(ddm.DDMError) as e:
+        ddm.match(*g, mode="count")
+    assert e.value.code == ddm.DDM_E_UNSUPPORTED
+
+
+def test_skewed_distribution(ddm, oracle):
+    """Lower corners spread over six orders of magnitude (log-uniform): the
+    linear bucket map is badly balanced, and the answer must not change."""
+    rng = np.random.default_rng(3)
+    for d in (1, 3):
+        n = 60_000
+        lo = np.exp(rng.uniform(0, np.log(1e6), size=(2 * n, d))).astype(np.float32)
+        side = np.exp(rng.uniform(np.log(0.5), np.log(50.0), size=(2 * n, d))).astype(np.float32)
+        hi = (lo + side).astype(np.float32)
+        inst = W.Instance(lo[:n], hi[:n], lo[n:], hi[n:], float("nan"), f"loguniform_d{d}")
+        check_all_modes(ddm, oracle, inst, expect_bucketed=False)
