@@ -32,14 +32,29 @@ METRIC = "matched regions/sec + HBM GB/s fraction at N=1e7; p50/p99 latency serv
 
 def algorithmic_bytes(phase: str, n: int, m: int, d: int, nonempty: int, mode: str):
     """Bytes a kernel phase must move once per launch (inputs read once,
-    outputs written once), independent of caching or re-reads.  Per region:
-    keys 8d (read lo, hi rows) + 8 (write lower/upper keys); a radix
-    down-sweep pass 8 read + 8 write per element (the first pass reads no
-    values: 4 + 8); up-sweep 4 per element; gather 4 (index) + 4 (upper key)
-    + 8(d-1) (other axes) read and 4 + 8(d-1) written per non-empty region;
-    count sweep 12 + 8(d-1) read per non-empty region plus 4 per update
-    written in per-update mode."""
+    outputs written once), independent of caching or re-reads.  A region
+    record carries 2d + 1 words (lower and upper key on the swept axis, the
+    region index, lo/hi on the d - 1 other axes).  Per region:
+
+      bucket.count    8d read (lo and hi rows);
+      bucket.scatter  8d read + 4(2d + 1) written (one record);
+      bucket.sweep    4(2d + 1) read (one record), + 4 per update written in
+                      per-update mode;
+      keys            8d read + 8 written (lower/upper keys);
+      sort.downsweep  8 read + 8 written per element (first pass: 4 + 8);
+      sort.upsweep    4 read per element;
+      gather          4 + 4 + 8(d-1) read, 4 + 8(d-1) written;
+      sweep.count     12 + 8(d-1) read (+ 4 per update in per-update mode).
+    """
     N = n + m
+    rec = 4 * (2 * d + 1)
+    out = 4 * n if mode != "count" else 0
+    if phase == "bucket.count":
+        return N * 8 * d
+    if phase == "bucket.scatter":
+        return N * 8 * d + nonempty * rec
+    if phase == "bucket.sweep":
+        return nonempty * rec + out
     if phase == "keys":
         return N * (8 * d + 8)
     if phase == "sort.upsweep":
@@ -83,7 +98,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--alpha", type=float, default=100.0)
+    ap.add_argument("--alpha", type=float, default=100.0,
+                    help="overlap degree of the timed workload")
+    ap.add_argument("--also-alphas", default="1,10",
+                    help="comma-separated extra alphas reported under per_alpha ('' for none)")
     ap.add_argument("--mode", default="per_update", choices=["count", "per_update"])
     ap.add_argument("--n", type=int, default=5_000_000, help="n = m boxes per side")
     ap.add_argument("--d", type=int, default=3)
@@ -166,6 +184,24 @@ def main():
                         "avg_launch_ms": round(avg_ms, 4),
                         "algorithmic_bytes_per_launch": int(alg)}
 
+    per_alpha = {}
+    for a in [float(x) for x in args.also_alphas.split(",") if x.strip()]:
+        extra = W.uniform_instance(n, m, d, a, seed=0)
+        ge = [torch.from_numpy(x).to(dev) for x in (extra.upd_lo, extra.upd_hi, extra.sub_lo, extra.sub_hi)]
+        for _ in range(args.warmup):
+            ddm.match_into(*ge, mode=args.mode, workspace=ws,
+                           per_update=per if args.mode == "per_update" else None, stream=stream)
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        for _ in range(args.steps):
+            ke = ddm.match_into(*ge, mode=args.mode, workspace=ws,
+                                per_update=per if args.mode == "per_update" else None, stream=stream)
+        torch.cuda.synchronize()
+        dte = (time.perf_counter() - te) / args.steps
+        per_alpha[f"{a:g}"] = {"ms_per_step": round(dte * 1e3, 4), "value": round(regions / dte, 1),
+                               "matches": ke, "path": ddm.last_path()}
+        del ge
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import oracle as O
@@ -174,7 +210,8 @@ def main():
         k_cpu, per_cpu, _ = o.sbm(inst.upd_lo, inst.upd_hi, inst.sub_lo, inst.sub_hi, pairs=False,
                                   per_update=args.mode == "per_update")
         dt = time.perf_counter() - tc
-        assert k_cpu == k, f"GPU count {k} != oracle {k_cpu}"
+        k_chk = step()  # the extra alphas reused the output buffer
+        assert k_cpu == k_chk == k, f"GPU count {k} != oracle {k_cpu}"
         if args.mode == "per_update":
             assert np.array_equal(per_cpu, per.cpu().numpy()), "per-update counts differ"
         cpu = {"value": round(regions / dt, 1), "unit": "regions/s", "cores": 1, "kind": "oracle",
@@ -199,11 +236,13 @@ def main():
                    "d": d, "n": n, "m": m, "alpha": args.alpha, "mode": args.mode,
                    "parallelism": "single GPU"},
         "matches": k,
+        "path": ddm.last_path(),
         "step_ms_p50": round(1e3 * statistics.median(per_step), 4),
         "step_ms_p99": round(1e3 * float(np.percentile(per_step, 99)), 4),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "phases_ms_per_step": {p: round(v["ms"] / args.steps, 4) for p, v in sorted(phases.items())},
+        "per_alpha": per_alpha,
         "input_generation_s": round(gen_s, 2),
     }
     print(json.dumps(out), flush=True)

@@ -170,6 +170,7 @@ int finish_pairs(const Call &c, unsigned long long K, Emit emit) {
   uint32_t *pu = at<uint32_t>(c.ws, L.pu), *ps = at<uint32_t>(c.ws, L.ps);
   uint32_t *pu2 = at<uint32_t>(c.ws, L.pu2), *ps2 = at<uint32_t>(c.ws, L.ps2);
   launch_widen(c.cnt, off, (size_t)c.n, c.s);
+  prof::mark(c.s, "pairs.scan");
   DDM_HIP(exclusive_scan_u64(off, off, (size_t)c.n, at<void>(c.ws, L.scan_tmp), c.s));
   prof::mark(c.s, "pairs.memset");
   DDM_HIP(hipMemsetAsync(cur, 0, (size_t)c.n * sizeof(uint32_t), c.s));
@@ -210,7 +211,7 @@ int run_bucketed(const Call &c) {
   DDM_HIP(hipStreamSynchronize(c.s));
   prof::flush();
   if (h.err) return DDM_E_INVAL;
-  if (h.overflow || h.pad[0]) return kFallback;
+  if (h.pad[0]) return kFallback;
   *c.count_host = h.total;
   if (c.mode != DDM_PAIRS || h.total == 0) return DDM_OK;
   return finish_pairs(c, h.total, [&](unsigned long long *off, uint32_t *cur, uint32_t *pu,

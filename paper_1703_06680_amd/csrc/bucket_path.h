@@ -20,11 +20,12 @@ namespace ddm {
 struct BucketLayout {
   uint32_t nb;          // number of buckets
   uint32_t nblk;        // blocks of the count and scatter passes
+  uint32_t gpb;         // groups of four rows per count/scatter block
   uint32_t bs_cap;      // capacity of the boundary-state record buffer
   int rec_words;        // 32-bit words per region record
   size_t bytes;         // workspace bytes for all buffers below
   // byte offsets inside the bucket workspace
-  size_t params, sample_part, counts, offsets, scan_tmp, bstart, bs_diff, bs_off, bs_cur, rec,
+  size_t params, sample_part, counts, transposed, offsets, block_offsets, scan_tmp, bs_cur, rec,
       bs_rec;
 };
 

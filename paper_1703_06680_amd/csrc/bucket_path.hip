@@ -6,27 +6,31 @@
 //            non-decreasing map, so every region of bucket b starts strictly
 //            before every region of bucket b' > b;
 //   count    validates every box, and per block of regions histograms the
-//            buckets of the non-empty ones; a region whose upper coordinate
-//            maps to a later bucket than its lower one may still be active in
-//            the buckets in between (it belongs to their boundary state), and
-//            adds +1 / -1 to a difference array at the ends of that range;
-//   scan     exclusive prefix sum of the bucket-major (bucket, block) counts
-//            gives every block its output slots in every bucket;
-//   finalize bucket start offsets; prefix sums of the difference array give
-//            the size of every bucket's boundary state (the counts of
-//            Algorithm 6's SubSet[p] and UpdSet[p] up to the cut being a
-//            bucket boundary), and their prefix sum its offset;
+//            buckets of the non-empty ones (block-major matrix); a region
+//            whose upper coordinate maps to a later bucket than its lower one
+//            may still be active in the buckets in between, so it is counted
+//            into the boundary state of each of them (the sizes of Algorithm
+//            6's SubSet[p] and UpdSet[p], taken at bucket boundaries);
+//   scan     the matrix is transposed to bucket-major order and one
+//            exclusive prefix sum over it, followed by the boundary-state
+//            sizes, gives every block its output slot in every bucket, every
+//            bucket's start and every boundary-state list's offset; the block
+//            offsets are transposed back so that each block reads its own row;
 //   scatter  writes one fixed-size record per non-empty region into its
 //            bucket, and a copy into the boundary state of every later bucket
 //            its interval may reach;
-//   sweep    one workgroup per bucket: records to registers, a stable LDS
-//            radix sort by lower key, per-kind lists in LDS, then every region
-//            walks forward over the later lower endpoints of the other kind
-//            while they start before it ends; boundary-state regions walk
-//            from the start of the bucket.  Each 1-D pair is met exactly once,
-//            at the later of the two lower endpoints (the pair Algorithm 4
-//            reports at the earlier upper endpoint), and kept if the boxes
-//            overlap on every other axis.
+//   sweep    one workgroup per bucket: records to registers, then an LDS
+//            counting sort of each kind into fine bins by a second monotone map
+//            of the lower coordinate (order inside a bin is left arbitrary);
+//            every region walks the other kind's entries in the bins from its
+//            own lower to its own upper coordinate and keeps those whose lower
+//            endpoint comes after its own and before its upper one (exact key
+//            tests; at equal coordinates an update's lower endpoint precedes a
+//            subscription's); boundary-state regions, whose lower endpoints
+//            precede the whole bucket, walk from the first bin.  Each 1-D pair
+//            is met exactly once, at the later of the two lower endpoints (the
+//            pair Algorithm 4 reports at the earlier upper endpoint), and kept
+//            if the boxes overlap on every other axis.
 #include "bucket_path.h"
 #include "primitives.h"
 #include "profile.h"
@@ -34,15 +38,17 @@
 namespace ddm {
 namespace {
 
-constexpr int kThreads = 256;                  // sample / count / scatter
-constexpr uint32_t kRegionsPerBlock = 16384;   // count / scatter tile
-constexpr int kSampleBlocks = 64;
-constexpr int kSamplesPerThread = 4;
+constexpr int kThreads = 1024;                 // count / scatter blocks
+constexpr uint32_t kMaxBlocks = 512;           // one resident round on 256 CUs
+constexpr int kSampleBlocks = 256;
+constexpr int kSampleThreads = 256;
 constexpr uint32_t kTargetBucket = 1536;       // mean records per bucket
 
-// The sweep workgroup: kCap records at most per bucket.
+// The sweep workgroup: kCap records at most per bucket, kFine fine bins per
+// kind.
 constexpr int kSweepThreads = 512;
 constexpr int kCap = 2048;
+constexpr int kFine = 512;
 
 struct BucketParams {
   float vmin;
@@ -94,7 +100,7 @@ __device__ __forceinline__ Box<D> load_box(const float *__restrict__ ulo,
   return b;
 }
 
-// err bits, emptiness
+// Error bits and emptiness of one box.
 template <int D>
 __device__ __forceinline__ uint32_t box_errors(const Box<D> &b, bool &empty) {
   uint32_t err = 0;
@@ -109,29 +115,43 @@ __device__ __forceinline__ uint32_t box_errors(const Box<D> &b, bool &empty) {
   return err;
 }
 
+// Offsets produced by the one prefix sum: S[b * nblk + k] is block k's first
+// slot in bucket b, S[cells] the number of records, S[cells + j] - S[cells]
+// the first boundary-state entry of bucket j (j <= nb).
+struct Offsets {
+  const uint32_t *S;
+  size_t cells;
+  uint32_t nblk, nb;
+  __device__ uint32_t records() const { return S[cells]; }
+  __device__ uint32_t bucket_begin(uint32_t b) const { return S[(size_t)b * nblk]; }
+  __device__ uint32_t bucket_end(uint32_t b) const {
+    return b + 1 < nb ? S[(size_t)(b + 1) * nblk] : S[cells];
+  }
+  __device__ uint32_t bs_begin(uint32_t j) const { return S[cells + j] - S[cells]; }
+};
+
 // ---------------------------------------------------------------- sample
 
 template <int D>
-__global__ __launch_bounds__(kThreads) void bk_sample_kernel(
+__global__ __launch_bounds__(kSampleThreads) void bk_sample_kernel(
     const float *__restrict__ ulo, const float *__restrict__ uhi, const float *__restrict__ slo,
     const float *__restrict__ shi, uint32_t n, uint32_t m, float4 *__restrict__ part) {
-  __shared__ float smin[kThreads / kWave], smax[kThreads / kWave];
-  __shared__ uint32_t scnt[kThreads / kWave];
+  __shared__ float smin[kSampleThreads / kWave], smax[kSampleThreads / kWave];
+  __shared__ uint32_t scnt[kSampleThreads / kWave];
   const uint32_t N = n + m;
   float mn = __int_as_float(0x7f800000), mx = -__int_as_float(0x7f800000);
   uint32_t c = 0;
-  for (int j = 0; j < kSamplesPerThread; ++j) {
-    const uint32_t i = (blockIdx.x * kThreads + threadIdx.x) * kSamplesPerThread + j;
-    const uint32_t r = (uint32_t)(((unsigned long long)mix32(i * 0x9E3779B9u + 0x632BE5ABu) * N) >> 32);
-    const Box<D> b = load_box<D>(ulo, uhi, slo, shi, n, r);
-    bool empty;
-    const uint32_t err = box_errors<D>(b, empty);
-    const float x = b.lo[0];
-    if (!err && !empty && fabsf(x) <= 3.0e38f) {
-      mn = fminf(mn, x);
-      mx = fmaxf(mx, x);
-      ++c;
-    }
+  const uint32_t i = blockIdx.x * kSampleThreads + threadIdx.x;
+  const uint32_t r =
+      (uint32_t)(((unsigned long long)mix32(i * 0x9E3779B9u + 0x632BE5ABu) * N) >> 32);
+  const Box<D> b = load_box<D>(ulo, uhi, slo, shi, n, r);
+  bool empty;
+  const uint32_t err = box_errors<D>(b, empty);
+  const float x = b.lo[0];
+  if (!err && !empty && fabsf(x) <= 3.0e38f) {
+    mn = x;
+    mx = x;
+    c = 1;
   }
   mn = wave_min(mn);
   mx = wave_max(mx);
@@ -144,21 +164,23 @@ __global__ __launch_bounds__(kThreads) void bk_sample_kernel(
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int i = 1; i < kThreads / kWave; ++i) {
-      mn = fminf(mn, smin[i]);
-      mx = fmaxf(mx, smax[i]);
-      c += scnt[i];
+    for (int k = 1; k < kSampleThreads / kWave; ++k) {
+      mn = fminf(mn, smin[k]);
+      mx = fmaxf(mx, smax[k]);
+      c += scnt[k];
     }
     part[blockIdx.x] = make_float4(mn, mx, __uint_as_float(c), 0.f);
   }
 }
 
-__global__ void bk_plan_kernel(const float4 *__restrict__ part, int nparts, uint32_t nb,
-                               BucketParams *__restrict__ P) {
-  if (threadIdx.x != 0) return;
+__global__ __launch_bounds__(kSampleThreads) void bk_plan_kernel(const float4 *__restrict__ part,
+                                                                 uint32_t nb,
+                                                                 BucketParams *__restrict__ P) {
+  __shared__ float smin[kSampleThreads / kWave], smax[kSampleThreads / kWave];
+  __shared__ uint32_t scnt[kSampleThreads / kWave];
   float mn = __int_as_float(0x7f800000), mx = -__int_as_float(0x7f800000);
   uint32_t c = 0;
-  for (int i = 0; i < nparts; ++i) {
+  for (int i = threadIdx.x; i < kSampleBlocks; i += kSampleThreads) {
     const float4 p = part[i];
     const uint32_t pc = __float_as_uint(p.z);
     if (pc) {
@@ -166,6 +188,22 @@ __global__ void bk_plan_kernel(const float4 *__restrict__ part, int nparts, uint
       mx = fmaxf(mx, p.y);
       c += pc;
     }
+  }
+  mn = wave_min(mn);
+  mx = wave_max(mx);
+  c = wave_sum(c);
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == 0) {
+    smin[w] = mn;
+    smax[w] = mx;
+    scnt[w] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int k = 1; k < kSampleThreads / kWave; ++k) {
+    mn = fminf(mn, smin[k]);
+    mx = fmaxf(mx, smax[k]);
+    c += scnt[k];
   }
   BucketParams q;
   q.nb = nb;
@@ -183,76 +221,126 @@ __global__ void bk_plan_kernel(const float4 *__restrict__ part, int nparts, uint
   *P = q;
 }
 
+// ------------------------------------------------------ row groups
+
+// Rows are read in groups of four consecutive rows of one kind, so that a
+// group of d-float rows is d aligned 16-byte loads.  Groups 0 .. Gu-1 cover the
+// updates, the rest the subscriptions.
+struct Group {
+  const float *lo, *hi;
+  uint32_t row0, rows, r0;  // first row, rows in the group (<= 4), region index of row0
+};
+
+__device__ __forceinline__ Group group_of(uint32_t g, uint32_t Gu, const float *ulo,
+                                          const float *uhi, const float *slo, const float *shi,
+                                          uint32_t n, uint32_t m) {
+  Group q;
+  if (g < Gu) {
+    q.lo = ulo;
+    q.hi = uhi;
+    q.row0 = 4 * g;
+    q.rows = min(4u, n - q.row0);
+    q.r0 = q.row0;
+  } else {
+    q.lo = slo;
+    q.hi = shi;
+    q.row0 = 4 * (g - Gu);
+    q.rows = min(4u, m - q.row0);
+    q.r0 = n + q.row0;
+  }
+  return q;
+}
+
+template <int D>
+__device__ __forceinline__ void load_group(const Group &q, bool vec, Box<D> (&bx)[4]) {
+  if (vec && q.rows == 4) {
+    const float4 *l4 = reinterpret_cast<const float4 *>(q.lo + (size_t)q.row0 * D);
+    const float4 *h4 = reinterpret_cast<const float4 *>(q.hi + (size_t)q.row0 * D);
+    float lf[4 * D], hf[4 * D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const float4 a = l4[i], b = h4[i];
+      lf[4 * i] = a.x;
+      lf[4 * i + 1] = a.y;
+      lf[4 * i + 2] = a.z;
+      lf[4 * i + 3] = a.w;
+      hf[4 * i] = b.x;
+      hf[4 * i + 1] = b.y;
+      hf[4 * i + 2] = b.z;
+      hf[4 * i + 3] = b.w;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        bx[r].lo[k] = lf[r * D + k];
+        bx[r].hi[k] = hf[r * D + k];
+      }
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        const bool ok = (uint32_t)r < q.rows;
+        bx[r].lo[k] = ok ? q.lo[(size_t)(q.row0 + r) * D + k] : 0.f;
+        bx[r].hi[k] = ok ? q.hi[(size_t)(q.row0 + r) * D + k] : 1.f;
+      }
+  }
+}
+
 // ------------------------------------------------------------ count pass
 
 template <int D>
 __global__ __launch_bounds__(kThreads) void bk_count_kernel(
     const float *__restrict__ ulo, const float *__restrict__ uhi, const float *__restrict__ slo,
-    const float *__restrict__ shi, uint32_t n, uint32_t m, const BucketParams *__restrict__ P,
-    uint32_t nb, uint32_t *__restrict__ counts, uint32_t nblk, int *__restrict__ bs_diff,
-    Header *__restrict__ hdr) {
+    const float *__restrict__ shi, uint32_t n, uint32_t m, int vec,
+    const BucketParams *__restrict__ P, uint32_t nb, uint32_t gpb, uint32_t *__restrict__ C,
+    uint32_t *__restrict__ bs_size, Header *__restrict__ hdr) {
   extern __shared__ uint32_t hist[];
   const BucketParams p = *P;
   for (uint32_t b = threadIdx.x; b < nb; b += kThreads) hist[b] = 0;
   __syncthreads();
-  const uint32_t N = n + m;
-  const uint32_t base = blockIdx.x * kRegionsPerBlock;
-  const uint32_t end = min(base + kRegionsPerBlock, N);
+  const uint32_t Gu = (n + 3) / 4, G = Gu + (m + 3) / 4;
+  const uint32_t g0 = blockIdx.x * gpb, g1 = min(G, g0 + gpb);
   uint32_t err = 0;
-  for (uint32_t r = base + threadIdx.x; r < end; r += kThreads) {
-    const Box<D> bx = load_box<D>(ulo, uhi, slo, shi, n, r);
-    bool empty;
-    err |= box_errors<D>(bx, empty);
-    if (empty) continue;
-    const uint32_t b = bucket_of(bx.lo[0], p.vmin, p.scale, nb);
-    atomicAdd(&hist[b], 1u);
-    const uint32_t last = bucket_of(bx.hi[0], p.vmin, p.scale, nb);
-    if (last > b) {
-      atomicAdd(&bs_diff[b + 1], 1);
-      if (last + 1 < nb) atomicAdd(&bs_diff[last + 1], -1);
+#pragma unroll 2
+  for (uint32_t g = g0 + threadIdx.x; g < g1; g += kThreads) {
+    const Group q = group_of(g, Gu, ulo, uhi, slo, shi, n, m);
+    Box<D> bx[4];
+    load_group<D>(q, vec != 0, bx);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if ((uint32_t)r >= q.rows) continue;
+      bool empty;
+      err |= box_errors<D>(bx[r], empty);
+      if (empty) continue;
+      const uint32_t b = bucket_of(bx[r].lo[0], p.vmin, p.scale, nb);
+      atomicAdd(&hist[b], 1u);
+      const uint32_t last = bucket_of(bx[r].hi[0], p.vmin, p.scale, nb);
+      for (uint32_t j = b + 1; j <= last; ++j) atomicAdd(&bs_size[j], 1u);
     }
   }
   __syncthreads();
-  for (uint32_t b = threadIdx.x; b < nb; b += kThreads) counts[(size_t)b * nblk + blockIdx.x] = hist[b];
+  for (uint32_t b = threadIdx.x; b < nb; b += kThreads) C[(size_t)blockIdx.x * nb + b] = hist[b];
   err = (__ballot(err & kErrNaN) ? kErrNaN : 0u) | (__ballot(err & kErrOrder) ? kErrOrder : 0u);
   if (err && lane_id() == 0) atomicOr(&hdr->err, err);
 }
 
-// One block: bucket starts, non-empty total, boundary-state sizes/offsets.
-__global__ __launch_bounds__(kThreads) void bk_finalize_kernel(
-    const uint32_t *__restrict__ counts, const uint32_t *__restrict__ offsets, uint32_t nb,
-    uint32_t nblk, const int *__restrict__ bs_diff, uint32_t bs_cap, uint32_t *__restrict__ bstart,
-    uint32_t *__restrict__ bs_off, uint32_t *__restrict__ bs_cur, Header *__restrict__ hdr) {
-  __shared__ uint32_t lds[kThreads / kWave + 1];
-  const size_t last = (size_t)nb * nblk - 1;
-  const uint32_t total = offsets[last] + counts[last];
-  for (uint32_t b = threadIdx.x; b < nb; b += kThreads) {
-    bstart[b] = offsets[(size_t)b * nblk];
-    bs_cur[b] = 0;
+// out[c][r] = in[r][c] for a rows x cols row-major matrix, 64x64 LDS tiles.
+__global__ __launch_bounds__(256) void transpose_kernel(const uint32_t *__restrict__ in,
+                                                        uint32_t *__restrict__ out, uint32_t rows,
+                                                        uint32_t cols) {
+  __shared__ uint32_t tile[64][65];
+  const uint32_t c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+  const uint32_t tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (uint32_t j = ty; j < 64; j += 4) {
+    const uint32_t r = r0 + j, c = c0 + tx;
+    if (r < rows && c < cols) tile[j][tx] = in[(size_t)r * cols + c];
   }
-  if (threadIdx.x == 0) {
-    bstart[nb] = total;
-    hdr->nonempty = total;
-  }
-  // size_j = diff[0] + ... + diff[j]; off_j = size_0 + ... + size_{j-1}
-  uint32_t carry_size = 0, carry_off = 0;
-  for (uint32_t base = 0; base < nb; base += kThreads) {
-    const uint32_t j = base + threadIdx.x;
-    const uint32_t dv = j < nb ? (uint32_t)bs_diff[j] : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_exclusive_scan<uint32_t, kThreads>(dv, lds, &tot);
-    const uint32_t size = carry_size + ex + dv;
-    carry_size += tot;
-    const uint32_t sz = j < nb ? size : 0u;
-    uint32_t tot2;
-    const uint32_t ex2 = block_exclusive_scan<uint32_t, kThreads>(sz, lds, &tot2);
-    if (j < nb) bs_off[j] = carry_off + ex2;
-    carry_off += tot2;
-  }
-  if (threadIdx.x == 0) {
-    bs_off[nb] = carry_off;
-    hdr->bs_total = carry_off;
-    if (carry_off > bs_cap) hdr->overflow = 1u;
+  __syncthreads();
+  for (uint32_t j = ty; j < 64; j += 4) {
+    const uint32_t c = c0 + j, r = r0 + tx;
+    if (c < cols && r < rows) out[(size_t)c * rows + r] = tile[tx][j];
   }
 }
 
@@ -264,194 +352,182 @@ template <int D>
 __device__ __forceinline__ void write_record(uint32_t *__restrict__ dst, const Box<D> &b,
                                              uint32_t r) {
   constexpr int RW = D == 1 ? 4 : 8;
-  uint32_t w[RW];
+  uint32_t w[8];
   w[0] = encode_coord(b.lo[0]);
   w[1] = encode_coord(b.hi[0]);
   w[2] = r;
   w[3] = 0;
 #pragma unroll
+  for (int k = 4; k < 8; ++k) w[k] = 0;
+#pragma unroll
   for (int k = 1; k < D; ++k) {
     w[4 + 2 * (k - 1)] = __float_as_uint(b.lo[k]);
     w[5 + 2 * (k - 1)] = __float_as_uint(b.hi[k]);
   }
-#pragma unroll
-  for (int k = 4 + 2 * (D - 1); k < RW; ++k) w[k] = 0;
   uint4 *d4 = reinterpret_cast<uint4 *>(dst);
   d4[0] = make_uint4(w[0], w[1], w[2], w[3]);
-  if (RW == 8) d4[1] = make_uint4(w[4 % RW], w[5 % RW], w[6 % RW], w[7 % RW]);
+  if (RW == 8) d4[1] = make_uint4(w[4], w[5], w[6], w[7]);
 }
 
 template <int D>
 __global__ __launch_bounds__(kThreads) void bk_scatter_kernel(
     const float *__restrict__ ulo, const float *__restrict__ uhi, const float *__restrict__ slo,
-    const float *__restrict__ shi, uint32_t n, uint32_t m, const BucketParams *__restrict__ P,
-    uint32_t nb, const uint32_t *__restrict__ offsets, uint32_t nblk,
-    const uint32_t *__restrict__ bs_off, uint32_t *__restrict__ bs_cur, uint32_t bs_cap,
-    uint32_t *__restrict__ rec, uint32_t *__restrict__ bs_rec) {
+    const float *__restrict__ shi, uint32_t n, uint32_t m, int vec,
+    const BucketParams *__restrict__ P, uint32_t gpb, Offsets O, const uint32_t *__restrict__ SB,
+    uint32_t *__restrict__ bs_cur, uint32_t bs_cap, uint32_t *__restrict__ rec,
+    uint32_t *__restrict__ bs_rec) {
   constexpr int RW = D == 1 ? 4 : 8;
   extern __shared__ uint32_t cur[];
   const BucketParams p = *P;
-  for (uint32_t b = threadIdx.x; b < nb; b += kThreads) cur[b] = offsets[(size_t)b * nblk + blockIdx.x];
+  const uint32_t nb = O.nb;
+  for (uint32_t b = threadIdx.x; b < nb; b += kThreads) cur[b] = SB[(size_t)blockIdx.x * nb + b];
   __syncthreads();
-  const uint32_t N = n + m;
-  const uint32_t base = blockIdx.x * kRegionsPerBlock;
-  const uint32_t end = min(base + kRegionsPerBlock, N);
-  for (uint32_t r = base + threadIdx.x; r < end; r += kThreads) {
-    const Box<D> bx = load_box<D>(ulo, uhi, slo, shi, n, r);
-    bool empty;
-    (void)box_errors<D>(bx, empty);
-    if (empty) continue;
-    const uint32_t b = bucket_of(bx.lo[0], p.vmin, p.scale, nb);
-    const uint32_t slot = atomicAdd(&cur[b], 1u);
-    write_record<D>(rec + (size_t)slot * RW, bx, r);
-    const uint32_t last = bucket_of(bx.hi[0], p.vmin, p.scale, nb);
-    for (uint32_t j = b + 1; j <= last; ++j) {
-      const uint32_t pos = bs_off[j] + atomicAdd(&bs_cur[j], 1u);
-      if (pos < bs_cap) write_record<D>(bs_rec + (size_t)pos * RW, bx, r);
+  const uint32_t Gu = (n + 3) / 4, G = Gu + (m + 3) / 4;
+  const uint32_t g0 = blockIdx.x * gpb, g1 = min(G, g0 + gpb);
+#pragma unroll 2
+  for (uint32_t g = g0 + threadIdx.x; g < g1; g += kThreads) {
+    const Group q = group_of(g, Gu, ulo, uhi, slo, shi, n, m);
+    Box<D> bx[4];
+    load_group<D>(q, vec != 0, bx);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if ((uint32_t)r >= q.rows) continue;
+      bool empty;
+      (void)box_errors<D>(bx[r], empty);
+      if (empty) continue;
+      const uint32_t b = bucket_of(bx[r].lo[0], p.vmin, p.scale, nb);
+      const uint32_t slot = atomicAdd(&cur[b], 1u);
+      write_record<D>(rec + (size_t)slot * RW, bx[r], q.r0 + r);
+      const uint32_t last = bucket_of(bx[r].hi[0], p.vmin, p.scale, nb);
+      for (uint32_t j = b + 1; j <= last; ++j) {
+        const uint32_t pos = O.bs_begin(j) + atomicAdd(&bs_cur[j], 1u);
+        if (pos < bs_cap) write_record<D>(bs_rec + (size_t)pos * RW, bx[r], q.r0 + r);
+      }
     }
   }
 }
 
 // ------------------------------------------------------------ sweep pass
 
-// One stable LSD pass over C <= CAP (key, value) pairs in LDS, 8-bit digit
-// at ``shift``.  Element order: wave w owns positions [w*64*ITEMS,
-// (w+1)*64*ITEMS); item i of lane l is position w*64*ITEMS + i*64 + l.
-template <int THREADS, int CAP>
-__device__ __forceinline__ void lds_radix_pass(const uint32_t *Kin, const uint32_t *Vin,
-                                               uint32_t *Kout, uint32_t *Vout, uint32_t C,
-                                               int shift, uint32_t *wcnt, uint32_t *dtot) {
-  constexpr int W = THREADS / kWave;
-  constexpr int ITEMS = CAP / THREADS;
-  const int t = threadIdx.x, w = t / kWave, lane = lane_id();
-  for (int i = t; i < W * 256; i += THREADS) wcnt[i] = 0;
-  __syncthreads();
-  uint32_t key[ITEMS], val[ITEMS], dig[ITEMS], rank[ITEMS];
-#pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
-    const uint32_t pos = (uint32_t)(w * (kWave * ITEMS) + i * kWave + lane);
-    const bool valid = pos < C;
-    key[i] = valid ? Kin[pos] : 0u;
-    val[i] = valid ? Vin[pos] : 0u;
-    const uint32_t d = (key[i] >> shift) & 255u;
-    dig[i] = d;
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t on = __ballot(bit);
-      peers &= bit ? on : ~on;
-    }
-    const uint32_t below = __popcll(peers & lanemask_lt());
-    const int leader = valid ? (__ffsll((unsigned long long)peers) - 1) : lane;
-    uint32_t old = 0;
-    if (valid && lane == leader) old = atomicAdd(&wcnt[w * 256 + d], (uint32_t)__popcll(peers));
-    old = __shfl(old, leader, kWave);
-    rank[i] = valid ? old + below : 0xFFFFFFFFu;
-  }
-  __syncthreads();
-  if (t < 256) {
-    uint32_t run = 0;
-#pragma unroll
-    for (int ww = 0; ww < W; ++ww) {
-      const uint32_t c = wcnt[ww * 256 + t];
-      wcnt[ww * 256 + t] = run;
-      run += c;
-    }
-    dtot[t] = run;
-  }
-  __syncthreads();
-  if (t < kWave) {
-    // exclusive scan of the 256 digit totals, 4 digits per lane
-    uint32_t v0 = dtot[4 * t], v1 = dtot[4 * t + 1], v2 = dtot[4 * t + 2], v3 = dtot[4 * t + 3];
-    const uint32_t s = v0 + v1 + v2 + v3;
-    const uint32_t ex = wave_inclusive_scan(s) - s;
-    dtot[4 * t] = ex;
-    dtot[4 * t + 1] = ex + v0;
-    dtot[4 * t + 2] = ex + v0 + v1;
-    dtot[4 * t + 3] = ex + v0 + v1 + v2;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
-    if (rank[i] != 0xFFFFFFFFu) {
-      const uint32_t np = dtot[dig[i]] + wcnt[w * 256 + dig[i]] + rank[i];
-      Kout[np] = key[i];
-      Vout[np] = val[i];
-    }
-  }
-  __syncthreads();
+// Inverse of encode_coord (for non-NaN codes; -0 comes back as +0).
+__device__ __forceinline__ float decode_coord(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
 }
 
-template <int THREADS>
-__device__ __forceinline__ uint32_t block_min_u32(uint32_t v, uint32_t *lds) {
-  v = wave_min(v);
-  const int w = threadIdx.x / kWave;
-  if (lane_id() == 0) lds[w] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int i = 1; i < THREADS / kWave; ++i) v = lds[i] < v ? lds[i] : v;
-    lds[THREADS / kWave] = v;
-  }
-  __syncthreads();
-  v = lds[THREADS / kWave];
-  __syncthreads();
-  return v;
+__device__ __forceinline__ uint32_t fine_of(float x, float vmin, float fscale) {
+  float t = (x - vmin) * fscale;
+  t = fminf(fmaxf(t, 0.0f), (float)(kFine - 1));
+  return (uint32_t)t;
 }
 
-template <int THREADS>
-__device__ __forceinline__ uint32_t block_max_u32(uint32_t v, uint32_t *lds) {
-  v = wave_max(v);
-  const int w = threadIdx.x / kWave;
-  if (lane_id() == 0) lds[w] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int i = 1; i < THREADS / kWave; ++i) v = lds[i] > v ? lds[i] : v;
-    lds[THREADS / kWave] = v;
+// Walk of region y over other-kind entries [j, jend) of the bucket: keeps x
+// when lo_x comes after lo_y (strictly, or on equal keys when y is the update
+// and x the subscription; "after" always holds for boundary-state regions) and
+// lo_x < hi_y, and the boxes overlap on the other axes.
+template <int DM1, int MODE>
+__device__ __forceinline__ uint32_t walk(const uint32_t *__restrict__ KLO,
+                                         const uint32_t *__restrict__ RID,
+                                         const float *__restrict__ CO, uint32_t j, uint32_t jend,
+                                         const uint32_t *y, uint32_t after_key, uint32_t n,
+                                         unsigned long long &hits,
+                                         int32_t *__restrict__ per_update,
+                                         const unsigned long long *__restrict__ pair_off,
+                                         uint32_t *__restrict__ cursor, uint32_t *__restrict__ out_u,
+                                         uint32_t *__restrict__ out_s) {
+  // x counts iff after_key <= KLO[x] < khi, where after_key is klo_y for an
+  // update y, klo_y + 1 for a subscription y and 0 for the boundary state.
+  constexpr int CW = DM1 == 0 ? 1 : 2 * DM1;
+  const uint32_t khi = y[1];
+  const uint32_t ry = y[2];
+  const bool y_upd = ry < n;
+  float ylo[2] = {0.f, 0.f}, yhi[2] = {0.f, 0.f};
+#pragma unroll
+  for (int c = 0; c < DM1; ++c) {
+    ylo[c] = __uint_as_float(y[4 + 2 * c]);
+    yhi[c] = __uint_as_float(y[5 + 2 * c]);
   }
-  __syncthreads();
-  v = lds[THREADS / kWave];
-  __syncthreads();
-  return v;
+  uint32_t own = 0;
+  for (; j < jend; j += 4) {
+    uint32_t idx[4];
+    bool hit[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      idx[u] = j + u < jend ? j + u : jend - 1;
+      const uint32_t k = KLO[idx[u]];
+      hit[u] = (j + u < jend) && k >= after_key && k < khi;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (DM1 == 1) {
+        const float2 xc = *reinterpret_cast<const float2 *>(&CO[idx[u] * CW]);
+        hit[u] = hit[u] && ylo[0] < xc.y && xc.x < yhi[0];
+      } else if (DM1 == 2) {
+        const float4 xc = *reinterpret_cast<const float4 *>(&CO[idx[u] * CW]);
+        hit[u] = hit[u] && ylo[0] < xc.y && xc.x < yhi[0] && ylo[1] < xc.w && xc.z < yhi[1];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (!hit[u]) continue;
+      ++hits;
+      if (MODE == 1) {
+        if (y_upd)
+          ++own;
+        else
+          atomicAdd(&per_update[RID[idx[u]]], 1);
+      } else if (MODE == 2) {
+        const uint32_t rx = RID[idx[u]];
+        const uint32_t uu = y_upd ? ry : rx;
+        const uint32_t sid = (y_upd ? rx : ry) - n;
+        const unsigned long long slot = pair_off[uu] + atomicAdd(&cursor[uu], 1u);
+        out_u[slot] = uu;
+        out_s[slot] = sid;
+      }
+    }
+  }
+  return own;
 }
 
 template <int DM1, int MODE, int CAP, int THREADS>
 __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
-    const uint32_t *__restrict__ rec, const uint32_t *__restrict__ bstart,
-    const uint32_t *__restrict__ bs_rec, const uint32_t *__restrict__ bs_off, uint32_t n,
-    Header *__restrict__ hdr, int32_t *__restrict__ per_update,
+    const uint32_t *__restrict__ rec, Offsets O, const uint32_t *__restrict__ bs_rec,
+    uint32_t bs_cap, uint32_t n, Header *__restrict__ hdr, int32_t *__restrict__ per_update,
     const unsigned long long *__restrict__ pair_off, uint32_t *__restrict__ cursor,
     uint32_t *__restrict__ out_u, uint32_t *__restrict__ out_s,
     unsigned long long *__restrict__ total) {
   constexpr int RW = DM1 == 0 ? 4 : 8;
-  constexpr int NC = 2 * DM1;               // other-axis words per record
-  constexpr int CW = DM1 == 0 ? 1 : NC;     // LDS words per element for coords
+  constexpr int NC = 2 * DM1;            // other-axis words per record
+  constexpr int CW = DM1 == 0 ? 1 : NC;  // LDS words per element for coords
   constexpr int ITEMS = CAP / THREADS;
   constexpr int W = THREADS / kWave;
-  constexpr int SOA = (3 + CW) * CAP;
-  constexpr int MAIN = SOA > 4 * CAP ? SOA : 4 * CAP;
-  constexpr int AUX = (W * 256) > CAP ? (W * 256) : CAP;
-  __shared__ __align__(16) uint32_t sm[MAIN];
-  __shared__ uint32_t aux[AUX];
-  __shared__ uint32_t dtot[256];
+  constexpr int NBINS = 2 * kFine;
+  constexpr int BPT = NBINS / THREADS;   // bins per thread in the scan
+  static_assert(NBINS % THREADS == 0, "bins must split evenly over the threads");
+  // the bucket in LDS, in fine-bin order (updates first): lower key, region
+  // index and the other axes' lo/hi of every region
+  __shared__ uint32_t KLO[CAP];
+  __shared__ uint32_t RID[CAP];
+  __shared__ __align__(16) float CO[DM1 == 0 ? 4 : CAP * CW];
+  __shared__ uint32_t BIN[NBINS];
+  __shared__ float redf[2 * W + 2];
   __shared__ uint32_t red[W + 2];
   __shared__ unsigned long long red64[W];
 
-  if (hdr->overflow) return;  // boundary state did not fit (set before launch)
   const uint32_t b = blockIdx.x;
-  const uint32_t start = bstart[b];
-  const uint32_t C = bstart[b + 1] - start;
-  if (C > (uint32_t)CAP) {
+  const uint32_t nbs_total = O.bs_begin(O.nb);
+  const uint32_t start = O.bucket_begin(b);
+  const uint32_t C = O.bucket_end(b) - start;
+  if (nbs_total > bs_cap || C > (uint32_t)CAP) {  // uniform: the host falls back
     if (threadIdx.x == 0) atomicOr(&hdr->pad[0], 1u);
     return;
   }
-  const uint32_t bs_begin = bs_off[b];
-  const uint32_t nbs = bs_off[b + 1] - bs_begin;
+  const uint32_t bs_begin = O.bs_begin(b);
+  const uint32_t nbs = O.bs_begin(b + 1) - bs_begin;
   const int t = threadIdx.x;
 
-  // 1. own records into registers (slot s = t + i * THREADS)
+  // 1. own records into registers (slot s = t + i * THREADS); value range
   uint32_t rk[ITEMS][RW];
-  uint32_t kmin = 0xFFFFFFFFu, kmax = 0u;
+  float vmn = __int_as_float(0x7f800000), vmx = -__int_as_float(0x7f800000);
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const uint32_t s = t + i * THREADS;
@@ -469,172 +545,115 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
         rk[i][6 % RW] = c.z;
         rk[i][7 % RW] = c.w;
       }
-      kmin = rk[i][0] < kmin ? rk[i][0] : kmin;
-      kmax = rk[i][0] > kmax ? rk[i][0] : kmax;
+      const float x = decode_coord(rk[i][0]);
+      vmn = fminf(vmn, x);
+      vmx = fmaxf(vmx, x);
     } else {
 #pragma unroll
       for (int k = 0; k < RW; ++k) rk[i][k] = 0;
     }
   }
-  kmin = block_min_u32<THREADS>(kmin, red);
-  kmax = block_max_u32<THREADS>(kmax, red);
+  vmn = wave_min(vmn);
+  vmx = wave_max(vmx);
+  if (lane_id() == 0) {
+    redf[2 * (t / kWave)] = vmn;
+    redf[2 * (t / kWave) + 1] = vmx;
+  }
+  for (int k = t; k < NBINS; k += THREADS) BIN[k] = 0;
+  __syncthreads();
+  vmn = redf[0];
+  vmx = redf[1];
+#pragma unroll
+  for (int w = 1; w < W; ++w) {
+    vmn = fminf(vmn, redf[2 * w]);
+    vmx = fmaxf(vmx, redf[2 * w + 1]);
+  }
+  float fscale = 0.f;
+  if (vmx > vmn) {
+    fscale = (float)kFine / (vmx - vmn);
+    if (!(fscale <= 3.0e38f)) fscale = 0.f;
+  }
 
-  // 2. stable LDS radix sort by (lower key - kmin); value = slot | kind << 31
-  uint32_t *K0 = sm, *V0 = sm + CAP, *K1 = sm + 2 * CAP, *V1 = sm + 3 * CAP;
+  // 2. counting sort into fine bins, updates first: bin = kind * kFine + fine(lo)
+  uint32_t key[ITEMS];
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const uint32_t s = t + i * THREADS;
     if (s < C) {
-      K0[s] = rk[i][0] - kmin;
-      V0[s] = s | ((rk[i][2] >= n) ? 0x80000000u : 0u);
+      key[i] = (rk[i][2] >= n ? kFine : 0u) + fine_of(decode_coord(rk[i][0]), vmn, fscale);
+      atomicAdd(&BIN[key[i]], 1u);
     }
   }
   __syncthreads();
-  const uint32_t range = C ? kmax - kmin : 0u;
-  const int bits = range ? 32 - __clz(range) : 0;
-  const int passes = (bits + 7) / 8;
-  uint32_t *Kc = K0, *Vc = V0, *Kn = K1, *Vn = V1;
-  for (int p = 0; p < passes; ++p) {
-    lds_radix_pass<THREADS, CAP>(Kc, Vc, Kn, Vn, C, 8 * p, aux, dtot);
-    uint32_t *tk = Kc, *tv = Vc;
-    Kc = Kn;
-    Vc = Vn;
-    Kn = tk;
-    Vn = tv;
-  }
-
-  // 3. per-kind lists: updates at [0, Cu), subscriptions at [Cu, C), both in
-  //    sorted order; DEST/STO (in the free buffers) give each slot its list
-  //    index and the first index of the other kind after it.
-  uint32_t *DEST = Kn, *STO = Vn;
-  uint32_t vq[ITEMS];
-  uint32_t nupd = 0;
+  {
+    uint32_t v[BPT], sum = 0;
 #pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
-    const uint32_t q = t * ITEMS + i;  // blocked order for the scan
-    vq[i] = q < C ? Vc[q] : 0x80000000u;
-    nupd += (q < C && !(vq[i] >> 31)) ? 1u : 0u;
-  }
-  uint32_t Cu;
-  uint32_t iu = block_exclusive_scan<uint32_t, THREADS>(nupd, red, &Cu);
+    for (int k = 0; k < BPT; ++k) {
+      v[k] = BIN[t * BPT + k];
+      sum += v[k];
+    }
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan<uint32_t, THREADS>(sum, red, &tot);
 #pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
-    const uint32_t q = t * ITEMS + i;
-    if (q < C) {
-      const uint32_t slot = vq[i] & 0x7FFFFFFFu;
-      const bool sub = vq[i] >> 31;
-      const uint32_t is = q - iu;  // subscriptions before q
-      DEST[slot] = sub ? Cu + is : iu;
-      STO[slot] = sub ? iu : Cu + is;
-      if (!sub) ++iu;
+    for (int k = 0; k < BPT; ++k) {
+      BIN[t * BPT + k] = run;
+      run += v[k];
     }
   }
   __syncthreads();
-  uint32_t dest[ITEMS], sto[ITEMS];
-#pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
-    const uint32_t s = t + i * THREADS;
-    dest[i] = s < C ? DEST[s] : 0u;
-    sto[i] = s < C ? STO[s] : 0u;
-  }
-  __syncthreads();
-  uint32_t *KLO = sm, *KHI = sm + CAP, *RID = sm + 2 * CAP, *CO = sm + 3 * CAP;
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const uint32_t s = t + i * THREADS;
     if (s < C) {
-      const uint32_t q = dest[i];
+      const uint32_t q = atomicAdd(&BIN[key[i]], 1u);
       KLO[q] = rk[i][0];
-      KHI[q] = rk[i][1];
       RID[q] = rk[i][2];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) CO[q * CW + c] = rk[i][4 + c];
+      for (int c = 0; c < NC; ++c) CO[q * CW + c] = __uint_as_float(rk[i][4 + c]);
     }
   }
-  uint32_t *RC = aux;  // received matches per update list entry
-  for (uint32_t j = t; j < (uint32_t)CAP; j += THREADS) RC[j] = 0;
   __syncthreads();
+  // BIN[k] is now the end of fine bin k; bin k starts at BIN[k - 1] (0 for k = 0)
+  auto bin_begin = [&](uint32_t k) { return k ? BIN[k - 1] : 0u; };
 
-  // 4. the sweep
+  // 3. the walks: every region of the bucket, then the boundary state
   unsigned long long hits = 0;
-  auto scan = [&](const uint32_t *y, uint32_t j, uint32_t jend, bool from_bs) {
-    const uint32_t khi = y[1];
-    const uint32_t ry = y[2];
-    const bool y_upd = ry < n;
-    float ylo[DM1 > 0 ? DM1 : 1], yhi[DM1 > 0 ? DM1 : 1];
-#pragma unroll
-    for (int c = 0; c < DM1; ++c) {
-      ylo[c] = __uint_as_float(y[4 + 2 * c]);
-      yhi[c] = __uint_as_float(y[5 + 2 * c]);
-    }
-    uint32_t own = 0;
-    for (; j < jend; ++j) {
-      if (KLO[j] >= khi) break;
-      bool hit = true;
-      if (DM1 == 1) {
-        const float2 xc = *reinterpret_cast<const float2 *>(&CO[j * CW]);
-        hit = ylo[0] < xc.y && xc.x < yhi[0];
-      } else if (DM1 == 2) {
-        const float4 xc = *reinterpret_cast<const float4 *>(&CO[j * CW]);
-        hit = ylo[0] < xc.y && xc.x < yhi[0] && ylo[DM1 - 1] < xc.w && xc.z < yhi[DM1 - 1];
-      }
-      if (!hit) continue;
-      ++hits;
-      if (MODE == 1) {
-        if (y_upd)
-          ++own;
-        else
-          atomicAdd(&RC[j], 1u);
-      } else if (MODE == 2) {
-        const uint32_t rx = RID[j];
-        const uint32_t u = y_upd ? ry : rx;
-        const uint32_t sid = (y_upd ? rx : ry) - n;
-        const unsigned long long slot = pair_off[u] + atomicAdd(&cursor[u], 1u);
-        out_u[slot] = u;
-        out_s[slot] = sid;
-      }
-    }
-    return own;
-  };
-
-  uint32_t own_upd[ITEMS];
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
-    own_upd[i] = 0;
     const uint32_t s = t + i * THREADS;
     if (s < C) {
       const bool y_upd = rk[i][2] < n;
-      own_upd[i] = scan(rk[i], sto[i], y_upd ? C : Cu, false);
+      const uint32_t fl = fine_of(decode_coord(rk[i][0]), vmn, fscale);
+      const uint32_t fh = fine_of(decode_coord(rk[i][1]), vmn, fscale);
+      const uint32_t other = y_upd ? kFine : 0u;
+      const uint32_t own = walk<DM1, MODE>(KLO, RID, CO, bin_begin(other + fl), BIN[other + fh],
+                                           rk[i], y_upd ? rk[i][0] : rk[i][0] + 1u, n, hits,
+                                           per_update, pair_off, cursor, out_u, out_s);
+      if (MODE == 1 && own) atomicAdd(&per_update[rk[i][2]], (int)own);
     }
   }
   for (uint32_t k = t; k < nbs; k += THREADS) {
-    uint32_t y[RW];
+    uint32_t y[8];
     const uint4 *src = reinterpret_cast<const uint4 *>(bs_rec + (size_t)(bs_begin + k) * RW);
     const uint4 a = src[0];
     y[0] = a.x;
     y[1] = a.y;
     y[2] = a.z;
     y[3] = a.w;
+    y[4] = y[5] = y[6] = y[7] = 0;
     if (RW == 8) {
       const uint4 c = src[1];
-      y[4 % RW] = c.x;
-      y[5 % RW] = c.y;
-      y[6 % RW] = c.z;
-      y[7 % RW] = c.w;
+      y[4] = c.x;
+      y[5] = c.y;
+      y[6] = c.z;
+      y[7] = c.w;
     }
     const bool y_upd = y[2] < n;
-    const uint32_t own = scan(y, y_upd ? Cu : 0u, y_upd ? C : Cu, true);
+    const uint32_t fh = fine_of(decode_coord(y[1]), vmn, fscale);
+    const uint32_t other = y_upd ? kFine : 0u;
+    const uint32_t own = walk<DM1, MODE>(KLO, RID, CO, bin_begin(other), BIN[other + fh], y, 0u,
+                                         n, hits, per_update, pair_off, cursor, out_u, out_s);
     if (MODE == 1 && own) atomicAdd(&per_update[y[2]], (int)own);
-  }
-  if (MODE == 1) {
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i)
-      if (own_upd[i]) atomicAdd(&RC[dest[i]], own_upd[i]);
-    __syncthreads();
-    for (uint32_t j = t; j < Cu; j += THREADS) {
-      const uint32_t c = RC[j];
-      if (c) atomicAdd(&per_update[RID[j]], (int)c);
-    }
   }
   hits = wave_sum(hits);
   if (lane_id() == 0) red64[t / kWave] = hits;
@@ -646,49 +665,73 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   }
 }
 
+struct Ptrs {
+  BucketParams *P;
+  float4 *part;
+  uint32_t *C, *T, *S, *SB, *bs_cur, *rec, *bs_rec;
+  void *scan_tmp;
+  Offsets O;
+};
+
+Ptrs pointers(const BucketArgs &a) {
+  const BucketLayout &L = a.L;
+  char *ws = static_cast<char *>(a.ws);
+  Ptrs p;
+  p.P = reinterpret_cast<BucketParams *>(ws + L.params);
+  p.part = reinterpret_cast<float4 *>(ws + L.sample_part);
+  p.C = reinterpret_cast<uint32_t *>(ws + L.counts);
+  p.T = reinterpret_cast<uint32_t *>(ws + L.transposed);
+  p.S = reinterpret_cast<uint32_t *>(ws + L.offsets);
+  p.SB = reinterpret_cast<uint32_t *>(ws + L.block_offsets);
+  p.bs_cur = reinterpret_cast<uint32_t *>(ws + L.bs_cur);
+  p.rec = reinterpret_cast<uint32_t *>(ws + L.rec);
+  p.bs_rec = reinterpret_cast<uint32_t *>(ws + L.bs_rec);
+  p.scan_tmp = ws + L.scan_tmp;
+  p.O.S = p.S;
+  p.O.cells = (size_t)L.nb * L.nblk;
+  p.O.nblk = L.nblk;
+  p.O.nb = L.nb;
+  return p;
+}
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
 template <int D>
 void prepare_impl(const BucketArgs &a, hipStream_t s) {
   const BucketLayout &L = a.L;
-  char *ws = static_cast<char *>(a.ws);
-  auto P = reinterpret_cast<BucketParams *>(ws + L.params);
-  auto part = reinterpret_cast<float4 *>(ws + L.sample_part);
-  auto counts = reinterpret_cast<uint32_t *>(ws + L.counts);
-  auto offsets = reinterpret_cast<uint32_t *>(ws + L.offsets);
-  auto bstart = reinterpret_cast<uint32_t *>(ws + L.bstart);
-  auto bs_diff = reinterpret_cast<int *>(ws + L.bs_diff);
-  auto bs_off = reinterpret_cast<uint32_t *>(ws + L.bs_off);
-  auto bs_cur = reinterpret_cast<uint32_t *>(ws + L.bs_cur);
-  auto rec = reinterpret_cast<uint32_t *>(ws + L.rec);
-  auto bs_rec = reinterpret_cast<uint32_t *>(ws + L.bs_rec);
+  Ptrs p = pointers(a);
+  const size_t cells = p.O.cells;
   const size_t lds = (size_t)L.nb * sizeof(uint32_t);
-
+  const int vec = aligned16(a.ulo) && aligned16(a.uhi) && aligned16(a.slo) && aligned16(a.shi);
   prof::mark(s, "bucket.sample");
-  bk_sample_kernel<D><<<kSampleBlocks, kThreads, 0, s>>>(a.ulo, a.uhi, a.slo, a.shi, a.n, a.m, part);
-  bk_plan_kernel<<<1, 64, 0, s>>>(part, kSampleBlocks, L.nb, P);
+  bk_sample_kernel<D><<<kSampleBlocks, kSampleThreads, 0, s>>>(a.ulo, a.uhi, a.slo, a.shi, a.n,
+                                                               a.m, p.part);
+  bk_plan_kernel<<<1, kSampleThreads, 0, s>>>(p.part, L.nb, p.P);
   prof::mark(s, "bucket.count");
-  hipMemsetAsync(bs_diff, 0, (size_t)(L.nb + 1) * sizeof(int), s);
-  bk_count_kernel<D><<<L.nblk, kThreads, lds, s>>>(a.ulo, a.uhi, a.slo, a.shi, a.n, a.m, P, L.nb,
-                                                   counts, L.nblk, bs_diff, a.hdr);
-  exclusive_scan_u32(counts, offsets, (size_t)L.nb * L.nblk, ws + L.scan_tmp, s);
-  prof::mark(s, "bucket.finalize");
-  bk_finalize_kernel<<<1, kThreads, 0, s>>>(counts, offsets, L.nb, L.nblk, bs_diff, L.bs_cap,
-                                            bstart, bs_off, bs_cur, a.hdr);
+  hipMemsetAsync(p.T + cells, 0, (size_t)(L.nb + 1) * sizeof(uint32_t), s);
+  bk_count_kernel<D><<<L.nblk, kThreads, lds, s>>>(a.ulo, a.uhi, a.slo, a.shi, a.n, a.m, vec, p.P,
+                                                   L.nb, L.gpb, p.C, p.T + cells, a.hdr);
+  prof::mark(s, "bucket.offsets");
+  transpose_kernel<<<dim3((L.nb + 63) / 64, (L.nblk + 63) / 64), 256, 0, s>>>(p.C, p.T, L.nblk,
+                                                                              L.nb);
+  exclusive_scan_u32(p.T, p.S, cells + L.nb + 1, p.scan_tmp, s);
+  transpose_kernel<<<dim3((L.nblk + 63) / 64, (L.nb + 63) / 64), 256, 0, s>>>(p.S, p.SB, L.nb,
+                                                                              L.nblk);
   prof::mark(s, "bucket.scatter");
-  bk_scatter_kernel<D><<<L.nblk, kThreads, lds, s>>>(a.ulo, a.uhi, a.slo, a.shi, a.n, a.m, P, L.nb,
-                                                     offsets, L.nblk, bs_off, bs_cur, L.bs_cap, rec,
-                                                     bs_rec);
+  hipMemsetAsync(p.bs_cur, 0, (size_t)L.nb * sizeof(uint32_t), s);
+  bk_scatter_kernel<D><<<L.nblk, kThreads, lds, s>>>(a.ulo, a.uhi, a.slo, a.shi, a.n, a.m, vec, p.P,
+                                                     L.gpb, p.O, p.SB, p.bs_cur, L.bs_cap, p.rec,
+                                                     p.bs_rec);
 }
 
 template <int DM1, int MODE>
 void sweep_impl(const BucketArgs &a, int32_t *per_update, const unsigned long long *pair_off,
                 uint32_t *cursor, uint32_t *out_u, uint32_t *out_s, unsigned long long *total,
                 hipStream_t s) {
-  const BucketLayout &L = a.L;
-  char *ws = static_cast<char *>(a.ws);
-  bk_sweep_kernel<DM1, MODE, kCap, kSweepThreads><<<L.nb, kSweepThreads, 0, s>>>(
-      reinterpret_cast<const uint32_t *>(ws + L.rec), reinterpret_cast<const uint32_t *>(ws + L.bstart),
-      reinterpret_cast<const uint32_t *>(ws + L.bs_rec), reinterpret_cast<const uint32_t *>(ws + L.bs_off),
-      a.n, a.hdr, per_update, pair_off, cursor, out_u, out_s, total);
+  Ptrs p = pointers(a);
+  bk_sweep_kernel<DM1, MODE, kCap, kSweepThreads><<<a.L.nb, kSweepThreads, 0, s>>>(
+      p.rec, p.O, p.bs_rec, a.L.bs_cap, a.n, a.hdr, per_update, pair_off, cursor, out_u, out_s,
+      total);
 }
 
 }  // namespace
@@ -706,8 +749,12 @@ BucketLayout bucket_layout(int64_t n, int64_t m, int d) {
   const uint64_t N = (uint64_t)(n + m);
   L.nb = (uint32_t)((N + kTargetBucket - 1) / kTargetBucket);
   if (L.nb < 1) L.nb = 1;
-  L.nblk = (uint32_t)((N + kRegionsPerBlock - 1) / kRegionsPerBlock);
-  if (L.nblk < 1) L.nblk = 1;
+  const uint64_t groups = (uint64_t)((n + 3) / 4) + (uint64_t)((m + 3) / 4);
+  uint64_t nblk = (groups + kThreads - 1) / kThreads;  // at least one group per thread
+  if (nblk > kMaxBlocks) nblk = kMaxBlocks;
+  if (nblk < 1) nblk = 1;
+  L.nblk = (uint32_t)nblk;
+  L.gpb = (uint32_t)((groups + nblk - 1) / nblk);
   L.bs_cap = (uint32_t)(N / 2 + 4096);
   L.rec_words = d == 1 ? 4 : 8;
   size_t at = 0;
@@ -717,14 +764,14 @@ BucketLayout bucket_layout(int64_t n, int64_t m, int d) {
     return o;
   };
   const size_t cells = (size_t)L.nb * L.nblk;
+  const size_t scanned = cells + L.nb + 1;  // counts + boundary-state sizes + sentinel
   L.params = take(sizeof(BucketParams));
   L.sample_part = take(kSampleBlocks * sizeof(float4));
   L.counts = take(cells * sizeof(uint32_t));
-  L.offsets = take(cells * sizeof(uint32_t));
-  L.scan_tmp = take(scan_temp_bytes(cells));
-  L.bstart = take((size_t)(L.nb + 1) * sizeof(uint32_t));
-  L.bs_diff = take((size_t)(L.nb + 1) * sizeof(int));
-  L.bs_off = take((size_t)(L.nb + 1) * sizeof(uint32_t));
+  L.transposed = take(scanned * sizeof(uint32_t));
+  L.offsets = take(scanned * sizeof(uint32_t));
+  L.block_offsets = take(cells * sizeof(uint32_t));
+  L.scan_tmp = take(scan_temp_bytes(scanned));
   L.bs_cur = take((size_t)L.nb * sizeof(uint32_t));
   L.rec = take((size_t)N * L.rec_words * sizeof(uint32_t));
   L.bs_rec = take((size_t)L.bs_cap * L.rec_words * sizeof(uint32_t));

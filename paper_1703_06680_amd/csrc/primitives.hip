@@ -103,7 +103,6 @@ hipError_t exclusive_scan_impl(const T *in, T *out, size_t count, void *temp, hi
   if (count == 0) return hipSuccess;
   size_t nb = div_up(count, kScanChunk);
   T *sums = static_cast<T *>(temp);
-  prof::mark(s, "scan");
   scan_reduce_kernel<T><<<dim3((unsigned)nb), dim3(kScanThreads), 0, s>>>(in, count, sums);
   scan_block_sums_kernel<T><<<dim3(1), dim3(kScanThreads), 0, s>>>(sums, nb);
   scan_apply_kernel<T><<<dim3((unsigned)nb), dim3(kScanThreads), 0, s>>>(in, out, count, sums);
