@@ -51,10 +51,12 @@ constexpr int kCap = 2048;
 constexpr int kFine = 512;
 
 struct BucketParams {
-  float vmin;
+  float vmin;        // bucket map of the swept axis' lower coordinate
   float scale;
   uint32_t nb;
   uint32_t valid;
+  float qmin[2];     // 16-bit quantisation of the other axes (pre-filter)
+  float qscale[2];
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -135,87 +137,121 @@ struct Offsets {
 template <int D>
 __global__ __launch_bounds__(kSampleThreads) void bk_sample_kernel(
     const float *__restrict__ ulo, const float *__restrict__ uhi, const float *__restrict__ slo,
-    const float *__restrict__ shi, uint32_t n, uint32_t m, float4 *__restrict__ part) {
-  __shared__ float smin[kSampleThreads / kWave], smax[kSampleThreads / kWave];
-  __shared__ uint32_t scnt[kSampleThreads / kWave];
+    const float *__restrict__ shi, uint32_t n, uint32_t m, float *__restrict__ part) {
+  // per block: min/max of the swept lower coordinate, count, and for the
+  // other axes min(lo) / max(hi), over the sampled valid non-empty boxes
+  constexpr int W = kSampleThreads / kWave;
+  __shared__ float sred[W][8];
   const uint32_t N = n + m;
-  float mn = __int_as_float(0x7f800000), mx = -__int_as_float(0x7f800000);
-  uint32_t c = 0;
+  const float inf = __int_as_float(0x7f800000);
+  float v[8] = {inf, -inf, 0.f, 0.f, inf, -inf, inf, -inf};
   const uint32_t i = blockIdx.x * kSampleThreads + threadIdx.x;
   const uint32_t r =
       (uint32_t)(((unsigned long long)mix32(i * 0x9E3779B9u + 0x632BE5ABu) * N) >> 32);
   const Box<D> b = load_box<D>(ulo, uhi, slo, shi, n, r);
   bool empty;
   const uint32_t err = box_errors<D>(b, empty);
-  const float x = b.lo[0];
-  if (!err && !empty && fabsf(x) <= 3.0e38f) {
-    mn = x;
-    mx = x;
-    c = 1;
+  bool ok = !err && !empty && fabsf(b.lo[0]) <= 3.0e38f;
+#pragma unroll
+  for (int k = 1; k < D; ++k) ok = ok && fabsf(b.lo[k]) <= 3.0e38f && fabsf(b.hi[k]) <= 3.0e38f;
+  if (ok) {
+    v[0] = v[1] = b.lo[0];
+    v[2] = 1.f;
+#pragma unroll
+    for (int k = 1; k < D; ++k) {
+      v[4 + 2 * (k - 1)] = b.lo[k];
+      v[5 + 2 * (k - 1)] = b.hi[k];
+    }
   }
-  mn = wave_min(mn);
-  mx = wave_max(mx);
-  c = wave_sum(c);
+#pragma unroll
+  for (int k = 0; k < 8; k += 2) {
+    if (k == 2) continue;  // slot 2 is the sample count, summed below
+    v[k] = wave_min(v[k]);
+    v[k + 1] = wave_max(v[k + 1]);
+  }
+  v[2] = wave_sum(v[2]);
   const int w = threadIdx.x / kWave;
-  if (lane_id() == 0) {
-    smin[w] = mn;
-    smax[w] = mx;
-    scnt[w] = c;
-  }
+  if (lane_id() == 0)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sred[w][k] = v[k];
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int k = 1; k < kSampleThreads / kWave; ++k) {
-      mn = fminf(mn, smin[k]);
-      mx = fmaxf(mx, smax[k]);
-      c += scnt[k];
-    }
-    part[blockIdx.x] = make_float4(mn, mx, __uint_as_float(c), 0.f);
+    for (int j = 1; j < W; ++j)
+#pragma unroll
+      for (int k = 0; k < 8; k += 2) {
+        if (k == 2) continue;
+        v[k] = fminf(v[k], sred[j][k]);
+        v[k + 1] = fmaxf(v[k + 1], sred[j][k + 1]);
+      }
+    float c = 0.f;
+    for (int j = 0; j < W; ++j) c += sred[j][2];
+    v[2] = c;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) part[blockIdx.x * 8 + k] = v[k];
   }
 }
 
-__global__ __launch_bounds__(kSampleThreads) void bk_plan_kernel(const float4 *__restrict__ part,
+__global__ __launch_bounds__(kSampleThreads) void bk_plan_kernel(const float *__restrict__ part,
                                                                  uint32_t nb,
                                                                  BucketParams *__restrict__ P) {
-  __shared__ float smin[kSampleThreads / kWave], smax[kSampleThreads / kWave];
-  __shared__ uint32_t scnt[kSampleThreads / kWave];
-  float mn = __int_as_float(0x7f800000), mx = -__int_as_float(0x7f800000);
-  uint32_t c = 0;
+  constexpr int W = kSampleThreads / kWave;
+  __shared__ float sred[W][8];
+  const float inf = __int_as_float(0x7f800000);
+  float v[8] = {inf, -inf, 0.f, 0.f, inf, -inf, inf, -inf};
   for (int i = threadIdx.x; i < kSampleBlocks; i += kSampleThreads) {
-    const float4 p = part[i];
-    const uint32_t pc = __float_as_uint(p.z);
-    if (pc) {
-      mn = fminf(mn, p.x);
-      mx = fmaxf(mx, p.y);
-      c += pc;
+#pragma unroll
+    for (int k = 0; k < 8; k += 2) {
+      if (k == 2) continue;
+      v[k] = fminf(v[k], part[i * 8 + k]);
+      v[k + 1] = fmaxf(v[k + 1], part[i * 8 + k + 1]);
     }
+    v[2] += part[i * 8 + 2];
   }
-  mn = wave_min(mn);
-  mx = wave_max(mx);
-  c = wave_sum(c);
+#pragma unroll
+  for (int k = 0; k < 8; k += 2) {
+    if (k == 2) continue;  // slot 2 is the sample count, summed below
+    v[k] = wave_min(v[k]);
+    v[k + 1] = wave_max(v[k + 1]);
+  }
+  v[2] = wave_sum(v[2]);
   const int w = threadIdx.x / kWave;
-  if (lane_id() == 0) {
-    smin[w] = mn;
-    smax[w] = mx;
-    scnt[w] = c;
-  }
+  if (lane_id() == 0)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sred[w][k] = v[k];
   __syncthreads();
   if (threadIdx.x != 0) return;
-  for (int k = 1; k < kSampleThreads / kWave; ++k) {
-    mn = fminf(mn, smin[k]);
-    mx = fmaxf(mx, smax[k]);
-    c += scnt[k];
-  }
+  for (int j = 1; j < W; ++j)
+#pragma unroll
+    for (int k = 0; k < 8; k += 2) {
+      if (k == 2) continue;
+      v[k] = fminf(v[k], sred[j][k]);
+      v[k + 1] = fmaxf(v[k + 1], sred[j][k + 1]);
+    }
+  float c = 0.f;
+  for (int j = 0; j < W; ++j) c += sred[j][2];
   BucketParams q;
   q.nb = nb;
   q.vmin = 0.f;
   q.scale = 0.f;
   q.valid = 0;
-  if (c && mx > mn) {
-    const float scale = (float)nb / (mx - mn);
+  if (c > 0.f && v[1] > v[0]) {
+    const float scale = (float)nb / (v[1] - v[0]);
     if (scale > 0.f && scale <= 3.0e38f) {
-      q.vmin = mn;
+      q.vmin = v[0];
       q.scale = scale;
       q.valid = 1;
+    }
+  }
+  for (int k = 0; k < 2; ++k) {
+    const float lo = v[4 + 2 * k], hi = v[5 + 2 * k];
+    q.qmin[k] = 0.f;
+    q.qscale[k] = 0.f;  // every box quantises to 0: the pre-filter lets all pass
+    if (c > 0.f && hi > lo) {
+      const float qs = 65535.0f / (hi - lo);
+      if (qs > 0.f && qs <= 3.0e38f) {
+        q.qmin[k] = lo;
+        q.qscale[k] = qs;
+      }
     }
   }
   *P = q;
@@ -420,94 +456,195 @@ __device__ __forceinline__ uint32_t fine_of(float x, float vmin, float fscale) {
   return (uint32_t)t;
 }
 
-// Walk of region y over other-kind entries [j, jend) of the bucket: keeps x
-// when lo_x comes after lo_y (strictly, or on equal keys when y is the update
-// and x the subscription; "after" always holds for boundary-state regions) and
-// lo_x < hi_y, and the boxes overlap on the other axes.
-template <int DM1, int MODE>
-__device__ __forceinline__ uint32_t walk(const uint32_t *__restrict__ KLO,
-                                         const uint32_t *__restrict__ RID,
-                                         const float *__restrict__ CO, uint32_t j, uint32_t jend,
-                                         const uint32_t *y, uint32_t after_key, uint32_t n,
-                                         unsigned long long &hits,
-                                         int32_t *__restrict__ per_update,
-                                         const unsigned long long *__restrict__ pair_off,
-                                         uint32_t *__restrict__ cursor, uint32_t *__restrict__ out_u,
-                                         uint32_t *__restrict__ out_s) {
-  // x counts iff after_key <= KLO[x] < khi, where after_key is klo_y for an
-  // update y, klo_y + 1 for a subscription y and 0 for the boundary state.
-  constexpr int CW = DM1 == 0 ? 1 : 2 * DM1;
-  const uint32_t khi = y[1];
-  const uint32_t ry = y[2];
-  const bool y_upd = ry < n;
-  float ylo[2] = {0.f, 0.f}, yhi[2] = {0.f, 0.f};
+// Conservative 16-bit quantisation of a coordinate of another axis under a
+// monotone map: lower bounds round down, upper bounds round up, so two boxes
+// that overlap on that axis also overlap after quantisation.  The quantised
+// test is only a pre-filter; survivors are tested on the exact floats.
+__device__ __forceinline__ uint32_t quant_lo(float x, float qmin, float qs) {
+  float t = (x - qmin) * qs;
+  t = fminf(fmaxf(t, 0.0f), 65535.0f);
+  return (uint32_t)t;
+}
+
+__device__ __forceinline__ uint32_t quant_hi(float x, float qmin, float qs) {
+  float t = (x - qmin) * qs;
+  t = fminf(fmaxf(t, 0.0f), 65535.0f);
+  return (uint32_t)ceilf(t);
+}
+
+// Two quantised intervals a = [alo, ahi] and b = [blo, bhi] pass the
+// pre-filter iff alo <= bhi and blo <= ahi.  Stored one as an "entry" word
+// alo | (65535 - ahi) << 16 and the other as a "walker" word
+// bhi | (65535 - blo) << 16, both conditions are one saturating packed
+// subtraction: entry -sat walker is zero in both halves exactly when
+// alo - bhi <= 0 and blo - ahi <= 0.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t qdiff(uint32_t entry, uint32_t walker) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(
+                                          __builtin_bit_cast(u16x2, entry),
+                                          __builtin_bit_cast(u16x2, walker)));
+}
+
+// entry / walker words of the other axes of one record (words 4.. hold
+// lo1, hi1, lo2, hi2)
+template <int DM1>
+__device__ __forceinline__ void qwords(const uint32_t *rw, const BucketParams &p, uint32_t *entry,
+                                       uint32_t *walker) {
 #pragma unroll
   for (int c = 0; c < DM1; ++c) {
-    ylo[c] = __uint_as_float(y[4 + 2 * c]);
-    yhi[c] = __uint_as_float(y[5 + 2 * c]);
+    const uint32_t lq = quant_lo(__uint_as_float(rw[4 + 2 * c]), p.qmin[c], p.qscale[c]);
+    const uint32_t hq = quant_hi(__uint_as_float(rw[5 + 2 * c]), p.qmin[c], p.qscale[c]);
+    if (entry) entry[c] = lq | ((65535u - hq) << 16);
+    if (walker) walker[c] = hq | ((65535u - lq) << 16);
   }
+}
+
+// Padding of the per-bucket LDS arrays: the unrolled interior loop reads up
+// to three entries past its range.
+constexpr int kPad = 4;
+
+// One walking region.  For d >= 2, q holds its walker words; for d = 1 the
+// LDS slot of the other axes holds region ids instead.
+template <int DM1>
+struct Walker {
+  uint32_t klo, khi, after_key;
+  uint32_t q[DM1 > 0 ? DM1 : 1];
+  uint32_t rid;         // valid for d = 1 (and whenever have_y below)
+  const uint32_t *rec;  // exact record (global memory)
+  bool upd;
+};
+
+struct SweepOut {
+  uint32_t n;
+  int32_t *per_update;
+  const unsigned long long *pair_off;
+  uint32_t *cursor;
+  uint32_t *out_u, *out_s;
+};
+
+// A pair of walker y and entry j that passed the key and pre-filter tests:
+// exact test on the other axes (d >= 2), then count or emit.
+template <int DM1, int MODE>
+__device__ __forceinline__ void visit(Walker<DM1> &y, bool &have_y, float (&ylo)[2],
+                                      float (&yhi)[2], uint32_t j,
+                                      const uint32_t *__restrict__ GIDX,
+                                      const uint32_t *__restrict__ Q,
+                                      const uint32_t *__restrict__ rec, unsigned long long &hits,
+                                      uint32_t &own, const SweepOut &o) {
+  uint32_t rx;
+  if (DM1 > 0) {
+    if (!have_y) {
+      have_y = true;
+      const uint4 a = *reinterpret_cast<const uint4 *>(y.rec);
+      const uint4 c = *reinterpret_cast<const uint4 *>(y.rec + 4);
+      y.rid = a.z;
+      ylo[0] = __uint_as_float(c.x);
+      yhi[0] = __uint_as_float(c.y);
+      ylo[1] = __uint_as_float(c.z);
+      yhi[1] = __uint_as_float(c.w);
+    }
+    const uint32_t *xr = rec + (size_t)GIDX[j] * 8;
+    const uint4 c = *reinterpret_cast<const uint4 *>(xr + 4);
+    bool hit = ylo[0] < __uint_as_float(c.y) && __uint_as_float(c.x) < yhi[0];
+    if (DM1 > 1) hit = hit && ylo[1] < __uint_as_float(c.w) && __uint_as_float(c.z) < yhi[1];
+    if (!hit) return;
+    rx = MODE == 0 ? 0u : xr[2];
+  } else {
+    rx = Q[j];
+  }
+  ++hits;
+  if (MODE == 1) {
+    if (y.upd)
+      ++own;
+    else
+      atomicAdd(&o.per_update[rx], 1);
+  } else if (MODE == 2) {
+    const uint32_t uu = y.upd ? y.rid : rx;
+    const uint32_t sid = (y.upd ? rx : y.rid) - o.n;
+    const unsigned long long slot = o.pair_off[uu] + atomicAdd(&o.cursor[uu], 1u);
+    o.out_u[slot] = uu;
+    o.out_s[slot] = sid;
+  }
+}
+
+template <int DM1>
+__device__ __forceinline__ bool qpass(const uint32_t *__restrict__ Q, uint32_t j,
+                                      const Walker<DM1> &y) {
+  if (DM1 == 2) {
+    const uint2 e = reinterpret_cast<const uint2 *>(Q)[j];
+    return (qdiff(e.x, y.q[0]) | qdiff(e.y, y.q[DM1 - 1])) == 0u;
+  }
+  if (DM1 == 1) return qdiff(Q[j], y.q[0]) == 0u;
+  return true;
+}
+
+// Walk of y over the other kind's entries [jA, jD) of the bucket.  Entries in
+// [jA, jB) (the first fine bin) must come after y's lower endpoint
+// (KLO >= after_key), entries in [jC, jD) (the last fine bin) must start
+// before its upper endpoint (KLO < khi); entries of the bins in between
+// satisfy both by the monotonicity of the fine-bin map, so that loop only
+// runs the pre-filter.
+template <int DM1, int MODE>
+__device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
+                                     const uint32_t *__restrict__ GIDX,
+                                     const uint32_t *__restrict__ Q, Walker<DM1> &y, uint32_t jA,
+                                     uint32_t jB, uint32_t jC, uint32_t jD,
+                                     const uint32_t *__restrict__ rec, unsigned long long &hits,
+                                     const SweepOut &o) {
   uint32_t own = 0;
-  for (; j < jend; j += 4) {
-    uint32_t idx[4];
-    bool hit[4];
+  bool have_y = DM1 == 0;
+  float ylo[2] = {0.f, 0.f}, yhi[2] = {0.f, 0.f};
+  // edge entries: the first bin, then the part of the last bin past it
+  const uint32_t e1 = jB - jA;
+  const uint32_t jC2 = jC > jB ? jC : jB;
+  const uint32_t e = e1 + (jD - jC2);
+  for (uint32_t t = 0; t < e; ++t) {
+    const uint32_t j = t < e1 ? jA + t : jC2 + (t - e1);
+    const uint32_t k = KLO[j];
+    if (k >= y.after_key && k < y.khi && qpass<DM1>(Q, j, y))
+      visit<DM1, MODE>(y, have_y, ylo, yhi, j, GIDX, Q, rec, hits, own, o);
+  }
+  // interior bins
+  if (DM1 == 0 && MODE == 0) {
+    if (jC > jB) hits += jC - jB;
+  } else {
+    for (uint32_t j = jB; j < jC; j += 4) {
+      uint32_t msk = 0;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      idx[u] = j + u < jend ? j + u : jend - 1;
-      const uint32_t k = KLO[idx[u]];
-      hit[u] = (j + u < jend) && k >= after_key && k < khi;
-    }
+      for (int u = 0; u < 4; ++u) msk |= qpass<DM1>(Q, j + u, y) ? (1u << u) : 0u;
+      if (jC - j < 4) msk &= (1u << (jC - j)) - 1u;
+      if (msk) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (DM1 == 1) {
-        const float2 xc = *reinterpret_cast<const float2 *>(&CO[idx[u] * CW]);
-        hit[u] = hit[u] && ylo[0] < xc.y && xc.x < yhi[0];
-      } else if (DM1 == 2) {
-        const float4 xc = *reinterpret_cast<const float4 *>(&CO[idx[u] * CW]);
-        hit[u] = hit[u] && ylo[0] < xc.y && xc.x < yhi[0] && ylo[1] < xc.w && xc.z < yhi[1];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (!hit[u]) continue;
-      ++hits;
-      if (MODE == 1) {
-        if (y_upd)
-          ++own;
-        else
-          atomicAdd(&per_update[RID[idx[u]]], 1);
-      } else if (MODE == 2) {
-        const uint32_t rx = RID[idx[u]];
-        const uint32_t uu = y_upd ? ry : rx;
-        const uint32_t sid = (y_upd ? rx : ry) - n;
-        const unsigned long long slot = pair_off[uu] + atomicAdd(&cursor[uu], 1u);
-        out_u[slot] = uu;
-        out_s[slot] = sid;
+        for (int u = 0; u < 4; ++u)
+          if (msk & (1u << u)) visit<DM1, MODE>(y, have_y, ylo, yhi, j + u, GIDX, Q, rec, hits, own, o);
       }
     }
   }
-  return own;
+  if (MODE == 1 && own) atomicAdd(&o.per_update[y.rid], (int)own);
 }
 
 template <int DM1, int MODE, int CAP, int THREADS>
 __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
     const uint32_t *__restrict__ rec, Offsets O, const uint32_t *__restrict__ bs_rec,
-    uint32_t bs_cap, uint32_t n, Header *__restrict__ hdr, int32_t *__restrict__ per_update,
-    const unsigned long long *__restrict__ pair_off, uint32_t *__restrict__ cursor,
-    uint32_t *__restrict__ out_u, uint32_t *__restrict__ out_s,
+    uint32_t bs_cap, uint32_t n, const BucketParams *__restrict__ P, Header *__restrict__ hdr,
+    int32_t *__restrict__ per_update, const unsigned long long *__restrict__ pair_off,
+    uint32_t *__restrict__ cursor, uint32_t *__restrict__ out_u, uint32_t *__restrict__ out_s,
     unsigned long long *__restrict__ total) {
   constexpr int RW = DM1 == 0 ? 4 : 8;
-  constexpr int NC = 2 * DM1;            // other-axis words per record
-  constexpr int CW = DM1 == 0 ? 1 : NC;  // LDS words per element for coords
+  constexpr int QW = DM1 > 0 ? DM1 : 1;
   constexpr int ITEMS = CAP / THREADS;
   constexpr int W = THREADS / kWave;
   constexpr int NBINS = 2 * kFine;
-  constexpr int BPT = NBINS / THREADS;   // bins per thread in the scan
+  constexpr int BPT = NBINS / THREADS;  // bins per thread in the scan
   static_assert(NBINS % THREADS == 0, "bins must split evenly over the threads");
-  // the bucket in LDS, in fine-bin order (updates first): lower key, region
-  // index and the other axes' lo/hi of every region
-  __shared__ uint32_t KLO[CAP];
-  __shared__ uint32_t RID[CAP];
-  __shared__ __align__(16) float CO[DM1 == 0 ? 4 : CAP * CW];
+  // the bucket in LDS, in fine-bin order (updates first): lower and upper
+  // key, global record index and the pre-filter words of the other axes
+  // (region ids for d = 1) of every region
+  __shared__ uint32_t KLO[CAP + kPad];
+  __shared__ uint32_t KHI[CAP + kPad];
+  __shared__ uint32_t GIDX[DM1 > 0 ? CAP + kPad : 1];
+  __shared__ __align__(16) uint32_t Q[(CAP + kPad) * QW];
   __shared__ uint32_t BIN[NBINS];
   __shared__ float redf[2 * W + 2];
   __shared__ uint32_t red[W + 2];
@@ -523,9 +660,11 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   }
   const uint32_t bs_begin = O.bs_begin(b);
   const uint32_t nbs = O.bs_begin(b + 1) - bs_begin;
+  const BucketParams prm = *P;
   const int t = threadIdx.x;
+  const SweepOut o{n, per_update, pair_off, cursor, out_u, out_s};
 
-  // 1. own records into registers (slot s = t + i * THREADS); value range
+  // 1. records into registers (slot s = t + i * THREADS); value range
   uint32_t rk[ITEMS][RW];
   float vmn = __int_as_float(0x7f800000), vmx = -__int_as_float(0x7f800000);
 #pragma unroll
@@ -560,6 +699,11 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
     redf[2 * (t / kWave) + 1] = vmx;
   }
   for (int k = t; k < NBINS; k += THREADS) BIN[k] = 0;
+  if (t < kPad) {  // defined values in the padding (never counted)
+    KLO[CAP + t] = 0;
+#pragma unroll
+    for (int c = 0; c < QW; ++c) Q[(CAP + t) * QW + c] = 0;
+  }
   __syncthreads();
   vmn = redf[0];
   vmx = redf[1];
@@ -605,55 +749,90 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   for (int i = 0; i < ITEMS; ++i) {
     const uint32_t s = t + i * THREADS;
     if (s < C) {
-      const uint32_t q = atomicAdd(&BIN[key[i]], 1u);
-      KLO[q] = rk[i][0];
-      RID[q] = rk[i][2];
+      const uint32_t qpos = atomicAdd(&BIN[key[i]], 1u);
+      KLO[qpos] = rk[i][0];
+      KHI[qpos] = rk[i][1];
+      if (DM1 > 0) {
+        GIDX[qpos] = start + s;
+        uint32_t q[QW];
+        qwords<DM1>(rk[i], prm, q, nullptr);
 #pragma unroll
-      for (int c = 0; c < NC; ++c) CO[q * CW + c] = __uint_as_float(rk[i][4 + c]);
+        for (int c = 0; c < QW; ++c) Q[qpos * QW + c] = q[c];
+      } else {
+        Q[qpos] = rk[i][2];
+      }
     }
   }
   __syncthreads();
   // BIN[k] is now the end of fine bin k; bin k starts at BIN[k - 1] (0 for k = 0)
   auto bin_begin = [&](uint32_t k) { return k ? BIN[k - 1] : 0u; };
+  const uint32_t Cu = BIN[kFine - 1];  // updates occupy [0, Cu)
 
-  // 3. the walks: every region of the bucket, then the boundary state
+  // 3. the walks, in bin order: the lanes of a wave take consecutive entries,
+  //    so they walk neighbouring, overlapping ranges of the other kind
   unsigned long long hits = 0;
+  const int lane = lane_id(), w = t / kWave;
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
-    const uint32_t s = t + i * THREADS;
-    if (s < C) {
-      const bool y_upd = rk[i][2] < n;
-      const uint32_t fl = fine_of(decode_coord(rk[i][0]), vmn, fscale);
-      const uint32_t fh = fine_of(decode_coord(rk[i][1]), vmn, fscale);
-      const uint32_t other = y_upd ? kFine : 0u;
-      const uint32_t own = walk<DM1, MODE>(KLO, RID, CO, bin_begin(other + fl), BIN[other + fh],
-                                           rk[i], y_upd ? rk[i][0] : rk[i][0] + 1u, n, hits,
-                                           per_update, pair_off, cursor, out_u, out_s);
-      if (MODE == 1 && own) atomicAdd(&per_update[rk[i][2]], (int)own);
+    const uint32_t qy = (uint32_t)(w * (kWave * ITEMS) + i * kWave + lane);
+    if (qy < C) {
+      Walker<DM1> y;
+      y.klo = KLO[qy];
+      y.khi = KHI[qy];
+      y.upd = qy < Cu;
+      y.after_key = y.upd ? y.klo : y.klo + 1u;
+      if (DM1 > 0) {
+        y.rec = rec + (size_t)GIDX[qy] * RW;
+        // walker words from the entry words: swap halves back to (lo, hi)
+#pragma unroll
+        for (int c = 0; c < DM1; ++c) {
+          const uint32_t ew = Q[qy * QW + c];
+          const uint32_t lq = ew & 0xFFFFu, hq = 65535u - (ew >> 16);
+          y.q[c] = hq | ((65535u - lq) << 16);
+        }
+        y.rid = 0;
+      } else {
+        y.rec = nullptr;
+        y.rid = Q[qy];
+        y.q[0] = 0;
+      }
+      const uint32_t fl = fine_of(decode_coord(y.klo), vmn, fscale);
+      const uint32_t fh = fine_of(decode_coord(y.khi), vmn, fscale);
+      const uint32_t other = y.upd ? kFine : 0u;
+      walk<DM1, MODE>(KLO, GIDX, Q, y, bin_begin(other + fl), BIN[other + fl],
+                      bin_begin(other + fh), BIN[other + fh], rec, hits, o);
     }
   }
   for (uint32_t k = t; k < nbs; k += THREADS) {
-    uint32_t y[8];
-    const uint4 *src = reinterpret_cast<const uint4 *>(bs_rec + (size_t)(bs_begin + k) * RW);
-    const uint4 a = src[0];
-    y[0] = a.x;
-    y[1] = a.y;
-    y[2] = a.z;
-    y[3] = a.w;
-    y[4] = y[5] = y[6] = y[7] = 0;
+    const uint32_t *yr = bs_rec + (size_t)(bs_begin + k) * RW;
+    uint32_t yw[8];
+    const uint4 a = *reinterpret_cast<const uint4 *>(yr);
+    yw[0] = a.x;
+    yw[1] = a.y;
+    yw[2] = a.z;
+    yw[3] = a.w;
+    yw[4] = yw[5] = yw[6] = yw[7] = 0;
     if (RW == 8) {
-      const uint4 c = src[1];
-      y[4] = c.x;
-      y[5] = c.y;
-      y[6] = c.z;
-      y[7] = c.w;
+      const uint4 c = *reinterpret_cast<const uint4 *>(yr + 4);
+      yw[4] = c.x;
+      yw[5] = c.y;
+      yw[6] = c.z;
+      yw[7] = c.w;
     }
-    const bool y_upd = y[2] < n;
-    const uint32_t fh = fine_of(decode_coord(y[1]), vmn, fscale);
-    const uint32_t other = y_upd ? kFine : 0u;
-    const uint32_t own = walk<DM1, MODE>(KLO, RID, CO, bin_begin(other), BIN[other + fh], y, 0u,
-                                         n, hits, per_update, pair_off, cursor, out_u, out_s);
-    if (MODE == 1 && own) atomicAdd(&per_update[y[2]], (int)own);
+    Walker<DM1> y;
+    y.klo = yw[0];
+    y.khi = yw[1];
+    y.rid = yw[2];
+    y.upd = yw[2] < n;
+    y.after_key = 0u;  // every lower endpoint of the bucket comes after it
+    y.q[0] = 0;
+    if (DM1 > 0) qwords<DM1>(yw, prm, nullptr, y.q);
+    y.rec = yr;
+    const uint32_t fh = fine_of(decode_coord(y.khi), vmn, fscale);
+    const uint32_t other = y.upd ? kFine : 0u;
+    const uint32_t jA = bin_begin(other);
+    walk<DM1, MODE>(KLO, GIDX, Q, y, jA, jA, bin_begin(other + fh), BIN[other + fh], rec, hits,
+                    o);
   }
   hits = wave_sum(hits);
   if (lane_id() == 0) red64[t / kWave] = hits;
@@ -667,7 +846,7 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
 
 struct Ptrs {
   BucketParams *P;
-  float4 *part;
+  float *part;
   uint32_t *C, *T, *S, *SB, *bs_cur, *rec, *bs_rec;
   void *scan_tmp;
   Offsets O;
@@ -678,7 +857,7 @@ Ptrs pointers(const BucketArgs &a) {
   char *ws = static_cast<char *>(a.ws);
   Ptrs p;
   p.P = reinterpret_cast<BucketParams *>(ws + L.params);
-  p.part = reinterpret_cast<float4 *>(ws + L.sample_part);
+  p.part = reinterpret_cast<float *>(ws + L.sample_part);
   p.C = reinterpret_cast<uint32_t *>(ws + L.counts);
   p.T = reinterpret_cast<uint32_t *>(ws + L.transposed);
   p.S = reinterpret_cast<uint32_t *>(ws + L.offsets);
@@ -730,8 +909,8 @@ void sweep_impl(const BucketArgs &a, int32_t *per_update, const unsigned long lo
                 hipStream_t s) {
   Ptrs p = pointers(a);
   bk_sweep_kernel<DM1, MODE, kCap, kSweepThreads><<<a.L.nb, kSweepThreads, 0, s>>>(
-      p.rec, p.O, p.bs_rec, a.L.bs_cap, a.n, a.hdr, per_update, pair_off, cursor, out_u, out_s,
-      total);
+      p.rec, p.O, p.bs_rec, a.L.bs_cap, a.n, p.P, a.hdr, per_update, pair_off, cursor, out_u,
+      out_s, total);
 }
 
 }  // namespace
@@ -766,7 +945,7 @@ BucketLayout bucket_layout(int64_t n, int64_t m, int d) {
   const size_t cells = (size_t)L.nb * L.nblk;
   const size_t scanned = cells + L.nb + 1;  // counts + boundary-state sizes + sentinel
   L.params = take(sizeof(BucketParams));
-  L.sample_part = take(kSampleBlocks * sizeof(float4));
+  L.sample_part = take(kSampleBlocks * 8 * sizeof(float));
   L.counts = take(cells * sizeof(uint32_t));
   L.transposed = take(scanned * sizeof(uint32_t));
   L.offsets = take(scanned * sizeof(uint32_t));
