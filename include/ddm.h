@@ -101,6 +101,112 @@ int ddm_match(const float *upd_lo, const float *upd_hi, int64_t n,
               uint64_t *count_host, int32_t *per_update,
               int32_t *pairs, int64_t pair_capacity);
 
+/* ------------------------------------------------------------------------
+ * Batches of independent instances.
+ *
+ * B instances of the problem above (Sec. 3) are stored back to back: instance
+ * b has the update rows [upd_off[b], upd_off[b+1]) of upd_lo / upd_hi and the
+ * subscription rows [sub_off[b], sub_off[b+1]) of sub_lo / sub_hi.  upd_off
+ * and sub_off are HOST arrays of B + 1 int64 offsets, starting at 0 and
+ * non-decreasing; instances may be empty.  Every instance is matched on its
+ * own, exactly as ddm_match() would match it; ids in the outputs are local to
+ * the instance (0-based within its rows).  All instances share one launch
+ * sequence: every kernel covers the buckets, blocks and pairs of the whole
+ * batch, which is what makes small instances cheap.  The outputs:
+ *
+ *   counts      device, out, uint64 [B]: pairs of each instance (required)
+ *   per_update  device, out, int32 [upd_off[B]]: matches of every update, at
+ *               its row; required for DDM_PER_UPDATE, optional for DDM_PAIRS
+ *   pairs       device, out, int32 [pair_capacity][2]: instance b's pairs at
+ *               rows [pair_off[b], pair_off[b+1]), each instance's in
+ *               lexicographic order; DDM_PAIRS only
+ *   pair_off    device, out, int64 [B + 1]; DDM_PAIRS only (set also when the
+ *               pairs do not fit, so the caller learns the size it needs)
+ *
+ * Totals over the batch must stay below 2^31 updates + subscriptions and
+ * pair_capacity below 2^31.
+ * ------------------------------------------------------------------------ */
+
+/* Launch-shape parameters of the batched path (see ddm_batch_autotune). */
+typedef struct ddm_tuning {
+  int32_t target;            /* mean regions per bucket, 64 .. 1536           */
+  int32_t sweep_threads;     /* threads of a sweep workgroup: 256 or 512      */
+  int32_t groups_per_thread; /* count/scatter: groups of 4 rows per thread    */
+  int32_t max_blocks;        /* count/scatter workgroups per instance at most */
+} ddm_tuning;
+
+/* The tuning used when none is given. */
+void ddm_default_tuning(ddm_tuning *out);
+
+/*
+ * Workspace bytes that ddm_match_batched() and ddm_batch_graph_create() need
+ * for this batch under the given tuning, or, if tuning is NULL, under the
+ * default tuning and every candidate of ddm_batch_autotune() (so that one
+ * workspace serves the autotuner), in both cases including what the
+ * per-instance fallback needs.  Returns 0 for arguments the calls would
+ * reject.  A call given a tuning whose need exceeds ws_bytes returns
+ * DDM_E_WORKSPACE.
+ */
+size_t ddm_batch_workspace_bytes(const int64_t *upd_off, const int64_t *sub_off, int64_t B, int d,
+                                 int mode, int64_t pair_capacity, const ddm_tuning *tuning);
+
+/*
+ * Matches every instance of the batch (arguments as described above; the
+ * other arguments as for ddm_match()).  tuning may be NULL (default).  The
+ * call synchronises with the stream and sets *total_host (required) to the
+ * sum of counts.  Errors: as ddm_match(); DDM_E_CAPACITY if the pairs of all
+ * instances exceed pair_capacity (counts, per_update and pair_off are then
+ * complete, pairs untouched).  When a bucket of some instance overflows its
+ * on-chip buffer, or d > 3, the instances are matched one by one with the
+ * device-wide path instead (same results).
+ */
+int ddm_match_batched(const float *upd_lo, const float *upd_hi, const int64_t *upd_off,
+                      const float *sub_lo, const float *sub_hi, const int64_t *sub_off,
+                      int64_t B, int d, int mode, void *workspace, size_t ws_bytes, void *stream,
+                      const ddm_tuning *tuning, uint64_t *counts, uint64_t *total_host,
+                      int32_t *per_update, int32_t *pairs, int64_t *pair_off,
+                      int64_t pair_capacity);
+
+/*
+ * The batch as one captured HIP graph.  ddm_batch_graph_create() validates
+ * the arguments, writes the batch plan into the workspace and captures every
+ * launch of ddm_match_batched() (from zeroing the outputs to the ordered
+ * pairs) into a graph, with the pointers and sizes given here; the buffers
+ * must stay valid and the workspace reserved for the graph until it is
+ * destroyed.  ddm_batch_graph_launch() enqueues one replay on a stream and
+ * returns at once; the input arrays may be rewritten between replays (same
+ * sizes).  ddm_batch_graph_result() waits for the stream, sets *total_host
+ * and returns what ddm_match_batched() would return for that replay (running
+ * the per-instance fallback itself if a bucket overflowed).  tuning may be
+ * NULL (default).  Errors of create: as ddm_match_batched() for the
+ * arguments, DDM_E_UNSUPPORTED if d > 3 or the batch does not fit the
+ * bucketed plan, DDM_E_DEVICE if capture fails.
+ */
+typedef struct ddm_batch_graph ddm_batch_graph;
+int ddm_batch_graph_create(const float *upd_lo, const float *upd_hi, const int64_t *upd_off,
+                           const float *sub_lo, const float *sub_hi, const int64_t *sub_off,
+                           int64_t B, int d, int mode, void *workspace, size_t ws_bytes,
+                           const ddm_tuning *tuning, uint64_t *counts, int32_t *per_update,
+                           int32_t *pairs, int64_t *pair_off, int64_t pair_capacity,
+                           ddm_batch_graph **out);
+int ddm_batch_graph_launch(ddm_batch_graph *g, void *stream);
+int ddm_batch_graph_result(ddm_batch_graph *g, void *stream, uint64_t *total_host);
+int ddm_batch_graph_destroy(ddm_batch_graph *g);
+
+/*
+ * Autotuner: times one replay of the batch's graph for every candidate
+ * tuning (bucket target 768 / 1024 / 1536, sweep workgroups of 256 / 512
+ * threads, 1 or 4 groups per count/scatter thread), checks that all
+ * candidates produce the same counts, and writes the fastest to *best and
+ * its replay time in milliseconds to *best_ms (optional).  Arguments as for
+ * ddm_batch_graph_create(); the outputs hold the last candidate's result.
+ */
+int ddm_batch_autotune(const float *upd_lo, const float *upd_hi, const int64_t *upd_off,
+                       const float *sub_lo, const float *sub_hi, const int64_t *sub_off,
+                       int64_t B, int d, int mode, void *workspace, size_t ws_bytes, void *stream,
+                       uint64_t *counts, int32_t *per_update, int32_t *pairs, int64_t *pair_off,
+                       int64_t pair_capacity, ddm_tuning *best, double *best_ms);
+
 /* Human-readable text for a DDM_* return code (static storage). */
 const char *ddm_strerror(int code);
 

@@ -193,12 +193,11 @@ int run_bucketed(const Call &c) {
   a.uhi = c.uhi;
   a.slo = c.slo;
   a.shi = c.shi;
-  a.n = (uint32_t)c.n;
-  a.m = (uint32_t)c.m;
   a.d = c.d;
   a.ws = at<void>(c.ws, c.L.region);
-  a.L = c.L.B;
+  a.L = &c.L.B;
   a.hdr = c.hdr;
+  a.inst_total = nullptr;
   int rc = reset_outputs(c);
   if (rc != DDM_OK) return rc;
   DDM_HIP(bucket_prepare(a, c.s));

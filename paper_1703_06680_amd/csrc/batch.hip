@@ -1,0 +1,604 @@
+// Batched matching and its captured-graph form (declared in include/ddm.h).
+//
+// A batch of B independent instances, stored back to back, runs through one
+// launch sequence of the bucketed path: every kernel covers the blocks,
+// buckets and pairs of all instances at once, so the per-launch cost is paid
+// once per batch instead of once per instance.  The sequence needs no host
+// round trip once the batch plan is on the device: outputs are cleared by
+// fill kernels, the pair count is compared with the capacity on the device
+// (the emitting sweep and the ordering sorts read the outcome from device
+// memory), so the whole sequence can be recorded into a HIP graph and
+// replayed by one launch.
+//
+// Pairs are produced as in a single call: per-update counts, an exclusive
+// scan into per-update slots (the first pass of a two-pass compaction), an
+// emitting sweep, and two stable radix sorts (by subscription row, then by
+// update row) into lexicographic order; the rows in the concatenated arrays
+// are finally turned into instance-local ids, and each instance's first pair
+// is the slot of its first update.
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "../../include/ddm.h"
+#include "bucket_path.h"
+#include "common.h"
+#include "primitives.h"
+#include "profile.h"
+
+namespace ddm {
+namespace {
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int bit_length(uint32_t x) { return x ? 32 - __builtin_clz(x) : 0; }
+
+template <typename T>
+T *at(void *ws, size_t off) {
+  return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+#define DDM_HIP(call)                              \
+  do {                                             \
+    if ((call) != hipSuccess) return DDM_E_DEVICE; \
+  } while (0)
+
+// ------------------------------------------------------------- kernels
+
+// off[i] = cnt[i] for i < count, off[count] = 0 (exclusive scan input).
+__global__ void bt_widen_kernel(const int32_t *__restrict__ cnt, unsigned long long *__restrict__ off,
+                                uint32_t count) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= count;
+       i += gridDim.x * blockDim.x)
+    off[i] = i < count ? (unsigned long long)(uint32_t)cnt[i] : 0ull;
+}
+
+// After the scan off[n_total] is the number of pairs K.  gate[0] = K if the
+// pairs fit the capacity, else 0 (nothing is emitted); gate[1] = 1 if they do
+// not fit.  pair_off[b] = off[first update row of instance b].
+__global__ void bt_gate_kernel(const unsigned long long *__restrict__ off, uint32_t n_total,
+                               uint64_t cap, const uint32_t *__restrict__ uoff, uint32_t B,
+                               int64_t *__restrict__ pair_off, uint32_t *__restrict__ gate) {
+  const unsigned long long K = off[n_total];
+  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b <= B; b += gridDim.x * blockDim.x)
+    pair_off[b] = (int64_t)off[uoff[b]];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    gate[0] = K <= cap ? (uint32_t)K : 0u;
+    gate[1] = K > cap ? 1u : 0u;
+  }
+}
+
+// Instance of an update row: the last b < B with uoff[b] <= row (that
+// instance is non-empty and holds the row).
+__device__ __forceinline__ uint32_t instance_of_row(const uint32_t *__restrict__ uoff, uint32_t B,
+                                                    uint32_t row) {
+  uint32_t lo = 0, hi = B;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (uoff[mid] <= row)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Ordered (update row, subscription row) pairs -> instance-local int32 ids.
+__global__ void bt_pairs_out_kernel(const uint32_t *__restrict__ ru, const uint32_t *__restrict__ rs,
+                                    const uint32_t *__restrict__ gate,
+                                    const uint32_t *__restrict__ uoff,
+                                    const uint32_t *__restrict__ soff, uint32_t B,
+                                    int32_t *__restrict__ pairs) {
+  const uint32_t K = gate[0];
+  for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < K; p += gridDim.x * blockDim.x) {
+    const uint32_t u = ru[p], s = rs[p];
+    const uint32_t b = instance_of_row(uoff, B, u);
+    pairs[2 * (size_t)p] = (int32_t)(u - uoff[b]);
+    pairs[2 * (size_t)p + 1] = (int32_t)(s - soff[b]);
+  }
+}
+
+unsigned grid_for(size_t count) {
+  return (unsigned)std::max<size_t>(1, std::min<size_t>((count + 255) / 256, 2048));
+}
+
+// ------------------------------------------------------------- host side
+
+BucketTuning to_tuning(const ddm_tuning *t) {
+  BucketTuning b;
+  if (t) {
+    b.target = (uint32_t)t->target;
+    b.sweep_threads = (uint32_t)t->sweep_threads;
+    b.groups_per_thread = (uint32_t)t->groups_per_thread;
+    b.max_blocks = (uint32_t)t->max_blocks;
+  }
+  return b;
+}
+
+bool tuning_valid(const ddm_tuning *t) {
+  if (!t) return true;
+  return t->target >= 64 && t->target <= (int32_t)(kBucketCap * 3 / 4) &&
+         (t->sweep_threads == 256 || t->sweep_threads == 512) && t->groups_per_thread >= 1 &&
+         t->groups_per_thread <= 64 && t->max_blocks >= 1 && t->max_blocks <= 65536;
+}
+
+// The autotuner's candidates (the default is among them).
+std::vector<BucketTuning> candidates() {
+  std::vector<BucketTuning> out;
+  for (uint32_t target : {768u, 1024u, 1536u})
+    for (uint32_t threads : {256u, 512u})
+      for (uint32_t gpt : {1u, 4u}) {
+        BucketTuning t;
+        t.target = target;
+        t.sweep_threads = threads;
+        t.groups_per_thread = gpt;
+        out.push_back(t);
+      }
+  return out;
+}
+
+bool shape_ok(const int64_t *uoff, const int64_t *soff, int64_t B, int d, int mode,
+              int64_t cap) {
+  if (!uoff || !soff || B < 1 || B >= (int64_t(1) << 24)) return false;
+  if (d < 1 || d > DDM_MAX_DIMS) return false;
+  if (mode != DDM_COUNT && mode != DDM_PER_UPDATE && mode != DDM_PAIRS) return false;
+  if (cap < 0 || cap >= (int64_t(1) << 31)) return false;
+  if (uoff[0] != 0 || soff[0] != 0) return false;
+  for (int64_t b = 0; b < B; ++b)
+    if (uoff[b + 1] < uoff[b] || soff[b + 1] < soff[b]) return false;
+  return uoff[B] + soff[B] < (int64_t(1) << 31);
+}
+
+// Byte offsets of the batch workspace.
+struct BatchLayout {
+  size_t hdr, offs, gate, cnt, off, cur, pu, ps, pu2, ps2, scan_tmp, sort_tmp, region;
+  BucketLayout bk;
+  size_t total;
+};
+
+BatchLayout batch_layout(const int64_t *uoff, const int64_t *soff, int64_t B, int d, int mode,
+                         int64_t cap, const BucketTuning &t) {
+  BatchLayout L{};
+  size_t at_ = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = at_;
+    at_ += align256(bytes);
+    return o;
+  };
+  const size_t n_total = (size_t)uoff[B];
+  const size_t c = (size_t)cap;
+  L.hdr = take(sizeof(Header));
+  L.offs = take(2 * ((size_t)B + 1) * sizeof(uint32_t));
+  L.gate = take(4 * sizeof(uint32_t));
+  if (mode != DDM_COUNT) L.cnt = take(n_total * sizeof(int32_t));
+  if (mode == DDM_PAIRS) {
+    L.off = take((n_total + 1) * sizeof(unsigned long long));
+    L.cur = take(n_total * sizeof(uint32_t));
+    L.pu = take(c * sizeof(uint32_t));
+    L.ps = take(c * sizeof(uint32_t));
+    L.pu2 = take(c * sizeof(uint32_t));
+    L.ps2 = take(c * sizeof(uint32_t));
+    L.scan_tmp = take(scan_temp_bytes(n_total + 1));
+    L.sort_tmp = take(radix_sort_temp_bytes((uint32_t)(c ? c : 1)));
+  }
+  L.region = at_;
+  L.bk = bucket_layout(uoff, soff, B, d, t);
+  L.total = L.region + align256(L.bk.bytes);
+  return L;
+}
+
+// What the per-instance fallback needs: the largest single-call workspace.
+size_t fallback_bytes(const int64_t *uoff, const int64_t *soff, int64_t B, int d, int mode,
+                      int64_t cap) {
+  size_t most = 0;
+  for (int64_t b = 0; b < B; ++b)
+    most = std::max(most, ddm_workspace_bytes(uoff[b + 1] - uoff[b], soff[b + 1] - soff[b], d,
+                                              mode, cap));
+  return most;
+}
+
+struct Batch {
+  const float *ulo, *uhi, *slo, *shi;
+  std::vector<int64_t> uoff, soff;
+  int64_t B;
+  int d, mode;
+  void *ws;
+  size_t ws_bytes;
+  uint64_t *counts;
+  int32_t *per_update, *pairs;
+  int64_t *pair_off;
+  int64_t cap;
+  bool bucketed;  // the batch fits the bucketed plan
+  BatchLayout L;
+};
+
+int make_batch(Batch &c, const float *ulo, const float *uhi, const int64_t *uoff,
+               const float *slo, const float *shi, const int64_t *soff, int64_t B, int d,
+               int mode, void *ws, size_t ws_bytes, const ddm_tuning *tuning, uint64_t *counts,
+               int32_t *per_update, int32_t *pairs, int64_t *pair_off, int64_t cap) {
+  if (!shape_ok(uoff, soff, B, d, mode, cap) || !tuning_valid(tuning)) return DDM_E_INVAL;
+  const int64_t n_total = uoff[B], m_total = soff[B];
+  if ((n_total > 0 && (!ulo || !uhi)) || (m_total > 0 && (!slo || !shi)) || !counts)
+    return DDM_E_INVAL;
+  if (mode == DDM_PER_UPDATE && n_total > 0 && !per_update) return DDM_E_INVAL;
+  if (mode == DDM_PAIRS && (!pair_off || (cap > 0 && !pairs))) return DDM_E_INVAL;
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255)) return ws ? DDM_E_INVAL : DDM_E_WORKSPACE;
+  c.ulo = ulo;
+  c.uhi = uhi;
+  c.slo = slo;
+  c.shi = shi;
+  c.uoff.assign(uoff, uoff + B + 1);
+  c.soff.assign(soff, soff + B + 1);
+  c.B = B;
+  c.d = d;
+  c.mode = mode;
+  c.ws = ws;
+  c.ws_bytes = ws_bytes;
+  c.counts = counts;
+  c.per_update = per_update;
+  c.pairs = pairs;
+  c.pair_off = pair_off;
+  c.cap = cap;
+  const BucketTuning t = to_tuning(tuning);
+  c.bucketed = bucket_path_supported(d, uoff, soff, B, t);
+  if (c.bucketed) {
+    c.L = batch_layout(uoff, soff, B, d, mode, cap, t);
+    if (ws_bytes < c.L.total) return DDM_E_WORKSPACE;
+  }
+  if (ws_bytes < fallback_bytes(uoff, soff, B, d, mode, cap)) return DDM_E_WORKSPACE;
+  return DDM_OK;
+}
+
+BucketArgs bucket_args(const Batch &c) {
+  BucketArgs a{};
+  a.ulo = c.ulo;
+  a.uhi = c.uhi;
+  a.slo = c.slo;
+  a.shi = c.shi;
+  a.d = c.d;
+  a.ws = at<void>(c.ws, c.L.region);
+  a.L = &c.L.bk;
+  a.hdr = at<Header>(c.ws, c.L.hdr);
+  a.inst_total = reinterpret_cast<unsigned long long *>(c.counts);
+  return a;
+}
+
+// Host-to-device copies of the plan and of the 32-bit instance offsets.
+// ``staging`` must stay alive until the stream has passed the copies.
+int upload(const Batch &c, hipStream_t s, std::vector<uint32_t> &staging) {
+  staging.resize(2 * ((size_t)c.B + 1));
+  for (int64_t b = 0; b <= c.B; ++b) {
+    staging[(size_t)b] = (uint32_t)c.uoff[(size_t)b];
+    staging[(size_t)c.B + 1 + (size_t)b] = (uint32_t)c.soff[(size_t)b];
+  }
+  DDM_HIP(hipMemcpyAsync(at<void>(c.ws, c.L.offs), staging.data(),
+                         staging.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+  DDM_HIP(bucket_upload_plan(bucket_args(c), s));
+  return DDM_OK;
+}
+
+// Every launch of one batched call, device-driven (capturable).
+int enqueue(const Batch &c, hipStream_t s) {
+  const BatchLayout &L = c.L;
+  const uint32_t n_total = (uint32_t)c.uoff[(size_t)c.B];
+  const uint32_t m_total = (uint32_t)c.soff[(size_t)c.B];
+  Header *hdr = at<Header>(c.ws, L.hdr);
+  const uint32_t *uoff = at<uint32_t>(c.ws, L.offs);
+  const uint32_t *soff = uoff + c.B + 1;
+  uint32_t *gate = at<uint32_t>(c.ws, L.gate);
+  int32_t *cnt = c.mode == DDM_COUNT ? nullptr
+                 : (c.per_update ? c.per_update : at<int32_t>(c.ws, L.cnt));
+  const BucketArgs a = bucket_args(c);
+  prof::mark(s, "batch.clear");
+  DDM_HIP(fill_u32(reinterpret_cast<uint32_t *>(hdr), 0u, sizeof(Header) / sizeof(uint32_t), s));
+  DDM_HIP(fill_u64(reinterpret_cast<unsigned long long *>(c.counts), 0ull, (size_t)c.B, s));
+  if (cnt) DDM_HIP(fill_u32(reinterpret_cast<uint32_t *>(cnt), 0u, n_total, s));
+  DDM_HIP(bucket_prepare(a, s));
+  DDM_HIP(bucket_sweep(a, c.mode == DDM_COUNT ? 0 : 1, cnt, nullptr, nullptr, nullptr, nullptr,
+                       &hdr->total, s));
+  if (c.mode == DDM_PAIRS) {
+    unsigned long long *off = at<unsigned long long>(c.ws, L.off);
+    uint32_t *cur = at<uint32_t>(c.ws, L.cur);
+    uint32_t *pu = at<uint32_t>(c.ws, L.pu), *ps = at<uint32_t>(c.ws, L.ps);
+    uint32_t *pu2 = at<uint32_t>(c.ws, L.pu2), *ps2 = at<uint32_t>(c.ws, L.ps2);
+    prof::mark(s, "batch.pairs.scan");
+    bt_widen_kernel<<<grid_for((size_t)n_total + 1), 256, 0, s>>>(cnt, off, n_total);
+    DDM_HIP(exclusive_scan_u64(off, off, (size_t)n_total + 1, at<void>(c.ws, L.scan_tmp), s));
+    bt_gate_kernel<<<grid_for((size_t)c.B + 1), 256, 0, s>>>(off, n_total, (uint64_t)c.cap, uoff,
+                                                             (uint32_t)c.B, c.pair_off, gate);
+    DDM_HIP(fill_u32(cur, 0u, n_total, s));
+    BucketArgs emit = a;
+    emit.inst_total = nullptr;  // the counting pass has set them
+    DDM_HIP(bucket_sweep(emit, 2, nullptr, off, cur, pu, ps, &hdr->aux[0], s, gate));
+    if (c.cap > 0) {
+      prof::mark(s, "batch.pairs.order");
+      KeyTransform raw{0, 0, 0};
+      const uint32_t cap = (uint32_t)c.cap;
+      int in_b = 0;
+      DDM_HIP(radix_sort_pairs(ps, pu, ps2, pu2, cap, bit_length(m_total ? m_total - 1 : 0), false,
+                               raw, at<void>(c.ws, L.sort_tmp), s, &in_b, gate));
+      uint32_t *sk = in_b ? ps2 : ps, *sv = in_b ? pu2 : pu;  // keys = s, vals = u
+      uint32_t *ok = in_b ? ps : ps2, *ov = in_b ? pu : pu2;
+      DDM_HIP(radix_sort_pairs(sv, sk, ok, ov, cap, bit_length(n_total ? n_total - 1 : 0), false,
+                               raw, at<void>(c.ws, L.sort_tmp), s, &in_b, gate));
+      const uint32_t *ru = in_b ? ok : sv, *rs = in_b ? ov : sk;
+      bt_pairs_out_kernel<<<grid_for(cap), 256, 0, s>>>(ru, rs, gate, uoff, soff, (uint32_t)c.B,
+                                                        c.pairs);
+    }
+  }
+  DDM_HIP(hipGetLastError());
+  prof::end(s);
+  return DDM_OK;
+}
+
+// Instance by instance through ddm_match() (any d; the path it picks falls
+// back by itself), writing the batch outputs.
+int run_each(const Batch &c, hipStream_t s, uint64_t *total_host) {
+  const int64_t B = c.B;
+  std::vector<uint64_t> counts((size_t)B, 0);
+  std::vector<int64_t> poff((size_t)B + 1, 0);
+  bool full = false;
+  int64_t used = 0;
+  uint64_t total = 0;
+  for (int64_t b = 0; b < B; ++b) {
+    const int64_t u0 = c.uoff[(size_t)b], n = c.uoff[(size_t)b + 1] - u0;
+    const int64_t s0 = c.soff[(size_t)b], m = c.soff[(size_t)b + 1] - s0;
+    const int64_t room = full ? 0 : c.cap - used;
+    uint64_t K = 0;
+    const int rc = ddm_match(c.ulo ? c.ulo + u0 * c.d : nullptr, c.uhi ? c.uhi + u0 * c.d : nullptr,
+                             n, c.slo ? c.slo + s0 * c.d : nullptr,
+                             c.shi ? c.shi + s0 * c.d : nullptr, m, c.d, c.mode, c.ws,
+                             c.ws_bytes, s, &K,
+                             c.per_update && n > 0 ? c.per_update + u0 : nullptr,
+                             c.mode == DDM_PAIRS && room > 0 ? c.pairs + 2 * used : nullptr,
+                             room);
+    if (rc == DDM_E_CAPACITY) {
+      full = true;
+    } else if (rc != DDM_OK) {
+      return rc;
+    }
+    counts[(size_t)b] = K;
+    total += K;
+    poff[(size_t)b] = used;
+    if (!full) used += (int64_t)K;
+  }
+  if (full) {  // offsets of every instance, as if the pairs had fit
+    int64_t run = 0;
+    for (int64_t b = 0; b < B; ++b) {
+      poff[(size_t)b] = run;
+      run += (int64_t)counts[(size_t)b];
+    }
+    used = run;
+  }
+  poff[(size_t)B] = used;
+  DDM_HIP(hipMemcpyAsync(c.counts, counts.data(), counts.size() * sizeof(uint64_t),
+                         hipMemcpyHostToDevice, s));
+  if (c.mode == DDM_PAIRS)
+    DDM_HIP(hipMemcpyAsync(c.pair_off, poff.data(), poff.size() * sizeof(int64_t),
+                           hipMemcpyHostToDevice, s));
+  DDM_HIP(hipStreamSynchronize(s));
+  *total_host = total;
+  return full ? DDM_E_CAPACITY : DDM_OK;
+}
+
+// Reads the outcome of an enqueued batch (stream synchronised first) and
+// falls back to run_each() if a bucket overflowed.
+int finish(const Batch &c, hipStream_t s, uint64_t *total_host) {
+  Header h{};
+  uint32_t gate[4] = {0, 0, 0, 0};
+  DDM_HIP(hipMemcpyAsync(&h, at<Header>(c.ws, c.L.hdr), sizeof(Header), hipMemcpyDeviceToHost, s));
+  DDM_HIP(hipMemcpyAsync(gate, at<uint32_t>(c.ws, c.L.gate), sizeof(gate), hipMemcpyDeviceToHost,
+                         s));
+  DDM_HIP(hipStreamSynchronize(s));
+  prof::flush();
+  if (h.err) return DDM_E_INVAL;
+  if (h.pad[0]) return run_each(c, s, total_host);
+  *total_host = h.total;
+  if (c.mode == DDM_PAIRS && gate[1]) return DDM_E_CAPACITY;
+  return DDM_OK;
+}
+
+}  // namespace
+}  // namespace ddm
+
+using namespace ddm;
+
+struct ddm_batch_graph {
+  Batch c;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" void ddm_default_tuning(ddm_tuning *out) {
+  if (!out) return;
+  const BucketTuning t;
+  out->target = (int32_t)t.target;
+  out->sweep_threads = (int32_t)t.sweep_threads;
+  out->groups_per_thread = (int32_t)t.groups_per_thread;
+  out->max_blocks = (int32_t)t.max_blocks;
+}
+
+extern "C" size_t ddm_batch_workspace_bytes(const int64_t *upd_off, const int64_t *sub_off,
+                                            int64_t B, int d, int mode, int64_t pair_capacity,
+                                            const ddm_tuning *tuning) {
+  if (!shape_ok(upd_off, sub_off, B, d, mode, pair_capacity) || !tuning_valid(tuning)) return 0;
+  size_t most = fallback_bytes(upd_off, sub_off, B, d, mode, pair_capacity);
+  std::vector<BucketTuning> ts;
+  if (tuning) {
+    ts.push_back(to_tuning(tuning));
+  } else {
+    ts = candidates();
+    ts.push_back(BucketTuning{});
+  }
+  for (const BucketTuning &t : ts)
+    if (bucket_path_supported(d, upd_off, sub_off, B, t))
+      most = std::max(most,
+                      batch_layout(upd_off, sub_off, B, d, mode, pair_capacity, t).total);
+  return std::max<size_t>(most, 256);
+}
+
+extern "C" int ddm_match_batched(const float *upd_lo, const float *upd_hi, const int64_t *upd_off,
+                                 const float *sub_lo, const float *sub_hi, const int64_t *sub_off,
+                                 int64_t B, int d, int mode, void *workspace, size_t ws_bytes,
+                                 void *stream, const ddm_tuning *tuning, uint64_t *counts,
+                                 uint64_t *total_host, int32_t *per_update, int32_t *pairs,
+                                 int64_t *pair_off, int64_t pair_capacity) {
+  if (!total_host) return DDM_E_INVAL;
+  Batch c;
+  int rc = make_batch(c, upd_lo, upd_hi, upd_off, sub_lo, sub_hi, sub_off, B, d, mode, workspace,
+                      ws_bytes, tuning, counts, per_update, pairs, pair_off, pair_capacity);
+  if (rc != DDM_OK) return rc;
+  *total_host = 0;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!c.bucketed) return run_each(c, s, total_host);
+  std::vector<uint32_t> staging;
+  rc = upload(c, s, staging);
+  if (rc != DDM_OK) return rc;
+  rc = enqueue(c, s);
+  if (rc != DDM_OK) return rc;
+  return finish(c, s, total_host);
+}
+
+extern "C" int ddm_batch_graph_create(const float *upd_lo, const float *upd_hi,
+                                      const int64_t *upd_off, const float *sub_lo,
+                                      const float *sub_hi, const int64_t *sub_off, int64_t B,
+                                      int d, int mode, void *workspace, size_t ws_bytes,
+                                      const ddm_tuning *tuning, uint64_t *counts,
+                                      int32_t *per_update, int32_t *pairs, int64_t *pair_off,
+                                      int64_t pair_capacity, ddm_batch_graph **out) {
+  if (!out) return DDM_E_INVAL;
+  *out = nullptr;
+  ddm_batch_graph *g = new (std::nothrow) ddm_batch_graph();
+  if (!g) return DDM_E_DEVICE;
+  int rc = make_batch(g->c, upd_lo, upd_hi, upd_off, sub_lo, sub_hi, sub_off, B, d, mode,
+                      workspace, ws_bytes, tuning, counts, per_update, pairs, pair_off,
+                      pair_capacity);
+  if (rc == DDM_OK && !g->c.bucketed) rc = DDM_E_UNSUPPORTED;
+  if (rc != DDM_OK) {
+    delete g;
+    return rc;
+  }
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+    delete g;
+    return DDM_E_DEVICE;
+  }
+  std::vector<uint32_t> staging;
+  rc = upload(g->c, cs, staging);
+  if (rc == DDM_OK && hipStreamSynchronize(cs) != hipSuccess) rc = DDM_E_DEVICE;
+  if (rc == DDM_OK) {
+    const bool was = prof::swap_enabled(false);  // no event records inside the graph
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      rc = DDM_E_DEVICE;
+    } else {
+      rc = enqueue(g->c, cs);
+      hipGraph_t graph = nullptr;
+      const hipError_t e = hipStreamEndCapture(cs, &graph);
+      if (rc == DDM_OK && e != hipSuccess) rc = DDM_E_DEVICE;
+      g->graph = graph;
+      if (rc == DDM_OK && hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess)
+        rc = DDM_E_DEVICE;
+    }
+    prof::swap_enabled(was);
+  }
+  hipStreamDestroy(cs);
+  if (rc != DDM_OK) {
+    ddm_batch_graph_destroy(g);
+    return rc;
+  }
+  *out = g;
+  return DDM_OK;
+}
+
+extern "C" int ddm_batch_graph_launch(ddm_batch_graph *g, void *stream) {
+  if (!g || !g->exec) return DDM_E_INVAL;
+  if (hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)) != hipSuccess) return DDM_E_DEVICE;
+  return DDM_OK;
+}
+
+extern "C" int ddm_batch_graph_result(ddm_batch_graph *g, void *stream, uint64_t *total_host) {
+  if (!g || !g->exec || !total_host) return DDM_E_INVAL;
+  *total_host = 0;
+  return finish(g->c, static_cast<hipStream_t>(stream), total_host);
+}
+
+extern "C" int ddm_batch_graph_destroy(ddm_batch_graph *g) {
+  if (!g) return DDM_OK;
+  int rc = DDM_OK;
+  if (g->exec && hipGraphExecDestroy(g->exec) != hipSuccess) rc = DDM_E_DEVICE;
+  if (g->graph && hipGraphDestroy(g->graph) != hipSuccess) rc = DDM_E_DEVICE;
+  delete g;
+  return rc;
+}
+
+extern "C" int ddm_batch_autotune(const float *upd_lo, const float *upd_hi,
+                                  const int64_t *upd_off, const float *sub_lo,
+                                  const float *sub_hi, const int64_t *sub_off, int64_t B, int d,
+                                  int mode, void *workspace, size_t ws_bytes, void *stream,
+                                  uint64_t *counts, int32_t *per_update, int32_t *pairs,
+                                  int64_t *pair_off, int64_t pair_capacity, ddm_tuning *best,
+                                  double *best_ms) {
+  if (!best) return DDM_E_INVAL;
+  if (!shape_ok(upd_off, sub_off, B, d, mode, pair_capacity)) return DDM_E_INVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return DDM_E_DEVICE;
+  std::vector<uint64_t> ref((size_t)B), got((size_t)B);
+  bool have_ref = false, have_best = false;
+  float best_t = 0.f;
+  int rc = DDM_OK;
+  for (const BucketTuning &t : candidates()) {
+    ddm_tuning cand{(int32_t)t.target, (int32_t)t.sweep_threads, (int32_t)t.groups_per_thread,
+                    (int32_t)t.max_blocks};
+    ddm_batch_graph *g = nullptr;
+    int r = ddm_batch_graph_create(upd_lo, upd_hi, upd_off, sub_lo, sub_hi, sub_off, B, d, mode,
+                                   workspace, ws_bytes, &cand, counts, per_update, pairs, pair_off,
+                                   pair_capacity, &g);
+    if (r == DDM_E_UNSUPPORTED) continue;  // this shape does not fit the candidate
+    if (r != DDM_OK) {
+      rc = r;
+      break;
+    }
+    uint64_t total = 0;
+    float tmin = 0.f;
+    for (int rep = 0; rep < 4 && r == DDM_OK; ++rep) {  // first replay warms up
+      if (hipEventRecord(e0, s) != hipSuccess) r = DDM_E_DEVICE;
+      if (r == DDM_OK) r = ddm_batch_graph_launch(g, stream);
+      if (r == DDM_OK && hipEventRecord(e1, s) != hipSuccess) r = DDM_E_DEVICE;
+      if (r == DDM_OK) r = ddm_batch_graph_result(g, stream, &total);
+      float ms = 0.f;
+      if (r == DDM_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) r = DDM_E_DEVICE;
+      if (r == DDM_OK && rep > 0 && (rep == 1 || ms < tmin)) tmin = ms;
+    }
+    if (r == DDM_OK &&
+        hipMemcpy(got.data(), counts, got.size() * sizeof(uint64_t), hipMemcpyDeviceToHost) !=
+            hipSuccess)
+      r = DDM_E_DEVICE;
+    ddm_batch_graph_destroy(g);
+    if (r == DDM_E_CAPACITY) r = DDM_OK;  // timing is still meaningful
+    if (r != DDM_OK) {
+      rc = r;
+      break;
+    }
+    if (!have_ref) {
+      ref = got;
+      have_ref = true;
+    } else if (ref != got) {  // every tuning must give the same result
+      rc = DDM_E_DEVICE;
+      break;
+    }
+    if (!have_best || tmin < best_t) {
+      have_best = true;
+      best_t = tmin;
+      *best = cand;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc != DDM_OK) return rc;
+  if (!have_best) return DDM_E_UNSUPPORTED;
+  if (best_ms) *best_ms = best_t;
+  return DDM_OK;
+}

@@ -7,53 +7,99 @@
 // LDS; the regions of earlier buckets that are still active when a bucket
 // starts (SubSet[p] and UpdSet[p] of Algorithms 5 and 6) are delivered to it
 // as a boundary-state list built by a span count, a prefix sum and a fill.
+//
+// One launch sequence serves a batch of independent instances stored back to
+// back: every instance has its own buckets, count/scatter blocks and sample
+// blocks, all numbered globally, and a single call is a batch of one.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "common.h"
 
 namespace ddm {
 
-struct BucketLayout {
-  uint32_t nb;          // number of buckets
-  uint32_t nblk;        // blocks of the count and scatter passes
-  uint32_t gpb;         // groups of four rows per count/scatter block
-  uint32_t bs_cap;      // capacity of the boundary-state record buffer
-  int rec_words;        // 32-bit words per region record
-  size_t bytes;         // workspace bytes for all buffers below
-  // byte offsets inside the bucket workspace
-  size_t params, sample_part, counts, transposed, offsets, block_offsets, scan_tmp, bs_cur, rec,
-      bs_rec;
+// Launch-shape parameters of the bucketed path.
+struct BucketTuning {
+  uint32_t target = 1536;         // mean records per bucket (at most 3/4 of kBucketCap)
+  uint32_t sweep_threads = 512;   // 256 or 512 threads per sweep workgroup
+  uint32_t groups_per_thread = 1; // count/scatter: groups of four rows per thread (minimum)
+  uint32_t max_blocks = 512;      // count/scatter blocks per instance at most
 };
 
-// Largest number of buckets the count/scatter passes handle (LDS-resident
-// per-bucket counters).
+// Records per bucket the sweep holds in LDS.
+constexpr uint32_t kBucketCap = 2048;
+// Largest number of buckets of one instance (LDS-resident per-bucket counters
+// of the count and scatter passes).
 constexpr uint32_t kMaxBuckets = 16384;
 
+// Per-instance launch plan, in device memory for batches of more than one.
+struct InstPlan {
+  uint32_t u0, n, s0, m;     // rows of the instance in the concatenated arrays
+  uint32_t gu, g;            // groups of up to four rows: of updates, of both kinds
+  uint32_t blk0, nblk, gpb;  // count/scatter blocks (first, number) and groups per block
+  uint32_t b0, nb;           // buckets (first, number)
+  uint32_t cell0;            // first cell of the instance's nblk x nb count matrix
+  uint32_t smp0, nsmp;       // sample blocks
+  uint32_t tile0, ntx;       // transpose tiles (first), tiles along the bucket axis
+};
+
+struct BucketLayout {
+  uint32_t B;                          // instances
+  uint32_t nb, nblk, nsmp, ntile;      // totals over the instances
+  uint32_t max_nb;                     // most buckets of one instance
+  uint32_t n_total, m_total;           // updates, subscriptions over the instances
+  uint32_t bs_cap;                     // capacity of the boundary-state record buffer
+  int rec_words;                       // 32-bit words per region record
+  BucketTuning tune;
+  size_t cells;                        // count-matrix cells over the instances
+  size_t bytes;                        // workspace bytes for all buffers below
+  // byte offsets inside the bucket workspace
+  size_t params, sample_part, counts, transposed, offsets, block_offsets, scan_tmp, bs_cur, rec,
+      bs_rec, plan, maps;
+  std::vector<InstPlan> inst;          // host copy of the per-instance plan
+};
+
+// upd_off / sub_off: host CSR offsets [B + 1] of the instances' rows.
+bool bucket_path_supported(int d, const int64_t *upd_off, const int64_t *sub_off, int64_t B,
+                           const BucketTuning &t);
+BucketLayout bucket_layout(const int64_t *upd_off, const int64_t *sub_off, int64_t B, int d,
+                           const BucketTuning &t);
+// Single instance of n updates and m subscriptions with the default tuning.
 bool bucket_path_supported(int d, int64_t n, int64_t m);
 BucketLayout bucket_layout(int64_t n, int64_t m, int d);
 
 struct BucketArgs {
-  const float *ulo, *uhi, *slo, *shi;
-  uint32_t n, m;
+  const float *ulo, *uhi, *slo, *shi;  // concatenated rows of all instances
   int d;
   void *ws;  // base of the bucket workspace (BucketLayout offsets apply)
-  BucketLayout L;
+  const BucketLayout *L;
   Header *hdr;
+  unsigned long long *inst_total;  // per-instance pair counts [B], or null
 };
+
+// Copies the per-instance plan to the workspace and expands the block,
+// sample, tile and bucket to instance maps (batches of more than one; no-op
+// otherwise).  The plan stays valid until the workspace is reused.
+hipError_t bucket_upload_plan(const BucketArgs &a, hipStream_t s);
 
 // Enqueue sampling, counting (with input validation), prefix sums and the
 // scatter of region records into buckets.
 hipError_t bucket_prepare(const BucketArgs &a, hipStream_t s);
 
-// Enqueue the per-bucket sweep.  mode 0: total only; 1: total and per-update
-// counts (per_update zeroed beforehand); 2: write pairs at pair_off[u] plus a
-// per-update cursor (zeroed beforehand).
+// Enqueue the per-bucket sweep.  mode 0: totals only; 1: totals and
+// per-update counts (per_update zeroed beforehand, indexed by the update's
+// row in the concatenated arrays); 2: write pairs (row of the update, row of
+// the subscription) at pair_off[u] plus a per-update cursor (zeroed
+// beforehand).  In mode 2, if ``gate`` is not null and *gate is 0 on the
+// device, the launch writes nothing (the pairs did not fit their buffer).
 hipError_t bucket_sweep(const BucketArgs &a, int mode, int32_t *per_update,
                         const unsigned long long *pair_off, uint32_t *cursor, uint32_t *out_u,
-                        uint32_t *out_s, unsigned long long *total, hipStream_t s);
+                        uint32_t *out_s, unsigned long long *total, hipStream_t s,
+                        const uint32_t *gate = nullptr);
 
 }  // namespace ddm

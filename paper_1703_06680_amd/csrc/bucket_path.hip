@@ -31,7 +31,15 @@
 //            is met exactly once, at the later of the two lower endpoints (the
 //            pair Algorithm 4 reports at the earlier upper endpoint), and kept
 //            if the boxes overlap on every other axis.
+//
+// A batch of instances runs through the same launches: each instance has its
+// own bucket map, buckets, count matrix and blocks; blocks, buckets, sample
+// blocks and transpose tiles are numbered over the whole batch and mapped
+// back to their instance by small tables (a batch of one needs none).
 #include "bucket_path.h"
+
+#include <algorithm>
+
 #include "primitives.h"
 #include "profile.h"
 
@@ -39,15 +47,13 @@ namespace ddm {
 namespace {
 
 constexpr int kThreads = 1024;                 // count / scatter blocks
-constexpr uint32_t kMaxBlocks = 512;           // one resident round on 256 CUs
-constexpr int kSampleBlocks = 256;
 constexpr int kSampleThreads = 256;
-constexpr uint32_t kTargetBucket = 1536;       // mean records per bucket
+constexpr uint32_t kSampleRows = 8192;         // rows per sample block (at most 256 blocks)
+constexpr uint32_t kMaxSampleBlocks = 256;
 
 // The sweep workgroup: kCap records at most per bucket, kFine fine bins per
 // kind.
-constexpr int kSweepThreads = 512;
-constexpr int kCap = 2048;
+constexpr int kCap = (int)kBucketCap;
 constexpr int kFine = 512;
 
 struct BucketParams {
@@ -85,19 +91,13 @@ struct Box {
 };
 
 template <int D>
-__device__ __forceinline__ Box<D> load_box(const float *__restrict__ ulo,
-                                           const float *__restrict__ uhi,
-                                           const float *__restrict__ slo,
-                                           const float *__restrict__ shi, uint32_t n, uint32_t r) {
+__device__ __forceinline__ Box<D> load_row(const float *__restrict__ lo,
+                                           const float *__restrict__ hi, uint32_t row) {
   Box<D> b;
-  const bool upd = r < n;
-  const size_t row = (size_t)(upd ? r : r - n) * D;
-  const float *lo = (upd ? ulo : slo) + row;
-  const float *hi = (upd ? uhi : shi) + row;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
-    b.lo[k] = lo[k];
-    b.hi[k] = hi[k];
+    b.lo[k] = lo[(size_t)row * D + k];
+    b.hi[k] = hi[(size_t)row * D + k];
   }
   return b;
 }
@@ -117,18 +117,30 @@ __device__ __forceinline__ uint32_t box_errors(const Box<D> &b, bool &empty) {
   return err;
 }
 
-// Offsets produced by the one prefix sum: S[b * nblk + k] is block k's first
-// slot in bucket b, S[cells] the number of records, S[cells + j] - S[cells]
-// the first boundary-state entry of bucket j (j <= nb).
+// The per-instance plan as the kernels see it: a device table for batches,
+// the one plan by value otherwise, and the maps from global block, sample
+// block, transpose tile and bucket numbers to instances.
+struct View {
+  const InstPlan *plan;  // null: a single instance, `one`
+  InstPlan one;
+  const uint32_t *blk_inst, *smp_inst, *tile_inst, *bucket_inst;
+  __device__ __forceinline__ InstPlan get(uint32_t i) const { return plan ? plan[i] : one; }
+  __device__ __forceinline__ uint32_t of_blk(uint32_t x) const { return plan ? blk_inst[x] : 0u; }
+  __device__ __forceinline__ uint32_t of_smp(uint32_t x) const { return plan ? smp_inst[x] : 0u; }
+  __device__ __forceinline__ uint32_t of_tile(uint32_t x) const { return plan ? tile_inst[x] : 0u; }
+  __device__ __forceinline__ uint32_t of_bucket(uint32_t x) const {
+    return plan ? bucket_inst[x] : 0u;
+  }
+};
+
+// Offsets produced by the one prefix sum over [count cells | boundary-state
+// sizes | 0]: S[cell0 + b * nblk + k] is block k's first slot in bucket b of
+// an instance, S[cells] the number of records, S[cells + j] - S[cells] the
+// first boundary-state entry of global bucket j (j <= total buckets).
 struct Offsets {
   const uint32_t *S;
   size_t cells;
-  uint32_t nblk, nb;
-  __device__ uint32_t records() const { return S[cells]; }
-  __device__ uint32_t bucket_begin(uint32_t b) const { return S[(size_t)b * nblk]; }
-  __device__ uint32_t bucket_end(uint32_t b) const {
-    return b + 1 < nb ? S[(size_t)(b + 1) * nblk] : S[cells];
-  }
+  uint32_t nb;  // buckets over all instances
   __device__ uint32_t bs_begin(uint32_t j) const { return S[cells + j] - S[cells]; }
 };
 
@@ -137,18 +149,21 @@ struct Offsets {
 template <int D>
 __global__ __launch_bounds__(kSampleThreads) void bk_sample_kernel(
     const float *__restrict__ ulo, const float *__restrict__ uhi, const float *__restrict__ slo,
-    const float *__restrict__ shi, uint32_t n, uint32_t m, float *__restrict__ part) {
+    const float *__restrict__ shi, View V, float *__restrict__ part) {
   // per block: min/max of the swept lower coordinate, count, and for the
-  // other axes min(lo) / max(hi), over the sampled valid non-empty boxes
+  // other axes min(lo) / max(hi), over the sampled valid non-empty boxes of
+  // the block's instance
   constexpr int W = kSampleThreads / kWave;
   __shared__ float sred[W][8];
-  const uint32_t N = n + m;
+  const InstPlan I = V.get(V.of_smp(blockIdx.x));
+  const uint32_t N = I.n + I.m;
   const float inf = __int_as_float(0x7f800000);
   float v[8] = {inf, -inf, 0.f, 0.f, inf, -inf, inf, -inf};
   const uint32_t i = blockIdx.x * kSampleThreads + threadIdx.x;
   const uint32_t r =
       (uint32_t)(((unsigned long long)mix32(i * 0x9E3779B9u + 0x632BE5ABu) * N) >> 32);
-  const Box<D> b = load_box<D>(ulo, uhi, slo, shi, n, r);
+  const bool upd = r < I.n;
+  const Box<D> b = load_row<D>(upd ? ulo : slo, upd ? uhi : shi, upd ? I.u0 + r : I.s0 + (r - I.n));
   bool empty;
   const uint32_t err = box_errors<D>(b, empty);
   bool ok = !err && !empty && fabsf(b.lo[0]) <= 3.0e38f;
@@ -191,21 +206,25 @@ __global__ __launch_bounds__(kSampleThreads) void bk_sample_kernel(
   }
 }
 
+// One block per instance: reduces the instance's sample partials into its
+// bucket map and quantisation parameters.
 __global__ __launch_bounds__(kSampleThreads) void bk_plan_kernel(const float *__restrict__ part,
-                                                                 uint32_t nb,
+                                                                 View V,
                                                                  BucketParams *__restrict__ P) {
   constexpr int W = kSampleThreads / kWave;
   __shared__ float sred[W][8];
+  const InstPlan I = V.get(blockIdx.x);
   const float inf = __int_as_float(0x7f800000);
   float v[8] = {inf, -inf, 0.f, 0.f, inf, -inf, inf, -inf};
-  for (int i = threadIdx.x; i < kSampleBlocks; i += kSampleThreads) {
+  for (uint32_t i = threadIdx.x; i < I.nsmp; i += kSampleThreads) {
+    const float *pp = part + (size_t)(I.smp0 + i) * 8;
 #pragma unroll
     for (int k = 0; k < 8; k += 2) {
       if (k == 2) continue;
-      v[k] = fminf(v[k], part[i * 8 + k]);
-      v[k + 1] = fmaxf(v[k + 1], part[i * 8 + k + 1]);
+      v[k] = fminf(v[k], pp[k]);
+      v[k + 1] = fmaxf(v[k + 1], pp[k + 1]);
     }
-    v[2] += part[i * 8 + 2];
+    v[2] += pp[2];
   }
 #pragma unroll
   for (int k = 0; k < 8; k += 2) {
@@ -230,12 +249,12 @@ __global__ __launch_bounds__(kSampleThreads) void bk_plan_kernel(const float *__
   float c = 0.f;
   for (int j = 0; j < W; ++j) c += sred[j][2];
   BucketParams q;
-  q.nb = nb;
+  q.nb = I.nb;
   q.vmin = 0.f;
   q.scale = 0.f;
   q.valid = 0;
-  if (c > 0.f && v[1] > v[0]) {
-    const float scale = (float)nb / (v[1] - v[0]);
+  if (c > 0.f && v[1] > v[0] && I.nb > 0) {
+    const float scale = (float)I.nb / (v[1] - v[0]);
     if (scale > 0.f && scale <= 3.0e38f) {
       q.vmin = v[0];
       q.scale = scale;
@@ -254,36 +273,35 @@ __global__ __launch_bounds__(kSampleThreads) void bk_plan_kernel(const float *__
       }
     }
   }
-  *P = q;
+  P[blockIdx.x] = q;
 }
 
 // ------------------------------------------------------ row groups
 
-// Rows are read in groups of four consecutive rows of one kind, so that a
-// group of d-float rows is d aligned 16-byte loads.  Groups 0 .. Gu-1 cover the
-// updates, the rest the subscriptions.
+// Rows are read in groups of up to four consecutive rows of one kind of one
+// instance, with group boundaries at multiples of four in the concatenated
+// arrays, so that a full group of d-float rows is d aligned 16-byte loads.
+// An instance's groups 0 .. gu-1 cover its updates, the rest its
+// subscriptions.
 struct Group {
   const float *lo, *hi;
   uint32_t row0, rows, r0;  // first row, rows in the group (<= 4), region index of row0
 };
 
-__device__ __forceinline__ Group group_of(uint32_t g, uint32_t Gu, const float *ulo,
+__device__ __forceinline__ Group group_of(uint32_t g, const InstPlan &I, const float *ulo,
                                           const float *uhi, const float *slo, const float *shi,
-                                          uint32_t n, uint32_t m) {
+                                          uint32_t n_total) {
   Group q;
-  if (g < Gu) {
-    q.lo = ulo;
-    q.hi = uhi;
-    q.row0 = 4 * g;
-    q.rows = min(4u, n - q.row0);
-    q.r0 = q.row0;
-  } else {
-    q.lo = slo;
-    q.hi = shi;
-    q.row0 = 4 * (g - Gu);
-    q.rows = min(4u, m - q.row0);
-    q.r0 = n + q.row0;
-  }
+  const bool upd = g < I.gu;
+  const uint32_t first = upd ? I.u0 : I.s0, count = upd ? I.n : I.m;
+  if (!upd) g -= I.gu;
+  q.lo = upd ? ulo : slo;
+  q.hi = upd ? uhi : shi;
+  const uint32_t a = 4u * ((first >> 2) + g);
+  const uint32_t lo = max(first, a), hi = min(first + count, a + 4u);
+  q.row0 = lo;
+  q.rows = hi - lo;
+  q.r0 = upd ? lo : n_total + lo;
   return q;
 }
 
@@ -329,19 +347,21 @@ __device__ __forceinline__ void load_group(const Group &q, bool vec, Box<D> (&bx
 template <int D>
 __global__ __launch_bounds__(kThreads) void bk_count_kernel(
     const float *__restrict__ ulo, const float *__restrict__ uhi, const float *__restrict__ slo,
-    const float *__restrict__ shi, uint32_t n, uint32_t m, int vec,
-    const BucketParams *__restrict__ P, uint32_t nb, uint32_t gpb, uint32_t *__restrict__ C,
-    uint32_t *__restrict__ bs_size, Header *__restrict__ hdr) {
+    const float *__restrict__ shi, uint32_t n_total, int vec, View V,
+    const BucketParams *__restrict__ P, uint32_t *__restrict__ C, uint32_t *__restrict__ bs_size,
+    Header *__restrict__ hdr) {
   extern __shared__ uint32_t hist[];
-  const BucketParams p = *P;
+  const uint32_t inst = V.of_blk(blockIdx.x);
+  const InstPlan I = V.get(inst);
+  const BucketParams p = P[inst];
+  const uint32_t nb = I.nb, lb = blockIdx.x - I.blk0;
   for (uint32_t b = threadIdx.x; b < nb; b += kThreads) hist[b] = 0;
   __syncthreads();
-  const uint32_t Gu = (n + 3) / 4, G = Gu + (m + 3) / 4;
-  const uint32_t g0 = blockIdx.x * gpb, g1 = min(G, g0 + gpb);
+  const uint32_t g0 = lb * I.gpb, g1 = min(I.g, g0 + I.gpb);
   uint32_t err = 0;
 #pragma unroll 2
   for (uint32_t g = g0 + threadIdx.x; g < g1; g += kThreads) {
-    const Group q = group_of(g, Gu, ulo, uhi, slo, shi, n, m);
+    const Group q = group_of(g, I, ulo, uhi, slo, shi, n_total);
     Box<D> bx[4];
     load_group<D>(q, vec != 0, bx);
 #pragma unroll
@@ -353,21 +373,30 @@ __global__ __launch_bounds__(kThreads) void bk_count_kernel(
       const uint32_t b = bucket_of(bx[r].lo[0], p.vmin, p.scale, nb);
       atomicAdd(&hist[b], 1u);
       const uint32_t last = bucket_of(bx[r].hi[0], p.vmin, p.scale, nb);
-      for (uint32_t j = b + 1; j <= last; ++j) atomicAdd(&bs_size[j], 1u);
+      for (uint32_t j = b + 1; j <= last; ++j) atomicAdd(&bs_size[I.b0 + j], 1u);
     }
   }
   __syncthreads();
-  for (uint32_t b = threadIdx.x; b < nb; b += kThreads) C[(size_t)blockIdx.x * nb + b] = hist[b];
+  uint32_t *row = C + I.cell0 + (size_t)lb * nb;
+  for (uint32_t b = threadIdx.x; b < nb; b += kThreads) row[b] = hist[b];
   err = (__ballot(err & kErrNaN) ? kErrNaN : 0u) | (__ballot(err & kErrOrder) ? kErrOrder : 0u);
   if (err && lane_id() == 0) atomicOr(&hdr->err, err);
 }
 
-// out[c][r] = in[r][c] for a rows x cols row-major matrix, 64x64 LDS tiles.
-__global__ __launch_bounds__(256) void transpose_kernel(const uint32_t *__restrict__ in,
-                                                        uint32_t *__restrict__ out, uint32_t rows,
-                                                        uint32_t cols) {
+// Per instance, out = transpose(in) for its count matrix: forward (back == 0)
+// from block-major nblk x nb to bucket-major nb x nblk, backward the reverse.
+// One 64 x 64 LDS tile per workgroup.
+__global__ __launch_bounds__(256) void bk_transpose_kernel(const uint32_t *__restrict__ in,
+                                                           uint32_t *__restrict__ out, View V,
+                                                           int back) {
   __shared__ uint32_t tile[64][65];
-  const uint32_t c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+  const InstPlan I = V.get(V.of_tile(blockIdx.x));
+  const uint32_t lt = blockIdx.x - I.tile0;
+  const uint32_t tb = lt % I.ntx, tk = lt / I.ntx;  // bucket tile, block tile
+  const uint32_t rows = back ? I.nb : I.nblk, cols = back ? I.nblk : I.nb;
+  const uint32_t r0 = (back ? tb : tk) * 64, c0 = (back ? tk : tb) * 64;
+  in += I.cell0;
+  out += I.cell0;
   const uint32_t tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   for (uint32_t j = ty; j < 64; j += 4) {
     const uint32_t r = r0 + j, c = c0 + tx;
@@ -408,21 +437,23 @@ __device__ __forceinline__ void write_record(uint32_t *__restrict__ dst, const B
 template <int D>
 __global__ __launch_bounds__(kThreads) void bk_scatter_kernel(
     const float *__restrict__ ulo, const float *__restrict__ uhi, const float *__restrict__ slo,
-    const float *__restrict__ shi, uint32_t n, uint32_t m, int vec,
-    const BucketParams *__restrict__ P, uint32_t gpb, Offsets O, const uint32_t *__restrict__ SB,
+    const float *__restrict__ shi, uint32_t n_total, int vec, View V,
+    const BucketParams *__restrict__ P, Offsets O, const uint32_t *__restrict__ SB,
     uint32_t *__restrict__ bs_cur, uint32_t bs_cap, uint32_t *__restrict__ rec,
     uint32_t *__restrict__ bs_rec) {
   constexpr int RW = D == 1 ? 4 : 8;
   extern __shared__ uint32_t cur[];
-  const BucketParams p = *P;
-  const uint32_t nb = O.nb;
-  for (uint32_t b = threadIdx.x; b < nb; b += kThreads) cur[b] = SB[(size_t)blockIdx.x * nb + b];
+  const uint32_t inst = V.of_blk(blockIdx.x);
+  const InstPlan I = V.get(inst);
+  const BucketParams p = P[inst];
+  const uint32_t nb = I.nb, lb = blockIdx.x - I.blk0;
+  const uint32_t *row = SB + I.cell0 + (size_t)lb * nb;
+  for (uint32_t b = threadIdx.x; b < nb; b += kThreads) cur[b] = row[b];
   __syncthreads();
-  const uint32_t Gu = (n + 3) / 4, G = Gu + (m + 3) / 4;
-  const uint32_t g0 = blockIdx.x * gpb, g1 = min(G, g0 + gpb);
+  const uint32_t g0 = lb * I.gpb, g1 = min(I.g, g0 + I.gpb);
 #pragma unroll 2
   for (uint32_t g = g0 + threadIdx.x; g < g1; g += kThreads) {
-    const Group q = group_of(g, Gu, ulo, uhi, slo, shi, n, m);
+    const Group q = group_of(g, I, ulo, uhi, slo, shi, n_total);
     Box<D> bx[4];
     load_group<D>(q, vec != 0, bx);
 #pragma unroll
@@ -436,11 +467,46 @@ __global__ __launch_bounds__(kThreads) void bk_scatter_kernel(
       write_record<D>(rec + (size_t)slot * RW, bx[r], q.r0 + r);
       const uint32_t last = bucket_of(bx[r].hi[0], p.vmin, p.scale, nb);
       for (uint32_t j = b + 1; j <= last; ++j) {
-        const uint32_t pos = O.bs_begin(j) + atomicAdd(&bs_cur[j], 1u);
+        const uint32_t jg = I.b0 + j;
+        const uint32_t pos = O.bs_begin(jg) + atomicAdd(&bs_cur[jg], 1u);
         if (pos < bs_cap) write_record<D>(bs_rec + (size_t)pos * RW, bx[r], q.r0 + r);
       }
     }
   }
+}
+
+// Instance of every global block, sample block, transpose tile and bucket.
+__device__ __forceinline__ uint32_t find_inst(const InstPlan *plan, uint32_t B, uint32_t x,
+                                              int which) {
+  // last instance whose first index (of the given kind) is <= x among those
+  // that own at least one such index
+  uint32_t lo = 0, hi = B;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    const InstPlan &I = plan[mid];
+    const uint32_t first = which == 0 ? I.blk0 : which == 1 ? I.smp0 : which == 2 ? I.tile0 : I.b0;
+    if (first <= x)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__global__ void bk_expand_maps_kernel(const InstPlan *__restrict__ plan, uint32_t B,
+                                      uint32_t *__restrict__ blk_inst, uint32_t nblk,
+                                      uint32_t *__restrict__ smp_inst, uint32_t nsmp,
+                                      uint32_t *__restrict__ tile_inst, uint32_t ntile,
+                                      uint32_t *__restrict__ bucket_inst, uint32_t nb) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < nblk; x += stride)
+    blk_inst[x] = find_inst(plan, B, x, 0);
+  for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < nsmp; x += stride)
+    smp_inst[x] = find_inst(plan, B, x, 1);
+  for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < ntile; x += stride)
+    tile_inst[x] = find_inst(plan, B, x, 2);
+  for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < nb; x += stride)
+    bucket_inst[x] = find_inst(plan, B, x, 3);
 }
 
 // ------------------------------------------------------------ sweep pass
@@ -626,11 +692,12 @@ __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
 
 template <int DM1, int MODE, int CAP, int THREADS>
 __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
-    const uint32_t *__restrict__ rec, Offsets O, const uint32_t *__restrict__ bs_rec,
+    const uint32_t *__restrict__ rec, Offsets O, View V, const uint32_t *__restrict__ bs_rec,
     uint32_t bs_cap, uint32_t n, const BucketParams *__restrict__ P, Header *__restrict__ hdr,
     int32_t *__restrict__ per_update, const unsigned long long *__restrict__ pair_off,
     uint32_t *__restrict__ cursor, uint32_t *__restrict__ out_u, uint32_t *__restrict__ out_s,
-    unsigned long long *__restrict__ total) {
+    unsigned long long *__restrict__ total, unsigned long long *__restrict__ inst_total,
+    const uint32_t *__restrict__ gate) {
   constexpr int RW = DM1 == 0 ? 4 : 8;
   constexpr int QW = DM1 > 0 ? DM1 : 1;
   constexpr int ITEMS = CAP / THREADS;
@@ -650,17 +717,21 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   __shared__ uint32_t red[W + 2];
   __shared__ unsigned long long red64[W];
 
+  if (MODE == 2 && gate && *gate == 0u) return;  // uniform over the grid
   const uint32_t b = blockIdx.x;
+  const uint32_t inst = V.of_bucket(b);
+  const InstPlan I = V.get(inst);
+  const size_t cell = I.cell0 + (size_t)(b - I.b0) * I.nblk;
   const uint32_t nbs_total = O.bs_begin(O.nb);
-  const uint32_t start = O.bucket_begin(b);
-  const uint32_t C = O.bucket_end(b) - start;
+  const uint32_t start = O.S[cell];
+  const uint32_t C = O.S[cell + I.nblk] - start;
   if (nbs_total > bs_cap || C > (uint32_t)CAP) {  // uniform: the host falls back
     if (threadIdx.x == 0) atomicOr(&hdr->pad[0], 1u);
     return;
   }
   const uint32_t bs_begin = O.bs_begin(b);
   const uint32_t nbs = O.bs_begin(b + 1) - bs_begin;
-  const BucketParams prm = *P;
+  const BucketParams prm = P[inst];
   const int t = threadIdx.x;
   const SweepOut o{n, per_update, pair_off, cursor, out_u, out_s};
 
@@ -840,7 +911,10 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   if (t == 0) {
     unsigned long long tot = 0;
     for (int i = 0; i < W; ++i) tot += red64[i];
-    if (tot) atomicAdd(total, tot);
+    if (tot) {
+      atomicAdd(total, tot);
+      if (inst_total) atomicAdd(&inst_total[inst], tot);
+    }
   }
 }
 
@@ -850,10 +924,11 @@ struct Ptrs {
   uint32_t *C, *T, *S, *SB, *bs_cur, *rec, *bs_rec;
   void *scan_tmp;
   Offsets O;
+  View V;
 };
 
 Ptrs pointers(const BucketArgs &a) {
-  const BucketLayout &L = a.L;
+  const BucketLayout &L = *a.L;
   char *ws = static_cast<char *>(a.ws);
   Ptrs p;
   p.P = reinterpret_cast<BucketParams *>(ws + L.params);
@@ -867,9 +942,20 @@ Ptrs pointers(const BucketArgs &a) {
   p.bs_rec = reinterpret_cast<uint32_t *>(ws + L.bs_rec);
   p.scan_tmp = ws + L.scan_tmp;
   p.O.S = p.S;
-  p.O.cells = (size_t)L.nb * L.nblk;
-  p.O.nblk = L.nblk;
+  p.O.cells = L.cells;
   p.O.nb = L.nb;
+  p.V = View{};
+  if (L.B == 1) {
+    p.V.plan = nullptr;
+    p.V.one = L.inst[0];
+  } else {
+    p.V.plan = reinterpret_cast<const InstPlan *>(ws + L.plan);
+    uint32_t *maps = reinterpret_cast<uint32_t *>(ws + L.maps);
+    p.V.blk_inst = maps;
+    p.V.smp_inst = maps + L.nblk;
+    p.V.tile_inst = maps + L.nblk + L.nsmp;
+    p.V.bucket_inst = maps + L.nblk + L.nsmp + L.ntile;
+  }
   return p;
 }
 
@@ -877,63 +963,130 @@ bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 
 
 template <int D>
 void prepare_impl(const BucketArgs &a, hipStream_t s) {
-  const BucketLayout &L = a.L;
+  const BucketLayout &L = *a.L;
   Ptrs p = pointers(a);
-  const size_t cells = p.O.cells;
-  const size_t lds = (size_t)L.nb * sizeof(uint32_t);
+  const size_t cells = L.cells;
+  const size_t lds = (size_t)L.max_nb * sizeof(uint32_t);
   const int vec = aligned16(a.ulo) && aligned16(a.uhi) && aligned16(a.slo) && aligned16(a.shi);
   prof::mark(s, "bucket.sample");
-  bk_sample_kernel<D><<<kSampleBlocks, kSampleThreads, 0, s>>>(a.ulo, a.uhi, a.slo, a.shi, a.n,
-                                                               a.m, p.part);
-  bk_plan_kernel<<<1, kSampleThreads, 0, s>>>(p.part, L.nb, p.P);
+  bk_sample_kernel<D><<<L.nsmp, kSampleThreads, 0, s>>>(a.ulo, a.uhi, a.slo, a.shi, p.V, p.part);
+  bk_plan_kernel<<<L.B, kSampleThreads, 0, s>>>(p.part, p.V, p.P);
   prof::mark(s, "bucket.count");
-  hipMemsetAsync(p.T + cells, 0, (size_t)(L.nb + 1) * sizeof(uint32_t), s);
-  bk_count_kernel<D><<<L.nblk, kThreads, lds, s>>>(a.ulo, a.uhi, a.slo, a.shi, a.n, a.m, vec, p.P,
-                                                   L.nb, L.gpb, p.C, p.T + cells, a.hdr);
+  (void)fill_u32(p.T + cells, 0u, (size_t)L.nb + 1, s);
+  bk_count_kernel<D><<<L.nblk, kThreads, lds, s>>>(a.ulo, a.uhi, a.slo, a.shi, L.n_total, vec,
+                                                   p.V, p.P, p.C, p.T + cells, a.hdr);
   prof::mark(s, "bucket.offsets");
-  transpose_kernel<<<dim3((L.nb + 63) / 64, (L.nblk + 63) / 64), 256, 0, s>>>(p.C, p.T, L.nblk,
-                                                                              L.nb);
-  exclusive_scan_u32(p.T, p.S, cells + L.nb + 1, p.scan_tmp, s);
-  transpose_kernel<<<dim3((L.nblk + 63) / 64, (L.nb + 63) / 64), 256, 0, s>>>(p.S, p.SB, L.nb,
-                                                                              L.nblk);
+  bk_transpose_kernel<<<L.ntile, 256, 0, s>>>(p.C, p.T, p.V, 0);
+  (void)exclusive_scan_u32(p.T, p.S, cells + L.nb + 1, p.scan_tmp, s);
+  bk_transpose_kernel<<<L.ntile, 256, 0, s>>>(p.S, p.SB, p.V, 1);
   prof::mark(s, "bucket.scatter");
-  hipMemsetAsync(p.bs_cur, 0, (size_t)L.nb * sizeof(uint32_t), s);
-  bk_scatter_kernel<D><<<L.nblk, kThreads, lds, s>>>(a.ulo, a.uhi, a.slo, a.shi, a.n, a.m, vec, p.P,
-                                                     L.gpb, p.O, p.SB, p.bs_cur, L.bs_cap, p.rec,
-                                                     p.bs_rec);
+  (void)fill_u32(p.bs_cur, 0u, L.nb, s);
+  bk_scatter_kernel<D><<<L.nblk, kThreads, lds, s>>>(a.ulo, a.uhi, a.slo, a.shi, L.n_total, vec,
+                                                     p.V, p.P, p.O, p.SB, p.bs_cur, L.bs_cap,
+                                                     p.rec, p.bs_rec);
 }
 
 template <int DM1, int MODE>
 void sweep_impl(const BucketArgs &a, int32_t *per_update, const unsigned long long *pair_off,
                 uint32_t *cursor, uint32_t *out_u, uint32_t *out_s, unsigned long long *total,
-                hipStream_t s) {
+                hipStream_t s, const uint32_t *gate) {
+  const BucketLayout &L = *a.L;
   Ptrs p = pointers(a);
-  bk_sweep_kernel<DM1, MODE, kCap, kSweepThreads><<<a.L.nb, kSweepThreads, 0, s>>>(
-      p.rec, p.O, p.bs_rec, a.L.bs_cap, a.n, p.P, a.hdr, per_update, pair_off, cursor, out_u,
-      out_s, total);
+  if (L.tune.sweep_threads == 256)
+    bk_sweep_kernel<DM1, MODE, kCap, 256><<<L.nb, 256, 0, s>>>(
+        p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, p.P, a.hdr, per_update, pair_off, cursor,
+        out_u, out_s, total, a.inst_total, gate);
+  else
+    bk_sweep_kernel<DM1, MODE, kCap, 512><<<L.nb, 512, 0, s>>>(
+        p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, p.P, a.hdr, per_update, pair_off, cursor,
+        out_u, out_s, total, a.inst_total, gate);
+}
+
+// Host-side plan of one instance; returns false if it does not fit.
+bool plan_instance(int64_t u0, int64_t n, int64_t s0, int64_t m, const BucketTuning &t,
+                   InstPlan &I) {
+  I = InstPlan{};
+  I.u0 = (uint32_t)u0;
+  I.n = (uint32_t)n;
+  I.s0 = (uint32_t)s0;
+  I.m = (uint32_t)m;
+  const uint64_t gu = n ? (uint64_t)((u0 + n + 3) / 4 - u0 / 4) : 0;
+  const uint64_t gs = m ? (uint64_t)((s0 + m + 3) / 4 - s0 / 4) : 0;
+  I.gu = (uint32_t)gu;
+  I.g = (uint32_t)(gu + gs);
+  const uint64_t N = (uint64_t)(n + m);
+  if (N == 0) return true;  // no blocks, buckets or samples
+  const uint64_t nb = (N + t.target - 1) / t.target;
+  if (nb > kMaxBuckets) return false;
+  I.nb = (uint32_t)nb;
+  const uint64_t per_blk = (uint64_t)kThreads * t.groups_per_thread;
+  uint64_t nblk = (I.g + per_blk - 1) / per_blk;
+  nblk = std::max<uint64_t>(1, std::min<uint64_t>(nblk, t.max_blocks));
+  I.nblk = (uint32_t)nblk;
+  I.gpb = (uint32_t)((I.g + nblk - 1) / nblk);
+  const uint64_t nsmp = std::min<uint64_t>(kMaxSampleBlocks, (N + kSampleRows - 1) / kSampleRows);
+  I.nsmp = (uint32_t)std::max<uint64_t>(1, nsmp);
+  I.ntx = (I.nb + 63) / 64;
+  return true;
 }
 
 }  // namespace
 
-bool bucket_path_supported(int d, int64_t n, int64_t m) {
-  if (d < 1 || d > 3) return false;
-  const int64_t N = n + m;
-  if (N < 1) return false;
-  const int64_t nb = (N + kTargetBucket - 1) / kTargetBucket;
-  return nb <= (int64_t)kMaxBuckets;
+bool bucket_path_supported(int d, const int64_t *upd_off, const int64_t *sub_off, int64_t B,
+                           const BucketTuning &t) {
+  if (d < 1 || d > 3 || B < 1) return false;
+  if (t.target < 64 || t.target > kBucketCap * 3 / 4) return false;
+  if (t.sweep_threads != 256 && t.sweep_threads != 512) return false;
+  if (t.groups_per_thread < 1 || t.max_blocks < 1) return false;
+  uint64_t cells = 0, nb = 0;
+  for (int64_t i = 0; i < B; ++i) {
+    InstPlan I;
+    if (!plan_instance(upd_off[i], upd_off[i + 1] - upd_off[i], sub_off[i],
+                       sub_off[i + 1] - sub_off[i], t, I))
+      return false;
+    cells += (uint64_t)I.nb * I.nblk;
+    nb += I.nb;
+  }
+  return cells + nb + 1 < (1ull << 31) && upd_off[B] + sub_off[B] > 0;
 }
 
-BucketLayout bucket_layout(int64_t n, int64_t m, int d) {
+bool bucket_path_supported(int d, int64_t n, int64_t m) {
+  const int64_t uo[2] = {0, n}, so[2] = {0, m};
+  return bucket_path_supported(d, uo, so, 1, BucketTuning{});
+}
+
+BucketLayout bucket_layout(const int64_t *upd_off, const int64_t *sub_off, int64_t B, int d,
+                           const BucketTuning &t) {
   BucketLayout L{};
-  const uint64_t N = (uint64_t)(n + m);
-  L.nb = (uint32_t)((N + kTargetBucket - 1) / kTargetBucket);
-  if (L.nb < 1) L.nb = 1;
-  const uint64_t groups = (uint64_t)((n + 3) / 4) + (uint64_t)((m + 3) / 4);
-  uint64_t nblk = (groups + kThreads - 1) / kThreads;  // at least one group per thread
-  if (nblk > kMaxBlocks) nblk = kMaxBlocks;
-  if (nblk < 1) nblk = 1;
-  L.nblk = (uint32_t)nblk;
-  L.gpb = (uint32_t)((groups + nblk - 1) / nblk);
+  L.B = (uint32_t)B;
+  L.tune = t;
+  L.inst.resize((size_t)B);
+  uint32_t blk = 0, smp = 0, tile = 0, bkt = 0;
+  size_t cell = 0;
+  for (int64_t i = 0; i < B; ++i) {
+    InstPlan &I = L.inst[(size_t)i];
+    plan_instance(upd_off[i], upd_off[i + 1] - upd_off[i], sub_off[i],
+                  sub_off[i + 1] - sub_off[i], t, I);
+    I.blk0 = blk;
+    I.smp0 = smp;
+    I.tile0 = tile;
+    I.b0 = bkt;
+    I.cell0 = (uint32_t)cell;
+    blk += I.nblk;
+    smp += I.nsmp;
+    tile += I.ntx * ((I.nblk + 63) / 64);
+    bkt += I.nb;
+    cell += (size_t)I.nb * I.nblk;
+    L.max_nb = std::max(L.max_nb, I.nb);
+  }
+  L.nb = bkt;
+  L.nblk = blk;
+  L.nsmp = smp;
+  L.ntile = tile;
+  L.cells = cell;
+  L.n_total = (uint32_t)upd_off[B];
+  L.m_total = (uint32_t)sub_off[B];
+  const uint64_t N = (uint64_t)L.n_total + L.m_total;
   L.bs_cap = (uint32_t)(N / 2 + 4096);
   L.rec_words = d == 1 ? 4 : 8;
   size_t at = 0;
@@ -942,20 +1095,43 @@ BucketLayout bucket_layout(int64_t n, int64_t m, int d) {
     at += align256(bytes);
     return o;
   };
-  const size_t cells = (size_t)L.nb * L.nblk;
-  const size_t scanned = cells + L.nb + 1;  // counts + boundary-state sizes + sentinel
-  L.params = take(sizeof(BucketParams));
-  L.sample_part = take(kSampleBlocks * 8 * sizeof(float));
-  L.counts = take(cells * sizeof(uint32_t));
+  const size_t scanned = cell + L.nb + 1;  // counts + boundary-state sizes + sentinel
+  L.params = take((size_t)B * sizeof(BucketParams));
+  L.sample_part = take((size_t)std::max<uint32_t>(L.nsmp, 1) * 8 * sizeof(float));
+  L.counts = take(cell * sizeof(uint32_t));
   L.transposed = take(scanned * sizeof(uint32_t));
   L.offsets = take(scanned * sizeof(uint32_t));
-  L.block_offsets = take(cells * sizeof(uint32_t));
+  L.block_offsets = take(cell * sizeof(uint32_t));
   L.scan_tmp = take(scan_temp_bytes(scanned));
-  L.bs_cur = take((size_t)L.nb * sizeof(uint32_t));
+  L.bs_cur = take((size_t)std::max<uint32_t>(L.nb, 1) * sizeof(uint32_t));
   L.rec = take((size_t)N * L.rec_words * sizeof(uint32_t));
   L.bs_rec = take((size_t)L.bs_cap * L.rec_words * sizeof(uint32_t));
+  L.plan = take(B > 1 ? (size_t)B * sizeof(InstPlan) : 0);
+  L.maps = take(B > 1 ? ((size_t)L.nblk + L.nsmp + L.ntile + L.nb) * sizeof(uint32_t) : 0);
   L.bytes = at;
   return L;
+}
+
+BucketLayout bucket_layout(int64_t n, int64_t m, int d) {
+  const int64_t uo[2] = {0, n}, so[2] = {0, m};
+  return bucket_layout(uo, so, 1, d, BucketTuning{});
+}
+
+hipError_t bucket_upload_plan(const BucketArgs &a, hipStream_t s) {
+  const BucketLayout &L = *a.L;
+  if (L.B <= 1) return hipSuccess;
+  Ptrs p = pointers(a);
+  InstPlan *plan = reinterpret_cast<InstPlan *>(static_cast<char *>(a.ws) + L.plan);
+  hipError_t e = hipMemcpyAsync(plan, L.inst.data(), L.inst.size() * sizeof(InstPlan),
+                                hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  const uint32_t most = std::max(std::max(L.nblk, L.nsmp), std::max(L.ntile, L.nb));
+  const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>((most + 255) / 256, 1024));
+  bk_expand_maps_kernel<<<grid, 256, 0, s>>>(plan, L.B, const_cast<uint32_t *>(p.V.blk_inst),
+                                             L.nblk, const_cast<uint32_t *>(p.V.smp_inst), L.nsmp,
+                                             const_cast<uint32_t *>(p.V.tile_inst), L.ntile,
+                                             const_cast<uint32_t *>(p.V.bucket_inst), L.nb);
+  return hipGetLastError();
 }
 
 hipError_t bucket_prepare(const BucketArgs &a, hipStream_t s) {
@@ -969,15 +1145,16 @@ hipError_t bucket_prepare(const BucketArgs &a, hipStream_t s) {
 
 hipError_t bucket_sweep(const BucketArgs &a, int mode, int32_t *per_update,
                         const unsigned long long *pair_off, uint32_t *cursor, uint32_t *out_u,
-                        uint32_t *out_s, unsigned long long *total, hipStream_t s) {
+                        uint32_t *out_s, unsigned long long *total, hipStream_t s,
+                        const uint32_t *gate) {
   prof::mark(s, mode == 2 ? "bucket.sweep.emit" : "bucket.sweep");
 #define DDM_SWEEP(DM1)                                                                     \
   if (mode == 0)                                                                           \
-    sweep_impl<DM1, 0>(a, per_update, pair_off, cursor, out_u, out_s, total, s);           \
+    sweep_impl<DM1, 0>(a, per_update, pair_off, cursor, out_u, out_s, total, s, gate);    \
   else if (mode == 1)                                                                      \
-    sweep_impl<DM1, 1>(a, per_update, pair_off, cursor, out_u, out_s, total, s);           \
+    sweep_impl<DM1, 1>(a, per_update, pair_off, cursor, out_u, out_s, total, s, gate);    \
   else                                                                                     \
-    sweep_impl<DM1, 2>(a, per_update, pair_off, cursor, out_u, out_s, total, s);
+    sweep_impl<DM1, 2>(a, per_update, pair_off, cursor, out_u, out_s, total, s, gate);
   switch (a.d) {
     case 1: DDM_SWEEP(0) break;
     case 2: DDM_SWEEP(1) break;

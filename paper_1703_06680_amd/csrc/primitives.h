@@ -17,6 +17,11 @@ hipError_t exclusive_scan_u32(const uint32_t *in, uint32_t *out, size_t count, v
 hipError_t exclusive_scan_u64(const unsigned long long *in, unsigned long long *out,
                               size_t count, void *temp, hipStream_t s);
 
+// out[i] = value for i < count, by a kernel (so that it may be recorded into a
+// graph, unlike a memset node).
+hipError_t fill_u32(uint32_t *out, uint32_t value, size_t count, hipStream_t s);
+hipError_t fill_u64(unsigned long long *out, unsigned long long value, size_t count, hipStream_t s);
+
 // Optional range reduction applied to keys before digits are taken:
 // key' = (key == 0xFFFFFFFF) ? sentinel_code : key - kmin.
 struct KeyTransform {
@@ -37,9 +42,11 @@ size_t radix_sort_temp_bytes(uint32_t count);
 // key, ping-ponging between buffer A and buffer B.  If ``vals_iota`` the
 // values of A are not read and value i is taken to be i.  ``*in_b`` is set
 // to 1 if the sorted result is in B, 0 if it is in A.  bits == 0 leaves the
-// data in A (and materialises the iota values if asked).
+// data in A (and materialises the iota values if asked).  If ``count_dev`` is
+// not null, the number of pairs is min(count, *count_dev), read on the device
+// (launch sizes follow ``count``, which is then a capacity).
 hipError_t radix_sort_pairs(uint32_t *keys_a, uint32_t *vals_a, uint32_t *keys_b, uint32_t *vals_b,
                             uint32_t count, int bits, bool vals_iota, KeyTransform xf, void *temp,
-                            hipStream_t s, int *in_b);
+                            hipStream_t s, int *in_b, const uint32_t *count_dev = nullptr);
 
 }  // namespace ddm

@@ -10,6 +10,8 @@
 // inside its tile (wave-level digit match with ballots, per-wave running
 // counters in LDS) and scatters it.  Ranks follow input order within a tile
 // and tiles follow input order within a digit, so every pass is stable.
+#include <algorithm>
+
 #include "common.h"
 #include "primitives.h"
 #include "profile.h"
@@ -116,10 +118,17 @@ __device__ __forceinline__ uint32_t transform_key(uint32_t k, KeyTransform xf) {
   return k == kSentinel ? xf.sentinel_code : k - xf.kmin;
 }
 
+__device__ __forceinline__ uint32_t live_count(uint32_t count, const uint32_t *count_dev) {
+  if (!count_dev) return count;
+  const uint32_t c = *count_dev;
+  return c < count ? c : count;
+}
+
 __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(
     const uint32_t *__restrict__ keys, uint32_t count, KeyTransform xf, int shift,
-    uint32_t *__restrict__ counts, uint32_t ntiles) {
+    uint32_t *__restrict__ counts, uint32_t ntiles, const uint32_t *__restrict__ count_dev) {
   __shared__ uint32_t hist[kRadix];
+  count = live_count(count, count_dev);
   for (int i = threadIdx.x; i < kRadix; i += kSortThreads) hist[i] = 0;
   __syncthreads();
   const size_t base = (size_t)blockIdx.x * kSortTile;
@@ -139,8 +148,10 @@ template <bool kIota>
 __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
     uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out, uint32_t count,
-    KeyTransform xf, int shift, const uint32_t *__restrict__ offsets, uint32_t ntiles) {
+    KeyTransform xf, int shift, const uint32_t *__restrict__ offsets, uint32_t ntiles,
+    const uint32_t *__restrict__ count_dev) {
   constexpr int W = kSortThreads / kWave;
+  count = live_count(count, count_dev);
   __shared__ uint32_t wcnt[W][kRadix];
   __shared__ uint32_t wbase[W][kRadix];
   const int tid = threadIdx.x;
@@ -198,13 +209,38 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
   }
 }
 
-__global__ void iota_kernel(uint32_t *out, uint32_t count) {
+__global__ void iota_kernel(uint32_t *out, uint32_t count, const uint32_t *count_dev) {
+  count = live_count(count, count_dev);
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
        i += (size_t)gridDim.x * blockDim.x)
     out[i] = (uint32_t)i;
 }
 
+template <typename T>
+__global__ void fill_kernel(T *out, T value, size_t count) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (size_t)gridDim.x * blockDim.x)
+    out[i] = value;
+}
+
+template <typename T>
+hipError_t fill_impl(T *out, T value, size_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  const size_t blocks = std::min<size_t>(div_up(count, 256), 2048);
+  fill_kernel<T><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(out, value, count);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t fill_u32(uint32_t *out, uint32_t value, size_t count, hipStream_t s) {
+  return fill_impl<uint32_t>(out, value, count, s);
+}
+
+hipError_t fill_u64(unsigned long long *out, unsigned long long value, size_t count,
+                    hipStream_t s) {
+  return fill_impl<unsigned long long>(out, value, count, s);
+}
 
 size_t scan_temp_bytes(size_t count) {
   return align256(div_up(count ? count : 1, kScanChunk) * sizeof(unsigned long long));
@@ -228,13 +264,13 @@ size_t radix_sort_temp_bytes(uint32_t count) {
 
 hipError_t radix_sort_pairs(uint32_t *keys_a, uint32_t *vals_a, uint32_t *keys_b, uint32_t *vals_b,
                             uint32_t count, int bits, bool vals_iota, KeyTransform xf, void *temp,
-                            hipStream_t s, int *in_b) {
+                            hipStream_t s, int *in_b, const uint32_t *count_dev) {
   *in_b = 0;
   if (count == 0) return hipSuccess;
   const int passes = (bits + kRadixBits - 1) / kRadixBits;
   if (passes == 0) {
     prof::mark(s, "sort.iota");
-    if (vals_iota) iota_kernel<<<dim3(1024), dim3(256), 0, s>>>(vals_a, count);
+    if (vals_iota) iota_kernel<<<dim3(1024), dim3(256), 0, s>>>(vals_a, count, count_dev);
     return hipGetLastError();
   }
   const uint32_t ntiles = (uint32_t)div_up(count, kSortTile);
@@ -247,16 +283,16 @@ hipError_t radix_sort_pairs(uint32_t *keys_a, uint32_t *vals_a, uint32_t *keys_b
     const int shift = p * kRadixBits;
     prof::mark(s, "sort.upsweep");
     radix_upsweep_kernel<<<dim3(ntiles), dim3(kSortThreads), 0, s>>>(ck, count, xf, shift, counts,
-                                                                     ntiles);
+                                                                     ntiles, count_dev);
     hipError_t e = exclusive_scan_u32(counts, counts, hist, scan_tmp, s);
     if (e != hipSuccess) return e;
     prof::mark(s, "sort.downsweep");
     if (iota)
       radix_downsweep_kernel<true><<<dim3(ntiles), dim3(kSortThreads), 0, s>>>(
-          ck, cv, ok, ov, count, xf, shift, counts, ntiles);
+          ck, cv, ok, ov, count, xf, shift, counts, ntiles, count_dev);
     else
       radix_downsweep_kernel<false><<<dim3(ntiles), dim3(kSortThreads), 0, s>>>(
-          ck, cv, ok, ov, count, xf, shift, counts, ntiles);
+          ck, cv, ok, ov, count, xf, shift, counts, ntiles, count_dev);
     iota = false;
     uint32_t *tk = ck, *tv = cv;
     ck = ok;

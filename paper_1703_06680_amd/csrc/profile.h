@@ -15,6 +15,9 @@ namespace ddm {
 namespace prof {
 
 bool enabled();
+// Sets recording on or off and returns the previous setting (recording is
+// switched off while a graph is captured).
+bool swap_enabled(bool on);
 void mark(hipStream_t s, const char *phase);
 void end(hipStream_t s);
 // Resolve the recorded events (the stream must have been synchronised).

@@ -43,6 +43,12 @@ hipEvent_t take_event() {
 
 bool enabled() { return g_on; }
 
+bool swap_enabled(bool on) {
+  const bool was = g_on;
+  g_on = on;
+  return was;
+}
+
 void mark(hipStream_t s, const char *phase) {
   if (!g_on) return;
   hipEvent_t e = take_event();

@@ -28,6 +28,15 @@ PATHS = {"auto": 0, "bucketed": 1, "global": 2}
 MAX_DIMS = 16
 
 
+class Tuning(ctypes.Structure):
+    """Launch shape of the batched path (``ddm_tuning``)."""
+    _fields_ = [("target", ctypes.c_int32), ("sweep_threads", ctypes.c_int32),
+                ("groups_per_thread", ctypes.c_int32), ("max_blocks", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
 class DDMError(RuntimeError):
     def __init__(self, code: int, where: str = "ddm_match"):
         self.code = code
@@ -62,6 +71,29 @@ def library() -> ctypes.CDLL:
         lib.ddm_profile.restype = ctypes.c_int
         lib.ddm_profile_report.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
         lib.ddm_profile_report.restype = ctypes.c_int
+        tp = ctypes.POINTER(Tuning)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        lib.ddm_default_tuning.argtypes = [tp]
+        lib.ddm_default_tuning.restype = None
+        lib.ddm_batch_workspace_bytes.argtypes = [vp, vp, i64, ctypes.c_int, ctypes.c_int, i64, tp]
+        lib.ddm_batch_workspace_bytes.restype = ctypes.c_size_t
+        lib.ddm_match_batched.argtypes = [vp, vp, vp, vp, vp, vp, i64, ctypes.c_int, ctypes.c_int,
+                                          vp, ctypes.c_size_t, vp, tp, vp, u64p, vp, vp, vp, i64]
+        lib.ddm_match_batched.restype = ctypes.c_int
+        lib.ddm_batch_graph_create.argtypes = [vp, vp, vp, vp, vp, vp, i64, ctypes.c_int,
+                                               ctypes.c_int, vp, ctypes.c_size_t, tp, vp, vp, vp,
+                                               vp, i64, ctypes.POINTER(vp)]
+        lib.ddm_batch_graph_create.restype = ctypes.c_int
+        lib.ddm_batch_graph_launch.argtypes = [vp, vp]
+        lib.ddm_batch_graph_launch.restype = ctypes.c_int
+        lib.ddm_batch_graph_result.argtypes = [vp, vp, u64p]
+        lib.ddm_batch_graph_result.restype = ctypes.c_int
+        lib.ddm_batch_graph_destroy.argtypes = [vp]
+        lib.ddm_batch_graph_destroy.restype = ctypes.c_int
+        lib.ddm_batch_autotune.argtypes = [vp, vp, vp, vp, vp, vp, i64, ctypes.c_int, ctypes.c_int,
+                                           vp, ctypes.c_size_t, vp, vp, vp, vp, vp, i64, tp,
+                                           ctypes.POINTER(ctypes.c_double)]
+        lib.ddm_batch_autotune.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -208,3 +240,184 @@ def match(upd_lo, upd_hi, sub_lo, sub_hi, mode: str = "count", *, pair_capacity:
                 raise DDMError(rc)
             k = int(cnt.value)
             return k, out[:k], (per[:n] if per is not None else None)
+
+
+# --------------------------------------------------------------- batches
+
+def default_tuning() -> Tuning:
+    t = Tuning()
+    library().ddm_default_tuning(ctypes.byref(t))
+    return t
+
+
+def _offsets(off, name: str):
+    """Host int64 CSR offsets as a contiguous numpy array (kept alive by the caller)."""
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(off, dtype=np.int64))
+    if a.ndim != 1 or a.size < 2:
+        raise ValueError(f"{name}: expected a 1-D array of B + 1 offsets")
+    return a
+
+
+def _aptr(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+class Batch:
+    """A batch of independent instances stored back to back.
+
+    ``upd_lo``/``upd_hi`` float32 [sum n, d] and ``sub_lo``/``sub_hi``
+    float32 [sum m, d] on one GPU; ``upd_off``/``sub_off`` host offsets
+    [B + 1] (instance b owns rows upd_off[b]:upd_off[b+1] and
+    sub_off[b]:sub_off[b+1]).  Holds the output tensors:
+    ``counts`` uint64-as-int64 [B], ``per_update`` int32 [sum n] (modes
+    per_update and pairs), ``pairs`` int32 [capacity, 2] and ``pair_off``
+    int64 [B + 1] (mode pairs), and the workspace.
+    """
+
+    def __init__(self, upd_lo, upd_hi, upd_off, sub_lo, sub_hi, sub_off, mode: str = "count",
+                 pair_capacity: int = 0, workspace: torch.Tensor | None = None):
+        if mode not in MODES:
+            raise ValueError(f"unknown mode {mode!r}")
+        _check_boxes(upd_lo, upd_hi, "updates")
+        _check_boxes(sub_lo, sub_hi, "subscriptions")
+        self.uoff = _offsets(upd_off, "upd_off")
+        self.soff = _offsets(sub_off, "sub_off")
+        if self.uoff.size != self.soff.size:
+            raise ValueError("upd_off and sub_off must have the same length")
+        self.B = self.uoff.size - 1
+        self.d = upd_lo.shape[1]
+        if sub_lo.shape[1] != self.d:
+            raise ValueError("updates and subscriptions differ in dimension")
+        if int(self.uoff[-1]) != upd_lo.shape[0] or int(self.soff[-1]) != sub_lo.shape[0]:
+            raise ValueError("the last offset must equal the number of rows")
+        self.mode = mode
+        self.code = MODES[mode]
+        self.dev = upd_lo.device
+        self.inputs = (upd_lo, upd_hi, sub_lo, sub_hi)
+        self.cap = int(pair_capacity)
+        self.ws = workspace
+        self._reserve(None)
+        n_total = int(self.uoff[-1])
+        self.counts = torch.zeros(self.B, dtype=torch.int64, device=self.dev)
+        self.per_update = (torch.zeros(max(n_total, 1), dtype=torch.int32, device=self.dev)
+                           if mode != "count" else None)
+        self.pairs = (torch.empty((max(self.cap, 1), 2), dtype=torch.int32, device=self.dev)
+                      if mode == "pairs" else None)
+        self.pair_off = (torch.zeros(self.B + 1, dtype=torch.int64, device=self.dev)
+                         if mode == "pairs" else None)
+
+    def _reserve(self, tuning) -> None:
+        """Grows the workspace to what ``tuning`` (None: the default and the
+        autotuner's candidates) needs."""
+        need = library().ddm_batch_workspace_bytes(
+            _aptr(self.uoff), _aptr(self.soff), self.B, self.d, self.code, self.cap,
+            ctypes.byref(tuning) if tuning is not None else None)
+        if need == 0:
+            raise DDMError(DDM_E_INVAL, "ddm_batch_workspace_bytes")
+        if self.ws is None or self.ws.numel() < need:
+            self.ws = torch.empty(need, dtype=torch.uint8, device=self.dev)
+
+    def _common(self):
+        ul, uh, sl, sh = self.inputs
+        return [_ptr(ul), _ptr(uh), _aptr(self.uoff), _ptr(sl), _ptr(sh), _aptr(self.soff),
+                self.B, self.d, self.code, ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel()]
+
+    def _outs(self):
+        return [_ptr(self.counts), _ptr(self.per_update) if self.per_update is not None else None,
+                _ptr(self.pairs) if self.pairs is not None else None,
+                _ptr(self.pair_off) if self.pair_off is not None else None, self.cap]
+
+    def run(self, tuning: Tuning | None = None, stream=None) -> int:
+        """One plain batched call; returns the total number of pairs."""
+        if stream is None:
+            stream = torch.cuda.current_stream(self.dev)
+        total = ctypes.c_uint64(0)
+        if tuning is not None:
+            self._reserve(tuning)
+        c, o = self._common(), self._outs()
+        with torch.cuda.device(self.dev):
+            rc = library().ddm_match_batched(
+                *c, ctypes.c_void_p(stream.cuda_stream),
+                ctypes.byref(tuning) if tuning is not None else None, o[0], ctypes.byref(total),
+                o[1], o[2], o[3], o[4])
+        if rc != DDM_OK:
+            raise DDMError(rc, "ddm_match_batched")
+        return int(total.value)
+
+    def graph(self, tuning: Tuning | None = None) -> "BatchGraph":
+        return BatchGraph(self, tuning)
+
+    def autotune(self, stream=None):
+        """Fastest tuning for this batch and its replay time in ms."""
+        if stream is None:
+            stream = torch.cuda.current_stream(self.dev)
+        best = Tuning()
+        ms = ctypes.c_double(0.0)
+        c, o = self._common(), self._outs()
+        with torch.cuda.device(self.dev):
+            rc = library().ddm_batch_autotune(*c, ctypes.c_void_p(stream.cuda_stream), *o,
+                                              ctypes.byref(best), ctypes.byref(ms))
+        if rc != DDM_OK:
+            raise DDMError(rc, "ddm_batch_autotune")
+        return best, float(ms.value)
+
+    # results of the last run / replay, per instance
+    def instance_pairs(self, b: int) -> torch.Tensor:
+        lo, hi = (int(x) for x in self.pair_off[b:b + 2].cpu())
+        return self.pairs[lo:hi]
+
+    def instance_per_update(self, b: int) -> torch.Tensor:
+        return self.per_update[int(self.uoff[b]):int(self.uoff[b + 1])]
+
+
+class BatchGraph:
+    """The batch captured as one HIP graph (``ddm_batch_graph_*``)."""
+
+    def __init__(self, batch: Batch, tuning: Tuning | None = None):
+        self.batch = batch
+        self.handle = ctypes.c_void_p(None)
+        # a graph keeps its plan in its workspace: give it one of its own
+        need = library().ddm_batch_workspace_bytes(
+            _aptr(batch.uoff), _aptr(batch.soff), batch.B, batch.d, batch.code, batch.cap,
+            ctypes.byref(tuning) if tuning is not None else None)
+        if need == 0:
+            raise DDMError(DDM_E_INVAL, "ddm_batch_workspace_bytes")
+        self.ws = torch.empty(need, dtype=torch.uint8, device=batch.dev)
+        c, o = batch._common(), batch._outs()
+        c[9], c[10] = ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel()
+        with torch.cuda.device(batch.dev):
+            rc = library().ddm_batch_graph_create(
+                *c, ctypes.byref(tuning) if tuning is not None else None, *o,
+                ctypes.byref(self.handle))
+        if rc != DDM_OK:
+            raise DDMError(rc, "ddm_batch_graph_create")
+
+    def launch(self, stream=None) -> None:
+        if stream is None:
+            stream = torch.cuda.current_stream(self.batch.dev)
+        rc = library().ddm_batch_graph_launch(self.handle, ctypes.c_void_p(stream.cuda_stream))
+        if rc != DDM_OK:
+            raise DDMError(rc, "ddm_batch_graph_launch")
+
+    def result(self, stream=None) -> int:
+        if stream is None:
+            stream = torch.cuda.current_stream(self.batch.dev)
+        total = ctypes.c_uint64(0)
+        with torch.cuda.device(self.batch.dev):
+            rc = library().ddm_batch_graph_result(self.handle, ctypes.c_void_p(stream.cuda_stream),
+                                                  ctypes.byref(total))
+        if rc != DDM_OK:
+            raise DDMError(rc, "ddm_batch_graph_result")
+        return int(total.value)
+
+    def close(self) -> None:
+        if self.handle and self.handle.value:
+            library().ddm_batch_graph_destroy(self.handle)
+            self.handle = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

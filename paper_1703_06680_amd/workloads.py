@@ -171,3 +171,24 @@ def batched_instances(count: int = 512, d: int = 2, seed: int = 0, lo: int = 1_0
         slo, shi = uniform_regions(rng, n, d, side)
         insts.append(Instance(ulo, uhi, slo, shi, float(al[i]), f"batch{i}"))
     return insts
+
+
+def concat_instances(insts):
+    """Stores instances back to back: (upd_lo, upd_hi, upd_off, sub_lo,
+    sub_hi, sub_off) with host int64 offsets [B + 1]; instance b owns rows
+    upd_off[b]:upd_off[b+1] and sub_off[b]:sub_off[b+1]."""
+    d = insts[0].d if insts else 1
+    uoff = np.zeros(len(insts) + 1, dtype=np.int64)
+    soff = np.zeros(len(insts) + 1, dtype=np.int64)
+    for i, t in enumerate(insts):
+        if t.d != d:
+            raise ValueError("instances of one batch share d")
+        uoff[i + 1] = uoff[i] + t.n
+        soff[i + 1] = soff[i] + t.m
+
+    def cat(arrs):
+        arrs = [np.asarray(a, dtype=np.float32).reshape(-1, d) for a in arrs]
+        return np.ascontiguousarray(np.concatenate(arrs) if arrs else np.zeros((0, d), np.float32))
+
+    return (cat([t.upd_lo for t in insts]), cat([t.upd_hi for t in insts]), uoff,
+            cat([t.sub_lo for t in insts]), cat([t.sub_hi for t in insts]), soff)

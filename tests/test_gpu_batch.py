@@ -1,0 +1,229 @@
+"""GPU parity of the batched entry points against the CPU oracle, instance by
+instance: plain batched calls, captured-graph replays (several, with eager
+work and input rewrites in between), capacity reporting, the per-instance
+fallback, and the autotuner's consistency.  Every comparison is exact."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1703_06680_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _note(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ddm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1703_06680_amd import ddm as D
+    D.library()
+    return D
+
+
+def _mixed(d, seed=0):
+    """Instances of uneven sizes, including empty ones and tie-heavy ones."""
+    out = []
+    sizes = [(0, 0), (5, 0), (0, 7), (1, 1), (300, 200), (2000, 2500), (17, 4000), (6000, 5000),
+             (33, 35), (1200, 900)]
+    for i, (n, m) in enumerate(sizes):
+        t = W.uniform_instance(n, m, d, alpha=[0.5, 3.0, 10.0][i % 3], seed=seed * 100 + i)
+        out.append(t)
+    out.append(W.tie_heavy(700, 800, d, grid=40, max_len=6, seed=seed + 5))
+    out.append(W.random_float_boxes(900, 700, d, seed=seed + 3, extent=200.0))
+    return out
+
+
+def _oracle_all(oracle, insts):
+    return [oracle.sbm(t.upd_lo, t.upd_hi, t.sub_lo, t.sub_hi, pairs=True) for t in insts]
+
+
+def _check(batch, insts, refs, mode, total):
+    counts = batch.counts.cpu().numpy()
+    assert total == sum(r[0] for r in refs)
+    for b, (t, (k, per, pairs)) in enumerate(zip(insts, refs)):
+        assert int(counts[b]) == k, (t.name, b, int(counts[b]), k)
+        if mode != "count" and t.n:
+            assert np.array_equal(batch.instance_per_update(b).cpu().numpy(), per), (t.name, b)
+        if mode == "pairs":
+            assert np.array_equal(batch.instance_pairs(b).cpu().numpy(), pairs), (t.name, b)
+
+
+def _device_batch(ddm, insts, mode, cap=0):
+    ulo, uhi, uoff, slo, shi, soff = W.concat_instances(insts)
+    g = [torch.from_numpy(a).cuda() for a in (ulo, uhi, slo, shi)]
+    return ddm.Batch(g[0], g[1], uoff, g[2], g[3], soff, mode=mode, pair_capacity=cap), g
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("mode", ["count", "per_update", "pairs"])
+def test_batched_matches_oracle(ddm, oracle, d, mode):
+    insts = _mixed(d, seed=d)
+    refs = _oracle_all(oracle, insts)
+    K = sum(r[0] for r in refs)
+    _note(f"batched d={d} mode={mode} B={len(insts)} K={K}")
+    batch, _ = _device_batch(ddm, insts, mode, cap=K + 10)
+    total = batch.run()
+    _check(batch, insts, refs, mode, total)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_graph_replays_and_rewrites(ddm, oracle, d):
+    insts = _mixed(d, seed=7)
+    refs = _oracle_all(oracle, insts)
+    K = sum(r[0] for r in refs)
+    batch, g = _device_batch(ddm, insts, "pairs", cap=2 * K + 100)
+    graph = batch.graph()
+    _note(f"graph d={d} B={len(insts)} K={K}")
+    for rep in range(3):
+        graph.launch()
+        total = graph.result()
+        _check(batch, insts, refs, "pairs", total)
+        # eager work of the program between replays
+        batch.pairs.fill_(-1)
+        batch.counts.fill_(12345)
+        torch.cuda.synchronize()
+    # same sizes, new coordinates: the replay sees the rewritten inputs
+    insts2 = _mixed(d, seed=8)
+    refs2 = _oracle_all(oracle, insts2)
+    if sum(r[0] for r in refs2) <= batch.cap:
+        ulo, uhi, _, slo, shi, _ = W.concat_instances(insts2)
+        for dst, src in zip(g, (ulo, uhi, slo, shi)):
+            dst.copy_(torch.from_numpy(src))
+        graph.launch()
+        total = graph.result()
+        _check(batch, insts2, refs2, "pairs", total)
+    graph.close()
+
+
+def test_graph_per_update_mode(ddm, oracle):
+    insts = _mixed(2, seed=11)
+    refs = _oracle_all(oracle, insts)
+    batch, _ = _device_batch(ddm, insts, "per_update")
+    graph = batch.graph()
+    for _ in range(2):
+        graph.launch()
+        total = graph.result()
+        _check(batch, insts, refs, "per_update", total)
+    graph.close()
+
+
+def test_batched_capacity(ddm, oracle):
+    insts = _mixed(2, seed=4)
+    refs = _oracle_all(oracle, insts)
+    K = sum(r[0] for r in refs)
+    assert K > 10
+    batch, _ = _device_batch(ddm, insts, "pairs", cap=K - 1)
+    with pytest.raises(ddm.DDMError) as e:
+        batch.run()
+    assert e.value.code == ddm.DDM_E_CAPACITY
+    counts = batch.counts.cpu().numpy()
+    assert [int(c) for c in counts] == [r[0] for r in refs]
+    expect_off = np.concatenate([[0], np.cumsum([r[0] for r in refs])])
+    assert np.array_equal(batch.pair_off.cpu().numpy(), expect_off)
+    # the graph reports the same
+    graph = batch.graph()
+    graph.launch()
+    with pytest.raises(ddm.DDMError) as e:
+        graph.result()
+    assert e.value.code == ddm.DDM_E_CAPACITY
+    graph.close()
+
+
+def test_batched_overflow_falls_back(ddm, oracle):
+    """One instance piles thousands of regions onto one coordinate (a bucket
+    cannot hold them): the batch is matched instance by instance instead,
+    with identical results, in a plain call and after a graph replay."""
+    d = 2
+    rng = np.random.default_rng(5)
+    lo = np.zeros((3000, d), np.float32)
+    hi = np.ones((3000, d), np.float32)
+    heavy = W.Instance(lo, hi, lo[:2500].copy(), hi[:2500].copy(), float("nan"), "identical")
+    insts = _mixed(d, seed=2)[:6] + [heavy] + _mixed(d, seed=2)[6:]
+    refs = _oracle_all(oracle, insts)
+    K = sum(r[0] for r in refs)
+    assert K >= 3000 * 2500
+    batch, _ = _device_batch(ddm, insts, "pairs", cap=K)
+    _check(batch, insts, refs, "pairs", batch.run())
+    del rng
+    graph = batch.graph()
+    graph.launch()
+    _check(batch, insts, refs, "pairs", graph.result())
+    graph.close()
+
+
+def test_batched_high_d_runs_each(ddm, oracle):
+    insts = [W.random_float_boxes(300, 250, 5, seed=s, extent=60.0) for s in range(4)]
+    refs = _oracle_all(oracle, insts)
+    batch, _ = _device_batch(ddm, insts, "pairs", cap=sum(r[0] for r in refs) + 1)
+    _check(batch, insts, refs, "pairs", batch.run())
+    with pytest.raises(ddm.DDMError) as e:
+        batch.graph()
+    assert e.value.code == ddm.DDM_E_UNSUPPORTED
+
+
+def test_tunings_agree(ddm, oracle):
+    """Every tuning gives the oracle's result, and the autotuner picks one."""
+    insts = _mixed(3, seed=9)
+    refs = _oracle_all(oracle, insts)
+    K = sum(r[0] for r in refs)
+    batch, _ = _device_batch(ddm, insts, "pairs", cap=K + 1)
+    for target in (64, 768, 1536):
+        for threads in (256, 512):
+            t = ddm.Tuning(target, threads, 2, 3)
+            _note(f"tuning {t.as_dict()}")
+            _check(batch, insts, refs, "pairs", batch.run(tuning=t))
+    best, ms = batch.autotune()
+    assert best.sweep_threads in (256, 512) and ms > 0
+    _check(batch, insts, refs, "pairs", batch.run(tuning=best))
+
+
+def test_batched_workload_sampled(ddm, oracle):
+    """The 512-instance d=2 batch (n = m log-uniform on [1e3, 2e5], alpha in
+    {0.01, 1, 10}), one captured graph, checked exactly against the oracle on
+    a sample of instances and for consistency on all of them."""
+    insts = W.batched_instances(512, d=2, seed=0)
+    ulo, uhi, uoff, slo, shi, soff = W.concat_instances(insts)
+    g = [torch.from_numpy(a).cuda() for a in (ulo, uhi, slo, shi)]
+    batch = ddm.Batch(g[0], g[1], uoff, g[2], g[3], soff, mode="pairs", pair_capacity=1 << 20)
+    graph = batch.graph()
+    graph.launch()
+    total = graph.result()
+    counts = batch.counts.cpu().numpy().astype(np.int64)
+    assert int(counts.sum()) == total
+    per = batch.per_update.cpu().numpy()
+    off = batch.pair_off.cpu().numpy()
+    assert off[-1] == total and np.all(np.diff(off) == counts)
+    for b in range(512):
+        assert int(per[uoff[b]:uoff[b + 1]].sum()) == counts[b]
+    rng = np.random.default_rng(1)
+    sample = sorted(set(rng.choice(512, size=12, replace=False).tolist()) | {int(np.argmax(uoff[1:] - uoff[:-1]))})
+    for b in sample:
+        t = insts[b]
+        k, p, pairs = oracle.sbm(t.upd_lo, t.upd_hi, t.sub_lo, t.sub_hi, pairs=True)
+        _note(f"batch instance {b} n={t.n} alpha={t.alpha} K={k}")
+        assert int(counts[b]) == k
+        assert np.array_equal(per[uoff[b]:uoff[b + 1]], p)
+        assert np.array_equal(batch.pairs[off[b]:off[b + 1]].cpu().numpy(), pairs)
+    graph.close()
+
+
+def test_same_arrays_for_both_kinds(ddm, oracle):
+    """Updates and subscriptions may be the very same device arrays."""
+    t = W.random_float_boxes(1500, 1500, 2, seed=21, extent=150.0)
+    k, per, pairs = oracle.sbm(t.upd_lo, t.upd_hi, t.upd_lo, t.upd_hi, pairs=True)
+    lo = torch.from_numpy(t.upd_lo).cuda()
+    hi = torch.from_numpy(t.upd_hi).cuda()
+    k2, p2, per2 = ddm.match(lo, hi, lo, hi, mode="pairs")
+    assert k2 == k and np.array_equal(p2.cpu().numpy(), pairs)
+    off = np.array([0, 1500])
+    batch = ddm.Batch(lo, hi, off, lo, hi, off, mode="pairs", pair_capacity=k + 1)
+    assert batch.run() == k
+    assert np.array_equal(batch.instance_pairs(0).cpu().numpy(), pairs)
