@@ -168,6 +168,25 @@ int ddm_match_batched(const float *upd_lo, const float *upd_hi, const int64_t *u
                       int64_t pair_capacity);
 
 /*
+ * The same for instances held in separate arrays: inst[b] gives instance b's
+ * device row arrays (float32 [n][d] / [m][d]) and sizes.  Output rows
+ * (per_update, pair_off) number the updates of all instances consecutively
+ * in instance order, exactly as if the instances were stored back to back;
+ * ids in pairs are local to the instance.  Errors as ddm_match_batched().
+ */
+typedef struct ddm_instance {
+  const float *upd_lo, *upd_hi;
+  const float *sub_lo, *sub_hi;
+  int64_t n, m;
+} ddm_instance;
+size_t ddm_multi_workspace_bytes(const ddm_instance *inst, int64_t B, int d, int mode,
+                                 int64_t pair_capacity, const ddm_tuning *tuning);
+int ddm_match_multi(const ddm_instance *inst, int64_t B, int d, int mode, void *workspace,
+                    size_t ws_bytes, void *stream, const ddm_tuning *tuning, uint64_t *counts,
+                    uint64_t *total_host, int32_t *per_update, int32_t *pairs,
+                    int64_t *pair_off, int64_t pair_capacity);
+
+/*
  * The batch as one captured HIP graph.  ddm_batch_graph_create() validates
  * the arguments, writes the batch plan into the workspace and captures every
  * launch of ddm_match_batched() (from zeroing the outputs to the ordered
@@ -206,6 +225,75 @@ int ddm_batch_autotune(const float *upd_lo, const float *upd_hi, const int64_t *
                        int64_t B, int d, int mode, void *workspace, size_t ws_bytes, void *stream,
                        uint64_t *counts, int32_t *per_update, int32_t *pairs, int64_t *pair_off,
                        int64_t pair_capacity, ddm_tuning *best, double *best_ms);
+
+/* ------------------------------------------------------------------------
+ * Serving: resident simulations, one matching request per time step.
+ *
+ * A simulation's regions (device float32 arrays, owned by the caller, updated
+ * in place) stay in device memory for its whole life.  A request for
+ * simulation j takes one random-walk step of j's regions and then counts the
+ * intersecting pairs of the moved regions (DDM_COUNT semantics).
+ *
+ * ddm_sim_step() enqueues one step on a stream: region r (updates are
+ * regions 0 .. n-1, subscriptions n .. n+m-1) moves its lower corner on axis
+ * k by sigma * z and its upper corner is reset to lo + side (IEEE float32
+ * operations, each rounded to nearest), where z is the sum of twelve uniforms
+ * minus six; the uniforms are the twelve 32-bit words (each shifted right by
+ * 8) of Philox4x32-10 at counters (r, k, step, 0..2) under the 64-bit key
+ * seed, so the motion is reproducible bit for bit by any implementation of
+ * that generator.  step numbers the step being taken (1 for the first).
+ * ------------------------------------------------------------------------ */
+int ddm_sim_step(float *upd_lo, float *upd_hi, int64_t n, float *sub_lo, float *sub_hi,
+                 int64_t m, int d, float side, float sigma, uint64_t seed, uint32_t step,
+                 void *stream);
+
+/* Scheduling policies of a server. */
+#define DDM_SERVE_BATCHED 0 /* continuous batching over several streams       */
+#define DDM_SERVE_PLAIN 1   /* one request at a time, in arrival order, with
+                               ddm_match(): the per-request baseline          */
+
+typedef struct ddm_serve_stats {
+  double wall_s;           /* first arrival slot to last completion           */
+  int64_t launches;        /* matching launches (groups) issued               */
+  double mean_batch;       /* requests per launch                             */
+  double peak_arena_bytes; /* most arena bytes in use at once                 */
+} ddm_serve_stats;
+
+/*
+ * Creates a server on the current device.  arena (device, arena_bytes,
+ * 256-byte aligned, owned by the caller) is the HBM budget from which every
+ * request's workspace is carved; requests are admitted only while their
+ * workspace fits.  slots (1 .. 16): groups in flight at once, each on its own
+ * stream (default priority); max_batch (1 .. 4096): requests matched by one
+ * launch at most.  The plain policy uses one slot and groups of one.  The
+ * server allocates a few small buffers of its own (per-slot counts, page-
+ * locked staging), freed by ddm_server_destroy().
+ */
+typedef struct ddm_server ddm_server;
+int ddm_server_create(void *arena, size_t arena_bytes, int policy, int slots, int max_batch,
+                      ddm_server **out);
+
+/* Registers a simulation (arguments as ddm_sim_step(); every simulation of a
+ * server has the same d).  DDM_E_WORKSPACE if one request of it alone would
+ * not fit the arena. */
+int ddm_server_add_sim(ddm_server *s, float *upd_lo, float *upd_hi, int64_t n, float *sub_lo,
+                       float *sub_hi, int64_t m, int d, float side, float sigma, uint64_t seed,
+                       int32_t *sim_id);
+
+/*
+ * Serves count requests open-loop: request i (for simulation sim[i]) arrives
+ * arrival_s[i] seconds after the start (host monotonic clock) and is released
+ * to the scheduler then; each simulation's requests are served in arrival
+ * order, so its k-th request always matches its state after k steps (steps
+ * continue across calls).  Returns when every request has completed.  Out
+ * (host, [count]): counts[i], the pairs of request i; steps[i], the step it
+ * matched; latency_s[i], completion minus arrival.  stats may be NULL.
+ * Errors: DDM_E_INVAL for bad arguments; the first error of a request
+ * otherwise (its count is then 0).
+ */
+int ddm_server_run(ddm_server *s, const int32_t *sim, const double *arrival_s, int64_t count,
+                   uint64_t *counts, uint32_t *steps, double *latency_s, ddm_serve_stats *stats);
+int ddm_server_destroy(ddm_server *s);
 
 /* Human-readable text for a DDM_* return code (static storage). */
 const char *ddm_strerror(int code);

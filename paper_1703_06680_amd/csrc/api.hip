@@ -41,7 +41,10 @@ struct Layout {
   size_t total;
 };
 
-Layout make_layout(int64_t n, int64_t m, int d, int mode, int64_t cap) {
+// The pointers only enter the bucketed plan (null when only sizes matter).
+Layout make_layout(int64_t n, int64_t m, int d, int mode, int64_t cap,
+                   const float *ulo = nullptr, const float *uhi = nullptr,
+                   const float *slo = nullptr, const float *shi = nullptr) {
   Layout L{};
   size_t at = 0;
   auto take = [&](size_t bytes) {
@@ -86,7 +89,7 @@ Layout make_layout(int64_t n, int64_t m, int d, int mode, int64_t cap) {
   L.bucket_ok = bucket_path_supported(d, n, m);
   size_t region_bytes = g;
   if (L.bucket_ok) {
-    L.B = bucket_layout(n, m, d);
+    L.B = bucket_layout(ulo, uhi, n, slo, shi, m, d);
     if (L.B.bytes > region_bytes) region_bytes = L.B.bytes;
   }
   L.total = L.region + align256(region_bytes);
@@ -189,10 +192,6 @@ int finish_pairs(const Call &c, unsigned long long K, Emit emit) {
 // ------------------------------------------------------- bucketed path
 int run_bucketed(const Call &c) {
   BucketArgs a{};
-  a.ulo = c.ulo;
-  a.uhi = c.uhi;
-  a.slo = c.slo;
-  a.shi = c.shi;
   a.d = c.d;
   a.ws = at<void>(c.ws, c.L.region);
   a.L = &c.L.B;
@@ -339,7 +338,7 @@ extern "C" int ddm_match(const float *upd_lo, const float *upd_hi, int64_t n, co
   if (mode == DDM_PER_UPDATE && n > 0 && !per_update) return DDM_E_INVAL;
   if (mode == DDM_PAIRS && pair_capacity > 0 && !pairs) return DDM_E_INVAL;
   Call c{};
-  c.L = make_layout(n, m, d, mode, pair_capacity);
+  c.L = make_layout(n, m, d, mode, pair_capacity, upd_lo, upd_hi, sub_lo, sub_hi);
   if (!workspace || ws_bytes < c.L.total) return DDM_E_WORKSPACE;
   if (reinterpret_cast<uintptr_t>(workspace) & 255) return DDM_E_INVAL;
   *count_host = 0;

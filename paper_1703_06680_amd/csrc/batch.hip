@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "../../include/ddm.h"
+#include "batch.h"
 #include "bucket_path.h"
 #include "common.h"
 #include "primitives.h"
@@ -151,15 +152,8 @@ bool shape_ok(const int64_t *uoff, const int64_t *soff, int64_t B, int d, int mo
   return uoff[B] + soff[B] < (int64_t(1) << 31);
 }
 
-// Byte offsets of the batch workspace.
-struct BatchLayout {
-  size_t hdr, offs, gate, cnt, off, cur, pu, ps, pu2, ps2, scan_tmp, sort_tmp, region;
-  BucketLayout bk;
-  size_t total;
-};
-
-BatchLayout batch_layout(const int64_t *uoff, const int64_t *soff, int64_t B, int d, int mode,
-                         int64_t cap, const BucketTuning &t) {
+BatchLayout batch_layout(const InstSpec *spec, int64_t B, int d, int mode, int64_t cap,
+                         const BucketTuning &t) {
   BatchLayout L{};
   size_t at_ = 0;
   auto take = [&](size_t bytes) {
@@ -167,7 +161,8 @@ BatchLayout batch_layout(const int64_t *uoff, const int64_t *soff, int64_t B, in
     at_ += align256(bytes);
     return o;
   };
-  const size_t n_total = (size_t)uoff[B];
+  size_t n_total = 0;
+  for (int64_t b = 0; b < B; ++b) n_total += (size_t)spec[b].n;
   const size_t c = (size_t)cap;
   L.hdr = take(sizeof(Header));
   L.offs = take(2 * ((size_t)B + 1) * sizeof(uint32_t));
@@ -184,53 +179,75 @@ BatchLayout batch_layout(const int64_t *uoff, const int64_t *soff, int64_t B, in
     L.sort_tmp = take(radix_sort_temp_bytes((uint32_t)(c ? c : 1)));
   }
   L.region = at_;
-  L.bk = bucket_layout(uoff, soff, B, d, t);
+  L.bk = bucket_layout(spec, B, d, t);
   L.total = L.region + align256(L.bk.bytes);
   return L;
 }
 
 // What the per-instance fallback needs: the largest single-call workspace.
-size_t fallback_bytes(const int64_t *uoff, const int64_t *soff, int64_t B, int d, int mode,
-                      int64_t cap) {
+size_t fallback_bytes(const InstSpec *spec, int64_t B, int d, int mode, int64_t cap) {
   size_t most = 0;
   for (int64_t b = 0; b < B; ++b)
-    most = std::max(most, ddm_workspace_bytes(uoff[b + 1] - uoff[b], soff[b + 1] - soff[b], d,
-                                              mode, cap));
+    most = std::max(most, ddm_workspace_bytes(spec[b].n, spec[b].m, d, mode, cap));
   return most;
 }
 
-struct Batch {
-  const float *ulo, *uhi, *slo, *shi;
-  std::vector<int64_t> uoff, soff;
-  int64_t B;
-  int d, mode;
-  void *ws;
-  size_t ws_bytes;
-  uint64_t *counts;
-  int32_t *per_update, *pairs;
-  int64_t *pair_off;
-  int64_t cap;
-  bool bucketed;  // the batch fits the bucketed plan
-  BatchLayout L;
-};
+// Instances of a CSR batch (pointers into the shared arrays; null pointers
+// when only the sizes matter).
+std::vector<InstSpec> csr_specs(const float *ulo, const float *uhi, const int64_t *uoff,
+                                const float *slo, const float *shi, const int64_t *soff,
+                                int64_t B, int d) {
+  std::vector<InstSpec> v((size_t)B);
+  for (int64_t b = 0; b < B; ++b) {
+    InstSpec &x = v[(size_t)b];
+    x.n = uoff[b + 1] - uoff[b];
+    x.m = soff[b + 1] - soff[b];
+    x.ulo = ulo ? ulo + uoff[b] * d : nullptr;
+    x.uhi = uhi ? uhi + uoff[b] * d : nullptr;
+    x.slo = slo ? slo + soff[b] * d : nullptr;
+    x.shi = shi ? shi + soff[b] * d : nullptr;
+  }
+  return v;
+}
 
-int make_batch(Batch &c, const float *ulo, const float *uhi, const int64_t *uoff,
-               const float *slo, const float *shi, const int64_t *soff, int64_t B, int d,
-               int mode, void *ws, size_t ws_bytes, const ddm_tuning *tuning, uint64_t *counts,
-               int32_t *per_update, int32_t *pairs, int64_t *pair_off, int64_t cap) {
-  if (!shape_ok(uoff, soff, B, d, mode, cap) || !tuning_valid(tuning)) return DDM_E_INVAL;
-  const int64_t n_total = uoff[B], m_total = soff[B];
-  if ((n_total > 0 && (!ulo || !uhi)) || (m_total > 0 && (!slo || !shi)) || !counts)
-    return DDM_E_INVAL;
+bool specs_ok(const InstSpec *spec, int64_t B, int d, int mode, int64_t cap) {
+  if (!spec || B < 1 || B >= (int64_t(1) << 24)) return false;
+  if (d < 1 || d > DDM_MAX_DIMS) return false;
+  if (mode != DDM_COUNT && mode != DDM_PER_UPDATE && mode != DDM_PAIRS) return false;
+  if (cap < 0 || cap >= (int64_t(1) << 31)) return false;
+  int64_t N = 0;
+  for (int64_t b = 0; b < B; ++b) {
+    if (spec[b].n < 0 || spec[b].m < 0) return false;
+    N += spec[b].n + spec[b].m;
+    if (N >= (int64_t(1) << 31)) return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+// Validates a batch given as instances and fills c (no device work).
+int make_batch(Batch &c, std::vector<InstSpec> spec, int d, int mode, void *ws, size_t ws_bytes,
+               const ddm_tuning *tuning, uint64_t *counts, int32_t *per_update, int32_t *pairs,
+               int64_t *pair_off, int64_t cap) {
+  const int64_t B = (int64_t)spec.size();
+  if (!specs_ok(spec.data(), B, d, mode, cap) || !tuning_valid(tuning)) return DDM_E_INVAL;
+  int64_t n_total = 0;
+  for (const InstSpec &x : spec) {
+    if ((x.n > 0 && (!x.ulo || !x.uhi)) || (x.m > 0 && (!x.slo || !x.shi))) return DDM_E_INVAL;
+    n_total += x.n;
+  }
+  if (!counts) return DDM_E_INVAL;
   if (mode == DDM_PER_UPDATE && n_total > 0 && !per_update) return DDM_E_INVAL;
   if (mode == DDM_PAIRS && (!pair_off || (cap > 0 && !pairs))) return DDM_E_INVAL;
   if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255)) return ws ? DDM_E_INVAL : DDM_E_WORKSPACE;
-  c.ulo = ulo;
-  c.uhi = uhi;
-  c.slo = slo;
-  c.shi = shi;
-  c.uoff.assign(uoff, uoff + B + 1);
-  c.soff.assign(soff, soff + B + 1);
+  c.spec = std::move(spec);
+  c.uoff.assign((size_t)B + 1, 0);
+  c.soff.assign((size_t)B + 1, 0);
+  for (int64_t b = 0; b < B; ++b) {
+    c.uoff[(size_t)b + 1] = c.uoff[(size_t)b] + c.spec[(size_t)b].n;
+    c.soff[(size_t)b + 1] = c.soff[(size_t)b] + c.spec[(size_t)b].m;
+  }
   c.B = B;
   c.d = d;
   c.mode = mode;
@@ -242,21 +259,45 @@ int make_batch(Batch &c, const float *ulo, const float *uhi, const int64_t *uoff
   c.pair_off = pair_off;
   c.cap = cap;
   const BucketTuning t = to_tuning(tuning);
-  c.bucketed = bucket_path_supported(d, uoff, soff, B, t);
+  c.bucketed = bucket_path_supported(d, c.spec.data(), B, t);
   if (c.bucketed) {
-    c.L = batch_layout(uoff, soff, B, d, mode, cap, t);
+    c.L = batch_layout(c.spec.data(), B, d, mode, cap, t);
     if (ws_bytes < c.L.total) return DDM_E_WORKSPACE;
   }
-  if (ws_bytes < fallback_bytes(uoff, soff, B, d, mode, cap)) return DDM_E_WORKSPACE;
+  if (ws_bytes < fallback_bytes(c.spec.data(), B, d, mode, cap)) return DDM_E_WORKSPACE;
   return DDM_OK;
 }
 
+int make_batch_csr(Batch &c, const float *ulo, const float *uhi, const int64_t *uoff,
+                   const float *slo, const float *shi, const int64_t *soff, int64_t B, int d,
+                   int mode, void *ws, size_t ws_bytes, const ddm_tuning *tuning, uint64_t *counts,
+                   int32_t *per_update, int32_t *pairs, int64_t *pair_off, int64_t cap) {
+  if (!shape_ok(uoff, soff, B, d, mode, cap)) return DDM_E_INVAL;
+  return make_batch(c, csr_specs(ulo, uhi, uoff, slo, shi, soff, B, d), d, mode, ws, ws_bytes,
+                    tuning, counts, per_update, pairs, pair_off, cap);
+}
+
+size_t workspace_for(const std::vector<InstSpec> &spec, int d, int mode, int64_t pair_capacity,
+                          const ddm_tuning *tuning) {
+  const int64_t B = (int64_t)spec.size();
+  size_t most = fallback_bytes(spec.data(), B, d, mode, pair_capacity);
+  std::vector<BucketTuning> ts;
+  if (tuning) {
+    ts.push_back(to_tuning(tuning));
+  } else {
+    ts = candidates();
+    ts.push_back(BucketTuning{});
+  }
+  for (const BucketTuning &t : ts)
+    if (bucket_path_supported(d, spec.data(), B, t))
+      most = std::max(most, batch_layout(spec.data(), B, d, mode, pair_capacity, t).total);
+  return std::max<size_t>(most, 256);
+}
+
+namespace {
+
 BucketArgs bucket_args(const Batch &c) {
   BucketArgs a{};
-  a.ulo = c.ulo;
-  a.uhi = c.uhi;
-  a.slo = c.slo;
-  a.shi = c.shi;
   a.d = c.d;
   a.ws = at<void>(c.ws, c.L.region);
   a.L = &c.L.bk;
@@ -265,17 +306,28 @@ BucketArgs bucket_args(const Batch &c) {
   return a;
 }
 
-// Host-to-device copies of the plan and of the 32-bit instance offsets.
-// ``staging`` must stay alive until the stream has passed the copies.
-int upload(const Batch &c, hipStream_t s, std::vector<uint32_t> &staging) {
-  staging.resize(2 * ((size_t)c.B + 1));
-  for (int64_t b = 0; b <= c.B; ++b) {
-    staging[(size_t)b] = (uint32_t)c.uoff[(size_t)b];
-    staging[(size_t)c.B + 1 + (size_t)b] = (uint32_t)c.soff[(size_t)b];
+// Host-to-device copies of the 32-bit instance offsets and of the plan.
+// With ``pinned`` (page-locked, batch_staging_bytes() bytes) the copies do
+// not block the host; otherwise ``staging`` holds the offsets and must stay
+// alive until the stream has passed the copies.
+int upload(const Batch &c, hipStream_t s, std::vector<uint32_t> &staging, void *pinned) {
+  const size_t words = 2 * ((size_t)c.B + 1);
+  uint32_t *offs;
+  if (pinned) {
+    offs = static_cast<uint32_t *>(pinned);
+  } else {
+    staging.resize(words);
+    offs = staging.data();
   }
-  DDM_HIP(hipMemcpyAsync(at<void>(c.ws, c.L.offs), staging.data(),
-                         staging.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-  DDM_HIP(bucket_upload_plan(bucket_args(c), s));
+  for (int64_t b = 0; b <= c.B; ++b) {
+    offs[(size_t)b] = (uint32_t)c.uoff[(size_t)b];
+    offs[(size_t)c.B + 1 + (size_t)b] = (uint32_t)c.soff[(size_t)b];
+  }
+  DDM_HIP(hipMemcpyAsync(at<void>(c.ws, c.L.offs), offs, words * sizeof(uint32_t),
+                         hipMemcpyHostToDevice, s));
+  void *plan_stage = pinned ? static_cast<char *>(pinned) + align256(words * sizeof(uint32_t))
+                            : nullptr;
+  DDM_HIP(bucket_upload_plan(bucket_args(c), s, plan_stage));
   return DDM_OK;
 }
 
@@ -343,14 +395,12 @@ int run_each(const Batch &c, hipStream_t s, uint64_t *total_host) {
   int64_t used = 0;
   uint64_t total = 0;
   for (int64_t b = 0; b < B; ++b) {
-    const int64_t u0 = c.uoff[(size_t)b], n = c.uoff[(size_t)b + 1] - u0;
-    const int64_t s0 = c.soff[(size_t)b], m = c.soff[(size_t)b + 1] - s0;
+    const InstSpec &x = c.spec[(size_t)b];
+    const int64_t u0 = c.uoff[(size_t)b], n = x.n, m = x.m;
     const int64_t room = full ? 0 : c.cap - used;
     uint64_t K = 0;
-    const int rc = ddm_match(c.ulo ? c.ulo + u0 * c.d : nullptr, c.uhi ? c.uhi + u0 * c.d : nullptr,
-                             n, c.slo ? c.slo + s0 * c.d : nullptr,
-                             c.shi ? c.shi + s0 * c.d : nullptr, m, c.d, c.mode, c.ws,
-                             c.ws_bytes, s, &K,
+    const int rc = ddm_match(x.ulo, x.uhi, n, x.slo, x.shi, m, c.d, c.mode, c.ws, c.ws_bytes, s,
+                             &K,
                              c.per_update && n > 0 ? c.per_update + u0 : nullptr,
                              c.mode == DDM_PAIRS && room > 0 ? c.pairs + 2 * used : nullptr,
                              room);
@@ -385,7 +435,7 @@ int run_each(const Batch &c, hipStream_t s, uint64_t *total_host) {
 
 // Reads the outcome of an enqueued batch (stream synchronised first) and
 // falls back to run_each() if a bucket overflowed.
-int finish(const Batch &c, hipStream_t s, uint64_t *total_host) {
+int finish(const Batch &c, hipStream_t s, uint64_t *total_host, bool *fell_back) {
   Header h{};
   uint32_t gate[4] = {0, 0, 0, 0};
   DDM_HIP(hipMemcpyAsync(&h, at<Header>(c.ws, c.L.hdr), sizeof(Header), hipMemcpyDeviceToHost, s));
@@ -394,13 +444,38 @@ int finish(const Batch &c, hipStream_t s, uint64_t *total_host) {
   DDM_HIP(hipStreamSynchronize(s));
   prof::flush();
   if (h.err) return DDM_E_INVAL;
-  if (h.pad[0]) return run_each(c, s, total_host);
+  if (h.pad[0]) {
+    if (fell_back) *fell_back = true;
+    return run_each(c, s, total_host);
+  }
   *total_host = h.total;
   if (c.mode == DDM_PAIRS && gate[1]) return DDM_E_CAPACITY;
   return DDM_OK;
 }
 
 }  // namespace
+
+size_t batch_staging_bytes(const Batch &c) {
+  return align256(2 * ((size_t)c.B + 1) * sizeof(uint32_t)) + plan_bytes(c.L.bk);
+}
+
+int batch_begin(const Batch &c, hipStream_t s, void *pinned) {
+  if (!c.bucketed) return DDM_E_UNSUPPORTED;
+  std::vector<uint32_t> staging;
+  int rc = upload(c, s, staging, pinned);
+  if (rc != DDM_OK) return rc;
+  rc = enqueue(c, s);
+  if (rc == DDM_OK && !pinned && hipStreamSynchronize(s) != hipSuccess) rc = DDM_E_DEVICE;
+  return rc;
+}
+
+int batch_finish(const Batch &c, hipStream_t s, uint64_t *total_host, bool *fell_back) {
+  *total_host = 0;
+  if (fell_back) *fell_back = !c.bucketed;
+  if (!c.bucketed) return run_each(c, s, total_host);
+  return finish(c, s, total_host, fell_back);
+}
+
 }  // namespace ddm
 
 using namespace ddm;
@@ -424,20 +499,21 @@ extern "C" size_t ddm_batch_workspace_bytes(const int64_t *upd_off, const int64_
                                             int64_t B, int d, int mode, int64_t pair_capacity,
                                             const ddm_tuning *tuning) {
   if (!shape_ok(upd_off, sub_off, B, d, mode, pair_capacity) || !tuning_valid(tuning)) return 0;
-  size_t most = fallback_bytes(upd_off, sub_off, B, d, mode, pair_capacity);
-  std::vector<BucketTuning> ts;
-  if (tuning) {
-    ts.push_back(to_tuning(tuning));
-  } else {
-    ts = candidates();
-    ts.push_back(BucketTuning{});
-  }
-  for (const BucketTuning &t : ts)
-    if (bucket_path_supported(d, upd_off, sub_off, B, t))
-      most = std::max(most,
-                      batch_layout(upd_off, sub_off, B, d, mode, pair_capacity, t).total);
-  return std::max<size_t>(most, 256);
+  const std::vector<InstSpec> spec =
+      csr_specs(nullptr, nullptr, upd_off, nullptr, nullptr, sub_off, B, d);
+  return workspace_for(spec, d, mode, pair_capacity, tuning);
 }
+
+extern "C" size_t ddm_multi_workspace_bytes(const ddm_instance *inst, int64_t B, int d, int mode,
+                                            int64_t pair_capacity, const ddm_tuning *tuning) {
+  if (!inst || B < 1 || !tuning_valid(tuning)) return 0;
+  std::vector<InstSpec> spec((size_t)B);
+  for (int64_t b = 0; b < B; ++b) spec[(size_t)b] = InstSpec{nullptr, nullptr, nullptr, nullptr,
+                                                             inst[b].n, inst[b].m};
+  if (!specs_ok(spec.data(), B, d, mode, pair_capacity)) return 0;
+  return workspace_for(spec, d, mode, pair_capacity, tuning);
+}
+
 
 extern "C" int ddm_match_batched(const float *upd_lo, const float *upd_hi, const int64_t *upd_off,
                                  const float *sub_lo, const float *sub_hi, const int64_t *sub_off,
@@ -447,18 +523,40 @@ extern "C" int ddm_match_batched(const float *upd_lo, const float *upd_hi, const
                                  int64_t *pair_off, int64_t pair_capacity) {
   if (!total_host) return DDM_E_INVAL;
   Batch c;
-  int rc = make_batch(c, upd_lo, upd_hi, upd_off, sub_lo, sub_hi, sub_off, B, d, mode, workspace,
-                      ws_bytes, tuning, counts, per_update, pairs, pair_off, pair_capacity);
+  int rc = make_batch_csr(c, upd_lo, upd_hi, upd_off, sub_lo, sub_hi, sub_off, B, d, mode,
+                          workspace, ws_bytes, tuning, counts, per_update, pairs, pair_off,
+                          pair_capacity);
   if (rc != DDM_OK) return rc;
   *total_host = 0;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (!c.bucketed) return run_each(c, s, total_host);
-  std::vector<uint32_t> staging;
-  rc = upload(c, s, staging);
+  if (c.bucketed) {
+    rc = batch_begin(c, s, nullptr);
+    if (rc != DDM_OK) return rc;
+  }
+  return batch_finish(c, s, total_host);
+}
+
+extern "C" int ddm_match_multi(const ddm_instance *inst, int64_t B, int d, int mode,
+                               void *workspace, size_t ws_bytes, void *stream,
+                               const ddm_tuning *tuning, uint64_t *counts, uint64_t *total_host,
+                               int32_t *per_update, int32_t *pairs, int64_t *pair_off,
+                               int64_t pair_capacity) {
+  if (!total_host || !inst || B < 1) return DDM_E_INVAL;
+  std::vector<InstSpec> spec((size_t)B);
+  for (int64_t b = 0; b < B; ++b)
+    spec[(size_t)b] = InstSpec{inst[b].upd_lo, inst[b].upd_hi, inst[b].sub_lo, inst[b].sub_hi,
+                               inst[b].n, inst[b].m};
+  Batch c;
+  int rc = make_batch(c, std::move(spec), d, mode, workspace, ws_bytes, tuning, counts,
+                      per_update, pairs, pair_off, pair_capacity);
   if (rc != DDM_OK) return rc;
-  rc = enqueue(c, s);
-  if (rc != DDM_OK) return rc;
-  return finish(c, s, total_host);
+  *total_host = 0;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (c.bucketed) {
+    rc = batch_begin(c, s, nullptr);
+    if (rc != DDM_OK) return rc;
+  }
+  return batch_finish(c, s, total_host);
 }
 
 extern "C" int ddm_batch_graph_create(const float *upd_lo, const float *upd_hi,
@@ -472,9 +570,9 @@ extern "C" int ddm_batch_graph_create(const float *upd_lo, const float *upd_hi,
   *out = nullptr;
   ddm_batch_graph *g = new (std::nothrow) ddm_batch_graph();
   if (!g) return DDM_E_DEVICE;
-  int rc = make_batch(g->c, upd_lo, upd_hi, upd_off, sub_lo, sub_hi, sub_off, B, d, mode,
-                      workspace, ws_bytes, tuning, counts, per_update, pairs, pair_off,
-                      pair_capacity);
+  int rc = make_batch_csr(g->c, upd_lo, upd_hi, upd_off, sub_lo, sub_hi, sub_off, B, d, mode,
+                          workspace, ws_bytes, tuning, counts, per_update, pairs, pair_off,
+                          pair_capacity);
   if (rc == DDM_OK && !g->c.bucketed) rc = DDM_E_UNSUPPORTED;
   if (rc != DDM_OK) {
     delete g;
@@ -486,7 +584,7 @@ extern "C" int ddm_batch_graph_create(const float *upd_lo, const float *upd_hi,
     return DDM_E_DEVICE;
   }
   std::vector<uint32_t> staging;
-  rc = upload(g->c, cs, staging);
+  rc = upload(g->c, cs, staging, nullptr);
   if (rc == DDM_OK && hipStreamSynchronize(cs) != hipSuccess) rc = DDM_E_DEVICE;
   if (rc == DDM_OK) {
     const bool was = prof::swap_enabled(false);  // no event records inside the graph
@@ -521,7 +619,7 @@ extern "C" int ddm_batch_graph_launch(ddm_batch_graph *g, void *stream) {
 extern "C" int ddm_batch_graph_result(ddm_batch_graph *g, void *stream, uint64_t *total_host) {
   if (!g || !g->exec || !total_host) return DDM_E_INVAL;
   *total_host = 0;
-  return finish(g->c, static_cast<hipStream_t>(stream), total_host);
+  return batch_finish(g->c, static_cast<hipStream_t>(stream), total_host);
 }
 
 extern "C" int ddm_batch_graph_destroy(ddm_batch_graph *g) {

@@ -37,15 +37,23 @@ constexpr uint32_t kBucketCap = 2048;
 // of the count and scatter passes).
 constexpr uint32_t kMaxBuckets = 16384;
 
+// One instance: its own row arrays (float32 [n][d] / [m][d]).
+struct InstSpec {
+  const float *ulo, *uhi, *slo, *shi;
+  int64_t n, m;
+};
+
 // Per-instance launch plan, in device memory for batches of more than one.
 struct InstPlan {
-  uint32_t u0, n, s0, m;     // rows of the instance in the concatenated arrays
+  const float *ulo, *uhi, *slo, *shi;  // the instance's rows
+  uint32_t u0, n, s0, m;     // first output row of its updates / subscriptions, counts
   uint32_t gu, g;            // groups of up to four rows: of updates, of both kinds
   uint32_t blk0, nblk, gpb;  // count/scatter blocks (first, number) and groups per block
   uint32_t b0, nb;           // buckets (first, number)
   uint32_t cell0;            // first cell of the instance's nblk x nb count matrix
   uint32_t smp0, nsmp;       // sample blocks
   uint32_t tile0, ntx;       // transpose tiles (first), tiles along the bucket axis
+  uint32_t vec, pad;         // rows may be read with 16-byte loads
 };
 
 struct BucketLayout {
@@ -64,17 +72,17 @@ struct BucketLayout {
   std::vector<InstPlan> inst;          // host copy of the per-instance plan
 };
 
-// upd_off / sub_off: host CSR offsets [B + 1] of the instances' rows.
-bool bucket_path_supported(int d, const int64_t *upd_off, const int64_t *sub_off, int64_t B,
-                           const BucketTuning &t);
-BucketLayout bucket_layout(const int64_t *upd_off, const int64_t *sub_off, int64_t B, int d,
-                           const BucketTuning &t);
+// Instances in order; output rows (per-update counts, pair rows) number the
+// updates and the subscriptions of all instances consecutively.  Only the
+// sizes are read by bucket_path_supported; the layout records the pointers.
+bool bucket_path_supported(int d, const InstSpec *inst, int64_t B, const BucketTuning &t);
+BucketLayout bucket_layout(const InstSpec *inst, int64_t B, int d, const BucketTuning &t);
 // Single instance of n updates and m subscriptions with the default tuning.
 bool bucket_path_supported(int d, int64_t n, int64_t m);
-BucketLayout bucket_layout(int64_t n, int64_t m, int d);
+BucketLayout bucket_layout(const float *ulo, const float *uhi, int64_t n, const float *slo,
+                           const float *shi, int64_t m, int d);
 
 struct BucketArgs {
-  const float *ulo, *uhi, *slo, *shi;  // concatenated rows of all instances
   int d;
   void *ws;  // base of the bucket workspace (BucketLayout offsets apply)
   const BucketLayout *L;
@@ -84,8 +92,12 @@ struct BucketArgs {
 
 // Copies the per-instance plan to the workspace and expands the block,
 // sample, tile and bucket to instance maps (batches of more than one; no-op
-// otherwise).  The plan stays valid until the workspace is reused.
-hipError_t bucket_upload_plan(const BucketArgs &a, hipStream_t s);
+// otherwise).  The plan stays valid until the workspace is reused.  If
+// ``pinned`` is given (page-locked host memory of plan_bytes(L) bytes), the
+// plan is staged there and the copy does not block the host; the caller
+// keeps it untouched until the stream has passed the copy.
+size_t plan_bytes(const BucketLayout &L);
+hipError_t bucket_upload_plan(const BucketArgs &a, hipStream_t s, void *pinned = nullptr);
 
 // Enqueue sampling, counting (with input validation), prefix sums and the
 // scatter of region records into buckets.

@@ -38,6 +38,8 @@
 // back to their instance by small tables (a batch of one needs none).
 #include "bucket_path.h"
 
+#include <string.h>
+
 #include <algorithm>
 
 #include "primitives.h"
@@ -147,9 +149,8 @@ struct Offsets {
 // ---------------------------------------------------------------- sample
 
 template <int D>
-__global__ __launch_bounds__(kSampleThreads) void bk_sample_kernel(
-    const float *__restrict__ ulo, const float *__restrict__ uhi, const float *__restrict__ slo,
-    const float *__restrict__ shi, View V, float *__restrict__ part) {
+__global__ __launch_bounds__(kSampleThreads) void bk_sample_kernel(View V,
+                                                                   float *__restrict__ part) {
   // per block: min/max of the swept lower coordinate, count, and for the
   // other axes min(lo) / max(hi), over the sampled valid non-empty boxes of
   // the block's instance
@@ -163,7 +164,7 @@ __global__ __launch_bounds__(kSampleThreads) void bk_sample_kernel(
   const uint32_t r =
       (uint32_t)(((unsigned long long)mix32(i * 0x9E3779B9u + 0x632BE5ABu) * N) >> 32);
   const bool upd = r < I.n;
-  const Box<D> b = load_row<D>(upd ? ulo : slo, upd ? uhi : shi, upd ? I.u0 + r : I.s0 + (r - I.n));
+  const Box<D> b = load_row<D>(upd ? I.ulo : I.slo, upd ? I.uhi : I.shi, upd ? r : r - I.n);
   bool empty;
   const uint32_t err = box_errors<D>(b, empty);
   bool ok = !err && !empty && fabsf(b.lo[0]) <= 3.0e38f;
@@ -279,29 +280,24 @@ __global__ __launch_bounds__(kSampleThreads) void bk_plan_kernel(const float *__
 // ------------------------------------------------------ row groups
 
 // Rows are read in groups of up to four consecutive rows of one kind of one
-// instance, with group boundaries at multiples of four in the concatenated
-// arrays, so that a full group of d-float rows is d aligned 16-byte loads.
-// An instance's groups 0 .. gu-1 cover its updates, the rest its
-// subscriptions.
+// instance, so that a full group of d-float rows is d 16-byte loads when the
+// instance's arrays are 16-byte aligned.  An instance's groups 0 .. gu-1
+// cover its updates, the rest its subscriptions.
 struct Group {
   const float *lo, *hi;
   uint32_t row0, rows, r0;  // first row, rows in the group (<= 4), region index of row0
 };
 
-__device__ __forceinline__ Group group_of(uint32_t g, const InstPlan &I, const float *ulo,
-                                          const float *uhi, const float *slo, const float *shi,
-                                          uint32_t n_total) {
+__device__ __forceinline__ Group group_of(uint32_t g, const InstPlan &I, uint32_t n_total) {
   Group q;
   const bool upd = g < I.gu;
-  const uint32_t first = upd ? I.u0 : I.s0, count = upd ? I.n : I.m;
+  const uint32_t count = upd ? I.n : I.m;
   if (!upd) g -= I.gu;
-  q.lo = upd ? ulo : slo;
-  q.hi = upd ? uhi : shi;
-  const uint32_t a = 4u * ((first >> 2) + g);
-  const uint32_t lo = max(first, a), hi = min(first + count, a + 4u);
-  q.row0 = lo;
-  q.rows = hi - lo;
-  q.r0 = upd ? lo : n_total + lo;
+  q.lo = upd ? I.ulo : I.slo;
+  q.hi = upd ? I.uhi : I.shi;
+  q.row0 = 4u * g;
+  q.rows = min(4u, count - q.row0);
+  q.r0 = upd ? I.u0 + q.row0 : n_total + I.s0 + q.row0;
   return q;
 }
 
@@ -346,10 +342,8 @@ __device__ __forceinline__ void load_group(const Group &q, bool vec, Box<D> (&bx
 
 template <int D>
 __global__ __launch_bounds__(kThreads) void bk_count_kernel(
-    const float *__restrict__ ulo, const float *__restrict__ uhi, const float *__restrict__ slo,
-    const float *__restrict__ shi, uint32_t n_total, int vec, View V,
-    const BucketParams *__restrict__ P, uint32_t *__restrict__ C, uint32_t *__restrict__ bs_size,
-    Header *__restrict__ hdr) {
+    uint32_t n_total, View V, const BucketParams *__restrict__ P, uint32_t *__restrict__ C,
+    uint32_t *__restrict__ bs_size, Header *__restrict__ hdr) {
   extern __shared__ uint32_t hist[];
   const uint32_t inst = V.of_blk(blockIdx.x);
   const InstPlan I = V.get(inst);
@@ -361,9 +355,9 @@ __global__ __launch_bounds__(kThreads) void bk_count_kernel(
   uint32_t err = 0;
 #pragma unroll 2
   for (uint32_t g = g0 + threadIdx.x; g < g1; g += kThreads) {
-    const Group q = group_of(g, I, ulo, uhi, slo, shi, n_total);
+    const Group q = group_of(g, I, n_total);
     Box<D> bx[4];
-    load_group<D>(q, vec != 0, bx);
+    load_group<D>(q, I.vec != 0, bx);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       if ((uint32_t)r >= q.rows) continue;
@@ -436,9 +430,8 @@ __device__ __forceinline__ void write_record(uint32_t *__restrict__ dst, const B
 
 template <int D>
 __global__ __launch_bounds__(kThreads) void bk_scatter_kernel(
-    const float *__restrict__ ulo, const float *__restrict__ uhi, const float *__restrict__ slo,
-    const float *__restrict__ shi, uint32_t n_total, int vec, View V,
-    const BucketParams *__restrict__ P, Offsets O, const uint32_t *__restrict__ SB,
+    uint32_t n_total, View V, const BucketParams *__restrict__ P, Offsets O,
+    const uint32_t *__restrict__ SB,
     uint32_t *__restrict__ bs_cur, uint32_t bs_cap, uint32_t *__restrict__ rec,
     uint32_t *__restrict__ bs_rec) {
   constexpr int RW = D == 1 ? 4 : 8;
@@ -453,9 +446,9 @@ __global__ __launch_bounds__(kThreads) void bk_scatter_kernel(
   const uint32_t g0 = lb * I.gpb, g1 = min(I.g, g0 + I.gpb);
 #pragma unroll 2
   for (uint32_t g = g0 + threadIdx.x; g < g1; g += kThreads) {
-    const Group q = group_of(g, I, ulo, uhi, slo, shi, n_total);
+    const Group q = group_of(g, I, n_total);
     Box<D> bx[4];
-    load_group<D>(q, vec != 0, bx);
+    load_group<D>(q, I.vec != 0, bx);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       if ((uint32_t)r >= q.rows) continue;
@@ -967,23 +960,20 @@ void prepare_impl(const BucketArgs &a, hipStream_t s) {
   Ptrs p = pointers(a);
   const size_t cells = L.cells;
   const size_t lds = (size_t)L.max_nb * sizeof(uint32_t);
-  const int vec = aligned16(a.ulo) && aligned16(a.uhi) && aligned16(a.slo) && aligned16(a.shi);
   prof::mark(s, "bucket.sample");
-  bk_sample_kernel<D><<<L.nsmp, kSampleThreads, 0, s>>>(a.ulo, a.uhi, a.slo, a.shi, p.V, p.part);
+  bk_sample_kernel<D><<<L.nsmp, kSampleThreads, 0, s>>>(p.V, p.part);
   bk_plan_kernel<<<L.B, kSampleThreads, 0, s>>>(p.part, p.V, p.P);
   prof::mark(s, "bucket.count");
   (void)fill_u32(p.T + cells, 0u, (size_t)L.nb + 1, s);
-  bk_count_kernel<D><<<L.nblk, kThreads, lds, s>>>(a.ulo, a.uhi, a.slo, a.shi, L.n_total, vec,
-                                                   p.V, p.P, p.C, p.T + cells, a.hdr);
+  bk_count_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.C, p.T + cells, a.hdr);
   prof::mark(s, "bucket.offsets");
   bk_transpose_kernel<<<L.ntile, 256, 0, s>>>(p.C, p.T, p.V, 0);
   (void)exclusive_scan_u32(p.T, p.S, cells + L.nb + 1, p.scan_tmp, s);
   bk_transpose_kernel<<<L.ntile, 256, 0, s>>>(p.S, p.SB, p.V, 1);
   prof::mark(s, "bucket.scatter");
   (void)fill_u32(p.bs_cur, 0u, L.nb, s);
-  bk_scatter_kernel<D><<<L.nblk, kThreads, lds, s>>>(a.ulo, a.uhi, a.slo, a.shi, L.n_total, vec,
-                                                     p.V, p.P, p.O, p.SB, p.bs_cur, L.bs_cap,
-                                                     p.rec, p.bs_rec);
+  bk_scatter_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.O, p.SB, p.bs_cur,
+                                                     L.bs_cap, p.rec, p.bs_rec);
 }
 
 template <int DM1, int MODE>
@@ -1003,15 +993,21 @@ void sweep_impl(const BucketArgs &a, int32_t *per_update, const unsigned long lo
 }
 
 // Host-side plan of one instance; returns false if it does not fit.
-bool plan_instance(int64_t u0, int64_t n, int64_t s0, int64_t m, const BucketTuning &t,
+bool plan_instance(const InstSpec &sp, int64_t u0, int64_t s0, const BucketTuning &t,
                    InstPlan &I) {
+  const int64_t n = sp.n, m = sp.m;
   I = InstPlan{};
+  I.ulo = sp.ulo;
+  I.uhi = sp.uhi;
+  I.slo = sp.slo;
+  I.shi = sp.shi;
+  I.vec = aligned16(sp.ulo) && aligned16(sp.uhi) && aligned16(sp.slo) && aligned16(sp.shi);
   I.u0 = (uint32_t)u0;
   I.n = (uint32_t)n;
   I.s0 = (uint32_t)s0;
   I.m = (uint32_t)m;
-  const uint64_t gu = n ? (uint64_t)((u0 + n + 3) / 4 - u0 / 4) : 0;
-  const uint64_t gs = m ? (uint64_t)((s0 + m + 3) / 4 - s0 / 4) : 0;
+  const uint64_t gu = (uint64_t)(n + 3) / 4;
+  const uint64_t gs = (uint64_t)(m + 3) / 4;
   I.gu = (uint32_t)gu;
   I.g = (uint32_t)(gu + gs);
   const uint64_t N = (uint64_t)(n + m);
@@ -1032,41 +1028,40 @@ bool plan_instance(int64_t u0, int64_t n, int64_t s0, int64_t m, const BucketTun
 
 }  // namespace
 
-bool bucket_path_supported(int d, const int64_t *upd_off, const int64_t *sub_off, int64_t B,
-                           const BucketTuning &t) {
+bool bucket_path_supported(int d, const InstSpec *inst, int64_t B, const BucketTuning &t) {
   if (d < 1 || d > 3 || B < 1) return false;
   if (t.target < 64 || t.target > kBucketCap * 3 / 4) return false;
   if (t.sweep_threads != 256 && t.sweep_threads != 512) return false;
   if (t.groups_per_thread < 1 || t.max_blocks < 1) return false;
-  uint64_t cells = 0, nb = 0;
+  uint64_t cells = 0, nb = 0, N = 0;
   for (int64_t i = 0; i < B; ++i) {
     InstPlan I;
-    if (!plan_instance(upd_off[i], upd_off[i + 1] - upd_off[i], sub_off[i],
-                       sub_off[i + 1] - sub_off[i], t, I))
-      return false;
+    if (!plan_instance(inst[i], 0, 0, t, I)) return false;
     cells += (uint64_t)I.nb * I.nblk;
     nb += I.nb;
+    N += (uint64_t)(inst[i].n + inst[i].m);
   }
-  return cells + nb + 1 < (1ull << 31) && upd_off[B] + sub_off[B] > 0;
+  return cells + nb + 1 < (1ull << 31) && N > 0 && N < (1ull << 31);
 }
 
 bool bucket_path_supported(int d, int64_t n, int64_t m) {
-  const int64_t uo[2] = {0, n}, so[2] = {0, m};
-  return bucket_path_supported(d, uo, so, 1, BucketTuning{});
+  const InstSpec sp{nullptr, nullptr, nullptr, nullptr, n, m};
+  return bucket_path_supported(d, &sp, 1, BucketTuning{});
 }
 
-BucketLayout bucket_layout(const int64_t *upd_off, const int64_t *sub_off, int64_t B, int d,
-                           const BucketTuning &t) {
+BucketLayout bucket_layout(const InstSpec *inst, int64_t B, int d, const BucketTuning &t) {
   BucketLayout L{};
   L.B = (uint32_t)B;
   L.tune = t;
   L.inst.resize((size_t)B);
   uint32_t blk = 0, smp = 0, tile = 0, bkt = 0;
   size_t cell = 0;
+  int64_t u0 = 0, s0 = 0;
   for (int64_t i = 0; i < B; ++i) {
     InstPlan &I = L.inst[(size_t)i];
-    plan_instance(upd_off[i], upd_off[i + 1] - upd_off[i], sub_off[i],
-                  sub_off[i + 1] - sub_off[i], t, I);
+    plan_instance(inst[i], u0, s0, t, I);
+    u0 += inst[i].n;
+    s0 += inst[i].m;
     I.blk0 = blk;
     I.smp0 = smp;
     I.tile0 = tile;
@@ -1084,8 +1079,8 @@ BucketLayout bucket_layout(const int64_t *upd_off, const int64_t *sub_off, int64
   L.nsmp = smp;
   L.ntile = tile;
   L.cells = cell;
-  L.n_total = (uint32_t)upd_off[B];
-  L.m_total = (uint32_t)sub_off[B];
+  L.n_total = (uint32_t)u0;
+  L.m_total = (uint32_t)s0;
   const uint64_t N = (uint64_t)L.n_total + L.m_total;
   L.bs_cap = (uint32_t)(N / 2 + 4096);
   L.rec_words = d == 1 ? 4 : 8;
@@ -1112,18 +1107,25 @@ BucketLayout bucket_layout(const int64_t *upd_off, const int64_t *sub_off, int64
   return L;
 }
 
-BucketLayout bucket_layout(int64_t n, int64_t m, int d) {
-  const int64_t uo[2] = {0, n}, so[2] = {0, m};
-  return bucket_layout(uo, so, 1, d, BucketTuning{});
+BucketLayout bucket_layout(const float *ulo, const float *uhi, int64_t n, const float *slo,
+                           const float *shi, int64_t m, int d) {
+  const InstSpec sp{ulo, uhi, slo, shi, n, m};
+  return bucket_layout(&sp, 1, d, BucketTuning{});
 }
 
-hipError_t bucket_upload_plan(const BucketArgs &a, hipStream_t s) {
+size_t plan_bytes(const BucketLayout &L) { return L.inst.size() * sizeof(InstPlan); }
+
+hipError_t bucket_upload_plan(const BucketArgs &a, hipStream_t s, void *pinned) {
   const BucketLayout &L = *a.L;
   if (L.B <= 1) return hipSuccess;
   Ptrs p = pointers(a);
   InstPlan *plan = reinterpret_cast<InstPlan *>(static_cast<char *>(a.ws) + L.plan);
-  hipError_t e = hipMemcpyAsync(plan, L.inst.data(), L.inst.size() * sizeof(InstPlan),
-                                hipMemcpyHostToDevice, s);
+  const void *src = L.inst.data();
+  if (pinned) {
+    memcpy(pinned, L.inst.data(), plan_bytes(L));
+    src = pinned;
+  }
+  hipError_t e = hipMemcpyAsync(plan, src, plan_bytes(L), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return e;
   const uint32_t most = std::max(std::max(L.nblk, L.nsmp), std::max(L.ntile, L.nb));
   const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>((most + 255) / 256, 1024));

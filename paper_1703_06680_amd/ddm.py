@@ -421,3 +421,119 @@ class BatchGraph:
             self.close()
         except Exception:
             pass
+
+
+# --------------------------------------------------------------- serving
+
+SERVE_POLICIES = {"batched": 0, "plain": 1}
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("wall_s", ctypes.c_double), ("launches", ctypes.c_int64),
+                ("mean_batch", ctypes.c_double), ("peak_arena_bytes", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: (int(getattr(self, f)) if f == "launches" else float(getattr(self, f)))
+                for f, _ in self._fields_}
+
+
+def _serve_prototypes(lib):
+    if getattr(lib, "_serve_ready", False):
+        return lib
+    i64, vp, f32 = ctypes.c_int64, ctypes.c_void_p, ctypes.c_float
+    lib.ddm_sim_step.argtypes = [vp, vp, i64, vp, vp, i64, ctypes.c_int, f32, f32,
+                                 ctypes.c_uint64, ctypes.c_uint32, vp]
+    lib.ddm_sim_step.restype = ctypes.c_int
+    lib.ddm_server_create.argtypes = [vp, ctypes.c_size_t, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, ctypes.POINTER(vp)]
+    lib.ddm_server_create.restype = ctypes.c_int
+    lib.ddm_server_add_sim.argtypes = [vp, vp, vp, i64, vp, vp, i64, ctypes.c_int, f32, f32,
+                                       ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]
+    lib.ddm_server_add_sim.restype = ctypes.c_int
+    lib.ddm_server_run.argtypes = [vp, vp, vp, i64, vp, vp, vp, ctypes.POINTER(ServeStats)]
+    lib.ddm_server_run.restype = ctypes.c_int
+    lib.ddm_server_destroy.argtypes = [vp]
+    lib.ddm_server_destroy.restype = ctypes.c_int
+    lib._serve_ready = True
+    return lib
+
+
+def sim_step(upd_lo, upd_hi, sub_lo, sub_hi, side: float, sigma: float, seed: int, step: int,
+             stream=None) -> None:
+    """One random-walk step of a simulation's regions, in place (``ddm_sim_step``)."""
+    lib = _serve_prototypes(library())
+    _check_boxes(upd_lo, upd_hi, "updates")
+    _check_boxes(sub_lo, sub_hi, "subscriptions")
+    if stream is None:
+        stream = torch.cuda.current_stream(upd_lo.device)
+    n, d = upd_lo.shape
+    m = sub_lo.shape[0]
+    rc = lib.ddm_sim_step(_ptr(upd_lo), _ptr(upd_hi), n, _ptr(sub_lo), _ptr(sub_hi), m, d,
+                          float(side), float(sigma), int(seed), int(step),
+                          ctypes.c_void_p(stream.cuda_stream))
+    if rc != DDM_OK:
+        raise DDMError(rc, "ddm_sim_step")
+
+
+class Server:
+    """Serving runtime (``ddm_server_*``): resident simulations, open-loop
+    request traces, continuous batching under an HBM budget (``arena``)."""
+
+    def __init__(self, arena_bytes: int, policy: str = "batched", slots: int = 4,
+                 max_batch: int = 32, device=None):
+        self.lib = _serve_prototypes(library())
+        self.dev = torch.device(device) if device is not None else torch.device("cuda", 0)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.dev)
+        self.sims = []
+        self.handle = ctypes.c_void_p(None)
+        with torch.cuda.device(self.dev):
+            rc = self.lib.ddm_server_create(ctypes.c_void_p(self.arena.data_ptr()),
+                                            self.arena.numel(), SERVE_POLICIES[policy], slots,
+                                            max_batch, ctypes.byref(self.handle))
+        if rc != DDM_OK:
+            raise DDMError(rc, "ddm_server_create")
+
+    def add_sim(self, upd_lo, upd_hi, sub_lo, sub_hi, side: float, sigma: float,
+                seed: int) -> int:
+        _check_boxes(upd_lo, upd_hi, "updates")
+        _check_boxes(sub_lo, sub_hi, "subscriptions")
+        sid = ctypes.c_int32(-1)
+        n, d = upd_lo.shape
+        rc = self.lib.ddm_server_add_sim(self.handle, _ptr(upd_lo), _ptr(upd_hi), n,
+                                         _ptr(sub_lo), _ptr(sub_hi), sub_lo.shape[0], d,
+                                         float(side), float(sigma), int(seed), ctypes.byref(sid))
+        if rc != DDM_OK:
+            raise DDMError(rc, "ddm_server_add_sim")
+        self.sims.append((upd_lo, upd_hi, sub_lo, sub_hi))  # keep the state alive
+        return int(sid.value)
+
+    def run(self, sim_ids, arrival_s):
+        """Serves the trace; returns (counts uint64 [R], steps uint32 [R],
+        latency_s float64 [R], stats dict)."""
+        import numpy as np
+        sims = np.ascontiguousarray(np.asarray(sim_ids, dtype=np.int32))
+        arr = np.ascontiguousarray(np.asarray(arrival_s, dtype=np.float64))
+        if sims.shape != arr.shape or sims.ndim != 1:
+            raise ValueError("sim_ids and arrival_s must be 1-D of one length")
+        R = sims.size
+        counts = np.zeros(max(R, 1), dtype=np.uint64)
+        steps = np.zeros(max(R, 1), dtype=np.uint32)
+        lat = np.zeros(max(R, 1), dtype=np.float64)
+        st = ServeStats()
+        with torch.cuda.device(self.dev):
+            rc = self.lib.ddm_server_run(self.handle, _aptr(sims), _aptr(arr), R, _aptr(counts),
+                                         _aptr(steps), _aptr(lat), ctypes.byref(st))
+        if rc != DDM_OK:
+            raise DDMError(rc, "ddm_server_run")
+        return counts[:R], steps[:R], lat[:R], st.as_dict()
+
+    def close(self) -> None:
+        if self.handle and self.handle.value:
+            self.lib.ddm_server_destroy(self.handle)
+            self.handle = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

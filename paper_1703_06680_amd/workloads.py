@@ -192,3 +192,32 @@ def concat_instances(insts):
 
     return (cat([t.upd_lo for t in insts]), cat([t.upd_hi for t in insts]), uoff,
             cat([t.sub_lo for t in insts]), cat([t.sub_hi for t in insts]), soff)
+
+
+def serving_sims(count: int = 32, d: int = 2, seed: int = 0, lo: int = 10_000,
+                 hi: int = 2_000_000, alpha: float = 1.0):
+    """Initial states of the serving workload: simulation j has n = m regions
+    (n log-uniform on [lo, hi]) placed uniformly, side alpha * L / (2n);
+    returns a list of (Instance, side, sigma = 0.1 * side, seed of its walk)."""
+    rng = generator(seed, SIM_STREAM_BASE - 1)
+    sizes = np.rint(np.exp(rng.uniform(math.log(lo), math.log(hi), size=count))).astype(np.int64)
+    out = []
+    for j in range(count):
+        n = int(sizes[j])
+        side = side_length(alpha, 2 * n)
+        r = generator(seed, SIM_STREAM_BASE + j)
+        ulo, uhi = uniform_regions(r, n, d, side)
+        slo, shi = uniform_regions(r, n, d, side)
+        walk_seed = (int(seed) << 32) | (SIM_STREAM_BASE + j)
+        out.append((Instance(ulo, uhi, slo, shi, alpha, f"sim{j}"), float(side),
+                    float(np.float32(0.1) * side), walk_seed))
+    return out
+
+
+def poisson_arrivals(count: int, qps: float, seed: int = 0, sims: int = 32):
+    """Open-loop trace: ``count`` requests with exponential inter-arrival
+    times of mean 1/qps, each for a uniformly chosen simulation.  Returns
+    (sim ids int32 [count], arrival times float64 [count] in seconds)."""
+    rng = generator(seed, SIM_STREAM_BASE - 2)
+    gaps = rng.exponential(1.0 / qps, size=count)
+    return rng.integers(0, sims, size=count).astype(np.int32), np.cumsum(gaps)
