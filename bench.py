@@ -68,6 +68,138 @@ def algorithmic_bytes(phase: str, n: int, m: int, d: int, nonempty: int, mode: s
     return None
 
 
+def bench_batched(args, ddm, W, torch, np):
+    """512 independent d=2 instances (n = m log-uniform on [1e3, 2e5], alpha
+    uniform in {0.01, 1, 10}), pairs mode: 512 plain ddm_match calls against
+    one batched call and against replays of the autotuned captured graph."""
+    dev = torch.device("cuda:0")
+    insts = W.batched_instances(args.batch_count, d=2, seed=0)
+    ulo, uhi, uoff, slo, shi, soff = W.concat_instances(insts)
+    g = [torch.from_numpy(a).to(dev) for a in (ulo, uhi, slo, shi)]
+    regions = int(uoff[-1] + soff[-1])
+    cap = 1 << 21
+    batch = ddm.Batch(g[0], g[1], uoff, g[2], g[3], soff, mode="pairs", pair_capacity=cap)
+    stream = torch.cuda.current_stream(dev)
+
+    # plain: one ddm_match per instance, each synchronising
+    big = max(range(len(insts)), key=lambda b: insts[b].n + insts[b].m)
+    ws = torch.empty(ddm.workspace_bytes(insts[big].n, insts[big].m, 2, "pairs", cap),
+                     dtype=torch.uint8, device=dev)
+    pbuf = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+
+    def plain_pass(keep=False):
+        ks, kept = [], []
+        for b in range(len(insts)):
+            u0, u1, s0, s1 = int(uoff[b]), int(uoff[b + 1]), int(soff[b]), int(soff[b + 1])
+            k = ddm.match_into(g[0][u0:u1], g[1][u0:u1], g[2][s0:s1], g[3][s0:s1], mode="pairs",
+                               workspace=ws, pairs=pbuf, stream=stream)
+            ks.append(k)
+            if keep:
+                kept.append(pbuf[:k].clone())
+        return ks, kept
+
+    plain_pass()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.batch_reps):
+        ks_plain, _ = plain_pass()
+    plain_ms = 1e3 * (time.perf_counter() - t) / args.batch_reps
+    ks_plain, kept = plain_pass(keep=True)
+    pairs_plain = torch.cat(kept) if kept else torch.empty((0, 2), dtype=torch.int32, device=dev)
+
+    # one batched call (plan upload included), default tuning
+    batch.run()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.batch_reps):
+        total = batch.run()
+    call_ms = 1e3 * (time.perf_counter() - t) / args.batch_reps
+
+    # autotuned graph
+    t = time.perf_counter()
+    best, best_ms = batch.autotune()
+    tune_s = time.perf_counter() - t
+    graph = batch.graph(best)
+    graph.launch()
+    total_g = graph.result()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.batch_reps):
+        graph.launch()
+    total_g = graph.result()
+    graph_ms = 1e3 * (time.perf_counter() - t) / args.batch_reps
+    counts = batch.counts.cpu().numpy().astype(np.int64)
+    exact = (total_g == total == sum(ks_plain) and counts.tolist() == ks_plain and
+             bool(torch.equal(batch.pairs[:total_g], pairs_plain)))
+    graph.close()
+    return {
+        "workload": f"{len(insts)} independent d=2 instances, n=m log-uniform on [1e3, 2e5] "
+                    f"(sum N = {regions}), alpha uniform in {{0.01, 1, 10}}, pairs mode",
+        "instances": len(insts), "regions": regions, "pairs": int(total_g),
+        "plain_ms": round(plain_ms, 3), "batched_call_ms": round(call_ms, 3),
+        "graph_ms": round(graph_ms, 3),
+        "graph_regions_per_s": round(regions / (graph_ms * 1e-3), 1),
+        "plain_regions_per_s": round(regions / (plain_ms * 1e-3), 1),
+        "speedup_graph_vs_plain": round(plain_ms / graph_ms, 2),
+        "tuning": best.as_dict(), "autotune_replay_ms": round(best_ms, 3),
+        "autotune_s": round(tune_s, 2), "exact": exact,
+    }
+
+
+def bench_served(args, ddm, W, torch, np):
+    """32 resident d=2 simulations (n = m log-uniform on [1e4, 2e6], alpha = 1,
+    random-walk sigma = 0.1 * side); open-loop Poisson traces at fractions of
+    the plain matcher's saturation rate, served by the plain per-request
+    policy and by continuous batching."""
+    dev = torch.device("cuda:0")
+    sims = W.serving_sims(32, d=2, seed=0)
+    init = [[torch.from_numpy(a).to(dev) for a in (t.upd_lo, t.upd_hi, t.sub_lo, t.sub_hi)]
+            for t, _, _, _ in sims]
+    sizes = np.array([t.n + t.m for t, _, _, _ in sims], dtype=np.int64)
+    budget = int(args.serve_budget_gib * (1 << 30))
+
+    def serve(policy, ids, arr):
+        sv = ddm.Server(budget, policy=policy, slots=args.serve_slots,
+                        max_batch=args.serve_max_batch)
+        for (t, side, sigma, seed), g0 in zip(sims, init):
+            sv.add_sim(*[x.clone() for x in g0], side, sigma, seed)
+        out = sv.run(ids, arr)
+        sv.close()
+        return out
+
+    # saturation rate of the plain matcher: everything arrives at once
+    R = args.serve_requests
+    ids_sat, _ = W.poisson_arrivals(R, 1.0, seed=5, sims=32)
+    serve("plain", ids_sat[:64], np.zeros(64))  # warm-up
+    _, _, _, st = serve("plain", ids_sat, np.zeros(R))
+    sat_qps = R / st["wall_s"]
+    levels = {}
+    for frac in (0.5, 0.8, 1.0, 1.2):
+        ids, arr = W.poisson_arrivals(R, frac * sat_qps, seed=int(frac * 10), sims=32)
+        row = {"qps": round(frac * sat_qps, 1)}
+        results = {}
+        for policy in ("plain", "batched"):
+            counts, steps, lat, stt = serve(policy, ids, arr)
+            results[policy] = (counts, steps)
+            row[policy] = {
+                "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
+                "regions_per_s": round(float(sizes[ids].sum()) / stt["wall_s"], 1),
+                "mean_batch": round(stt["mean_batch"], 2),
+                "peak_arena_gib": round(stt["peak_arena_bytes"] / (1 << 30), 3),
+            }
+        row["exact"] = bool(np.array_equal(results["plain"][0], results["batched"][0]) and
+                            np.array_equal(results["plain"][1], results["batched"][1]))
+        levels[f"{frac:g}x"] = row
+    return {
+        "workload": "32 resident d=2 simulations, n=m log-uniform on [1e4, 2e6] "
+                    f"(sum N = {int(sizes.sum())}), alpha=1, random walk sigma=0.1*side, "
+                    f"{R} Poisson requests per level, count mode",
+        "plain_saturation_qps": round(sat_qps, 1), "budget_gib": args.serve_budget_gib,
+        "slots": args.serve_slots, "max_batch": args.serve_max_batch, "levels": levels,
+    }
+
+
 def source_digest(paths):
     h = hashlib.sha256()
     for p in paths:
@@ -108,6 +240,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the per-phase event timing (roofline becomes null)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched measurement")
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--no-served", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-budget-gib", type=float, default=4.0)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-max-batch", type=int, default=8)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -218,6 +358,9 @@ def main():
                "sample": f"the full workload (n = m = {n}, d = {d}, alpha = {args.alpha:g}), one "
                          f"serial run of the C oracle ({dt:.2f} s), checked equal to the GPU result"}
 
+    batched = None if args.no_batched else bench_batched(args, ddm, W, torch, np)
+    served = None if args.no_served else bench_served(args, ddm, W, torch, np)
+
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -243,6 +386,10 @@ def main():
         "cpu_baseline": cpu,
         "phases_ms_per_step": {p: round(v["ms"] / args.steps, 4) for p, v in sorted(phases.items())},
         "per_alpha": per_alpha,
+        "served_p50_ms": served["levels"]["1x"]["batched"]["p50_ms"] if served else None,
+        "served_p99_ms": served["levels"]["1x"]["batched"]["p99_ms"] if served else None,
+        "batched": batched,
+        "served": served,
         "input_generation_s": round(gen_s, 2),
     }
     print(json.dumps(out), flush=True)
