@@ -33,12 +33,12 @@ METRIC = "matched regions/sec + HBM GB/s fraction at N=1e7; p50/p99 latency serv
 def algorithmic_bytes(phase: str, n: int, m: int, d: int, nonempty: int, mode: str):
     """Bytes a kernel phase must move once per launch (inputs read once,
     outputs written once), independent of caching or re-reads.  A region
-    record carries 2d + 1 words (lower and upper key on the swept axis, the
-    region index, lo/hi on the d - 1 other axes).  Per region:
+    record is 16 bytes (lower and upper key on the swept axis, the region
+    index, quantised bounds of the other axes).  Per region:
 
       bucket.count    8d read (lo and hi rows);
-      bucket.scatter  8d read + 4(2d + 1) written (one record);
-      bucket.sweep    4(2d + 1) read (one record), + 4 per update written in
+      bucket.scatter  8d read + 16 written (one record);
+      bucket.sweep    16 read (one record), + 4 per update written in
                       per-update mode;
       keys            8d read + 8 written (lower/upper keys);
       sort.downsweep  8 read + 8 written per element (first pass: 4 + 8);
@@ -47,7 +47,7 @@ def algorithmic_bytes(phase: str, n: int, m: int, d: int, nonempty: int, mode: s
       sweep.count     12 + 8(d-1) read (+ 4 per update in per-update mode).
     """
     N = n + m
-    rec = 4 * (2 * d + 1)
+    rec = 16
     out = 4 * n if mode != "count" else 0
     if phase == "bucket.count":
         return N * 8 * d

@@ -405,27 +405,52 @@ __global__ __launch_bounds__(256) void bk_transpose_kernel(const uint32_t *__res
 
 // ---------------------------------------------------------- scatter pass
 
-// Record: word 0 = encoded lower key (swept axis), 1 = encoded upper key,
-// 2 = region index (updates first), 3 = 0, then lo/hi of each other axis.
+// Conservative quantisation of a coordinate of another axis onto 16 bits by
+// the monotone map t = clamp((x - qmin) * qscale, 0, 65535): lower bounds
+// round down, upper bounds round up, so two boxes that overlap on that axis
+// also overlap after quantisation.  Quantised bounds only serve the
+// sweep's pre-filter; survivors are tested on the exact coordinates.
+__device__ __forceinline__ uint32_t quant_lo(float x, float qmin, float qs) {
+  float t = (x - qmin) * qs;
+  t = fminf(fmaxf(t, 0.0f), 65535.0f);
+  return (uint32_t)t;
+}
+
+__device__ __forceinline__ uint32_t quant_hi(float x, float qmin, float qs) {
+  float t = (x - qmin) * qs;
+  t = fminf(fmaxf(t, 0.0f), 65535.0f);
+  return (uint32_t)ceilf(t);
+}
+
+// Record (16 bytes): word 0 = encoded lower key (swept axis), 1 = encoded
+// upper key, 2 = region index (updates first), 3 = quantised bounds of the
+// other axes: for d = 2 the 16-bit lower | upper << 16 of axis 1; for d = 3
+// 8-bit bounds (the 16-bit ones, lower rounded down and upper rounded up to a
+// multiple of 256) lo1 | hi1 << 8 | lo2 << 16 | hi2 << 24; 0 for d = 1.
+template <int D>
+__device__ __forceinline__ uint32_t qword_of(const Box<D> &b, const BucketParams &p) {
+  if (D == 2) {
+    return quant_lo(b.lo[1 % D], p.qmin[0], p.qscale[0]) |
+           (quant_hi(b.hi[1 % D], p.qmin[0], p.qscale[0]) << 16);
+  }
+  if (D == 3) {
+    uint32_t w = 0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const uint32_t l8 = quant_lo(b.lo[(1 + c) % D], p.qmin[c], p.qscale[c]) >> 8;
+      const uint32_t h8 = min(255u, (quant_hi(b.hi[(1 + c) % D], p.qmin[c], p.qscale[c]) + 255u) >> 8);
+      w |= (l8 | (h8 << 8)) << (16 * c);
+    }
+    return w;
+  }
+  return 0u;
+}
+
 template <int D>
 __device__ __forceinline__ void write_record(uint32_t *__restrict__ dst, const Box<D> &b,
-                                             uint32_t r) {
-  constexpr int RW = D == 1 ? 4 : 8;
-  uint32_t w[8];
-  w[0] = encode_coord(b.lo[0]);
-  w[1] = encode_coord(b.hi[0]);
-  w[2] = r;
-  w[3] = 0;
-#pragma unroll
-  for (int k = 4; k < 8; ++k) w[k] = 0;
-#pragma unroll
-  for (int k = 1; k < D; ++k) {
-    w[4 + 2 * (k - 1)] = __float_as_uint(b.lo[k]);
-    w[5 + 2 * (k - 1)] = __float_as_uint(b.hi[k]);
-  }
-  uint4 *d4 = reinterpret_cast<uint4 *>(dst);
-  d4[0] = make_uint4(w[0], w[1], w[2], w[3]);
-  if (RW == 8) d4[1] = make_uint4(w[4], w[5], w[6], w[7]);
+                                             uint32_t r, const BucketParams &p) {
+  *reinterpret_cast<uint4 *>(dst) =
+      make_uint4(encode_coord(b.lo[0]), encode_coord(b.hi[0]), r, qword_of<D>(b, p));
 }
 
 template <int D>
@@ -434,7 +459,7 @@ __global__ __launch_bounds__(kThreads) void bk_scatter_kernel(
     const uint32_t *__restrict__ SB,
     uint32_t *__restrict__ bs_cur, uint32_t bs_cap, uint32_t *__restrict__ rec,
     uint32_t *__restrict__ bs_rec) {
-  constexpr int RW = D == 1 ? 4 : 8;
+  constexpr int RW = 4;
   extern __shared__ uint32_t cur[];
   const uint32_t inst = V.of_blk(blockIdx.x);
   const InstPlan I = V.get(inst);
@@ -457,12 +482,12 @@ __global__ __launch_bounds__(kThreads) void bk_scatter_kernel(
       if (empty) continue;
       const uint32_t b = bucket_of(bx[r].lo[0], p.vmin, p.scale, nb);
       const uint32_t slot = atomicAdd(&cur[b], 1u);
-      write_record<D>(rec + (size_t)slot * RW, bx[r], q.r0 + r);
+      write_record<D>(rec + (size_t)slot * RW, bx[r], q.r0 + r, p);
       const uint32_t last = bucket_of(bx[r].hi[0], p.vmin, p.scale, nb);
       for (uint32_t j = b + 1; j <= last; ++j) {
         const uint32_t jg = I.b0 + j;
         const uint32_t pos = O.bs_begin(jg) + atomicAdd(&bs_cur[jg], 1u);
-        if (pos < bs_cap) write_record<D>(bs_rec + (size_t)pos * RW, bx[r], q.r0 + r);
+        if (pos < bs_cap) write_record<D>(bs_rec + (size_t)pos * RW, bx[r], q.r0 + r, p);
       }
     }
   }
@@ -515,22 +540,6 @@ __device__ __forceinline__ uint32_t fine_of(float x, float vmin, float fscale) {
   return (uint32_t)t;
 }
 
-// Conservative 16-bit quantisation of a coordinate of another axis under a
-// monotone map: lower bounds round down, upper bounds round up, so two boxes
-// that overlap on that axis also overlap after quantisation.  The quantised
-// test is only a pre-filter; survivors are tested on the exact floats.
-__device__ __forceinline__ uint32_t quant_lo(float x, float qmin, float qs) {
-  float t = (x - qmin) * qs;
-  t = fminf(fmaxf(t, 0.0f), 65535.0f);
-  return (uint32_t)t;
-}
-
-__device__ __forceinline__ uint32_t quant_hi(float x, float qmin, float qs) {
-  float t = (x - qmin) * qs;
-  t = fminf(fmaxf(t, 0.0f), 65535.0f);
-  return (uint32_t)ceilf(t);
-}
-
 // Two quantised intervals a = [alo, ahi] and b = [blo, bhi] pass the
 // pre-filter iff alo <= bhi and blo <= ahi.  Stored one as an "entry" word
 // alo | (65535 - ahi) << 16 and the other as a "walker" word
@@ -545,72 +554,91 @@ __device__ __forceinline__ uint32_t qdiff(uint32_t entry, uint32_t walker) {
                                           __builtin_bit_cast(u16x2, walker)));
 }
 
-// entry / walker words of the other axes of one record (words 4.. hold
-// lo1, hi1, lo2, hi2)
+// 16-bit bounds of other axis c from a record's word 3 (see qword_of): the
+// 8-bit bounds of d = 3 widen to lo * 256 and hi * 256 (65535 for 255), which
+// still contain the 16-bit ones.
 template <int DM1>
-__device__ __forceinline__ void qwords(const uint32_t *rw, const BucketParams &p, uint32_t *entry,
-                                       uint32_t *walker) {
-#pragma unroll
-  for (int c = 0; c < DM1; ++c) {
-    const uint32_t lq = quant_lo(__uint_as_float(rw[4 + 2 * c]), p.qmin[c], p.qscale[c]);
-    const uint32_t hq = quant_hi(__uint_as_float(rw[5 + 2 * c]), p.qmin[c], p.qscale[c]);
-    if (entry) entry[c] = lq | ((65535u - hq) << 16);
-    if (walker) walker[c] = hq | ((65535u - lq) << 16);
+__device__ __forceinline__ void qbounds(uint32_t w, int c, uint32_t &lo, uint32_t &hi) {
+  if (DM1 == 1) {
+    lo = w & 0xFFFFu;
+    hi = w >> 16;
+  } else {
+    const uint32_t l8 = (w >> (16 * c)) & 0xFFu, h8 = (w >> (16 * c + 8)) & 0xFFu;
+    lo = l8 << 8;
+    hi = h8 == 255u ? 65535u : h8 << 8;
   }
+}
+
+template <int DM1>
+__device__ __forceinline__ uint32_t entry_word(uint32_t w, int c) {
+  uint32_t lo, hi;
+  qbounds<DM1>(w, c, lo, hi);
+  return lo | ((65535u - hi) << 16);
+}
+
+template <int DM1>
+__device__ __forceinline__ uint32_t walker_word(uint32_t w, int c) {
+  uint32_t lo, hi;
+  qbounds<DM1>(w, c, lo, hi);
+  return hi | ((65535u - lo) << 16);
 }
 
 // Padding of the per-bucket LDS arrays: the unrolled interior loop reads up
 // to three entries past its range.
 constexpr int kPad = 4;
 
-// One walking region.  For d >= 2, q holds its walker words; for d = 1 the
-// LDS slot of the other axes holds region ids instead.
+// One walking region: keys, region index, pre-filter walker words.
 template <int DM1>
 struct Walker {
-  uint32_t klo, khi, after_key;
+  uint32_t klo, khi, after_key, rid;
   uint32_t q[DM1 > 0 ? DM1 : 1];
-  uint32_t rid;         // valid for d = 1 (and whenever have_y below)
-  const uint32_t *rec;  // exact record (global memory)
   bool upd;
 };
 
-struct SweepOut {
-  uint32_t n;
+struct SweepCtx {
+  InstPlan I;  // the bucket's instance: rows of its regions
+  uint32_t n;  // updates over the batch (region indices below are updates)
   int32_t *per_update;
   const unsigned long long *pair_off;
   uint32_t *cursor;
   uint32_t *out_u, *out_s;
 };
 
+// Exact other-axis coordinates of region rid, from the instance's rows.
+template <int DM1>
+__device__ __forceinline__ void other_axes(const SweepCtx &o, uint32_t rid, float (&lo)[2],
+                                           float (&hi)[2]) {
+  constexpr int D = DM1 + 1;
+  const bool upd = rid < o.n;
+  const size_t row = upd ? rid - o.I.u0 : rid - o.n - o.I.s0;
+  const float *L = (upd ? o.I.ulo : o.I.slo) + row * D;
+  const float *H = (upd ? o.I.uhi : o.I.shi) + row * D;
+#pragma unroll
+  for (int c = 0; c < DM1; ++c) {
+    lo[c] = L[1 + c];
+    hi[c] = H[1 + c];
+  }
+}
+
 // A pair of walker y and entry j that passed the key and pre-filter tests:
 // exact test on the other axes (d >= 2), then count or emit.
 template <int DM1, int MODE>
-__device__ __forceinline__ void visit(Walker<DM1> &y, bool &have_y, float (&ylo)[2],
+__device__ __forceinline__ void visit(const Walker<DM1> &y, bool &have_y, float (&ylo)[2],
                                       float (&yhi)[2], uint32_t j,
-                                      const uint32_t *__restrict__ GIDX,
-                                      const uint32_t *__restrict__ Q,
-                                      const uint32_t *__restrict__ rec, unsigned long long &hits,
-                                      uint32_t &own, const SweepOut &o) {
-  uint32_t rx;
+                                      const uint32_t *__restrict__ RID, unsigned long long &hits,
+                                      uint32_t &own, const SweepCtx &o) {
+  const uint32_t rx = RID[j];
   if (DM1 > 0) {
     if (!have_y) {
       have_y = true;
-      const uint4 a = *reinterpret_cast<const uint4 *>(y.rec);
-      const uint4 c = *reinterpret_cast<const uint4 *>(y.rec + 4);
-      y.rid = a.z;
-      ylo[0] = __uint_as_float(c.x);
-      yhi[0] = __uint_as_float(c.y);
-      ylo[1] = __uint_as_float(c.z);
-      yhi[1] = __uint_as_float(c.w);
+      other_axes<DM1>(o, y.rid, ylo, yhi);
     }
-    const uint32_t *xr = rec + (size_t)GIDX[j] * 8;
-    const uint4 c = *reinterpret_cast<const uint4 *>(xr + 4);
-    bool hit = ylo[0] < __uint_as_float(c.y) && __uint_as_float(c.x) < yhi[0];
-    if (DM1 > 1) hit = hit && ylo[1] < __uint_as_float(c.w) && __uint_as_float(c.z) < yhi[1];
+    float xlo[2], xhi[2];
+    other_axes<DM1>(o, rx, xlo, xhi);
+    bool hit = true;
+#pragma unroll
+    for (int c = 0; c < DM1; ++c) hit = hit && ylo[c] < xhi[c] && xlo[c] < yhi[c];
     if (!hit) return;
-    rx = MODE == 0 ? 0u : xr[2];
-  } else {
-    rx = Q[j];
   }
   ++hits;
   if (MODE == 1) {
@@ -646,13 +674,12 @@ __device__ __forceinline__ bool qpass(const uint32_t *__restrict__ Q, uint32_t j
 // runs the pre-filter.
 template <int DM1, int MODE>
 __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
-                                     const uint32_t *__restrict__ GIDX,
-                                     const uint32_t *__restrict__ Q, Walker<DM1> &y, uint32_t jA,
-                                     uint32_t jB, uint32_t jC, uint32_t jD,
-                                     const uint32_t *__restrict__ rec, unsigned long long &hits,
-                                     const SweepOut &o) {
+                                     const uint32_t *__restrict__ RID,
+                                     const uint32_t *__restrict__ Q, const Walker<DM1> &y,
+                                     uint32_t jA, uint32_t jB, uint32_t jC, uint32_t jD,
+                                     unsigned long long &hits, const SweepCtx &o) {
   uint32_t own = 0;
-  bool have_y = DM1 == 0;
+  bool have_y = false;
   float ylo[2] = {0.f, 0.f}, yhi[2] = {0.f, 0.f};
   // edge entries: the first bin, then the part of the last bin past it
   const uint32_t e1 = jB - jA;
@@ -662,7 +689,7 @@ __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
     const uint32_t j = t < e1 ? jA + t : jC2 + (t - e1);
     const uint32_t k = KLO[j];
     if (k >= y.after_key && k < y.khi && qpass<DM1>(Q, j, y))
-      visit<DM1, MODE>(y, have_y, ylo, yhi, j, GIDX, Q, rec, hits, own, o);
+      visit<DM1, MODE>(y, have_y, ylo, yhi, j, RID, hits, own, o);
   }
   // interior bins
   if (DM1 == 0 && MODE == 0) {
@@ -676,7 +703,7 @@ __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
       if (msk) {
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-          if (msk & (1u << u)) visit<DM1, MODE>(y, have_y, ylo, yhi, j + u, GIDX, Q, rec, hits, own, o);
+          if (msk & (1u << u)) visit<DM1, MODE>(y, have_y, ylo, yhi, j + u, RID, hits, own, o);
       }
     }
   }
@@ -686,12 +713,11 @@ __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
 template <int DM1, int MODE, int CAP, int THREADS>
 __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
     const uint32_t *__restrict__ rec, Offsets O, View V, const uint32_t *__restrict__ bs_rec,
-    uint32_t bs_cap, uint32_t n, const BucketParams *__restrict__ P, Header *__restrict__ hdr,
-    int32_t *__restrict__ per_update, const unsigned long long *__restrict__ pair_off,
-    uint32_t *__restrict__ cursor, uint32_t *__restrict__ out_u, uint32_t *__restrict__ out_s,
+    uint32_t bs_cap, uint32_t n, Header *__restrict__ hdr, int32_t *__restrict__ per_update,
+    const unsigned long long *__restrict__ pair_off, uint32_t *__restrict__ cursor,
+    uint32_t *__restrict__ out_u, uint32_t *__restrict__ out_s,
     unsigned long long *__restrict__ total, unsigned long long *__restrict__ inst_total,
     const uint32_t *__restrict__ gate) {
-  constexpr int RW = DM1 == 0 ? 4 : 8;
   constexpr int QW = DM1 > 0 ? DM1 : 1;
   constexpr int ITEMS = CAP / THREADS;
   constexpr int W = THREADS / kWave;
@@ -699,12 +725,11 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   constexpr int BPT = NBINS / THREADS;  // bins per thread in the scan
   static_assert(NBINS % THREADS == 0, "bins must split evenly over the threads");
   // the bucket in LDS, in fine-bin order (updates first): lower and upper
-  // key, global record index and the pre-filter words of the other axes
-  // (region ids for d = 1) of every region
+  // key, region index and the pre-filter entry words of the other axes
   __shared__ uint32_t KLO[CAP + kPad];
   __shared__ uint32_t KHI[CAP + kPad];
-  __shared__ uint32_t GIDX[DM1 > 0 ? CAP + kPad : 1];
-  __shared__ __align__(16) uint32_t Q[(CAP + kPad) * QW];
+  __shared__ uint32_t RID[CAP + kPad];
+  __shared__ __align__(16) uint32_t Q[DM1 > 0 ? (CAP + kPad) * QW : 1];
   __shared__ uint32_t BIN[NBINS];
   __shared__ float redf[2 * W + 2];
   __shared__ uint32_t red[W + 2];
@@ -724,36 +749,21 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   }
   const uint32_t bs_begin = O.bs_begin(b);
   const uint32_t nbs = O.bs_begin(b + 1) - bs_begin;
-  const BucketParams prm = P[inst];
   const int t = threadIdx.x;
-  const SweepOut o{n, per_update, pair_off, cursor, out_u, out_s};
+  const SweepCtx o{I, n, per_update, pair_off, cursor, out_u, out_s};
 
   // 1. records into registers (slot s = t + i * THREADS); value range
-  uint32_t rk[ITEMS][RW];
+  uint4 rk[ITEMS];
   float vmn = __int_as_float(0x7f800000), vmx = -__int_as_float(0x7f800000);
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const uint32_t s = t + i * THREADS;
+    rk[i] = make_uint4(0u, 0u, 0u, 0u);
     if (s < C) {
-      const uint4 *src = reinterpret_cast<const uint4 *>(rec + (size_t)(start + s) * RW);
-      const uint4 a = src[0];
-      rk[i][0] = a.x;
-      rk[i][1] = a.y;
-      rk[i][2] = a.z;
-      rk[i][3] = a.w;
-      if (RW == 8) {
-        const uint4 c = src[1];
-        rk[i][4 % RW] = c.x;
-        rk[i][5 % RW] = c.y;
-        rk[i][6 % RW] = c.z;
-        rk[i][7 % RW] = c.w;
-      }
-      const float x = decode_coord(rk[i][0]);
+      rk[i] = reinterpret_cast<const uint4 *>(rec)[start + s];
+      const float x = decode_coord(rk[i].x);
       vmn = fminf(vmn, x);
       vmx = fmaxf(vmx, x);
-    } else {
-#pragma unroll
-      for (int k = 0; k < RW; ++k) rk[i][k] = 0;
     }
   }
   vmn = wave_min(vmn);
@@ -766,7 +776,8 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   if (t < kPad) {  // defined values in the padding (never counted)
     KLO[CAP + t] = 0;
 #pragma unroll
-    for (int c = 0; c < QW; ++c) Q[(CAP + t) * QW + c] = 0;
+    for (int c = 0; c < QW; ++c)
+      if (DM1 > 0) Q[(CAP + t) * QW + c] = 0;
   }
   __syncthreads();
   vmn = redf[0];
@@ -788,7 +799,7 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   for (int i = 0; i < ITEMS; ++i) {
     const uint32_t s = t + i * THREADS;
     if (s < C) {
-      key[i] = (rk[i][2] >= n ? kFine : 0u) + fine_of(decode_coord(rk[i][0]), vmn, fscale);
+      key[i] = (rk[i].z >= n ? kFine : 0u) + fine_of(decode_coord(rk[i].x), vmn, fscale);
       atomicAdd(&BIN[key[i]], 1u);
     }
   }
@@ -814,17 +825,11 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
     const uint32_t s = t + i * THREADS;
     if (s < C) {
       const uint32_t qpos = atomicAdd(&BIN[key[i]], 1u);
-      KLO[qpos] = rk[i][0];
-      KHI[qpos] = rk[i][1];
-      if (DM1 > 0) {
-        GIDX[qpos] = start + s;
-        uint32_t q[QW];
-        qwords<DM1>(rk[i], prm, q, nullptr);
+      KLO[qpos] = rk[i].x;
+      KHI[qpos] = rk[i].y;
+      RID[qpos] = rk[i].z;
 #pragma unroll
-        for (int c = 0; c < QW; ++c) Q[qpos * QW + c] = q[c];
-      } else {
-        Q[qpos] = rk[i][2];
-      }
+      for (int c = 0; c < DM1; ++c) Q[qpos * QW + c] = entry_word<DM1>(rk[i].w, c);
     }
   }
   __syncthreads();
@@ -843,60 +848,39 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
       Walker<DM1> y;
       y.klo = KLO[qy];
       y.khi = KHI[qy];
+      y.rid = RID[qy];
       y.upd = qy < Cu;
       y.after_key = y.upd ? y.klo : y.klo + 1u;
-      if (DM1 > 0) {
-        y.rec = rec + (size_t)GIDX[qy] * RW;
-        // walker words from the entry words: swap halves back to (lo, hi)
+      y.q[0] = 0;
 #pragma unroll
-        for (int c = 0; c < DM1; ++c) {
-          const uint32_t ew = Q[qy * QW + c];
-          const uint32_t lq = ew & 0xFFFFu, hq = 65535u - (ew >> 16);
-          y.q[c] = hq | ((65535u - lq) << 16);
-        }
-        y.rid = 0;
-      } else {
-        y.rec = nullptr;
-        y.rid = Q[qy];
-        y.q[0] = 0;
+      for (int c = 0; c < DM1; ++c) {
+        // walker word from the entry word: swap the halves back to (lo, hi)
+        const uint32_t ew = Q[qy * QW + c];
+        const uint32_t lq = ew & 0xFFFFu, hq = 65535u - (ew >> 16);
+        y.q[c] = hq | ((65535u - lq) << 16);
       }
       const uint32_t fl = fine_of(decode_coord(y.klo), vmn, fscale);
       const uint32_t fh = fine_of(decode_coord(y.khi), vmn, fscale);
       const uint32_t other = y.upd ? kFine : 0u;
-      walk<DM1, MODE>(KLO, GIDX, Q, y, bin_begin(other + fl), BIN[other + fl],
-                      bin_begin(other + fh), BIN[other + fh], rec, hits, o);
+      walk<DM1, MODE>(KLO, RID, Q, y, bin_begin(other + fl), BIN[other + fl],
+                      bin_begin(other + fh), BIN[other + fh], hits, o);
     }
   }
   for (uint32_t k = t; k < nbs; k += THREADS) {
-    const uint32_t *yr = bs_rec + (size_t)(bs_begin + k) * RW;
-    uint32_t yw[8];
-    const uint4 a = *reinterpret_cast<const uint4 *>(yr);
-    yw[0] = a.x;
-    yw[1] = a.y;
-    yw[2] = a.z;
-    yw[3] = a.w;
-    yw[4] = yw[5] = yw[6] = yw[7] = 0;
-    if (RW == 8) {
-      const uint4 c = *reinterpret_cast<const uint4 *>(yr + 4);
-      yw[4] = c.x;
-      yw[5] = c.y;
-      yw[6] = c.z;
-      yw[7] = c.w;
-    }
+    const uint4 yr = reinterpret_cast<const uint4 *>(bs_rec)[bs_begin + k];
     Walker<DM1> y;
-    y.klo = yw[0];
-    y.khi = yw[1];
-    y.rid = yw[2];
-    y.upd = yw[2] < n;
+    y.klo = yr.x;
+    y.khi = yr.y;
+    y.rid = yr.z;
+    y.upd = yr.z < n;
     y.after_key = 0u;  // every lower endpoint of the bucket comes after it
     y.q[0] = 0;
-    if (DM1 > 0) qwords<DM1>(yw, prm, nullptr, y.q);
-    y.rec = yr;
+#pragma unroll
+    for (int c = 0; c < DM1; ++c) y.q[c] = walker_word<DM1>(yr.w, c);
     const uint32_t fh = fine_of(decode_coord(y.khi), vmn, fscale);
     const uint32_t other = y.upd ? kFine : 0u;
     const uint32_t jA = bin_begin(other);
-    walk<DM1, MODE>(KLO, GIDX, Q, y, jA, jA, bin_begin(other + fh), BIN[other + fh], rec, hits,
-                    o);
+    walk<DM1, MODE>(KLO, RID, Q, y, jA, jA, bin_begin(other + fh), BIN[other + fh], hits, o);
   }
   hits = wave_sum(hits);
   if (lane_id() == 0) red64[t / kWave] = hits;
@@ -984,11 +968,11 @@ void sweep_impl(const BucketArgs &a, int32_t *per_update, const unsigned long lo
   Ptrs p = pointers(a);
   if (L.tune.sweep_threads == 256)
     bk_sweep_kernel<DM1, MODE, kCap, 256><<<L.nb, 256, 0, s>>>(
-        p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, p.P, a.hdr, per_update, pair_off, cursor,
+        p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
         out_u, out_s, total, a.inst_total, gate);
   else
     bk_sweep_kernel<DM1, MODE, kCap, 512><<<L.nb, 512, 0, s>>>(
-        p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, p.P, a.hdr, per_update, pair_off, cursor,
+        p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
         out_u, out_s, total, a.inst_total, gate);
 }
 
@@ -1083,7 +1067,7 @@ BucketLayout bucket_layout(const InstSpec *inst, int64_t B, int d, const BucketT
   L.m_total = (uint32_t)s0;
   const uint64_t N = (uint64_t)L.n_total + L.m_total;
   L.bs_cap = (uint32_t)(N / 2 + 4096);
-  L.rec_words = d == 1 ? 4 : 8;
+  L.rec_words = 4;
   size_t at = 0;
   auto take = [&](size_t bytes) {
     size_t o = at;
