@@ -425,8 +425,9 @@ __device__ __forceinline__ uint32_t quant_hi(float x, float qmin, float qs) {
 // Record (16 bytes): word 0 = encoded lower key (swept axis), 1 = encoded
 // upper key, 2 = region index (updates first), 3 = quantised bounds of the
 // other axes: for d = 2 the 16-bit lower | upper << 16 of axis 1; for d = 3
-// 8-bit bounds (the 16-bit ones, lower rounded down and upper rounded up to a
-// multiple of 256) lo1 | hi1 << 8 | lo2 << 16 | hi2 << 24; 0 for d = 1.
+// 7-bit bounds (the 16-bit ones scaled by 2^-9, lower rounded down, upper
+// rounded up and capped at 127) lo1 | hi1 << 8 | lo2 << 16 | hi2 << 24; 0
+// for d = 1.
 template <int D>
 __device__ __forceinline__ uint32_t qword_of(const Box<D> &b, const BucketParams &p) {
   if (D == 2) {
@@ -437,9 +438,9 @@ __device__ __forceinline__ uint32_t qword_of(const Box<D> &b, const BucketParams
     uint32_t w = 0;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-      const uint32_t l8 = quant_lo(b.lo[(1 + c) % D], p.qmin[c], p.qscale[c]) >> 8;
-      const uint32_t h8 = min(255u, (quant_hi(b.hi[(1 + c) % D], p.qmin[c], p.qscale[c]) + 255u) >> 8);
-      w |= (l8 | (h8 << 8)) << (16 * c);
+      const uint32_t l7 = quant_lo(b.lo[(1 + c) % D], p.qmin[c], p.qscale[c]) >> 9;
+      const uint32_t h7 = min(127u, (quant_hi(b.hi[(1 + c) % D], p.qmin[c], p.qscale[c]) + 511u) >> 9);
+      w |= (l7 | (h7 << 8)) << (16 * c);
     }
     return w;
   }
@@ -554,33 +555,35 @@ __device__ __forceinline__ uint32_t qdiff(uint32_t entry, uint32_t walker) {
                                           __builtin_bit_cast(u16x2, walker)));
 }
 
-// 16-bit bounds of other axis c from a record's word 3 (see qword_of): the
-// 8-bit bounds of d = 3 widen to lo * 256 and hi * 256 (65535 for 255), which
-// still contain the 16-bit ones.
+// Pre-filter words.  d = 2: the 16-bit bounds of axis 1 as above.  d = 3:
+// one word of four 7-bit fields; the entry word holds, per axis, lo and
+// 127 - hi in consecutive bytes, the walker word hi and 127 - lo with the top
+// bit of every byte set.  walker - entry then borrows across no byte, and the
+// top bit of each byte survives exactly when that byte of the entry is not
+// above the walker's: both axes pass iff all four top bits survive.
 template <int DM1>
-__device__ __forceinline__ void qbounds(uint32_t w, int c, uint32_t &lo, uint32_t &hi) {
+__device__ __forceinline__ uint32_t entry_word(uint32_t w) {
+  if (DM1 == 1) return (w & 0xFFFFu) | ((65535u - (w >> 16)) << 16);
+  // bytes lo1, hi1, lo2, hi2 -> lo1, 127 - hi1, lo2, 127 - hi2
+  return (w & 0x00FF00FFu) | (0x7F007F00u - (w & 0xFF00FF00u));
+}
+
+// The walker word of a region from its own entry word.
+template <int DM1>
+__device__ __forceinline__ uint32_t walker_from_entry(uint32_t e) {
   if (DM1 == 1) {
-    lo = w & 0xFFFFu;
-    hi = w >> 16;
-  } else {
-    const uint32_t l8 = (w >> (16 * c)) & 0xFFu, h8 = (w >> (16 * c + 8)) & 0xFFu;
-    lo = l8 << 8;
-    hi = h8 == 255u ? 65535u : h8 << 8;
+    const uint32_t lq = e & 0xFFFFu, hq = 65535u - (e >> 16);
+    return hq | ((65535u - lq) << 16);
   }
+  // entry bytes a0, b0, a1, b1 (a = lo, b = 127 - hi) -> walker bytes
+  // hi, 127 - lo per axis = 127 - b, 127 - a, plus the top bits
+  const uint32_t swapped = ((e & 0x00FF00FFu) << 8) | ((e >> 8) & 0x00FF00FFu);
+  return (0x7F7F7F7Fu - swapped) | 0x80808080u;
 }
 
 template <int DM1>
-__device__ __forceinline__ uint32_t entry_word(uint32_t w, int c) {
-  uint32_t lo, hi;
-  qbounds<DM1>(w, c, lo, hi);
-  return lo | ((65535u - hi) << 16);
-}
-
-template <int DM1>
-__device__ __forceinline__ uint32_t walker_word(uint32_t w, int c) {
-  uint32_t lo, hi;
-  qbounds<DM1>(w, c, lo, hi);
-  return hi | ((65535u - lo) << 16);
+__device__ __forceinline__ uint32_t walker_word(uint32_t w) {
+  return walker_from_entry<DM1>(entry_word<DM1>(w));
 }
 
 // Padding of the per-bucket LDS arrays: the unrolled interior loop reads up
@@ -591,7 +594,7 @@ constexpr int kPad = 4;
 template <int DM1>
 struct Walker {
   uint32_t klo, khi, after_key, rid;
-  uint32_t q[DM1 > 0 ? DM1 : 1];
+  uint32_t q;  // pre-filter walker word (d >= 2)
   bool upd;
 };
 
@@ -658,11 +661,8 @@ __device__ __forceinline__ void visit(const Walker<DM1> &y, bool &have_y, float 
 template <int DM1>
 __device__ __forceinline__ bool qpass(const uint32_t *__restrict__ Q, uint32_t j,
                                       const Walker<DM1> &y) {
-  if (DM1 == 2) {
-    const uint2 e = reinterpret_cast<const uint2 *>(Q)[j];
-    return (qdiff(e.x, y.q[0]) | qdiff(e.y, y.q[DM1 - 1])) == 0u;
-  }
-  if (DM1 == 1) return qdiff(Q[j], y.q[0]) == 0u;
+  if (DM1 == 2) return ((y.q - Q[j]) & 0x80808080u) == 0x80808080u;
+  if (DM1 == 1) return qdiff(Q[j], y.q) == 0u;
   return true;
 }
 
@@ -718,7 +718,6 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
     uint32_t *__restrict__ out_u, uint32_t *__restrict__ out_s,
     unsigned long long *__restrict__ total, unsigned long long *__restrict__ inst_total,
     const uint32_t *__restrict__ gate) {
-  constexpr int QW = DM1 > 0 ? DM1 : 1;
   constexpr int ITEMS = CAP / THREADS;
   constexpr int W = THREADS / kWave;
   constexpr int NBINS = 2 * kFine;
@@ -729,7 +728,7 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   __shared__ uint32_t KLO[CAP + kPad];
   __shared__ uint32_t KHI[CAP + kPad];
   __shared__ uint32_t RID[CAP + kPad];
-  __shared__ __align__(16) uint32_t Q[DM1 > 0 ? (CAP + kPad) * QW : 1];
+  __shared__ uint32_t Q[DM1 > 0 ? CAP + kPad : 1];
   __shared__ uint32_t BIN[NBINS];
   __shared__ float redf[2 * W + 2];
   __shared__ uint32_t red[W + 2];
@@ -775,9 +774,7 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   for (int k = t; k < NBINS; k += THREADS) BIN[k] = 0;
   if (t < kPad) {  // defined values in the padding (never counted)
     KLO[CAP + t] = 0;
-#pragma unroll
-    for (int c = 0; c < QW; ++c)
-      if (DM1 > 0) Q[(CAP + t) * QW + c] = 0;
+    if (DM1 > 0) Q[CAP + t] = 0;
   }
   __syncthreads();
   vmn = redf[0];
@@ -828,8 +825,7 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
       KLO[qpos] = rk[i].x;
       KHI[qpos] = rk[i].y;
       RID[qpos] = rk[i].z;
-#pragma unroll
-      for (int c = 0; c < DM1; ++c) Q[qpos * QW + c] = entry_word<DM1>(rk[i].w, c);
+      if (DM1 > 0) Q[qpos] = entry_word<DM1>(rk[i].w);
     }
   }
   __syncthreads();
@@ -851,14 +847,7 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
       y.rid = RID[qy];
       y.upd = qy < Cu;
       y.after_key = y.upd ? y.klo : y.klo + 1u;
-      y.q[0] = 0;
-#pragma unroll
-      for (int c = 0; c < DM1; ++c) {
-        // walker word from the entry word: swap the halves back to (lo, hi)
-        const uint32_t ew = Q[qy * QW + c];
-        const uint32_t lq = ew & 0xFFFFu, hq = 65535u - (ew >> 16);
-        y.q[c] = hq | ((65535u - lq) << 16);
-      }
+      y.q = DM1 > 0 ? walker_from_entry<DM1>(Q[qy]) : 0u;
       const uint32_t fl = fine_of(decode_coord(y.klo), vmn, fscale);
       const uint32_t fh = fine_of(decode_coord(y.khi), vmn, fscale);
       const uint32_t other = y.upd ? kFine : 0u;
@@ -874,9 +863,7 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
     y.rid = yr.z;
     y.upd = yr.z < n;
     y.after_key = 0u;  // every lower endpoint of the bucket comes after it
-    y.q[0] = 0;
-#pragma unroll
-    for (int c = 0; c < DM1; ++c) y.q[c] = walker_word<DM1>(yr.w, c);
+    y.q = DM1 > 0 ? walker_word<DM1>(yr.w) : 0u;
     const uint32_t fh = fine_of(decode_coord(y.khi), vmn, fscale);
     const uint32_t other = y.upd ? kFine : 0u;
     const uint32_t jA = bin_begin(other);
