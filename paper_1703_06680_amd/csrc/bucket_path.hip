@@ -658,20 +658,33 @@ __device__ __forceinline__ void visit(const Walker<DM1> &y, bool &have_y, float 
   }
 }
 
+// Zero iff entry word e passes the walker's pre-filter (d >= 2).
+template <int DM1>
+__device__ __forceinline__ uint32_t qfail(uint32_t e, uint32_t wq) {
+  if (DM1 == 2) return ~(wq - e) & 0x80808080u;  // a cleared top bit: some byte failed
+  if (DM1 == 1) return qdiff(e, wq);
+  return 0u;
+}
+
 template <int DM1>
 __device__ __forceinline__ bool qpass(const uint32_t *__restrict__ Q, uint32_t j,
                                       const Walker<DM1> &y) {
-  if (DM1 == 2) return ((y.q - Q[j]) & 0x80808080u) == 0x80808080u;
-  if (DM1 == 1) return qdiff(Q[j], y.q) == 0u;
-  return true;
+  return DM1 == 0 || qfail<DM1>(Q[j], y.q) == 0u;
+}
+
+__device__ __forceinline__ uint32_t min4(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+  return min(min(a, b), min(c, d));
 }
 
 // Walk of y over the other kind's entries [jA, jD) of the bucket.  Entries in
 // [jA, jB) (the first fine bin) must come after y's lower endpoint
 // (KLO >= after_key), entries in [jC, jD) (the last fine bin) must start
 // before its upper endpoint (KLO < khi); entries of the bins in between
-// satisfy both by the monotonicity of the fine-bin map, so that loop only
-// runs the pre-filter.
+// satisfy both by the monotonicity of the fine-bin map.  The edge loop tests
+// keys and covers the first bin up to a multiple of four and the last bin
+// back to one; the interior loop reads four aligned entry words at a time and
+// runs only the pre-filter (skipping a chunk with one compare when none of
+// the four passes).
 template <int DM1, int MODE>
 __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
                                      const uint32_t *__restrict__ RID,
@@ -681,29 +694,39 @@ __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
   uint32_t own = 0;
   bool have_y = false;
   float ylo[2] = {0.f, 0.f}, yhi[2] = {0.f, 0.f};
-  // edge entries: the first bin, then the part of the last bin past it
-  const uint32_t e1 = jB - jA;
-  const uint32_t jC2 = jC > jB ? jC : jB;
-  const uint32_t e = e1 + (jD - jC2);
+  // interior [a, b): multiples of four inside [jB, jC) (empty if first and
+  // last bin coincide, jC <= jB)
+  uint32_t a = jD, b = jD;
+  if (jC > jB) {
+    a = min((jB + 3u) & ~3u, jC);
+    b = max(jC & ~3u, a);
+  }
+  // edge entries [jA, a) and [b, jD), with key tests
+  const uint32_t e1 = a - jA;
+  const uint32_t e = e1 + (jD - b);
   for (uint32_t t = 0; t < e; ++t) {
-    const uint32_t j = t < e1 ? jA + t : jC2 + (t - e1);
+    const uint32_t j = t < e1 ? jA + t : b + (t - e1);
     const uint32_t k = KLO[j];
     if (k >= y.after_key && k < y.khi && qpass<DM1>(Q, j, y))
       visit<DM1, MODE>(y, have_y, ylo, yhi, j, RID, hits, own, o);
   }
-  // interior bins
-  if (DM1 == 0 && MODE == 0) {
-    if (jC > jB) hits += jC - jB;
+  // interior: every entry satisfies the key tests
+  if (DM1 == 0) {
+    if (MODE == 0) {
+      hits += b - a;
+    } else {
+      for (uint32_t j = a; j < b; ++j) visit<DM1, MODE>(y, have_y, ylo, yhi, j, RID, hits, own, o);
+    }
   } else {
-    for (uint32_t j = jB; j < jC; j += 4) {
-      uint32_t msk = 0;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) msk |= qpass<DM1>(Q, j + u, y) ? (1u << u) : 0u;
-      if (jC - j < 4) msk &= (1u << (jC - j)) - 1u;
-      if (msk) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (msk & (1u << u)) visit<DM1, MODE>(y, have_y, ylo, yhi, j + u, RID, hits, own, o);
+    for (uint32_t j = a; j < b; j += 4) {
+      const uint4 q4 = reinterpret_cast<const uint4 *>(Q)[j >> 2];
+      const uint32_t f0 = qfail<DM1>(q4.x, y.q), f1 = qfail<DM1>(q4.y, y.q);
+      const uint32_t f2 = qfail<DM1>(q4.z, y.q), f3 = qfail<DM1>(q4.w, y.q);
+      if (min4(f0, f1, f2, f3) == 0u) {
+        if (f0 == 0u) visit<DM1, MODE>(y, have_y, ylo, yhi, j, RID, hits, own, o);
+        if (f1 == 0u) visit<DM1, MODE>(y, have_y, ylo, yhi, j + 1, RID, hits, own, o);
+        if (f2 == 0u) visit<DM1, MODE>(y, have_y, ylo, yhi, j + 2, RID, hits, own, o);
+        if (f3 == 0u) visit<DM1, MODE>(y, have_y, ylo, yhi, j + 3, RID, hits, own, o);
       }
     }
   }
@@ -728,7 +751,7 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   __shared__ uint32_t KLO[CAP + kPad];
   __shared__ uint32_t KHI[CAP + kPad];
   __shared__ uint32_t RID[CAP + kPad];
-  __shared__ uint32_t Q[DM1 > 0 ? CAP + kPad : 1];
+  __shared__ __align__(16) uint32_t Q[DM1 > 0 ? CAP + kPad : 4];
   __shared__ uint32_t BIN[NBINS];
   __shared__ float redf[2 * W + 2];
   __shared__ uint32_t red[W + 2];
