@@ -197,8 +197,8 @@ int run_bucketed(const Call &c) {
   a.L = &c.L.B;
   a.hdr = c.hdr;
   a.inst_total = nullptr;
-  int rc = reset_outputs(c);
-  if (rc != DDM_OK) return rc;
+  a.zero = c.mode != DDM_COUNT && c.n > 0 ? c.cnt : nullptr;  // cleared by the count pass
+  a.zero_count = (uint32_t)c.n;
   DDM_HIP(bucket_prepare(a, c.s));
   const int count_mode = c.mode == DDM_COUNT ? 0 : 1;
   DDM_HIP(bucket_sweep(a, count_mode, c.cnt, nullptr, nullptr, nullptr, nullptr, &c.hdr->total,

@@ -343,11 +343,12 @@ int enqueue(const Batch &c, hipStream_t s) {
   int32_t *cnt = c.mode == DDM_COUNT ? nullptr
                  : (c.per_update ? c.per_update : at<int32_t>(c.ws, L.cnt));
   const BucketArgs a = bucket_args(c);
-  prof::mark(s, "batch.clear");
-  DDM_HIP(fill_u32(reinterpret_cast<uint32_t *>(hdr), 0u, sizeof(Header) / sizeof(uint32_t), s));
-  DDM_HIP(fill_u64(reinterpret_cast<unsigned long long *>(c.counts), 0ull, (size_t)c.B, s));
-  if (cnt) DDM_HIP(fill_u32(reinterpret_cast<uint32_t *>(cnt), 0u, n_total, s));
-  DDM_HIP(bucket_prepare(a, s));
+  // the sampling pass clears the header and the per-instance counts, the
+  // count pass the per-update counts
+  BucketArgs prep = a;
+  prep.zero = cnt;
+  prep.zero_count = cnt ? n_total : 0u;
+  DDM_HIP(bucket_prepare(prep, s));
   DDM_HIP(bucket_sweep(a, c.mode == DDM_COUNT ? 0 : 1, cnt, nullptr, nullptr, nullptr, nullptr,
                        &hdr->total, s));
   if (c.mode == DDM_PAIRS) {

@@ -88,6 +88,8 @@ struct BucketArgs {
   const BucketLayout *L;
   Header *hdr;
   unsigned long long *inst_total;  // per-instance pair counts [B], or null
+  int32_t *zero;                   // cleared by bucket_prepare ([zero_count]), or null
+  uint32_t zero_count;
 };
 
 // Copies the per-instance plan to the workspace and expands the block,
@@ -100,7 +102,9 @@ size_t plan_bytes(const BucketLayout &L);
 hipError_t bucket_upload_plan(const BucketArgs &a, hipStream_t s, void *pinned = nullptr);
 
 // Enqueue sampling, counting (with input validation), prefix sums and the
-// scatter of region records into buckets.
+// scatter of region records into buckets.  It clears the header, the
+// per-instance totals and a.zero itself (so the outputs need no clearing
+// beforehand).
 hipError_t bucket_prepare(const BucketArgs &a, hipStream_t s);
 
 // Enqueue the per-bucket sweep.  mode 0: totals only; 1: totals and

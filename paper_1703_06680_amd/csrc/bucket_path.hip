@@ -148,9 +148,31 @@ struct Offsets {
 
 // ---------------------------------------------------------------- sample
 
+// Clears, before the count pass runs: the header, the boundary-state sizes
+// and fill cursors (nb + 1 and nb words) and the per-instance totals.
+struct Clear {
+  Header *hdr;
+  uint32_t *bs_size, *bs_cur;
+  uint32_t nb;
+  unsigned long long *inst_total;
+  uint32_t B;
+};
+
 template <int D>
 __global__ __launch_bounds__(kSampleThreads) void bk_sample_kernel(View V,
-                                                                   float *__restrict__ part) {
+                                                                   float *__restrict__ part,
+                                                                   Clear clr) {
+  {
+    const uint32_t tid = blockIdx.x * kSampleThreads + threadIdx.x;
+    const uint32_t stride = gridDim.x * kSampleThreads;
+    if (tid < sizeof(Header) / sizeof(uint32_t)) reinterpret_cast<uint32_t *>(clr.hdr)[tid] = 0u;
+    for (uint32_t i = tid; i <= clr.nb; i += stride) {
+      clr.bs_size[i] = 0u;
+      if (i < clr.nb) clr.bs_cur[i] = 0u;
+    }
+    if (clr.inst_total)
+      for (uint32_t i = tid; i < clr.B; i += stride) clr.inst_total[i] = 0ull;
+  }
   // per block: min/max of the swept lower coordinate, count, and for the
   // other axes min(lo) / max(hi), over the sampled valid non-empty boxes of
   // the block's instance
@@ -207,17 +229,17 @@ __global__ __launch_bounds__(kSampleThreads) void bk_sample_kernel(View V,
   }
 }
 
-// One block per instance: reduces the instance's sample partials into its
-// bucket map and quantisation parameters.
-__global__ __launch_bounds__(kSampleThreads) void bk_plan_kernel(const float *__restrict__ part,
-                                                                 View V,
-                                                                 BucketParams *__restrict__ P) {
-  constexpr int W = kSampleThreads / kWave;
-  __shared__ float sred[W][8];
-  const InstPlan I = V.get(blockIdx.x);
+// The bucket map and quantisation parameters of instance I, reduced by the
+// whole workgroup from the instance's sample partials (every workgroup of
+// the count and scatter passes computes the same values: min, max and a sum
+// of small integers do not depend on the order of reduction).
+template <int THREADS>
+__device__ BucketParams block_plan(const float *__restrict__ part, const InstPlan &I,
+                                   float (*sred)[8], BucketParams *shared_out) {
+  constexpr int W = THREADS / kWave;
   const float inf = __int_as_float(0x7f800000);
   float v[8] = {inf, -inf, 0.f, 0.f, inf, -inf, inf, -inf};
-  for (uint32_t i = threadIdx.x; i < I.nsmp; i += kSampleThreads) {
+  for (uint32_t i = threadIdx.x; i < I.nsmp; i += THREADS) {
     const float *pp = part + (size_t)(I.smp0 + i) * 8;
 #pragma unroll
     for (int k = 0; k < 8; k += 2) {
@@ -239,42 +261,55 @@ __global__ __launch_bounds__(kSampleThreads) void bk_plan_kernel(const float *__
 #pragma unroll
     for (int k = 0; k < 8; ++k) sred[w][k] = v[k];
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  for (int j = 1; j < W; ++j)
+  if (threadIdx.x == 0) {
+    for (int j = 1; j < W; ++j)
 #pragma unroll
-    for (int k = 0; k < 8; k += 2) {
-      if (k == 2) continue;
-      v[k] = fminf(v[k], sred[j][k]);
-      v[k + 1] = fmaxf(v[k + 1], sred[j][k + 1]);
-    }
-  float c = 0.f;
-  for (int j = 0; j < W; ++j) c += sred[j][2];
-  BucketParams q;
-  q.nb = I.nb;
-  q.vmin = 0.f;
-  q.scale = 0.f;
-  q.valid = 0;
-  if (c > 0.f && v[1] > v[0] && I.nb > 0) {
-    const float scale = (float)I.nb / (v[1] - v[0]);
-    if (scale > 0.f && scale <= 3.0e38f) {
-      q.vmin = v[0];
-      q.scale = scale;
-      q.valid = 1;
-    }
-  }
-  for (int k = 0; k < 2; ++k) {
-    const float lo = v[4 + 2 * k], hi = v[5 + 2 * k];
-    q.qmin[k] = 0.f;
-    q.qscale[k] = 0.f;  // every box quantises to 0: the pre-filter lets all pass
-    if (c > 0.f && hi > lo) {
-      const float qs = 65535.0f / (hi - lo);
-      if (qs > 0.f && qs <= 3.0e38f) {
-        q.qmin[k] = lo;
-        q.qscale[k] = qs;
+      for (int k = 0; k < 8; k += 2) {
+        if (k == 2) continue;
+        v[k] = fminf(v[k], sred[j][k]);
+        v[k + 1] = fmaxf(v[k + 1], sred[j][k + 1]);
+      }
+    float c = 0.f;
+    for (int j = 0; j < W; ++j) c += sred[j][2];
+    BucketParams q;
+    q.nb = I.nb;
+    q.vmin = 0.f;
+    q.scale = 0.f;
+    q.valid = 0;
+    if (c > 0.f && v[1] > v[0] && I.nb > 0) {
+      const float scale = (float)I.nb / (v[1] - v[0]);
+      if (scale > 0.f && scale <= 3.0e38f) {
+        q.vmin = v[0];
+        q.scale = scale;
+        q.valid = 1;
       }
     }
+    for (int k = 0; k < 2; ++k) {
+      const float lo = v[4 + 2 * k], hi = v[5 + 2 * k];
+      q.qmin[k] = 0.f;
+      q.qscale[k] = 0.f;  // every box quantises to 0: the pre-filter lets all pass
+      if (c > 0.f && hi > lo) {
+        const float qs = 65535.0f / (hi - lo);
+        if (qs > 0.f && qs <= 3.0e38f) {
+          q.qmin[k] = lo;
+          q.qscale[k] = qs;
+        }
+      }
+    }
+    *shared_out = q;
   }
-  P[blockIdx.x] = q;
+  __syncthreads();
+  return *shared_out;
+}
+
+// One workgroup per instance: its bucket map and quantisation parameters.
+__global__ __launch_bounds__(kSampleThreads) void bk_plan_kernel(const float *__restrict__ part,
+                                                                 View V,
+                                                                 BucketParams *__restrict__ P) {
+  __shared__ float sred[kSampleThreads / kWave][8];
+  __shared__ BucketParams shp;
+  const BucketParams q = block_plan<kSampleThreads>(part, V.get(blockIdx.x), sred, &shp);
+  if (threadIdx.x == 0) P[blockIdx.x] = q;
 }
 
 // ------------------------------------------------------ row groups
@@ -343,11 +378,15 @@ __device__ __forceinline__ void load_group(const Group &q, bool vec, Box<D> (&bx
 template <int D>
 __global__ __launch_bounds__(kThreads) void bk_count_kernel(
     uint32_t n_total, View V, const BucketParams *__restrict__ P, uint32_t *__restrict__ C,
-    uint32_t *__restrict__ bs_size, Header *__restrict__ hdr) {
+    uint32_t *__restrict__ bs_size, Header *__restrict__ hdr, int32_t *__restrict__ zero,
+    uint32_t zero_count) {
   extern __shared__ uint32_t hist[];
   const uint32_t inst = V.of_blk(blockIdx.x);
   const InstPlan I = V.get(inst);
   const BucketParams p = P[inst];
+  // the per-update output, cleared here for the sweep
+  for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < zero_count; i += gridDim.x * kThreads)
+    zero[i] = 0;
   const uint32_t nb = I.nb, lb = blockIdx.x - I.blk0;
   for (uint32_t b = threadIdx.x; b < nb; b += kThreads) hist[b] = 0;
   __syncthreads();
@@ -598,6 +637,12 @@ struct Walker {
   bool upd;
 };
 
+// Pairs that pass the pre-filter wait in a small LDS queue for the exact
+// test, which then runs for all of them at once after the walks, so that the
+// latency of reading their coordinates overlaps; a full queue sends further
+// pairs through the exact test at once.
+constexpr int kQueue = 320;
+
 struct SweepCtx {
   InstPlan I;  // the bucket's instance: rows of its regions
   uint32_t n;  // updates over the batch (region indices below are updates)
@@ -605,6 +650,8 @@ struct SweepCtx {
   const unsigned long long *pair_off;
   uint32_t *cursor;
   uint32_t *out_u, *out_s;
+  uint2 *queue;     // LDS: (walker region, entry region) pairs awaiting the exact test
+  uint32_t *queued; // LDS: number of pairs offered to the queue
 };
 
 // Exact other-axis coordinates of region rid, from the instance's rows.
@@ -632,6 +679,11 @@ __device__ __forceinline__ void visit(const Walker<DM1> &y, bool &have_y, float 
                                       uint32_t &own, const SweepCtx &o) {
   const uint32_t rx = RID[j];
   if (DM1 > 0) {
+    const uint32_t at = atomicAdd(o.queued, 1u);
+    if (at < (uint32_t)kQueue) {
+      o.queue[at] = make_uint2(y.rid, rx);
+      return;
+    }
     if (!have_y) {
       have_y = true;
       other_axes<DM1>(o, y.rid, ylo, yhi);
@@ -655,6 +707,29 @@ __device__ __forceinline__ void visit(const Walker<DM1> &y, bool &have_y, float 
     const unsigned long long slot = o.pair_off[uu] + atomicAdd(&o.cursor[uu], 1u);
     o.out_u[slot] = uu;
     o.out_s[slot] = sid;
+  }
+}
+
+// The exact test of a queued pair (ry walked, rx was met), then count or
+// emit as visit() does.
+template <int DM1, int MODE>
+__device__ __forceinline__ void resolve(uint32_t ry, uint32_t rx, unsigned long long &hits,
+                                        const SweepCtx &o) {
+  float ylo[2], yhi[2], xlo[2], xhi[2];
+  other_axes<DM1>(o, ry, ylo, yhi);
+  other_axes<DM1>(o, rx, xlo, xhi);
+  bool hit = true;
+#pragma unroll
+  for (int c = 0; c < DM1; ++c) hit = hit && ylo[c] < xhi[c] && xlo[c] < yhi[c];
+  if (!hit) return;
+  ++hits;
+  const uint32_t uu = ry < o.n ? ry : rx, ss = ry < o.n ? rx : ry;
+  if (MODE == 1) {
+    atomicAdd(&o.per_update[uu], 1);
+  } else if (MODE == 2) {
+    const unsigned long long slot = o.pair_off[uu] + atomicAdd(&o.cursor[uu], 1u);
+    o.out_u[slot] = uu;
+    o.out_s[slot] = ss - o.n;
   }
 }
 
@@ -756,6 +831,8 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   __shared__ float redf[2 * W + 2];
   __shared__ uint32_t red[W + 2];
   __shared__ unsigned long long red64[W];
+  __shared__ uint2 queue[DM1 > 0 ? kQueue : 1];
+  __shared__ uint32_t queued;
 
   if (MODE == 2 && gate && *gate == 0u) return;  // uniform over the grid
   const uint32_t b = blockIdx.x;
@@ -772,7 +849,7 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   const uint32_t bs_begin = O.bs_begin(b);
   const uint32_t nbs = O.bs_begin(b + 1) - bs_begin;
   const int t = threadIdx.x;
-  const SweepCtx o{I, n, per_update, pair_off, cursor, out_u, out_s};
+  const SweepCtx o{I, n, per_update, pair_off, cursor, out_u, out_s, queue, &queued};
 
   // 1. records into registers (slot s = t + i * THREADS); value range
   uint4 rk[ITEMS];
@@ -795,6 +872,7 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
     redf[2 * (t / kWave) + 1] = vmx;
   }
   for (int k = t; k < NBINS; k += THREADS) BIN[k] = 0;
+  if (t == 0) queued = 0;
   if (t < kPad) {  // defined values in the padding (never counted)
     KLO[CAP + t] = 0;
     if (DM1 > 0) Q[CAP + t] = 0;
@@ -892,6 +970,14 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
     const uint32_t jA = bin_begin(other);
     walk<DM1, MODE>(KLO, RID, Q, y, jA, jA, bin_begin(other + fh), BIN[other + fh], hits, o);
   }
+  if (DM1 > 0) {  // 4. the exact test of the queued pairs, all at once
+    __syncthreads();
+    const uint32_t nq = min(queued, (uint32_t)kQueue);
+    for (uint32_t k = t; k < nq; k += THREADS) {
+      const uint2 pr = queue[k];
+      resolve<DM1, MODE>(pr.x, pr.y, hits, o);
+    }
+  }
   hits = wave_sum(hits);
   if (lane_id() == 0) red64[t / kWave] = hits;
   __syncthreads();
@@ -955,17 +1041,17 @@ void prepare_impl(const BucketArgs &a, hipStream_t s) {
   const size_t cells = L.cells;
   const size_t lds = (size_t)L.max_nb * sizeof(uint32_t);
   prof::mark(s, "bucket.sample");
-  bk_sample_kernel<D><<<L.nsmp, kSampleThreads, 0, s>>>(p.V, p.part);
+  const Clear clr{a.hdr, p.T + cells, p.bs_cur, L.nb, a.inst_total, L.B};
+  bk_sample_kernel<D><<<L.nsmp, kSampleThreads, 0, s>>>(p.V, p.part, clr);
   bk_plan_kernel<<<L.B, kSampleThreads, 0, s>>>(p.part, p.V, p.P);
   prof::mark(s, "bucket.count");
-  (void)fill_u32(p.T + cells, 0u, (size_t)L.nb + 1, s);
-  bk_count_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.C, p.T + cells, a.hdr);
+  bk_count_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.C, p.T + cells, a.hdr,
+                                                   a.zero, a.zero ? a.zero_count : 0u);
   prof::mark(s, "bucket.offsets");
   bk_transpose_kernel<<<L.ntile, 256, 0, s>>>(p.C, p.T, p.V, 0);
   (void)exclusive_scan_u32(p.T, p.S, cells + L.nb + 1, p.scan_tmp, s);
   bk_transpose_kernel<<<L.ntile, 256, 0, s>>>(p.S, p.SB, p.V, 1);
   prof::mark(s, "bucket.scatter");
-  (void)fill_u32(p.bs_cur, 0u, L.nb, s);
   bk_scatter_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.O, p.SB, p.bs_cur,
                                                      L.bs_cap, p.rec, p.bs_rec);
 }
