@@ -36,10 +36,12 @@ def algorithmic_bytes(phase: str, n: int, m: int, d: int, nonempty: int, mode: s
     record is 16 bytes (lower and upper key on the swept axis, the region
     index, quantised bounds of the other axes).  Per region:
 
-      bucket.count    8d read (lo and hi rows);
+      bucket.count    8d read (lo and hi rows), + 4 per update written in
+                      per-update mode (the count pass clears that output);
       bucket.scatter  8d read + 16 written (one record);
-      bucket.sweep    16 read (one record), + 4 per update written in
-                      per-update mode;
+      bucket.sweep    16 read (one record), + what the matches write (not
+                      counted: at most 4 bytes per update, in practice
+                      negligible next to the records);
       keys            8d read + 8 written (lower/upper keys);
       sort.downsweep  8 read + 8 written per element (first pass: 4 + 8);
       sort.upsweep    4 read per element;
@@ -50,11 +52,11 @@ def algorithmic_bytes(phase: str, n: int, m: int, d: int, nonempty: int, mode: s
     rec = 16
     out = 4 * n if mode != "count" else 0
     if phase == "bucket.count":
-        return N * 8 * d
+        return N * 8 * d + out
     if phase == "bucket.scatter":
         return N * 8 * d + nonempty * rec
     if phase == "bucket.sweep":
-        return nonempty * rec + out
+        return nonempty * rec
     if phase == "keys":
         return N * (8 * d + 8)
     if phase == "sort.upsweep":
@@ -284,8 +286,6 @@ def main():
         k = step()
     torch.cuda.synchronize()
 
-    if not args.no_profile:
-        ddm.profile(True)
     per_step = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -295,8 +295,14 @@ def main():
         per_step.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    # per-phase times from HIP events on the library's stream, in a second
+    # pass of the same steps (event records are not part of the timed pass)
     phases = {}
     if not args.no_profile:
+        ddm.profile(True)
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
         phases = ddm.profile_report()
         ddm.profile(False)
 
