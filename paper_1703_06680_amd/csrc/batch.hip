@@ -120,8 +120,10 @@ BucketTuning to_tuning(const ddm_tuning *t) {
 
 bool tuning_valid(const ddm_tuning *t) {
   if (!t) return true;
-  return t->target >= 64 && t->target <= (int32_t)(kBucketCap * 3 / 4) &&
-         (t->sweep_threads == 256 || t->sweep_threads == 512) && t->groups_per_thread >= 1 &&
+  const bool big = t->sweep_threads == 1024;
+  return t->target >= 64 && t->target <= (int32_t)((big ? kBigBucketCap : kBucketCap) * 3 / 4) &&
+         (t->sweep_threads == 256 || t->sweep_threads == 512 || big) &&
+         t->groups_per_thread >= 1 &&
          t->groups_per_thread <= 64 && t->max_blocks >= 1 && t->max_blocks <= 65536;
 }
 

@@ -25,14 +25,16 @@ namespace ddm {
 
 // Launch-shape parameters of the bucketed path.
 struct BucketTuning {
-  uint32_t target = 1536;         // mean records per bucket (at most 3/4 of kBucketCap)
-  uint32_t sweep_threads = 512;   // 256 or 512 threads per sweep workgroup
+  uint32_t target = 1536;         // mean records per bucket (at most 3/4 of the capacity)
+  uint32_t sweep_threads = 512;   // 256, 512 or 1024 threads per sweep workgroup
   uint32_t groups_per_thread = 1; // count/scatter: groups of four rows per thread (minimum)
   uint32_t max_blocks = 512;      // count/scatter blocks per instance at most
 };
 
-// Records per bucket the sweep holds in LDS.
+// Records per bucket the sweep holds in LDS: kBucketCap for sweep
+// workgroups of 256 or 512 threads, kBigBucketCap for 1024.
 constexpr uint32_t kBucketCap = 2048;
+constexpr uint32_t kBigBucketCap = 4096;
 // Largest number of buckets of one instance (LDS-resident per-bucket counters
 // of the count and scatter passes).
 constexpr uint32_t kMaxBuckets = 16384;
@@ -55,6 +57,10 @@ struct InstPlan {
   uint32_t tile0, ntx;       // transpose tiles (first), tiles along the bucket axis
   uint32_t vec, pad;         // rows may be read with 16-byte loads
 };
+
+inline uint32_t bucket_cap(const BucketTuning &t) {
+  return t.sweep_threads == 1024 ? kBigBucketCap : kBucketCap;
+}
 
 struct BucketLayout {
   uint32_t B;                          // instances

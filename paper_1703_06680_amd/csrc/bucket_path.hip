@@ -53,10 +53,11 @@ constexpr int kSampleThreads = 256;
 constexpr uint32_t kSampleRows = 8192;         // rows per sample block (at most 256 blocks)
 constexpr uint32_t kMaxSampleBlocks = 256;
 
-// The sweep workgroup: kCap records at most per bucket, kFine fine bins per
-// kind.
+// The sweep workgroup: at most kBucketCap records per bucket with 512 fine
+// bins per kind (256 or 512 threads), or kBigBucketCap records with 1024
+// bins per kind (1024 threads).
 constexpr int kCap = (int)kBucketCap;
-constexpr int kFine = 512;
+constexpr int kBigCap = (int)kBigBucketCap;
 
 struct BucketParams {
   float vmin;        // bucket map of the swept axis' lower coordinate
@@ -574,9 +575,9 @@ __device__ __forceinline__ float decode_coord(uint32_t k) {
   return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
 }
 
-__device__ __forceinline__ uint32_t fine_of(float x, float vmin, float fscale) {
+__device__ __forceinline__ uint32_t fine_of(float x, float vmin, float fscale, int fine) {
   float t = (x - vmin) * fscale;
-  t = fminf(fmaxf(t, 0.0f), (float)(kFine - 1));
+  t = fminf(fmaxf(t, 0.0f), (float)(fine - 1));
   return (uint32_t)t;
 }
 
@@ -808,7 +809,7 @@ __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
   if (MODE == 1 && own) atomicAdd(&o.per_update[y.rid], (int)own);
 }
 
-template <int DM1, int MODE, int CAP, int THREADS>
+template <int DM1, int MODE, int CAP, int THREADS, int FINE>
 __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
     const uint32_t *__restrict__ rec, Offsets O, View V, const uint32_t *__restrict__ bs_rec,
     uint32_t bs_cap, uint32_t n, Header *__restrict__ hdr, int32_t *__restrict__ per_update,
@@ -818,7 +819,7 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
     const uint32_t *__restrict__ gate) {
   constexpr int ITEMS = CAP / THREADS;
   constexpr int W = THREADS / kWave;
-  constexpr int NBINS = 2 * kFine;
+  constexpr int NBINS = 2 * FINE;
   constexpr int BPT = NBINS / THREADS;  // bins per thread in the scan
   static_assert(NBINS % THREADS == 0, "bins must split evenly over the threads");
   // the bucket in LDS, in fine-bin order (updates first): lower and upper
@@ -887,17 +888,17 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   }
   float fscale = 0.f;
   if (vmx > vmn) {
-    fscale = (float)kFine / (vmx - vmn);
+    fscale = (float)FINE / (vmx - vmn);
     if (!(fscale <= 3.0e38f)) fscale = 0.f;
   }
 
-  // 2. counting sort into fine bins, updates first: bin = kind * kFine + fine(lo)
+  // 2. counting sort into fine bins, updates first: bin = kind * FINE + fine(lo)
   uint32_t key[ITEMS];
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const uint32_t s = t + i * THREADS;
     if (s < C) {
-      key[i] = (rk[i].z >= n ? kFine : 0u) + fine_of(decode_coord(rk[i].x), vmn, fscale);
+      key[i] = (rk[i].z >= n ? (uint32_t)FINE : 0u) + fine_of(decode_coord(rk[i].x), vmn, fscale, FINE);
       atomicAdd(&BIN[key[i]], 1u);
     }
   }
@@ -932,43 +933,44 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   __syncthreads();
   // BIN[k] is now the end of fine bin k; bin k starts at BIN[k - 1] (0 for k = 0)
   auto bin_begin = [&](uint32_t k) { return k ? BIN[k - 1] : 0u; };
-  const uint32_t Cu = BIN[kFine - 1];  // updates occupy [0, Cu)
+  const uint32_t Cu = BIN[FINE - 1];  // updates occupy [0, Cu)
 
-  // 3. the walks, in bin order: the lanes of a wave take consecutive entries,
-  //    so they walk neighbouring, overlapping ranges of the other kind
+  // 3. the walks.  Walkers are the bucket's regions in bin order followed by
+  //    its boundary-state regions; each wave takes chunks of 64 consecutive
+  //    walkers in turn, so the lanes of a wave walk neighbouring, overlapping
+  //    ranges and the boundary-state walkers are spread over all waves.
   unsigned long long hits = 0;
   const int lane = lane_id(), w = t / kWave;
-#pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
-    const uint32_t qy = (uint32_t)(w * (kWave * ITEMS) + i * kWave + lane);
-    if (qy < C) {
-      Walker<DM1> y;
-      y.klo = KLO[qy];
-      y.khi = KHI[qy];
-      y.rid = RID[qy];
-      y.upd = qy < Cu;
-      y.after_key = y.upd ? y.klo : y.klo + 1u;
-      y.q = DM1 > 0 ? walker_from_entry<DM1>(Q[qy]) : 0u;
-      const uint32_t fl = fine_of(decode_coord(y.klo), vmn, fscale);
-      const uint32_t fh = fine_of(decode_coord(y.khi), vmn, fscale);
-      const uint32_t other = y.upd ? kFine : 0u;
-      walk<DM1, MODE>(KLO, RID, Q, y, bin_begin(other + fl), BIN[other + fl],
-                      bin_begin(other + fh), BIN[other + fh], hits, o);
-    }
-  }
-  for (uint32_t k = t; k < nbs; k += THREADS) {
-    const uint4 yr = reinterpret_cast<const uint4 *>(bs_rec)[bs_begin + k];
+  const uint32_t walkers = C + nbs;
+  for (uint32_t base = (uint32_t)w * kWave; base < walkers; base += (uint32_t)THREADS) {
+    const uint32_t q = base + (uint32_t)lane;
+    if (q >= walkers) continue;
     Walker<DM1> y;
-    y.klo = yr.x;
-    y.khi = yr.y;
-    y.rid = yr.z;
-    y.upd = yr.z < n;
-    y.after_key = 0u;  // every lower endpoint of the bucket comes after it
-    y.q = DM1 > 0 ? walker_word<DM1>(yr.w) : 0u;
-    const uint32_t fh = fine_of(decode_coord(y.khi), vmn, fscale);
-    const uint32_t other = y.upd ? kFine : 0u;
-    const uint32_t jA = bin_begin(other);
-    walk<DM1, MODE>(KLO, RID, Q, y, jA, jA, bin_begin(other + fh), BIN[other + fh], hits, o);
+    uint32_t jA, jB;
+    if (q < C) {  // a region of the bucket, from its own bin
+      y.klo = KLO[q];
+      y.khi = KHI[q];
+      y.rid = RID[q];
+      y.upd = q < Cu;
+      y.after_key = y.upd ? y.klo : y.klo + 1u;
+      y.q = DM1 > 0 ? walker_from_entry<DM1>(Q[q]) : 0u;
+      const uint32_t fl = fine_of(decode_coord(y.klo), vmn, fscale, FINE);
+      const uint32_t other = y.upd ? (uint32_t)FINE : 0u;
+      jA = bin_begin(other + fl);
+      jB = BIN[other + fl];
+    } else {  // a boundary-state region: every lower endpoint of the bucket comes after it
+      const uint4 yr = reinterpret_cast<const uint4 *>(bs_rec)[bs_begin + (q - C)];
+      y.klo = yr.x;
+      y.khi = yr.y;
+      y.rid = yr.z;
+      y.upd = yr.z < n;
+      y.after_key = 0u;
+      y.q = DM1 > 0 ? walker_word<DM1>(yr.w) : 0u;
+      jA = jB = bin_begin(y.upd ? (uint32_t)FINE : 0u);
+    }
+    const uint32_t fh = fine_of(decode_coord(y.khi), vmn, fscale, FINE);
+    const uint32_t last = (y.upd ? (uint32_t)FINE : 0u) + fh;
+    walk<DM1, MODE>(KLO, RID, Q, y, jA, jB, bin_begin(last), BIN[last], hits, o);
   }
   if (DM1 > 0) {  // 4. the exact test of the queued pairs, all at once
     __syncthreads();
@@ -1062,12 +1064,16 @@ void sweep_impl(const BucketArgs &a, int32_t *per_update, const unsigned long lo
                 hipStream_t s, const uint32_t *gate) {
   const BucketLayout &L = *a.L;
   Ptrs p = pointers(a);
-  if (L.tune.sweep_threads == 256)
-    bk_sweep_kernel<DM1, MODE, kCap, 256><<<L.nb, 256, 0, s>>>(
+  if (L.tune.sweep_threads == 1024)
+    bk_sweep_kernel<DM1, MODE, kBigCap, 1024, 1024><<<L.nb, 1024, 0, s>>>(
+        p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
+        out_u, out_s, total, a.inst_total, gate);
+  else if (L.tune.sweep_threads == 256)
+    bk_sweep_kernel<DM1, MODE, kCap, 256, 512><<<L.nb, 256, 0, s>>>(
         p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
         out_u, out_s, total, a.inst_total, gate);
   else
-    bk_sweep_kernel<DM1, MODE, kCap, 512><<<L.nb, 512, 0, s>>>(
+    bk_sweep_kernel<DM1, MODE, kCap, 512, 512><<<L.nb, 512, 0, s>>>(
         p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
         out_u, out_s, total, a.inst_total, gate);
 }
@@ -1110,8 +1116,8 @@ bool plan_instance(const InstSpec &sp, int64_t u0, int64_t s0, const BucketTunin
 
 bool bucket_path_supported(int d, const InstSpec *inst, int64_t B, const BucketTuning &t) {
   if (d < 1 || d > 3 || B < 1) return false;
-  if (t.target < 64 || t.target > kBucketCap * 3 / 4) return false;
-  if (t.sweep_threads != 256 && t.sweep_threads != 512) return false;
+  if (t.target < 64 || t.target > bucket_cap(t) * 3 / 4) return false;
+  if (t.sweep_threads != 256 && t.sweep_threads != 512 && t.sweep_threads != 1024) return false;
   if (t.groups_per_thread < 1 || t.max_blocks < 1) return false;
   uint64_t cells = 0, nb = 0, N = 0;
   for (int64_t i = 0; i < B; ++i) {

@@ -175,11 +175,11 @@ def test_tunings_agree(ddm, oracle):
     refs = _oracle_all(oracle, insts)
     K = sum(r[0] for r in refs)
     batch, _ = _device_batch(ddm, insts, "pairs", cap=K + 1)
-    for target in (64, 768, 1536):
-        for threads in (256, 512):
-            t = ddm.Tuning(target, threads, 2, 3)
-            _note(f"tuning {t.as_dict()}")
-            _check(batch, insts, refs, "pairs", batch.run(tuning=t))
+    for target, threads in ((64, 256), (768, 512), (1536, 256), (1536, 512), (1024, 1024),
+                            (3072, 1024)):
+        t = ddm.Tuning(target, threads, 2, 3)
+        _note(f"tuning {t.as_dict()}")
+        _check(batch, insts, refs, "pairs", batch.run(tuning=t))
     best, ms = batch.autotune()
     assert best.sweep_threads in (256, 512) and ms > 0
     _check(batch, insts, refs, "pairs", batch.run(tuning=best))
