@@ -13,6 +13,9 @@
 // Both produce identical results; ddm_set_path() can force one of them.
 #include <string.h>
 
+#include <mutex>
+#include <vector>
+
 #include "../../include/ddm.h"
 #include "bucket_path.h"
 #include "common.h"
@@ -296,6 +299,96 @@ int run_global(const Call &c) {
   });
 }
 
+// ------------------------------------------------- repeated single calls
+//
+// A count or per-update call on the bucketed path needs no host decision
+// between its launches, so when the same call (same pointers, sizes, mode and
+// workspace) comes again, its launches are captured once into a HIP graph and
+// replayed by one launch; the header reaches the host through page-locked
+// memory.  Captured on the second sighting of a call, so one-off calls pay
+// nothing; a small LRU bounds the cache.  Profiling, pair mode and forced
+// device-wide calls run eagerly.
+struct GraphKey {
+  const float *ulo, *uhi, *slo, *shi;
+  int64_t n, m;
+  int d, mode;
+  void *ws;
+  size_t ws_bytes;
+  int32_t *per_update;
+  bool same(const GraphKey &o) const {
+    return ulo == o.ulo && uhi == o.uhi && slo == o.slo && shi == o.shi && n == o.n &&
+           m == o.m && d == o.d && mode == o.mode && ws == o.ws && ws_bytes == o.ws_bytes &&
+           per_update == o.per_update;
+  }
+};
+
+struct CachedGraph {
+  GraphKey key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  Header *hdr_host = nullptr;  // page-locked
+  uint64_t used = 0;
+  bool captured = false, failed = false;
+};
+
+constexpr size_t kGraphCache = 8;
+std::mutex g_graph_mu;
+std::vector<CachedGraph> g_graphs;
+uint64_t g_graph_tick = 0;
+
+void release(CachedGraph &e) {
+  if (e.exec) (void)hipGraphExecDestroy(e.exec);
+  if (e.graph) (void)hipGraphDestroy(e.graph);
+  if (e.hdr_host) (void)hipHostFree(e.hdr_host);
+  e.exec = nullptr;
+  e.graph = nullptr;
+  e.hdr_host = nullptr;
+  e.captured = false;
+}
+
+// Captures the bucketed count / per-update launches of call c.
+bool capture(CachedGraph &e, const Call &c) {
+  if (hipHostMalloc(reinterpret_cast<void **>(&e.hdr_host), sizeof(Header), hipHostMallocDefault) !=
+      hipSuccess)
+    return false;
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return false;
+  BucketArgs a{};
+  a.d = c.d;
+  a.ws = at<void>(c.ws, c.L.region);
+  a.L = &c.L.B;
+  a.hdr = c.hdr;
+  a.zero = c.mode != DDM_COUNT && c.n > 0 ? c.cnt : nullptr;
+  a.zero_count = (uint32_t)c.n;
+  bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    bool enq = bucket_prepare(a, cs) == hipSuccess;
+    enq = enq && bucket_sweep(a, c.mode == DDM_COUNT ? 0 : 1, c.cnt, nullptr, nullptr, nullptr,
+                              nullptr, &c.hdr->total, cs) == hipSuccess;
+    enq = enq && hipMemcpyAsync(e.hdr_host, c.hdr, sizeof(Header), hipMemcpyDeviceToHost, cs) ==
+                     hipSuccess;
+    hipGraph_t g = nullptr;
+    ok = hipStreamEndCapture(cs, &g) == hipSuccess && enq;
+    e.graph = g;
+    ok = ok && hipGraphInstantiate(&e.exec, g, nullptr, nullptr, 0) == hipSuccess;
+  }
+  (void)hipStreamDestroy(cs);
+  e.captured = ok;
+  return ok;
+}
+
+// Replays a captured call: DDM_OK, DDM_E_INVAL, DDM_E_DEVICE or kFallback.
+int replay(const CachedGraph &e, hipStream_t s, uint64_t *count_host) {
+  DDM_HIP(hipGraphLaunch(e.exec, s));
+  DDM_HIP(hipStreamSynchronize(s));
+  Header h;
+  memcpy(&h, e.hdr_host, sizeof(Header));  // written by the graph's copy, complete after the sync
+  if (h.err) return DDM_E_INVAL;
+  if (h.pad[0]) return kFallback;
+  *count_host = h.total;
+  return DDM_OK;
+}
+
 }  // namespace
 }  // namespace ddm
 
@@ -337,6 +430,44 @@ extern "C" int ddm_match(const float *upd_lo, const float *upd_hi, int64_t n, co
   if ((n > 0 && (!upd_lo || !upd_hi)) || (m > 0 && (!sub_lo || !sub_hi))) return DDM_E_INVAL;
   if (mode == DDM_PER_UPDATE && n > 0 && !per_update) return DDM_E_INVAL;
   if (mode == DDM_PAIRS && pair_capacity > 0 && !pairs) return DDM_E_INVAL;
+  const bool graphable = mode != DDM_PAIRS && n + m > 0 && !prof::enabled() &&
+                         g_path_request != DDM_PATH_GLOBAL && workspace &&
+                         !(reinterpret_cast<uintptr_t>(workspace) & 255);
+  const GraphKey key{upd_lo, upd_hi, sub_lo, sub_hi, n, m, d, mode, workspace, ws_bytes,
+                     mode == DDM_COUNT ? nullptr : per_update};
+  std::unique_lock<std::mutex> cache_lock(g_graph_mu, std::defer_lock);
+  CachedGraph *entry = nullptr;
+  if (graphable) {
+    cache_lock.lock();
+    for (CachedGraph &e : g_graphs)
+      if (e.key.same(key)) entry = &e;
+    if (entry && entry->captured) {
+      entry->used = ++g_graph_tick;
+      *count_host = 0;
+      const int rc = replay(*entry, static_cast<hipStream_t>(stream), count_host);
+      if (rc != kFallback) {
+        g_last_path = rc == DDM_OK ? DDM_PATH_BUCKETED : 0;
+        return rc;
+      }
+      if (g_path_request == DDM_PATH_BUCKETED) return DDM_E_UNSUPPORTED;
+      entry = nullptr;  // the device-wide path below
+    } else if (!entry) {  // first sighting: remember the call, run it eagerly
+      if (g_graphs.size() >= kGraphCache) {
+        size_t old = 0;
+        for (size_t i = 1; i < g_graphs.size(); ++i)
+          if (g_graphs[i].used < g_graphs[old].used) old = i;
+        release(g_graphs[old]);
+        g_graphs.erase(g_graphs.begin() + (std::ptrdiff_t)old);
+      }
+      g_graphs.push_back(CachedGraph{});
+      g_graphs.back().key = key;
+      g_graphs.back().used = ++g_graph_tick;
+    } else if (entry->failed) {
+      entry = nullptr;
+    }
+    // else: second sighting, captured below once the call is laid out
+    if (!entry) cache_lock.unlock();  // an eager call needs no cache entry
+  }
   Call c{};
   c.L = make_layout(n, m, d, mode, pair_capacity, upd_lo, upd_hi, sub_lo, sub_hi);
   if (!workspace || ws_bytes < c.L.total) return DDM_E_WORKSPACE;
@@ -367,6 +498,23 @@ extern "C" int ddm_match(const float *upd_lo, const float *upd_hi, int64_t n, co
   }
   if (g_path_request == DDM_PATH_BUCKETED && !c.L.bucket_ok) return DDM_E_UNSUPPORTED;
   int rc;
+  if (entry && c.L.bucket_ok) {  // second sighting of a repeated call: capture and replay
+    entry->used = ++g_graph_tick;
+    if (capture(*entry, c)) {
+      rc = replay(*entry, c.s, count_host);
+      if (rc != kFallback) {
+        if (rc == DDM_OK) g_last_path = DDM_PATH_BUCKETED;
+        return rc;
+      }
+      if (g_path_request == DDM_PATH_BUCKETED) return DDM_E_UNSUPPORTED;
+      rc = run_global(c);
+      if (rc == DDM_OK || rc == DDM_E_CAPACITY) g_last_path = DDM_PATH_GLOBAL;
+      return rc;
+    }
+    release(*entry);
+    entry->failed = true;  // run eagerly from now on
+    (void)hipGetLastError();
+  }
   if (g_path_request != DDM_PATH_GLOBAL && c.L.bucket_ok) {
     rc = run_bucketed(c);
     if (rc != kFallback) {

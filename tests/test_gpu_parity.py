@@ -277,3 +277,31 @@ def test_skewed_distribution(ddm, oracle):
         hi = (lo + side).astype(np.float32)
         inst = W.Instance(lo[:n], hi[:n], lo[n:], hi[n:], float("nan"), f"loguniform_d{d}")
         check_all_modes(ddm, oracle, inst, expect_bucketed=False)
+
+
+@pytest.mark.parametrize("mode", ["count", "per_update"])
+def test_repeated_call_replays_graph(ddm, oracle, mode):
+    """Identical repeated calls are captured once and replayed: every replay
+    reads the current contents of the same buffers, including contents that
+    overflow a bucket (replay falls back to the device-wide path)."""
+    n, m, d = 20_000, 18_000, 3
+    g = [torch.empty((k, d), dtype=torch.float32, device="cuda") for k in (n, n, m, m)]
+    ws = torch.empty(ddm.workspace_bytes(n, m, d, mode), dtype=torch.uint8, device="cuda")
+    per = torch.empty(n, dtype=torch.int32, device="cuda")
+    cases = [W.uniform_instance(n, m, d, 50.0, seed=s) for s in range(3)]
+    lo = np.zeros((n, d), np.float32)
+    hi = np.ones((n, d), np.float32)
+    cases.append(W.Instance(lo, hi, lo[:m].copy(), hi[:m].copy(), float("nan"), "identical"))
+    cases += [W.correlated_d3(n, 20.0, seed=5), W.uniform_instance(n, m, d, 5.0, seed=9)]
+    cases[4] = W.Instance(cases[4].upd_lo, cases[4].upd_hi, cases[4].sub_lo[:m], cases[4].sub_hi[:m],
+                          cases[4].alpha, "correlated")
+    for rep, inst in enumerate(cases + cases[:2]):
+        for dst, src in zip(g, (inst.upd_lo, inst.upd_hi, inst.sub_lo, inst.sub_hi)):
+            dst.copy_(torch.from_numpy(np.ascontiguousarray(src)))
+        k_ref, per_ref, _ = oracle.sbm(inst.upd_lo, inst.upd_hi, inst.sub_lo, inst.sub_hi,
+                                       pairs=False)
+        _note(f"replay {rep} {inst.name} mode={mode}")
+        k = ddm.match_into(*g, mode=mode, workspace=ws, per_update=per if mode == "per_update" else None)
+        assert k == k_ref, (rep, inst.name)
+        if mode == "per_update":
+            assert np.array_equal(per.cpu().numpy(), per_ref), (rep, inst.name)
