@@ -28,7 +28,7 @@ struct BucketTuning {
   uint32_t target = 1536;         // mean records per bucket (at most 3/4 of the capacity)
   uint32_t sweep_threads = 512;   // 256, 512 or 1024 threads per sweep workgroup
   uint32_t groups_per_thread = 1; // count/scatter: groups of four rows per thread (minimum)
-  uint32_t max_blocks = 512;      // count/scatter blocks per instance at most
+  uint32_t max_blocks = 256;      // count/scatter blocks per instance at most
 };
 
 // Records per bucket the sweep holds in LDS: kBucketCap for sweep

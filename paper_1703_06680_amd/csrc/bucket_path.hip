@@ -278,9 +278,14 @@ __device__ BucketParams block_plan(const float *__restrict__ part, const InstPla
     q.scale = 0.f;
     q.valid = 0;
     if (c > 0.f && v[1] > v[0] && I.nb > 0) {
-      const float scale = (float)I.nb / (v[1] - v[0]);
-      if (scale > 0.f && scale <= 3.0e38f) {
-        q.vmin = v[0];
+      // the sample's extremes lie about (max - min) / c inside the true ones;
+      // widening the map by two such gaps keeps the regions beyond them from
+      // piling into the first and last bucket
+      const float gap = 2.0f * (v[1] - v[0]) / c;
+      const float lo = v[0] - gap, hi = v[1] + gap;
+      const float scale = (float)I.nb / (hi - lo);
+      if (scale > 0.f && scale <= 3.0e38f && lo > -3.0e38f && hi < 3.0e38f) {
+        q.vmin = lo;
         q.scale = scale;
         q.valid = 1;
       }
