@@ -101,6 +101,21 @@ int ddm_match(const float *upd_lo, const float *upd_hi, int64_t n,
               uint64_t *count_host, int32_t *per_update,
               int32_t *pairs, int64_t pair_capacity);
 
+/*
+ * Per-axis 1-D candidate counts (diagnostic).  counts_host[k] (host, [d])
+ * receives K_1D(k): the number of (update, subscription) pairs whose
+ * intervals on axis k intersect, counted among the boxes that are non-empty
+ * on every axis -- the pairs a sweep along axis k would examine before the
+ * other axes filter them (Sec. 3, the reduction of d axes to one after
+ * Algorithm 1; the d = 1 count of Algorithm 4 on each axis).  Arguments as
+ * for ddm_match(); the workspace is ddm_dim_counts_workspace_bytes() bytes.
+ * Synchronises with the stream.  Errors as ddm_match() in DDM_COUNT mode.
+ */
+size_t ddm_dim_counts_workspace_bytes(int64_t n, int64_t m, int d);
+int ddm_dim_counts(const float *upd_lo, const float *upd_hi, int64_t n,
+                   const float *sub_lo, const float *sub_hi, int64_t m, int d,
+                   void *workspace, size_t ws_bytes, void *stream, uint64_t *counts_host);
+
 /* ------------------------------------------------------------------------
  * Batches of independent instances.
  *

@@ -331,7 +331,7 @@ struct CachedGraph {
   bool captured = false, failed = false;
 };
 
-constexpr size_t kGraphCache = 8;
+constexpr size_t kGraphCache = 64;
 std::mutex g_graph_mu;
 std::vector<CachedGraph> g_graphs;
 uint64_t g_graph_tick = 0;

@@ -604,7 +604,7 @@ extern "C" int ddm_batch_graph_create(const float *upd_lo, const float *upd_hi,
     }
     prof::swap_enabled(was);
   }
-  hipStreamDestroy(cs);
+  (void)hipStreamDestroy(cs);
   if (rc != DDM_OK) {
     ddm_batch_graph_destroy(g);
     return rc;
@@ -696,8 +696,8 @@ extern "C" int ddm_batch_autotune(const float *upd_lo, const float *upd_hi,
       *best = cand;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (rc != DDM_OK) return rc;
   if (!have_best) return DDM_E_UNSUPPORTED;
   if (best_ms) *best_ms = best_t;

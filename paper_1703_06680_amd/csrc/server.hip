@@ -129,11 +129,11 @@ struct ddm_server {
 namespace {
 
 void free_slot(Slot &s) {
-  if (s.stream) hipStreamDestroy(s.stream);
-  if (s.done) hipEventDestroy(s.done);
-  if (s.counts_dev) hipFree(s.counts_dev);
-  if (s.counts_host) hipHostFree(s.counts_host);
-  if (s.staging) hipHostFree(s.staging);
+  if (s.stream) (void)hipStreamDestroy(s.stream);
+  if (s.done) (void)hipEventDestroy(s.done);
+  if (s.counts_dev) (void)hipFree(s.counts_dev);
+  if (s.counts_host) (void)hipHostFree(s.counts_host);
+  if (s.staging) (void)hipHostFree(s.staging);
   s = Slot{};
 }
 
@@ -379,7 +379,7 @@ extern "C" int ddm_server_run(ddm_server *sv, const int32_t *sim, const double *
         if (e != DDM_OK) {
           // nothing usable was enqueued for this group: finish it as failed
           fail(e);
-          hipStreamSynchronize(s.stream);
+          (void)hipStreamSynchronize(s.stream);
           const double now = seconds_since(t0, Clock::now());
           for (int64_t r : group) {
             counts[r] = 0;
@@ -421,7 +421,7 @@ extern "C" int ddm_server_run(ddm_server *sv, const int32_t *sim, const double *
 extern "C" int ddm_server_destroy(ddm_server *sv) {
   if (!sv) return DDM_OK;
   for (Slot &s : sv->slots) {
-    if (s.stream) hipStreamSynchronize(s.stream);
+    if (s.stream) (void)hipStreamSynchronize(s.stream);
     free_slot(s);
   }
   delete sv;

@@ -73,6 +73,11 @@ def library() -> ctypes.CDLL:
         lib.ddm_profile_report.restype = ctypes.c_int
         tp = ctypes.POINTER(Tuning)
         u64p = ctypes.POINTER(ctypes.c_uint64)
+        lib.ddm_dim_counts_workspace_bytes.argtypes = [i64, i64, ctypes.c_int]
+        lib.ddm_dim_counts_workspace_bytes.restype = ctypes.c_size_t
+        lib.ddm_dim_counts.argtypes = [vp, vp, i64, vp, vp, i64, ctypes.c_int, vp, ctypes.c_size_t,
+                                       vp, vp]
+        lib.ddm_dim_counts.restype = ctypes.c_int
         lib.ddm_default_tuning.argtypes = [tp]
         lib.ddm_default_tuning.restype = None
         lib.ddm_batch_workspace_bytes.argtypes = [vp, vp, i64, ctypes.c_int, ctypes.c_int, i64, tp]
@@ -240,6 +245,29 @@ def match(upd_lo, upd_hi, sub_lo, sub_hi, mode: str = "count", *, pair_capacity:
                 raise DDMError(rc)
             k = int(cnt.value)
             return k, out[:k], (per[:n] if per is not None else None)
+
+
+def dim_counts(upd_lo, upd_hi, sub_lo, sub_hi, stream=None):
+    """Per-axis 1-D candidate counts K_1D(k), k = 0 .. d-1 (``ddm_dim_counts``)."""
+    import numpy as np
+    _check_boxes(upd_lo, upd_hi, "updates")
+    _check_boxes(sub_lo, sub_hi, "subscriptions")
+    n, d = upd_lo.shape
+    m = sub_lo.shape[0]
+    lib = library()
+    if stream is None:
+        stream = torch.cuda.current_stream(upd_lo.device)
+    ws = torch.empty(max(lib.ddm_dim_counts_workspace_bytes(n, m, d), 256), dtype=torch.uint8,
+                     device=upd_lo.device)
+    out = np.zeros(d, dtype=np.uint64)
+    with torch.cuda.device(upd_lo.device):
+        rc = lib.ddm_dim_counts(_ptr(upd_lo), _ptr(upd_hi), n, _ptr(sub_lo), _ptr(sub_hi), m, d,
+                                ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                ctypes.c_void_p(stream.cuda_stream),
+                                ctypes.c_void_p(out.ctypes.data))
+    if rc != DDM_OK:
+        raise DDMError(rc, "ddm_dim_counts")
+    return [int(x) for x in out]
 
 
 # --------------------------------------------------------------- batches

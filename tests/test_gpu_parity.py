@@ -305,3 +305,18 @@ def test_repeated_call_replays_graph(ddm, oracle, mode):
         assert k == k_ref, (rep, inst.name)
         if mode == "per_update":
             assert np.array_equal(per.cpu().numpy(), per_ref), (rep, inst.name)
+
+
+@pytest.mark.parametrize("inst_fn", [
+    lambda: W.uniform_instance(300_000, 250_000, 3, 30.0, seed=4),
+    lambda: W.tie_heavy(20_000, 15_000, 2, grid=300, max_len=12, seed=6),
+    lambda: W.random_float_boxes(5000, 4000, 4, seed=8, extent=300.0),
+])
+def test_dim_counts_equal_closed_form(ddm, inst_fn):
+    """K_1D of every axis equals the oracle's closed form summed over updates."""
+    inst = inst_fn()
+    g = _dev(inst)
+    got = ddm.dim_counts(*g)
+    want = [int(O.closed_form_1d(*_host(inst), axis=k).sum()) for k in range(inst.d)]
+    _note(f"dim counts {inst.name}: {got}")
+    assert got == want
