@@ -175,6 +175,8 @@ def bench_served(args, ddm, W, torch, np):
     serve("plain", ids_sat[:64], np.zeros(64))  # warm-up
     _, _, _, st = serve("plain", ids_sat, np.zeros(R))
     sat_qps = R / st["wall_s"]
+    _, _, _, stb = serve("batched", ids_sat, np.zeros(R))
+    sat_batched = R / stb["wall_s"]
     levels = {}
     for frac in (0.5, 0.8, 1.0, 1.2):
         ids, arr = W.poisson_arrivals(R, frac * sat_qps, seed=int(frac * 10), sims=32)
@@ -197,7 +199,11 @@ def bench_served(args, ddm, W, torch, np):
         "workload": "32 resident d=2 simulations, n=m log-uniform on [1e4, 2e6] "
                     f"(sum N = {int(sizes.sum())}), alpha=1, random walk sigma=0.1*side, "
                     f"{R} Poisson requests per level, count mode",
-        "plain_saturation_qps": round(sat_qps, 1), "budget_gib": args.serve_budget_gib,
+        "plain_saturation_qps": round(sat_qps, 1),
+        "batched_saturation_qps": round(sat_batched, 1),
+        "saturation_regions_per_s": {"plain": round(float(sizes[ids_sat].sum()) / st["wall_s"], 1),
+                                     "batched": round(float(sizes[ids_sat].sum()) / stb["wall_s"], 1)},
+        "budget_gib": args.serve_budget_gib,
         "slots": args.serve_slots, "max_batch": args.serve_max_batch, "levels": levels,
     }
 

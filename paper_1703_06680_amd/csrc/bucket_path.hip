@@ -762,10 +762,10 @@ __device__ __forceinline__ uint32_t min4(uint32_t a, uint32_t b, uint32_t c, uin
 // (KLO >= after_key), entries in [jC, jD) (the last fine bin) must start
 // before its upper endpoint (KLO < khi); entries of the bins in between
 // satisfy both by the monotonicity of the fine-bin map.  The edge loop tests
-// keys and covers the first bin up to a multiple of four and the last bin
-// back to one; the interior loop reads four aligned entry words at a time and
-// runs only the pre-filter (skipping a chunk with one compare when none of
-// the four passes).
+// keys on the first and last bin; the interior loop reads four aligned entry
+// words at a time, masks the ones outside the interior and runs only the
+// pre-filter (skipping a chunk with one compare when none of the four
+// passes).
 template <int DM1, int MODE>
 __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
                                      const uint32_t *__restrict__ RID,
@@ -775,41 +775,54 @@ __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
   uint32_t own = 0;
   bool have_y = false;
   float ylo[2] = {0.f, 0.f}, yhi[2] = {0.f, 0.f};
-  // interior [a, b): multiples of four inside [jB, jC) (empty if first and
-  // last bin coincide, jC <= jB)
-  uint32_t a = jD, b = jD;
-  if (jC > jB) {
-    a = min((jB + 3u) & ~3u, jC);
-    b = max(jC & ~3u, a);
-  }
-  // edge entries [jA, a) and [b, jD), with key tests
-  const uint32_t e1 = a - jA;
-  const uint32_t e = e1 + (jD - b);
+  // the first bin [jA, jB) and, if it is another one, the last bin
+  // [jC, jD) are the edge entries, with key tests; the bins between,
+  // [jB, jC), need the pre-filter alone and are read in aligned chunks of
+  // four whose entries outside the range are masked off
+  const bool split = jC > jB;
+  const uint32_t e1 = (split ? jB : jD) - jA;
+  const uint32_t e = e1 + (split ? jD - jC : 0u);
   for (uint32_t t = 0; t < e; ++t) {
-    const uint32_t j = t < e1 ? jA + t : b + (t - e1);
+    const uint32_t j = t < e1 ? jA + t : jC + (t - e1);
     const uint32_t k = KLO[j];
     if (k >= y.after_key && k < y.khi && qpass<DM1>(Q, j, y))
       visit<DM1, MODE>(y, have_y, ylo, yhi, j, RID, hits, own, o);
   }
-  // interior: every entry satisfies the key tests
-  if (DM1 == 0) {
+  if (!split) {
+    // first and last bin coincide: the edge loop has seen every entry
+  } else if (DM1 == 0) {
     if (MODE == 0) {
-      hits += b - a;
+      hits += jC - jB;
     } else {
-      for (uint32_t j = a; j < b; ++j) visit<DM1, MODE>(y, have_y, ylo, yhi, j, RID, hits, own, o);
+      for (uint32_t j = jB; j < jC; ++j) visit<DM1, MODE>(y, have_y, ylo, yhi, j, RID, hits, own, o);
     }
   } else {
-    for (uint32_t j = a; j < b; j += 4) {
+    // one aligned chunk of four: entries outside [jB, jC) get a non-zero
+    // fail value when ``masked``
+    auto chunk = [&](uint32_t j, bool masked) {
       const uint4 q4 = reinterpret_cast<const uint4 *>(Q)[j >> 2];
-      const uint32_t f0 = qfail<DM1>(q4.x, y.q), f1 = qfail<DM1>(q4.y, y.q);
-      const uint32_t f2 = qfail<DM1>(q4.z, y.q), f3 = qfail<DM1>(q4.w, y.q);
+      uint32_t f0 = qfail<DM1>(q4.x, y.q), f1 = qfail<DM1>(q4.y, y.q);
+      uint32_t f2 = qfail<DM1>(q4.z, y.q), f3 = qfail<DM1>(q4.w, y.q);
+      if (masked) {
+        f0 |= (j < jB || j >= jC) ? 1u : 0u;
+        f1 |= (j + 1 < jB || j + 1 >= jC) ? 1u : 0u;
+        f2 |= (j + 2 < jB || j + 2 >= jC) ? 1u : 0u;
+        f3 |= (j + 3 < jB || j + 3 >= jC) ? 1u : 0u;
+      }
       if (min4(f0, f1, f2, f3) == 0u) {
         if (f0 == 0u) visit<DM1, MODE>(y, have_y, ylo, yhi, j, RID, hits, own, o);
         if (f1 == 0u) visit<DM1, MODE>(y, have_y, ylo, yhi, j + 1, RID, hits, own, o);
         if (f2 == 0u) visit<DM1, MODE>(y, have_y, ylo, yhi, j + 2, RID, hits, own, o);
         if (f3 == 0u) visit<DM1, MODE>(y, have_y, ylo, yhi, j + 3, RID, hits, own, o);
       }
+    };
+    uint32_t j = jB & ~3u;
+    if (j != jB || j + 4 > jC) {  // head chunk (partial)
+      chunk(j, true);
+      j += 4;
     }
+    for (; j + 4 <= jC; j += 4) chunk(j, false);
+    if (j < jC) chunk(j, true);  // tail chunk (partial)
   }
   if (MODE == 1 && own) atomicAdd(&o.per_update[y.rid], (int)own);
 }

@@ -227,3 +227,23 @@ def test_same_arrays_for_both_kinds(ddm, oracle):
     batch = ddm.Batch(lo, hi, off, lo, hi, off, mode="pairs", pair_capacity=k + 1)
     assert batch.run() == k
     assert np.array_equal(batch.instance_pairs(0).cpu().numpy(), pairs)
+
+
+def test_batched_invalid_input(ddm):
+    """A NaN or lo > hi in any instance makes the batch fail with DDM_E_INVAL,
+    in a plain call and after a graph replay."""
+    insts = _mixed(2, seed=13)
+    insts[5].sub_lo[3, 1] = np.float32("nan")
+    batch, _ = _device_batch(ddm, insts, "count")
+    with pytest.raises(ddm.DDMError) as e:
+        batch.run()
+    assert e.value.code == ddm.DDM_E_INVAL
+    insts = _mixed(2, seed=14)
+    insts[7].upd_lo[2, 0] = insts[7].upd_hi[2, 0] + 1.0
+    batch, _ = _device_batch(ddm, insts, "per_update")
+    graph = batch.graph()
+    graph.launch()
+    with pytest.raises(ddm.DDMError) as e:
+        graph.result()
+    assert e.value.code == ddm.DDM_E_INVAL
+    graph.close()

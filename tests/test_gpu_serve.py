@@ -141,3 +141,21 @@ def test_server_rejects_bad_requests(ddm):
         small.add_sim(*_upload(inst), 1.0, 0.1, 1)
     assert e.value.code == ddm.DDM_E_WORKSPACE
     small.close()
+
+
+def test_served_d3_and_invalid_state(ddm, oracle):
+    """d = 3 simulations are served exactly; a simulation whose state holds a
+    NaN makes its request fail with DDM_E_INVAL while the others still
+    count."""
+    sims = W.serving_sims(3, d=3, seed=12, lo=2_000, hi=9_000)
+    expected = [_expected_counts(oracle, *s, 2) for s in sims]
+    sv, states = _server(ddm, sims, max_batch=3)
+    ids = np.array([0, 1, 2, 0, 1, 2], np.int32)
+    counts, steps, _, _ = sv.run(ids, np.zeros(6))
+    for i in range(6):
+        assert int(counts[i]) == expected[ids[i]][int(steps[i])]
+    states[1][0][7, 2] = float("nan")  # poison simulation 1
+    with pytest.raises(ddm.DDMError) as e:
+        sv.run(np.array([1], np.int32), np.zeros(1))
+    assert e.value.code == ddm.DDM_E_INVAL
+    sv.close()
