@@ -259,8 +259,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py: this library runs on exactly one GPU (asked for --gpus {args.gpus}); "
+              "sharding across GPUs is designed but not built.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
