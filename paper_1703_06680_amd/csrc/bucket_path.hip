@@ -784,8 +784,10 @@ __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
   const uint32_t e = e1 + (split ? jD - jC : 0u);
   for (uint32_t t = 0; t < e; ++t) {
     const uint32_t j = t < e1 ? jA + t : jC + (t - e1);
+    // both LDS reads issued before either is needed
     const uint32_t k = KLO[j];
-    if (k >= y.after_key && k < y.khi && qpass<DM1>(Q, j, y))
+    const uint32_t fail = DM1 > 0 ? qfail<DM1>(Q[j], y.q) : 0u;
+    if ((k >= y.after_key) & (k < y.khi) & (fail == 0u))
       visit<DM1, MODE>(y, have_y, ylo, yhi, j, RID, hits, own, o);
   }
   if (!split) {
@@ -820,6 +822,18 @@ __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
     if (j != jB || j + 4 > jC) {  // head chunk (partial)
       chunk(j, true);
       j += 4;
+    }
+    for (; j + 8 <= jC; j += 8) {  // two chunks per step: both reads in flight
+      const uint4 qa = reinterpret_cast<const uint4 *>(Q)[j >> 2];
+      const uint4 qb = reinterpret_cast<const uint4 *>(Q)[(j >> 2) + 1];
+      const uint32_t f0 = qfail<DM1>(qa.x, y.q), f1 = qfail<DM1>(qa.y, y.q);
+      const uint32_t f2 = qfail<DM1>(qa.z, y.q), f3 = qfail<DM1>(qa.w, y.q);
+      const uint32_t f4 = qfail<DM1>(qb.x, y.q), f5 = qfail<DM1>(qb.y, y.q);
+      const uint32_t f6 = qfail<DM1>(qb.z, y.q), f7 = qfail<DM1>(qb.w, y.q);
+      if (min(min4(f0, f1, f2, f3), min4(f4, f5, f6, f7)) == 0u) {
+        chunk(j, false);
+        chunk(j + 4, false);
+      }
     }
     for (; j + 4 <= jC; j += 4) chunk(j, false);
     if (j < jC) chunk(j, true);  // tail chunk (partial)
