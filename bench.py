@@ -248,6 +248,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the per-phase event timing (roofline becomes null)")
+    ap.add_argument("--no-closed", action="store_true",
+                    help="skip the closed-interval measurement of the headline workload")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched measurement")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-reps", type=int, default=5)
@@ -354,6 +356,35 @@ def main():
                                "matches": ke, "path": ddm.last_path()}
         del ge
 
+    closed = None
+    if not args.no_closed:
+        # the headline inputs as closed boxes [lo, hi]; checked against the
+        # half-open match of [lo, nextafter(hi)), which is the same set
+        def closed_step():
+            return ddm.match_into(*g, mode=args.mode, workspace=ws,
+                                  per_update=per if args.mode == "per_update" else None,
+                                  stream=stream, closed=True)
+        for _ in range(args.warmup):
+            closed_step()
+        torch.cuda.synchronize()
+        tcl = time.perf_counter()
+        for _ in range(args.steps):
+            kc = closed_step()
+        torch.cuda.synchronize()
+        dtc = (time.perf_counter() - tcl) / args.steps
+        path_c = ddm.last_path()
+        per_c = per.clone() if args.mode == "per_update" else None
+        inf = torch.tensor(float("inf"), device=dev)
+        up = [torch.nextafter(t, inf) for t in (g[1], g[3])]
+        kh = ddm.match(g[0], up[0], g[2], up[1], mode="count")
+        same = kh == kc
+        if args.mode == "per_update":
+            _, per_h = ddm.match(g[0], up[0], g[2], up[1], mode="per_update")
+            same = same and bool(torch.equal(per_h, per_c))
+        del up
+        closed = {"ms_per_step": round(dtc * 1e3, 4), "value": round(regions / dtc, 1),
+                  "matches": kc, "path": path_c, "equal_to_half_open_next_float": same}
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import oracle as O
@@ -398,6 +429,7 @@ def main():
         "cpu_baseline": cpu,
         "phases_ms_per_step": {p: round(v["ms"] / args.steps, 4) for p, v in sorted(phases.items())},
         "per_alpha": per_alpha,
+        "closed": closed,
         "served_p50_ms": served["levels"]["1x"]["batched"]["p50_ms"] if served else None,
         "served_p99_ms": served["levels"]["1x"]["batched"]["p99_ms"] if served else None,
         "batched": batched,

@@ -8,7 +8,10 @@
  * subscription regions S_j, each an axis-parallel box in d dimensions, report
  * every pair (i, j) whose boxes intersect.  Boxes are half-open on every axis,
  * [lo_k, hi_k), so boxes that only touch do not match, and a box with
- * lo_k == hi_k on some axis is empty and matches nothing.  The reduction of d
+ * lo_k == hi_k on some axis is empty and matches nothing -- unless the mode
+ * carries DDM_CLOSED (below): then boxes are closed, [lo_k, hi_k], as in the
+ * tests of Algorithm 1, touching boxes match and lo_k == hi_k is a point that
+ * matches every box containing it.  The reduction of d
  * axes to one (AND of the 1-D tests, Sec. 3 after Algorithm 1) and the
  * sort-then-sweep structure of Algorithm 4 are what the library computes.
  *
@@ -51,6 +54,12 @@ extern "C" {
 #define DDM_PER_UPDATE 1 /* total + per-update match counts                  */
 #define DDM_PAIRS 2      /* total + per-update counts (optional) + pair list  */
 
+/* Interval flag, OR-ed into the mode of ddm_workspace_bytes, ddm_match, the
+ * batched calls and the graph calls: closed boxes [lo_k, hi_k] on every axis
+ * (Algorithm 1's tests: lo <= hi' and lo' <= hi).  Without it boxes are
+ * half-open.  The serving runtime and ddm_dim_counts are half-open only. */
+#define DDM_CLOSED 16
+
 /* Limits: n + m must be below 2^31 (ids and sorted positions are 32-bit) and
  * 1 <= d <= DDM_MAX_DIMS. */
 #define DDM_MAX_DIMS 16
@@ -72,7 +81,8 @@ size_t ddm_workspace_bytes(int64_t n, int64_t m, int d, int mode, int64_t pair_c
  *   sub_lo, sub_hi  device, float32 [m][d] row-major, same layout
  *   n, m            number of update / subscription boxes (>= 0)
  *   d               number of axes (1 .. DDM_MAX_DIMS)
- *   mode            DDM_COUNT, DDM_PER_UPDATE or DDM_PAIRS
+ *   mode            DDM_COUNT, DDM_PER_UPDATE or DDM_PAIRS, optionally
+ *                   | DDM_CLOSED
  *   workspace       device, at least ddm_workspace_bytes(n, m, d, mode,
  *                   pair_capacity) bytes, 256-byte aligned; contents on entry
  *                   are ignored and on return undefined

@@ -25,7 +25,9 @@ Readings of the paper (see the header of ``sbm_oracle.c``): half-open
 intervals; ties upper-before-lower, then update-before-subscription, then id;
 empty regions (lo == hi on some axis) match nothing; NaN or lo > hi is an
 error; 0-based ids; pairs are (update id, subscription id) in lexicographic
-order.
+order.  ``closed=True`` selects the closed reading instead (Algorithm 1's
+tests as printed, lo <= hi' and lo' <= hi): no region is empty and ties sort
+lower-before-upper.
 """
 from __future__ import annotations
 
@@ -81,7 +83,8 @@ class Oracle:
         sig = [fp, fp, ctypes.c_int64, fp, fp, ctypes.c_int64, ctypes.c_int,
                ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int32),
                ctypes.POINTER(ctypes.c_int32), ctypes.c_int64]
-        for name in ("oracle_sbm", "oracle_bruteforce"):
+        for name in ("oracle_sbm", "oracle_bruteforce", "oracle_sbm_closed",
+                     "oracle_bruteforce_closed"):
             fn = getattr(self.lib, name)
             fn.argtypes = sig
             fn.restype = ctypes.c_int
@@ -127,14 +130,17 @@ class Oracle:
             return k, (per[:n].copy() if per_update else None), buf[:k].copy()
 
     def sbm(self, ulo, uhi, slo, shi, pairs: bool = True, per_update: bool = True,
-            capacity: int | None = None):
+            capacity: int | None = None, closed: bool = False):
         """Algorithm 4 + per-axis AND.  Returns (count, per_update[n] int32,
-        pairs[K,2] int32 or None)."""
-        return self._run("oracle_sbm", ulo, uhi, slo, shi, pairs, per_update, capacity)
+        pairs[K,2] int32 or None).  ``closed``: closed intervals."""
+        name = "oracle_sbm_closed" if closed else "oracle_sbm"
+        return self._run(name, ulo, uhi, slo, shi, pairs, per_update, capacity)
 
-    def bruteforce(self, ulo, uhi, slo, shi, pairs: bool = True, per_update: bool = True):
+    def bruteforce(self, ulo, uhi, slo, shi, pairs: bool = True, per_update: bool = True,
+                   closed: bool = False):
         """Algorithm 2 over d axes.  Same return convention as ``sbm``."""
-        return self._run("oracle_bruteforce", ulo, uhi, slo, shi, pairs, per_update)
+        name = "oracle_bruteforce_closed" if closed else "oracle_bruteforce"
+        return self._run(name, ulo, uhi, slo, shi, pairs, per_update)
 
     def sweep_state(self, ulo, uhi, slo, shi, cuts):
         """Serial SubSet/UpdSet of Algorithm 4 after ``cuts[c]`` endpoints of
@@ -173,14 +179,14 @@ def default() -> Oracle:
 # Plain definitions in numpy (independent of the C code)
 # ---------------------------------------------------------------------------
 
-def bruteforce_numpy(ulo, uhi, slo, shi) -> np.ndarray:
+def bruteforce_numpy(ulo, uhi, slo, shi, closed: bool = False) -> np.ndarray:
     """The problem statement of Sec. 3 with half-open boxes: returns the
-    boolean matrix hit[i, j] = AND_k max(ulo_ik, slo_jk) < min(uhi_ik, shi_jk).
-    Intended for n*m up to a few million."""
+    boolean matrix hit[i, j] = AND_k max(ulo_ik, slo_jk) < min(uhi_ik, shi_jk)
+    (<= for closed boxes).  Intended for n*m up to a few million."""
     ulo, uhi, slo, shi = (_f32(a).astype(np.float64) for a in (ulo, uhi, slo, shi))
     lo_max = np.maximum(ulo[:, None, :], slo[None, :, :])
     hi_min = np.minimum(uhi[:, None, :], shi[None, :, :])
-    return np.all(lo_max < hi_min, axis=2)
+    return np.all(lo_max <= hi_min if closed else lo_max < hi_min, axis=2)
 
 
 def pairs_from_matrix(hit: np.ndarray) -> np.ndarray:
@@ -194,7 +200,7 @@ def nonempty_mask(lo, hi) -> np.ndarray:
     return np.all(lo != hi, axis=1)
 
 
-def closed_form_1d(ulo, uhi, slo, shi, axis: int = 0) -> np.ndarray:
+def closed_form_1d(ulo, uhi, slo, shi, axis: int = 0, closed: bool = False) -> np.ndarray:
     """Per-update overlap counts on one axis among non-empty regions.
 
     For half-open intervals, subscription s overlaps update u iff
@@ -202,8 +208,17 @@ def closed_form_1d(ulo, uhi, slo, shi, axis: int = 0) -> np.ndarray:
     contained in the first, so the count is
         #{s : s.lo < u.hi} - #{s : s.hi <= u.lo}.
     Regions that are empty on any axis are excluded on both sides, and an
-    empty update gets 0.  Returns int64 counts."""
+    empty update gets 0.  For closed intervals (none is empty) the same
+    argument with s.lo <= s.hi gives
+        #{s : s.lo <= u.hi} - #{s : s.hi < u.lo}.
+    Returns int64 counts."""
     ulo, uhi, slo, shi = _f32(ulo), _f32(uhi), _f32(slo), _f32(shi)
+    if closed:
+        s_lo = np.sort(slo[:, axis].astype(np.float64))
+        s_hi = np.sort(shi[:, axis].astype(np.float64))
+        starts = np.searchsorted(s_lo, uhi[:, axis].astype(np.float64), side="right")
+        ends = np.searchsorted(s_hi, ulo[:, axis].astype(np.float64), side="left")
+        return starts.astype(np.int64) - ends.astype(np.int64)
     su = nonempty_mask(ulo, uhi)
     ss = nonempty_mask(slo, shi)
     s_lo = np.sort(slo[ss, axis].astype(np.float64))

@@ -32,6 +32,13 @@
  *   R5  ids are 0-based; pairs are reported as (update id, subscription id)
  *       and returned in lexicographic order (the paper's L is an unordered
  *       set).
+ *   R6  the closed reading, selected by the *_closed entry points, takes
+ *       Algorithm 1's tests as printed: intervals [lo, hi], overlap iff
+ *       lo <= hi' and lo' <= hi.  Then no interval is empty (lo == hi is a
+ *       point), and endpoints with equal coordinates sort lower-before-upper
+ *       (then kind, then id), so that an interval whose lower endpoint
+ *       equals another's upper one is still active when that upper endpoint
+ *       is swept.
  *
  * Coordinates are float32 on input and are only ever compared; each one is
  * widened to double (exact) before any comparison.
@@ -56,9 +63,29 @@
 typedef struct {
     double coord;
     int type;   /* TYPE_UPPER or TYPE_LOWER */
+    int rank;   /* tie order of the type: R2 (half-open) or R6 (closed) */
     int kind;   /* KIND_UPD or KIND_SUB */
     int64_t id; /* 0-based index inside its own set */
 } Endpoint;
+
+/* The interval reading of a call: R1-R3 (half-open) or R6 (closed). */
+typedef struct {
+    int closed;
+} Reading;
+
+/* Tie rank of an endpoint type: uppers first when half-open (R2), lowers
+ * first when closed (R6). */
+static int type_rank(const Reading *rd, int type)
+{
+    if (rd->closed) return type == TYPE_LOWER ? 0 : 1;
+    return type == TYPE_UPPER ? 0 : 1;
+}
+
+/* a < b for half-open intervals, a <= b for closed ones (R1 / R6). */
+static int before(const Reading *rd, double a, double b)
+{
+    return rd->closed ? a <= b : a < b;
+}
 
 /* Output sink shared by the brute force and the sweep. */
 typedef struct {
@@ -91,31 +118,32 @@ static int validate(const float *lo, const float *hi, int64_t cnt, int d)
     return OR_OK;
 }
 
-/* R3: empty on any axis means the region is empty. */
-static int is_empty(const float *lo, const float *hi, int64_t i, int d)
+/* R3: empty on any axis means the region is empty; R6: never when closed. */
+static int is_empty(const Reading *rd, const float *lo, const float *hi, int64_t i, int d)
 {
+    if (rd->closed) return 0;
     for (int k = 0; k < d; ++k)
         if ((double)lo[i * d + k] == (double)hi[i * d + k]) return 1;
     return 0;
 }
 
-/* Algorithm 1 in its half-open reading (R1) for axis k. */
-static int intersect_1d(const float *alo, const float *ahi, int64_t a,
+/* Algorithm 1 for axis k, in the reading of the call (R1 or R6). */
+static int intersect_1d(const Reading *rd, const float *alo, const float *ahi, int64_t a,
                         const float *blo, const float *bhi, int64_t b,
                         int d, int k)
 {
     double a_low = alo[a * d + k], a_high = ahi[a * d + k];
     double b_low = blo[b * d + k], b_high = bhi[b * d + k];
-    return a_low < b_high && b_low < a_high;
+    return before(rd, a_low, b_high) && before(rd, b_low, a_high);
 }
 
 /* The AND over the remaining axes 1..d-1 (axis 0 is the swept one). */
-static int intersect_other_axes(const float *ulo, const float *uhi, int64_t u,
+static int intersect_other_axes(const Reading *rd, const float *ulo, const float *uhi, int64_t u,
                                 const float *slo, const float *shi, int64_t s,
                                 int d)
 {
     for (int k = 1; k < d; ++k)
-        if (!intersect_1d(ulo, uhi, u, slo, shi, s, d, k)) return 0;
+        if (!intersect_1d(rd, ulo, uhi, u, slo, shi, s, d, k)) return 0;
     return 1;
 }
 
@@ -150,9 +178,10 @@ static int check_args(int64_t n, int64_t m, int d, const float *ulo,
  * Algorithm 2 (BruteForce-1D) generalised to d axes: test all n*m pairs.
  * The per-pair test is the plain definition of a non-empty intersection of
  * two half-open boxes, max(lo) < min(hi) on every axis, which is false for
- * any empty region without a separate rule.
+ * any empty region without a separate rule; for closed boxes (R6) it is
+ * max(lo) <= min(hi).
  */
-int oracle_bruteforce(const float *ulo, const float *uhi, int64_t n,
+static int bruteforce(const Reading *rd, const float *ulo, const float *uhi, int64_t n,
                       const float *slo, const float *shi, int64_t m, int d,
                       uint64_t *count, int32_t *per_update, int32_t *pairs,
                       int64_t pair_cap)
@@ -167,7 +196,7 @@ int oracle_bruteforce(const float *ulo, const float *uhi, int64_t n,
             for (int k = 0; k < d && hit; ++k) {
                 double lo_max = fmax((double)ulo[i * d + k], (double)slo[j * d + k]);
                 double hi_min = fmin((double)uhi[i * d + k], (double)shi[j * d + k]);
-                hit = lo_max < hi_min;
+                hit = before(rd, lo_max, hi_min);
             }
             if (hit) report(&s, i, j);
         }
@@ -176,18 +205,38 @@ int oracle_bruteforce(const float *ulo, const float *uhi, int64_t n,
     return finish(&s, pairs != NULL);
 }
 
-/* R2: coordinate, then upper before lower, then update before
- * subscription, then id.  The order is total, so qsort's instability does
- * not matter. */
+/* R2: coordinate, then upper before lower (lower before upper under R6),
+ * then update before subscription, then id.  The order is total, so qsort's
+ * instability does not matter. */
 static int cmp_endpoint(const void *a, const void *b)
 {
     const Endpoint *x = (const Endpoint *)a, *y = (const Endpoint *)b;
     if (x->coord < y->coord) return -1;
     if (x->coord > y->coord) return 1;
-    if (x->type != y->type) return x->type < y->type ? -1 : 1;
+    if (x->rank != y->rank) return x->rank < y->rank ? -1 : 1;
     if (x->kind != y->kind) return x->kind < y->kind ? -1 : 1;
     if (x->id != y->id) return x->id < y->id ? -1 : 1;
     return 0;
+}
+
+/* Step 2 of Algorithm 4: the lower and upper endpoint on axis 0 of every
+ * region that is not empty (R3), into T; returns the number written. */
+static int64_t fill_endpoints(const Reading *rd, const float *ulo, const float *uhi, int64_t n,
+                              const float *slo, const float *shi, int64_t m, int d, Endpoint *T)
+{
+    const int rl = type_rank(rd, TYPE_LOWER), ru = type_rank(rd, TYPE_UPPER);
+    int64_t t = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (is_empty(rd, ulo, uhi, i, d)) continue;
+        T[t++] = (Endpoint){(double)ulo[i * d], TYPE_LOWER, rl, KIND_UPD, i};
+        T[t++] = (Endpoint){(double)uhi[i * d], TYPE_UPPER, ru, KIND_UPD, i};
+    }
+    for (int64_t j = 0; j < m; ++j) {
+        if (is_empty(rd, slo, shi, j, d)) continue;
+        T[t++] = (Endpoint){(double)slo[j * d], TYPE_LOWER, rl, KIND_SUB, j};
+        T[t++] = (Endpoint){(double)shi[j * d], TYPE_UPPER, ru, KIND_SUB, j};
+    }
+    return t;
 }
 
 /* SubSet / UpdSet of Algorithm 4: an unordered set of ids with O(1)
@@ -248,7 +297,7 @@ static int idset_erase(IdSet *s, int64_t id)
  *      other set (the pairs whose other axes also overlap are reported);
  *   5. return the pairs in lexicographic order (R5).
  */
-int oracle_sbm(const float *ulo, const float *uhi, int64_t n,
+static int sbm(const Reading *rd, const float *ulo, const float *uhi, int64_t n,
                const float *slo, const float *shi, int64_t m, int d,
                uint64_t *count, int32_t *per_update, int32_t *pairs,
                int64_t pair_cap)
@@ -261,17 +310,7 @@ int oracle_sbm(const float *ulo, const float *uhi, int64_t n,
     if (!T) return OR_E_NOMEM;
 
     /* step 2: endpoints of the non-empty regions */
-    int64_t t = 0;
-    for (int64_t i = 0; i < n; ++i) {
-        if (is_empty(ulo, uhi, i, d)) continue;
-        T[t++] = (Endpoint){(double)ulo[i * d], TYPE_LOWER, KIND_UPD, i};
-        T[t++] = (Endpoint){(double)uhi[i * d], TYPE_UPPER, KIND_UPD, i};
-    }
-    for (int64_t j = 0; j < m; ++j) {
-        if (is_empty(slo, shi, j, d)) continue;
-        T[t++] = (Endpoint){(double)slo[j * d], TYPE_LOWER, KIND_SUB, j};
-        T[t++] = (Endpoint){(double)shi[j * d], TYPE_UPPER, KIND_SUB, j};
-    }
+    int64_t t = fill_endpoints(rd, ulo, uhi, n, slo, shi, m, d, T);
 
     /* step 3 */
     qsort(T, (size_t)t, sizeof(Endpoint), cmp_endpoint);
@@ -298,7 +337,7 @@ int oracle_sbm(const float *ulo, const float *uhi, int64_t n,
                 rc = idset_erase(&SubSet, e->id);
                 for (int64_t a = 0; a < UpdSet.size; ++a) {
                     int64_t u = UpdSet.items[a];
-                    if (intersect_other_axes(ulo, uhi, u, slo, shi, e->id, d))
+                    if (intersect_other_axes(rd, ulo, uhi, u, slo, shi, e->id, d))
                         report(&s, u, e->id);
                 }
             }
@@ -309,7 +348,7 @@ int oracle_sbm(const float *ulo, const float *uhi, int64_t n,
                 rc = idset_erase(&UpdSet, e->id);
                 for (int64_t a = 0; a < SubSet.size; ++a) {
                     int64_t sb = SubSet.items[a];
-                    if (intersect_other_axes(ulo, uhi, e->id, slo, shi, sb, d))
+                    if (intersect_other_axes(rd, ulo, uhi, e->id, slo, shi, sb, d))
                         report(&s, e->id, sb);
                 }
             }
@@ -323,6 +362,43 @@ int oracle_sbm(const float *ulo, const float *uhi, int64_t n,
     if (count) *count = s.count;
     /* step 5 */
     return finish(&s, pairs != NULL);
+}
+
+/* Public entry points: half-open (R1-R3) and closed (R6) readings. */
+int oracle_bruteforce(const float *ulo, const float *uhi, int64_t n,
+                      const float *slo, const float *shi, int64_t m, int d,
+                      uint64_t *count, int32_t *per_update, int32_t *pairs,
+                      int64_t pair_cap)
+{
+    const Reading rd = {0};
+    return bruteforce(&rd, ulo, uhi, n, slo, shi, m, d, count, per_update, pairs, pair_cap);
+}
+
+int oracle_bruteforce_closed(const float *ulo, const float *uhi, int64_t n,
+                             const float *slo, const float *shi, int64_t m, int d,
+                             uint64_t *count, int32_t *per_update, int32_t *pairs,
+                             int64_t pair_cap)
+{
+    const Reading rd = {1};
+    return bruteforce(&rd, ulo, uhi, n, slo, shi, m, d, count, per_update, pairs, pair_cap);
+}
+
+int oracle_sbm(const float *ulo, const float *uhi, int64_t n,
+               const float *slo, const float *shi, int64_t m, int d,
+               uint64_t *count, int32_t *per_update, int32_t *pairs,
+               int64_t pair_cap)
+{
+    const Reading rd = {0};
+    return sbm(&rd, ulo, uhi, n, slo, shi, m, d, count, per_update, pairs, pair_cap);
+}
+
+int oracle_sbm_closed(const float *ulo, const float *uhi, int64_t n,
+                      const float *slo, const float *shi, int64_t m, int d,
+                      uint64_t *count, int32_t *per_update, int32_t *pairs,
+                      int64_t pair_cap)
+{
+    const Reading rd = {1};
+    return sbm(&rd, ulo, uhi, n, slo, shi, m, d, count, per_update, pairs, pair_cap);
 }
 
 /*
@@ -356,17 +432,8 @@ int64_t oracle_sweep_state(const float *ulo, const float *uhi, int64_t n,
     int64_t total = 2 * (n + m);
     Endpoint *T = (Endpoint *)malloc((size_t)(total > 0 ? total : 1) * sizeof(Endpoint));
     if (!T) return OR_E_NOMEM;
-    int64_t t = 0;
-    for (int64_t i = 0; i < n; ++i) {
-        if (is_empty(ulo, uhi, i, d)) continue;
-        T[t++] = (Endpoint){(double)ulo[i * d], TYPE_LOWER, KIND_UPD, i};
-        T[t++] = (Endpoint){(double)uhi[i * d], TYPE_UPPER, KIND_UPD, i};
-    }
-    for (int64_t j = 0; j < m; ++j) {
-        if (is_empty(slo, shi, j, d)) continue;
-        T[t++] = (Endpoint){(double)slo[j * d], TYPE_LOWER, KIND_SUB, j};
-        T[t++] = (Endpoint){(double)shi[j * d], TYPE_UPPER, KIND_SUB, j};
-    }
+    const Reading half_open = {0};
+    int64_t t = fill_endpoints(&half_open, ulo, uhi, n, slo, shi, m, d, T);
     qsort(T, (size_t)t, sizeof(Endpoint), cmp_endpoint);
 
     IdSet SubSet, UpdSet;

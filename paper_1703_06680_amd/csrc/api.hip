@@ -47,7 +47,8 @@ struct Layout {
 // The pointers only enter the bucketed plan (null when only sizes matter).
 Layout make_layout(int64_t n, int64_t m, int d, int mode, int64_t cap,
                    const float *ulo = nullptr, const float *uhi = nullptr,
-                   const float *slo = nullptr, const float *shi = nullptr) {
+                   const float *slo = nullptr, const float *shi = nullptr,
+                   bool closed = false) {
   Layout L{};
   size_t at = 0;
   auto take = [&](size_t bytes) {
@@ -92,11 +93,19 @@ Layout make_layout(int64_t n, int64_t m, int d, int mode, int64_t cap,
   L.bucket_ok = bucket_path_supported(d, n, m);
   size_t region_bytes = g;
   if (L.bucket_ok) {
-    L.B = bucket_layout(ulo, uhi, n, slo, shi, m, d);
+    L.B = bucket_layout(ulo, uhi, n, slo, shi, m, d, closed);
     if (L.B.bytes > region_bytes) region_bytes = L.B.bytes;
   }
   L.total = L.region + align256(region_bytes);
   return L;
+}
+
+// Splits a mode argument into the output mode and the interval flag; false
+// for unknown bits.
+bool split_mode(int mode, int *out, bool *closed) {
+  *closed = (mode & DDM_CLOSED) != 0;
+  *out = mode & ~DDM_CLOSED;
+  return *out == DDM_COUNT || *out == DDM_PER_UPDATE || *out == DDM_PAIRS;
 }
 
 bool sizes_ok(int64_t n, int64_t m, int d, int mode) {
@@ -144,7 +153,8 @@ hipError_t order_pairs(uint32_t *pu, uint32_t *ps, uint32_t *pu2, uint32_t *ps2,
 struct Call {
   const float *ulo, *uhi, *slo, *shi;
   int64_t n, m;
-  int d, mode;
+  int d, mode;    // output mode (without DDM_CLOSED)
+  uint32_t closed;
   void *ws;
   Layout L;
   hipStream_t s;
@@ -233,7 +243,7 @@ int run_global(const Call &c) {
   uint32_t *klo = at<uint32_t>(R, L.klo);
   uint32_t *khi = at<uint32_t>(R, L.khi);
   const int axis = 0;
-  launch_keys(c.ulo, c.uhi, un, c.slo, c.shi, um, c.d, axis, klo, khi,
+  launch_keys(c.ulo, c.uhi, un, c.slo, c.shi, um, c.d, axis, c.closed, klo, khi,
               at<uint4>(c.ws, L.partial), c.hdr, c.s);
   DDM_HIP(hipGetLastError());
   Header h{};
@@ -275,6 +285,7 @@ int run_global(const Call &c) {
   a.count = nne;
   a.n = un;
   a.dm1 = c.d - 1;
+  a.closed = c.closed;
   a.per_update = c.cnt;
   a.total = &c.hdr->total;
   launch_sweep(c.mode != DDM_COUNT ? 1 : 0, a, c.s);
@@ -396,8 +407,11 @@ using namespace ddm;
 
 extern "C" size_t ddm_workspace_bytes(int64_t n, int64_t m, int d, int mode,
                                       int64_t pair_capacity) {
-  if (!sizes_ok(n, m, d, mode) || pair_capacity < 0) return 0;
-  return make_layout(n, m, d, mode, pair_capacity).total;
+  int out;
+  bool closed;
+  if (!split_mode(mode, &out, &closed)) return 0;
+  if (!sizes_ok(n, m, d, out) || pair_capacity < 0) return 0;
+  return make_layout(n, m, d, out, pair_capacity).total;
 }
 
 extern "C" const char *ddm_strerror(int code) {
@@ -426,6 +440,9 @@ extern "C" int ddm_match(const float *upd_lo, const float *upd_hi, int64_t n, co
                          size_t ws_bytes, void *stream, uint64_t *count_host, int32_t *per_update,
                          int32_t *pairs, int64_t pair_capacity) {
   // host-side checks: nothing is launched when one fails
+  const int mode_arg = mode;  // with the interval flag (the graph cache key)
+  bool closed;
+  if (!split_mode(mode_arg, &mode, &closed)) return DDM_E_INVAL;
   if (!sizes_ok(n, m, d, mode) || !count_host || pair_capacity < 0) return DDM_E_INVAL;
   if ((n > 0 && (!upd_lo || !upd_hi)) || (m > 0 && (!sub_lo || !sub_hi))) return DDM_E_INVAL;
   if (mode == DDM_PER_UPDATE && n > 0 && !per_update) return DDM_E_INVAL;
@@ -433,7 +450,7 @@ extern "C" int ddm_match(const float *upd_lo, const float *upd_hi, int64_t n, co
   const bool graphable = mode != DDM_PAIRS && n + m > 0 && !prof::enabled() &&
                          g_path_request != DDM_PATH_GLOBAL && workspace &&
                          !(reinterpret_cast<uintptr_t>(workspace) & 255);
-  const GraphKey key{upd_lo, upd_hi, sub_lo, sub_hi, n, m, d, mode, workspace, ws_bytes,
+  const GraphKey key{upd_lo, upd_hi, sub_lo, sub_hi, n, m, d, mode_arg, workspace, ws_bytes,
                      mode == DDM_COUNT ? nullptr : per_update};
   std::unique_lock<std::mutex> cache_lock(g_graph_mu, std::defer_lock);
   CachedGraph *entry = nullptr;
@@ -469,7 +486,7 @@ extern "C" int ddm_match(const float *upd_lo, const float *upd_hi, int64_t n, co
     if (!entry) cache_lock.unlock();  // an eager call needs no cache entry
   }
   Call c{};
-  c.L = make_layout(n, m, d, mode, pair_capacity, upd_lo, upd_hi, sub_lo, sub_hi);
+  c.L = make_layout(n, m, d, mode, pair_capacity, upd_lo, upd_hi, sub_lo, sub_hi, closed);
   if (!workspace || ws_bytes < c.L.total) return DDM_E_WORKSPACE;
   if (reinterpret_cast<uintptr_t>(workspace) & 255) return DDM_E_INVAL;
   *count_host = 0;
@@ -481,6 +498,7 @@ extern "C" int ddm_match(const float *upd_lo, const float *upd_hi, int64_t n, co
   c.m = m;
   c.d = d;
   c.mode = mode;
+  c.closed = closed ? 1u : 0u;
   c.ws = workspace;
   c.s = static_cast<hipStream_t>(stream);
   c.count_host = count_host;

@@ -25,7 +25,8 @@ struct Batch {
   std::vector<InstSpec> spec;
   std::vector<int64_t> uoff, soff;  // first output row of each instance's updates / subscriptions
   int64_t B;
-  int d, mode;
+  int d, mode;      // output mode (without DDM_CLOSED)
+  uint32_t closed;  // closed intervals
   void *ws;
   size_t ws_bytes;
   uint64_t *counts;
@@ -34,6 +35,7 @@ struct Batch {
   int64_t cap;
   bool bucketed;  // the batch fits the bucketed plan
   BatchLayout L;
+  int match_mode() const { return mode | (closed ? DDM_CLOSED : 0); }  // as ddm_match takes it
 };
 
 // Validates a batch given as instances (output rows follow the instance

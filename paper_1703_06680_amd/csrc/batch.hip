@@ -142,11 +142,19 @@ std::vector<BucketTuning> candidates() {
   return out;
 }
 
+// The output mode of a mode argument (without the interval flag).
+inline int out_mode(int mode) { return mode & ~DDM_CLOSED; }
+
+bool mode_ok(int mode) {
+  const int o = out_mode(mode);
+  return o == DDM_COUNT || o == DDM_PER_UPDATE || o == DDM_PAIRS;
+}
+
 bool shape_ok(const int64_t *uoff, const int64_t *soff, int64_t B, int d, int mode,
               int64_t cap) {
   if (!uoff || !soff || B < 1 || B >= (int64_t(1) << 24)) return false;
   if (d < 1 || d > DDM_MAX_DIMS) return false;
-  if (mode != DDM_COUNT && mode != DDM_PER_UPDATE && mode != DDM_PAIRS) return false;
+  if (!mode_ok(mode)) return false;
   if (cap < 0 || cap >= (int64_t(1) << 31)) return false;
   if (uoff[0] != 0 || soff[0] != 0) return false;
   for (int64_t b = 0; b < B; ++b)
@@ -156,6 +164,7 @@ bool shape_ok(const int64_t *uoff, const int64_t *soff, int64_t B, int d, int mo
 
 BatchLayout batch_layout(const InstSpec *spec, int64_t B, int d, int mode, int64_t cap,
                          const BucketTuning &t) {
+  mode = out_mode(mode);
   BatchLayout L{};
   size_t at_ = 0;
   auto take = [&](size_t bytes) {
@@ -215,7 +224,7 @@ std::vector<InstSpec> csr_specs(const float *ulo, const float *uhi, const int64_
 bool specs_ok(const InstSpec *spec, int64_t B, int d, int mode, int64_t cap) {
   if (!spec || B < 1 || B >= (int64_t(1) << 24)) return false;
   if (d < 1 || d > DDM_MAX_DIMS) return false;
-  if (mode != DDM_COUNT && mode != DDM_PER_UPDATE && mode != DDM_PAIRS) return false;
+  if (!mode_ok(mode)) return false;
   if (cap < 0 || cap >= (int64_t(1) << 31)) return false;
   int64_t N = 0;
   for (int64_t b = 0; b < B; ++b) {
@@ -234,8 +243,11 @@ int make_batch(Batch &c, std::vector<InstSpec> spec, int d, int mode, void *ws, 
                int64_t *pair_off, int64_t cap) {
   const int64_t B = (int64_t)spec.size();
   if (!specs_ok(spec.data(), B, d, mode, cap) || !tuning_valid(tuning)) return DDM_E_INVAL;
+  const uint32_t closed = (mode & DDM_CLOSED) ? 1u : 0u;
+  mode = out_mode(mode);
   int64_t n_total = 0;
-  for (const InstSpec &x : spec) {
+  for (InstSpec &x : spec) {
+    x.closed = closed;
     if ((x.n > 0 && (!x.ulo || !x.uhi)) || (x.m > 0 && (!x.slo || !x.shi))) return DDM_E_INVAL;
     n_total += x.n;
   }
@@ -253,6 +265,7 @@ int make_batch(Batch &c, std::vector<InstSpec> spec, int d, int mode, void *ws, 
   c.B = B;
   c.d = d;
   c.mode = mode;
+  c.closed = closed;
   c.ws = ws;
   c.ws_bytes = ws_bytes;
   c.counts = counts;
@@ -266,7 +279,7 @@ int make_batch(Batch &c, std::vector<InstSpec> spec, int d, int mode, void *ws, 
     c.L = batch_layout(c.spec.data(), B, d, mode, cap, t);
     if (ws_bytes < c.L.total) return DDM_E_WORKSPACE;
   }
-  if (ws_bytes < fallback_bytes(c.spec.data(), B, d, mode, cap)) return DDM_E_WORKSPACE;
+  if (ws_bytes < fallback_bytes(c.spec.data(), B, d, c.match_mode(), cap)) return DDM_E_WORKSPACE;
   return DDM_OK;
 }
 
@@ -402,7 +415,8 @@ int run_each(const Batch &c, hipStream_t s, uint64_t *total_host) {
     const int64_t u0 = c.uoff[(size_t)b], n = x.n, m = x.m;
     const int64_t room = full ? 0 : c.cap - used;
     uint64_t K = 0;
-    const int rc = ddm_match(x.ulo, x.uhi, n, x.slo, x.shi, m, c.d, c.mode, c.ws, c.ws_bytes, s,
+    const int rc = ddm_match(x.ulo, x.uhi, n, x.slo, x.shi, m, c.d, c.match_mode(), c.ws,
+                             c.ws_bytes, s,
                              &K,
                              c.per_update && n > 0 ? c.per_update + u0 : nullptr,
                              c.mode == DDM_PAIRS && room > 0 ? c.pairs + 2 * used : nullptr,

@@ -39,10 +39,12 @@ constexpr uint32_t kBigBucketCap = 4096;
 // of the count and scatter passes).
 constexpr uint32_t kMaxBuckets = 16384;
 
-// One instance: its own row arrays (float32 [n][d] / [m][d]).
+// One instance: its own row arrays (float32 [n][d] / [m][d]); closed != 0
+// matches closed intervals [lo, hi] instead of half-open [lo, hi).
 struct InstSpec {
   const float *ulo, *uhi, *slo, *shi;
   int64_t n, m;
+  uint32_t closed = 0;
 };
 
 // Per-instance launch plan, in device memory for batches of more than one.
@@ -55,7 +57,8 @@ struct InstPlan {
   uint32_t cell0;            // first cell of the instance's nblk x nb count matrix
   uint32_t smp0, nsmp;       // sample blocks
   uint32_t tile0, ntx;       // transpose tiles (first), tiles along the bucket axis
-  uint32_t vec, pad;         // rows may be read with 16-byte loads
+  uint32_t vec;              // rows may be read with 16-byte loads
+  uint32_t closed;           // 1: closed intervals (records hold enc(hi) + 1)
 };
 
 inline uint32_t bucket_cap(const BucketTuning &t) {
@@ -86,7 +89,7 @@ BucketLayout bucket_layout(const InstSpec *inst, int64_t B, int d, const BucketT
 // Single instance of n updates and m subscriptions with the default tuning.
 bool bucket_path_supported(int d, int64_t n, int64_t m);
 BucketLayout bucket_layout(const float *ulo, const float *uhi, int64_t n, const float *slo,
-                           const float *shi, int64_t m, int d);
+                           const float *shi, int64_t m, int d, bool closed = false);
 
 struct BucketArgs {
   int d;

@@ -105,9 +105,10 @@ __device__ __forceinline__ Box<D> load_row(const float *__restrict__ lo,
   return b;
 }
 
-// Error bits and emptiness of one box.
+// Error bits and emptiness of one box.  A half-open box with lo == hi on
+// some axis is empty; a closed one never is (lo == hi is a point).
 template <int D>
-__device__ __forceinline__ uint32_t box_errors(const Box<D> &b, bool &empty) {
+__device__ __forceinline__ uint32_t box_errors(const Box<D> &b, bool &empty, uint32_t closed) {
   uint32_t err = 0;
   empty = false;
 #pragma unroll
@@ -115,7 +116,7 @@ __device__ __forceinline__ uint32_t box_errors(const Box<D> &b, bool &empty) {
     const float l = b.lo[k], h = b.hi[k];
     if (l != l || h != h) err |= kErrNaN;
     if (l > h) err |= kErrOrder;
-    if (l == h) empty = true;
+    if (l == h && !closed) empty = true;
   }
   return err;
 }
@@ -189,7 +190,7 @@ __global__ __launch_bounds__(kSampleThreads) void bk_sample_kernel(View V,
   const bool upd = r < I.n;
   const Box<D> b = load_row<D>(upd ? I.ulo : I.slo, upd ? I.uhi : I.shi, upd ? r : r - I.n);
   bool empty;
-  const uint32_t err = box_errors<D>(b, empty);
+  const uint32_t err = box_errors<D>(b, empty, I.closed);
   bool ok = !err && !empty && fabsf(b.lo[0]) <= 3.0e38f;
 #pragma unroll
   for (int k = 1; k < D; ++k) ok = ok && fabsf(b.lo[k]) <= 3.0e38f && fabsf(b.hi[k]) <= 3.0e38f;
@@ -407,7 +408,7 @@ __global__ __launch_bounds__(kThreads) void bk_count_kernel(
     for (int r = 0; r < 4; ++r) {
       if ((uint32_t)r >= q.rows) continue;
       bool empty;
-      err |= box_errors<D>(bx[r], empty);
+      err |= box_errors<D>(bx[r], empty, I.closed);
       if (empty) continue;
       const uint32_t b = bucket_of(bx[r].lo[0], p.vmin, p.scale, nb);
       atomicAdd(&hist[b], 1u);
@@ -468,7 +469,9 @@ __device__ __forceinline__ uint32_t quant_hi(float x, float qmin, float qs) {
 }
 
 // Record (16 bytes): word 0 = encoded lower key (swept axis), 1 = encoded
-// upper key, 2 = region index (updates first), 3 = quantised bounds of the
+// upper key, plus one for closed intervals (keys are integers, so x <= hi is
+// x < enc(hi) + 1, and enc(+inf) + 1 does not wrap), 2 = region index
+// (updates first), 3 = quantised bounds of the
 // other axes: for d = 2 the 16-bit lower | upper << 16 of axis 1; for d = 3
 // 7-bit bounds (the 16-bit ones scaled by 2^-9, lower rounded down, upper
 // rounded up and capped at 127) lo1 | hi1 << 8 | lo2 << 16 | hi2 << 24; 0
@@ -494,9 +497,9 @@ __device__ __forceinline__ uint32_t qword_of(const Box<D> &b, const BucketParams
 
 template <int D>
 __device__ __forceinline__ void write_record(uint32_t *__restrict__ dst, const Box<D> &b,
-                                             uint32_t r, const BucketParams &p) {
+                                             uint32_t r, const BucketParams &p, uint32_t closed) {
   *reinterpret_cast<uint4 *>(dst) =
-      make_uint4(encode_coord(b.lo[0]), encode_coord(b.hi[0]), r, qword_of<D>(b, p));
+      make_uint4(encode_coord(b.lo[0]), encode_coord(b.hi[0]) + closed, r, qword_of<D>(b, p));
 }
 
 template <int D>
@@ -524,16 +527,16 @@ __global__ __launch_bounds__(kThreads) void bk_scatter_kernel(
     for (int r = 0; r < 4; ++r) {
       if ((uint32_t)r >= q.rows) continue;
       bool empty;
-      (void)box_errors<D>(bx[r], empty);
+      (void)box_errors<D>(bx[r], empty, I.closed);
       if (empty) continue;
       const uint32_t b = bucket_of(bx[r].lo[0], p.vmin, p.scale, nb);
       const uint32_t slot = atomicAdd(&cur[b], 1u);
-      write_record<D>(rec + (size_t)slot * RW, bx[r], q.r0 + r, p);
+      write_record<D>(rec + (size_t)slot * RW, bx[r], q.r0 + r, p, I.closed);
       const uint32_t last = bucket_of(bx[r].hi[0], p.vmin, p.scale, nb);
       for (uint32_t j = b + 1; j <= last; ++j) {
         const uint32_t jg = I.b0 + j;
         const uint32_t pos = O.bs_begin(jg) + atomicAdd(&bs_cur[jg], 1u);
-        if (pos < bs_cap) write_record<D>(bs_rec + (size_t)pos * RW, bx[r], q.r0 + r, p);
+        if (pos < bs_cap) write_record<D>(bs_rec + (size_t)pos * RW, bx[r], q.r0 + r, p, I.closed);
       }
     }
   }
@@ -578,6 +581,11 @@ __global__ void bk_expand_maps_kernel(const InstPlan *__restrict__ plan, uint32_
 // Inverse of encode_coord (for non-NaN codes; -0 comes back as +0).
 __device__ __forceinline__ float decode_coord(uint32_t k) {
   return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
+// The strict test a < b of half-open intervals, a <= b for closed ones.
+__device__ __forceinline__ bool before(float a, float b, uint32_t closed) {
+  return a < b || (closed && a == b);
 }
 
 __device__ __forceinline__ uint32_t fine_of(float x, float vmin, float fscale, int fine) {
@@ -698,7 +706,8 @@ __device__ __forceinline__ void visit(const Walker<DM1> &y, bool &have_y, float 
     other_axes<DM1>(o, rx, xlo, xhi);
     bool hit = true;
 #pragma unroll
-    for (int c = 0; c < DM1; ++c) hit = hit && ylo[c] < xhi[c] && xlo[c] < yhi[c];
+    for (int c = 0; c < DM1; ++c)
+      hit = hit && before(ylo[c], xhi[c], o.I.closed) && before(xlo[c], yhi[c], o.I.closed);
     if (!hit) return;
   }
   ++hits;
@@ -726,7 +735,8 @@ __device__ __forceinline__ void resolve(uint32_t ry, uint32_t rx, unsigned long 
   other_axes<DM1>(o, rx, xlo, xhi);
   bool hit = true;
 #pragma unroll
-  for (int c = 0; c < DM1; ++c) hit = hit && ylo[c] < xhi[c] && xlo[c] < yhi[c];
+  for (int c = 0; c < DM1; ++c)
+    hit = hit && before(ylo[c], xhi[c], o.I.closed) && before(xlo[c], yhi[c], o.I.closed);
   if (!hit) return;
   ++hits;
   const uint32_t uu = ry < o.n ? ry : rx, ss = ry < o.n ? rx : ry;
@@ -1000,7 +1010,7 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
       y.q = DM1 > 0 ? walker_word<DM1>(yr.w) : 0u;
       jA = jB = bin_begin(y.upd ? (uint32_t)FINE : 0u);
     }
-    const uint32_t fh = fine_of(decode_coord(y.khi), vmn, fscale, FINE);
+    const uint32_t fh = fine_of(decode_coord(y.khi - I.closed), vmn, fscale, FINE);
     const uint32_t last = (y.upd ? (uint32_t)FINE : 0u) + fh;
     walk<DM1, MODE>(KLO, RID, Q, y, jA, jB, bin_begin(last), BIN[last], hits, o);
   }
@@ -1120,6 +1130,7 @@ bool plan_instance(const InstSpec &sp, int64_t u0, int64_t s0, const BucketTunin
   I.slo = sp.slo;
   I.shi = sp.shi;
   I.vec = aligned16(sp.ulo) && aligned16(sp.uhi) && aligned16(sp.slo) && aligned16(sp.shi);
+  I.closed = sp.closed ? 1u : 0u;
   I.u0 = (uint32_t)u0;
   I.n = (uint32_t)n;
   I.s0 = (uint32_t)s0;
@@ -1226,8 +1237,8 @@ BucketLayout bucket_layout(const InstSpec *inst, int64_t B, int d, const BucketT
 }
 
 BucketLayout bucket_layout(const float *ulo, const float *uhi, int64_t n, const float *slo,
-                           const float *shi, int64_t m, int d) {
-  const InstSpec sp{ulo, uhi, slo, shi, n, m};
+                           const float *shi, int64_t m, int d, bool closed) {
+  const InstSpec sp{ulo, uhi, slo, shi, n, m, closed ? 1u : 0u};
   return bucket_layout(&sp, 1, d, BucketTuning{});
 }
 

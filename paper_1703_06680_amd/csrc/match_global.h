@@ -19,6 +19,7 @@ struct SweepArgs {
   uint32_t count;          // non-empty regions
   uint32_t n;              // number of updates (regions < n are updates)
   int dm1;                 // number of other axes (d - 1)
+  uint32_t closed;         // 1: closed intervals (s_khi holds enc(hi) + 1)
   int32_t *per_update;     // mode 1: per-update counts (zeroed beforehand)
   const unsigned long long *offsets;  // mode 2: first pair slot of each update
   uint32_t *cursor;        // mode 2: per-update running slot (zeroed)
@@ -30,9 +31,10 @@ constexpr unsigned kKeysMaxBlocks = 8192;
 unsigned keys_grid(size_t regions);
 // Validates and encodes; per-block partials (<= kKeysMaxBlocks uint4) are
 // folded into hdr->err / nonempty / kmin / kmax by a one-block kernel.
+// closed = 1: closed intervals (no empty boxes; khi = enc(hi) + 1).
 void launch_keys(const float *ulo, const float *uhi, uint32_t n, const float *slo,
-                 const float *shi, uint32_t m, int d, int axis, uint32_t *klo, uint32_t *khi,
-                 uint4 *partial, Header *hdr, hipStream_t s);
+                 const float *shi, uint32_t m, int d, int axis, uint32_t closed, uint32_t *klo,
+                 uint32_t *khi, uint4 *partial, Header *hdr, hipStream_t s);
 void launch_gather(const uint32_t *sidx, uint32_t count, const uint32_t *khi, const float *ulo,
                    const float *uhi, uint32_t n, const float *slo, const float *shi, int d,
                    int axis, uint32_t *s_khi, float *s_other, size_t stride, hipStream_t s);

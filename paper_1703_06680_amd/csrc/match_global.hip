@@ -23,6 +23,10 @@
 // enc(x.lo) < enc(y.hi), so no upper endpoint needs to be materialised.  The
 // pair is then kept iff the boxes also overlap on every other axis (the AND
 // over axes of Sec. 3).
+//
+// Closed intervals [lo, hi] (Algorithm 1's own tests) differ in two places
+// only: no box is empty, and the stored upper key is enc(hi) + 1, because on
+// integer keys x <= enc(hi) is x < enc(hi) + 1; the other axes use <=.
 #include "common.h"
 #include "match_global.h"
 #include "profile.h"
@@ -36,7 +40,8 @@ constexpr int kThreads = 256;
 __global__ __launch_bounds__(kThreads) void keys_kernel(
     const float *__restrict__ ulo, const float *__restrict__ uhi, uint32_t n,
     const float *__restrict__ slo, const float *__restrict__ shi, uint32_t m, int d, int axis,
-    uint32_t *__restrict__ klo, uint32_t *__restrict__ khi, uint4 *__restrict__ partial) {
+    uint32_t closed, uint32_t *__restrict__ klo, uint32_t *__restrict__ khi,
+    uint4 *__restrict__ partial) {
   __shared__ uint32_t red[4][kThreads / kWave];
   const uint32_t N = n + m;
   uint32_t err = 0, nonempty = 0, kmin = 0xFFFFFFFFu, kmax = 0u;
@@ -51,7 +56,7 @@ __global__ __launch_bounds__(kThreads) void keys_kernel(
       const float l = lo[k], h = hi[k];
       if (l != l || h != h) err |= kErrNaN;
       if (l > h) err |= kErrOrder;
-      if (l == h) empty = true;
+      if (l == h && !closed) empty = true;
       if (k == axis) {
         alo = l;
         ahi = h;
@@ -59,7 +64,7 @@ __global__ __launch_bounds__(kThreads) void keys_kernel(
     }
     const uint32_t el = encode_coord(alo);
     klo[r] = empty ? kSentinel : el;
-    khi[r] = encode_coord(ahi);
+    khi[r] = encode_coord(ahi) + closed;
     if (!empty) {
       ++nonempty;
       kmin = el < kmin ? el : kmin;
@@ -159,7 +164,7 @@ template <int kMode, int kDm1>
 __global__ __launch_bounds__(kThreads) void sweep_kernel(
     const uint32_t *__restrict__ skey, const uint32_t *__restrict__ sidx,
     const uint32_t *__restrict__ s_khi, const float *__restrict__ s_other, size_t stride,
-    uint32_t count, uint32_t n, int dm1_rt, int32_t *__restrict__ per_update,
+    uint32_t count, uint32_t n, int dm1_rt, uint32_t closed, int32_t *__restrict__ per_update,
     const unsigned long long *__restrict__ offsets, uint32_t *__restrict__ cursor,
     uint32_t *__restrict__ out_u, uint32_t *__restrict__ out_s,
     unsigned long long *__restrict__ total) {
@@ -188,7 +193,8 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(
         if (j < dm1 && hit) {
           const float xlo = s_other[(size_t)(2 * j) * stride + q2];
           const float xhi = s_other[(size_t)(2 * j + 1) * stride + q2];
-          hit = ylo[j] < xhi && xlo < yhi[j];
+          hit = (ylo[j] < xhi || (closed && ylo[j] == xhi)) &&
+                (xlo < yhi[j] || (closed && xlo == yhi[j]));
         }
       }
       if (!hit) continue;
@@ -242,22 +248,22 @@ void launch_sweep(const SweepArgs &a, hipStream_t s) {
   switch (a.dm1) {
     case 0:
       sweep_kernel<kMode, 0><<<grid, kThreads, 0, s>>>(a.skey, a.sidx, a.s_khi, a.s_other, a.stride,
-                                                       a.count, a.n, a.dm1, a.per_update, a.offsets,
+                                                       a.count, a.n, a.dm1, a.closed, a.per_update, a.offsets,
                                                        a.cursor, a.out_u, a.out_s, a.total);
       break;
     case 1:
       sweep_kernel<kMode, 1><<<grid, kThreads, 0, s>>>(a.skey, a.sidx, a.s_khi, a.s_other, a.stride,
-                                                       a.count, a.n, a.dm1, a.per_update, a.offsets,
+                                                       a.count, a.n, a.dm1, a.closed, a.per_update, a.offsets,
                                                        a.cursor, a.out_u, a.out_s, a.total);
       break;
     case 2:
       sweep_kernel<kMode, 2><<<grid, kThreads, 0, s>>>(a.skey, a.sidx, a.s_khi, a.s_other, a.stride,
-                                                       a.count, a.n, a.dm1, a.per_update, a.offsets,
+                                                       a.count, a.n, a.dm1, a.closed, a.per_update, a.offsets,
                                                        a.cursor, a.out_u, a.out_s, a.total);
       break;
     default:
       sweep_kernel<kMode, -1><<<grid, kThreads, 0, s>>>(a.skey, a.sidx, a.s_khi, a.s_other,
-                                                        a.stride, a.count, a.n, a.dm1, a.per_update,
+                                                        a.stride, a.count, a.n, a.dm1, a.closed, a.per_update,
                                                         a.offsets, a.cursor, a.out_u, a.out_s,
                                                         a.total);
       break;
@@ -269,11 +275,12 @@ void launch_sweep(const SweepArgs &a, hipStream_t s) {
 unsigned keys_grid(size_t regions) { return grid_for(regions, kKeysMaxBlocks); }
 
 void launch_keys(const float *ulo, const float *uhi, uint32_t n, const float *slo,
-                 const float *shi, uint32_t m, int d, int axis, uint32_t *klo, uint32_t *khi,
-                 uint4 *partial, Header *hdr, hipStream_t s) {
+                 const float *shi, uint32_t m, int d, int axis, uint32_t closed, uint32_t *klo,
+                 uint32_t *khi, uint4 *partial, Header *hdr, hipStream_t s) {
   const unsigned grid = keys_grid((size_t)n + m);
   prof::mark(s, "keys");
-  keys_kernel<<<grid, kThreads, 0, s>>>(ulo, uhi, n, slo, shi, m, d, axis, klo, khi, partial);
+  keys_kernel<<<grid, kThreads, 0, s>>>(ulo, uhi, n, slo, shi, m, d, axis, closed, klo, khi,
+                                        partial);
   prof::mark(s, "keys.finalize");
   keys_finalize_kernel<<<1, kThreads, 0, s>>>(partial, grid, hdr);
 }

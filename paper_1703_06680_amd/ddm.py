@@ -24,6 +24,7 @@ DDM_E_DEVICE = -4
 DDM_E_UNSUPPORTED = -5
 
 MODES = {"count": 0, "per_update": 1, "pairs": 2}
+DDM_CLOSED = 16  # interval flag OR-ed into a mode: closed boxes [lo, hi]
 PATHS = {"auto": 0, "bucketed": 1, "global": 2}
 MAX_DIMS = 16
 
@@ -141,9 +142,15 @@ def profile_report() -> dict:
     return json.loads(buf.value.decode())
 
 
+def _code(mode: str, closed: bool) -> int:
+    if mode not in MODES:
+        raise ValueError(f"unknown mode {mode!r}")
+    return MODES[mode] | (DDM_CLOSED if closed else 0)
+
+
 def match_into(upd_lo, upd_hi, sub_lo, sub_hi, mode: str, workspace: torch.Tensor,
                per_update: torch.Tensor | None = None, pairs: torch.Tensor | None = None,
-               stream=None) -> int:
+               stream=None, closed: bool = False) -> int:
     """Low-level call with caller-provided workspace and outputs (no
     allocation); returns the number of pairs, raises DDMError on failure."""
     n, d = upd_lo.shape
@@ -153,7 +160,8 @@ def match_into(upd_lo, upd_hi, sub_lo, sub_hi, mode: str, workspace: torch.Tenso
     cnt = ctypes.c_uint64(0)
     cap = pairs.shape[0] if pairs is not None else 0
     rc = library().ddm_match(_ptr(upd_lo), _ptr(upd_hi), n, _ptr(sub_lo), _ptr(sub_hi), m, d,
-                             MODES[mode], ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                             _code(mode, closed), ctypes.c_void_p(workspace.data_ptr()),
+                             workspace.numel(),
                              ctypes.c_void_p(stream.cuda_stream), ctypes.byref(cnt),
                              _ptr(per_update) if per_update is not None else None,
                              _ptr(pairs) if pairs is not None else None, cap)
@@ -162,8 +170,9 @@ def match_into(upd_lo, upd_hi, sub_lo, sub_hi, mode: str, workspace: torch.Tenso
     return int(cnt.value)
 
 
-def workspace_bytes(n: int, m: int, d: int, mode: str = "count", pair_capacity: int = 0) -> int:
-    return int(library().ddm_workspace_bytes(n, m, d, MODES[mode], pair_capacity))
+def workspace_bytes(n: int, m: int, d: int, mode: str = "count", pair_capacity: int = 0,
+                    closed: bool = False) -> int:
+    return int(library().ddm_workspace_bytes(n, m, d, _code(mode, closed), pair_capacity))
 
 
 def _check_boxes(lo: torch.Tensor, hi: torch.Tensor, name: str):
@@ -184,11 +193,13 @@ def _ptr(t):
 
 
 def match(upd_lo, upd_hi, sub_lo, sub_hi, mode: str = "count", *, pair_capacity: int | None = None,
-          per_update: bool = True, workspace: torch.Tensor | None = None, stream=None):
+          per_update: bool = True, workspace: torch.Tensor | None = None, stream=None,
+          closed: bool = False):
     """Sort-based matching of update boxes against subscription boxes.
 
     ``upd_lo``/``upd_hi`` are float32 [n, d], ``sub_lo``/``sub_hi`` float32
-    [m, d], all on the same GPU.  Returns
+    [m, d], all on the same GPU; boxes are half-open [lo, hi), or closed
+    [lo, hi] with ``closed=True``.  Returns
       mode="count":      int K (number of intersecting pairs)
       mode="per_update": (K, int32 tensor [n] of matches per update)
       mode="pairs":      (K, int32 tensor [K, 2] of (update id, subscription
@@ -206,7 +217,7 @@ def match(upd_lo, upd_hi, sub_lo, sub_hi, mode: str = "count", *, pair_capacity:
         raise ValueError("all tensors must be on the same device")
     dev = upd_lo.device
     lib = library()
-    code = MODES[mode]
+    code = _code(mode, closed)
     if stream is None:
         stream = torch.cuda.current_stream(dev)
     handle = ctypes.c_void_p(stream.cuda_stream)
@@ -300,11 +311,13 @@ class Batch:
     sub_off[b]:sub_off[b+1]).  Holds the output tensors:
     ``counts`` uint64-as-int64 [B], ``per_update`` int32 [sum n] (modes
     per_update and pairs), ``pairs`` int32 [capacity, 2] and ``pair_off``
-    int64 [B + 1] (mode pairs), and the workspace.
+    int64 [B + 1] (mode pairs), and the workspace.  ``closed=True`` matches
+    closed boxes [lo, hi] instead of half-open ones.
     """
 
     def __init__(self, upd_lo, upd_hi, upd_off, sub_lo, sub_hi, sub_off, mode: str = "count",
-                 pair_capacity: int = 0, workspace: torch.Tensor | None = None):
+                 pair_capacity: int = 0, workspace: torch.Tensor | None = None,
+                 closed: bool = False):
         if mode not in MODES:
             raise ValueError(f"unknown mode {mode!r}")
         _check_boxes(upd_lo, upd_hi, "updates")
@@ -320,7 +333,7 @@ class Batch:
         if int(self.uoff[-1]) != upd_lo.shape[0] or int(self.soff[-1]) != sub_lo.shape[0]:
             raise ValueError("the last offset must equal the number of rows")
         self.mode = mode
-        self.code = MODES[mode]
+        self.code = _code(mode, closed)
         self.dev = upd_lo.device
         self.inputs = (upd_lo, upd_hi, sub_lo, sub_hi)
         self.cap = int(pair_capacity)

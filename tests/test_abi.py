@@ -52,6 +52,12 @@ def test_host_only_queries(lib):
     # pair capacity grows the pair workspace only in pair mode
     assert lib.ddm_workspace_bytes(10, 10, 2, 2, 10**6) > lib.ddm_workspace_bytes(10, 10, 2, 2, 0)
     assert lib.ddm_workspace_bytes(10, 10, 2, 0, 10**6) == lib.ddm_workspace_bytes(10, 10, 2, 0, 0)
+    # the closed-interval flag (16) changes no buffer size; other bits are rejected
+    for mode in (0, 1, 2):
+        assert lib.ddm_workspace_bytes(500, 700, 3, mode | 16, 1000) == \
+            lib.ddm_workspace_bytes(500, 700, 3, mode, 1000)
+    assert lib.ddm_workspace_bytes(10, 10, 2, 32, 0) == 0
+    assert lib.ddm_workspace_bytes(10, 10, 2, 16 | 3, 0) == 0
     lib.ddm_strerror.restype = ctypes.c_char_p
     assert b"workspace" in lib.ddm_strerror(-3)
 
@@ -69,6 +75,7 @@ def test_host_side_argument_errors_return_before_any_launch(lib):
     assert lib.ddm_match(fake, fake, -1, fake, fake, 1, 1, 0, fake, 1 << 30, None, ctypes.byref(cnt), None, None, 0) == -1
     assert lib.ddm_match(fake, fake, 1, fake, fake, 1, 0, 0, fake, 1 << 30, None, ctypes.byref(cnt), None, None, 0) == -1
     assert lib.ddm_match(fake, fake, 1, fake, fake, 1, 1, 9, fake, 1 << 30, None, ctypes.byref(cnt), None, None, 0) == -1
+    assert lib.ddm_match(fake, fake, 1, fake, fake, 1, 1, 16 | 3, fake, 1 << 30, None, ctypes.byref(cnt), None, None, 0) == -1
     assert lib.ddm_match(fake, fake, 1, fake, fake, 1, 1, 0, fake, 1 << 30, None, None, None, None, 0) == -1
     assert lib.ddm_match(None, fake, 1, fake, fake, 1, 1, 0, fake, 1 << 30, None, ctypes.byref(cnt), None, None, 0) == -1
     # per-update mode without the output, pair mode without the pair buffer

@@ -247,3 +247,44 @@ def test_batched_invalid_input(ddm):
         graph.result()
     assert e.value.code == ddm.DDM_E_INVAL
     graph.close()
+
+
+# ------------------------------------------------------- closed intervals
+
+def _closed_refs(oracle, insts):
+    return [oracle.sbm(t.upd_lo, t.upd_hi, t.sub_lo, t.sub_hi, pairs=True, closed=True)
+            for t in insts]
+
+
+def _closed_batch(ddm, insts, mode, cap=0):
+    ulo, uhi, uoff, slo, shi, soff = W.concat_instances(insts)
+    g = [torch.from_numpy(a).cuda() for a in (ulo, uhi, slo, shi)]
+    return ddm.Batch(g[0], g[1], uoff, g[2], g[3], soff, mode=mode, pair_capacity=cap,
+                     closed=True)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_closed_batched_and_graph(ddm, oracle, d):
+    """Closed boxes through the batched call and the captured graph."""
+    insts = _mixed(d, seed=20 + d)
+    refs = _closed_refs(oracle, insts)
+    K = sum(r[0] for r in refs)
+    _note(f"closed batched d={d} B={len(insts)} K={K}")
+    batch = _closed_batch(ddm, insts, "pairs", cap=K + 10)
+    _check(batch, insts, refs, "pairs", batch.run())
+    graph = batch.graph()
+    for _ in range(2):
+        graph.launch()
+        _check(batch, insts, refs, "pairs", graph.result())
+        batch.pairs.fill_(-1)
+        torch.cuda.synchronize()
+    graph.close()
+
+
+def test_closed_batched_high_d_runs_each(ddm, oracle):
+    """d = 5 goes instance by instance through the single call, which must
+    keep the closed reading."""
+    insts = [W.tie_heavy(300, 250, 5, grid=8, max_len=3, seed=s) for s in range(3)]
+    refs = _closed_refs(oracle, insts)
+    batch = _closed_batch(ddm, insts, "pairs", cap=sum(r[0] for r in refs) + 1)
+    _check(batch, insts, refs, "pairs", batch.run())

@@ -50,24 +50,25 @@ def _reset_path(ddm):
     ddm.set_path("auto")
 
 
-def check_all_modes(ddm, oracle, inst, pairs=True, expect_bucketed=None):
-    """Every output mode, on both implementations, equal to the oracle.
-    Returns the implementation that served the "auto" calls."""
-    k_ref, per_ref, pairs_ref = oracle.sbm(*_host(inst), pairs=pairs)
+def check_all_modes(ddm, oracle, inst, pairs=True, expect_bucketed=None, closed=False):
+    """Every output mode, on both implementations, equal to the oracle
+    (closed boxes with ``closed``).  Returns the implementation that served
+    the "auto" calls."""
+    k_ref, per_ref, pairs_ref = oracle.sbm(*_host(inst), pairs=pairs, closed=closed)
     g = _dev(inst)
     served = None
     for path in PATHS:
-        _note(f"{inst.name} n={inst.n} m={inst.m} d={inst.d} path={path}")
+        _note(f"{inst.name} n={inst.n} m={inst.m} d={inst.d} path={path} closed={closed}")
         ddm.set_path(path)
-        k = ddm.match(*g, mode="count")
+        k = ddm.match(*g, mode="count", closed=closed)
         assert k == k_ref, (inst.name, path, k, k_ref)
         if path == "auto":
             served = ddm.last_path()
-        k1, per = ddm.match(*g, mode="per_update")
+        k1, per = ddm.match(*g, mode="per_update", closed=closed)
         assert k1 == k_ref, (inst.name, path)
         assert np.array_equal(per.cpu().numpy(), per_ref), (inst.name, path)
         if pairs:
-            k2, pr, per2 = ddm.match(*g, mode="pairs")
+            k2, pr, per2 = ddm.match(*g, mode="pairs", closed=closed)
             assert k2 == k_ref, (inst.name, path)
             assert np.array_equal(pr.cpu().numpy(), pairs_ref), (inst.name, path)
             assert np.array_equal(per2.cpu().numpy(), per_ref), (inst.name, path)
@@ -320,3 +321,64 @@ def test_dim_counts_equal_closed_form(ddm, inst_fn):
     want = [int(O.closed_form_1d(*_host(inst), axis=k).sum()) for k in range(inst.d)]
     _note(f"dim counts {inst.name}: {got}")
     assert got == want
+
+
+# ------------------------------------------------------- closed intervals
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_closed_tie_heavy_small(ddm, oracle, d):
+    rng = np.random.default_rng(177 + d)
+    for seed in range(30):
+        n, m = int(rng.integers(0, 60)), int(rng.integers(0, 60))
+        inst = W.tie_heavy(n, m, d, grid=int(rng.integers(2, 20)), max_len=int(rng.integers(0, 6)),
+                           seed=seed)
+        check_all_modes(ddm, oracle, inst, expect_bucketed=inst.n + inst.m > 0, closed=True)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_closed_tie_heavy_many_buckets(ddm, oracle, d):
+    """Points and touching intervals everywhere, thousands of buckets."""
+    inst = W.tie_heavy(30_000, 25_000, d, grid=4000, max_len=40, seed=12)
+    check_all_modes(ddm, oracle, inst, closed=True)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 5])
+def test_closed_random_float_boxes(ddm, oracle, d):
+    for seed in range(4):
+        inst = W.random_float_boxes(700, 900, d, seed=seed, extent=300.0)
+        check_all_modes(ddm, oracle, inst, expect_bucketed=d <= 3, closed=True)
+
+
+def test_closed_infinite_and_zero_bounds(ddm, oracle):
+    """Closed boxes reaching +-inf (enc(+inf) + 1 must not wrap) and points at
+    signed zero."""
+    rng = np.random.default_rng(5)
+    inst = W.tie_heavy(3000, 3000, 2, grid=50, max_len=3, seed=5)
+    ul, uh, sl, sh = (a.copy() for a in _host(inst))
+    inf = np.float32(np.inf)
+    for lo, hi in ((ul, uh), (sl, sh)):
+        rows = rng.choice(lo.shape[0], 200, replace=False)
+        hi[rows[:100], 0] = inf
+        lo[rows[100:150], 0] = -inf
+        lo[rows[150:], 1] = -0.0
+        hi[rows[150:], 1] = 0.0
+    check_all_modes(ddm, oracle, W.Instance(ul, uh, sl, sh, float("nan"), "closed_inf"),
+                    closed=True)
+
+
+@pytest.mark.parametrize("d,alpha", [(2, 1.0), (2, 100.0), (3, 100.0)])
+def test_closed_paper_workload(ddm, oracle, d, alpha):
+    inst = W.uniform_instance(200_000, 200_000, d, alpha, seed=21)
+    check_all_modes(ddm, oracle, inst, pairs=d == 2, closed=True)
+
+
+def test_closed_full_size_equals_half_open_next_float(ddm):
+    """At the d = 3, n = m = 5e6 size: closed [lo, hi] matches exactly as
+    half-open [lo, nextafter(hi)), per update."""
+    inst = W.uniform_instance(5_000_000, 5_000_000, 3, 100.0, seed=0)
+    g = _dev(inst)
+    up = [torch.nextafter(t, torch.tensor(float("inf"), device=t.device)) for t in (g[1], g[3])]
+    _note("closed vs next-float half-open, d=3 n=m=5e6")
+    kc, pc = ddm.match(*g, mode="per_update", closed=True)
+    kh, ph = ddm.match(g[0], up[0], g[2], up[1], mode="per_update")
+    assert kc == kh and torch.equal(pc, ph)

@@ -22,23 +22,23 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _sbm_body(src):
-    start = src.index("int oracle_sbm(")
-    end = src.index("int64_t oracle_sweep_state(")
+    start = src.index("static int sbm(")
+    end = src.index("/* Public entry points")
     return start, end
 
 
 MUTANTS = {
     # half-open filter on the other axes becomes closed
-    "closed_other_axes": ("all", "return a_low < b_high && b_low < a_high;",
+    "closed_other_axes": ("all", "return before(rd, a_low, b_high) && before(rd, b_low, a_high);",
                           "return a_low <= b_high && b_low <= a_high;"),
     # ties sort lower-before-upper
-    "lower_before_upper": ("all", "if (x->type != y->type) return x->type < y->type ? -1 : 1;",
-                           "if (x->type != y->type) return x->type > y->type ? -1 : 1;"),
+    "lower_before_upper": ("all", "    return type == TYPE_UPPER ? 0 : 1;",
+                           "    return type == TYPE_LOWER ? 0 : 1;"),
     # ties by coordinate only
-    "coordinate_only_order": ("all", "if (x->type != y->type) return x->type < y->type ? -1 : 1;",
+    "coordinate_only_order": ("all", "if (x->rank != y->rank) return x->rank < y->rank ? -1 : 1;",
                               "return 0;"),
     # empty regions kept in the sweep
-    "keep_empties": ("sbm", "if (is_empty(ulo, uhi, i, d)) continue;", ""),
+    "keep_empties": ("all", "if (is_empty(rd, ulo, uhi, i, d)) continue;", ""),
     # other axes never tested
     "no_axis_filter": ("all", "for (int k = 1; k < d; ++k)", "for (int k = 1; k < 1; ++k)"),
     # wrong axis range in the filter (0..d-2 instead of 1..d-1)
@@ -47,12 +47,12 @@ MUTANTS = {
     "drop_update_upper_emission": ("sbm", "report(&s, e->id, sb);", "(void)sb;"),
     # ids swapped when reporting at subscription uppers
     "swapped_report_operands": ("sbm", "report(&s, u, e->id);", "report(&s, e->id, u);"),
-    # the sweep uses axis 1 for the endpoints when d > 1
-    "sweep_wrong_axis": ("sbm", "T[t++] = (Endpoint){(double)uhi[i * d], TYPE_UPPER, KIND_UPD, i};",
-                         "T[t++] = (Endpoint){(double)uhi[i * d + (d - 1)], TYPE_UPPER, KIND_UPD, i};"),
+    # the sweep uses axis d-1 for the update upper endpoints
+    "sweep_wrong_axis": ("all", "T[t++] = (Endpoint){(double)uhi[i * d], TYPE_UPPER, ru, KIND_UPD, i};",
+                         "T[t++] = (Endpoint){(double)uhi[i * d + (d - 1)], TYPE_UPPER, ru, KIND_UPD, i};"),
     # the lower endpoint of subscriptions is taken from the upper array
-    "lower_from_upper_array": ("sbm", "T[t++] = (Endpoint){(double)slo[j * d], TYPE_LOWER, KIND_SUB, j};",
-                               "T[t++] = (Endpoint){(double)shi[j * d], TYPE_LOWER, KIND_SUB, j};"),
+    "lower_from_upper_array": ("all", "T[t++] = (Endpoint){(double)slo[j * d], TYPE_LOWER, rl, KIND_SUB, j};",
+                               "T[t++] = (Endpoint){(double)shi[j * d], TYPE_LOWER, rl, KIND_SUB, j};"),
     # per-update histogram indexed by the subscription id
     "histogram_by_sub": ("all", "if (s->per_update) s->per_update[upd] += 1;",
                          "if (s->per_update) s->per_update[sub % 1] += 1;"),
@@ -60,6 +60,13 @@ MUTANTS = {
     "no_order_validation": ("all", "if (l > h) return OR_E_INVAL;", ""),
     # pairs not sorted at the end
     "unsorted_pairs": ("all", "qsort(s->pairs, (size_t)s->count, 2 * sizeof(int32_t), cmp_pair);", ""),
+    # closed reading: ties sort upper-before-lower
+    "closed_upper_first": ("all", "if (rd->closed) return type == TYPE_LOWER ? 0 : 1;",
+                           "if (rd->closed) return type == TYPE_UPPER ? 0 : 1;"),
+    # closed reading: points (lo == hi) dropped as if empty
+    "closed_drops_points": ("all", "if (rd->closed) return 0;", ""),
+    # closed reading: strict comparisons
+    "closed_strict": ("all", "return rd->closed ? a <= b : a < b;", "return a < b;"),
 }
 
 
@@ -94,6 +101,21 @@ BATTERY = textwrap.dedent(r"""
                 check("count", k == int(hit.sum()))
                 check("pairs", np.array_equal(pairs, O.pairs_from_matrix(hit)))
                 check("per_update", np.array_equal(per, hit.sum(axis=1).astype(np.int32)))
+    # closed intervals: the plain definition with <=, and its 1-D closed form
+    for d in (1, 2, 3):
+        for seed in range(15):
+            inst = W.tie_heavy(19, 19, d, seed=seed)
+            a = (inst.upd_lo, inst.upd_hi, inst.sub_lo, inst.sub_hi)
+            hit = O.bruteforce_numpy(*a, closed=True)
+            try:
+                k, per, pairs = o.sbm(*a, closed=True)
+            except Exception:
+                fails.append("closed-raised"); continue
+            check("closed-count", k == int(hit.sum()))
+            check("closed-pairs", np.array_equal(pairs, O.pairs_from_matrix(hit)))
+            if d == 1:
+                check("closed-form", np.array_equal(per.astype(np.int64),
+                                                    O.closed_form_1d(*a, closed=True)))
     # closed form on one axis
     inst = W.uniform_instance(3000, 3000, 1, 1.0, seed=1)
     a = (inst.upd_lo, inst.upd_hi, inst.sub_lo, inst.sub_hi)
