@@ -148,6 +148,74 @@ def bench_batched(args, ddm, W, torch, np):
     }
 
 
+def bench_output_heavy(args, ddm, W, torch, np):
+    """The output-bound case: d = 1, n = m = 5e6, alpha = 100, so about 5e8
+    pairs (4 GB as a pair list, 2 GB as CSR).  Times the pair list and the
+    CSR output, checks the per-update counts against the 1-D counting
+    identity and the order of every row, and reports the written bytes per
+    second against HBM peak."""
+    dev = torch.device("cuda:0")
+    n = m = args.heavy_n
+    inst = W.uniform_instance(n, m, 1, 100.0, seed=0)
+    g = [torch.from_numpy(a).to(dev) for a in (inst.upd_lo, inst.upd_hi, inst.sub_lo, inst.sub_hi)]
+    # expected per-update counts: #{s.lo < u.hi} - #{s.hi <= u.lo} (no empty boxes here)
+    s_lo = torch.sort(g[2][:, 0]).values
+    s_hi = torch.sort(g[3][:, 0]).values
+    want = (torch.searchsorted(s_lo, g[1][:, 0], right=False) -
+            torch.searchsorted(s_hi, g[0][:, 0], right=True))
+    K = int(want.sum())
+    cap = K
+    stream = torch.cuda.current_stream(dev)
+    ws = torch.empty(ddm.workspace_bytes(n, m, 1, "pairs", cap), dtype=torch.uint8, device=dev)
+    out = {"workload": f"uniform intervals d=1, n=m={n}, alpha=100, side=alpha*1e6/N",
+           "pairs": K}
+    for kind in ("csr", "pairs"):
+        if kind == "csr":
+            row_off = torch.empty(n + 1, dtype=torch.int64, device=dev)
+            ids = torch.empty(cap, dtype=torch.int32, device=dev)
+            call = lambda: ddm.match_csr_into(*g, workspace=ws, row_off=row_off, sub_ids=ids,  # noqa: E731
+                                              stream=stream)
+            written = 4 * K + 8 * (n + 1)
+        else:
+            pairs = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+            per = torch.empty(n, dtype=torch.int32, device=dev)
+            call = lambda: ddm.match_into(*g, mode="pairs", workspace=ws, per_update=per,  # noqa: E731
+                                          pairs=pairs, stream=stream)
+            written = 8 * K + 4 * n
+        k = call()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.heavy_reps):
+            k = call()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t) / args.heavy_reps
+        ddm.profile(True)
+        call()
+        torch.cuda.synchronize()
+        phases = {p: round(v["ms"], 3) for p, v in sorted(ddm.profile_report().items())}
+        ddm.profile(False)
+        if kind == "csr":
+            counts = row_off[1:] - row_off[:-1]
+            first = torch.zeros(K, dtype=torch.bool, device=dev)
+            first[row_off[:-1][counts > 0]] = True
+            ordered = bool((first[1:] | (ids[1:] > ids[:-1])).all())
+            ok = k == K and bool(torch.equal(counts, want)) and ordered
+            del row_off, ids, first
+        else:
+            ordered = bool(((pairs[1:, 0] > pairs[:-1, 0]) |
+                            ((pairs[1:, 0] == pairs[:-1, 0]) & (pairs[1:, 1] > pairs[:-1, 1]))).all())
+            ok = k == K and bool(torch.equal(per.to(torch.int64), want)) and ordered
+            del pairs, per
+        alg = 8 * (n + m) + written
+        out[kind] = {"ms": round(ms, 3), "pairs_per_s": round(K / (ms * 1e-3), 1),
+                     "written_bytes": written, "hbm_frac": round(alg / (ms * 1e-3) / 1e9 /
+                                                                  HBM_PEAK_GBS, 4),
+                     "exact_counts_and_order": ok, "phases_ms": phases}
+    del ws
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_served(args, ddm, W, torch, np):
     """32 resident d=2 simulations (n = m log-uniform on [1e4, 2e6], alpha = 1,
     random-walk sigma = 0.1 * side); open-loop Poisson traces at fractions of
@@ -250,6 +318,10 @@ def main():
                     help="skip the per-phase event timing (roofline becomes null)")
     ap.add_argument("--no-closed", action="store_true",
                     help="skip the closed-interval measurement of the headline workload")
+    ap.add_argument("--no-heavy", action="store_true",
+                    help="skip the output-heavy (d=1, alpha=100, ~5e8 pairs) measurement")
+    ap.add_argument("--heavy-n", type=int, default=5_000_000)
+    ap.add_argument("--heavy-reps", type=int, default=3)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched measurement")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-reps", type=int, default=5)
@@ -401,6 +473,7 @@ def main():
                "sample": f"the full workload (n = m = {n}, d = {d}, alpha = {args.alpha:g}), one "
                          f"serial run of the C oracle ({dt:.2f} s), checked equal to the GPU result"}
 
+    heavy = None if args.no_heavy else bench_output_heavy(args, ddm, W, torch, np)
     batched = None if args.no_batched else bench_batched(args, ddm, W, torch, np)
     served = None if args.no_served else bench_served(args, ddm, W, torch, np)
 
@@ -432,6 +505,7 @@ def main():
         "closed": closed,
         "served_p50_ms": served["levels"]["1x"]["batched"]["p50_ms"] if served else None,
         "served_p99_ms": served["levels"]["1x"]["batched"]["p99_ms"] if served else None,
+        "output_heavy": heavy,
         "batched": batched,
         "served": served,
         "input_generation_s": round(gen_s, 2),

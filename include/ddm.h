@@ -112,6 +112,31 @@ int ddm_match(const float *upd_lo, const float *upd_hi, int64_t n,
               int32_t *pairs, int64_t pair_capacity);
 
 /*
+ * The same matching with the result as compressed rows (CSR), the form an
+ * event router consumes: update i's matching subscriptions are
+ * sub_ids[row_off[i] .. row_off[i+1]), in ascending order.  This is the pair
+ * list of DDM_PAIRS without its first column (the pairs of the problem
+ * statement of Sec. 3, grouped by update).
+ *
+ *   flags      0 or DDM_CLOSED
+ *   workspace  at least ddm_workspace_bytes(n, m, d, DDM_PAIRS | flags,
+ *              capacity) bytes, 256-byte aligned
+ *   row_off    device, out, int64 [n + 1] (required): row_off[0] = 0,
+ *              row_off[n] = K
+ *   sub_ids    device, out, int32 [capacity] (required if capacity > 0)
+ *   capacity   entries available in sub_ids
+ *
+ * Other arguments and errors as for ddm_match().  If K > capacity the call
+ * returns DDM_E_CAPACITY with *count_host = K and row_off complete (sub_ids
+ * untouched), so the caller can size sub_ids and retry.
+ */
+int ddm_match_csr(const float *upd_lo, const float *upd_hi, int64_t n,
+                  const float *sub_lo, const float *sub_hi, int64_t m,
+                  int d, int flags, void *workspace, size_t ws_bytes, void *stream,
+                  uint64_t *count_host, int64_t *row_off, int32_t *sub_ids,
+                  int64_t capacity);
+
+/*
  * Per-axis 1-D candidate counts (diagnostic).  counts_host[k] (host, [d])
  * receives K_1D(k): the number of (update, subscription) pairs whose
  * intervals on axis k intersect, counted among the boxes that are non-empty

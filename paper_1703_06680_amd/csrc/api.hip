@@ -164,7 +164,19 @@ struct Call {
   int64_t cap;
   Header *hdr;
   int32_t *cnt;  // per-update counts (caller's or workspace), pair/per-update modes
+  // CSR output instead of the pair list (pair mode): row offsets [n + 1] and
+  // subscription ids [cap], or null
+  int64_t *csr_off;
+  int32_t *csr_ids;
 };
+
+// CSR output of a call with no pairs: every row empty.
+int csr_zero(const Call &c) {
+  if (!c.csr_off) return DDM_OK;
+  DDM_HIP(fill_u64(reinterpret_cast<unsigned long long *>(c.csr_off), 0ull, (size_t)c.n + 1, c.s));
+  DDM_HIP(hipStreamSynchronize(c.s));
+  return DDM_OK;
+}
 
 int reset_outputs(const Call &c) {
   DDM_HIP(hipMemsetAsync(c.hdr, 0, sizeof(Header), c.s));
@@ -175,26 +187,67 @@ int reset_outputs(const Call &c) {
 }
 
 // Pair list from per-update counts already in c.cnt and K pairs: offsets,
-// the emitting sweep (``emit``), lexicographic ordering into c.pairs.
+// the emitting sweep (``emit``), lexicographic ordering into c.pairs (or,
+// for CSR output, the offsets into c.csr_off and the ordered subscription
+// ids into c.csr_ids; the offsets are written even when K exceeds the
+// capacity).
 template <typename Emit>
 int finish_pairs(const Call &c, unsigned long long K, Emit emit) {
+  const Layout &L = c.L;
+  unsigned long long *off = c.csr_off ? reinterpret_cast<unsigned long long *>(c.csr_off)
+                                      : at<unsigned long long>(c.ws, L.off);
+  // offsets, and the longest row into hdr->aux[1]
+  auto offsets = [&]() -> int {
+    DDM_HIP(fill_u64(&c.hdr->aux[1], 0ull, 1, c.s));
+    launch_widen(c.cnt, off, (size_t)c.n, c.s, &c.hdr->aux[1]);
+    prof::mark(c.s, "pairs.scan");
+    DDM_HIP(exclusive_scan_u64(off, off, (size_t)c.n, at<void>(c.ws, L.scan_tmp), c.s));
+    return DDM_OK;
+  };
+  if (c.csr_off) {
+    const int rc = offsets();
+    if (rc != DDM_OK) return rc;
+    DDM_HIP(fill_u64(off + c.n, K, 1, c.s));  // row_off[n] = K
+    if ((int64_t)K > c.cap || K == 0) {
+      prof::end(c.s);
+      DDM_HIP(hipStreamSynchronize(c.s));
+      prof::flush();
+      return (int64_t)K > c.cap ? DDM_E_CAPACITY : DDM_OK;
+    }
+  }
   if ((int64_t)K > c.cap) return DDM_E_CAPACITY;
   if (K >= (1ull << 32)) return DDM_E_UNSUPPORTED;  // pair staging uses 32-bit positions
-  const Layout &L = c.L;
-  unsigned long long *off = at<unsigned long long>(c.ws, L.off);
   uint32_t *cur = at<uint32_t>(c.ws, L.cur);
   uint32_t *pu = at<uint32_t>(c.ws, L.pu), *ps = at<uint32_t>(c.ws, L.ps);
   uint32_t *pu2 = at<uint32_t>(c.ws, L.pu2), *ps2 = at<uint32_t>(c.ws, L.ps2);
-  launch_widen(c.cnt, off, (size_t)c.n, c.s);
-  prof::mark(c.s, "pairs.scan");
-  DDM_HIP(exclusive_scan_u64(off, off, (size_t)c.n, at<void>(c.ws, L.scan_tmp), c.s));
+  if (!c.csr_off) {
+    const int rc = offsets();
+    if (rc != DDM_OK) return rc;
+  }
+  // rows of at most kRowMax pairs are ordered one by one, in LDS; otherwise
+  // the pairs are sorted device-wide by (update, subscription)
+  unsigned long long longest = 0;
+  DDM_HIP(hipMemcpyAsync(&longest, &c.hdr->aux[1], sizeof(longest), hipMemcpyDeviceToHost, c.s));
+  DDM_HIP(hipStreamSynchronize(c.s));
+  const bool by_rows = longest <= kRowMax;
   prof::mark(c.s, "pairs.memset");
   DDM_HIP(hipMemsetAsync(cur, 0, (size_t)c.n * sizeof(uint32_t), c.s));
-  DDM_HIP(emit(off, cur, pu, ps));
-  uint32_t *ru = nullptr, *rs = nullptr;
-  DDM_HIP(order_pairs(pu, ps, pu2, ps2, (uint32_t)K, c.n, c.m, at<void>(c.ws, L.pair_sort_tmp),
-                      c.s, &ru, &rs));
-  launch_interleave(ru, rs, c.pairs, (size_t)K, c.s);
+  DDM_HIP(emit(off, cur, by_rows ? nullptr : pu, ps));
+  if (by_rows) {
+    launch_row_sort(off, c.cnt, ps, (uint32_t)c.n, reinterpret_cast<uint32_t *>(c.csr_ids),
+                    c.csr_ids ? nullptr : c.pairs, c.s);
+  } else {
+    uint32_t *ru = nullptr, *rs = nullptr;
+    DDM_HIP(order_pairs(pu, ps, pu2, ps2, (uint32_t)K, c.n, c.m,
+                        at<void>(c.ws, L.pair_sort_tmp), c.s, &ru, &rs));
+    if (c.csr_ids) {
+      prof::mark(c.s, "pairs.csr");
+      DDM_HIP(hipMemcpyAsync(c.csr_ids, rs, (size_t)K * sizeof(uint32_t),
+                             hipMemcpyDeviceToDevice, c.s));
+    } else {
+      launch_interleave(ru, rs, c.pairs, (size_t)K, c.s);
+    }
+  }
   DDM_HIP(hipGetLastError());
   prof::end(c.s);
   DDM_HIP(hipStreamSynchronize(c.s));
@@ -224,7 +277,7 @@ int run_bucketed(const Call &c) {
   if (h.err) return DDM_E_INVAL;
   if (h.pad[0]) return kFallback;
   *c.count_host = h.total;
-  if (c.mode != DDM_PAIRS || h.total == 0) return DDM_OK;
+  if (c.mode != DDM_PAIRS || (h.total == 0 && !c.csr_off)) return DDM_OK;
   return finish_pairs(c, h.total, [&](unsigned long long *off, uint32_t *cur, uint32_t *pu,
                                       uint32_t *ps) {
     return bucket_sweep(a, 2, nullptr, off, cur, pu, ps, &c.hdr->aux[0], c.s);
@@ -253,7 +306,7 @@ int run_global(const Call &c) {
   prof::flush();
   if (h.err) return DDM_E_INVAL;
   const uint32_t nne = h.nonempty;
-  if (nne == 0 || c.n == 0 || c.m == 0) return DDM_OK;  // counts already zeroed
+  if (nne == 0 || c.n == 0 || c.m == 0) return csr_zero(c);  // counts already zeroed
 
   // 2. radix sort of the lower keys (range-reduced; empties last)
   const bool has_empty = nne < N;
@@ -296,7 +349,7 @@ int run_global(const Call &c) {
   DDM_HIP(hipStreamSynchronize(c.s));
   prof::flush();
   *c.count_host = K;
-  if (c.mode != DDM_PAIRS || K == 0) return DDM_OK;
+  if (c.mode != DDM_PAIRS || (K == 0 && !c.csr_off)) return DDM_OK;
   return finish_pairs(c, K, [&](unsigned long long *off, uint32_t *cur, uint32_t *pu,
                                 uint32_t *ps) {
     SweepArgs e = a;
@@ -435,10 +488,14 @@ extern "C" int ddm_set_path(int path) {
 
 extern "C" int ddm_last_path(void) { return g_last_path; }
 
-extern "C" int ddm_match(const float *upd_lo, const float *upd_hi, int64_t n, const float *sub_lo,
-                         const float *sub_hi, int64_t m, int d, int mode, void *workspace,
-                         size_t ws_bytes, void *stream, uint64_t *count_host, int32_t *per_update,
-                         int32_t *pairs, int64_t pair_capacity) {
+namespace {
+
+// ddm_match and ddm_match_csr: the pair list goes to ``pairs``, or, with
+// csr_off given, CSR rows to csr_off / csr_ids.
+int match_entry(const float *upd_lo, const float *upd_hi, int64_t n, const float *sub_lo,
+                const float *sub_hi, int64_t m, int d, int mode, void *workspace, size_t ws_bytes,
+                void *stream, uint64_t *count_host, int32_t *per_update, int32_t *pairs,
+                int64_t pair_capacity, int64_t *csr_off, int32_t *csr_ids) {
   // host-side checks: nothing is launched when one fails
   const int mode_arg = mode;  // with the interval flag (the graph cache key)
   bool closed;
@@ -446,7 +503,7 @@ extern "C" int ddm_match(const float *upd_lo, const float *upd_hi, int64_t n, co
   if (!sizes_ok(n, m, d, mode) || !count_host || pair_capacity < 0) return DDM_E_INVAL;
   if ((n > 0 && (!upd_lo || !upd_hi)) || (m > 0 && (!sub_lo || !sub_hi))) return DDM_E_INVAL;
   if (mode == DDM_PER_UPDATE && n > 0 && !per_update) return DDM_E_INVAL;
-  if (mode == DDM_PAIRS && pair_capacity > 0 && !pairs) return DDM_E_INVAL;
+  if (mode == DDM_PAIRS && pair_capacity > 0 && !(csr_off ? csr_ids : pairs)) return DDM_E_INVAL;
   const bool graphable = mode != DDM_PAIRS && n + m > 0 && !prof::enabled() &&
                          g_path_request != DDM_PATH_GLOBAL && workspace &&
                          !(reinterpret_cast<uintptr_t>(workspace) & 255);
@@ -508,10 +565,13 @@ extern "C" int ddm_match(const float *upd_lo, const float *upd_hi, int64_t n, co
   c.hdr = at<Header>(workspace, c.L.hdr);
   c.cnt = mode == DDM_PAIRS ? (per_update ? per_update : at<int32_t>(workspace, c.L.cnt))
                             : per_update;
+  c.csr_off = csr_off;
+  c.csr_ids = csr_ids;
   g_last_path = 0;
   if (n + m == 0) {
-    const int rc = reset_outputs(c);
+    int rc = reset_outputs(c);
     if (rc == DDM_OK && hipStreamSynchronize(c.s) != hipSuccess) return DDM_E_DEVICE;
+    if (rc == DDM_OK) rc = csr_zero(c);
     return rc;
   }
   if (g_path_request == DDM_PATH_BUCKETED && !c.L.bucket_ok) return DDM_E_UNSUPPORTED;
@@ -544,4 +604,23 @@ extern "C" int ddm_match(const float *upd_lo, const float *upd_hi, int64_t n, co
   rc = run_global(c);
   if (rc == DDM_OK || rc == DDM_E_CAPACITY) g_last_path = DDM_PATH_GLOBAL;
   return rc;
+}
+
+}  // namespace
+
+extern "C" int ddm_match(const float *upd_lo, const float *upd_hi, int64_t n, const float *sub_lo,
+                         const float *sub_hi, int64_t m, int d, int mode, void *workspace,
+                         size_t ws_bytes, void *stream, uint64_t *count_host, int32_t *per_update,
+                         int32_t *pairs, int64_t pair_capacity) {
+  return match_entry(upd_lo, upd_hi, n, sub_lo, sub_hi, m, d, mode, workspace, ws_bytes, stream,
+                     count_host, per_update, pairs, pair_capacity, nullptr, nullptr);
+}
+
+extern "C" int ddm_match_csr(const float *upd_lo, const float *upd_hi, int64_t n,
+                             const float *sub_lo, const float *sub_hi, int64_t m, int d, int flags,
+                             void *workspace, size_t ws_bytes, void *stream, uint64_t *count_host,
+                             int64_t *row_off, int32_t *sub_ids, int64_t capacity) {
+  if ((flags & ~DDM_CLOSED) != 0 || !row_off) return DDM_E_INVAL;
+  return match_entry(upd_lo, upd_hi, n, sub_lo, sub_hi, m, d, DDM_PAIRS | flags, workspace,
+                     ws_bytes, stream, count_host, nullptr, nullptr, capacity, row_off, sub_ids);
 }

@@ -720,7 +720,7 @@ __device__ __forceinline__ void visit(const Walker<DM1> &y, bool &have_y, float 
     const uint32_t uu = y.upd ? y.rid : rx;
     const uint32_t sid = (y.upd ? rx : y.rid) - o.n;
     const unsigned long long slot = o.pair_off[uu] + atomicAdd(&o.cursor[uu], 1u);
-    o.out_u[slot] = uu;
+    if (o.out_u) o.out_u[slot] = uu;  // null: rows are implied by the offsets
     o.out_s[slot] = sid;
   }
 }
@@ -744,7 +744,7 @@ __device__ __forceinline__ void resolve(uint32_t ry, uint32_t rx, unsigned long 
     atomicAdd(&o.per_update[uu], 1);
   } else if (MODE == 2) {
     const unsigned long long slot = o.pair_off[uu] + atomicAdd(&o.cursor[uu], 1u);
-    o.out_u[slot] = uu;
+    if (o.out_u) o.out_u[slot] = uu;  // null: rows are implied by the offsets
     o.out_s[slot] = ss - o.n;
   }
 }

@@ -208,7 +208,7 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(
           atomicAdd(&per_update[u], 1);
       } else if (kMode == 2) {
         const unsigned long long slot = offsets[u] + atomicAdd(&cursor[u], 1u);
-        out_u[slot] = u;
+        if (out_u) out_u[slot] = u;  // null: rows are implied by the offsets
         out_s[slot] = s;
       }
     }
@@ -230,10 +230,73 @@ __global__ void interleave_kernel(const uint32_t *__restrict__ u, const uint32_t
 }
 
 __global__ void widen_kernel(const int32_t *__restrict__ in, unsigned long long *__restrict__ out,
-                             size_t count) {
+                             size_t count, unsigned long long *__restrict__ max_out) {
+  unsigned long long most = 0;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-       i += (size_t)gridDim.x * blockDim.x)
-    out[i] = (unsigned long long)(uint32_t)in[i];
+       i += (size_t)gridDim.x * blockDim.x) {
+    const unsigned long long v = (uint32_t)in[i];
+    out[i] = v;
+    most = v > most ? v : most;
+  }
+  if (max_out) {
+    most = wave_max(most);
+    if (lane_id() == 0 && most) atomicMax(max_out, most);
+  }
+}
+
+// Orders every row of an emitted pair list: row u holds the cnt[u]
+// subscription ids of update u at in[off[u] ..), in the order the sweep found
+// them.  One wave per row: the row is staged in the wave's LDS slice and
+// every id goes to off[u] + (number of ids of the row below it); ids in a
+// row are distinct (every pair is found once), so the ranks are a
+// permutation.  Rows of at most kRowMax ids.
+constexpr int kRowWaves = kThreads / kWave;
+
+template <bool kPairs>
+__global__ __launch_bounds__(kThreads) void row_sort_kernel(
+    const unsigned long long *__restrict__ off, const int32_t *__restrict__ cnt,
+    const uint32_t *__restrict__ in, uint32_t n, uint32_t *__restrict__ ids,
+    int2 *__restrict__ pairs) {
+  constexpr int kPer = 4;  // ids per lane per scan of the row
+  __shared__ __align__(16) uint32_t stage[kRowWaves][kRowMax];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  uint32_t *row = stage[w];
+  const uint32_t step = gridDim.x * kRowWaves;
+  for (uint32_t u = blockIdx.x * kRowWaves + w; u < n; u += step) {
+    const uint32_t L = (uint32_t)cnt[u];
+    if (L == 0 || L > kRowMax) continue;  // longer rows are never passed here
+    const unsigned long long base = off[u];
+    const uint32_t L4 = (L + 3) & ~3u;  // padded with ids above every real one
+    for (uint32_t i = lane; i < L4; i += kWave) row[i] = i < L ? in[base + i] : 0xFFFFFFFFu;
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t i0 = 0; i0 < L; i0 += kPer * kWave) {
+      uint32_t v[kPer], rank[kPer];
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        const uint32_t i = i0 + k * kWave + lane;
+        v[k] = i < L ? row[i] : 0xFFFFFFFFu;
+        rank[k] = 0;
+      }
+      for (uint32_t j = 0; j < L4; j += 4) {
+        const uint4 q = *reinterpret_cast<const uint4 *>(row + j);  // same address in every lane
+#pragma unroll
+        for (int k = 0; k < kPer; ++k)
+          rank[k] += (uint32_t)(q.x < v[k]) + (uint32_t)(q.y < v[k]) + (uint32_t)(q.z < v[k]) +
+                     (uint32_t)(q.w < v[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        const uint32_t i = i0 + k * kWave + lane;
+        if (i < L) {
+          if (kPairs)
+            pairs[base + rank[k]] = make_int2((int32_t)u, (int32_t)v[k]);
+          else
+            ids[base + rank[k]] = v[k];
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();  // every lane done with the row before the next one
+  }
 }
 
 inline unsigned grid_for(size_t count, unsigned cap = 8192) {
@@ -312,10 +375,23 @@ void launch_interleave(const uint32_t *u, const uint32_t *sidx, int32_t *out, si
   interleave_kernel<<<grid_for(count), kThreads, 0, s>>>(u, sidx, out, count);
 }
 
-void launch_widen(const int32_t *in, unsigned long long *out, size_t count, hipStream_t s) {
+void launch_widen(const int32_t *in, unsigned long long *out, size_t count, hipStream_t s,
+                  unsigned long long *max_out) {
   if (!count) return;
   prof::mark(s, "pairs.widen");
-  widen_kernel<<<grid_for(count), kThreads, 0, s>>>(in, out, count);
+  widen_kernel<<<grid_for(count), kThreads, 0, s>>>(in, out, count, max_out);
+}
+
+void launch_row_sort(const unsigned long long *off, const int32_t *cnt, const uint32_t *in,
+                     uint32_t n, uint32_t *ids, int32_t *pairs, hipStream_t s) {
+  if (!n) return;
+  prof::mark(s, "pairs.rowsort");
+  const unsigned grid = grid_for((size_t)n * kWave / kRowWaves, 4096);
+  if (pairs)
+    row_sort_kernel<true><<<grid, kThreads, 0, s>>>(off, cnt, in, n, nullptr,
+                                                    reinterpret_cast<int2 *>(pairs));
+  else
+    row_sort_kernel<false><<<grid, kThreads, 0, s>>>(off, cnt, in, n, ids, nullptr);
 }
 
 }  // namespace ddm

@@ -62,6 +62,10 @@ def library() -> ctypes.CDLL:
         lib.ddm_match.argtypes = [vp, vp, i64, vp, vp, i64, ctypes.c_int, ctypes.c_int, vp,
                                   ctypes.c_size_t, vp, ctypes.POINTER(ctypes.c_uint64), vp, vp, i64]
         lib.ddm_match.restype = ctypes.c_int
+        lib.ddm_match_csr.argtypes = [vp, vp, i64, vp, vp, i64, ctypes.c_int, ctypes.c_int, vp,
+                                      ctypes.c_size_t, vp, ctypes.POINTER(ctypes.c_uint64), vp, vp,
+                                      i64]
+        lib.ddm_match_csr.restype = ctypes.c_int
         lib.ddm_strerror.argtypes = [ctypes.c_int]
         lib.ddm_strerror.restype = ctypes.c_char_p
         lib.ddm_set_path.argtypes = [ctypes.c_int]
@@ -170,6 +174,27 @@ def match_into(upd_lo, upd_hi, sub_lo, sub_hi, mode: str, workspace: torch.Tenso
     return int(cnt.value)
 
 
+def match_csr_into(upd_lo, upd_hi, sub_lo, sub_hi, workspace: torch.Tensor,
+                   row_off: torch.Tensor, sub_ids: torch.Tensor, stream=None,
+                   closed: bool = False) -> int:
+    """Low-level CSR call (``ddm_match_csr``) with caller-provided workspace
+    (``workspace_bytes(n, m, d, "pairs", capacity)``), int64 ``row_off``
+    [n + 1] and int32 ``sub_ids`` [capacity]; returns K, raises DDMError."""
+    n, d = upd_lo.shape
+    m = sub_lo.shape[0]
+    if stream is None:
+        stream = torch.cuda.current_stream(upd_lo.device)
+    cnt = ctypes.c_uint64(0)
+    rc = library().ddm_match_csr(_ptr(upd_lo), _ptr(upd_hi), n, _ptr(sub_lo), _ptr(sub_hi), m, d,
+                                 DDM_CLOSED if closed else 0, ctypes.c_void_p(workspace.data_ptr()),
+                                 workspace.numel(), ctypes.c_void_p(stream.cuda_stream),
+                                 ctypes.byref(cnt), ctypes.c_void_p(row_off.data_ptr()),
+                                 _ptr(sub_ids), sub_ids.numel())
+    if rc != DDM_OK:
+        raise DDMError(rc, "ddm_match_csr")
+    return int(cnt.value)
+
+
 def workspace_bytes(n: int, m: int, d: int, mode: str = "count", pair_capacity: int = 0,
                     closed: bool = False) -> int:
     return int(library().ddm_workspace_bytes(n, m, d, _code(mode, closed), pair_capacity))
@@ -204,7 +229,12 @@ def match(upd_lo, upd_hi, sub_lo, sub_hi, mode: str = "count", *, pair_capacity:
       mode="per_update": (K, int32 tensor [n] of matches per update)
       mode="pairs":      (K, int32 tensor [K, 2] of (update id, subscription
                          id) in lexicographic order, int32 [n] counts or None)
+      mode="csr":        (K, int64 tensor [n + 1] of row offsets, int32 tensor
+                         [K] of subscription ids, ascending within each row)
     """
+    if mode == "csr":
+        return _match_csr(upd_lo, upd_hi, sub_lo, sub_hi, pair_capacity, workspace, stream,
+                          closed)
     if mode not in MODES:
         raise ValueError(f"unknown mode {mode!r}")
     _check_boxes(upd_lo, upd_hi, "updates")
@@ -256,6 +286,44 @@ def match(upd_lo, upd_hi, sub_lo, sub_hi, mode: str = "count", *, pair_capacity:
                 raise DDMError(rc)
             k = int(cnt.value)
             return k, out[:k], (per[:n] if per is not None else None)
+
+
+def _match_csr(upd_lo, upd_hi, sub_lo, sub_hi, capacity, workspace, stream, closed):
+    _check_boxes(upd_lo, upd_hi, "updates")
+    _check_boxes(sub_lo, sub_hi, "subscriptions")
+    n, d = upd_lo.shape
+    m, d2 = sub_lo.shape
+    if d != d2:
+        raise ValueError("updates and subscriptions differ in dimension")
+    dev = upd_lo.device
+    lib = library()
+    flags = DDM_CLOSED if closed else 0
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    handle = ctypes.c_void_p(stream.cuda_stream)
+    cnt = ctypes.c_uint64(0)
+    row_off = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    cap = int(capacity) if capacity is not None else max(1024, n + m)
+    with torch.cuda.device(dev):
+        while True:
+            need = lib.ddm_workspace_bytes(n, m, d, MODES["pairs"] | flags, cap)
+            if need == 0:
+                raise DDMError(DDM_E_INVAL, "ddm_workspace_bytes")
+            ws = workspace
+            if ws is None or ws.numel() < need:
+                ws = torch.empty(need, dtype=torch.uint8, device=dev)
+            ids = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+            rc = lib.ddm_match_csr(_ptr(upd_lo), _ptr(upd_hi), n, _ptr(sub_lo), _ptr(sub_hi), m, d,
+                                   flags, ctypes.c_void_p(ws.data_ptr()), ws.numel(), handle,
+                                   ctypes.byref(cnt), ctypes.c_void_p(row_off.data_ptr()),
+                                   _ptr(ids), cap)
+            if rc == DDM_E_CAPACITY and capacity is None:
+                cap = int(cnt.value)
+                continue
+            if rc != DDM_OK:
+                raise DDMError(rc, "ddm_match_csr")
+            k = int(cnt.value)
+            return k, row_off, ids[:k]
 
 
 def dim_counts(upd_lo, upd_hi, sub_lo, sub_hi, stream=None):

@@ -72,6 +72,11 @@ def check_all_modes(ddm, oracle, inst, pairs=True, expect_bucketed=None, closed=
             assert k2 == k_ref, (inst.name, path)
             assert np.array_equal(pr.cpu().numpy(), pairs_ref), (inst.name, path)
             assert np.array_equal(per2.cpu().numpy(), per_ref), (inst.name, path)
+            k3, row_off, ids = ddm.match(*g, mode="csr", closed=closed)
+            assert k3 == k_ref, (inst.name, path)
+            want_off = np.concatenate([[0], np.cumsum(per_ref, dtype=np.int64)])
+            assert np.array_equal(row_off.cpu().numpy(), want_off), (inst.name, path)
+            assert np.array_equal(ids.cpu().numpy(), pairs_ref[:, 1]), (inst.name, path)
     ddm.set_path("auto")
     if expect_bucketed is None:
         expect_bucketed = inst.d <= 3 and inst.n + inst.m > 0
@@ -382,3 +387,69 @@ def test_closed_full_size_equals_half_open_next_float(ddm):
     kc, pc = ddm.match(*g, mode="per_update", closed=True)
     kh, ph = ddm.match(g[0], up[0], g[2], up[1], mode="per_update")
     assert kc == kh and torch.equal(pc, ph)
+
+
+# ------------------------------------------------------------ CSR output
+
+def test_csr_capacity_and_empty_cases(ddm, oracle):
+    """K above the capacity: DDM_E_CAPACITY, the count set and the row
+    offsets complete; no pairs, no updates, no subscriptions: empty rows."""
+    import ctypes
+    inst = W.tie_heavy(3000, 2000, 2, grid=200, max_len=8, seed=3)
+    k_ref, per_ref, pairs_ref = oracle.sbm(*_host(inst))
+    assert k_ref > 10
+    g = _dev(inst)
+    lib = ddm.library()
+    n, m, d = inst.n, inst.m, inst.d
+    cap = k_ref - 1
+    ws = torch.empty(ddm.workspace_bytes(n, m, d, "pairs", cap), dtype=torch.uint8, device="cuda")
+    row_off = torch.full((n + 1,), -7, dtype=torch.int64, device="cuda")
+    ids = torch.full((cap,), -7, dtype=torch.int32, device="cuda")
+    cnt = ctypes.c_uint64(0)
+    for path in PATHS:
+        ddm.set_path(path)
+        row_off.fill_(-7)
+        rc = lib.ddm_match_csr(*[ctypes.c_void_p(t.data_ptr()) for t in g[:2]], n,
+                               *[ctypes.c_void_p(t.data_ptr()) for t in g[2:]], m, d, 0,
+                               ctypes.c_void_p(ws.data_ptr()), ws.numel(), None, ctypes.byref(cnt),
+                               ctypes.c_void_p(row_off.data_ptr()), ctypes.c_void_p(ids.data_ptr()),
+                               cap)
+        assert rc == ddm.DDM_E_CAPACITY and cnt.value == k_ref, (path, rc)
+        want_off = np.concatenate([[0], np.cumsum(per_ref, dtype=np.int64)])
+        assert np.array_equal(row_off.cpu().numpy(), want_off), path
+        assert bool((ids == -7).all()), path
+    ddm.set_path("auto")
+    # a retry with the reported size succeeds
+    k, ro, got = ddm.match(*g, mode="csr", pair_capacity=int(cnt.value))
+    assert k == k_ref and np.array_equal(got.cpu().numpy(), pairs_ref[:, 1])
+    # no pairs at all / no updates / no subscriptions
+    far = [t + 1e5 for t in g[2:]]
+    k, ro, got = ddm.match(g[0], g[1], far[0], far[1], mode="csr")
+    assert k == 0 and not bool(ro.any()) and ro.numel() == n + 1 and got.numel() == 0
+    z = torch.zeros((0, d), dtype=torch.float32, device="cuda")
+    k, ro, got = ddm.match(z, z, g[2], g[3], mode="csr")
+    assert k == 0 and ro.cpu().tolist() == [0]
+    k, ro, got = ddm.match(g[0], g[1], z, z, mode="csr")
+    assert k == 0 and ro.numel() == n + 1 and not bool(ro.any())
+    # bad flags are rejected before any launch
+    rc = lib.ddm_match_csr(*[ctypes.c_void_p(t.data_ptr()) for t in g[:2]], n,
+                           *[ctypes.c_void_p(t.data_ptr()) for t in g[2:]], m, d, 1,
+                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), None, ctypes.byref(cnt),
+                           ctypes.c_void_p(row_off.data_ptr()), ctypes.c_void_p(ids.data_ptr()), cap)
+    assert rc == ddm.DDM_E_INVAL
+
+
+@pytest.mark.parametrize("rows", [(2048, 10, 1), (3000, 2048, 2049, 10)])
+def test_pairs_rows_at_and_beyond_the_row_sort_limit(ddm, oracle, rows):
+    """Rows of up to 2048 pairs are ordered one by one; a longer row sends
+    the whole call to the device-wide sort.  Both must give the same,
+    oracle-equal pair lists and CSR rows."""
+    m = 3000
+    slo = np.arange(m, dtype=np.float32).reshape(-1, 1)
+    shi = slo + np.float32(0.5)
+    ulo = np.zeros((len(rows), 1), np.float32)
+    uhi = np.array([[r - 0.25] for r in rows], np.float32)  # row r covers subs 0 .. r-1
+    inst = W.Instance(ulo, uhi, slo, shi, float("nan"), f"rows{rows}")
+    k_ref, per_ref, _ = oracle.sbm(*_host(inst))
+    assert per_ref.tolist() == list(rows)
+    check_all_modes(ddm, oracle, inst, expect_bucketed=False)
