@@ -35,7 +35,7 @@ int g_last_path = 0;
 // one region (only one path runs at a time).
 struct Layout {
   size_t hdr, partial;
-  size_t cnt, off, cur, pu, ps, pu2, ps2, scan_tmp, pair_sort_tmp;  // pair mode
+  size_t cnt, off, cur, own, pu, ps, pu2, ps2, scan_tmp, pair_sort_tmp;  // pair mode
   size_t region;
   // device-wide path, relative to region
   size_t klo, khi, vals_a, keys_b, vals_b, sort_tmp, s_khi, s_other, global_bytes;
@@ -63,6 +63,7 @@ Layout make_layout(int64_t n, int64_t m, int d, int mode, int64_t cap,
     L.cnt = take((size_t)n * sizeof(int32_t));
     L.off = take((size_t)n * sizeof(unsigned long long));
     L.cur = take((size_t)n * sizeof(uint32_t));
+    L.own = take((size_t)n * sizeof(uint32_t));
     L.pu = take(c * sizeof(uint32_t));
     L.ps = take(c * sizeof(uint32_t));
     L.pu2 = take(c * sizeof(uint32_t));
@@ -265,6 +266,9 @@ int run_bucketed(const Call &c) {
   a.inst_total = nullptr;
   a.zero = c.mode != DDM_COUNT && c.n > 0 ? c.cnt : nullptr;  // cleared by the count pass
   a.zero_count = (uint32_t)c.n;
+  // d = 1 pairs: the count pass records each update's own-bucket pairs, so
+  // that the emitting pass needs device-wide cursors only for the rest
+  a.own = c.mode == DDM_PAIRS && c.d == 1 ? at<uint32_t>(c.ws, c.L.own) : nullptr;
   DDM_HIP(bucket_prepare(a, c.s));
   const int count_mode = c.mode == DDM_COUNT ? 0 : 1;
   DDM_HIP(bucket_sweep(a, count_mode, c.cnt, nullptr, nullptr, nullptr, nullptr, &c.hdr->total,

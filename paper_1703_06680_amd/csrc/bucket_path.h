@@ -99,6 +99,9 @@ struct BucketArgs {
   unsigned long long *inst_total;  // per-instance pair counts [B], or null
   int32_t *zero;                   // cleared by bucket_prepare ([zero_count]), or null
   uint32_t zero_count;
+  // d = 1 pair mode: per update, its pairs found in its own bucket ([n],
+  // written by the count sweep, read by the emitting sweep), or null
+  uint32_t *own = nullptr;
 };
 
 // Copies the per-instance plan to the workspace and expands the block,

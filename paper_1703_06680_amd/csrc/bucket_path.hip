@@ -647,9 +647,11 @@ constexpr int kPad = 4;
 template <int DM1>
 struct Walker {
   uint32_t klo, khi, after_key, rid;
-  uint32_t q;  // pre-filter walker word (d >= 2)
+  uint32_t q;    // pre-filter walker word (d >= 2)
+  uint32_t pos;  // LDS position of a bucket region, kNoPos for a boundary-state region
   bool upd;
 };
+constexpr uint32_t kNoPos = 0xFFFFFFFFu;
 
 // Pairs that pass the pre-filter wait in a small LDS queue for the exact
 // test, which then runs for all of them at once after the walks, so that the
@@ -666,6 +668,13 @@ struct SweepCtx {
   uint32_t *out_u, *out_s;
   uint2 *queue;     // LDS: (walker region, entry region) pairs awaiting the exact test
   uint32_t *queued; // LDS: number of pairs offered to the queue
+  // d = 1 only (else unused): per LDS position of the bucket's updates, a
+  // difference array of their pairs found in this bucket (count pass) or
+  // their emission cursors (emitting pass); and, per update, the number of
+  // its pairs found in its own bucket (written by the count pass, read by
+  // the emitting pass), or null
+  uint32_t *dl;
+  uint32_t *own;
 };
 
 // Exact other-axis coordinates of region rid, from the instance's rows.
@@ -712,14 +721,30 @@ __device__ __forceinline__ void visit(const Walker<DM1> &y, bool &have_y, float 
   }
   ++hits;
   if (MODE == 1) {
-    if (y.upd)
+    if (y.upd) {
       ++own;
-    else
+    } else if (DM1 == 0) {  // +1 on update entry j, in LDS
+      atomicAdd(&o.dl[j], 1u);
+      atomicAdd(&o.dl[j + 1], 0xFFFFFFFFu);
+    } else {
       atomicAdd(&o.per_update[rx], 1);
+    }
   } else if (MODE == 2) {
     const uint32_t uu = y.upd ? y.rid : rx;
     const uint32_t sid = (y.upd ? rx : y.rid) - o.n;
-    const unsigned long long slot = o.pair_off[uu] + atomicAdd(&o.cursor[uu], 1u);
+    unsigned long long slot;
+    if (DM1 == 0 && o.own) {
+      // an update's row: first its pairs found in its own bucket (LDS
+      // cursor of its entry), then those its boundary-state copies find
+      if (!y.upd)
+        slot = o.pair_off[uu] + atomicAdd(&o.dl[j], 1u);
+      else if (y.pos != kNoPos)
+        slot = o.pair_off[uu] + atomicAdd(&o.dl[y.pos], 1u);
+      else
+        slot = o.pair_off[uu] + o.own[uu] + atomicAdd(&o.cursor[uu], 1u);
+    } else {
+      slot = o.pair_off[uu] + atomicAdd(&o.cursor[uu], 1u);
+    }
     if (o.out_u) o.out_u[slot] = uu;  // null: rows are implied by the offsets
     o.out_s[slot] = sid;
   }
@@ -805,6 +830,14 @@ __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
   } else if (DM1 == 0) {
     if (MODE == 0) {
       hits += jC - jB;
+    } else if (MODE == 1) {  // every interior entry matches: the range at once
+      hits += jC - jB;
+      if (y.upd) {
+        own += jC - jB;
+      } else {
+        atomicAdd(&o.dl[jB], 1u);
+        atomicAdd(&o.dl[jC], 0xFFFFFFFFu);
+      }
     } else {
       for (uint32_t j = jB; j < jC; ++j) visit<DM1, MODE>(y, have_y, ylo, yhi, j, RID, hits, own, o);
     }
@@ -848,7 +881,14 @@ __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
     for (; j + 4 <= jC; j += 4) chunk(j, false);
     if (j < jC) chunk(j, true);  // tail chunk (partial)
   }
-  if (MODE == 1 && own) atomicAdd(&o.per_update[y.rid], (int)own);
+  if (MODE == 1 && own) {
+    if (DM1 == 0 && y.pos != kNoPos) {  // a bucket update: into its LDS entry
+      atomicAdd(&o.dl[y.pos], own);
+      atomicAdd(&o.dl[y.pos + 1], 0u - own);
+    } else {
+      atomicAdd(&o.per_update[y.rid], (int)own);
+    }
+  }
 }
 
 template <int DM1, int MODE, int CAP, int THREADS, int FINE>
@@ -858,7 +898,7 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
     const unsigned long long *__restrict__ pair_off, uint32_t *__restrict__ cursor,
     uint32_t *__restrict__ out_u, uint32_t *__restrict__ out_s,
     unsigned long long *__restrict__ total, unsigned long long *__restrict__ inst_total,
-    const uint32_t *__restrict__ gate) {
+    const uint32_t *__restrict__ gate, uint32_t *__restrict__ own_cnt) {
   constexpr int ITEMS = CAP / THREADS;
   constexpr int W = THREADS / kWave;
   constexpr int NBINS = 2 * FINE;
@@ -876,6 +916,8 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   __shared__ unsigned long long red64[W];
   __shared__ uint2 queue[DM1 > 0 ? kQueue : 1];
   __shared__ uint32_t queued;
+  constexpr bool kDL = DM1 == 0 && MODE != 0;
+  __shared__ uint32_t DL[kDL ? CAP + kPad : 1];
 
   if (MODE == 2 && gate && *gate == 0u) return;  // uniform over the grid
   const uint32_t b = blockIdx.x;
@@ -892,7 +934,7 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   const uint32_t bs_begin = O.bs_begin(b);
   const uint32_t nbs = O.bs_begin(b + 1) - bs_begin;
   const int t = threadIdx.x;
-  const SweepCtx o{I, n, per_update, pair_off, cursor, out_u, out_s, queue, &queued};
+  const SweepCtx o{I, n, per_update, pair_off, cursor, out_u, out_s, queue, &queued, DL, own_cnt};
 
   // 1. records into registers (slot s = t + i * THREADS); value range
   uint4 rk[ITEMS];
@@ -915,6 +957,8 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
     redf[2 * (t / kWave) + 1] = vmx;
   }
   for (int k = t; k < NBINS; k += THREADS) BIN[k] = 0;
+  if (kDL)
+    for (int k = t; k < CAP + kPad; k += THREADS) DL[k] = 0;
   if (t == 0) queued = 0;
   if (t < kPad) {  // defined values in the padding (never counted)
     KLO[CAP + t] = 0;
@@ -993,6 +1037,7 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
       y.klo = KLO[q];
       y.khi = KHI[q];
       y.rid = RID[q];
+      y.pos = q;
       y.upd = q < Cu;
       y.after_key = y.upd ? y.klo : y.klo + 1u;
       y.q = DM1 > 0 ? walker_from_entry<DM1>(Q[q]) : 0u;
@@ -1005,6 +1050,7 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
       y.klo = yr.x;
       y.khi = yr.y;
       y.rid = yr.z;
+      y.pos = kNoPos;
       y.upd = yr.z < n;
       y.after_key = 0u;
       y.q = DM1 > 0 ? walker_word<DM1>(yr.w) : 0u;
@@ -1013,6 +1059,30 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
     const uint32_t fh = fine_of(decode_coord(y.khi - I.closed), vmn, fscale, FINE);
     const uint32_t last = (y.upd ? (uint32_t)FINE : 0u) + fh;
     walk<DM1, MODE>(KLO, RID, Q, y, jA, jB, bin_begin(last), BIN[last], hits, o);
+  }
+  if (DM1 == 0 && MODE == 1) {
+    // 4. d = 1: the pairs of each bucket update found here, by a prefix sum
+    //    of the difference array, into the per-update counts
+    __syncthreads();
+    constexpr int PER = CAP / THREADS;
+    const uint32_t j0 = (uint32_t)t * PER;
+    uint32_t v[PER], sum = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      v[k] = DL[j0 + k];
+      sum += v[k];
+    }
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan<uint32_t, THREADS>(sum, red, &tot);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      run += v[k];
+      const uint32_t j = j0 + k;
+      if (j < Cu) {
+        if (run) atomicAdd(&per_update[RID[j]], (int)run);
+        if (own_cnt) own_cnt[RID[j]] = run;
+      }
+    }
   }
   if (DM1 > 0) {  // 4. the exact test of the queued pairs, all at once
     __syncthreads();
@@ -1109,15 +1179,15 @@ void sweep_impl(const BucketArgs &a, int32_t *per_update, const unsigned long lo
   if (L.tune.sweep_threads == 1024)
     bk_sweep_kernel<DM1, MODE, kBigCap, 1024, 1024><<<L.nb, 1024, 0, s>>>(
         p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
-        out_u, out_s, total, a.inst_total, gate);
+        out_u, out_s, total, a.inst_total, gate, a.own);
   else if (L.tune.sweep_threads == 256)
     bk_sweep_kernel<DM1, MODE, kCap, 256, 512><<<L.nb, 256, 0, s>>>(
         p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
-        out_u, out_s, total, a.inst_total, gate);
+        out_u, out_s, total, a.inst_total, gate, a.own);
   else
     bk_sweep_kernel<DM1, MODE, kCap, 512, 512><<<L.nb, 512, 0, s>>>(
         p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
-        out_u, out_s, total, a.inst_total, gate);
+        out_u, out_s, total, a.inst_total, gate, a.own);
 }
 
 // Host-side plan of one instance; returns false if it does not fit.

@@ -240,7 +240,8 @@ __global__ void widen_kernel(const int32_t *__restrict__ in, unsigned long long 
   }
   if (max_out) {
     most = wave_max(most);
-    if (lane_id() == 0 && most) atomicMax(max_out, most);
+    // a read first: most waves see a larger maximum already and skip the atomic
+    if (lane_id() == 0 && most > *(volatile unsigned long long *)max_out) atomicMax(max_out, most);
   }
 }
 
@@ -252,12 +253,44 @@ __global__ void widen_kernel(const int32_t *__restrict__ in, unsigned long long 
 // permutation.  Rows of at most kRowMax ids.
 constexpr int kRowWaves = kThreads / kWave;
 
+// Ranks of ids v (kPer per lane, chunk starting at i0) among the row's L4
+// staged ids (padding above every id), and their stores.
+template <bool kPairs, int kPer>
+__device__ __forceinline__ void rank_and_store(const uint32_t *row, uint32_t L, uint32_t L4,
+                                               uint32_t i0, int lane, uint32_t u,
+                                               unsigned long long base, uint32_t *ids,
+                                               int2 *pairs) {
+  uint32_t v[kPer], rank[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const uint32_t i = i0 + k * kWave + lane;
+    v[k] = i < L ? row[i] : 0xFFFFFFFFu;
+    rank[k] = 0;
+  }
+  for (uint32_t j = 0; j < L4; j += 4) {
+    const uint4 q = *reinterpret_cast<const uint4 *>(row + j);  // same address in every lane
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+      rank[k] += (uint32_t)(q.x < v[k]) + (uint32_t)(q.y < v[k]) + (uint32_t)(q.z < v[k]) +
+                 (uint32_t)(q.w < v[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const uint32_t i = i0 + k * kWave + lane;
+    if (i < L) {
+      if (kPairs)
+        pairs[base + rank[k]] = make_int2((int32_t)u, (int32_t)v[k]);
+      else
+        ids[base + rank[k]] = v[k];
+    }
+  }
+}
+
 template <bool kPairs>
 __global__ __launch_bounds__(kThreads) void row_sort_kernel(
     const unsigned long long *__restrict__ off, const int32_t *__restrict__ cnt,
     const uint32_t *__restrict__ in, uint32_t n, uint32_t *__restrict__ ids,
     int2 *__restrict__ pairs) {
-  constexpr int kPer = 4;  // ids per lane per scan of the row
   __shared__ __align__(16) uint32_t stage[kRowWaves][kRowMax];
   const int w = threadIdx.x / kWave, lane = lane_id();
   uint32_t *row = stage[w];
@@ -266,34 +299,26 @@ __global__ __launch_bounds__(kThreads) void row_sort_kernel(
     const uint32_t L = (uint32_t)cnt[u];
     if (L == 0 || L > kRowMax) continue;  // longer rows are never passed here
     const unsigned long long base = off[u];
+    if (L == 1) {
+      if (lane == 0) {
+        if (kPairs)
+          pairs[base] = make_int2((int32_t)u, (int32_t)in[base]);
+        else
+          ids[base] = in[base];
+      }
+      continue;
+    }
     const uint32_t L4 = (L + 3) & ~3u;  // padded with ids above every real one
     for (uint32_t i = lane; i < L4; i += kWave) row[i] = i < L ? in[base + i] : 0xFFFFFFFFu;
     __builtin_amdgcn_wave_barrier();
-    for (uint32_t i0 = 0; i0 < L; i0 += kPer * kWave) {
-      uint32_t v[kPer], rank[kPer];
-#pragma unroll
-      for (int k = 0; k < kPer; ++k) {
-        const uint32_t i = i0 + k * kWave + lane;
-        v[k] = i < L ? row[i] : 0xFFFFFFFFu;
-        rank[k] = 0;
-      }
-      for (uint32_t j = 0; j < L4; j += 4) {
-        const uint4 q = *reinterpret_cast<const uint4 *>(row + j);  // same address in every lane
-#pragma unroll
-        for (int k = 0; k < kPer; ++k)
-          rank[k] += (uint32_t)(q.x < v[k]) + (uint32_t)(q.y < v[k]) + (uint32_t)(q.z < v[k]) +
-                     (uint32_t)(q.w < v[k]);
-      }
-#pragma unroll
-      for (int k = 0; k < kPer; ++k) {
-        const uint32_t i = i0 + k * kWave + lane;
-        if (i < L) {
-          if (kPairs)
-            pairs[base + rank[k]] = make_int2((int32_t)u, (int32_t)v[k]);
-          else
-            ids[base + rank[k]] = v[k];
-        }
-      }
+    // as many ids per lane as the row needs, up to four per scan of the row
+    if (L <= kWave) {
+      rank_and_store<kPairs, 1>(row, L, L4, 0, lane, u, base, ids, pairs);
+    } else if (L <= 2 * kWave) {
+      rank_and_store<kPairs, 2>(row, L, L4, 0, lane, u, base, ids, pairs);
+    } else {
+      for (uint32_t i0 = 0; i0 < L; i0 += 4 * kWave)
+        rank_and_store<kPairs, 4>(row, L, L4, i0, lane, u, base, ids, pairs);
     }
     __builtin_amdgcn_wave_barrier();  // every lane done with the row before the next one
   }
