@@ -313,6 +313,8 @@ def main():
     ap.add_argument("--mode", default="per_update", choices=["count", "per_update"])
     ap.add_argument("--n", type=int, default=5_000_000, help="n = m boxes per side")
     ap.add_argument("--d", type=int, default=3)
+    ap.add_argument("--path", default="auto", choices=["auto", "bucketed", "global"],
+                    help="implementation of the headline calls (default: the library's choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the per-phase event timing (roofline becomes null)")
@@ -330,7 +332,26 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=4.0)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-max-batch", type=int, default=8)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only time a plain 256 MiB device-to-device copy (the reference kernel "
+                         "for scaling HBM traffic counters) and exit")
     args = ap.parse_args()
+
+    if args.copy_probe:
+        import torch
+        x = torch.rand(64 * 1024 * 1024, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(10):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) / 10 * 1e3
+        print(json.dumps({"copy_bytes": 2 * x.numel() * 4, "ms": round(ms, 4),
+                          "gb_per_s": round(2 * x.numel() * 4 / ms / 1e6, 1)}), flush=True)
+        return
 
     if args.gpus != 1:
         print(f"bench.py: this library runs on exactly one GPU (asked for --gpus {args.gpus}); "
@@ -348,6 +369,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
+    ddm.set_path(args.path)
     n = m = args.n
     d = args.d
     t0 = time.time()
@@ -375,6 +397,7 @@ def main():
         per_step.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    head_path = ddm.last_path()
     # per-phase times from HIP events on the library's stream, in a second
     # pass of the same steps (event records are not part of the timed pass)
     phases = {}
@@ -428,6 +451,7 @@ def main():
                                "matches": ke, "path": ddm.last_path()}
         del ge
 
+    ddm.set_path("auto")  # the other measurements use the library's choice
     closed = None
     if not args.no_closed:
         # the headline inputs as closed boxes [lo, hi]; checked against the
@@ -495,7 +519,7 @@ def main():
                    "d": d, "n": n, "m": m, "alpha": args.alpha, "mode": args.mode,
                    "parallelism": "single GPU"},
         "matches": k,
-        "path": ddm.last_path(),
+        "path": head_path,
         "step_ms_p50": round(1e3 * statistics.median(per_step), 4),
         "step_ms_p99": round(1e3 * float(np.percentile(per_step, 99)), 4),
         "roofline": roofline,
