@@ -56,7 +56,6 @@ struct InstPlan {
   uint32_t b0, nb;           // buckets (first, number)
   uint32_t cell0;            // first cell of the instance's nblk x nb count matrix
   uint32_t smp0, nsmp;       // sample blocks
-  uint32_t tile0, ntx;       // transpose tiles (first), tiles along the bucket axis
   uint32_t vec;              // rows may be read with 16-byte loads
   uint32_t closed;           // 1: closed intervals (records hold enc(hi) + 1)
 };
@@ -67,7 +66,7 @@ inline uint32_t bucket_cap(const BucketTuning &t) {
 
 struct BucketLayout {
   uint32_t B;                          // instances
-  uint32_t nb, nblk, nsmp, ntile;      // totals over the instances
+  uint32_t nb, nblk, nsmp;             // totals over the instances
   uint32_t max_nb;                     // most buckets of one instance
   uint32_t n_total, m_total;           // updates, subscriptions over the instances
   uint32_t bs_cap;                     // capacity of the boundary-state record buffer
@@ -76,7 +75,7 @@ struct BucketLayout {
   size_t cells;                        // count-matrix cells over the instances
   size_t bytes;                        // workspace bytes for all buffers below
   // byte offsets inside the bucket workspace
-  size_t params, sample_part, counts, transposed, offsets, block_offsets, scan_tmp, bs_cur, rec,
+  size_t params, sample_part, counts, totals, offsets, block_offsets, scan_tmp, bs_cur, rec,
       bs_rec, plan, maps;
   std::vector<InstPlan> inst;          // host copy of the per-instance plan
 };

@@ -127,25 +127,25 @@ __device__ __forceinline__ uint32_t box_errors(const Box<D> &b, bool &empty, uin
 struct View {
   const InstPlan *plan;  // null: a single instance, `one`
   InstPlan one;
-  const uint32_t *blk_inst, *smp_inst, *tile_inst, *bucket_inst;
+  const uint32_t *blk_inst, *smp_inst, *bucket_inst;
   __device__ __forceinline__ InstPlan get(uint32_t i) const { return plan ? plan[i] : one; }
   __device__ __forceinline__ uint32_t of_blk(uint32_t x) const { return plan ? blk_inst[x] : 0u; }
   __device__ __forceinline__ uint32_t of_smp(uint32_t x) const { return plan ? smp_inst[x] : 0u; }
-  __device__ __forceinline__ uint32_t of_tile(uint32_t x) const { return plan ? tile_inst[x] : 0u; }
   __device__ __forceinline__ uint32_t of_bucket(uint32_t x) const {
     return plan ? bucket_inst[x] : 0u;
   }
 };
 
-// Offsets produced by the one prefix sum over [count cells | boundary-state
-// sizes | 0]: S[cell0 + b * nblk + k] is block k's first slot in bucket b of
-// an instance, S[cells] the number of records, S[cells + j] - S[cells] the
-// first boundary-state entry of global bucket j (j <= total buckets).
+// Offsets produced by the one prefix sum over [bucket sizes | boundary-state
+// sizes | 0] (2 nb + 1 entries, buckets numbered over all instances): S[j] is
+// the first record slot of bucket j, S[nb] the number of records,
+// S[nb + j] - S[nb] the first boundary-state entry of bucket j (j <= nb).
+// Block k's first slot in bucket j is S[j] plus the block-major prefix
+// written by bk_colscan_kernel.
 struct Offsets {
   const uint32_t *S;
-  size_t cells;
   uint32_t nb;  // buckets over all instances
-  __device__ uint32_t bs_begin(uint32_t j) const { return S[cells + j] - S[cells]; }
+  __device__ uint32_t bs_begin(uint32_t j) const { return S[nb + j] - S[nb]; }
 };
 
 // ---------------------------------------------------------------- sample
@@ -423,29 +423,42 @@ __global__ __launch_bounds__(kThreads) void bk_count_kernel(
   if (err && lane_id() == 0) atomicOr(&hdr->err, err);
 }
 
-// Per instance, out = transpose(in) for its count matrix: forward (back == 0)
-// from block-major nblk x nb to bucket-major nb x nblk, backward the reverse.
-// One 64 x 64 LDS tile per workgroup.
-__global__ __launch_bounds__(256) void bk_transpose_kernel(const uint32_t *__restrict__ in,
-                                                           uint32_t *__restrict__ out, View V,
-                                                           int back) {
-  __shared__ uint32_t tile[64][65];
-  const InstPlan I = V.get(V.of_tile(blockIdx.x));
-  const uint32_t lt = blockIdx.x - I.tile0;
-  const uint32_t tb = lt % I.ntx, tk = lt / I.ntx;  // bucket tile, block tile
-  const uint32_t rows = back ? I.nb : I.nblk, cols = back ? I.nblk : I.nb;
-  const uint32_t r0 = (back ? tb : tk) * 64, c0 = (back ? tk : tb) * 64;
-  in += I.cell0;
-  out += I.cell0;
-  const uint32_t tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  for (uint32_t j = ty; j < 64; j += 4) {
-    const uint32_t r = r0 + j, c = c0 + tx;
-    if (r < rows && c < cols) tile[j][tx] = in[(size_t)r * cols + c];
+// Column prefix of every instance's block-major count matrix: for bucket j
+// (local column lb) and block k, P[k][lb] = sum of C[k'][lb] over k' < k,
+// written block-major like C, and the column total into tot[j].  One lane
+// per bucket (64 buckets per workgroup, consecutive lanes on consecutive
+// columns, so every row access is coalesced); the 16 waves of a workgroup
+// take 16 consecutive ranges of blocks and combine their sums in LDS.
+constexpr int kColWaves = 16;
+
+__global__ __launch_bounds__(kColWaves * kWave) void bk_colscan_kernel(
+    const uint32_t *__restrict__ C, uint32_t *__restrict__ P, uint32_t *__restrict__ tot,
+    View V, uint32_t nb_total) {
+  __shared__ uint32_t part[kColWaves][kWave];
+  const uint32_t lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const uint32_t j = blockIdx.x * kWave + lane;
+  uint32_t k0 = 0, k1 = 0, stride = 0;
+  size_t base = 0;
+  if (j < nb_total) {
+    const InstPlan I = V.get(V.of_bucket(j));
+    const uint32_t per = (I.nblk + kColWaves - 1) / kColWaves;
+    k0 = min(I.nblk, w * per);
+    k1 = min(I.nblk, k0 + per);
+    stride = I.nb;
+    base = I.cell0 + (size_t)(j - I.b0);
   }
+  uint32_t sum = 0;
+  for (uint32_t k = k0; k < k1; ++k) sum += C[base + (size_t)k * stride];
+  part[w][lane] = sum;
   __syncthreads();
-  for (uint32_t j = ty; j < 64; j += 4) {
-    const uint32_t c = c0 + j, r = r0 + tx;
-    if (c < cols && r < rows) out[(size_t)c * rows + r] = tile[tx][j];
+  uint32_t run = 0;
+  for (uint32_t v = 0; v < w; ++v) run += part[v][lane];
+  if (j < nb_total && w == kColWaves - 1) tot[j] = run + sum;
+  for (uint32_t k = k0; k < k1; ++k) {
+    const size_t at = base + (size_t)k * stride;
+    const uint32_t c = C[at];
+    P[at] = run;
+    run += c;
   }
 }
 
@@ -515,7 +528,7 @@ __global__ __launch_bounds__(kThreads) void bk_scatter_kernel(
   const BucketParams p = P[inst];
   const uint32_t nb = I.nb, lb = blockIdx.x - I.blk0;
   const uint32_t *row = SB + I.cell0 + (size_t)lb * nb;
-  for (uint32_t b = threadIdx.x; b < nb; b += kThreads) cur[b] = row[b];
+  for (uint32_t b = threadIdx.x; b < nb; b += kThreads) cur[b] = O.S[I.b0 + b] + row[b];
   __syncthreads();
   const uint32_t g0 = lb * I.gpb, g1 = min(I.g, g0 + I.gpb);
 #pragma unroll 2
@@ -542,7 +555,7 @@ __global__ __launch_bounds__(kThreads) void bk_scatter_kernel(
   }
 }
 
-// Instance of every global block, sample block, transpose tile and bucket.
+// Instance of every global block, sample block and bucket.
 __device__ __forceinline__ uint32_t find_inst(const InstPlan *plan, uint32_t B, uint32_t x,
                                               int which) {
   // last instance whose first index (of the given kind) is <= x among those
@@ -551,7 +564,7 @@ __device__ __forceinline__ uint32_t find_inst(const InstPlan *plan, uint32_t B, 
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) / 2;
     const InstPlan &I = plan[mid];
-    const uint32_t first = which == 0 ? I.blk0 : which == 1 ? I.smp0 : which == 2 ? I.tile0 : I.b0;
+    const uint32_t first = which == 0 ? I.blk0 : which == 1 ? I.smp0 : I.b0;
     if (first <= x)
       lo = mid;
     else
@@ -563,17 +576,14 @@ __device__ __forceinline__ uint32_t find_inst(const InstPlan *plan, uint32_t B, 
 __global__ void bk_expand_maps_kernel(const InstPlan *__restrict__ plan, uint32_t B,
                                       uint32_t *__restrict__ blk_inst, uint32_t nblk,
                                       uint32_t *__restrict__ smp_inst, uint32_t nsmp,
-                                      uint32_t *__restrict__ tile_inst, uint32_t ntile,
                                       uint32_t *__restrict__ bucket_inst, uint32_t nb) {
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < nblk; x += stride)
     blk_inst[x] = find_inst(plan, B, x, 0);
   for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < nsmp; x += stride)
     smp_inst[x] = find_inst(plan, B, x, 1);
-  for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < ntile; x += stride)
-    tile_inst[x] = find_inst(plan, B, x, 2);
   for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < nb; x += stride)
-    bucket_inst[x] = find_inst(plan, B, x, 3);
+    bucket_inst[x] = find_inst(plan, B, x, 2);
 }
 
 // ------------------------------------------------------------ sweep pass
@@ -923,10 +933,9 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   const uint32_t b = blockIdx.x;
   const uint32_t inst = V.of_bucket(b);
   const InstPlan I = V.get(inst);
-  const size_t cell = I.cell0 + (size_t)(b - I.b0) * I.nblk;
   const uint32_t nbs_total = O.bs_begin(O.nb);
-  const uint32_t start = O.S[cell];
-  const uint32_t C = O.S[cell + I.nblk] - start;
+  const uint32_t start = O.S[b];
+  const uint32_t C = O.S[b + 1] - start;
   if (nbs_total > bs_cap || C > (uint32_t)CAP) {  // uniform: the host falls back
     if (threadIdx.x == 0) atomicOr(&hdr->pad[0], 1u);
     return;
@@ -1121,7 +1130,7 @@ Ptrs pointers(const BucketArgs &a) {
   p.P = reinterpret_cast<BucketParams *>(ws + L.params);
   p.part = reinterpret_cast<float *>(ws + L.sample_part);
   p.C = reinterpret_cast<uint32_t *>(ws + L.counts);
-  p.T = reinterpret_cast<uint32_t *>(ws + L.transposed);
+  p.T = reinterpret_cast<uint32_t *>(ws + L.totals);
   p.S = reinterpret_cast<uint32_t *>(ws + L.offsets);
   p.SB = reinterpret_cast<uint32_t *>(ws + L.block_offsets);
   p.bs_cur = reinterpret_cast<uint32_t *>(ws + L.bs_cur);
@@ -1129,7 +1138,6 @@ Ptrs pointers(const BucketArgs &a) {
   p.bs_rec = reinterpret_cast<uint32_t *>(ws + L.bs_rec);
   p.scan_tmp = ws + L.scan_tmp;
   p.O.S = p.S;
-  p.O.cells = L.cells;
   p.O.nb = L.nb;
   p.V = View{};
   if (L.B == 1) {
@@ -1140,8 +1148,7 @@ Ptrs pointers(const BucketArgs &a) {
     uint32_t *maps = reinterpret_cast<uint32_t *>(ws + L.maps);
     p.V.blk_inst = maps;
     p.V.smp_inst = maps + L.nblk;
-    p.V.tile_inst = maps + L.nblk + L.nsmp;
-    p.V.bucket_inst = maps + L.nblk + L.nsmp + L.ntile;
+    p.V.bucket_inst = maps + L.nblk + L.nsmp;
   }
   return p;
 }
@@ -1152,19 +1159,18 @@ template <int D>
 void prepare_impl(const BucketArgs &a, hipStream_t s) {
   const BucketLayout &L = *a.L;
   Ptrs p = pointers(a);
-  const size_t cells = L.cells;
   const size_t lds = (size_t)L.max_nb * sizeof(uint32_t);
   prof::mark(s, "bucket.sample");
-  const Clear clr{a.hdr, p.T + cells, p.bs_cur, L.nb, a.inst_total, L.B};
+  const Clear clr{a.hdr, p.T + L.nb, p.bs_cur, L.nb, a.inst_total, L.B};
   bk_sample_kernel<D><<<L.nsmp, kSampleThreads, 0, s>>>(p.V, p.part, clr);
   bk_plan_kernel<<<L.B, kSampleThreads, 0, s>>>(p.part, p.V, p.P);
   prof::mark(s, "bucket.count");
-  bk_count_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.C, p.T + cells, a.hdr,
+  bk_count_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.C, p.T + L.nb, a.hdr,
                                                    a.zero, a.zero ? a.zero_count : 0u);
   prof::mark(s, "bucket.offsets");
-  bk_transpose_kernel<<<L.ntile, 256, 0, s>>>(p.C, p.T, p.V, 0);
-  (void)exclusive_scan_u32(p.T, p.S, cells + L.nb + 1, p.scan_tmp, s);
-  bk_transpose_kernel<<<L.ntile, 256, 0, s>>>(p.S, p.SB, p.V, 1);
+  bk_colscan_kernel<<<(L.nb + kWave - 1) / kWave, kColWaves * kWave, 0, s>>>(p.C, p.SB, p.T, p.V,
+                                                                         L.nb);
+  (void)exclusive_scan_u32(p.T, p.S, 2 * (size_t)L.nb + 1, p.scan_tmp, s);
   prof::mark(s, "bucket.scatter");
   bk_scatter_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.O, p.SB, p.bs_cur,
                                                      L.bs_cap, p.rec, p.bs_rec);
@@ -1221,7 +1227,6 @@ bool plan_instance(const InstSpec &sp, int64_t u0, int64_t s0, const BucketTunin
   I.gpb = (uint32_t)((I.g + nblk - 1) / nblk);
   const uint64_t nsmp = std::min<uint64_t>(kMaxSampleBlocks, (N + kSampleRows - 1) / kSampleRows);
   I.nsmp = (uint32_t)std::max<uint64_t>(1, nsmp);
-  I.ntx = (I.nb + 63) / 64;
   return true;
 }
 
@@ -1253,7 +1258,7 @@ BucketLayout bucket_layout(const InstSpec *inst, int64_t B, int d, const BucketT
   L.B = (uint32_t)B;
   L.tune = t;
   L.inst.resize((size_t)B);
-  uint32_t blk = 0, smp = 0, tile = 0, bkt = 0;
+  uint32_t blk = 0, smp = 0, bkt = 0;
   size_t cell = 0;
   int64_t u0 = 0, s0 = 0;
   for (int64_t i = 0; i < B; ++i) {
@@ -1263,12 +1268,10 @@ BucketLayout bucket_layout(const InstSpec *inst, int64_t B, int d, const BucketT
     s0 += inst[i].m;
     I.blk0 = blk;
     I.smp0 = smp;
-    I.tile0 = tile;
     I.b0 = bkt;
     I.cell0 = (uint32_t)cell;
     blk += I.nblk;
     smp += I.nsmp;
-    tile += I.ntx * ((I.nblk + 63) / 64);
     bkt += I.nb;
     cell += (size_t)I.nb * I.nblk;
     L.max_nb = std::max(L.max_nb, I.nb);
@@ -1276,7 +1279,6 @@ BucketLayout bucket_layout(const InstSpec *inst, int64_t B, int d, const BucketT
   L.nb = bkt;
   L.nblk = blk;
   L.nsmp = smp;
-  L.ntile = tile;
   L.cells = cell;
   L.n_total = (uint32_t)u0;
   L.m_total = (uint32_t)s0;
@@ -1289,11 +1291,11 @@ BucketLayout bucket_layout(const InstSpec *inst, int64_t B, int d, const BucketT
     at += align256(bytes);
     return o;
   };
-  const size_t scanned = cell + L.nb + 1;  // counts + boundary-state sizes + sentinel
+  const size_t scanned = 2 * (size_t)L.nb + 1;  // bucket sizes + boundary-state sizes + 0
   L.params = take((size_t)B * sizeof(BucketParams));
   L.sample_part = take((size_t)std::max<uint32_t>(L.nsmp, 1) * 8 * sizeof(float));
   L.counts = take(cell * sizeof(uint32_t));
-  L.transposed = take(scanned * sizeof(uint32_t));
+  L.totals = take(scanned * sizeof(uint32_t));
   L.offsets = take(scanned * sizeof(uint32_t));
   L.block_offsets = take(cell * sizeof(uint32_t));
   L.scan_tmp = take(scan_temp_bytes(scanned));
@@ -1301,7 +1303,7 @@ BucketLayout bucket_layout(const InstSpec *inst, int64_t B, int d, const BucketT
   L.rec = take((size_t)N * L.rec_words * sizeof(uint32_t));
   L.bs_rec = take((size_t)L.bs_cap * L.rec_words * sizeof(uint32_t));
   L.plan = take(B > 1 ? (size_t)B * sizeof(InstPlan) : 0);
-  L.maps = take(B > 1 ? ((size_t)L.nblk + L.nsmp + L.ntile + L.nb) * sizeof(uint32_t) : 0);
+  L.maps = take(B > 1 ? ((size_t)L.nblk + L.nsmp + L.nb) * sizeof(uint32_t) : 0);
   L.bytes = at;
   return L;
 }
@@ -1326,11 +1328,10 @@ hipError_t bucket_upload_plan(const BucketArgs &a, hipStream_t s, void *pinned) 
   }
   hipError_t e = hipMemcpyAsync(plan, src, plan_bytes(L), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return e;
-  const uint32_t most = std::max(std::max(L.nblk, L.nsmp), std::max(L.ntile, L.nb));
+  const uint32_t most = std::max(std::max(L.nblk, L.nsmp), L.nb);
   const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>((most + 255) / 256, 1024));
   bk_expand_maps_kernel<<<grid, 256, 0, s>>>(plan, L.B, const_cast<uint32_t *>(p.V.blk_inst),
                                              L.nblk, const_cast<uint32_t *>(p.V.smp_inst), L.nsmp,
-                                             const_cast<uint32_t *>(p.V.tile_inst), L.ntile,
                                              const_cast<uint32_t *>(p.V.bucket_inst), L.nb);
   return hipGetLastError();
 }
