@@ -193,7 +193,7 @@ int reset_outputs(const Call &c) {
 // ids into c.csr_ids; the offsets are written even when K exceeds the
 // capacity).
 template <typename Emit>
-int finish_pairs(const Call &c, unsigned long long K, Emit emit) {
+int finish_pairs(const Call &c, unsigned long long K, Emit emit, bool bucketed) {
   const Layout &L = c.L;
   unsigned long long *off = c.csr_off ? reinterpret_cast<unsigned long long *>(c.csr_off)
                                       : at<unsigned long long>(c.ws, L.off);
@@ -231,13 +231,35 @@ int finish_pairs(const Call &c, unsigned long long K, Emit emit) {
   DDM_HIP(hipMemcpyAsync(&longest, &c.hdr->aux[1], sizeof(longest), hipMemcpyDeviceToHost, c.s));
   DDM_HIP(hipStreamSynchronize(c.s));
   const bool by_rows = longest <= kRowMax;
+  uint32_t *ids_out = reinterpret_cast<uint32_t *>(c.csr_ids);
+  int32_t *pairs_out = c.csr_ids ? nullptr : c.pairs;
   prof::mark(c.s, "pairs.memset");
   DDM_HIP(hipMemsetAsync(cur, 0, (size_t)c.n * sizeof(uint32_t), c.s));
-  DDM_HIP(emit(off, cur, by_rows ? nullptr : pu, ps));
-  if (by_rows) {
-    launch_row_sort(off, c.cnt, ps, (uint32_t)c.n, reinterpret_cast<uint32_t *>(c.csr_ids),
-                    c.csr_ids ? nullptr : c.pairs, c.s);
+  // d = 1 on the bucketed path: the emitting sweep writes whole ordered rows
+  // (those of updates with no pairs in later buckets finished in place)
+  bool rows_done = false;
+  if (by_rows && bucketed && c.d == 1 && longest <= kRowStage) {
+    uint32_t *flag = reinterpret_cast<uint32_t *>(&c.hdr->aux[2]);
+    DDM_HIP(fill_u32(flag, 0u, 1, c.s));
+    const RowEmit re{c.cnt, ids_out, pairs_out, flag};
+    DDM_HIP(emit(off, cur, nullptr, ps, &re));
+    uint32_t failed = 0;
+    DDM_HIP(hipMemcpyAsync(&failed, flag, sizeof(failed), hipMemcpyDeviceToHost, c.s));
+    DDM_HIP(hipStreamSynchronize(c.s));
+    if (!failed) {
+      launch_row_sort(off, c.cnt, ps, (uint32_t)c.n, ids_out, pairs_out, c.s,
+                      at<uint32_t>(c.ws, L.own));
+      rows_done = true;
+    } else {  // some bucket could not: emit pair by pair from scratch
+      DDM_HIP(hipMemsetAsync(cur, 0, (size_t)c.n * sizeof(uint32_t), c.s));
+    }
+  }
+  if (rows_done) {
+  } else if (by_rows) {
+    DDM_HIP(emit(off, cur, nullptr, ps, nullptr));
+    launch_row_sort(off, c.cnt, ps, (uint32_t)c.n, ids_out, pairs_out, c.s);
   } else {
+    DDM_HIP(emit(off, cur, pu, ps, nullptr));
     uint32_t *ru = nullptr, *rs = nullptr;
     DDM_HIP(order_pairs(pu, ps, pu2, ps2, (uint32_t)K, c.n, c.m,
                         at<void>(c.ws, L.pair_sort_tmp), c.s, &ru, &rs));
@@ -282,10 +304,14 @@ int run_bucketed(const Call &c) {
   if (h.pad[0]) return kFallback;
   *c.count_host = h.total;
   if (c.mode != DDM_PAIRS || (h.total == 0 && !c.csr_off)) return DDM_OK;
-  return finish_pairs(c, h.total, [&](unsigned long long *off, uint32_t *cur, uint32_t *pu,
-                                      uint32_t *ps) {
-    return bucket_sweep(a, 2, nullptr, off, cur, pu, ps, &c.hdr->aux[0], c.s);
-  });
+  return finish_pairs(
+      c, h.total,
+      [&](unsigned long long *off, uint32_t *cur, uint32_t *pu, uint32_t *ps, const RowEmit *rows) {
+        BucketArgs e = a;
+        if (rows) e.rows = *rows;
+        return bucket_sweep(e, 2, nullptr, off, cur, pu, ps, &c.hdr->aux[0], c.s);
+      },
+      true);
 }
 
 // ---------------------------------------------------- device-wide path
@@ -355,7 +381,7 @@ int run_global(const Call &c) {
   *c.count_host = K;
   if (c.mode != DDM_PAIRS || (K == 0 && !c.csr_off)) return DDM_OK;
   return finish_pairs(c, K, [&](unsigned long long *off, uint32_t *cur, uint32_t *pu,
-                                uint32_t *ps) {
+                                uint32_t *ps, const RowEmit *) {
     SweepArgs e = a;
     e.offsets = off;
     e.cursor = cur;
@@ -364,7 +390,7 @@ int run_global(const Call &c) {
     e.total = &c.hdr->aux[0];
     launch_sweep(2, e, c.s);
     return hipGetLastError();
-  });
+  }, false);
 }
 
 // ------------------------------------------------- repeated single calls

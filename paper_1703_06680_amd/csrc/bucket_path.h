@@ -23,6 +23,19 @@
 
 namespace ddm {
 
+// d = 1 pair emission by rows (see bucket_sweep): each bucket update's pairs
+// found in its bucket are gathered by one wave, ordered in LDS and written
+// as a finished row; rows that also get pairs from later buckets are left,
+// ordered, in the staging array for a final row sort.
+constexpr uint32_t kRowStage = 512;    // longest row the emitting waves can hold
+constexpr uint32_t kBsSubCap = 1024;   // boundary-state subscriptions per bucket held in LDS
+struct RowEmit {
+  const int32_t *cnt;  // per-update pair counts (null: emission pair by pair)
+  uint32_t *ids;       // CSR output (subscription ids), or null
+  int32_t *pairs;      // pair-list output [K][2], or null
+  uint32_t *flag;      // set to 1 if some bucket could not emit by rows
+};
+
 // Launch-shape parameters of the bucketed path.
 struct BucketTuning {
   uint32_t target = 1536;         // mean records per bucket (at most 3/4 of the capacity)
@@ -101,6 +114,7 @@ struct BucketArgs {
   // d = 1 pair mode: per update, its pairs found in its own bucket ([n],
   // written by the count sweep, read by the emitting sweep), or null
   uint32_t *own = nullptr;
+  RowEmit rows{};  // d = 1 emitting sweep by rows (rows.cnt non-null), with own
 };
 
 // Copies the per-instance plan to the workspace and expands the block,

@@ -792,12 +792,6 @@ __device__ __forceinline__ uint32_t qfail(uint32_t e, uint32_t wq) {
   return 0u;
 }
 
-template <int DM1>
-__device__ __forceinline__ bool qpass(const uint32_t *__restrict__ Q, uint32_t j,
-                                      const Walker<DM1> &y) {
-  return DM1 == 0 || qfail<DM1>(Q[j], y.q) == 0u;
-}
-
 __device__ __forceinline__ uint32_t min4(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
   return min(min(a, b), min(c, d));
 }
@@ -901,6 +895,150 @@ __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
   }
 }
 
+// Ranks of ids v (kPer per lane, from position i0) among the L4 staged ids
+// of a row (padding above every id); each id is written to its rank.
+template <int kPer>
+__device__ __forceinline__ void rank_row(const uint32_t *stage, uint32_t L, uint32_t L4,
+                                         uint32_t i0, int lane, uint32_t u, unsigned long long base,
+                                         uint32_t *ids, int2 *pairs) {
+  uint32_t v[kPer], rank[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const uint32_t i = i0 + k * kWave + lane;
+    v[k] = i < L ? stage[i] : 0xFFFFFFFFu;
+    rank[k] = 0;
+  }
+  for (uint32_t j = 0; j < L4; j += 4) {
+    const uint4 q = *reinterpret_cast<const uint4 *>(stage + j);  // same address in every lane
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+      rank[k] += (uint32_t)(q.x < v[k]) + (uint32_t)(q.y < v[k]) + (uint32_t)(q.z < v[k]) +
+                 (uint32_t)(q.w < v[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const uint32_t i = i0 + k * kWave + lane;
+    if (i < L) {
+      if (pairs)
+        pairs[base + rank[k]] = make_int2((int32_t)u, (int32_t)v[k]);
+      else
+        ids[base + rank[k]] = v[k];
+    }
+  }
+}
+
+// d = 1 emission by rows.  One wave per update of the bucket collects, with
+// ballots, the subscriptions it meets here: those of the bucket starting in
+// [its lower key, its upper key) (the forward walk), those of the bucket
+// starting before it and still active at its lower key (at most ``span``
+// fine bins back), and the boundary-state subscriptions still active there
+// (staged in LDS first).  These are the update's pairs found in its own
+// bucket, in any order; ranked in LDS (ids in a row are distinct), they are
+// written as the finished row when the update has no other pairs, otherwise
+// at the start of its row in the staging array (the pairs its
+// boundary-state copies find in later buckets follow them; a final row sort
+// orders the whole row).  Then the boundary-state updates walk as usual and
+// emit through device-wide cursors; subscriptions emit nothing.  If the
+// bucket's boundary state holds more than kBsSubCap subscriptions, or a row
+// more than kRowStage pairs, R.flag is set and the caller emits pair by pair
+// instead.
+template <int THREADS, int FINE>
+__device__ __forceinline__ void emit_rows(
+    const uint32_t *KLO, const uint32_t *KHI, const uint32_t *RID, const uint32_t *BIN,
+    uint32_t *stage, uint32_t *BSH, uint32_t *BSR, uint32_t *nbsub, uint32_t span,
+    float vmn, float fscale, uint32_t Cu, uint32_t nbs, const uint32_t *__restrict__ bsr,
+    const RowEmit &R, unsigned long long &hits, const SweepCtx &o) {
+  constexpr int W = THREADS / kWave;
+  const int t = threadIdx.x, lane = lane_id(), w = t / kWave;
+  const uint32_t n = o.n;
+  auto bin_begin = [&](uint32_t k) { return k ? BIN[k - 1] : 0u; };
+  // (a) the boundary-state subscriptions, into LDS
+  for (uint32_t i = (uint32_t)t; i < nbs; i += THREADS) {
+    const uint4 r = reinterpret_cast<const uint4 *>(bsr)[i];
+    if (r.z >= n) {
+      const uint32_t at = atomicAdd(nbsub, 1u);
+      if (at < kBsSubCap) {
+        BSH[at] = r.y;
+        BSR[at] = r.z;
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t nsb = *nbsub;
+  if (nsb > kBsSubCap) {  // uniform over the workgroup
+    if (t == 0) atomicOr(R.flag, 1u);
+    return;
+  }
+  // (b) one wave per bucket update
+  for (uint32_t up = (uint32_t)w; up < Cu; up += W) {
+    const uint32_t ku = KLO[up], hu = KHI[up], ru = RID[up];
+    const uint32_t fl = fine_of(decode_coord(ku), vmn, fscale, FINE);
+    const uint32_t fh = fine_of(decode_coord(hu - o.I.closed), vmn, fscale, FINE);
+    const uint32_t j0 = bin_begin(FINE + (fl > span ? fl - span : 0u));
+    const uint32_t j1 = BIN[FINE + fh];
+    uint32_t L = 0;
+    auto append = [&](bool hit, uint32_t sid) {
+      const uint64_t m = __ballot(hit);
+      const uint32_t at = L + (uint32_t)__popcll(m & lanemask_lt());
+      if (hit && at < kRowStage) stage[at] = sid;
+      L += (uint32_t)__popcll(m);
+    };
+    for (uint32_t j = j0; j < j1; j += kWave) {
+      const uint32_t jj = j + (uint32_t)lane;
+      bool hit = false;
+      uint32_t sid = 0;
+      if (jj < j1) {
+        const uint32_t k = KLO[jj];
+        hit = k < hu && (k >= ku || KHI[jj] > ku);
+        sid = RID[jj] - n;
+      }
+      append(hit, sid);
+    }
+    for (uint32_t i = 0; i < nsb; i += kWave) {
+      const uint32_t ii = i + (uint32_t)lane;
+      const bool hit = ii < nsb && BSH[ii] > ku;  // it starts in an earlier bucket
+      append(hit, hit ? BSR[ii] - n : 0u);
+    }
+    if (L == 0) continue;
+    if (L > kRowStage || L > (uint32_t)R.cnt[ru]) {  // uniform over the wave; never expected
+      if (lane == 0) atomicOr(R.flag, 1u);
+      continue;
+    }
+    if (lane == 0) hits += L;
+    const uint32_t L4 = (L + 3) & ~3u;
+    if ((uint32_t)lane < L4 - L) stage[L + lane] = 0xFFFFFFFFu;
+    __builtin_amdgcn_wave_barrier();
+    const unsigned long long base = o.pair_off[ru];
+    const bool full = (uint32_t)R.cnt[ru] == L;  // no pairs in later buckets
+    uint32_t *ids = full ? R.ids : o.out_s;
+    int2 *pairs = full ? reinterpret_cast<int2 *>(R.pairs) : nullptr;
+    if (L <= kWave)
+      rank_row<1>(stage, L, L4, 0, lane, ru, base, ids, pairs);
+    else if (L <= 2 * kWave)
+      rank_row<2>(stage, L, L4, 0, lane, ru, base, ids, pairs);
+    else
+      for (uint32_t i0 = 0; i0 < L; i0 += 4 * kWave)
+        rank_row<4>(stage, L, L4, i0, lane, ru, base, ids, pairs);
+    __builtin_amdgcn_wave_barrier();  // the row is read before the next one is staged
+  }
+  // (c) the boundary-state updates: the rest of their rows
+  for (uint32_t i = (uint32_t)t; i < nbs; i += THREADS) {
+    const uint4 yr = reinterpret_cast<const uint4 *>(bsr)[i];
+    if (yr.z >= n) continue;
+    Walker<0> y;
+    y.klo = yr.x;
+    y.khi = yr.y;
+    y.rid = yr.z;
+    y.pos = kNoPos;
+    y.upd = true;
+    y.after_key = 0u;
+    y.q = 0u;
+    const uint32_t jA = bin_begin(FINE);
+    const uint32_t fh = fine_of(decode_coord(y.khi - o.I.closed), vmn, fscale, FINE);
+    walk<0, 2>(KLO, RID, nullptr, y, jA, jA, bin_begin(FINE + fh), BIN[FINE + fh], hits, o);
+  }
+}
+
 template <int DM1, int MODE, int CAP, int THREADS, int FINE>
 __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
     const uint32_t *__restrict__ rec, Offsets O, View V, const uint32_t *__restrict__ bs_rec,
@@ -908,7 +1046,7 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
     const unsigned long long *__restrict__ pair_off, uint32_t *__restrict__ cursor,
     uint32_t *__restrict__ out_u, uint32_t *__restrict__ out_s,
     unsigned long long *__restrict__ total, unsigned long long *__restrict__ inst_total,
-    const uint32_t *__restrict__ gate, uint32_t *__restrict__ own_cnt) {
+    const uint32_t *__restrict__ gate, uint32_t *__restrict__ own_cnt, RowEmit R) {
   constexpr int ITEMS = CAP / THREADS;
   constexpr int W = THREADS / kWave;
   constexpr int NBINS = 2 * FINE;
@@ -928,6 +1066,13 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   __shared__ uint32_t queued;
   constexpr bool kDL = DM1 == 0 && MODE != 0;
   __shared__ uint32_t DL[kDL ? CAP + kPad : 1];
+  // d = 1 emission by rows: one row stage per wave, the bucket's
+  // boundary-state subscriptions, the widest subscription in fine bins
+  constexpr bool kRows = DM1 == 0 && MODE == 2;
+  __shared__ __align__(16) uint32_t STAGE[kRows ? W : 1][kRows ? kRowStage + kPad : 1];
+  __shared__ uint32_t BSH[kRows ? kBsSubCap : 1], BSR[kRows ? kBsSubCap : 1];
+  __shared__ uint32_t nbsub, maxspan;
+  const bool rows = kRows && R.cnt != nullptr && own_cnt != nullptr;
 
   if (MODE == 2 && gate && *gate == 0u) return;  // uniform over the grid
   const uint32_t b = blockIdx.x;
@@ -968,7 +1113,11 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   for (int k = t; k < NBINS; k += THREADS) BIN[k] = 0;
   if (kDL)
     for (int k = t; k < CAP + kPad; k += THREADS) DL[k] = 0;
-  if (t == 0) queued = 0;
+  if (t == 0) {
+    queued = 0;
+    nbsub = 0;
+    maxspan = 0;
+  }
   if (t < kPad) {  // defined values in the padding (never counted)
     KLO[CAP + t] = 0;
     if (DM1 > 0) Q[CAP + t] = 0;
@@ -993,8 +1142,11 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   for (int i = 0; i < ITEMS; ++i) {
     const uint32_t s = t + i * THREADS;
     if (s < C) {
-      key[i] = (rk[i].z >= n ? (uint32_t)FINE : 0u) + fine_of(decode_coord(rk[i].x), vmn, fscale, FINE);
+      const uint32_t f = fine_of(decode_coord(rk[i].x), vmn, fscale, FINE);
+      key[i] = (rk[i].z >= n ? (uint32_t)FINE : 0u) + f;
       atomicAdd(&BIN[key[i]], 1u);
+      if (rows && rk[i].z >= n)  // fine bins a subscription spans past its own
+        atomicMax(&maxspan, fine_of(decode_coord(rk[i].y - I.closed), vmn, fscale, FINE) - f);
     }
   }
   __syncthreads();
@@ -1036,7 +1188,11 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   //    ranges and the boundary-state walkers are spread over all waves.
   unsigned long long hits = 0;
   const int lane = lane_id(), w = t / kWave;
-  const uint32_t walkers = C + nbs;
+  const uint32_t walkers = rows ? 0u : C + nbs;
+  if (kRows && rows)
+    emit_rows<THREADS, FINE>(KLO, KHI, RID, BIN, STAGE[kRows ? w : 0], BSH, BSR, &nbsub,
+                             maxspan, vmn, fscale, Cu, nbs, bs_rec + (size_t)bs_begin * 4, R,
+                             hits, o);
   for (uint32_t base = (uint32_t)w * kWave; base < walkers; base += (uint32_t)THREADS) {
     const uint32_t q = base + (uint32_t)lane;
     if (q >= walkers) continue;
@@ -1185,15 +1341,15 @@ void sweep_impl(const BucketArgs &a, int32_t *per_update, const unsigned long lo
   if (L.tune.sweep_threads == 1024)
     bk_sweep_kernel<DM1, MODE, kBigCap, 1024, 1024><<<L.nb, 1024, 0, s>>>(
         p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
-        out_u, out_s, total, a.inst_total, gate, a.own);
+        out_u, out_s, total, a.inst_total, gate, a.own, a.rows);
   else if (L.tune.sweep_threads == 256)
     bk_sweep_kernel<DM1, MODE, kCap, 256, 512><<<L.nb, 256, 0, s>>>(
         p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
-        out_u, out_s, total, a.inst_total, gate, a.own);
+        out_u, out_s, total, a.inst_total, gate, a.own, a.rows);
   else
     bk_sweep_kernel<DM1, MODE, kCap, 512, 512><<<L.nb, 512, 0, s>>>(
         p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
-        out_u, out_s, total, a.inst_total, gate, a.own);
+        out_u, out_s, total, a.inst_total, gate, a.own, a.rows);
 }
 
 // Host-side plan of one instance; returns false if it does not fit.
@@ -1253,7 +1409,7 @@ bool bucket_path_supported(int d, int64_t n, int64_t m) {
   return bucket_path_supported(d, &sp, 1, BucketTuning{});
 }
 
-BucketLayout bucket_layout(const InstSpec *inst, int64_t B, int d, const BucketTuning &t) {
+BucketLayout bucket_layout(const InstSpec *inst, int64_t B, int /*d*/, const BucketTuning &t) {
   BucketLayout L{};
   L.B = (uint32_t)B;
   L.tune = t;

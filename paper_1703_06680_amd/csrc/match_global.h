@@ -49,8 +49,10 @@ constexpr uint32_t kRowMax = 2048;
 // Orders each row u (cnt[u] subscription ids at in[off[u] ..)) by id into
 // ids[off[u] ..) (CSR), or, with pairs non-null, into pairs rows
 // (u, id) at off[u] .. (int32 [K][2]).  Every row must hold distinct ids and
-// at most kRowMax of them.
+// at most kRowMax of them.  With ``done``, rows with done[u] == cnt[u] are
+// skipped (already written in order).
 void launch_row_sort(const unsigned long long *off, const int32_t *cnt, const uint32_t *in,
-                     uint32_t n, uint32_t *ids, int32_t *pairs, hipStream_t s);
+                     uint32_t n, uint32_t *ids, int32_t *pairs, hipStream_t s,
+                     const uint32_t *done = nullptr);
 
 }  // namespace ddm

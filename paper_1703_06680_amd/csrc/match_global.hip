@@ -290,7 +290,7 @@ template <bool kPairs>
 __global__ __launch_bounds__(kThreads) void row_sort_kernel(
     const unsigned long long *__restrict__ off, const int32_t *__restrict__ cnt,
     const uint32_t *__restrict__ in, uint32_t n, uint32_t *__restrict__ ids,
-    int2 *__restrict__ pairs) {
+    int2 *__restrict__ pairs, const uint32_t *__restrict__ done) {
   __shared__ __align__(16) uint32_t stage[kRowWaves][kRowMax];
   const int w = threadIdx.x / kWave, lane = lane_id();
   uint32_t *row = stage[w];
@@ -298,6 +298,7 @@ __global__ __launch_bounds__(kThreads) void row_sort_kernel(
   for (uint32_t u = blockIdx.x * kRowWaves + w; u < n; u += step) {
     const uint32_t L = (uint32_t)cnt[u];
     if (L == 0 || L > kRowMax) continue;  // longer rows are never passed here
+    if (done && done[u] == L) continue;   // already written in order
     const unsigned long long base = off[u];
     if (L == 1) {
       if (lane == 0) {
@@ -408,15 +409,16 @@ void launch_widen(const int32_t *in, unsigned long long *out, size_t count, hipS
 }
 
 void launch_row_sort(const unsigned long long *off, const int32_t *cnt, const uint32_t *in,
-                     uint32_t n, uint32_t *ids, int32_t *pairs, hipStream_t s) {
+                     uint32_t n, uint32_t *ids, int32_t *pairs, hipStream_t s,
+                     const uint32_t *done) {
   if (!n) return;
   prof::mark(s, "pairs.rowsort");
   const unsigned grid = grid_for((size_t)n * kWave / kRowWaves, 4096);
   if (pairs)
     row_sort_kernel<true><<<grid, kThreads, 0, s>>>(off, cnt, in, n, nullptr,
-                                                    reinterpret_cast<int2 *>(pairs));
+                                                    reinterpret_cast<int2 *>(pairs), done);
   else
-    row_sort_kernel<false><<<grid, kThreads, 0, s>>>(off, cnt, in, n, ids, nullptr);
+    row_sort_kernel<false><<<grid, kThreads, 0, s>>>(off, cnt, in, n, ids, nullptr, done);
 }
 
 }  // namespace ddm

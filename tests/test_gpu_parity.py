@@ -453,3 +453,22 @@ def test_pairs_rows_at_and_beyond_the_row_sort_limit(ddm, oracle, rows):
     k_ref, per_ref, _ = oracle.sbm(*_host(inst))
     assert per_ref.tolist() == list(rows)
     check_all_modes(ddm, oracle, inst, expect_bucketed=False)
+
+
+def test_d1_rows_boundary_state_beyond_lds(ddm, oracle):
+    """d = 1 pairs where some buckets carry more boundary-state subscriptions
+    than the row emission holds in LDS, so the call falls back to emission
+    pair by pair, while every row is short: 3000 long subscriptions on
+    [0, 2000) that meet no update, and 20000 short updates on [2000, 12000)
+    each with one subscription on top of it."""
+    rng = np.random.default_rng(9)
+    long_lo = (rng.random(3000) * 1000.0).astype(np.float32)
+    long_hi = (long_lo + np.float32(1000.0)).astype(np.float32)
+    u_lo = (2000.0 + rng.random(20000) * 10000.0).astype(np.float32)
+    u_hi = (u_lo + np.float32(0.001)).astype(np.float32)
+    slo = np.concatenate([long_lo, u_lo]).reshape(-1, 1)
+    shi = np.concatenate([long_hi, u_hi]).reshape(-1, 1)
+    inst = W.Instance(u_lo.reshape(-1, 1), u_hi.reshape(-1, 1), slo, shi, float("nan"),
+                      "d1_wide_boundary_state")
+    assert oracle.sbm(*_host(inst), pairs=False)[0] >= 20000
+    check_all_modes(ddm, oracle, inst)
