@@ -27,8 +27,8 @@ namespace ddm {
 // found in its bucket are gathered by one wave, ordered in LDS and written
 // as a finished row; rows that also get pairs from later buckets are left,
 // ordered, in the staging array for a final row sort.
-constexpr uint32_t kRowStage = 512;    // longest row the emitting waves can hold
-constexpr uint32_t kBsSubCap = 1024;   // boundary-state subscriptions per bucket held in LDS
+constexpr uint32_t kRowStage = 256;    // longest row the emitting waves can hold
+constexpr uint32_t kBsSubCap = 512;    // boundary-state subscriptions per bucket held in LDS
 struct RowEmit {
   const int32_t *cnt;  // per-update pair counts (null: emission pair by pair)
   uint32_t *ids;       // CSR output (subscription ids), or null

@@ -945,7 +945,8 @@ __device__ __forceinline__ void rank_row(const uint32_t *stage, uint32_t L, uint
 template <int THREADS, int FINE>
 __device__ __forceinline__ void emit_rows(
     const uint32_t *KLO, const uint32_t *KHI, const uint32_t *RID, const uint32_t *BIN,
-    uint32_t *stage, uint32_t *BSH, uint32_t *BSR, uint32_t *nbsub, uint32_t span,
+    uint32_t *stage, uint32_t *BSH, uint32_t *BSR, uint32_t *nbsub, uint32_t *maxbsh,
+    uint32_t span,
     float vmn, float fscale, uint32_t Cu, uint32_t nbs, const uint32_t *__restrict__ bsr,
     const RowEmit &R, unsigned long long &hits, const SweepCtx &o) {
   constexpr int W = THREADS / kWave;
@@ -961,10 +962,11 @@ __device__ __forceinline__ void emit_rows(
         BSH[at] = r.y;
         BSR[at] = r.z;
       }
+      atomicMax(maxbsh, r.y);
     }
   }
   __syncthreads();
-  const uint32_t nsb = *nbsub;
+  const uint32_t nsb = *nbsub, reach = *maxbsh;
   if (nsb > kBsSubCap) {  // uniform over the workgroup
     if (t == 0) atomicOr(R.flag, 1u);
     return;
@@ -994,7 +996,8 @@ __device__ __forceinline__ void emit_rows(
       }
       append(hit, sid);
     }
-    for (uint32_t i = 0; i < nsb; i += kWave) {
+    // boundary-state subscriptions reach only the start of the bucket
+    for (uint32_t i = 0; ku < reach && i < nsb; i += kWave) {
       const uint32_t ii = i + (uint32_t)lane;
       const bool hit = ii < nsb && BSH[ii] > ku;  // it starts in an earlier bucket
       append(hit, hit ? BSR[ii] - n : 0u);
@@ -1064,14 +1067,19 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   __shared__ unsigned long long red64[W];
   __shared__ uint2 queue[DM1 > 0 ? kQueue : 1];
   __shared__ uint32_t queued;
+  // d = 1: the per-position array DL of the count pass and of the
+  // pair-by-pair emission, or, for the emission by rows, one row stage per
+  // wave and the bucket's boundary-state subscriptions (upper key, region);
+  // the two uses share the space
   constexpr bool kDL = DM1 == 0 && MODE != 0;
-  __shared__ uint32_t DL[kDL ? CAP + kPad : 1];
-  // d = 1 emission by rows: one row stage per wave, the bucket's
-  // boundary-state subscriptions, the widest subscription in fine bins
   constexpr bool kRows = DM1 == 0 && MODE == 2;
-  __shared__ __align__(16) uint32_t STAGE[kRows ? W : 1][kRows ? kRowStage + kPad : 1];
-  __shared__ uint32_t BSH[kRows ? kBsSubCap : 1], BSR[kRows ? kBsSubCap : 1];
-  __shared__ uint32_t nbsub, maxspan;
+  constexpr uint32_t kStageWords = W * (kRowStage + kPad);
+  constexpr uint32_t kRowsWords = kStageWords + 2 * kBsSubCap;
+  constexpr uint32_t kDLWords = CAP + kPad;
+  __shared__ __align__(16) uint32_t SCR[kRows ? (kRowsWords > kDLWords ? kRowsWords : kDLWords)
+                                              : (kDL ? kDLWords : 1)];
+  uint32_t *DL = SCR;
+  __shared__ uint32_t nbsub, maxspan, maxbsh;
   const bool rows = kRows && R.cnt != nullptr && own_cnt != nullptr;
 
   if (MODE == 2 && gate && *gate == 0u) return;  // uniform over the grid
@@ -1111,12 +1119,13 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
     redf[2 * (t / kWave) + 1] = vmx;
   }
   for (int k = t; k < NBINS; k += THREADS) BIN[k] = 0;
-  if (kDL)
+  if (kDL && !rows)
     for (int k = t; k < CAP + kPad; k += THREADS) DL[k] = 0;
   if (t == 0) {
     queued = 0;
     nbsub = 0;
     maxspan = 0;
+    maxbsh = 0;
   }
   if (t < kPad) {  // defined values in the padding (never counted)
     KLO[CAP + t] = 0;
@@ -1190,7 +1199,8 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   const int lane = lane_id(), w = t / kWave;
   const uint32_t walkers = rows ? 0u : C + nbs;
   if (kRows && rows)
-    emit_rows<THREADS, FINE>(KLO, KHI, RID, BIN, STAGE[kRows ? w : 0], BSH, BSR, &nbsub,
+    emit_rows<THREADS, FINE>(KLO, KHI, RID, BIN, SCR + (size_t)w * (kRowStage + kPad),
+                             SCR + kStageWords, SCR + kStageWords + kBsSubCap, &nbsub, &maxbsh,
                              maxspan, vmn, fscale, Cu, nbs, bs_rec + (size_t)bs_begin * 4, R,
                              hits, o);
   for (uint32_t base = (uint32_t)w * kWave; base < walkers; base += (uint32_t)THREADS) {
