@@ -895,6 +895,30 @@ __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
   }
 }
 
+// A row of L <= 64 * NPER ids staged in LDS, sorted across the wave in
+// registers and written in order (coalesced).
+template <int NPER>
+__device__ __forceinline__ void sort_row(const uint32_t *stage, uint32_t L, int lane, uint32_t u,
+                                         unsigned long long base, uint32_t *ids, int2 *pairs) {
+  uint32_t v[NPER];
+#pragma unroll
+  for (int r = 0; r < NPER; ++r) {
+    const uint32_t e = (uint32_t)lane + 64u * (uint32_t)r;
+    v[r] = e < L ? stage[e] : 0xFFFFFFFFu;
+  }
+  wave_bitonic_sort<NPER>(v);
+#pragma unroll
+  for (int r = 0; r < NPER; ++r) {
+    const uint32_t e = (uint32_t)lane + 64u * (uint32_t)r;
+    if (e < L) {
+      if (pairs)
+        pairs[base + e] = make_int2((int32_t)u, (int32_t)v[r]);
+      else
+        ids[base + e] = v[r];
+    }
+  }
+}
+
 // Ranks of ids v (kPer per lane, from position i0) among the L4 staged ids
 // of a row (padding above every id); each id is written to its rank.
 template <int kPer>
@@ -1016,9 +1040,9 @@ __device__ __forceinline__ void emit_rows(
     uint32_t *ids = full ? R.ids : o.out_s;
     int2 *pairs = full ? reinterpret_cast<int2 *>(R.pairs) : nullptr;
     if (L <= kWave)
-      rank_row<1>(stage, L, L4, 0, lane, ru, base, ids, pairs);
+      sort_row<1>(stage, L, lane, ru, base, ids, pairs);
     else if (L <= 2 * kWave)
-      rank_row<2>(stage, L, L4, 0, lane, ru, base, ids, pairs);
+      sort_row<2>(stage, L, lane, ru, base, ids, pairs);
     else
       for (uint32_t i0 = 0; i0 < L; i0 += 4 * kWave)
         rank_row<4>(stage, L, L4, i0, lane, ru, base, ids, pairs);

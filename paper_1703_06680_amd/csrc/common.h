@@ -78,6 +78,37 @@ __device__ __forceinline__ T wave_inclusive_scan(T v) {
   return v;
 }
 
+// Ascending bitonic sort of the 64 * NPER values held by a wave, element e
+// in lane e % 64 of register e / 64 (NPER = 1 or 2).  After the call the
+// same layout holds the sorted sequence.
+template <int NPER>
+__device__ __forceinline__ void wave_bitonic_sort(uint32_t (&v)[NPER]) {
+  static_assert(NPER == 1 || NPER == 2, "64 or 128 values");
+  constexpr uint32_t N = 64u * NPER;
+  const uint32_t lane = (uint32_t)lane_id();
+#pragma unroll
+  for (uint32_t k = 2; k <= N; k <<= 1) {
+#pragma unroll
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      if (j >= 64u) {  // partner in the other register of the same lane
+        const uint32_t lo = min(v[0], v[NPER - 1]), hi = max(v[0], v[NPER - 1]);
+        // element e keeps the smaller value iff (e & k == 0) == (e & j == 0)
+        const bool up0 = (lane & k) == 0;  // element lane has bit j clear
+        v[0] = up0 ? lo : hi;
+        v[NPER - 1] = up0 ? hi : lo;
+      } else {
+#pragma unroll
+        for (int r = 0; r < NPER; ++r) {
+          const uint32_t e = lane + 64u * (uint32_t)r;
+          const uint32_t p = __shfl_xor(v[r], (int)j, kWave);
+          const bool keep_min = ((e & k) == 0) == ((e & j) == 0);
+          v[r] = keep_min ? min(v[r], p) : max(v[r], p);
+        }
+      }
+    }
+  }
+}
+
 // Exclusive prefix sum over a block of THREADS threads.  ``lds`` must hold
 // THREADS/64 + 1 elements.  Returns the exclusive prefix of ``v`` and writes
 // the block total to ``*total``.  Contains barriers: every thread must call.

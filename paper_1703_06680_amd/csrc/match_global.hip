@@ -312,11 +312,30 @@ __global__ __launch_bounds__(kThreads) void row_sort_kernel(
     const uint32_t L4 = (L + 3) & ~3u;  // padded with ids above every real one
     for (uint32_t i = lane; i < L4; i += kWave) row[i] = i < L ? in[base + i] : 0xFFFFFFFFu;
     __builtin_amdgcn_wave_barrier();
-    // as many ids per lane as the row needs, up to four per scan of the row
-    if (L <= kWave) {
-      rank_and_store<kPairs, 1>(row, L, L4, 0, lane, u, base, ids, pairs);
-    } else if (L <= 2 * kWave) {
-      rank_and_store<kPairs, 2>(row, L, L4, 0, lane, u, base, ids, pairs);
+    // up to 128 ids: sorted across the wave in registers; longer rows: ranks
+    if (L <= 2 * kWave) {
+      uint32_t v[2];
+      v[0] = row[lane];
+      v[1] = L > kWave ? row[kWave + lane] : 0xFFFFFFFFu;
+      if ((uint32_t)lane >= L) v[0] = 0xFFFFFFFFu;
+      if ((uint32_t)(kWave + lane) >= L) v[1] = 0xFFFFFFFFu;
+      if (L <= kWave) {
+        uint32_t one[1] = {v[0]};
+        wave_bitonic_sort<1>(one);
+        v[0] = one[0];
+      } else {
+        wave_bitonic_sort<2>(v);
+      }
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const uint32_t e = (uint32_t)(lane + kWave * r);
+        if (e < L) {
+          if (kPairs)
+            pairs[base + e] = make_int2((int32_t)u, (int32_t)v[r]);
+          else
+            ids[base + e] = v[r];
+        }
+      }
     } else {
       for (uint32_t i0 = 0; i0 < L; i0 += 4 * kWave)
         rank_and_store<kPairs, 4>(row, L, L4, i0, lane, u, base, ids, pairs);
