@@ -294,53 +294,65 @@ __global__ __launch_bounds__(kThreads) void row_sort_kernel(
   __shared__ __align__(16) uint32_t stage[kRowWaves][kRowMax];
   const int w = threadIdx.x / kWave, lane = lane_id();
   uint32_t *row = stage[w];
-  const uint32_t step = gridDim.x * kRowWaves;
-  for (uint32_t u = blockIdx.x * kRowWaves + w; u < n; u += step) {
-    const uint32_t L = (uint32_t)cnt[u];
-    if (L == 0 || L > kRowMax) continue;  // longer rows are never passed here
-    if (done && done[u] == L) continue;   // already written in order
-    const unsigned long long base = off[u];
-    if (L == 1) {
-      if (lane == 0) {
-        if (kPairs)
-          pairs[base] = make_int2((int32_t)u, (int32_t)in[base]);
-        else
-          ids[base] = in[base];
-      }
-      continue;
+  // each wave takes 64 consecutive rows at a time, finds with one ballot the
+  // ones with work and orders those one after the other
+  const uint32_t step = gridDim.x * kRowWaves * kWave;
+  for (uint32_t u0 = (blockIdx.x * kRowWaves + w) * kWave; u0 < n; u0 += step) {
+    const uint32_t mine = u0 + (uint32_t)lane;
+    bool work = false;
+    if (mine < n) {
+      const uint32_t c = (uint32_t)cnt[mine];
+      // longer rows are never passed here; done rows are already in order
+      work = c != 0 && c <= kRowMax && !(done && done[mine] == c);
     }
-    const uint32_t L4 = (L + 3) & ~3u;  // padded with ids above every real one
-    for (uint32_t i = lane; i < L4; i += kWave) row[i] = i < L ? in[base + i] : 0xFFFFFFFFu;
-    __builtin_amdgcn_wave_barrier();
-    // up to 128 ids: sorted across the wave in registers; longer rows: ranks
-    if (L <= 2 * kWave) {
-      uint32_t v[2];
-      v[0] = row[lane];
-      v[1] = L > kWave ? row[kWave + lane] : 0xFFFFFFFFu;
-      if ((uint32_t)lane >= L) v[0] = 0xFFFFFFFFu;
-      if ((uint32_t)(kWave + lane) >= L) v[1] = 0xFFFFFFFFu;
-      if (L <= kWave) {
-        uint32_t one[1] = {v[0]};
-        wave_bitonic_sort<1>(one);
-        v[0] = one[0];
-      } else {
-        wave_bitonic_sort<2>(v);
-      }
-#pragma unroll
-      for (int r = 0; r < 2; ++r) {
-        const uint32_t e = (uint32_t)(lane + kWave * r);
-        if (e < L) {
+    uint64_t todo = __ballot(work);
+    while (todo) {
+      const uint32_t u = u0 + (uint32_t)(__ffsll((unsigned long long)todo) - 1);
+      todo &= todo - 1;
+      const uint32_t L = (uint32_t)cnt[u];
+      const unsigned long long base = off[u];
+      if (L == 1) {
+        if (lane == 0) {
           if (kPairs)
-            pairs[base + e] = make_int2((int32_t)u, (int32_t)v[r]);
+            pairs[base] = make_int2((int32_t)u, (int32_t)in[base]);
           else
-            ids[base + e] = v[r];
+            ids[base] = in[base];
         }
+        continue;
       }
-    } else {
-      for (uint32_t i0 = 0; i0 < L; i0 += 4 * kWave)
-        rank_and_store<kPairs, 4>(row, L, L4, i0, lane, u, base, ids, pairs);
+      const uint32_t L4 = (L + 3) & ~3u;  // padded with ids above every real one
+      for (uint32_t i = lane; i < L4; i += kWave) row[i] = i < L ? in[base + i] : 0xFFFFFFFFu;
+      __builtin_amdgcn_wave_barrier();
+      // up to 128 ids: sorted across the wave in registers; longer rows: ranks
+      if (L <= 2 * kWave) {
+        uint32_t v[2];
+        v[0] = row[lane];
+        v[1] = L > kWave ? row[kWave + lane] : 0xFFFFFFFFu;
+        if ((uint32_t)lane >= L) v[0] = 0xFFFFFFFFu;
+        if ((uint32_t)(kWave + lane) >= L) v[1] = 0xFFFFFFFFu;
+        if (L <= kWave) {
+          uint32_t one[1] = {v[0]};
+          wave_bitonic_sort<1>(one);
+          v[0] = one[0];
+        } else {
+          wave_bitonic_sort<2>(v);
+        }
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          const uint32_t e = (uint32_t)(lane + kWave * r);
+          if (e < L) {
+            if (kPairs)
+              pairs[base + e] = make_int2((int32_t)u, (int32_t)v[r]);
+            else
+              ids[base + e] = v[r];
+          }
+        }
+      } else {
+        for (uint32_t i0 = 0; i0 < L; i0 += 4 * kWave)
+          rank_and_store<kPairs, 4>(row, L, L4, i0, lane, u, base, ids, pairs);
+      }
+      __builtin_amdgcn_wave_barrier();  // every lane done with the row before the next one
     }
-    __builtin_amdgcn_wave_barrier();  // every lane done with the row before the next one
   }
 }
 
@@ -432,7 +444,7 @@ void launch_row_sort(const unsigned long long *off, const int32_t *cnt, const ui
                      const uint32_t *done) {
   if (!n) return;
   prof::mark(s, "pairs.rowsort");
-  const unsigned grid = grid_for((size_t)n * kWave / kRowWaves, 4096);
+  const unsigned grid = grid_for((size_t)n / kRowWaves, 4096);
   if (pairs)
     row_sort_kernel<true><<<grid, kThreads, 0, s>>>(off, cnt, in, n, nullptr,
                                                     reinterpret_cast<int2 *>(pairs), done);
