@@ -895,62 +895,6 @@ __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
   }
 }
 
-// A row of L <= 64 * NPER ids staged in LDS, sorted across the wave in
-// registers and written in order (coalesced).
-template <int NPER>
-__device__ __forceinline__ void sort_row(const uint32_t *stage, uint32_t L, int lane, uint32_t u,
-                                         unsigned long long base, uint32_t *ids, int2 *pairs) {
-  uint32_t v[NPER];
-#pragma unroll
-  for (int r = 0; r < NPER; ++r) {
-    const uint32_t e = (uint32_t)lane + 64u * (uint32_t)r;
-    v[r] = e < L ? stage[e] : 0xFFFFFFFFu;
-  }
-  wave_bitonic_sort<NPER>(v);
-#pragma unroll
-  for (int r = 0; r < NPER; ++r) {
-    const uint32_t e = (uint32_t)lane + 64u * (uint32_t)r;
-    if (e < L) {
-      if (pairs)
-        pairs[base + e] = make_int2((int32_t)u, (int32_t)v[r]);
-      else
-        ids[base + e] = v[r];
-    }
-  }
-}
-
-// Ranks of ids v (kPer per lane, from position i0) among the L4 staged ids
-// of a row (padding above every id); each id is written to its rank.
-template <int kPer>
-__device__ __forceinline__ void rank_row(const uint32_t *stage, uint32_t L, uint32_t L4,
-                                         uint32_t i0, int lane, uint32_t u, unsigned long long base,
-                                         uint32_t *ids, int2 *pairs) {
-  uint32_t v[kPer], rank[kPer];
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    const uint32_t i = i0 + k * kWave + lane;
-    v[k] = i < L ? stage[i] : 0xFFFFFFFFu;
-    rank[k] = 0;
-  }
-  for (uint32_t j = 0; j < L4; j += 4) {
-    const uint4 q = *reinterpret_cast<const uint4 *>(stage + j);  // same address in every lane
-#pragma unroll
-    for (int k = 0; k < kPer; ++k)
-      rank[k] += (uint32_t)(q.x < v[k]) + (uint32_t)(q.y < v[k]) + (uint32_t)(q.z < v[k]) +
-                 (uint32_t)(q.w < v[k]);
-  }
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    const uint32_t i = i0 + k * kWave + lane;
-    if (i < L) {
-      if (pairs)
-        pairs[base + rank[k]] = make_int2((int32_t)u, (int32_t)v[k]);
-      else
-        ids[base + rank[k]] = v[k];
-    }
-  }
-}
-
 // d = 1 emission by rows.  One wave per update of the bucket collects, with
 // ballots, the subscriptions it meets here: those of the bucket starting in
 // [its lower key, its upper key) (the forward walk), those of the bucket

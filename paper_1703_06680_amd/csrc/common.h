@@ -109,6 +109,68 @@ __device__ __forceinline__ void wave_bitonic_sort(uint32_t (&v)[NPER]) {
   }
 }
 
+// Ordering one row of a pair list (update u's subscription ids, all
+// distinct) that a wave has staged in LDS: the ids go to
+// ids[base + position] (CSR), or, with pairs non-null, to
+// pairs[base + position] = (u, id).
+//
+// sort_row: a row of L <= 64 * NPER ids, sorted across the wave in
+// registers and written in order (coalesced).
+template <int NPER>
+__device__ __forceinline__ void sort_row(const uint32_t *stage, uint32_t L, int lane, uint32_t u,
+                                         unsigned long long base, uint32_t *ids, int2 *pairs) {
+  uint32_t v[NPER];
+#pragma unroll
+  for (int r = 0; r < NPER; ++r) {
+    const uint32_t e = (uint32_t)lane + 64u * (uint32_t)r;
+    v[r] = e < L ? stage[e] : 0xFFFFFFFFu;
+  }
+  wave_bitonic_sort<NPER>(v);
+#pragma unroll
+  for (int r = 0; r < NPER; ++r) {
+    const uint32_t e = (uint32_t)lane + 64u * (uint32_t)r;
+    if (e < L) {
+      if (pairs)
+        pairs[base + e] = make_int2((int32_t)u, (int32_t)v[r]);
+      else
+        ids[base + e] = v[r];
+    }
+  }
+}
+
+// rank_row: the ids at positions i0 .. i0 + 64 kPer of a row of L ids,
+// staged with padding above every id up to L4 (a multiple of four); each
+// goes to its rank, the number of the row's ids below it.
+template <int kPer>
+__device__ __forceinline__ void rank_row(const uint32_t *stage, uint32_t L, uint32_t L4,
+                                         uint32_t i0, int lane, uint32_t u, unsigned long long base,
+                                         uint32_t *ids, int2 *pairs) {
+  uint32_t v[kPer], rank[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const uint32_t i = i0 + k * kWave + lane;
+    v[k] = i < L ? stage[i] : 0xFFFFFFFFu;
+    rank[k] = 0;
+  }
+  for (uint32_t j = 0; j < L4; j += 4) {
+    const uint4 q = *reinterpret_cast<const uint4 *>(stage + j);  // same address in every lane
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+      rank[k] += (uint32_t)(q.x < v[k]) + (uint32_t)(q.y < v[k]) + (uint32_t)(q.z < v[k]) +
+                 (uint32_t)(q.w < v[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const uint32_t i = i0 + k * kWave + lane;
+    if (i < L) {
+      if (pairs)
+        pairs[base + rank[k]] = make_int2((int32_t)u, (int32_t)v[k]);
+      else
+        ids[base + rank[k]] = v[k];
+    }
+  }
+}
+
 // Exclusive prefix sum over a block of THREADS threads.  ``lds`` must hold
 // THREADS/64 + 1 elements.  Returns the exclusive prefix of ``v`` and writes
 // the block total to ``*total``.  Contains barriers: every thread must call.

@@ -253,39 +253,6 @@ __global__ void widen_kernel(const int32_t *__restrict__ in, unsigned long long 
 // permutation.  Rows of at most kRowMax ids.
 constexpr int kRowWaves = kThreads / kWave;
 
-// Ranks of ids v (kPer per lane, chunk starting at i0) among the row's L4
-// staged ids (padding above every id), and their stores.
-template <bool kPairs, int kPer>
-__device__ __forceinline__ void rank_and_store(const uint32_t *row, uint32_t L, uint32_t L4,
-                                               uint32_t i0, int lane, uint32_t u,
-                                               unsigned long long base, uint32_t *ids,
-                                               int2 *pairs) {
-  uint32_t v[kPer], rank[kPer];
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    const uint32_t i = i0 + k * kWave + lane;
-    v[k] = i < L ? row[i] : 0xFFFFFFFFu;
-    rank[k] = 0;
-  }
-  for (uint32_t j = 0; j < L4; j += 4) {
-    const uint4 q = *reinterpret_cast<const uint4 *>(row + j);  // same address in every lane
-#pragma unroll
-    for (int k = 0; k < kPer; ++k)
-      rank[k] += (uint32_t)(q.x < v[k]) + (uint32_t)(q.y < v[k]) + (uint32_t)(q.z < v[k]) +
-                 (uint32_t)(q.w < v[k]);
-  }
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    const uint32_t i = i0 + k * kWave + lane;
-    if (i < L) {
-      if (kPairs)
-        pairs[base + rank[k]] = make_int2((int32_t)u, (int32_t)v[k]);
-      else
-        ids[base + rank[k]] = v[k];
-    }
-  }
-}
-
 template <bool kPairs>
 __global__ __launch_bounds__(kThreads) void row_sort_kernel(
     const unsigned long long *__restrict__ off, const int32_t *__restrict__ cnt,
@@ -324,33 +291,14 @@ __global__ __launch_bounds__(kThreads) void row_sort_kernel(
       for (uint32_t i = lane; i < L4; i += kWave) row[i] = i < L ? in[base + i] : 0xFFFFFFFFu;
       __builtin_amdgcn_wave_barrier();
       // up to 128 ids: sorted across the wave in registers; longer rows: ranks
-      if (L <= 2 * kWave) {
-        uint32_t v[2];
-        v[0] = row[lane];
-        v[1] = L > kWave ? row[kWave + lane] : 0xFFFFFFFFu;
-        if ((uint32_t)lane >= L) v[0] = 0xFFFFFFFFu;
-        if ((uint32_t)(kWave + lane) >= L) v[1] = 0xFFFFFFFFu;
-        if (L <= kWave) {
-          uint32_t one[1] = {v[0]};
-          wave_bitonic_sort<1>(one);
-          v[0] = one[0];
-        } else {
-          wave_bitonic_sort<2>(v);
-        }
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-          const uint32_t e = (uint32_t)(lane + kWave * r);
-          if (e < L) {
-            if (kPairs)
-              pairs[base + e] = make_int2((int32_t)u, (int32_t)v[r]);
-            else
-              ids[base + e] = v[r];
-          }
-        }
-      } else {
+      int2 *prow = kPairs ? pairs : nullptr;
+      if (L <= kWave)
+        sort_row<1>(row, L, lane, u, base, ids, prow);
+      else if (L <= 2 * kWave)
+        sort_row<2>(row, L, lane, u, base, ids, prow);
+      else
         for (uint32_t i0 = 0; i0 < L; i0 += 4 * kWave)
-          rank_and_store<kPairs, 4>(row, L, L4, i0, lane, u, base, ids, pairs);
-      }
+          rank_row<4>(row, L, L4, i0, lane, u, base, ids, prow);
       __builtin_amdgcn_wave_barrier();  // every lane done with the row before the next one
     }
   }
