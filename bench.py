@@ -435,6 +435,18 @@ def main():
                         "avg_launch_ms": round(avg_ms, 4),
                         "algorithmic_bytes_per_launch": int(alg)}
 
+    # HBM traffic of the whole step by counters (count + scatter + sweep, the
+    # kernels that move the data) over their measured time
+    step_traffic = None
+    if phases:
+        kern = ("bucket.count", "bucket.scatter", "bucket.sweep")
+        tb = [load_traffic(k) for k in kern]
+        if all(tb) and all(k in phases for k in kern):
+            ms = sum(phases[k]["ms"] / max(phases[k]["launches"], 1) for k in kern)
+            gbs = sum(tb) / (ms * 1e-3) / 1e9
+            step_traffic = {"kernels": list(kern), "bytes": int(sum(tb)), "ms": round(ms, 4),
+                            "gb_per_s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
     per_alpha = {}
     for a in [float(x) for x in args.also_alphas.split(",") if x.strip()]:
         extra = W.uniform_instance(n, m, d, a, seed=0)
@@ -556,6 +568,7 @@ def main():
         "step_ms_p50": round(1e3 * statistics.median(per_step), 4),
         "step_ms_p99": round(1e3 * float(np.percentile(per_step, 99)), 4),
         "roofline": roofline,
+        "step_counter_traffic": step_traffic,
         "cpu_baseline": cpu,
         "phases_ms_per_step": {p: round(v["ms"] / args.steps, 4) for p, v in sorted(phases.items())},
         "per_alpha": per_alpha,
