@@ -78,35 +78,61 @@ __device__ __forceinline__ T wave_inclusive_scan(T v) {
   return v;
 }
 
+// Value of lane (lane ^ J) of a wave: DPP quad permutes for J = 1, 2,
+// ds_swizzle (bitmask mode, within 32-lane halves) for J = 4, 8, 16, a
+// lane permute for 32.
+template <uint32_t J>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v) {
+  if constexpr (J == 1)
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);  // [1,0,3,2]
+  else if constexpr (J == 2)
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);  // [2,3,0,1]
+  else if constexpr (J == 4 || J == 8 || J == 16)
+    return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (J << 10));
+  else
+    return (uint32_t)__shfl_xor((int)v, (int)J, kWave);
+}
+
+// One compare-exchange stage of the bitonic network (partner distance J
+// below 64, block size K).
+template <int NPER, uint32_t K, uint32_t J>
+__device__ __forceinline__ void bitonic_stage(uint32_t (&v)[NPER], uint32_t lane) {
+#pragma unroll
+  for (int r = 0; r < NPER; ++r) {
+    const uint32_t e = lane + 64u * (uint32_t)r;
+    const uint32_t p = lane_xor<J>(v[r]);
+    // element e keeps the smaller value iff (e & K == 0) == (e & J == 0)
+    const bool keep_min = ((e & K) == 0) == ((e & J) == 0);
+    v[r] = keep_min ? min(v[r], p) : max(v[r], p);
+  }
+}
+
+template <int NPER, uint32_t K, uint32_t J>
+__device__ __forceinline__ void bitonic_merge(uint32_t (&v)[NPER], uint32_t lane) {
+  if constexpr (J >= 64) {  // partner in the other register of the same lane
+    const uint32_t lo = min(v[0], v[NPER - 1]), hi = max(v[0], v[NPER - 1]);
+    const bool up0 = (lane & K) == 0;
+    v[0] = up0 ? lo : hi;
+    v[NPER - 1] = up0 ? hi : lo;
+  } else {
+    bitonic_stage<NPER, K, J>(v, lane);
+  }
+  if constexpr (J > 1) bitonic_merge<NPER, K, J / 2>(v, lane);
+}
+
+template <int NPER, uint32_t K>
+__device__ __forceinline__ void bitonic_from(uint32_t (&v)[NPER], uint32_t lane) {
+  bitonic_merge<NPER, K, K / 2>(v, lane);
+  if constexpr (K < 64u * NPER) bitonic_from<NPER, 2 * K>(v, lane);
+}
+
 // Ascending bitonic sort of the 64 * NPER values held by a wave, element e
 // in lane e % 64 of register e / 64 (NPER = 1 or 2).  After the call the
 // same layout holds the sorted sequence.
 template <int NPER>
 __device__ __forceinline__ void wave_bitonic_sort(uint32_t (&v)[NPER]) {
   static_assert(NPER == 1 || NPER == 2, "64 or 128 values");
-  constexpr uint32_t N = 64u * NPER;
-  const uint32_t lane = (uint32_t)lane_id();
-#pragma unroll
-  for (uint32_t k = 2; k <= N; k <<= 1) {
-#pragma unroll
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      if (j >= 64u) {  // partner in the other register of the same lane
-        const uint32_t lo = min(v[0], v[NPER - 1]), hi = max(v[0], v[NPER - 1]);
-        // element e keeps the smaller value iff (e & k == 0) == (e & j == 0)
-        const bool up0 = (lane & k) == 0;  // element lane has bit j clear
-        v[0] = up0 ? lo : hi;
-        v[NPER - 1] = up0 ? hi : lo;
-      } else {
-#pragma unroll
-        for (int r = 0; r < NPER; ++r) {
-          const uint32_t e = lane + 64u * (uint32_t)r;
-          const uint32_t p = __shfl_xor(v[r], (int)j, kWave);
-          const bool keep_min = ((e & k) == 0) == ((e & j) == 0);
-          v[r] = keep_min ? min(v[r], p) : max(v[r], p);
-        }
-      }
-    }
-  }
+  bitonic_from<NPER, 2>(v, (uint32_t)lane_id());
 }
 
 // Ordering one row of a pair list (update u's subscription ids, all
