@@ -297,10 +297,81 @@ int ddm_sim_step(float *upd_lo, float *upd_hi, int64_t n, float *sub_lo, float *
                  int64_t m, int d, float side, float sigma, uint64_t seed, uint32_t step,
                  void *stream);
 
+/* ------------------------------------------------------------------------
+ * Resident simulations matched incrementally.
+ *
+ * The dynamic matching problem the paper names as its next step (Sec. 6;
+ * regions that move between matching requests, solved for serial SBM by
+ * the work cited in Sec. 2): a simulation whose regions move a little
+ * between two requests keeps its sorted state instead of sorting again.  Here the state is the bucket order of the
+ * bucketed path (the segments of Algorithm 5): the library keeps the
+ * regions themselves in device memory, grouped by bucket in fixed-capacity
+ * slabs, and a step moves them in place, moves the few that leave their
+ * bucket to their new one, rebuilds the boundary state of Algorithm 6 and
+ * sweeps every bucket (Algorithm 4).  Motion and result are exactly those of
+ * ddm_sim_step() followed by ddm_match(DDM_COUNT) on the same rows: the
+ * count is the number of intersecting pairs of half-open boxes.  When the
+ * slabs cannot hold a step's outcome, that step is counted by ddm_match()
+ * and the slabs are rebuilt; a simulation that keeps overflowing, or whose
+ * regions do not fit the slabs (d > 3, a bucket with more than 2048
+ * regions, more than 512 regions active at a bucket boundary), is matched
+ * by ddm_match() at every step from then on.
+ *
+ * ddm_resident_bytes() gives the device state size for n updates and m
+ * subscriptions in d dimensions (0 for invalid sizes).
+ *
+ * ddm_resident_create() copies the regions in (device rows as in
+ * ddm_match(); the caller's arrays are not referenced afterwards),
+ * validates them and builds the slabs in state (device, 256-byte aligned,
+ * owned by the caller, at least ddm_resident_bytes(); the library keeps a
+ * pointer to it until ddm_resident_destroy()).  side, sigma and seed define
+ * the motion as for ddm_sim_step() (side finite and >= 0, |sigma| <= 1e30).
+ * It synchronises with the stream.  Errors: DDM_E_INVAL for bad arguments,
+ * NaN or lo > hi; DDM_E_WORKSPACE if state_bytes is too small.  The handle
+ * holds a HIP event and 256 bytes of page-locked host memory of its own.
+ *
+ * ddm_resident_step() enqueues step number step (>= 1; the caller numbers
+ * steps as for ddm_sim_step()) and its count on the stream without blocking;
+ * ddm_resident_finish() waits for it and reports the count in *count (host).
+ * Every step must be finished before the next one is enqueued (DDM_E_INVAL
+ * otherwise).  finish() may run repair work on the stream of the step and
+ * synchronise with it.
+ *
+ * ddm_resident_export() writes the current corners in region order to
+ * device rows of the caller (as ddm_sim_step()'s arrays) and synchronises.
+ * ------------------------------------------------------------------------ */
+typedef struct ddm_resident ddm_resident;
+
+typedef struct ddm_resident_info {
+  int64_t steps;        /* steps finished                                    */
+  int64_t rebuilds;     /* slab rebuilds after a slab or the mover list filled */
+  int64_t full_matches; /* steps counted by ddm_match() instead of the slabs */
+  int64_t movers;       /* regions that changed bucket in the last step      */
+  int32_t buckets;      /* buckets of the slab layout (0 in full-match mode) */
+  int32_t full_mode;    /* 1: every step is matched by ddm_match()           */
+} ddm_resident_info;
+
+size_t ddm_resident_bytes(int64_t n, int64_t m, int d);
+int ddm_resident_create(void *state, size_t state_bytes, const float *upd_lo,
+                        const float *upd_hi, int64_t n, const float *sub_lo,
+                        const float *sub_hi, int64_t m, int d, float side, float sigma,
+                        uint64_t seed, void *stream, ddm_resident **out);
+int ddm_resident_step(ddm_resident *r, uint32_t step, void *stream);
+int ddm_resident_finish(ddm_resident *r, uint64_t *count);
+int ddm_resident_export(ddm_resident *r, float *upd_lo, float *upd_hi, float *sub_lo,
+                        float *sub_hi, void *stream);
+int ddm_resident_get_info(const ddm_resident *r, ddm_resident_info *out);
+int ddm_resident_destroy(ddm_resident *r);
+
 /* Scheduling policies of a server. */
 #define DDM_SERVE_BATCHED 0 /* continuous batching over several streams       */
 #define DDM_SERVE_PLAIN 1   /* one request at a time, in arrival order, with
                                ddm_match(): the per-request baseline          */
+#define DDM_SERVE_INCREMENTAL 2 /* continuous scheduling over several streams of
+                               resident simulations (ddm_resident_*): each
+                               simulation's state lives in the arena from its
+                               registration on; the caller's arrays keep the
+                               registered state until ddm_server_export()     */
 
 typedef struct ddm_serve_stats {
   double wall_s;           /* first arrival slot to last completion           */
@@ -343,6 +414,10 @@ int ddm_server_add_sim(ddm_server *s, float *upd_lo, float *upd_hi, int64_t n, f
  */
 int ddm_server_run(ddm_server *s, const int32_t *sim, const double *arrival_s, int64_t count,
                    uint64_t *counts, uint32_t *steps, double *latency_s, ddm_serve_stats *stats);
+/* Writes simulation sim_id's current state into the arrays it was
+ * registered with (DDM_SERVE_INCREMENTAL; a no-op for the other policies,
+ * whose steps update those arrays in place).  Synchronises. */
+int ddm_server_export(ddm_server *s, int32_t sim_id);
 int ddm_server_destroy(ddm_server *s);
 
 /* Human-readable text for a DDM_* return code (static storage). */

@@ -143,4 +143,36 @@ hipError_t bucket_sweep(const BucketArgs &a, int mode, int32_t *per_update,
                         uint32_t *out_s, unsigned long long *total, hipStream_t s,
                         const uint32_t *gate = nullptr);
 
+// Slab layout of one instance for a resident simulation (resident.hip):
+// bucket j's regions at slots [j * cap, j * cap + cnt[j]) of ids (region
+// index, updates first), lo and hi (float [slots][d], row-major); empty
+// regions in the extra slab nb.  Requires cap == kBucketCap.
+struct SlabBuild {
+  uint32_t *ids;
+  float *lo, *hi;
+  uint32_t *cnt;       // [nb + 1]
+  uint32_t cap;
+  uint32_t *overflow;  // set to nonzero if some slab could not hold its regions
+};
+
+// Enqueues sampling, the bucket map, validation and counting (as
+// bucket_prepare, into a.hdr), then the slab fill.  a describes a batch of
+// one with at least one bucket.
+hipError_t bucket_build_slabs(const BucketArgs &a, const SlabBuild &sb, hipStream_t s);
+
+// Count-mode sweep of slab-resident buckets.  rec / bs_rec hold the records
+// of bucket j at [j * cap, j * cap + cnt[j]) and its boundary-state records
+// at [j * bs_slab, j * bs_slab + bs_cnt[j]).  A record's region field is the
+// slot g of the region's coordinates in lo / hi (float [slots][d]) for an
+// update, nv + g for a subscription.  Pairs are added to hdr->total; a
+// bucket that does not fit sets hdr->pad[0].
+struct SlabSweep {
+  const uint32_t *rec, *bs_rec, *cnt, *bs_cnt;
+  uint32_t cap, bs_slab, nb, nv;
+  const float *lo, *hi;
+  Header *hdr;
+  int d;
+};
+hipError_t bucket_sweep_slabs(const SlabSweep &w, hipStream_t s);
+
 }  // namespace ddm

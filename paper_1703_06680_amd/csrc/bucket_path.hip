@@ -42,6 +42,7 @@
 
 #include <algorithm>
 
+#include "bucket_dev.h"
 #include "primitives.h"
 #include "profile.h"
 
@@ -59,15 +60,6 @@ constexpr uint32_t kMaxSampleBlocks = 256;
 constexpr int kCap = (int)kBucketCap;
 constexpr int kBigCap = (int)kBigBucketCap;
 
-struct BucketParams {
-  float vmin;        // bucket map of the swept axis' lower coordinate
-  float scale;
-  uint32_t nb;
-  uint32_t valid;
-  float qmin[2];     // 16-bit quantisation of the other axes (pre-filter)
-  float qscale[2];
-};
-
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Integer mixing function (xor-shift-multiply), used only to spread the
@@ -81,18 +73,6 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
   return x;
 }
 
-__device__ __forceinline__ uint32_t bucket_of(float x, float vmin, float scale, uint32_t nb) {
-  float t = (x - vmin) * scale;
-  t = fminf(fmaxf(t, 0.0f), (float)(nb - 1));
-  return (uint32_t)t;
-}
-
-template <int D>
-struct Box {
-  float lo[D];
-  float hi[D];
-};
-
 template <int D>
 __device__ __forceinline__ Box<D> load_row(const float *__restrict__ lo,
                                            const float *__restrict__ hi, uint32_t row) {
@@ -103,22 +83,6 @@ __device__ __forceinline__ Box<D> load_row(const float *__restrict__ lo,
     b.hi[k] = hi[(size_t)row * D + k];
   }
   return b;
-}
-
-// Error bits and emptiness of one box.  A half-open box with lo == hi on
-// some axis is empty; a closed one never is (lo == hi is a point).
-template <int D>
-__device__ __forceinline__ uint32_t box_errors(const Box<D> &b, bool &empty, uint32_t closed) {
-  uint32_t err = 0;
-  empty = false;
-#pragma unroll
-  for (int k = 0; k < D; ++k) {
-    const float l = b.lo[k], h = b.hi[k];
-    if (l != l || h != h) err |= kErrNaN;
-    if (l > h) err |= kErrOrder;
-    if (l == h && !closed) empty = true;
-  }
-  return err;
 }
 
 // The per-instance plan as the kernels see it: a device table for batches,
@@ -134,18 +98,6 @@ struct View {
   __device__ __forceinline__ uint32_t of_bucket(uint32_t x) const {
     return plan ? bucket_inst[x] : 0u;
   }
-};
-
-// Offsets produced by the one prefix sum over [bucket sizes | boundary-state
-// sizes | 0] (2 nb + 1 entries, buckets numbered over all instances): S[j] is
-// the first record slot of bucket j, S[nb] the number of records,
-// S[nb + j] - S[nb] the first boundary-state entry of bucket j (j <= nb).
-// Block k's first slot in bucket j is S[j] plus the block-major prefix
-// written by bk_colscan_kernel.
-struct Offsets {
-  const uint32_t *S;
-  uint32_t nb;  // buckets over all instances
-  __device__ uint32_t bs_begin(uint32_t j) const { return S[nb + j] - S[nb]; }
 };
 
 // ---------------------------------------------------------------- sample
@@ -464,50 +416,10 @@ __global__ __launch_bounds__(kColWaves * kWave) void bk_colscan_kernel(
 
 // ---------------------------------------------------------- scatter pass
 
-// Conservative quantisation of a coordinate of another axis onto 16 bits by
-// the monotone map t = clamp((x - qmin) * qscale, 0, 65535): lower bounds
-// round down, upper bounds round up, so two boxes that overlap on that axis
-// also overlap after quantisation.  Quantised bounds only serve the
-// sweep's pre-filter; survivors are tested on the exact coordinates.
-__device__ __forceinline__ uint32_t quant_lo(float x, float qmin, float qs) {
-  float t = (x - qmin) * qs;
-  t = fminf(fmaxf(t, 0.0f), 65535.0f);
-  return (uint32_t)t;
-}
-
-__device__ __forceinline__ uint32_t quant_hi(float x, float qmin, float qs) {
-  float t = (x - qmin) * qs;
-  t = fminf(fmaxf(t, 0.0f), 65535.0f);
-  return (uint32_t)ceilf(t);
-}
-
 // Record (16 bytes): word 0 = encoded lower key (swept axis), 1 = encoded
 // upper key, plus one for closed intervals (keys are integers, so x <= hi is
 // x < enc(hi) + 1, and enc(+inf) + 1 does not wrap), 2 = region index
-// (updates first), 3 = quantised bounds of the
-// other axes: for d = 2 the 16-bit lower | upper << 16 of axis 1; for d = 3
-// 7-bit bounds (the 16-bit ones scaled by 2^-9, lower rounded down, upper
-// rounded up and capped at 127) lo1 | hi1 << 8 | lo2 << 16 | hi2 << 24; 0
-// for d = 1.
-template <int D>
-__device__ __forceinline__ uint32_t qword_of(const Box<D> &b, const BucketParams &p) {
-  if (D == 2) {
-    return quant_lo(b.lo[1 % D], p.qmin[0], p.qscale[0]) |
-           (quant_hi(b.hi[1 % D], p.qmin[0], p.qscale[0]) << 16);
-  }
-  if (D == 3) {
-    uint32_t w = 0;
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const uint32_t l7 = quant_lo(b.lo[(1 + c) % D], p.qmin[c], p.qscale[c]) >> 9;
-      const uint32_t h7 = min(127u, (quant_hi(b.hi[(1 + c) % D], p.qmin[c], p.qscale[c]) + 511u) >> 9);
-      w |= (l7 | (h7 << 8)) << (16 * c);
-    }
-    return w;
-  }
-  return 0u;
-}
-
+// (updates first), 3 = quantised bounds of the other axes (qword_of).
 template <int D>
 __device__ __forceinline__ void write_record(uint32_t *__restrict__ dst, const Box<D> &b,
                                              uint32_t r, const BucketParams &p, uint32_t closed) {
@@ -550,6 +462,64 @@ __global__ __launch_bounds__(kThreads) void bk_scatter_kernel(
         const uint32_t jg = I.b0 + j;
         const uint32_t pos = O.bs_begin(jg) + atomicAdd(&bs_cur[jg], 1u);
         if (pos < bs_cap) write_record<D>(bs_rec + (size_t)pos * RW, bx[r], q.r0 + r, p, I.closed);
+      }
+    }
+  }
+}
+
+// Slab layout of a single instance (a resident simulation): every region
+// goes, by its swept-axis lower coordinate, into its bucket's slab of cap
+// slots, at the block's prefix within that bucket (from bk_colscan_kernel)
+// plus an LDS cursor, as (region index, lower corner, upper corner); empty
+// regions go to the extra slab nb.  Slots past cap are not written and set
+// *overflow (the bucket's total is then above cap).
+template <int D>
+__global__ __launch_bounds__(kThreads) void bk_slab_scatter_kernel(
+    View V, const BucketParams *__restrict__ P, const uint32_t *__restrict__ SB,
+    const uint32_t *__restrict__ T, uint32_t *__restrict__ ids, float *__restrict__ lo,
+    float *__restrict__ hi, uint32_t *__restrict__ cnt, uint32_t cap,
+    uint32_t *__restrict__ overflow) {
+  extern __shared__ uint32_t cur[];
+  const InstPlan I = V.get(0);
+  const BucketParams p = P[0];
+  const uint32_t nb = I.nb, lb = blockIdx.x;
+  const uint32_t *row = SB + (size_t)lb * nb;
+  for (uint32_t b = threadIdx.x; b < nb; b += kThreads) {
+    cur[b] = row[b];
+    if (lb == 0) {
+      cnt[b] = min(T[b], cap);
+      if (T[b] > cap) atomicOr(overflow, 1u);
+    }
+  }
+  __syncthreads();
+  const uint32_t g0 = lb * I.gpb, g1 = min(I.g, g0 + I.gpb);
+  for (uint32_t g = g0 + threadIdx.x; g < g1; g += kThreads) {
+    const Group q = group_of(g, I, I.n);
+    Box<D> bx[4];
+    load_group<D>(q, I.vec != 0, bx);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if ((uint32_t)r >= q.rows) continue;
+      bool empty;
+      (void)box_errors<D>(bx[r], empty, 0u);
+      uint32_t b, local;
+      if (empty) {
+        b = nb;
+        local = atomicAdd(&cnt[nb], 1u);
+      } else {
+        b = bucket_of(bx[r].lo[0], p.vmin, p.scale, nb);
+        local = atomicAdd(&cur[b], 1u);
+      }
+      if (local >= cap) {
+        atomicOr(overflow, 1u);
+        continue;
+      }
+      const size_t at = (size_t)b * cap + local;
+      ids[at] = q.r0 + r;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        lo[at * D + k] = bx[r].lo[k];
+        hi[at * D + k] = bx[r].hi[k];
       }
     }
   }
@@ -1010,7 +980,7 @@ __device__ __forceinline__ void emit_rows(
   }
 }
 
-template <int DM1, int MODE, int CAP, int THREADS, int FINE>
+template <int DM1, int MODE, int CAP, int THREADS, int FINE, bool SLAB = false>
 __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
     const uint32_t *__restrict__ rec, Offsets O, View V, const uint32_t *__restrict__ bs_rec,
     uint32_t bs_cap, uint32_t n, Header *__restrict__ hdr, int32_t *__restrict__ per_update,
@@ -1054,15 +1024,25 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   const uint32_t b = blockIdx.x;
   const uint32_t inst = V.of_bucket(b);
   const InstPlan I = V.get(inst);
-  const uint32_t nbs_total = O.bs_begin(O.nb);
-  const uint32_t start = O.S[b];
-  const uint32_t C = O.S[b + 1] - start;
-  if (nbs_total > bs_cap || C > (uint32_t)CAP) {  // uniform: the host falls back
+  uint32_t start, C, bs_begin, nbs;
+  bool fits;
+  if (SLAB) {
+    start = b * O.cap;
+    C = O.cnt[b];
+    bs_begin = b * O.bs_slab;
+    nbs = O.bs_cnt[b];
+    fits = C <= (uint32_t)CAP && nbs <= O.bs_slab;
+  } else {
+    start = O.S[b];
+    C = O.S[b + 1] - start;
+    bs_begin = O.bs_begin(b);
+    nbs = O.bs_begin(b + 1) - bs_begin;
+    fits = O.bs_begin(O.nb) <= bs_cap && C <= (uint32_t)CAP;
+  }
+  if (!fits) {  // uniform: the host falls back
     if (threadIdx.x == 0) atomicOr(&hdr->pad[0], 1u);
     return;
   }
-  const uint32_t bs_begin = O.bs_begin(b);
-  const uint32_t nbs = O.bs_begin(b + 1) - bs_begin;
   const int t = threadIdx.x;
   const SweepCtx o{I, n, per_update, pair_off, cursor, out_u, out_s, queue, &queued, DL, own_cnt};
 
@@ -1330,6 +1310,43 @@ void sweep_impl(const BucketArgs &a, int32_t *per_update, const unsigned long lo
         out_u, out_s, total, a.inst_total, gate, a.own, a.rows);
 }
 
+template <int D>
+void build_slabs_impl(const BucketArgs &a, const SlabBuild &sb, hipStream_t s) {
+  const BucketLayout &L = *a.L;
+  Ptrs p = pointers(a);
+  const size_t lds = (size_t)L.max_nb * sizeof(uint32_t);
+  const Clear clr{a.hdr, p.T + L.nb, p.bs_cur, L.nb, nullptr, L.B};
+  bk_sample_kernel<D><<<L.nsmp, kSampleThreads, 0, s>>>(p.V, p.part, clr);
+  bk_plan_kernel<<<L.B, kSampleThreads, 0, s>>>(p.part, p.V, p.P);
+  bk_count_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.C, p.T + L.nb, a.hdr,
+                                                   nullptr, 0u);
+  bk_colscan_kernel<<<(L.nb + kWave - 1) / kWave, kColWaves * kWave, 0, s>>>(p.C, p.SB, p.T, p.V,
+                                                                         L.nb);
+  (void)fill_u32(sb.cnt + L.nb, 0u, 1, s);
+  bk_slab_scatter_kernel<D><<<L.nblk, kThreads, lds, s>>>(p.V, p.P, p.SB, p.T, sb.ids, sb.lo,
+                                                          sb.hi, sb.cnt, sb.cap, sb.overflow);
+}
+
+template <int DM1>
+void sweep_slabs_impl(const SlabSweep &w, hipStream_t s) {
+  View V{};
+  V.plan = nullptr;
+  V.one = InstPlan{};
+  V.one.ulo = V.one.slo = w.lo;
+  V.one.uhi = V.one.shi = w.hi;
+  V.one.nb = w.nb;
+  Offsets O{};
+  O.S = nullptr;
+  O.nb = w.nb;
+  O.cnt = w.cnt;
+  O.bs_cnt = w.bs_cnt;
+  O.cap = w.cap;
+  O.bs_slab = w.bs_slab;
+  bk_sweep_kernel<DM1, 0, kCap, 512, 512, true><<<w.nb, 512, 0, s>>>(
+      w.rec, O, V, w.bs_rec, 0u, w.nv, w.hdr, nullptr, nullptr, nullptr, nullptr, nullptr,
+      &w.hdr->total, nullptr, nullptr, nullptr, RowEmit{});
+}
+
 // Host-side plan of one instance; returns false if it does not fit.
 bool plan_instance(const InstSpec &sp, int64_t u0, int64_t s0, const BucketTuning &t,
                    InstPlan &I) {
@@ -1475,6 +1492,30 @@ hipError_t bucket_prepare(const BucketArgs &a, hipStream_t s) {
     case 1: prepare_impl<1>(a, s); break;
     case 2: prepare_impl<2>(a, s); break;
     default: prepare_impl<3>(a, s); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t bucket_build_slabs(const BucketArgs &a, const SlabBuild &sb, hipStream_t s) {
+  if (a.L->B != 1 || a.L->nb == 0 || sb.cap != kBucketCap) return hipErrorInvalidValue;
+  switch (a.d) {
+    case 1: build_slabs_impl<1>(a, sb, s); break;
+    case 2: build_slabs_impl<2>(a, sb, s); break;
+    case 3: build_slabs_impl<3>(a, sb, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t bucket_sweep_slabs(const SlabSweep &w, hipStream_t s) {
+  if (w.nb == 0) return hipSuccess;
+  if (w.cap != kBucketCap) return hipErrorInvalidValue;
+  prof::mark(s, "resident.sweep");
+  switch (w.d) {
+    case 1: sweep_slabs_impl<0>(w, s); break;
+    case 2: sweep_slabs_impl<1>(w, s); break;
+    case 3: sweep_slabs_impl<2>(w, s); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

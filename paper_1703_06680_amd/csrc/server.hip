@@ -20,7 +20,11 @@
 //     returned to the arena and their simulations become free.
 // Groups in different slots run on different streams and overlap on the
 // device.  The plain policy is the per-request baseline: one request at a
-// time in arrival order, each a step followed by ddm_match().
+// time in arrival order, each a step followed by ddm_match().  The incremental
+// policy schedules like the batched one, but each simulation keeps a
+// resident state (ddm_resident_*, carved from the front of the arena when it
+// is registered) and a request is that state's step: no workspace is
+// admitted per request.
 #include <string.h>
 
 #include <algorithm>
@@ -49,6 +53,7 @@ struct Sim {
   WalkArgs w;
   uint32_t steps = 0;  // steps enqueued so far
   bool busy = false;
+  ddm_resident *res = nullptr;  // incremental policy: the resident state
 };
 
 // First-fit allocator of 256-byte aligned blocks over [0, size).
@@ -121,6 +126,7 @@ struct ddm_server {
   int policy = DDM_SERVE_BATCHED;
   int max_batch = 1;
   int d = 0;
+  size_t resident_top = 0;  // incremental policy: arena bytes held by resident states
   std::vector<Sim> sims;
   std::vector<Slot> slots;
   Arena alloc;
@@ -186,7 +192,9 @@ extern "C" int ddm_server_create(void *arena, size_t arena_bytes, int policy, in
   *out = nullptr;
   if (!arena || (reinterpret_cast<uintptr_t>(arena) & 255) || arena_bytes < 256)
     return DDM_E_INVAL;
-  if (policy != DDM_SERVE_BATCHED && policy != DDM_SERVE_PLAIN) return DDM_E_INVAL;
+  if (policy != DDM_SERVE_BATCHED && policy != DDM_SERVE_PLAIN &&
+      policy != DDM_SERVE_INCREMENTAL)
+    return DDM_E_INVAL;
   if (slots < 1 || slots > 16 || max_batch < 1 || max_batch > 4096) return DDM_E_INVAL;
   ddm_server *sv = new (std::nothrow) ddm_server();
   if (!sv) return DDM_E_DEVICE;
@@ -223,6 +231,22 @@ extern "C" int ddm_server_add_sim(ddm_server *sv, float *upd_lo, float *upd_hi, 
   if ((n > 0 && (!upd_lo || !upd_hi)) || (m > 0 && (!sub_lo || !sub_hi))) return DDM_E_INVAL;
   if ((n + m) * (int64_t)d >= (int64_t(1) << 32)) return DDM_E_INVAL;
   if (sv->d && d != sv->d) return DDM_E_INVAL;  // one batch holds one d
+  if (sv->policy == DDM_SERVE_INCREMENTAL) {
+    const size_t bytes = ddm_resident_bytes(n, m, d);
+    if (bytes == 0) return DDM_E_INVAL;
+    if (sv->resident_top + align256(bytes) > sv->arena_bytes) return DDM_E_WORKSPACE;
+    Sim s;
+    s.w = WalkArgs{upd_lo, upd_hi, n, sub_lo, sub_hi, m, d, side, sigma, seed, 0};
+    const int e = ddm_resident_create(sv->arena + sv->resident_top, bytes, upd_lo, upd_hi, n,
+                                      sub_lo, sub_hi, m, d, side, sigma, seed,
+                                      sv->slots[0].stream, &s.res);
+    if (e != DDM_OK) return e;
+    sv->resident_top += align256(bytes);
+    sv->d = d;
+    sv->sims.push_back(s);
+    *sim_id = (int32_t)sv->sims.size() - 1;
+    return DDM_OK;
+  }
   // the budget must hold any single request alone
   size_t need = ddm_workspace_bytes(n, m, d, DDM_COUNT, 0);
   if (sv->policy == DDM_SERVE_BATCHED) {
@@ -291,6 +315,79 @@ extern "C" int ddm_server_run(ddm_server *sv, const int32_t *sim, const double *
       ++completed;
       ++batches;
       ++batched_requests;
+    }
+  } else if (sv->policy == DDM_SERVE_INCREMENTAL) {
+    while (completed < count) {
+      bool progress = false;
+      for (Slot &s : sv->slots) {
+        if (!s.busy || hipEventQuery(s.done) != hipSuccess) continue;
+        const double now = seconds_since(t0, Clock::now());
+        for (int64_t r : s.reqs) {
+          Sim &sm = sv->sims[(size_t)sim[r]];
+          uint64_t K = 0;
+          const int e = ddm_resident_finish(sm.res, &K);
+          if (e != DDM_OK) fail(e);
+          counts[r] = K;
+          latency_s[r] = now - arrival_s[r];
+          sm.busy = false;
+        }
+        completed += (int64_t)s.reqs.size();
+        s.busy = false;
+        s.reqs.clear();
+        progress = true;
+      }
+      std::unique_lock<std::mutex> g(dv.mu);
+      for (Slot &s : sv->slots) {
+        if (s.busy || dv.pending.empty()) continue;
+        std::vector<int64_t> group;
+        for (size_t p = 0; p < dv.pending.size() && (int)group.size() < sv->max_batch;) {
+          const int64_t r = dv.pending[p];
+          Sim &sm = sv->sims[(size_t)sim[r]];
+          if (sm.busy) {
+            ++p;
+            continue;
+          }
+          sm.busy = true;  // also keeps a second request of it out of this group
+          group.push_back(r);
+          dv.pending.erase(dv.pending.begin() + (std::ptrdiff_t)p);
+        }
+        if (group.empty()) break;
+        s.reqs.clear();
+        for (int64_t r : group) {
+          Sim &sm = sv->sims[(size_t)sim[r]];
+          sm.w.step = ++sm.steps;
+          steps[r] = sm.w.step;
+          const int e = ddm_resident_step(sm.res, sm.w.step, s.stream);
+          if (e != DDM_OK) {
+            fail(e);
+            counts[r] = 0;
+            latency_s[r] = seconds_since(t0, Clock::now()) - arrival_s[r];
+            sm.busy = false;
+            ++completed;
+            continue;
+          }
+          s.reqs.push_back(r);
+        }
+        if (s.reqs.empty()) continue;
+        if (hipEventRecord(s.done, s.stream) != hipSuccess) {
+          fail(DDM_E_DEVICE);
+          (void)hipStreamSynchronize(s.stream);
+        }
+        s.busy = true;
+        ++batches;
+        batched_requests += (int64_t)s.reqs.size();
+        progress = true;
+      }
+      if (progress) continue;
+      bool inflight = false;
+      for (const Slot &s : sv->slots) inflight = inflight || s.busy;
+      if (inflight) {
+        g.unlock();
+        std::this_thread::yield();
+      } else if (completed < count) {
+        const int64_t seen = dv.released;
+        dv.cv.wait(g, [&] { return dv.released > seen || !dv.pending.empty(); });
+      }
     }
   } else {
     while (completed < count) {
@@ -413,15 +510,32 @@ extern "C" int ddm_server_run(ddm_server *sv, const int32_t *sim, const double *
     stats->wall_s = seconds_since(t0, Clock::now());
     stats->launches = batches;
     stats->mean_batch = batches ? (double)batched_requests / (double)batches : 0.0;
-    stats->peak_arena_bytes = (double)sv->alloc.peak();
+    stats->peak_arena_bytes = sv->policy == DDM_SERVE_INCREMENTAL ? (double)sv->resident_top
+                                                                  : (double)sv->alloc.peak();
   }
   return rc;
+}
+
+extern "C" int ddm_server_export(ddm_server *sv, int32_t sim_id) {
+  if (!sv || sim_id < 0 || (size_t)sim_id >= sv->sims.size()) return DDM_E_INVAL;
+  for (const Slot &s : sv->slots)
+    if (s.busy) return DDM_E_INVAL;
+  const Sim &sm = sv->sims[(size_t)sim_id];
+  if (!sm.res) return DDM_OK;
+  return ddm_resident_export(sm.res, sm.w.upd_lo, sm.w.upd_hi, sm.w.sub_lo, sm.w.sub_hi,
+                             sv->slots[0].stream);
 }
 
 extern "C" int ddm_server_destroy(ddm_server *sv) {
   if (!sv) return DDM_OK;
   for (Slot &s : sv->slots) {
     if (s.stream) (void)hipStreamSynchronize(s.stream);
+  }
+  for (Sim &sm : sv->sims) {
+    if (sm.res) (void)ddm_resident_destroy(sm.res);
+    sm.res = nullptr;
+  }
+  for (Slot &s : sv->slots) {
     free_slot(s);
   }
   delete sv;

@@ -14,42 +14,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "philox.h"
 #include "sim.h"
 
 namespace ddm {
 namespace {
-
-__device__ __forceinline__ uint4 philox_round(uint4 x, uint32_t k0, uint32_t k1) {
-  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
-  const uint32_t hi0 = __umulhi(M0, x.x), lo0 = M0 * x.x;
-  const uint32_t hi1 = __umulhi(M1, x.z), lo1 = M1 * x.z;
-  return make_uint4(hi1 ^ x.y ^ k0, lo1, hi0 ^ x.w ^ k1, lo0);
-}
-
-__device__ __forceinline__ uint4 philox4x32_10(uint4 ctr, uint32_t k0, uint32_t k1) {
-  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    ctr = philox_round(ctr, k0, k1);
-    k0 += W0;
-    k1 += W1;
-  }
-  return ctr;
-}
-
-// z for (region, axis, step): twelve 24-bit uniforms from three Philox draws.
-__device__ __forceinline__ float irwin_hall12(uint32_t region, uint32_t axis, uint32_t step,
-                                              uint32_t k0, uint32_t k1) {
-  uint32_t sum = 0;
-#pragma unroll
-  for (uint32_t j = 0; j < 3; ++j) {
-    const uint4 w = philox4x32_10(make_uint4(region, axis, step, j), k0, k1);
-    sum += (w.x >> 8) + (w.y >> 8) + (w.z >> 8) + (w.w >> 8);
-  }
-  // sum < 12 * 2^24 < 2^28: exact in uint32; one rounding to float32
-  const float s = __uint2float_rn(sum);
-  return s * 5.9604644775390625e-08f - 6.0f;  // 2^-24
-}
 
 __global__ void walk_kernel(float *__restrict__ lo, float *__restrict__ hi, uint32_t rows, int d,
                             uint32_t region0, float side, float sigma, uint32_t step, uint32_t k0,

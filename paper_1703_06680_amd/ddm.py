@@ -534,7 +534,7 @@ class BatchGraph:
 
 # --------------------------------------------------------------- serving
 
-SERVE_POLICIES = {"batched": 0, "plain": 1}
+SERVE_POLICIES = {"batched": 0, "plain": 1, "incremental": 2}
 
 
 class ServeStats(ctypes.Structure):
@@ -544,6 +544,15 @@ class ServeStats(ctypes.Structure):
     def as_dict(self) -> dict:
         return {f: (int(getattr(self, f)) if f == "launches" else float(getattr(self, f)))
                 for f, _ in self._fields_}
+
+
+class ResidentInfo(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("rebuilds", ctypes.c_int64),
+                ("full_matches", ctypes.c_int64), ("movers", ctypes.c_int64),
+                ("buckets", ctypes.c_int32), ("full_mode", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 def _serve_prototypes(lib):
@@ -563,6 +572,24 @@ def _serve_prototypes(lib):
     lib.ddm_server_run.restype = ctypes.c_int
     lib.ddm_server_destroy.argtypes = [vp]
     lib.ddm_server_destroy.restype = ctypes.c_int
+    lib.ddm_server_export.argtypes = [vp, ctypes.c_int32]
+    lib.ddm_server_export.restype = ctypes.c_int
+    lib.ddm_resident_bytes.argtypes = [i64, i64, ctypes.c_int]
+    lib.ddm_resident_bytes.restype = ctypes.c_size_t
+    lib.ddm_resident_create.argtypes = [vp, ctypes.c_size_t, vp, vp, i64, vp, vp, i64,
+                                        ctypes.c_int, f32, f32, ctypes.c_uint64, vp,
+                                        ctypes.POINTER(vp)]
+    lib.ddm_resident_create.restype = ctypes.c_int
+    lib.ddm_resident_step.argtypes = [vp, ctypes.c_uint32, vp]
+    lib.ddm_resident_step.restype = ctypes.c_int
+    lib.ddm_resident_finish.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
+    lib.ddm_resident_finish.restype = ctypes.c_int
+    lib.ddm_resident_export.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.ddm_resident_export.restype = ctypes.c_int
+    lib.ddm_resident_get_info.argtypes = [vp, ctypes.POINTER(ResidentInfo)]
+    lib.ddm_resident_get_info.restype = ctypes.c_int
+    lib.ddm_resident_destroy.argtypes = [vp]
+    lib.ddm_resident_destroy.restype = ctypes.c_int
     lib._serve_ready = True
     return lib
 
@@ -636,9 +663,99 @@ class Server:
             raise DDMError(rc, "ddm_server_run")
         return counts[:R], steps[:R], lat[:R], st.as_dict()
 
+    def export(self, sim_id: int) -> None:
+        """Brings the arrays simulation ``sim_id`` was registered with up to
+        date (incremental policy; a no-op for the others)."""
+        with torch.cuda.device(self.dev):
+            rc = self.lib.ddm_server_export(self.handle, int(sim_id))
+        if rc != DDM_OK:
+            raise DDMError(rc, "ddm_server_export")
+
     def close(self) -> None:
         if self.handle and self.handle.value:
             self.lib.ddm_server_destroy(self.handle)
+            self.handle = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def resident_bytes(n: int, m: int, d: int) -> int:
+    return int(_serve_prototypes(library()).ddm_resident_bytes(n, m, d))
+
+
+class Resident:
+    """A simulation matched incrementally (``ddm_resident_*``): its regions
+    live in a device state in bucket order; ``step(k)`` moves them by step
+    k of the random walk (as ``sim_step``) and returns the count of
+    intersecting pairs (as ``match(..., "count")`` on the moved rows)."""
+
+    def __init__(self, upd_lo, upd_hi, sub_lo, sub_hi, side: float, sigma: float, seed: int,
+                 stream=None):
+        self.lib = _serve_prototypes(library())
+        _check_boxes(upd_lo, upd_hi, "updates")
+        _check_boxes(sub_lo, sub_hi, "subscriptions")
+        self.dev = upd_lo.device
+        self.n, self.d = upd_lo.shape
+        self.m = sub_lo.shape[0]
+        size = self.lib.ddm_resident_bytes(self.n, self.m, self.d)
+        if size == 0:
+            raise DDMError(DDM_E_INVAL, "ddm_resident_bytes")
+        self.state = torch.empty(int(size), dtype=torch.uint8, device=self.dev)
+        self.handle = ctypes.c_void_p(None)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.dev)
+        rc = self.lib.ddm_resident_create(ctypes.c_void_p(self.state.data_ptr()), size,
+                                          _ptr(upd_lo), _ptr(upd_hi), self.n, _ptr(sub_lo),
+                                          _ptr(sub_hi), self.m, self.d, float(side), float(sigma),
+                                          int(seed), ctypes.c_void_p(stream.cuda_stream),
+                                          ctypes.byref(self.handle))
+        if rc != DDM_OK:
+            raise DDMError(rc, "ddm_resident_create")
+
+    def step_async(self, step: int, stream=None) -> None:
+        if stream is None:
+            stream = torch.cuda.current_stream(self.dev)
+        rc = self.lib.ddm_resident_step(self.handle, int(step), ctypes.c_void_p(stream.cuda_stream))
+        if rc != DDM_OK:
+            raise DDMError(rc, "ddm_resident_step")
+
+    def finish(self) -> int:
+        k = ctypes.c_uint64(0)
+        rc = self.lib.ddm_resident_finish(self.handle, ctypes.byref(k))
+        if rc != DDM_OK:
+            raise DDMError(rc, "ddm_resident_finish")
+        return int(k.value)
+
+    def step(self, step: int, stream=None) -> int:
+        self.step_async(step, stream)
+        return self.finish()
+
+    def export(self, stream=None):
+        """Current (upd_lo, upd_hi, sub_lo, sub_hi) in region order."""
+        out = [torch.empty((r, self.d), dtype=torch.float32, device=self.dev)
+               for r in (self.n, self.n, self.m, self.m)]
+        if stream is None:
+            stream = torch.cuda.current_stream(self.dev)
+        rc = self.lib.ddm_resident_export(self.handle, *[_ptr(t) for t in out],
+                                          ctypes.c_void_p(stream.cuda_stream))
+        if rc != DDM_OK:
+            raise DDMError(rc, "ddm_resident_export")
+        return out
+
+    def info(self) -> dict:
+        st = ResidentInfo()
+        rc = self.lib.ddm_resident_get_info(self.handle, ctypes.byref(st))
+        if rc != DDM_OK:
+            raise DDMError(rc, "ddm_resident_get_info")
+        return st.as_dict()
+
+    def close(self) -> None:
+        if self.handle and self.handle.value:
+            self.lib.ddm_resident_destroy(self.handle)
             self.handle = ctypes.c_void_p(None)
 
     def __del__(self):

@@ -85,3 +85,63 @@ def test_host_side_argument_errors_return_before_any_launch(lib):
     need = lib.ddm_workspace_bytes(5, 5, 2, 0, 0)
     assert lib.ddm_match(fake, fake, 5, fake, fake, 5, 2, 0, fake, need - 1, None, ctypes.byref(cnt), None, None, 0) == -3
     assert lib.ddm_match(fake, fake, 5, fake, fake, 5, 2, 0, None, need, None, ctypes.byref(cnt), None, None, 0) == -3
+
+
+def test_resident_sizes_and_argument_errors(lib):
+    """Resident-simulation entry points: state sizes and the checks that
+    return before any device call."""
+    vp, i64, f32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_float
+    lib.ddm_resident_bytes.argtypes = [i64, i64, ctypes.c_int]
+    lib.ddm_resident_bytes.restype = ctypes.c_size_t
+    small = lib.ddm_resident_bytes(1000, 1000, 2)
+    assert small > 0 and small % 256 == 0
+    assert lib.ddm_resident_bytes(100000, 100000, 2) > small
+    # one slab per bucket of about 1536 regions: at least a slab of 2048
+    # records (16 bytes) and coordinates per region slot
+    assert lib.ddm_resident_bytes(100000, 100000, 2) >= (200000 // 1536) * 2048 * (16 + 4 + 16)
+    assert lib.ddm_resident_bytes(10, 10, 7) > 0      # d > 3: matched by the full call
+    assert lib.ddm_resident_bytes(0, 0, 2) > 0        # nothing to match, still a state
+    assert lib.ddm_resident_bytes(-1, 10, 2) == 0
+    assert lib.ddm_resident_bytes(10, 10, 0) == 0
+    assert lib.ddm_resident_bytes(10, 10, 17) == 0
+    assert lib.ddm_resident_bytes(2**30, 2**30, 1) == 0
+    lib.ddm_resident_create.argtypes = [vp, ctypes.c_size_t, vp, vp, i64, vp, vp, i64,
+                                        ctypes.c_int, f32, f32, ctypes.c_uint64, vp,
+                                        ctypes.POINTER(vp)]
+    lib.ddm_resident_create.restype = ctypes.c_int
+    fake, state = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x100000)
+    out = ctypes.c_void_p(None)
+    need = lib.ddm_resident_bytes(5, 5, 2)
+
+    def create(**kw):
+        a = dict(state=state, size=need, n=5, m=5, d=2, side=1.0, sigma=0.1, out=ctypes.byref(out))
+        a.update(kw)
+        return lib.ddm_resident_create(a["state"], a["size"], fake, fake, a["n"], fake, fake,
+                                       a["m"], a["d"], a["side"], a["sigma"], 1, None, a["out"])
+
+    assert create(out=None) == -1
+    assert create(n=-1) == -1
+    assert create(d=0) == -1
+    assert create(side=float("nan")) == -1
+    assert create(side=-1.0) == -1
+    assert create(side=float("inf")) == -1
+    assert create(sigma=float("nan")) == -1
+    assert create(sigma=1e31) == -1
+    assert create(state=ctypes.c_void_p(0x100010)) == -1  # not 256-byte aligned
+    assert create(state=None) == -1
+    assert create(size=need - 1) == -3
+    assert out.value is None
+    for name in ("ddm_resident_step", "ddm_resident_finish", "ddm_resident_export",
+                 "ddm_resident_get_info"):
+        getattr(lib, name).restype = ctypes.c_int
+    lib.ddm_resident_step.argtypes = [vp, ctypes.c_uint32, vp]
+    assert lib.ddm_resident_step(None, 1, None) == -1
+    lib.ddm_resident_finish.argtypes = [vp, vp]
+    assert lib.ddm_resident_finish(None, None) == -1
+    lib.ddm_resident_export.argtypes = [vp, vp, vp, vp, vp, vp]
+    assert lib.ddm_resident_export(None, fake, fake, fake, fake, None) == -1
+    lib.ddm_resident_get_info.argtypes = [vp, vp]
+    assert lib.ddm_resident_get_info(None, None) == -1
+    lib.ddm_resident_destroy.argtypes = [vp]
+    lib.ddm_resident_destroy.restype = ctypes.c_int
+    assert lib.ddm_resident_destroy(None) == 0

@@ -68,7 +68,7 @@ def _server(ddm, sims, policy="batched", arena=1 << 30, slots=4, max_batch=8):
     return sv, states
 
 
-@pytest.mark.parametrize("policy", ["batched", "plain"])
+@pytest.mark.parametrize("policy", ["batched", "plain", "incremental"])
 def test_served_counts_alone_equal_mix_equal_oracle(ddm, oracle, policy):
     sims = _small_sims(6)
     per_sim = 4
@@ -89,7 +89,10 @@ def test_served_counts_alone_equal_mix_equal_oracle(ddm, oracle, policy):
         mine = steps[ids == j]
         assert sorted(mine.tolist()) == list(range(1, per_sim + 1))
         assert np.all(np.diff(steps[np.argsort(arr)][ids[np.argsort(arr)] == j].astype(int)) > 0)
-    # final device state equals the reference after per_sim steps
+    # final device state equals the reference after per_sim steps (the
+    # incremental policy writes it back on request)
+    for j in range(6):
+        sv.export(j)
     for (inst, side, sigma, seed), g in zip(sims, states):
         *_, (st, ul, uh, sl, sh) = list(walk.walk(inst.upd_lo, inst.sub_lo, side, sigma, seed,
                                                   per_sim))
