@@ -220,16 +220,21 @@ def bench_served(args, ddm, W, torch, np):
     """32 resident d=2 simulations (n = m log-uniform on [1e4, 2e6], alpha = 1,
     random-walk sigma = 0.1 * side); open-loop Poisson traces at fractions of
     the plain matcher's saturation rate, served by the plain per-request
-    policy and by continuous batching."""
+    policy, by continuous batching and by incremental matching of resident
+    states."""
     dev = torch.device("cuda:0")
     sims = W.serving_sims(32, d=2, seed=0)
     init = [[torch.from_numpy(a).to(dev) for a in (t.upd_lo, t.upd_hi, t.sub_lo, t.sub_hi)]
             for t, _, _, _ in sims]
     sizes = np.array([t.n + t.m for t, _, _, _ in sims], dtype=np.int64)
     budget = int(args.serve_budget_gib * (1 << 30))
+    # the incremental policy holds every simulation's resident state
+    resident = sum((ddm.resident_bytes(t.n, t.m, 2) + 255) // 256 * 256 for t, _, _, _ in sims)
+    budgets = {"plain": budget, "batched": budget, "incremental": max(budget, resident)}
+    policies = ("plain", "batched", "incremental")
 
     def serve(policy, ids, arr):
-        sv = ddm.Server(budget, policy=policy, slots=args.serve_slots,
+        sv = ddm.Server(budgets[policy], policy=policy, slots=args.serve_slots,
                         max_batch=args.serve_max_batch)
         for (t, side, sigma, seed), g0 in zip(sims, init):
             sv.add_sim(*[x.clone() for x in g0], side, sigma, seed)
@@ -245,12 +250,15 @@ def bench_served(args, ddm, W, torch, np):
     sat_qps = R / st["wall_s"]
     _, _, _, stb = serve("batched", ids_sat, np.zeros(R))
     sat_batched = R / stb["wall_s"]
+    serve("incremental", ids_sat[:64], np.zeros(64))  # warm-up
+    _, _, _, sti = serve("incremental", ids_sat, np.zeros(R))
+    sat_incremental = R / sti["wall_s"]
     levels = {}
     for frac in (0.5, 0.8, 1.0, 1.2):
         ids, arr = W.poisson_arrivals(R, frac * sat_qps, seed=int(frac * 10), sims=32)
         row = {"qps": round(frac * sat_qps, 1)}
         results = {}
-        for policy in ("plain", "batched"):
+        for policy in policies:
             counts, steps, lat, stt = serve(policy, ids, arr)
             results[policy] = (counts, steps)
             row[policy] = {
@@ -260,8 +268,8 @@ def bench_served(args, ddm, W, torch, np):
                 "mean_batch": round(stt["mean_batch"], 2),
                 "peak_arena_gib": round(stt["peak_arena_bytes"] / (1 << 30), 3),
             }
-        row["exact"] = bool(np.array_equal(results["plain"][0], results["batched"][0]) and
-                            np.array_equal(results["plain"][1], results["batched"][1]))
+        row["exact"] = bool(all(np.array_equal(results["plain"][k], results[p][k])
+                                for p in policies[1:] for k in (0, 1)))
         levels[f"{frac:g}x"] = row
     return {
         "workload": "32 resident d=2 simulations, n=m log-uniform on [1e4, 2e6] "
@@ -269,10 +277,87 @@ def bench_served(args, ddm, W, torch, np):
                     f"{R} Poisson requests per level, count mode",
         "plain_saturation_qps": round(sat_qps, 1),
         "batched_saturation_qps": round(sat_batched, 1),
-        "saturation_regions_per_s": {"plain": round(float(sizes[ids_sat].sum()) / st["wall_s"], 1),
-                                     "batched": round(float(sizes[ids_sat].sum()) / stb["wall_s"], 1)},
+        "incremental_saturation_qps": round(sat_incremental, 1),
+        "saturation_regions_per_s": {
+            "plain": round(float(sizes[ids_sat].sum()) / st["wall_s"], 1),
+            "batched": round(float(sizes[ids_sat].sum()) / stb["wall_s"], 1),
+            "incremental": round(float(sizes[ids_sat].sum()) / sti["wall_s"], 1)},
         "budget_gib": args.serve_budget_gib,
+        "incremental_state_gib": round(resident / (1 << 30), 3),
         "slots": args.serve_slots, "max_batch": args.serve_max_batch, "levels": levels,
+    }
+
+
+def bench_resident(args, ddm, W, torch, np):
+    """One resident simulation of the serving workload's kind at the headline
+    scale (d = 2, n = m = 5e6, alpha = 1, random walk sigma = 0.1 side):
+    closed-loop steps matched incrementally (ddm_resident_*) against the same
+    steps taken by ddm_sim_step followed by the full ddm_match count, with
+    equal counts at every step."""
+    dev = torch.device("cuda:0")
+    n = args.resident_n
+    d, alpha = 2, 1.0
+    inst = W.uniform_instance(n, n, d, alpha, seed=11)
+    side = float(W.side_length(alpha, 2 * n))
+    sigma = float(np.float32(0.1) * np.float32(side))
+    seed = 0x5EED
+    g = [torch.from_numpy(a).to(dev) for a in (inst.upd_lo, inst.upd_hi, inst.sub_lo, inst.sub_hi)]
+    full = [x.clone() for x in g]
+    res = ddm.Resident(*g, side, sigma, seed)
+    ws = torch.empty(ddm.workspace_bytes(n, n, d, "count"), dtype=torch.uint8, device=dev)
+    K, W_ = args.resident_steps, 3
+    counts_res, counts_full = [], []
+    step = 0
+    for _ in range(W_):
+        step += 1
+        counts_res.append(res.step(step))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        step += 1
+        counts_res.append(res.step(step))
+    t_res = (time.perf_counter() - t0) / K
+    ddm.profile(True)
+    for _ in range(3):
+        step += 1
+        counts_res.append(res.step(step))
+    phases = {p: round(v["ms"] / 3, 4) for p, v in sorted(ddm.profile_report().items())}
+    ddm.profile(False)
+    for st in range(1, W_ + 1):
+        ddm.sim_step(*full, side, sigma, seed, st)
+        counts_full.append(ddm.match_into(*full, "count", ws))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for st in range(W_ + 1, W_ + K + 1):
+        ddm.sim_step(*full, side, sigma, seed, st)
+        counts_full.append(ddm.match_into(*full, "count", ws))
+    t_full = (time.perf_counter() - t0) / K
+    for st in range(W_ + K + 1, step + 1):
+        ddm.sim_step(*full, side, sigma, seed, st)
+        counts_full.append(ddm.match_into(*full, "count", ws))
+    exact = counts_res == counts_full
+    state = res.export()
+    exact = exact and all(torch.equal(a, b) for a, b in zip(state, full))
+    info = res.info()
+    res.close()
+    step_ms = phases.get("resident.step")
+    # algorithmic bytes of the step kernels per region: read its index and
+    # lower corner (4 + 4d), write both corners and the 16-byte sweep record
+    # (8d + 16); indices are rewritten only in the few slabs a region left
+    bytes_step = 2 * n * (4 + 4 * d + 8 * d + 16)
+    return {
+        "workload": f"one resident simulation d={d}, n=m={n}, alpha={alpha:g}, "
+                    f"random walk sigma=0.1*side, {K} closed-loop steps",
+        "ms_per_step": round(1e3 * t_res, 4),
+        "full_ms_per_step": round(1e3 * t_full, 4),
+        "speedup": round(t_full / t_res, 2),
+        "regions_per_s": round(2 * n / t_res, 1),
+        "phases_ms": phases,
+        "step_kernels_gb_s": round(bytes_step / (step_ms * 1e-3) / 1e9, 1) if step_ms else None,
+        "movers_last_step": info["movers"],
+        "buckets": info["buckets"],
+        "full_matches": info["full_matches"],
+        "exact": bool(exact),
     }
 
 
@@ -330,6 +415,10 @@ def main():
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--no-served", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-resident", action="store_true",
+                    help="skip the incremental (resident simulation) measurement")
+    ap.add_argument("--resident-n", type=int, default=5_000_000)
+    ap.add_argument("--resident-steps", type=int, default=20)
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-budget-gib", type=float, default=4.0)
     ap.add_argument("--serve-slots", type=int, default=4)
@@ -545,6 +634,7 @@ def main():
     heavy = None if args.no_heavy else bench_output_heavy(args, ddm, W, torch, np)
     batched = None if args.no_batched else bench_batched(args, ddm, W, torch, np)
     served = None if args.no_served else bench_served(args, ddm, W, torch, np)
+    resident = None if args.no_resident else bench_resident(args, ddm, W, torch, np)
 
     out = {
         "metric": METRIC,
@@ -579,6 +669,7 @@ def main():
         "output_heavy": heavy,
         "batched": batched,
         "served": served,
+        "resident": resident,
         "input_generation_s": round(gen_s, 2),
     }
     print(json.dumps(out), flush=True)

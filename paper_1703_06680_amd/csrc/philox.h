@@ -9,11 +9,13 @@
 
 namespace ddm {
 
+// One round: the two 32 x 32 -> 64-bit products, each taken whole (one
+// v_mad_u64_u32 rather than separate low and high multiplies).
 __device__ __forceinline__ uint4 philox_round(uint4 x, uint32_t k0, uint32_t k1) {
-  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
-  const uint32_t hi0 = __umulhi(M0, x.x), lo0 = M0 * x.x;
-  const uint32_t hi1 = __umulhi(M1, x.z), lo1 = M1 * x.z;
-  return make_uint4(hi1 ^ x.y ^ k0, lo1, hi0 ^ x.w ^ k1, lo0);
+  const uint64_t p0 = (uint64_t)0xD2511F53u * x.x;
+  const uint64_t p1 = (uint64_t)0xCD9E8D57u * x.z;
+  return make_uint4((uint32_t)(p1 >> 32) ^ x.y ^ k0, (uint32_t)p1,
+                    (uint32_t)(p0 >> 32) ^ x.w ^ k1, (uint32_t)p0);
 }
 
 __device__ __forceinline__ uint4 philox4x32_10(uint4 ctr, uint32_t k0, uint32_t k1) {

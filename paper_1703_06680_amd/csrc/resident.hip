@@ -157,7 +157,7 @@ __global__ __launch_bounds__(kStepThreads) void res_step_kernel(ResDev a, uint32
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       bx[i].lo[k] = a.lo[g * D + k];
-      bx[i].hi[k] = a.hi[g * D + k];
+      bx[i].hi[k] = move ? 0.f : a.hi[g * D + k];  // a move recomputes it
     }
     if (move) {
 #pragma unroll
@@ -193,14 +193,23 @@ __global__ __launch_bounds__(kStepThreads) void res_step_kernel(ResDev a, uint32
   }
   if (flags) atomicOr(&a.ctr->flags[par], flags);
   // every slot of the slab is in registers before the scan's barriers, so
-  // the compacted stores below overwrite nothing still to be read
+  // the compacted stores below overwrite nothing still to be read.  A slab
+  // that lost no region keeps every region in its slot (its index need not
+  // be written again); one that did is compacted.
   uint32_t total;
   uint32_t pos = block_exclusive_scan<uint32_t, kStepThreads>(nkeep, red, &total);
+  const bool stay = total == C;
 #pragma unroll
   for (int i = 0; i < kStepItems; ++i) {
     if (!keep[i]) continue;
-    const size_t g = (size_t)b * kSlab + pos++;
-    res_store<D>(a, g, id[i], bx[i]);
+    const size_t g =
+        (size_t)b * kSlab + (stay ? (uint32_t)t + (uint32_t)i * kStepThreads : pos++);
+    if (!stay) a.ids[g] = id[i];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      a.lo[g * D + k] = bx[i].lo[k];
+      a.hi[g * D + k] = bx[i].hi[k];
+    }
     if (b < a.nb) {
       const uint4 r = res_record<D>(bx[i], id[i], (uint32_t)g, a, p);
       a.rec[g] = r;
@@ -539,6 +548,7 @@ extern "C" int ddm_resident_step(ddm_resident *r, uint32_t step, void *stream) {
     e = launch_walk(w, s);
   } else {
     e = launch_step(*r, step, 1u, s);
+    prof::end(s);
     if (e == hipSuccess)
       e = hipMemcpyAsync(r->host, r->state + r->R.hdr, sizeof(Header) + sizeof(ResCounters),
                          hipMemcpyDeviceToHost, s);
@@ -556,6 +566,7 @@ extern "C" int ddm_resident_finish(ddm_resident *r, uint64_t *count) {
   *count = 0;
   r->pending = false;
   if (hipEventSynchronize(r->done) != hipSuccess) return DDM_E_DEVICE;
+  prof::flush();
   hipStream_t s = r->stream;
   ++r->info.steps;
   if (r->full_mode) {
