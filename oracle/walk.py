@@ -26,11 +26,46 @@ IEEE float32 implementation):
 
 Parity of this module itself is pinned by a second, scalar implementation
 of the same definition in the tests and by distribution checks; no published
-known-answer vectors are used.
+known-answer vectors are used.  ``walk_fast`` runs the same motion through a
+C implementation (``walk_oracle.c``, pinned bit for bit to this module by the
+tests) for full-size replays.
 """
 from __future__ import annotations
 
+import ctypes
+import os
+import subprocess
+
 import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+C_SOURCE = os.path.join(_HERE, "walk_oracle.c")
+C_LIBRARY = os.path.join(_HERE, "libwalk.so")
+_clib = None
+
+
+def build_c(source: str = C_SOURCE, output: str = C_LIBRARY) -> str:
+    """Compile the C motion with the host compiler, one rounding per float
+    operation (no contraction into fused multiply-adds)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared", "-o", output,
+           source]
+    subprocess.run(cmd, check=True)
+    return output
+
+
+def _c():
+    global _clib
+    if _clib is None:
+        if not os.path.exists(C_LIBRARY):
+            build_c()
+        lib = ctypes.CDLL(C_LIBRARY)
+        fp = ctypes.POINTER(ctypes.c_float)
+        lib.walk_oracle_step.argtypes = [fp, fp, ctypes.c_int64, ctypes.c_int, ctypes.c_uint32,
+                                         ctypes.c_float, ctypes.c_float, ctypes.c_uint64,
+                                         ctypes.c_uint32]
+        lib.walk_oracle_step.restype = None
+        _clib = lib
+    return _clib
 
 _M0 = np.uint64(0xD2511F53)
 _M1 = np.uint64(0xCD9E8D57)
@@ -93,4 +128,31 @@ def walk(upd_lo, sub_lo, side: float, sigma: float, seed: int, steps: int, first
     for st in range(first_step, first_step + steps):
         ul, uh = walk_step(ul, 0, side, sigma, seed, st)
         sl, sh = walk_step(sl, n, side, sigma, seed, st)
+        yield st, ul, uh, sl, sh
+
+
+def walk_step_c(lo: np.ndarray, region0: int, side: float, sigma: float, seed: int,
+                step: int):
+    """``walk_step`` by the C implementation; returns the new (lo, hi)."""
+    out = np.ascontiguousarray(np.asarray(lo, dtype=np.float32)).copy()
+    rows = out.shape[0]
+    d = out.shape[1] if out.ndim == 2 else 1
+    hi = np.empty_like(out)
+    fp = ctypes.POINTER(ctypes.c_float)
+    if rows:
+        _c().walk_oracle_step(out.ctypes.data_as(fp), hi.ctypes.data_as(fp), rows, d,
+                              region0, float(np.float32(side)), float(np.float32(sigma)),
+                              int(seed) & 0xFFFFFFFFFFFFFFFF, int(step))
+    return out, hi
+
+
+def walk_fast(upd_lo, sub_lo, side: float, sigma: float, seed: int, steps: int,
+              first_step: int = 1):
+    """``walk`` by the C implementation."""
+    ul = np.asarray(upd_lo, dtype=np.float32)
+    sl = np.asarray(sub_lo, dtype=np.float32)
+    n = ul.shape[0]
+    for st in range(first_step, first_step + steps):
+        ul, uh = walk_step_c(ul, 0, side, sigma, seed, st)
+        sl, sh = walk_step_c(sl, n, side, sigma, seed, st)
         yield st, ul, uh, sl, sh

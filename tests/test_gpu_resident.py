@@ -169,3 +169,27 @@ def test_resident_invalid_input_and_protocol(ddm):
         r.export()
     r.finish()
     r.close()
+
+
+def test_resident_full_size_against_oracle(ddm, oracle):
+    """The benchmark's resident workload kind at full size (d = 2, n = m =
+    5e6, alpha = 30 so that the counts are not trivially small): two steps,
+    each count against the oracle on the C replay of the motion, and the
+    final state against that replay bit for bit."""
+    n, d, alpha = 5_000_000, 2, 30.0
+    inst = W.uniform_instance(n, n, d, alpha, seed=11)
+    side = float(W.side_length(alpha, 2 * n))
+    sigma = float(np.float32(0.1) * np.float32(side))
+    seed = 0x5EED
+    _note(f"resident full size d={d} n=m={n} alpha={alpha}")
+    r = ddm.Resident(*_dev(inst.upd_lo, inst.upd_hi, inst.sub_lo, inst.sub_hi), side, sigma, seed)
+    for st, ul, uh, sl, sh in walk.walk_fast(inst.upd_lo, inst.sub_lo, side, sigma, seed, 2):
+        got = r.step(st)
+        want, _, _ = oracle.sbm(ul, uh, sl, sh, pairs=False, per_update=False)
+        _note(f"step {st}: {got} pairs, oracle {want}")
+        assert got == want
+    info = r.info()
+    assert info["full_matches"] == 0 and info["movers"] > 0
+    for dev, ref in zip(r.export(), (ul, uh, sl, sh)):
+        assert np.array_equal(dev.cpu().numpy(), ref)
+    r.close()

@@ -89,3 +89,22 @@ def test_walk_generator_matches_steps(steps):
         u, _ = walk.walk_step(u, 0, 2.0, 0.2, 5, st)
         s, _ = walk.walk_step(s, 40, 2.0, 0.2, 5, st)
     assert last[0] == steps and np.array_equal(last[1], u) and np.array_equal(last[2], s)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_c_walk_equals_numpy_walk(d):
+    """The C replay used for full-size checks gives the numpy reference's
+    bits: ordinary coordinates, large ones (where lo + side rounds back to
+    lo), negative and huge sigmas, several steps and a 64-bit seed."""
+    rng = np.random.default_rng(100 + d)
+    lo = (rng.random((3000, d)) * 1e6).astype(np.float32)
+    lo[:50] = np.float32(3.0e10)
+    lo[50:60] = np.float32(-1.0e38)
+    for side, sigma, seed in ((0.25, 0.025, 7), (400.0, -2.0e5, 0xDEADBEEF12345678),
+                              (0.0, 1.0e30, 2**63 + 5)):
+        fast = list(walk.walk_fast(lo, lo[::-1], side, sigma, seed, 3, first_step=4))
+        ref = list(walk.walk(lo, lo[::-1], side, sigma, seed, 3, first_step=4))
+        for a, b in zip(fast, ref):
+            assert a[0] == b[0]
+            for x, y in zip(a[1:], b[1:]):
+                assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
