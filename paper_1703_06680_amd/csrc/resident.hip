@@ -387,7 +387,8 @@ namespace {
 
 hipError_t launch_step(const ddm_resident &r, uint32_t step, uint32_t move, hipStream_t s) {
   const ResDev a = r.dev();
-  const unsigned grid = std::max(1u, std::min(1024u, (a.mcap + kInsertThreads - 1) / kInsertThreads));
+  // movers are a few per million regions: a small grid, striding over more
+  const unsigned grid = std::max(1u, std::min(16u, (a.mcap + kInsertThreads - 1) / kInsertThreads));
   prof::mark(s, "resident.step");
   switch (r.d) {
     case 1:
