@@ -313,9 +313,10 @@ int ddm_sim_step(float *upd_lo, float *upd_hi, int64_t n, float *sub_lo, float *
  * count is the number of intersecting pairs of half-open boxes.  When the
  * slabs cannot hold a step's outcome, that step is counted by ddm_match()
  * and the slabs are rebuilt; a simulation that keeps overflowing, or whose
- * regions do not fit the slabs (d > 3, a bucket with more than 2048
- * regions, more than 512 regions active at a bucket boundary), is matched
- * by ddm_match() at every step from then on.
+ * regions do not fit the slabs (a bucket with more than 2048 regions, more
+ * than 512 regions active at a bucket boundary), is matched by ddm_match()
+ * instead, and the slabs are tried again every 64 steps; d > 3 is always
+ * matched by ddm_match().
  *
  * ddm_resident_bytes() gives the device state size for n updates and m
  * subscriptions in d dimensions (0 for invalid sizes).

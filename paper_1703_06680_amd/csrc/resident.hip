@@ -26,7 +26,8 @@
 // state is written back in region order, counted by the full matching call
 // (ddm_match), and the slabs are rebuilt from it; a simulation that needs
 // this twice in a row, or whose regions do not fit the slabs at all, keeps
-// its regions in region order and is matched by the full call at every step.
+// its regions in region order and is matched by the full call, trying the
+// slabs again every 64 steps (one repair in the first slab step sends it back).
 #include <string.h>
 
 #include <algorithm>
@@ -48,6 +49,7 @@ constexpr uint32_t kBsSlab = 512;       // boundary-state records per bucket
 constexpr int kStepThreads = 512;
 constexpr int kStepItems = (int)kSlab / kStepThreads;
 constexpr int kInsertThreads = 256;
+constexpr int kRetrySteps = 64;  // full-match steps before the slabs are tried again
 
 // Step flags (ResCounters::flags, one word per step parity).
 constexpr uint32_t kResMoverFull = 1u;  // the mover list was full: a region stayed misplaced
@@ -344,6 +346,7 @@ struct ddm_resident {
   float side = 0.f, sigma = 0.f;
   uint64_t seed = 0;
   bool full_mode = false;  // every step by launch_walk + ddm_match on the home rows
+  int full_steps = 0;      // steps in full-match mode since it was entered or last retried
   bool pending = false;
   uint32_t step = 0;       // step of the pending (or last) request
   int consecutive_repairs = 0;
@@ -572,7 +575,19 @@ extern "C" int ddm_resident_finish(ddm_resident *r, uint64_t *count) {
   ++r->info.steps;
   if (r->full_mode) {
     ++r->info.full_matches;
-    return full_match(*r, s, count);
+    const int rc = full_match(*r, s, count);
+    if (rc != DDM_OK || !r->R.slabs || ++r->full_steps < kRetrySteps) return rc;
+    // try the slabs again, from the home rows (the current state)
+    r->full_steps = 0;
+    ++r->info.rebuilds;
+    const int b = build(*r, s);
+    if (b == 1) return DDM_OK;
+    if (b != DDM_OK) return b;
+    r->full_mode = false;
+    r->consecutive_repairs = 1;  // a repair in the next step returns to full-match mode
+    r->info.full_mode = 0;
+    r->info.buckets = (int32_t)r->R.nb;
+    return DDM_OK;
   }
   const uint32_t par = r->step & 1u;
   const Header *h = reinterpret_cast<const Header *>(r->host);
@@ -604,6 +619,7 @@ extern "C" int ddm_resident_finish(ddm_resident *r, uint64_t *count) {
       return b;
   }
   if (r->full_mode) {
+    r->full_steps = 0;
     r->info.full_mode = 1;
     r->info.buckets = 0;
   }

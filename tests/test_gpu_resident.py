@@ -193,3 +193,26 @@ def test_resident_full_size_against_oracle(ddm, oracle):
     for dev, ref in zip(r.export(), (ul, uh, sl, sh)):
         assert np.array_equal(dev.cpu().numpy(), ref)
     r.close()
+
+
+def test_resident_retries_the_slabs(ddm, oracle):
+    """2500 regions empty at creation overflow the slab of empty regions, so
+    the simulation starts in full-match mode; the first step gives them their
+    side back, and the retry after 64 full-match steps returns the simulation
+    to the slabs.  Every count is exact throughout."""
+    inst, side, sigma, seed = _sim(10_000, 2, 5.0, seed=95)
+    inst.upd_hi[:2500, 1] = inst.upd_lo[:2500, 1]
+    _note("resident retry d=2 n=m=10000, 2500 empty at creation")
+    r = ddm.Resident(*_dev(inst.upd_lo, inst.upd_hi, inst.sub_lo, inst.sub_hi), side, sigma, seed)
+    assert r.info()["full_mode"] == 1
+    for st, ul, uh, sl, sh in walk.walk_fast(inst.upd_lo, inst.sub_lo, side, sigma, seed, 70):
+        got = r.step(st)
+        want, _, _ = oracle.sbm(ul, uh, sl, sh, pairs=False, per_update=False)
+        assert got == want, st
+        if st == 63:
+            assert r.info()["full_mode"] == 1
+    info = r.info()
+    assert info["full_mode"] == 0 and info["rebuilds"] == 1 and info["full_matches"] == 64, info
+    for dev, ref in zip(r.export(), (ul, uh, sl, sh)):
+        assert np.array_equal(dev.cpu().numpy(), ref)
+    r.close()
