@@ -378,34 +378,37 @@ __global__ __launch_bounds__(kThreads) void bk_count_kernel(
 // Column prefix of every instance's block-major count matrix: for bucket j
 // (local column lb) and block k, P[k][lb] = sum of C[k'][lb] over k' < k,
 // written block-major like C, and the column total into tot[j].  One lane
-// per bucket (64 buckets per workgroup, consecutive lanes on consecutive
-// columns, so every row access is coalesced); the 16 waves of a workgroup
-// take 16 consecutive ranges of blocks and combine their sums in LDS.
+// per bucket and block range: a workgroup takes kColBuckets consecutive
+// buckets, and its kColRanges lane groups (two per wave) take consecutive
+// ranges of blocks (consecutive lanes on consecutive columns, so every row
+// access is coalesced) and combine their sums in LDS.
 constexpr int kColWaves = 16;
+constexpr int kColBuckets = kWave / 2;
+constexpr int kColRanges = 2 * kColWaves;
 
 __global__ __launch_bounds__(kColWaves * kWave) void bk_colscan_kernel(
     const uint32_t *__restrict__ C, uint32_t *__restrict__ P, uint32_t *__restrict__ tot,
     View V, uint32_t nb_total) {
-  __shared__ uint32_t part[kColWaves][kWave];
-  const uint32_t lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-  const uint32_t j = blockIdx.x * kWave + lane;
+  __shared__ uint32_t part[kColRanges][kColBuckets];
+  const uint32_t col = threadIdx.x % kColBuckets, g = threadIdx.x / kColBuckets;  // g: range
+  const uint32_t j = blockIdx.x * kColBuckets + col;
   uint32_t k0 = 0, k1 = 0, stride = 0;
   size_t base = 0;
   if (j < nb_total) {
     const InstPlan I = V.get(V.of_bucket(j));
-    const uint32_t per = (I.nblk + kColWaves - 1) / kColWaves;
-    k0 = min(I.nblk, w * per);
+    const uint32_t per = (I.nblk + kColRanges - 1) / kColRanges;
+    k0 = min(I.nblk, g * per);
     k1 = min(I.nblk, k0 + per);
     stride = I.nb;
     base = I.cell0 + (size_t)(j - I.b0);
   }
   uint32_t sum = 0;
   for (uint32_t k = k0; k < k1; ++k) sum += C[base + (size_t)k * stride];
-  part[w][lane] = sum;
+  part[g][col] = sum;
   __syncthreads();
   uint32_t run = 0;
-  for (uint32_t v = 0; v < w; ++v) run += part[v][lane];
-  if (j < nb_total && w == kColWaves - 1) tot[j] = run + sum;
+  for (uint32_t v = 0; v < g; ++v) run += part[v][col];
+  if (j < nb_total && g == kColRanges - 1) tot[j] = run + sum;
   for (uint32_t k = k0; k < k1; ++k) {
     const size_t at = base + (size_t)k * stride;
     const uint32_t c = C[at];
@@ -1282,8 +1285,8 @@ void prepare_impl(const BucketArgs &a, hipStream_t s) {
   bk_count_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.C, p.T + L.nb, a.hdr,
                                                    a.zero, a.zero ? a.zero_count : 0u);
   prof::mark(s, "bucket.offsets");
-  bk_colscan_kernel<<<(L.nb + kWave - 1) / kWave, kColWaves * kWave, 0, s>>>(p.C, p.SB, p.T, p.V,
-                                                                         L.nb);
+  bk_colscan_kernel<<<(L.nb + kColBuckets - 1) / kColBuckets, kColWaves * kWave, 0, s>>>(
+      p.C, p.SB, p.T, p.V, L.nb);
   (void)exclusive_scan_u32(p.T, p.S, 2 * (size_t)L.nb + 1, p.scan_tmp, s);
   prof::mark(s, "bucket.scatter");
   bk_scatter_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.O, p.SB, p.bs_cur,
@@ -1320,8 +1323,8 @@ void build_slabs_impl(const BucketArgs &a, const SlabBuild &sb, hipStream_t s) {
   bk_plan_kernel<<<L.B, kSampleThreads, 0, s>>>(p.part, p.V, p.P);
   bk_count_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.C, p.T + L.nb, a.hdr,
                                                    nullptr, 0u);
-  bk_colscan_kernel<<<(L.nb + kWave - 1) / kWave, kColWaves * kWave, 0, s>>>(p.C, p.SB, p.T, p.V,
-                                                                         L.nb);
+  bk_colscan_kernel<<<(L.nb + kColBuckets - 1) / kColBuckets, kColWaves * kWave, 0, s>>>(
+      p.C, p.SB, p.T, p.V, L.nb);
   (void)fill_u32(sb.cnt + L.nb, 0u, 1, s);
   bk_slab_scatter_kernel<D><<<L.nblk, kThreads, lds, s>>>(p.V, p.P, p.SB, p.T, sb.ids, sb.lo,
                                                           sb.hi, sb.cnt, sb.cap, sb.overflow);

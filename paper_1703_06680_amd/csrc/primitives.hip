@@ -100,9 +100,45 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const T *in, T
   }
 }
 
+// Arrays of at most kSmallScan elements are scanned by one workgroup in one
+// launch: thread t owns a run of at most kSmallItems consecutive elements,
+// loads it into registers at once, takes its offset from a workgroup scan of
+// the run sums and writes the run (every element is read before any is
+// written, so out may alias in).
+constexpr int kSmallScanThreads = 1024;
+constexpr int kSmallItems = 16;
+constexpr size_t kSmallScan = (size_t)kSmallItems * kSmallScanThreads;
+
+template <typename T>
+__global__ __launch_bounds__(kSmallScanThreads) void scan_small_kernel(const T *in, T *out,
+                                                                       uint32_t count) {
+  __shared__ T lds[kSmallScanThreads / kWave + 1];
+  const uint32_t per = (count + kSmallScanThreads - 1) / kSmallScanThreads;
+  const uint32_t b0 = min(count, threadIdx.x * per);
+  T v[kSmallItems], sum = 0;
+#pragma unroll
+  for (int q = 0; q < kSmallItems; ++q) {
+    const uint32_t i = b0 + (uint32_t)q;
+    v[q] = (uint32_t)q < per && i < count ? in[i] : T(0);
+    sum += v[q];
+  }
+  T total;
+  T run = block_exclusive_scan<T, kSmallScanThreads>(sum, lds, &total);
+#pragma unroll
+  for (int q = 0; q < kSmallItems; ++q) {
+    const uint32_t i = b0 + (uint32_t)q;
+    if ((uint32_t)q < per && i < count) out[i] = run;
+    run += v[q];
+  }
+}
+
 template <typename T>
 hipError_t exclusive_scan_impl(const T *in, T *out, size_t count, void *temp, hipStream_t s) {
   if (count == 0) return hipSuccess;
+  if (count <= kSmallScan) {
+    scan_small_kernel<T><<<dim3(1), dim3(kSmallScanThreads), 0, s>>>(in, out, (uint32_t)count);
+    return hipGetLastError();
+  }
   size_t nb = div_up(count, kScanChunk);
   T *sums = static_cast<T *>(temp);
   scan_reduce_kernel<T><<<dim3((unsigned)nb), dim3(kScanThreads), 0, s>>>(in, count, sums);
