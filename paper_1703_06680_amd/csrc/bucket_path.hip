@@ -470,6 +470,108 @@ __global__ __launch_bounds__(kThreads) void bk_scatter_kernel(
   }
 }
 
+// Scatter with record pairs.  Random 16-byte stores are bound by their
+// number, so two records of one bucket in the same aligned 32 bytes of the
+// output are written together by one thread.  Records take their slots as
+// in bk_scatter_kernel, kPairGroups groups per thread per round.  A record
+// in an even slot s offers itself in its bucket's LDS mailbox (a tag, the
+// pair index s / 2, claimed by compare-and-swap, and the record; a busy
+// mailbox makes it a single store); after a barrier, the record in odd slot
+// s + 1 takes the offer if the tag is its pair's and writes both (else it is
+// written alone: its neighbour was another block's or wrote itself).  Offers
+// left when the block ends (the last slot of its cell, even) are written
+// alone.  Every record is written exactly once.  LDS: 24 bytes per bucket.
+constexpr uint32_t kTagFree = 0xFFFFFFFFu;
+constexpr uint32_t kPairScatterMaxBuckets = 6656;
+constexpr int kPairGroups = 2;
+
+template <int D>
+__global__ __launch_bounds__(kThreads) void bk_scatter_pair_kernel(
+    uint32_t n_total, View V, const BucketParams *__restrict__ P, Offsets O,
+    const uint32_t *__restrict__ SB, uint32_t *__restrict__ bs_cur, uint32_t bs_cap,
+    uint32_t *__restrict__ rec, uint32_t *__restrict__ bs_rec) {
+  constexpr int RW = 4;
+  extern __shared__ uint4 stash[];  // [max_nb] records, then tag[nb], cur[nb]
+  const uint32_t inst = V.of_blk(blockIdx.x);
+  const InstPlan I = V.get(inst);
+  const BucketParams p = P[inst];
+  const uint32_t nb = I.nb, lb = blockIdx.x - I.blk0;
+  uint32_t *tag = reinterpret_cast<uint32_t *>(stash + nb);
+  uint32_t *cur = tag + nb;
+  const uint32_t *row = SB + I.cell0 + (size_t)lb * nb;
+  for (uint32_t b = threadIdx.x; b < nb; b += kThreads) {
+    cur[b] = O.S[I.b0 + b] + row[b];
+    tag[b] = kTagFree;
+  }
+  __syncthreads();
+  const uint32_t g0 = lb * I.gpb, g1 = min(I.g, g0 + I.gpb);
+  for (uint32_t base = g0; base < g1; base += kPairGroups * kThreads) {  // uniform
+    Group q[kPairGroups];
+    Box<D> bx[kPairGroups][4];
+#pragma unroll
+    for (int k = 0; k < kPairGroups; ++k) {
+      const uint32_t g = base + (uint32_t)k * kThreads + threadIdx.x;
+      q[k] = Group{};
+      if (g < g1) {
+        q[k] = group_of(g, I, n_total);
+        load_group<D>(q[k], I.vec != 0, bx[k]);
+      }
+    }
+    uint32_t slot[kPairGroups][4];  // odd slots still to collect, else ~0u
+#pragma unroll
+    for (int k = 0; k < kPairGroups; ++k)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        slot[k][r] = ~0u;
+        if ((uint32_t)r >= q[k].rows) continue;
+        bool empty;
+        (void)box_errors<D>(bx[k][r], empty, I.closed);
+        if (empty) continue;
+        const uint32_t rid = q[k].r0 + r;
+        const uint32_t b = bucket_of(bx[k][r].lo[0], p.vmin, p.scale, nb);
+        const uint32_t s = atomicAdd(&cur[b], 1u);
+        bool alone = true;
+        if ((s & 1u) == 0u) {
+          if (atomicCAS(&tag[b], kTagFree, s >> 1) == kTagFree) {
+            stash[b] = make_uint4(encode_coord(bx[k][r].lo[0]),
+                                  encode_coord(bx[k][r].hi[0]) + I.closed, rid,
+                                  qword_of<D>(bx[k][r], p));
+            alone = false;
+          }
+        } else {
+          slot[k][r] = s;
+          alone = false;
+        }
+        if (alone) write_record<D>(rec + (size_t)s * RW, bx[k][r], rid, p, I.closed);
+        const uint32_t last = bucket_of(bx[k][r].hi[0], p.vmin, p.scale, nb);
+        for (uint32_t j = b + 1; j <= last; ++j) {
+          const uint32_t jg = I.b0 + j;
+          const uint32_t pos = O.bs_begin(jg) + atomicAdd(&bs_cur[jg], 1u);
+          if (pos < bs_cap) write_record<D>(bs_rec + (size_t)pos * RW, bx[k][r], rid, p, I.closed);
+        }
+      }
+    __syncthreads();  // every offer of this round is in its mailbox
+#pragma unroll
+    for (int k = 0; k < kPairGroups; ++k)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t s = slot[k][r];
+        if (s == ~0u) continue;
+        const uint32_t rid = q[k].r0 + r;
+        const uint32_t b = bucket_of(bx[k][r].lo[0], p.vmin, p.scale, nb);
+        if (tag[b] == (s >> 1)) {
+          const uint4 even = stash[b];
+          tag[b] = kTagFree;
+          *reinterpret_cast<uint4 *>(rec + (size_t)(s - 1) * RW) = even;
+        }
+        write_record<D>(rec + (size_t)s * RW, bx[k][r], rid, p, I.closed);
+      }
+    __syncthreads();  // mailboxes are settled before the next round's offers
+  }
+  for (uint32_t b = threadIdx.x; b < nb; b += kThreads)  // offers without a partner here
+    if (tag[b] != kTagFree) *reinterpret_cast<uint4 *>(rec + (size_t)tag[b] * 2 * RW) = stash[b];
+}
+
 // Slab layout of a single instance (a resident simulation): every region
 // goes, by its swept-axis lower coordinate, into its bucket's slab of cap
 // slots, at the block's prefix within that bucket (from bk_colscan_kernel)
@@ -1289,8 +1391,12 @@ void prepare_impl(const BucketArgs &a, hipStream_t s) {
       p.C, p.SB, p.T, p.V, L.nb);
   (void)exclusive_scan_u32(p.T, p.S, 2 * (size_t)L.nb + 1, p.scan_tmp, s);
   prof::mark(s, "bucket.scatter");
-  bk_scatter_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.O, p.SB, p.bs_cur,
-                                                     L.bs_cap, p.rec, p.bs_rec);
+  if (L.max_nb <= kPairScatterMaxBuckets)
+    bk_scatter_pair_kernel<D><<<L.nblk, kThreads, (size_t)L.max_nb * 24, s>>>(
+        L.n_total, p.V, p.P, p.O, p.SB, p.bs_cur, L.bs_cap, p.rec, p.bs_rec);
+  else
+    bk_scatter_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.O, p.SB, p.bs_cur,
+                                                       L.bs_cap, p.rec, p.bs_rec);
 }
 
 template <int DM1, int MODE>
