@@ -666,6 +666,10 @@ def main():
         "correlated": correlated,
         "served_p50_ms": served["levels"]["1x"]["batched"]["p50_ms"] if served else None,
         "served_p99_ms": served["levels"]["1x"]["batched"]["p99_ms"] if served else None,
+        "served_incremental_p50_ms":
+            served["levels"]["1x"]["incremental"]["p50_ms"] if served else None,
+        "served_incremental_p99_ms":
+            served["levels"]["1x"]["incremental"]["p99_ms"] if served else None,
         "output_heavy": heavy,
         "batched": batched,
         "served": served,
