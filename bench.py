@@ -361,6 +361,18 @@ def bench_resident(args, ddm, W, torch, np):
     }
 
 
+def host_cpu() -> str:
+    """Model name of the host CPU (Linux), for the baseline's description."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "host CPU"
+
+
 def source_digest(paths):
     h = hashlib.sha256()
     for p in paths:
@@ -389,7 +401,7 @@ def load_traffic(kernel_phase: str):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--alpha", type=float, default=100.0,
                     help="overlap degree of the timed workload")
@@ -415,6 +427,7 @@ def main():
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--no-served", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--cpu-runs", type=int, default=3, help="runs of the CPU oracle baseline")
     ap.add_argument("--no-resident", action="store_true",
                     help="skip the incremental (resident simulation) measurement")
     ap.add_argument("--resident-n", type=int, default=5_000_000)
@@ -619,17 +632,22 @@ def main():
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         o = O.default()
-        tc = time.perf_counter()
-        k_cpu, per_cpu, _ = o.sbm(inst.upd_lo, inst.upd_hi, inst.sub_lo, inst.sub_hi, pairs=False,
-                                  per_update=args.mode == "per_update")
-        dt = time.perf_counter() - tc
+        times = []
+        for _ in range(args.cpu_runs):
+            tc = time.perf_counter()
+            k_cpu, per_cpu, _ = o.sbm(inst.upd_lo, inst.upd_hi, inst.sub_lo, inst.sub_hi,
+                                      pairs=False, per_update=args.mode == "per_update")
+            times.append(time.perf_counter() - tc)
+        dt = statistics.median(times)
         k_chk = step()  # the extra alphas reused the output buffer
         assert k_cpu == k_chk == k, f"GPU count {k} != oracle {k_cpu}"
         if args.mode == "per_update":
             assert np.array_equal(per_cpu, per.cpu().numpy()), "per-update counts differ"
         cpu = {"value": round(regions / dt, 1), "unit": "regions/s", "cores": 1, "kind": "oracle",
-               "sample": f"the full workload (n = m = {n}, d = {d}, alpha = {args.alpha:g}), one "
-                         f"serial run of the C oracle ({dt:.2f} s), checked equal to the GPU result"}
+               "sample": f"the full workload (n = m = {n}, d = {d}, alpha = {args.alpha:g}), "
+                         f"{len(times)} serial runs of the C oracle on one core of a {host_cpu()} "
+                         f"({os.cpu_count()} logical CPUs visible): median {dt:.2f} s, min "
+                         f"{min(times):.2f} s; checked equal to the GPU result"}
 
     heavy = None if args.no_heavy else bench_output_heavy(args, ddm, W, torch, np)
     batched = None if args.no_batched else bench_batched(args, ddm, W, torch, np)
