@@ -70,7 +70,7 @@ def algorithmic_bytes(phase: str, n: int, m: int, d: int, nonempty: int, mode: s
     return None
 
 
-def bench_batched(args, ddm, W, torch, np):
+def bench_batched(args, ddm, W, torch, np, cpu=None):
     """512 independent d=2 instances (n = m log-uniform on [1e3, 2e5], alpha
     uniform in {0.01, 1, 10}), pairs mode: 512 plain ddm_match calls against
     one batched call and against replays of the autotuned captured graph."""
@@ -134,6 +134,10 @@ def bench_batched(args, ddm, W, torch, np):
     exact = (total_g == total == sum(ks_plain) and counts.tolist() == ks_plain and
              bool(torch.equal(batch.pairs[:total_g], pairs_plain)))
     graph.close()
+    cpu_baseline = None
+    if cpu is not None:
+        exact = exact and [int(counts[b]) for b in cpu["instances"]] == cpu["counts"]
+        cpu_baseline = {k: cpu[k] for k in ("one_core", "all_cores", "sample")}
     return {
         "workload": f"{len(insts)} independent d=2 instances, n=m log-uniform on [1e3, 2e5] "
                     f"(sum N = {regions}), alpha uniform in {{0.01, 1, 10}}, pairs mode",
@@ -144,7 +148,7 @@ def bench_batched(args, ddm, W, torch, np):
         "plain_regions_per_s": round(regions / (plain_ms * 1e-3), 1),
         "speedup_graph_vs_plain": round(plain_ms / graph_ms, 2),
         "tuning": best.as_dict(), "autotune_replay_ms": round(best_ms, 3),
-        "autotune_s": round(tune_s, 2), "exact": exact,
+        "autotune_s": round(tune_s, 2), "exact": exact, "cpu_baseline": cpu_baseline,
     }
 
 
@@ -361,6 +365,52 @@ def bench_resident(args, ddm, W, torch, np):
     }
 
 
+_BATCH_WORK = []  # the batched baseline's instances, shared with forked workers
+
+
+def _oracle_count(i):
+    """Worker of the batched CPU baseline: the oracle's count of instance i."""
+    from oracle import oracle as O
+    k, _, _ = O.default().sbm(*_BATCH_WORK[i], pairs=False, per_update=False)
+    return k
+
+
+def cpu_batched_baseline(args, W, np):
+    """The oracle on a sample of the batched workload (every 8th instance), on
+    one core and over a process pool on the host cores.  Runs before the GPU
+    is first touched, so the pool's processes fork from a process without GPU
+    state."""
+    import multiprocessing as mp
+    insts = W.batched_instances(args.batch_count, d=2, seed=0)
+    picked = list(range(0, len(insts), 8))
+    _BATCH_WORK[:] = [(insts[b].upd_lo, insts[b].upd_hi, insts[b].sub_lo, insts[b].sub_hi)
+                      for b in picked]
+    regions = sum(insts[b].n + insts[b].m for b in picked)
+    t = time.perf_counter()
+    serial = [_oracle_count(i) for i in range(len(picked))]
+    t_serial = time.perf_counter() - t
+    procs = max(1, min(16, os.cpu_count() or 1))
+    # largest instances first, one at a time; the workers read the instances
+    # from the memory they share with this process by fork
+    order = sorted(range(len(picked)), key=lambda i: -(insts[picked[i]].n + insts[picked[i]].m))
+    with mp.get_context("fork").Pool(procs) as pool:
+        pool.map(_oracle_count, order[-procs:], chunksize=1)  # workers up, oracle loaded
+        t = time.perf_counter()
+        pooled = pool.map(_oracle_count, order, chunksize=1)
+        t_pool = time.perf_counter() - t
+    assert [pooled[order.index(i)] for i in range(len(picked))] == serial
+    return {
+        "instances": picked, "counts": serial,
+        "one_core": {"value": round(regions / t_serial, 1), "unit": "regions/s", "cores": 1,
+                     "kind": "oracle"},
+        "all_cores": {"value": round(regions / t_pool, 1), "unit": "regions/s", "cores": procs,
+                      "kind": "oracle"},
+        "sample": f"every 8th instance ({len(picked)} instances, {regions} regions), the C "
+                  f"oracle per instance: {t_serial:.2f} s on one core, {t_pool:.2f} s over "
+                  f"{procs} processes",
+    }
+
+
 def host_cpu() -> str:
     """Model name of the host CPU (Linux), for the baseline's description."""
     try:
@@ -466,6 +516,10 @@ def main():
     import torch
 
     from paper_1703_06680_amd import ddm, workloads as W
+
+    batched_cpu = None
+    if not args.no_batched and not args.no_cpu_baseline:
+        batched_cpu = cpu_batched_baseline(args, W, np)  # before the GPU is touched
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -650,7 +704,7 @@ def main():
                          f"{min(times):.2f} s; checked equal to the GPU result"}
 
     heavy = None if args.no_heavy else bench_output_heavy(args, ddm, W, torch, np)
-    batched = None if args.no_batched else bench_batched(args, ddm, W, torch, np)
+    batched = None if args.no_batched else bench_batched(args, ddm, W, torch, np, batched_cpu)
     served = None if args.no_served else bench_served(args, ddm, W, torch, np)
     resident = None if args.no_resident else bench_resident(args, ddm, W, torch, np)
 
