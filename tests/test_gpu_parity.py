@@ -152,6 +152,32 @@ def test_cfg3_full_counts(ddm, oracle, alpha):
             assert ddm.last_path() == "bucketed"
 
 
+def test_more_buckets_than_the_pair_scatter_holds(ddm, oracle):
+    """n = m = 5.5e6 (7162 buckets, beyond the 6656 the pairing scatter keeps
+    in LDS): the single-store scatter, per-update counts against the 1-D
+    closed form, and pairs of a sample of updates against the oracle's."""
+    from oracle import oracle as O
+    inst = W.uniform_instance(5_500_000, 5_500_000, 1, 20.0, seed=8)
+    _note(f"{inst.name} beyond the pairing scatter")
+    g = _dev(inst)
+    ddm.set_path("bucketed")
+    k, per = ddm.match(*g, mode="per_update")
+    want = O.closed_form_1d(*_host(inst))
+    assert np.array_equal(per.cpu().numpy().astype(np.int64), want)
+    assert k == int(want.sum())
+    # the sampled updates' rows of the pair list against the oracle's
+    k2, pairs, _ = ddm.match(*g, mode="pairs")
+    assert k2 == k
+    pairs = pairs.cpu().numpy()
+    off = np.concatenate([[0], np.cumsum(want)])
+    rows = np.random.default_rng(3).choice(inst.n, size=200, replace=False)
+    sub = (inst.upd_lo[rows], inst.upd_hi[rows], inst.sub_lo, inst.sub_hi)
+    _, _, ref = oracle.sbm(*sub)
+    for i, r in enumerate(rows):
+        got = pairs[off[r]:off[r + 1], 1]
+        assert np.array_equal(got, ref[ref[:, 0] == i, 1]), r
+
+
 @pytest.mark.parametrize("alpha", [1.0, 100.0])
 def test_correlated_d3_stress(ddm, oracle, alpha):
     """Many true 3-D matches, so per-update counts and pairs are exercised."""
