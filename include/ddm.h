@@ -207,7 +207,7 @@ size_t ddm_batch_workspace_bytes(const int64_t *upd_off, const int64_t *sub_off,
  * sum of counts.  Errors: as ddm_match(); DDM_E_CAPACITY if the pairs of all
  * instances exceed pair_capacity (counts, per_update and pair_off are then
  * complete, pairs untouched).  When a bucket of some instance overflows its
- * on-chip buffer, or d > 3, the instances are matched one by one with the
+ * on-chip buffer, or d > 8, the instances are matched one by one with the
  * device-wide path instead (same results).
  */
 int ddm_match_batched(const float *upd_lo, const float *upd_hi, const int64_t *upd_off,
@@ -248,7 +248,7 @@ int ddm_match_multi(const ddm_instance *inst, int64_t B, int d, int mode, void *
  * and returns what ddm_match_batched() would return for that replay (running
  * the per-instance fallback itself if a bucket overflowed).  tuning may be
  * NULL (default).  Errors of create: as ddm_match_batched() for the
- * arguments, DDM_E_UNSUPPORTED if d > 3 or the batch does not fit the
+ * arguments, DDM_E_UNSUPPORTED if d > 8 or the batch does not fit the
  * bucketed plan, DDM_E_DEVICE if capture fails.
  */
 typedef struct ddm_batch_graph ddm_batch_graph;
@@ -434,7 +434,8 @@ const char *ddm_strerror(int code);
  *                      is sorted and swept in on-chip memory, starting from
  *                      the regions of earlier buckets still active at its
  *                      start (the boundary state of Algorithm 6); available
- *                      for d <= 3;
+ *                      for d <= 8 (a pre-filter on axes 1 and 2, the exact
+ *                      test on every axis);
  *   DDM_PATH_GLOBAL    a device-wide sort of the lower endpoints and a sweep
  *                      over device memory; any d.
  * DDM_PATH_AUTO (default) uses the bucketed path where available and falls

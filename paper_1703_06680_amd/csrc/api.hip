@@ -4,7 +4,7 @@
 //   - the bucketed path (bucket_path.hip): regions are partitioned by their
 //     swept-axis lower coordinate into buckets that are sorted and swept in
 //     LDS, with each bucket's boundary state delivered from the earlier ones;
-//     used when d <= 3 and the bucket count fits, and every bucket and the
+//     used when d <= 8 and the bucket count fits, and every bucket and the
 //     boundary state fit their buffers;
 //   - the device-wide path (match_global.hip): a global radix sort of the
 //     lower keys, a gather of the other axes into sorted order and a forward

@@ -69,16 +69,16 @@ __device__ __forceinline__ uint32_t quant_hi(float x, float qmin, float qs) {
 }
 
 // Word 3 of a region record: the quantised bounds of the other axes.  d = 2:
-// the 16-bit lower | upper << 16 of axis 1; d = 3: 7-bit bounds (the 16-bit
-// ones scaled by 2^-9, lower rounded down, upper rounded up and capped at
-// 127) lo1 | hi1 << 8 | lo2 << 16 | hi2 << 24; 0 for d = 1.
+// the 16-bit lower | upper << 16 of axis 1; d >= 3: 7-bit bounds of axes 1
+// and 2 (the 16-bit ones scaled by 2^-9, lower rounded down, upper rounded
+// up and capped at 127) lo1 | hi1 << 8 | lo2 << 16 | hi2 << 24; 0 for d = 1.
 template <int D>
 __device__ __forceinline__ uint32_t qword_of(const Box<D> &b, const BucketParams &p) {
   if (D == 2) {
     return quant_lo(b.lo[1 % D], p.qmin[0], p.qscale[0]) |
            (quant_hi(b.hi[1 % D], p.qmin[0], p.qscale[0]) << 16);
   }
-  if (D == 3) {
+  if (D >= 3) {
     uint32_t w = 0;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {

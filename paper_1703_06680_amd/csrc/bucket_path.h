@@ -44,6 +44,10 @@ struct BucketTuning {
   uint32_t max_blocks = 256;      // count/scatter blocks per instance at most
 };
 
+// Largest d of the bucketed path (the pre-filter quantises axes 1 and 2; the
+// exact test reads every other axis).
+constexpr int kBucketMaxDims = 8;
+
 // Records per bucket the sweep holds in LDS: kBucketCap for sweep
 // workgroups of 256 or 512 threads, kBigBucketCap for 1024.
 constexpr uint32_t kBucketCap = 2048;
@@ -71,6 +75,7 @@ struct InstPlan {
   uint32_t smp0, nsmp;       // sample blocks
   uint32_t vec;              // rows may be read with 16-byte loads
   uint32_t closed;           // 1: closed intervals (records hold enc(hi) + 1)
+  uint32_t d;                // dimensions (floats per row)
 };
 
 inline uint32_t bucket_cap(const BucketTuning &t) {

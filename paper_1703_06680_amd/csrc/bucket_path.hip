@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kSampleThreads) void bk_sample_kernel(View V,
     v[0] = v[1] = b.lo[0];
     v[2] = 1.f;
 #pragma unroll
-    for (int k = 1; k < D; ++k) {
+    for (int k = 1; k < (D < 3 ? D : 3); ++k) {  // the quantised axes 1 and 2
       v[4 + 2 * (k - 1)] = b.lo[k];
       v[5 + 2 * (k - 1)] = b.hi[k];
     }
@@ -505,11 +505,12 @@ __global__ __launch_bounds__(kThreads) void bk_scatter_pair_kernel(
   }
   __syncthreads();
   const uint32_t g0 = lb * I.gpb, g1 = min(I.g, g0 + I.gpb);
-  for (uint32_t base = g0; base < g1; base += kPairGroups * kThreads) {  // uniform
-    Group q[kPairGroups];
-    Box<D> bx[kPairGroups][4];
+  constexpr int G = D <= 3 ? kPairGroups : 1;  // wider rows: one group per round
+  for (uint32_t base = g0; base < g1; base += G * kThreads) {  // uniform
+    Group q[G];
+    Box<D> bx[G][4];
 #pragma unroll
-    for (int k = 0; k < kPairGroups; ++k) {
+    for (int k = 0; k < G; ++k) {
       const uint32_t g = base + (uint32_t)k * kThreads + threadIdx.x;
       q[k] = Group{};
       if (g < g1) {
@@ -517,9 +518,9 @@ __global__ __launch_bounds__(kThreads) void bk_scatter_pair_kernel(
         load_group<D>(q[k], I.vec != 0, bx[k]);
       }
     }
-    uint32_t slot[kPairGroups][4];  // odd slots still to collect, else ~0u
+    uint32_t slot[G][4];  // odd slots still to collect, else ~0u
 #pragma unroll
-    for (int k = 0; k < kPairGroups; ++k)
+    for (int k = 0; k < G; ++k)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         slot[k][r] = ~0u;
@@ -552,7 +553,7 @@ __global__ __launch_bounds__(kThreads) void bk_scatter_pair_kernel(
       }
     __syncthreads();  // every offer of this round is in its mailbox
 #pragma unroll
-    for (int k = 0; k < kPairGroups; ++k)
+    for (int k = 0; k < G; ++k)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const uint32_t s = slot[k][r];
@@ -693,7 +694,7 @@ __device__ __forceinline__ uint32_t qdiff(uint32_t entry, uint32_t walker) {
                                           __builtin_bit_cast(u16x2, walker)));
 }
 
-// Pre-filter words.  d = 2: the 16-bit bounds of axis 1 as above.  d = 3:
+// Pre-filter words.  d = 2: the 16-bit bounds of axis 1 as above.  d >= 3:
 // one word of four 7-bit fields; the entry word holds, per axis, lo and
 // 127 - hi in consecutive bytes, the walker word hi and 127 - lo with the top
 // bit of every byte set.  walker - entry then borrows across no byte, and the
@@ -762,20 +763,41 @@ struct SweepCtx {
   uint32_t *own;
 };
 
-// Exact other-axis coordinates of region rid, from the instance's rows.
+// DM1 is d - 1 for d <= 3; DM1 = 3 stands for every d >= 4, whose records
+// and pre-filter are those of d = 3 (axes 1 and 2) and whose exact test also
+// reads axes 3 .. d-1 (extra_axes).  Axes held in the walkers' caches:
+template <int DM1>
+constexpr int kNearAxes = DM1 < 2 ? DM1 : 2;
+
+// Exact coordinates of axes 1 and 2 (at most) of region rid, from its row.
 template <int DM1>
 __device__ __forceinline__ void other_axes(const SweepCtx &o, uint32_t rid, float (&lo)[2],
                                            float (&hi)[2]) {
-  constexpr int D = DM1 + 1;
   const bool upd = rid < o.n;
   const size_t row = upd ? rid - o.I.u0 : rid - o.n - o.I.s0;
+  const size_t D = DM1 == 3 ? (size_t)o.I.d : (size_t)(DM1 + 1);  // floats per row
   const float *L = (upd ? o.I.ulo : o.I.slo) + row * D;
   const float *H = (upd ? o.I.uhi : o.I.shi) + row * D;
 #pragma unroll
-  for (int c = 0; c < DM1; ++c) {
+  for (int c = 0; c < kNearAxes<DM1>; ++c) {
     lo[c] = L[1 + c];
     hi[c] = H[1 + c];
   }
+}
+
+// Axes 3 .. d-1 of regions ry and rx (d >= 4; the pre-filter and the
+// cached test cover axes 1 and 2): whether they overlap on all of them.
+__device__ __forceinline__ bool extra_axes(const SweepCtx &o, uint32_t ry, uint32_t rx) {
+  const uint32_t d = o.I.d;
+  const bool uy = ry < o.n, ux = rx < o.n;
+  const size_t y = uy ? ry - o.I.u0 : ry - o.n - o.I.s0;
+  const size_t x = ux ? rx - o.I.u0 : rx - o.n - o.I.s0;
+  const float *yl = (uy ? o.I.ulo : o.I.slo) + y * d, *yh = (uy ? o.I.uhi : o.I.shi) + y * d;
+  const float *xl = (ux ? o.I.ulo : o.I.slo) + x * d, *xh = (ux ? o.I.uhi : o.I.shi) + x * d;
+  bool hit = true;
+  for (uint32_t k = 3; k < d; ++k)
+    hit = hit && before(yl[k], xh[k], o.I.closed) && before(xl[k], yh[k], o.I.closed);
+  return hit;
 }
 
 // A pair of walker y and entry j that passed the key and pre-filter tests:
@@ -800,8 +822,9 @@ __device__ __forceinline__ void visit(const Walker<DM1> &y, bool &have_y, float 
     other_axes<DM1>(o, rx, xlo, xhi);
     bool hit = true;
 #pragma unroll
-    for (int c = 0; c < DM1; ++c)
+    for (int c = 0; c < kNearAxes<DM1>; ++c)
       hit = hit && before(ylo[c], xhi[c], o.I.closed) && before(xlo[c], yhi[c], o.I.closed);
+    if (DM1 == 3 && hit) hit = extra_axes(o, y.rid, rx);
     if (!hit) return;
   }
   ++hits;
@@ -845,8 +868,9 @@ __device__ __forceinline__ void resolve(uint32_t ry, uint32_t rx, unsigned long 
   other_axes<DM1>(o, rx, xlo, xhi);
   bool hit = true;
 #pragma unroll
-  for (int c = 0; c < DM1; ++c)
+  for (int c = 0; c < kNearAxes<DM1>; ++c)
     hit = hit && before(ylo[c], xhi[c], o.I.closed) && before(xlo[c], yhi[c], o.I.closed);
+  if (DM1 == 3 && hit) hit = extra_axes(o, ry, rx);
   if (!hit) return;
   ++hits;
   const uint32_t uu = ry < o.n ? ry : rx, ss = ry < o.n ? rx : ry;
@@ -862,7 +886,7 @@ __device__ __forceinline__ void resolve(uint32_t ry, uint32_t rx, unsigned long 
 // Zero iff entry word e passes the walker's pre-filter (d >= 2).
 template <int DM1>
 __device__ __forceinline__ uint32_t qfail(uint32_t e, uint32_t wq) {
-  if (DM1 == 2) return ~(wq - e) & 0x80808080u;  // a cleared top bit: some byte failed
+  if (DM1 >= 2) return ~(wq - e) & 0x80808080u;  // a cleared top bit: some byte failed
   if (DM1 == 1) return qdiff(e, wq);
   return 0u;
 }
@@ -1444,6 +1468,7 @@ void sweep_slabs_impl(const SlabSweep &w, hipStream_t s) {
   V.one.ulo = V.one.slo = w.lo;
   V.one.uhi = V.one.shi = w.hi;
   V.one.nb = w.nb;
+  V.one.d = (uint32_t)w.d;
   Offsets O{};
   O.S = nullptr;
   O.nb = w.nb;
@@ -1493,7 +1518,7 @@ bool plan_instance(const InstSpec &sp, int64_t u0, int64_t s0, const BucketTunin
 }  // namespace
 
 bool bucket_path_supported(int d, const InstSpec *inst, int64_t B, const BucketTuning &t) {
-  if (d < 1 || d > 3 || B < 1) return false;
+  if (d < 1 || d > kBucketMaxDims || B < 1) return false;
   if (t.target < 64 || t.target > bucket_cap(t) * 3 / 4) return false;
   if (t.sweep_threads != 256 && t.sweep_threads != 512 && t.sweep_threads != 1024) return false;
   if (t.groups_per_thread < 1 || t.max_blocks < 1) return false;
@@ -1513,7 +1538,7 @@ bool bucket_path_supported(int d, int64_t n, int64_t m) {
   return bucket_path_supported(d, &sp, 1, BucketTuning{});
 }
 
-BucketLayout bucket_layout(const InstSpec *inst, int64_t B, int /*d*/, const BucketTuning &t) {
+BucketLayout bucket_layout(const InstSpec *inst, int64_t B, int d, const BucketTuning &t) {
   BucketLayout L{};
   L.B = (uint32_t)B;
   L.tune = t;
@@ -1524,6 +1549,7 @@ BucketLayout bucket_layout(const InstSpec *inst, int64_t B, int /*d*/, const Buc
   for (int64_t i = 0; i < B; ++i) {
     InstPlan &I = L.inst[(size_t)i];
     plan_instance(inst[i], u0, s0, t, I);
+    I.d = (uint32_t)d;
     u0 += inst[i].n;
     s0 += inst[i].m;
     I.blk0 = blk;
@@ -1600,7 +1626,12 @@ hipError_t bucket_prepare(const BucketArgs &a, hipStream_t s) {
   switch (a.d) {
     case 1: prepare_impl<1>(a, s); break;
     case 2: prepare_impl<2>(a, s); break;
-    default: prepare_impl<3>(a, s); break;
+    case 3: prepare_impl<3>(a, s); break;
+    case 4: prepare_impl<4>(a, s); break;
+    case 5: prepare_impl<5>(a, s); break;
+    case 6: prepare_impl<6>(a, s); break;
+    case 7: prepare_impl<7>(a, s); break;
+    default: prepare_impl<8>(a, s); break;
   }
   return hipGetLastError();
 }
@@ -1644,7 +1675,8 @@ hipError_t bucket_sweep(const BucketArgs &a, int mode, int32_t *per_update,
   switch (a.d) {
     case 1: DDM_SWEEP(0) break;
     case 2: DDM_SWEEP(1) break;
-    default: DDM_SWEEP(2) break;
+    case 3: DDM_SWEEP(2) break;
+    default: DDM_SWEEP(3) break;
   }
 #undef DDM_SWEEP
   return hipGetLastError();

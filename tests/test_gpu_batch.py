@@ -159,14 +159,25 @@ def test_batched_overflow_falls_back(ddm, oracle):
     graph.close()
 
 
-def test_batched_high_d_runs_each(ddm, oracle):
-    insts = [W.random_float_boxes(300, 250, 5, seed=s, extent=60.0) for s in range(4)]
+@pytest.mark.parametrize("d", [5, 9])
+def test_batched_high_d(ddm, oracle, d):
+    """d = 5 runs as one bucketed batch and replays as a graph; d = 9, beyond
+    the bucketed path, goes instance by instance and cannot be captured."""
+    insts = [W.random_float_boxes(300, 250, d, seed=s, extent=60.0 if d == 5 else 30.0)
+             for s in range(4)]
     refs = _oracle_all(oracle, insts)
     batch, _ = _device_batch(ddm, insts, "pairs", cap=sum(r[0] for r in refs) + 1)
     _check(batch, insts, refs, "pairs", batch.run())
-    with pytest.raises(ddm.DDMError) as e:
-        batch.graph()
-    assert e.value.code == ddm.DDM_E_UNSUPPORTED
+    if d <= 8:
+        graph = batch.graph()
+        for _ in range(2):
+            graph.launch()
+            _check(batch, insts, refs, "pairs", graph.result())
+        graph.close()
+    else:
+        with pytest.raises(ddm.DDMError) as e:
+            batch.graph()
+        assert e.value.code == ddm.DDM_E_UNSUPPORTED
 
 
 def test_tunings_agree(ddm, oracle):
@@ -281,10 +292,11 @@ def test_closed_batched_and_graph(ddm, oracle, d):
     graph.close()
 
 
-def test_closed_batched_high_d_runs_each(ddm, oracle):
-    """d = 5 goes instance by instance through the single call, which must
-    keep the closed reading."""
-    insts = [W.tie_heavy(300, 250, 5, grid=8, max_len=3, seed=s) for s in range(3)]
+@pytest.mark.parametrize("d", [5, 9])
+def test_closed_batched_high_d(ddm, oracle, d):
+    """d = 5 in one bucketed batch and d = 9 instance by instance through the
+    single call both keep the closed reading."""
+    insts = [W.tie_heavy(300, 250, d, grid=8, max_len=3, seed=s) for s in range(3)]
     refs = _closed_refs(oracle, insts)
     batch = _closed_batch(ddm, insts, "pairs", cap=sum(r[0] for r in refs) + 1)
     _check(batch, insts, refs, "pairs", batch.run())

@@ -79,7 +79,7 @@ def check_all_modes(ddm, oracle, inst, pairs=True, expect_bucketed=None, closed=
             assert np.array_equal(ids.cpu().numpy(), pairs_ref[:, 1]), (inst.name, path)
     ddm.set_path("auto")
     if expect_bucketed is None:
-        expect_bucketed = inst.d <= 3 and inst.n + inst.m > 0
+        expect_bucketed = inst.d <= 8 and inst.n + inst.m > 0
     if expect_bucketed:
         assert served == "bucketed", (inst.name, served)
     return served
@@ -117,11 +117,34 @@ def test_tie_heavy_many_buckets(ddm, oracle, d):
     check_all_modes(ddm, oracle, inst)
 
 
-@pytest.mark.parametrize("d", [1, 2, 3, 5])
+@pytest.mark.parametrize("d", [1, 2, 3, 5, 9])
 def test_random_float_boxes(ddm, oracle, d):
     for seed in range(6):
         check_all_modes(ddm, oracle, W.random_float_boxes(700, 900, d, seed=seed, extent=300.0),
-                        expect_bucketed=d <= 3)
+                        expect_bucketed=d <= 8)
+
+
+@pytest.mark.parametrize("d", [4, 6, 8])
+def test_high_d_bucketed_with_many_matches(ddm, oracle, d):
+    """d = 4 .. 8 on the bucketed path (pre-filter on axes 1 and 2, exact
+    test on every axis), with boxes dense enough that thousands of pairs
+    overlap on all d axes."""
+    for seed in range(3):
+        inst = W.random_float_boxes(2000, 2000, d, seed=seed, extent=40.0)
+        check_all_modes(ddm, oracle, inst, expect_bucketed=True)
+
+
+def test_high_d_full_counts(ddm, oracle):
+    """d = 5, n = m = 5e6, alpha = 30: total and per-update counts on the
+    bucketed path against the oracle."""
+    inst = W.uniform_instance(5_000_000, 5_000_000, 5, 30.0, seed=21)
+    _note(f"{inst.name}")
+    g = _dev(inst)
+    k_ref, per_ref, _ = oracle.sbm(*_host(inst), pairs=False)
+    k, per = ddm.match(*g, mode="per_update")
+    assert ddm.last_path() == "bucketed"
+    assert k == k_ref
+    assert np.array_equal(per.cpu().numpy(), per_ref)
 
 
 @pytest.mark.parametrize("d,alpha", [(1, 100.0), (2, 1.0), (3, 100.0)])
@@ -373,11 +396,11 @@ def test_closed_tie_heavy_many_buckets(ddm, oracle, d):
     check_all_modes(ddm, oracle, inst, closed=True)
 
 
-@pytest.mark.parametrize("d", [1, 2, 3, 5])
+@pytest.mark.parametrize("d", [1, 2, 3, 5, 9])
 def test_closed_random_float_boxes(ddm, oracle, d):
     for seed in range(4):
         inst = W.random_float_boxes(700, 900, d, seed=seed, extent=300.0)
-        check_all_modes(ddm, oracle, inst, expect_bucketed=d <= 3, closed=True)
+        check_all_modes(ddm, oracle, inst, expect_bucketed=d <= 8, closed=True)
 
 
 def test_closed_infinite_and_zero_bounds(ddm, oracle):
