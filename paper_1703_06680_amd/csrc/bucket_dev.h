@@ -11,13 +11,21 @@
 
 namespace ddm {
 
+// Buckets are the cells of a grid: nx columns by the swept axis' lower
+// coordinate, each cut into ny rows by axis 1's lower coordinate (ny = 1:
+// plain slabs of the swept axis).  Cell (column a, row c) is bucket
+// a * ny + c, so a column's cells are consecutive; buckets from nx * ny to
+// nb - 1 stay empty.
 struct BucketParams {
-  float vmin;        // bucket map of the swept axis' lower coordinate
+  float vmin;        // column map of the swept axis' lower coordinate
   float scale;
   uint32_t nb;
   uint32_t valid;
   float qmin[2];     // 16-bit quantisation of the other axes (pre-filter)
   float qscale[2];
+  uint32_t nx, ny;   // columns, rows per column
+  float vmin1;       // row map of axis 1's lower coordinate (ny > 1)
+  float scale1;
 };
 
 // bucket(x) = clamp(floor((x - vmin) * scale), 0, nb - 1): monotone
@@ -34,6 +42,53 @@ struct Box {
   float lo[D];
   float hi[D];
 };
+
+// The grid cells a box overlaps: columns [a0, a1] (of its swept-axis
+// bounds) by rows [c0, c1] (of its axis-1 bounds).  Its record goes to cell
+// (a0, c0); the cells (a0, c) for c > c0 get copies as records (the box is
+// in them from their start on the swept axis); cells of later columns get
+// boundary-state copies.  A pair is found in the cell of its swept-axis
+// order (as with slabs) whose row holds the larger of the two axis-1 lower
+// bounds; both boxes are present in that cell, since the maps are monotone.
+template <int D>
+struct Cells {
+  uint32_t a0, a1, c0, c1;
+};
+
+// Kernels take the per-box work in two forms, chosen once per workgroup:
+// GRID = false for slabs (ny = 1, rows known to be 0 at compile time) and
+// GRID = true for a grid.
+template <bool GRID>
+struct GridTag {
+  static constexpr bool value = GRID;
+};
+
+template <bool GRID>
+__device__ __forceinline__ uint32_t cell_index(uint32_t a, uint32_t c, const BucketParams &p) {
+  return GRID ? a * p.ny + c : a;
+}
+
+// The cell of a box's record and its row: (a0 * ny + c0, c0).
+template <int D, bool GRID>
+__device__ __forceinline__ uint2 home_of(const Box<D> &b, const BucketParams &p) {
+  const uint32_t a = bucket_of(b.lo[0], p.vmin, p.scale, p.nx);
+  uint32_t c = 0u;
+  if (GRID && D >= 2) c = bucket_of(b.lo[1 % D], p.vmin1, p.scale1, p.ny);
+  return make_uint2(cell_index<GRID>(a, c, p), c);
+}
+
+template <int D, bool GRID>
+__device__ __forceinline__ Cells<D> cells_of(const Box<D> &b, const BucketParams &p) {
+  Cells<D> c;
+  c.a0 = bucket_of(b.lo[0], p.vmin, p.scale, p.nx);
+  c.a1 = bucket_of(b.hi[0], p.vmin, p.scale, p.nx);
+  c.c0 = c.c1 = 0u;
+  if (GRID && D >= 2) {
+    c.c0 = bucket_of(b.lo[1 % D], p.vmin1, p.scale1, p.ny);
+    c.c1 = bucket_of(b.hi[1 % D], p.vmin1, p.scale1, p.ny);
+  }
+  return c;
+}
 
 // Error bits and emptiness of one box.  A half-open box with lo == hi on
 // some axis is empty; a closed one never is (lo == hi is a point).
@@ -68,25 +123,41 @@ __device__ __forceinline__ uint32_t quant_hi(float x, float qmin, float qs) {
   return (uint32_t)ceilf(t);
 }
 
-// Word 3 of a region record: the quantised bounds of the other axes.  d = 2:
-// the 16-bit lower | upper << 16 of axis 1; d >= 3: 7-bit bounds of axes 1
-// and 2 (the 16-bit ones scaled by 2^-9, lower rounded down, upper rounded
-// up and capped at 127) lo1 | hi1 << 8 | lo2 << 16 | hi2 << 24; 0 for d = 1.
+// Axis 1 on a grid (ny > 1) is quantised over the record's own row: every
+// record of a cell, copies included, is written for that cell's row, and
+// t = ((x - vmin1) * scale1 - row) * 65535 is as monotone as the map above,
+// so the pre-filter stays conservative while keeping its resolution inside
+// a row (bounds beyond the row clamp to its ends).
+__device__ __forceinline__ uint32_t quant1_lo(float x, const BucketParams &p, uint32_t row) {
+  if (p.ny <= 1) return quant_lo(x, p.qmin[0], p.qscale[0]);
+  float t = ((x - p.vmin1) * p.scale1 - (float)row) * 65535.0f;
+  t = fminf(fmaxf(t, 0.0f), 65535.0f);
+  return (uint32_t)t;
+}
+
+__device__ __forceinline__ uint32_t quant1_hi(float x, const BucketParams &p, uint32_t row) {
+  if (p.ny <= 1) return quant_hi(x, p.qmin[0], p.qscale[0]);
+  float t = ((x - p.vmin1) * p.scale1 - (float)row) * 65535.0f;
+  t = fminf(fmaxf(t, 0.0f), 65535.0f);
+  return (uint32_t)ceilf(t);
+}
+
+// Word 3 of a region record in a cell of grid row ``row``: the quantised
+// bounds of the other axes.  d = 2: the 16-bit lower | upper << 16 of axis
+// 1; d >= 3: 7-bit bounds of axes 1 and 2 (the 16-bit ones scaled by 2^-9,
+// lower rounded down, upper rounded up and capped at 127) lo1 | hi1 << 8 |
+// lo2 << 16 | hi2 << 24; 0 for d = 1.
 template <int D>
-__device__ __forceinline__ uint32_t qword_of(const Box<D> &b, const BucketParams &p) {
-  if (D == 2) {
-    return quant_lo(b.lo[1 % D], p.qmin[0], p.qscale[0]) |
-           (quant_hi(b.hi[1 % D], p.qmin[0], p.qscale[0]) << 16);
-  }
+__device__ __forceinline__ uint32_t qword_of(const Box<D> &b, const BucketParams &p,
+                                             uint32_t row) {
+  if (D == 2)
+    return quant1_lo(b.lo[1 % D], p, row) | (quant1_hi(b.hi[1 % D], p, row) << 16);
   if (D >= 3) {
-    uint32_t w = 0;
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const uint32_t l7 = quant_lo(b.lo[(1 + c) % D], p.qmin[c], p.qscale[c]) >> 9;
-      const uint32_t h7 = min(127u, (quant_hi(b.hi[(1 + c) % D], p.qmin[c], p.qscale[c]) + 511u) >> 9);
-      w |= (l7 | (h7 << 8)) << (16 * c);
-    }
-    return w;
+    const uint32_t l1 = quant1_lo(b.lo[1 % D], p, row) >> 9;
+    const uint32_t h1 = min(127u, (quant1_hi(b.hi[1 % D], p, row) + 511u) >> 9);
+    const uint32_t l2 = quant_lo(b.lo[2 % D], p.qmin[1], p.qscale[1]) >> 9;
+    const uint32_t h2 = min(127u, (quant_hi(b.hi[2 % D], p.qmin[1], p.qscale[1]) + 511u) >> 9);
+    return l1 | (h1 << 8) | (l2 << 16) | (h2 << 24);
   }
   return 0u;
 }
@@ -110,6 +181,11 @@ struct Offsets {
   uint32_t nb;  // buckets over all instances
   const uint32_t *cnt = nullptr, *bs_cnt = nullptr;
   uint32_t cap = 0, bs_slab = 0;
+  // packed layout: every instance's grid, and the record buffer's capacity
+  // (copies into later rows make the records more than the regions; slots
+  // from rec_cap on are not written and the sweep sends the call back)
+  const BucketParams *P = nullptr;
+  uint32_t rec_cap = 0;
   __device__ uint32_t bs_begin(uint32_t j) const { return S[nb + j] - S[nb]; }
 };
 

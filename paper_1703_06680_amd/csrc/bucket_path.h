@@ -7,6 +7,10 @@
 // LDS; the regions of earlier buckets that are still active when a bucket
 // starts (SubSet[p] and UpdSet[p] of Algorithms 5 and 6) are delivered to it
 // as a boundary-state list built by a span count, a prefix sum and a fill.
+// For d >= 2 the plan may also cut every such segment (a column) into rows
+// by axis 1's lower coordinate: boxes reaching later rows of their column are
+// copied there as records, and a pair is counted only in the row of the
+// larger of its two axis-1 lower bounds, so that each is counted once.
 //
 // One launch sequence serves a batch of independent instances stored back to
 // back: every instance has its own buckets, count/scatter blocks and sample
@@ -88,13 +92,14 @@ struct BucketLayout {
   uint32_t max_nb;                     // most buckets of one instance
   uint32_t n_total, m_total;           // updates, subscriptions over the instances
   uint32_t bs_cap;                     // capacity of the boundary-state record buffer
+  uint32_t rec_cap;                    // capacity of the record buffer (even)
   int rec_words;                       // 32-bit words per region record
   BucketTuning tune;
   size_t cells;                        // count-matrix cells over the instances
   size_t bytes;                        // workspace bytes for all buffers below
   // byte offsets inside the bucket workspace
-  size_t params, sample_part, counts, totals, offsets, block_offsets, scan_tmp, bs_cur, rec,
-      bs_rec, plan, maps;
+  size_t params, sample_part, sample_pts, counts, totals, offsets, block_offsets, scan_tmp, bs_cur,
+      rec, bs_rec, plan, maps;
   std::vector<InstPlan> inst;          // host copy of the per-instance plan
 };
 

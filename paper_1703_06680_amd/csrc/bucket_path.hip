@@ -53,6 +53,13 @@ constexpr int kThreads = 1024;                 // count / scatter blocks
 constexpr int kSampleThreads = 256;
 constexpr uint32_t kSampleRows = 8192;         // rows per sample block (at most 256 blocks)
 constexpr uint32_t kMaxSampleBlocks = 256;
+constexpr int kPart = 10;                      // floats per sample block partial
+// Sampled lower corners (swept axis, axis 1) the plan tries a grid on, the
+// plan's workgroup size, and the mean slab walk (entries) from which rows
+// are tried.
+constexpr uint32_t kPlanPoints = 8192;
+constexpr int kPlanThreads = 512;
+constexpr float kGridWalk = 8.0f;
 
 // The sweep workgroup: at most kBucketCap records per bucket with 512 fine
 // bins per kind (256 or 512 threads), or kBigBucketCap records with 1024
@@ -115,6 +122,7 @@ struct Clear {
 template <int D>
 __global__ __launch_bounds__(kSampleThreads) void bk_sample_kernel(View V,
                                                                    float *__restrict__ part,
+                                                                   float2 *__restrict__ pts,
                                                                    Clear clr) {
   {
     const uint32_t tid = blockIdx.x * kSampleThreads + threadIdx.x;
@@ -127,15 +135,16 @@ __global__ __launch_bounds__(kSampleThreads) void bk_sample_kernel(View V,
     if (clr.inst_total)
       for (uint32_t i = tid; i < clr.B; i += stride) clr.inst_total[i] = 0ull;
   }
-  // per block: min/max of the swept lower coordinate, count, and for the
-  // other axes min(lo) / max(hi), over the sampled valid non-empty boxes of
-  // the block's instance
+  // per block, over the sampled valid non-empty boxes of the block's
+  // instance: min/max of the swept lower coordinate (slots 0, 1), count (2),
+  // the sum of the axis-1 extents hi - lo (3), for axes 1 and 2 min(lo) /
+  // max(hi) (4 .. 7) and the sum of the swept-axis extents (8)
   constexpr int W = kSampleThreads / kWave;
-  __shared__ float sred[W][8];
+  __shared__ float sred[W][kPart];
   const InstPlan I = V.get(V.of_smp(blockIdx.x));
   const uint32_t N = I.n + I.m;
   const float inf = __int_as_float(0x7f800000);
-  float v[8] = {inf, -inf, 0.f, 0.f, inf, -inf, inf, -inf};
+  float v[kPart] = {inf, -inf, 0.f, 0.f, inf, -inf, inf, -inf, 0.f, 0.f};
   const uint32_t i = blockIdx.x * kSampleThreads + threadIdx.x;
   const uint32_t r =
       (uint32_t)(((unsigned long long)mix32(i * 0x9E3779B9u + 0x632BE5ABu) * N) >> 32);
@@ -149,6 +158,14 @@ __global__ __launch_bounds__(kSampleThreads) void bk_sample_kernel(View V,
   if (ok) {
     v[0] = v[1] = b.lo[0];
     v[2] = 1.f;
+    if (D >= 2) v[3] = b.hi[1 % D] - b.lo[1 % D];
+    v[8] = b.hi[0] - b.lo[0];
+  }
+  if (D >= 2) {  // the sampled lower corner on the swept axis and axis 1, for the plan
+    const float nan = __int_as_float(0x7fc00000);
+    pts[i] = ok ? make_float2(b.lo[0], b.lo[1 % D]) : make_float2(nan, nan);
+  }
+  if (ok) {
 #pragma unroll
     for (int k = 1; k < (D < 3 ? D : 3); ++k) {  // the quantised axes 1 and 2
       v[4 + 2 * (k - 1)] = b.lo[k];
@@ -157,15 +174,17 @@ __global__ __launch_bounds__(kSampleThreads) void bk_sample_kernel(View V,
   }
 #pragma unroll
   for (int k = 0; k < 8; k += 2) {
-    if (k == 2) continue;  // slot 2 is the sample count, summed below
+    if (k == 2) continue;  // slots 2 and 3 are sums, below
     v[k] = wave_min(v[k]);
     v[k + 1] = wave_max(v[k + 1]);
   }
   v[2] = wave_sum(v[2]);
+  v[3] = wave_sum(v[3]);
+  v[8] = wave_sum(v[8]);
   const int w = threadIdx.x / kWave;
   if (lane_id() == 0)
 #pragma unroll
-    for (int k = 0; k < 8; ++k) sred[w][k] = v[k];
+    for (int k = 0; k < kPart; ++k) sred[w][k] = v[k];
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int j = 1; j < W; ++j)
@@ -175,26 +194,34 @@ __global__ __launch_bounds__(kSampleThreads) void bk_sample_kernel(View V,
         v[k] = fminf(v[k], sred[j][k]);
         v[k + 1] = fmaxf(v[k + 1], sred[j][k + 1]);
       }
-    float c = 0.f;
-    for (int j = 0; j < W; ++j) c += sred[j][2];
+    float c = 0.f, e = 0.f, e0 = 0.f;
+    for (int j = 0; j < W; ++j) {
+      c += sred[j][2];
+      e += sred[j][3];
+      e0 += sred[j][8];
+    }
     v[2] = c;
+    v[3] = e;
+    v[8] = e0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) part[blockIdx.x * 8 + k] = v[k];
+    for (int k = 0; k < kPart; ++k) part[blockIdx.x * kPart + k] = v[k];
   }
 }
 
 // The bucket map and quantisation parameters of instance I, reduced by the
-// whole workgroup from the instance's sample partials (every workgroup of
-// the count and scatter passes computes the same values: min, max and a sum
-// of small integers do not depend on the order of reduction).
+// whole workgroup from the instance's sample partials: out[0] the slab map
+// (nx = nb columns, one row), out[1] a grid of ny > 1 rows by axis 1 to try
+// (out[1].ny = 1: none).  The grid's cells are about as long on axis 1 as
+// on the swept axis, and its rows are at least eight mean axis-1 extents
+// high, so that copies into later rows stay rare.
 template <int THREADS>
-__device__ BucketParams block_plan(const float *__restrict__ part, const InstPlan &I,
-                                   float (*sred)[8], BucketParams *shared_out) {
+__device__ void block_plan(const float *__restrict__ part, const InstPlan &I, bool grid,
+                           float (*sred)[kPart], BucketParams *out) {
   constexpr int W = THREADS / kWave;
   const float inf = __int_as_float(0x7f800000);
-  float v[8] = {inf, -inf, 0.f, 0.f, inf, -inf, inf, -inf};
+  float v[kPart] = {inf, -inf, 0.f, 0.f, inf, -inf, inf, -inf, 0.f, 0.f};
   for (uint32_t i = threadIdx.x; i < I.nsmp; i += THREADS) {
-    const float *pp = part + (size_t)(I.smp0 + i) * 8;
+    const float *pp = part + (size_t)(I.smp0 + i) * kPart;
 #pragma unroll
     for (int k = 0; k < 8; k += 2) {
       if (k == 2) continue;
@@ -202,20 +229,25 @@ __device__ BucketParams block_plan(const float *__restrict__ part, const InstPla
       v[k + 1] = fmaxf(v[k + 1], pp[k + 1]);
     }
     v[2] += pp[2];
+    v[3] += pp[3];
+    v[8] += pp[8];
   }
 #pragma unroll
   for (int k = 0; k < 8; k += 2) {
-    if (k == 2) continue;  // slot 2 is the sample count, summed below
+    if (k == 2) continue;  // slots 2 and 3 are sums, below
     v[k] = wave_min(v[k]);
     v[k + 1] = wave_max(v[k + 1]);
   }
   v[2] = wave_sum(v[2]);
+  v[3] = wave_sum(v[3]);
+  v[8] = wave_sum(v[8]);
   const int w = threadIdx.x / kWave;
   if (lane_id() == 0)
 #pragma unroll
-    for (int k = 0; k < 8; ++k) sred[w][k] = v[k];
+    for (int k = 0; k < kPart; ++k) sred[w][k] = v[k];
   __syncthreads();
   if (threadIdx.x == 0) {
+#pragma unroll 1
     for (int j = 1; j < W; ++j)
 #pragma unroll
       for (int k = 0; k < 8; k += 2) {
@@ -223,26 +255,22 @@ __device__ BucketParams block_plan(const float *__restrict__ part, const InstPla
         v[k] = fminf(v[k], sred[j][k]);
         v[k + 1] = fmaxf(v[k + 1], sred[j][k + 1]);
       }
-    float c = 0.f;
-    for (int j = 0; j < W; ++j) c += sred[j][2];
+    float c = 0.f, ext = 0.f, ext0 = 0.f;
+#pragma unroll 1
+    for (int j = 0; j < W; ++j) {
+      c += sred[j][2];
+      ext += sred[j][3];
+      ext0 += sred[j][8];
+    }
     BucketParams q;
     q.nb = I.nb;
     q.vmin = 0.f;
     q.scale = 0.f;
     q.valid = 0;
-    if (c > 0.f && v[1] > v[0] && I.nb > 0) {
-      // the sample's extremes lie about (max - min) / c inside the true ones;
-      // widening the map by two such gaps keeps the regions beyond them from
-      // piling into the first and last bucket
-      const float gap = 2.0f * (v[1] - v[0]) / c;
-      const float lo = v[0] - gap, hi = v[1] + gap;
-      const float scale = (float)I.nb / (hi - lo);
-      if (scale > 0.f && scale <= 3.0e38f && lo > -3.0e38f && hi < 3.0e38f) {
-        q.vmin = lo;
-        q.scale = scale;
-        q.valid = 1;
-      }
-    }
+    q.nx = I.nb;
+    q.ny = 1;
+    q.vmin1 = 0.f;
+    q.scale1 = 0.f;
     for (int k = 0; k < 2; ++k) {
       const float lo = v[4 + 2 * k], hi = v[5 + 2 * k];
       q.qmin[k] = 0.f;
@@ -255,20 +283,110 @@ __device__ BucketParams block_plan(const float *__restrict__ part, const InstPla
         }
       }
     }
-    *shared_out = q;
+    BucketParams g = q;
+    if (c > 0.f && v[1] > v[0] && I.nb > 0) {
+      // the sample's extremes lie about (max - min) / c inside the true ones;
+      // widening the map by two such gaps keeps the regions beyond them from
+      // piling into the first and last bucket
+      const float gap = 2.0f * (v[1] - v[0]) / c;
+      const float lo = v[0] - gap, hi = v[1] + gap;
+      const float scale = (float)I.nb / (hi - lo);
+      if (scale > 0.f && scale <= 3.0e38f && lo > -3.0e38f && hi < 3.0e38f) {
+        q.vmin = lo;
+        q.scale = scale;
+        q.valid = 1;
+      }
+      // a walk in a slab meets about N * ext0 / (2 (hi - lo)) entries of the
+      // other kind (ext0 the mean swept-axis extent); rows pay for their
+      // extra plan, count and copy work only when that is several
+      const float walk = (float)(I.n + I.m) * (ext0 / c) / (2.0f * (hi - lo));
+      if (q.valid && grid && I.d >= 2 && I.nb >= 4 && v[5] > v[4] && walk >= kGridWalk) {
+        const float gap1 = 2.0f * (v[5] - v[4]) / c;
+        const float lo1 = v[4] - gap1, hi1 = v[5] + gap1;
+        float t = sqrtf((float)I.nb * ((hi1 - lo1) / (hi - lo)));
+        if (ext > 0.f) t = fminf(t, (hi1 - lo1) / (8.0f * (ext / c)));
+        if (t >= 2.0f) {  // false for NaN
+          const uint32_t ny = (uint32_t)fminf(t, (float)I.nb / 2.0f);
+          const uint32_t nx = I.nb / ny;
+          const float s0 = (float)nx / (hi - lo), s1 = (float)ny / (hi1 - lo1);
+          if (ny >= 2 && s0 > 0.f && s0 <= 3.0e38f && s1 > 0.f && s1 <= 3.0e38f &&
+              lo1 > -3.0e38f && hi1 < 3.0e38f) {
+            g = q;
+            g.scale = s0;
+            g.nx = nx;
+            g.ny = ny;
+            g.vmin1 = lo1;
+            g.scale1 = s1;
+          }
+        }
+      }
+    }
+    out[0] = q;
+    out[1] = g;
   }
   __syncthreads();
-  return *shared_out;
 }
 
+
 // One workgroup per instance: its bucket map and quantisation parameters.
-__global__ __launch_bounds__(kSampleThreads) void bk_plan_kernel(const float *__restrict__ part,
-                                                                 View V,
-                                                                 BucketParams *__restrict__ P) {
-  __shared__ float sred[kSampleThreads / kWave][8];
-  __shared__ BucketParams shp;
-  const BucketParams q = block_plan<kSampleThreads>(part, V.get(blockIdx.x), sred, &shp);
-  if (threadIdx.x == 0) P[blockIdx.x] = q;
+// A grid (grid != 0, d >= 2) is kept if the sampled corners' sum of squared
+// cell counts, which grows as they crowd into fewer cells, is at most 5/4 of
+// the slab map's: inputs whose axis-1 corners follow their swept-axis ones
+// (which fill only a diagonal of the grid) keep the slabs.  LDS: 2 nb words
+// with grid != 0.
+__global__ __launch_bounds__(kPlanThreads) void bk_plan_kernel(const float *__restrict__ part,
+                                                               const float2 *__restrict__ pts,
+                                                               View V,
+                                                               BucketParams *__restrict__ P,
+                                                               uint32_t grid) {
+  __shared__ float sred[kPlanThreads / kWave][kPart];
+  __shared__ BucketParams shp[2];
+  __shared__ unsigned long long ssq[2];
+  extern __shared__ uint32_t hist[];
+  const InstPlan I = V.get(blockIdx.x);
+  const uint32_t t = threadIdx.x;
+  // the sampled corners, loaded before the partials are reduced
+  constexpr int U = (int)(kPlanPoints / kPlanThreads);
+  const uint32_t cnt = min(I.nsmp * (uint32_t)kSampleThreads, kPlanPoints);
+  const float2 *pp = pts + (size_t)I.smp0 * kSampleThreads;
+  float2 x[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const uint32_t i = (uint32_t)u * kPlanThreads + t;
+    x[u] = grid && i < cnt ? pp[i] : make_float2(__int_as_float(0x7fc00000), 0.f);
+  }
+  block_plan<kPlanThreads>(part, I, grid != 0u, sred, shp);
+  const BucketParams &q = shp[0], &g = shp[1];
+  bool use_grid = false;
+  if (g.ny > 1) {  // uniform over the workgroup
+    const uint32_t nb = I.nb;
+    for (uint32_t k = t; k < 2 * nb; k += kPlanThreads) hist[k] = 0u;
+    if (t < 2) ssq[t] = 0ull;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (x[u].x != x[u].x) continue;  // no valid box was sampled there
+      atomicAdd(&hist[bucket_of(x[u].x, q.vmin, q.scale, nb)], 1u);
+      const uint32_t a = bucket_of(x[u].x, g.vmin, g.scale, g.nx);
+      const uint32_t c = bucket_of(x[u].y, g.vmin1, g.scale1, g.ny);
+      atomicAdd(&hist[nb + a * g.ny + c], 1u);
+    }
+    __syncthreads();
+    unsigned long long s1 = 0, s2 = 0;
+    for (uint32_t k = t; k < nb; k += kPlanThreads) {
+      s1 += (unsigned long long)hist[k] * hist[k];
+      s2 += (unsigned long long)hist[nb + k] * hist[nb + k];
+    }
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    if (lane_id() == 0) {
+      atomicAdd(&ssq[0], s1);
+      atomicAdd(&ssq[1], s2);
+    }
+    __syncthreads();
+    use_grid = 4ull * ssq[1] <= 5ull * ssq[0];
+  }
+  if (t == 0) P[blockIdx.x] = shp[use_grid ? 1 : 0];
 }
 
 // ------------------------------------------------------ row groups
@@ -351,23 +469,32 @@ __global__ __launch_bounds__(kThreads) void bk_count_kernel(
   __syncthreads();
   const uint32_t g0 = lb * I.gpb, g1 = min(I.g, g0 + I.gpb);
   uint32_t err = 0;
+  auto count = [&](auto tag) {
+    constexpr bool GR = decltype(tag)::value;
 #pragma unroll 2
-  for (uint32_t g = g0 + threadIdx.x; g < g1; g += kThreads) {
-    const Group q = group_of(g, I, n_total);
-    Box<D> bx[4];
-    load_group<D>(q, I.vec != 0, bx);
+    for (uint32_t g = g0 + threadIdx.x; g < g1; g += kThreads) {
+      const Group q = group_of(g, I, n_total);
+      Box<D> bx[4];
+      load_group<D>(q, I.vec != 0, bx);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      if ((uint32_t)r >= q.rows) continue;
-      bool empty;
-      err |= box_errors<D>(bx[r], empty, I.closed);
-      if (empty) continue;
-      const uint32_t b = bucket_of(bx[r].lo[0], p.vmin, p.scale, nb);
-      atomicAdd(&hist[b], 1u);
-      const uint32_t last = bucket_of(bx[r].hi[0], p.vmin, p.scale, nb);
-      for (uint32_t j = b + 1; j <= last; ++j) atomicAdd(&bs_size[I.b0 + j], 1u);
+      for (int r = 0; r < 4; ++r) {
+        if ((uint32_t)r >= q.rows) continue;
+        bool empty;
+        err |= box_errors<D>(bx[r], empty, I.closed);
+        if (empty) continue;
+        const Cells<D> c = cells_of<D, GR>(bx[r], p);
+        atomicAdd(&hist[cell_index<GR>(c.a0, c.c0, p)], 1u);
+        for (uint32_t y = c.c0 + 1; y <= c.c1; ++y) atomicAdd(&hist[cell_index<GR>(c.a0, y, p)], 1u);
+        for (uint32_t a = c.a0 + 1; a <= c.a1; ++a)
+          for (uint32_t y = c.c0; y <= c.c1; ++y)
+            atomicAdd(&bs_size[I.b0 + cell_index<GR>(a, y, p)], 1u);
+      }
     }
-  }
+  };
+  if (D >= 2 && p.ny > 1)  // uniform
+    count(GridTag<true>{});
+  else
+    count(GridTag<false>{});
   __syncthreads();
   uint32_t *row = C + I.cell0 + (size_t)lb * nb;
   for (uint32_t b = threadIdx.x; b < nb; b += kThreads) row[b] = hist[b];
@@ -425,9 +552,25 @@ __global__ __launch_bounds__(kColWaves * kWave) void bk_colscan_kernel(
 // (updates first), 3 = quantised bounds of the other axes (qword_of).
 template <int D>
 __device__ __forceinline__ void write_record(uint32_t *__restrict__ dst, const Box<D> &b,
-                                             uint32_t r, const BucketParams &p, uint32_t closed) {
-  *reinterpret_cast<uint4 *>(dst) =
-      make_uint4(encode_coord(b.lo[0]), encode_coord(b.hi[0]) + closed, r, qword_of<D>(b, p));
+                                             uint32_t r, const BucketParams &p, uint32_t closed,
+                                             uint32_t row) {
+  *reinterpret_cast<uint4 *>(dst) = make_uint4(encode_coord(b.lo[0]), encode_coord(b.hi[0]) + closed,
+                                               r, qword_of<D>(b, p, row));
+}
+
+// Boundary-state copies of a box into the cells of the columns after its
+// own that it overlaps, at positions handed out by the cells' cursors.
+template <int D, bool GRID>
+__device__ __forceinline__ void bs_copies(const Cells<D> &c, const Box<D> &b, uint32_t rid,
+                                          const BucketParams &p, const InstPlan &I,
+                                          const Offsets &O, uint32_t *__restrict__ bs_cur,
+                                          uint32_t bs_cap, uint32_t *__restrict__ bs_rec) {
+  for (uint32_t a = c.a0 + 1; a <= c.a1; ++a)
+    for (uint32_t y = c.c0; y <= c.c1; ++y) {
+      const uint32_t jg = I.b0 + cell_index<GRID>(a, y, p);
+      const uint32_t pos = O.bs_begin(jg) + atomicAdd(&bs_cur[jg], 1u);
+      if (pos < bs_cap) write_record<D>(bs_rec + (size_t)pos * 4, b, rid, p, I.closed, y);
+    }
 }
 
 template <int D>
@@ -457,15 +600,13 @@ __global__ __launch_bounds__(kThreads) void bk_scatter_kernel(
       bool empty;
       (void)box_errors<D>(bx[r], empty, I.closed);
       if (empty) continue;
-      const uint32_t b = bucket_of(bx[r].lo[0], p.vmin, p.scale, nb);
-      const uint32_t slot = atomicAdd(&cur[b], 1u);
-      write_record<D>(rec + (size_t)slot * RW, bx[r], q.r0 + r, p, I.closed);
-      const uint32_t last = bucket_of(bx[r].hi[0], p.vmin, p.scale, nb);
-      for (uint32_t j = b + 1; j <= last; ++j) {
-        const uint32_t jg = I.b0 + j;
-        const uint32_t pos = O.bs_begin(jg) + atomicAdd(&bs_cur[jg], 1u);
-        if (pos < bs_cap) write_record<D>(bs_rec + (size_t)pos * RW, bx[r], q.r0 + r, p, I.closed);
+      const Cells<D> c = cells_of<D, true>(bx[r], p);
+      for (uint32_t y = c.c0; y == c.c0 || y <= c.c1; ++y) {  // its own cell, then later rows
+        const uint32_t slot = atomicAdd(&cur[c.a0 * p.ny + y], 1u);
+        if (slot < O.rec_cap)
+          write_record<D>(rec + (size_t)slot * RW, bx[r], q.r0 + r, p, I.closed, y);
       }
+      bs_copies<D, true>(c, bx[r], q.r0 + r, p, I, O, bs_cur, bs_cap, bs_rec);
     }
   }
 }
@@ -506,71 +647,82 @@ __global__ __launch_bounds__(kThreads) void bk_scatter_pair_kernel(
   __syncthreads();
   const uint32_t g0 = lb * I.gpb, g1 = min(I.g, g0 + I.gpb);
   constexpr int G = D <= 3 ? kPairGroups : 1;  // wider rows: one group per round
-  for (uint32_t base = g0; base < g1; base += G * kThreads) {  // uniform
-    Group q[G];
-    Box<D> bx[G][4];
+  auto rounds = [&](auto mode) {
+    constexpr bool GR = decltype(mode)::value;
+    for (uint32_t base = g0; base < g1; base += G * kThreads) {  // uniform
+      Group q[G];
+      Box<D> bx[G][4];
 #pragma unroll
-    for (int k = 0; k < G; ++k) {
-      const uint32_t g = base + (uint32_t)k * kThreads + threadIdx.x;
-      q[k] = Group{};
-      if (g < g1) {
-        q[k] = group_of(g, I, n_total);
-        load_group<D>(q[k], I.vec != 0, bx[k]);
+      for (int k = 0; k < G; ++k) {
+        const uint32_t g = base + (uint32_t)k * kThreads + threadIdx.x;
+        q[k] = Group{};
+        if (g < g1) {
+          q[k] = group_of(g, I, n_total);
+          load_group<D>(q[k], I.vec != 0, bx[k]);
+        }
       }
-    }
-    uint32_t slot[G][4];  // odd slots still to collect, else ~0u
+      uint32_t slot[G][4];  // odd slots still to collect, else ~0u
 #pragma unroll
-    for (int k = 0; k < G; ++k)
+      for (int k = 0; k < G; ++k)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        slot[k][r] = ~0u;
-        if ((uint32_t)r >= q[k].rows) continue;
-        bool empty;
-        (void)box_errors<D>(bx[k][r], empty, I.closed);
-        if (empty) continue;
-        const uint32_t rid = q[k].r0 + r;
-        const uint32_t b = bucket_of(bx[k][r].lo[0], p.vmin, p.scale, nb);
-        const uint32_t s = atomicAdd(&cur[b], 1u);
-        bool alone = true;
-        if ((s & 1u) == 0u) {
-          if (atomicCAS(&tag[b], kTagFree, s >> 1) == kTagFree) {
-            stash[b] = make_uint4(encode_coord(bx[k][r].lo[0]),
-                                  encode_coord(bx[k][r].hi[0]) + I.closed, rid,
-                                  qword_of<D>(bx[k][r], p));
+        for (int r = 0; r < 4; ++r) {
+          slot[k][r] = ~0u;
+          if ((uint32_t)r >= q[k].rows) continue;
+          bool empty;
+          (void)box_errors<D>(bx[k][r], empty, I.closed);
+          if (empty) continue;
+          const uint32_t rid = q[k].r0 + r;
+          const Cells<D> c = cells_of<D, GR>(bx[k][r], p);
+          const uint32_t b = cell_index<GR>(c.a0, c.c0, p);
+          const uint32_t s = atomicAdd(&cur[b], 1u);
+          bool alone = true;
+          if ((s & 1u) == 0u) {
+            if (atomicCAS(&tag[b], kTagFree, s >> 1) == kTagFree) {
+              stash[b] = make_uint4(encode_coord(bx[k][r].lo[0]),
+                                    encode_coord(bx[k][r].hi[0]) + I.closed, rid,
+                                    qword_of<D>(bx[k][r], p, c.c0));
+              alone = false;
+            }
+          } else {
+            slot[k][r] = s;
             alone = false;
           }
-        } else {
-          slot[k][r] = s;
-          alone = false;
+          if (alone && s < O.rec_cap)
+            write_record<D>(rec + (size_t)s * RW, bx[k][r], rid, p, I.closed, c.c0);
+          for (uint32_t y = c.c0 + 1; y <= c.c1; ++y) {  // copies into later rows, alone
+            const uint32_t sy = atomicAdd(&cur[cell_index<GR>(c.a0, y, p)], 1u);
+            if (sy < O.rec_cap) write_record<D>(rec + (size_t)sy * RW, bx[k][r], rid, p, I.closed, y);
+          }
+          bs_copies<D, GR>(c, bx[k][r], rid, p, I, O, bs_cur, bs_cap, bs_rec);
         }
-        if (alone) write_record<D>(rec + (size_t)s * RW, bx[k][r], rid, p, I.closed);
-        const uint32_t last = bucket_of(bx[k][r].hi[0], p.vmin, p.scale, nb);
-        for (uint32_t j = b + 1; j <= last; ++j) {
-          const uint32_t jg = I.b0 + j;
-          const uint32_t pos = O.bs_begin(jg) + atomicAdd(&bs_cur[jg], 1u);
-          if (pos < bs_cap) write_record<D>(bs_rec + (size_t)pos * RW, bx[k][r], rid, p, I.closed);
-        }
-      }
-    __syncthreads();  // every offer of this round is in its mailbox
+      __syncthreads();  // every offer of this round is in its mailbox
 #pragma unroll
-    for (int k = 0; k < G; ++k)
+      for (int k = 0; k < G; ++k)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const uint32_t s = slot[k][r];
-        if (s == ~0u) continue;
-        const uint32_t rid = q[k].r0 + r;
-        const uint32_t b = bucket_of(bx[k][r].lo[0], p.vmin, p.scale, nb);
-        if (tag[b] == (s >> 1)) {
-          const uint4 even = stash[b];
-          tag[b] = kTagFree;
-          *reinterpret_cast<uint4 *>(rec + (size_t)(s - 1) * RW) = even;
+        for (int r = 0; r < 4; ++r) {
+          const uint32_t s = slot[k][r];
+          if (s == ~0u) continue;
+          const uint32_t rid = q[k].r0 + r;
+          const uint2 h = home_of<D, GR>(bx[k][r], p);
+          const uint32_t b = h.x;
+          const bool in = s < O.rec_cap;  // rec_cap is even: so is the pair's first slot
+          if (tag[b] == (s >> 1)) {
+            const uint4 even = stash[b];
+            tag[b] = kTagFree;
+            if (in) *reinterpret_cast<uint4 *>(rec + (size_t)(s - 1) * RW) = even;
+          }
+          if (in) write_record<D>(rec + (size_t)s * RW, bx[k][r], rid, p, I.closed, h.y);
         }
-        write_record<D>(rec + (size_t)s * RW, bx[k][r], rid, p, I.closed);
-      }
-    __syncthreads();  // mailboxes are settled before the next round's offers
-  }
+      __syncthreads();  // mailboxes are settled before the next round's offers
+    }
+  };
+  if (D >= 2 && p.ny > 1)  // uniform
+    rounds(GridTag<true>{});
+  else
+    rounds(GridTag<false>{});
   for (uint32_t b = threadIdx.x; b < nb; b += kThreads)  // offers without a partner here
-    if (tag[b] != kTagFree) *reinterpret_cast<uint4 *>(rec + (size_t)tag[b] * 2 * RW) = stash[b];
+    if (tag[b] != kTagFree && tag[b] < O.rec_cap / 2)
+      *reinterpret_cast<uint4 *>(rec + (size_t)tag[b] * 2 * RW) = stash[b];
 }
 
 // Slab layout of a single instance (a resident simulation): every region
@@ -761,7 +913,21 @@ struct SweepCtx {
   // the emitting pass), or null
   uint32_t *dl;
   uint32_t *own;
+  // the bucket's grid (null for slabs of a resident simulation) and its
+  // index within the instance: in a grid of ny > 1 rows a pair counts here
+  // only if the larger of its two axis-1 lower bounds falls in this cell's
+  // row (both regions are also present in the cells of later rows they both
+  // reach).  Read only for pairs that pass the exact test.
+  const BucketParams *grid = nullptr;
+  uint32_t cell = 0;
 };
+
+// The row test of a pair whose axis-1 lower bounds are ly and lx.
+__device__ __forceinline__ bool in_row(const SweepCtx &o, float ly, float lx) {
+  if (!o.grid) return true;
+  const BucketParams &g = *o.grid;
+  return g.ny <= 1 || bucket_of(fmaxf(ly, lx), g.vmin1, g.scale1, g.ny) == o.cell % g.ny;
+}
 
 // DM1 is d - 1 for d <= 3; DM1 = 3 stands for every d >= 4, whose records
 // and pre-filter are those of d = 3 (axes 1 and 2) and whose exact test also
@@ -825,7 +991,7 @@ __device__ __forceinline__ void visit(const Walker<DM1> &y, bool &have_y, float 
     for (int c = 0; c < kNearAxes<DM1>; ++c)
       hit = hit && before(ylo[c], xhi[c], o.I.closed) && before(xlo[c], yhi[c], o.I.closed);
     if (DM1 == 3 && hit) hit = extra_axes(o, y.rid, rx);
-    if (!hit) return;
+    if (!hit || !in_row(o, ylo[0], xlo[0])) return;
   }
   ++hits;
   if (MODE == 1) {
@@ -871,7 +1037,7 @@ __device__ __forceinline__ void resolve(uint32_t ry, uint32_t rx, unsigned long 
   for (int c = 0; c < kNearAxes<DM1>; ++c)
     hit = hit && before(ylo[c], xhi[c], o.I.closed) && before(xlo[c], yhi[c], o.I.closed);
   if (DM1 == 3 && hit) hit = extra_axes(o, ry, rx);
-  if (!hit) return;
+  if (!hit || !in_row(o, ylo[0], xlo[0])) return;
   ++hits;
   const uint32_t uu = ry < o.n ? ry : rx, ss = ry < o.n ? rx : ry;
   if (MODE == 1) {
@@ -1166,14 +1332,18 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
     C = O.S[b + 1] - start;
     bs_begin = O.bs_begin(b);
     nbs = O.bs_begin(b + 1) - bs_begin;
-    fits = O.bs_begin(O.nb) <= bs_cap && C <= (uint32_t)CAP;
+    fits = O.bs_begin(O.nb) <= bs_cap && C <= (uint32_t)CAP && start + C <= O.rec_cap;
   }
   if (!fits) {  // uniform: the host falls back
     if (threadIdx.x == 0) atomicOr(&hdr->pad[0], 1u);
     return;
   }
   const int t = threadIdx.x;
-  const SweepCtx o{I, n, per_update, pair_off, cursor, out_u, out_s, queue, &queued, DL, own_cnt};
+  SweepCtx o{I, n, per_update, pair_off, cursor, out_u, out_s, queue, &queued, DL, own_cnt};
+  if (DM1 > 0 && !SLAB && O.P) {
+    o.grid = O.P + inst;
+    o.cell = b - I.b0;
+  }
 
   // 1. records into registers (slot s = t + i * THREADS); value range
   uint4 rk[ITEMS];
@@ -1360,6 +1530,7 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
 struct Ptrs {
   BucketParams *P;
   float *part;
+  float2 *pts;
   uint32_t *C, *T, *S, *SB, *bs_cur, *rec, *bs_rec;
   void *scan_tmp;
   Offsets O;
@@ -1372,6 +1543,7 @@ Ptrs pointers(const BucketArgs &a) {
   Ptrs p;
   p.P = reinterpret_cast<BucketParams *>(ws + L.params);
   p.part = reinterpret_cast<float *>(ws + L.sample_part);
+  p.pts = reinterpret_cast<float2 *>(ws + L.sample_pts);
   p.C = reinterpret_cast<uint32_t *>(ws + L.counts);
   p.T = reinterpret_cast<uint32_t *>(ws + L.totals);
   p.S = reinterpret_cast<uint32_t *>(ws + L.offsets);
@@ -1382,6 +1554,8 @@ Ptrs pointers(const BucketArgs &a) {
   p.scan_tmp = ws + L.scan_tmp;
   p.O.S = p.S;
   p.O.nb = L.nb;
+  p.O.P = p.P;
+  p.O.rec_cap = L.rec_cap;
   p.V = View{};
   if (L.B == 1) {
     p.V.plan = nullptr;
@@ -1405,8 +1579,9 @@ void prepare_impl(const BucketArgs &a, hipStream_t s) {
   const size_t lds = (size_t)L.max_nb * sizeof(uint32_t);
   prof::mark(s, "bucket.sample");
   const Clear clr{a.hdr, p.T + L.nb, p.bs_cur, L.nb, a.inst_total, L.B};
-  bk_sample_kernel<D><<<L.nsmp, kSampleThreads, 0, s>>>(p.V, p.part, clr);
-  bk_plan_kernel<<<L.B, kSampleThreads, 0, s>>>(p.part, p.V, p.P);
+  bk_sample_kernel<D><<<L.nsmp, kSampleThreads, 0, s>>>(p.V, p.part, p.pts, clr);
+  const uint32_t grid = D >= 2 ? 1u : 0u;
+  bk_plan_kernel<<<L.B, kPlanThreads, grid ? 2 * lds : 0, s>>>(p.part, p.pts, p.V, p.P, grid);
   prof::mark(s, "bucket.count");
   bk_count_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.C, p.T + L.nb, a.hdr,
                                                    a.zero, a.zero ? a.zero_count : 0u);
@@ -1449,8 +1624,8 @@ void build_slabs_impl(const BucketArgs &a, const SlabBuild &sb, hipStream_t s) {
   Ptrs p = pointers(a);
   const size_t lds = (size_t)L.max_nb * sizeof(uint32_t);
   const Clear clr{a.hdr, p.T + L.nb, p.bs_cur, L.nb, nullptr, L.B};
-  bk_sample_kernel<D><<<L.nsmp, kSampleThreads, 0, s>>>(p.V, p.part, clr);
-  bk_plan_kernel<<<L.B, kSampleThreads, 0, s>>>(p.part, p.V, p.P);
+  bk_sample_kernel<D><<<L.nsmp, kSampleThreads, 0, s>>>(p.V, p.part, p.pts, clr);
+  bk_plan_kernel<<<L.B, kPlanThreads, 0, s>>>(p.part, p.pts, p.V, p.P, 0u);  // slabs only
   bk_count_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.C, p.T + L.nb, a.hdr,
                                                    nullptr, 0u);
   bk_colscan_kernel<<<(L.nb + kColBuckets - 1) / kColBuckets, kColWaves * kWave, 0, s>>>(
@@ -1570,6 +1745,10 @@ BucketLayout bucket_layout(const InstSpec *inst, int64_t B, int d, const BucketT
   L.m_total = (uint32_t)s0;
   const uint64_t N = (uint64_t)L.n_total + L.m_total;
   L.bs_cap = (uint32_t)(N / 2 + 4096);
+  // d >= 2: room for copies into later grid rows (the plan keeps them to
+  // about an eighth of the regions); the sweep sends the call back if they
+  // are more
+  L.rec_cap = (uint32_t)(d >= 2 ? (N + N / 4 + 4096) & ~(uint64_t)1 : (N + 1) & ~(uint64_t)1);
   L.rec_words = 4;
   size_t at = 0;
   auto take = [&](size_t bytes) {
@@ -1579,14 +1758,15 @@ BucketLayout bucket_layout(const InstSpec *inst, int64_t B, int d, const BucketT
   };
   const size_t scanned = 2 * (size_t)L.nb + 1;  // bucket sizes + boundary-state sizes + 0
   L.params = take((size_t)B * sizeof(BucketParams));
-  L.sample_part = take((size_t)std::max<uint32_t>(L.nsmp, 1) * 8 * sizeof(float));
+  L.sample_part = take((size_t)std::max<uint32_t>(L.nsmp, 1) * kPart * sizeof(float));
+  L.sample_pts = take((size_t)std::max<uint32_t>(L.nsmp, 1) * kSampleThreads * 2 * sizeof(float));
   L.counts = take(cell * sizeof(uint32_t));
   L.totals = take(scanned * sizeof(uint32_t));
   L.offsets = take(scanned * sizeof(uint32_t));
   L.block_offsets = take(cell * sizeof(uint32_t));
   L.scan_tmp = take(scan_temp_bytes(scanned));
   L.bs_cur = take((size_t)std::max<uint32_t>(L.nb, 1) * sizeof(uint32_t));
-  L.rec = take((size_t)N * L.rec_words * sizeof(uint32_t));
+  L.rec = take((size_t)L.rec_cap * L.rec_words * sizeof(uint32_t));
   L.bs_rec = take((size_t)L.bs_cap * L.rec_words * sizeof(uint32_t));
   L.plan = take(B > 1 ? (size_t)B * sizeof(InstPlan) : 0);
   L.maps = take(B > 1 ? ((size_t)L.nblk + L.nsmp + L.nb) * sizeof(uint32_t) : 0);

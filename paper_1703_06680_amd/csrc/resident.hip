@@ -96,7 +96,7 @@ template <int D>
 __device__ __forceinline__ uint4 res_record(const Box<D> &b, uint32_t id, uint32_t g,
                                             const ResDev &a, const BucketParams &p) {
   return make_uint4(encode_coord(b.lo[0]), encode_coord(b.hi[0]), id < a.n ? g : a.nv + g,
-                    qword_of<D>(b, p));
+                    qword_of<D>(b, p, 0u));
 }
 
 // Copies of the record into the boundary state of every later bucket the

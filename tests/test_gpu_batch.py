@@ -74,6 +74,30 @@ def test_batched_matches_oracle(ddm, oracle, d, mode):
     _check(batch, insts, refs, mode, total)
 
 
+@pytest.mark.parametrize("mode", ["per_update", "pairs"])
+def test_batched_grid_and_slab_instances(ddm, oracle, mode):
+    """Instances cut into grid rows (long swept-axis walks) beside slab ones
+    and a tie-heavy lattice, in one batch and in a graph replayed twice."""
+    insts = [W.uniform_instance(20_000, 15_000, 2, 40.0, seed=s) for s in range(3)]
+    insts += [W.uniform_instance(5_000, 6_000, 2, 1.0, seed=4),
+              W.tie_heavy(12_000, 12_000, 2, grid=200, max_len=6, seed=6)]
+    refs = _oracle_all(oracle, insts)
+    K = sum(r[0] for r in refs)
+    _note(f"batched grid instances mode={mode} K={K}")
+    batch, _ = _device_batch(ddm, insts, mode, cap=K + 10)
+    total = batch.run()
+    _check(batch, insts, refs, mode, total)
+    graph = batch.graph()
+    for _ in range(2):
+        graph.launch()
+        total = graph.result()
+        _check(batch, insts, refs, mode, total)
+        if mode == "pairs":
+            batch.pairs.fill_(-1)
+        torch.cuda.synchronize()
+    graph.close()
+
+
 @pytest.mark.parametrize("d", [2, 3])
 def test_graph_replays_and_rewrites(ddm, oracle, d):
     insts = _mixed(d, seed=7)

@@ -201,6 +201,36 @@ def test_more_buckets_than_the_pair_scatter_holds(ddm, oracle):
         assert np.array_equal(got, ref[ref[:, 0] == i, 1]), r
 
 
+@pytest.mark.parametrize("d", [2, 3, 5])
+@pytest.mark.parametrize("closed", [False, True])
+def test_grid_cells(ddm, oracle, d, closed):
+    """Inputs whose walks in swept-axis slabs would be long (alpha = 40,
+    about 20 entries), so the plan cuts the slabs into rows by axis 1: every
+    mode on both paths, on float boxes and on an integer lattice whose
+    coordinates fall on cell boundaries (touching and point boxes)."""
+    inst = W.uniform_instance(30_000, 25_000, d, 40.0, seed=11 + d)
+    check_all_modes(ddm, oracle, inst, closed=closed)
+    ties = W.tie_heavy(30_000, 30_000, d, grid=300, max_len=8, seed=d)
+    check_all_modes(ddm, oracle, ties, closed=closed)
+
+
+def test_grid_rows_with_long_axis1_boxes(ddm, oracle):
+    """Grid rows with boxes that reach many later rows of their column
+    (copies as records) beside small ones, and boxes that also cross into
+    later columns (boundary-state copies in several rows)."""
+    rng = np.random.default_rng(5)
+    n = m = 30_000
+    lo = (rng.random((n + m, 3)) * 1000.0).astype(np.float32)
+    side = np.full((n + m, 3), 10.0, dtype=np.float32)
+    long1 = rng.random(n + m) < 0.02
+    side[long1, 1] = 400.0
+    long0 = rng.random(n + m) < 0.01
+    side[long0, 0] = 150.0
+    hi = (lo + side).astype(np.float32)
+    inst = W.Instance(lo[:n], hi[:n], lo[n:], hi[n:], float("nan"), "long_axis1_rows")
+    check_all_modes(ddm, oracle, inst)
+
+
 @pytest.mark.parametrize("alpha", [1.0, 100.0])
 def test_correlated_d3_stress(ddm, oracle, alpha):
     """Many true 3-D matches, so per-update counts and pairs are exercised."""
