@@ -913,20 +913,19 @@ struct SweepCtx {
   // the emitting pass), or null
   uint32_t *dl;
   uint32_t *own;
-  // the bucket's grid (null for slabs of a resident simulation) and its
-  // index within the instance: in a grid of ny > 1 rows a pair counts here
-  // only if the larger of its two axis-1 lower bounds falls in this cell's
-  // row (both regions are also present in the cells of later rows they both
-  // reach).  Read only for pairs that pass the exact test.
-  const BucketParams *grid = nullptr;
-  uint32_t cell = 0;
+  // a grid cell (ny > 1): its row, and the row map of axis 1's lower bounds;
+  // a pair counts here only if the larger of its two axis-1 lower bounds
+  // falls in this row (both regions are also present in the cells of later
+  // rows they both reach)
+  uint32_t ny = 1, row = 0;
+  float vmin1 = 0.f, scale1 = 0.f;
 };
 
-// The row test of a pair whose axis-1 lower bounds are ly and lx.
+// The row test of a pair whose axis-1 lower bounds are ly and lx; the sweep
+// takes its walks in a slab form (GRID = false, no test) and a grid form.
+template <bool GRID>
 __device__ __forceinline__ bool in_row(const SweepCtx &o, float ly, float lx) {
-  if (!o.grid) return true;
-  const BucketParams &g = *o.grid;
-  return g.ny <= 1 || bucket_of(fmaxf(ly, lx), g.vmin1, g.scale1, g.ny) == o.cell % g.ny;
+  return !GRID || bucket_of(fmaxf(ly, lx), o.vmin1, o.scale1, o.ny) == o.row;
 }
 
 // DM1 is d - 1 for d <= 3; DM1 = 3 stands for every d >= 4, whose records
@@ -968,7 +967,7 @@ __device__ __forceinline__ bool extra_axes(const SweepCtx &o, uint32_t ry, uint3
 
 // A pair of walker y and entry j that passed the key and pre-filter tests:
 // exact test on the other axes (d >= 2), then count or emit.
-template <int DM1, int MODE>
+template <int DM1, int MODE, bool GR>
 __device__ __forceinline__ void visit(const Walker<DM1> &y, bool &have_y, float (&ylo)[2],
                                       float (&yhi)[2], uint32_t j,
                                       const uint32_t *__restrict__ RID, unsigned long long &hits,
@@ -991,7 +990,7 @@ __device__ __forceinline__ void visit(const Walker<DM1> &y, bool &have_y, float 
     for (int c = 0; c < kNearAxes<DM1>; ++c)
       hit = hit && before(ylo[c], xhi[c], o.I.closed) && before(xlo[c], yhi[c], o.I.closed);
     if (DM1 == 3 && hit) hit = extra_axes(o, y.rid, rx);
-    if (!hit || !in_row(o, ylo[0], xlo[0])) return;
+    if (!hit || !in_row<GR>(o, ylo[0], xlo[0])) return;
   }
   ++hits;
   if (MODE == 1) {
@@ -1026,7 +1025,7 @@ __device__ __forceinline__ void visit(const Walker<DM1> &y, bool &have_y, float 
 
 // The exact test of a queued pair (ry walked, rx was met), then count or
 // emit as visit() does.
-template <int DM1, int MODE>
+template <int DM1, int MODE, bool GR>
 __device__ __forceinline__ void resolve(uint32_t ry, uint32_t rx, unsigned long long &hits,
                                         const SweepCtx &o) {
   float ylo[2], yhi[2], xlo[2], xhi[2];
@@ -1037,7 +1036,7 @@ __device__ __forceinline__ void resolve(uint32_t ry, uint32_t rx, unsigned long 
   for (int c = 0; c < kNearAxes<DM1>; ++c)
     hit = hit && before(ylo[c], xhi[c], o.I.closed) && before(xlo[c], yhi[c], o.I.closed);
   if (DM1 == 3 && hit) hit = extra_axes(o, ry, rx);
-  if (!hit || !in_row(o, ylo[0], xlo[0])) return;
+  if (!hit || !in_row<GR>(o, ylo[0], xlo[0])) return;
   ++hits;
   const uint32_t uu = ry < o.n ? ry : rx, ss = ry < o.n ? rx : ry;
   if (MODE == 1) {
@@ -1070,7 +1069,7 @@ __device__ __forceinline__ uint32_t min4(uint32_t a, uint32_t b, uint32_t c, uin
 // words at a time, masks the ones outside the interior and runs only the
 // pre-filter (skipping a chunk with one compare when none of the four
 // passes).
-template <int DM1, int MODE>
+template <int DM1, int MODE, bool GR>
 __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
                                      const uint32_t *__restrict__ RID,
                                      const uint32_t *__restrict__ Q, const Walker<DM1> &y,
@@ -1092,7 +1091,7 @@ __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
     const uint32_t k = KLO[j];
     const uint32_t fail = DM1 > 0 ? qfail<DM1>(Q[j], y.q) : 0u;
     if ((k >= y.after_key) & (k < y.khi) & (fail == 0u))
-      visit<DM1, MODE>(y, have_y, ylo, yhi, j, RID, hits, own, o);
+      visit<DM1, MODE, GR>(y, have_y, ylo, yhi, j, RID, hits, own, o);
   }
   if (!split) {
     // first and last bin coincide: the edge loop has seen every entry
@@ -1108,7 +1107,7 @@ __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
         atomicAdd(&o.dl[jC], 0xFFFFFFFFu);
       }
     } else {
-      for (uint32_t j = jB; j < jC; ++j) visit<DM1, MODE>(y, have_y, ylo, yhi, j, RID, hits, own, o);
+      for (uint32_t j = jB; j < jC; ++j) visit<DM1, MODE, GR>(y, have_y, ylo, yhi, j, RID, hits, own, o);
     }
   } else {
     // one aligned chunk of four: entries outside [jB, jC) get a non-zero
@@ -1124,10 +1123,10 @@ __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
         f3 |= (j + 3 < jB || j + 3 >= jC) ? 1u : 0u;
       }
       if (min4(f0, f1, f2, f3) == 0u) {
-        if (f0 == 0u) visit<DM1, MODE>(y, have_y, ylo, yhi, j, RID, hits, own, o);
-        if (f1 == 0u) visit<DM1, MODE>(y, have_y, ylo, yhi, j + 1, RID, hits, own, o);
-        if (f2 == 0u) visit<DM1, MODE>(y, have_y, ylo, yhi, j + 2, RID, hits, own, o);
-        if (f3 == 0u) visit<DM1, MODE>(y, have_y, ylo, yhi, j + 3, RID, hits, own, o);
+        if (f0 == 0u) visit<DM1, MODE, GR>(y, have_y, ylo, yhi, j, RID, hits, own, o);
+        if (f1 == 0u) visit<DM1, MODE, GR>(y, have_y, ylo, yhi, j + 1, RID, hits, own, o);
+        if (f2 == 0u) visit<DM1, MODE, GR>(y, have_y, ylo, yhi, j + 2, RID, hits, own, o);
+        if (f3 == 0u) visit<DM1, MODE, GR>(y, have_y, ylo, yhi, j + 3, RID, hits, own, o);
       }
     };
     uint32_t j = jB & ~3u;
@@ -1271,7 +1270,7 @@ __device__ __forceinline__ void emit_rows(
     y.q = 0u;
     const uint32_t jA = bin_begin(FINE);
     const uint32_t fh = fine_of(decode_coord(y.khi - o.I.closed), vmn, fscale, FINE);
-    walk<0, 2>(KLO, RID, nullptr, y, jA, jA, bin_begin(FINE + fh), BIN[FINE + fh], hits, o);
+    walk<0, 2, false>(KLO, RID, nullptr, y, jA, jA, bin_begin(FINE + fh), BIN[FINE + fh], hits, o);
   }
 }
 
@@ -1341,8 +1340,13 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   const int t = threadIdx.x;
   SweepCtx o{I, n, per_update, pair_off, cursor, out_u, out_s, queue, &queued, DL, own_cnt};
   if (DM1 > 0 && !SLAB && O.P) {
-    o.grid = O.P + inst;
-    o.cell = b - I.b0;
+    const BucketParams &bp = O.P[inst];
+    if (bp.ny > 1) {
+      o.ny = bp.ny;
+      o.row = (b - I.b0) % bp.ny;
+      o.vmin1 = bp.vmin1;
+      o.scale1 = bp.scale1;
+    }
   }
 
   // 1. records into registers (slot s = t + i * THREADS); value range
@@ -1450,6 +1454,8 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
                              SCR + kStageWords, SCR + kStageWords + kBsSubCap, &nbsub, &maxbsh,
                              maxspan, vmn, fscale, Cu, nbs, bs_rec + (size_t)bs_begin * 4, R,
                              hits, o);
+  auto walks = [&](auto tag) {
+  constexpr bool GR = decltype(tag)::value;
   for (uint32_t base = (uint32_t)w * kWave; base < walkers; base += (uint32_t)THREADS) {
     const uint32_t q = base + (uint32_t)lane;
     if (q >= walkers) continue;
@@ -1480,7 +1486,7 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
     }
     const uint32_t fh = fine_of(decode_coord(y.khi - I.closed), vmn, fscale, FINE);
     const uint32_t last = (y.upd ? (uint32_t)FINE : 0u) + fh;
-    walk<DM1, MODE>(KLO, RID, Q, y, jA, jB, bin_begin(last), BIN[last], hits, o);
+    walk<DM1, MODE, GR>(KLO, RID, Q, y, jA, jB, bin_begin(last), BIN[last], hits, o);
   }
   if (DM1 == 0 && MODE == 1) {
     // 4. d = 1: the pairs of each bucket update found here, by a prefix sum
@@ -1511,9 +1517,14 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
     const uint32_t nq = min(queued, (uint32_t)kQueue);
     for (uint32_t k = t; k < nq; k += THREADS) {
       const uint2 pr = queue[k];
-      resolve<DM1, MODE>(pr.x, pr.y, hits, o);
+      resolve<DM1, MODE, GR>(pr.x, pr.y, hits, o);
     }
   }
+  };
+  if (DM1 > 0 && o.ny > 1)  // uniform
+    walks(GridTag<true>{});
+  else
+    walks(GridTag<false>{});
   hits = wave_sum(hits);
   if (lane_id() == 0) red64[t / kWave] = hits;
   __syncthreads();
