@@ -59,7 +59,7 @@ constexpr int kPart = 10;                      // floats per sample block partia
 // are tried.
 constexpr uint32_t kPlanPoints = 8192;
 constexpr int kPlanThreads = 512;
-constexpr float kGridWalk = 8.0f;
+constexpr float kGridWalk = 2.0f;
 
 // The sweep workgroup: at most kBucketCap records per bucket with 512 fine
 // bins per kind (256 or 512 threads), or kBigBucketCap records with 1024
@@ -298,7 +298,7 @@ __device__ void block_plan(const float *__restrict__ part, const InstPlan &I, bo
       }
       // a walk in a slab meets about N * ext0 / (2 (hi - lo)) entries of the
       // other kind (ext0 the mean swept-axis extent); rows pay for their
-      // extra plan, count and copy work only when that is several
+      // extra plan, count and copy work only when that is a few
       const float walk = (float)(I.n + I.m) * (ext0 / c) / (2.0f * (hi - lo));
       if (q.valid && grid && I.d >= 2 && I.nb >= 4 && v[5] > v[4] && walk >= kGridWalk) {
         const float gap1 = 2.0f * (v[5] - v[4]) / c;
