@@ -433,7 +433,12 @@ const char *ddm_strerror(int code);
  *                      sorted endpoint list, as in Algorithm 5); each bucket
  *                      is sorted and swept in on-chip memory, starting from
  *                      the regions of earlier buckets still active at its
- *                      start (the boundary state of Algorithm 6); available
+ *                      start (the boundary state of Algorithm 6); for d >= 2
+ *                      the buckets may also be cut into rows by axis 1
+ *                      (boxes reaching later rows are copied there, and a
+ *                      pair is counted in the row of its larger axis-1
+ *                      lower bound), which the plan chooses from a sample
+ *                      when it shortens the sweep; available
  *                      for d <= 8 (a pre-filter on axes 1 and 2, the exact
  *                      test on every axis);
  *   DDM_PATH_GLOBAL    a device-wide sort of the lower endpoints and a sweep
