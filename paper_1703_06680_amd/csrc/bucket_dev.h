@@ -45,11 +45,12 @@ struct Box {
 
 // The grid cells a box overlaps: columns [a0, a1] (of its swept-axis
 // bounds) by rows [c0, c1] (of its axis-1 bounds).  Its record goes to cell
-// (a0, c0); the cells (a0, c) for c > c0 get copies as records (the box is
-// in them from their start on the swept axis); cells of later columns get
-// boundary-state copies.  A pair is found in the cell of its swept-axis
-// order (as with slabs) whose row holds the larger of the two axis-1 lower
-// bounds; both boxes are present in that cell, since the maps are monotone.
+// (a0, c0); the cells (a0, c) for c > c0 get copies as ordinary records
+// (within the column the box keeps its own swept-axis position); cells of
+// later columns get boundary-state copies.  A pair is found in the column
+// of its later swept-axis lower bound (as with slabs) and counted in the
+// row that holds the larger of its two axis-1 lower bounds; both boxes are
+// present in that cell, since the maps are monotone.
 template <int D>
 struct Cells {
   uint32_t a0, a1, c0, c1;
