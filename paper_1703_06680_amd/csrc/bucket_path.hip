@@ -1455,71 +1455,71 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
                              maxspan, vmn, fscale, Cu, nbs, bs_rec + (size_t)bs_begin * 4, R,
                              hits, o);
   auto walks = [&](auto tag) {
-  constexpr bool GR = decltype(tag)::value;
-  for (uint32_t base = (uint32_t)w * kWave; base < walkers; base += (uint32_t)THREADS) {
-    const uint32_t q = base + (uint32_t)lane;
-    if (q >= walkers) continue;
-    Walker<DM1> y;
-    uint32_t jA, jB;
-    if (q < C) {  // a region of the bucket, from its own bin
-      y.klo = KLO[q];
-      y.khi = KHI[q];
-      y.rid = RID[q];
-      y.pos = q;
-      y.upd = q < Cu;
-      y.after_key = y.upd ? y.klo : y.klo + 1u;
-      y.q = DM1 > 0 ? walker_from_entry<DM1>(Q[q]) : 0u;
-      const uint32_t fl = fine_of(decode_coord(y.klo), vmn, fscale, FINE);
-      const uint32_t other = y.upd ? (uint32_t)FINE : 0u;
-      jA = bin_begin(other + fl);
-      jB = BIN[other + fl];
-    } else {  // a boundary-state region: every lower endpoint of the bucket comes after it
-      const uint4 yr = reinterpret_cast<const uint4 *>(bs_rec)[bs_begin + (q - C)];
-      y.klo = yr.x;
-      y.khi = yr.y;
-      y.rid = yr.z;
-      y.pos = kNoPos;
-      y.upd = yr.z < n;
-      y.after_key = 0u;
-      y.q = DM1 > 0 ? walker_word<DM1>(yr.w) : 0u;
-      jA = jB = bin_begin(y.upd ? (uint32_t)FINE : 0u);
+    constexpr bool GR = decltype(tag)::value;
+    for (uint32_t base = (uint32_t)w * kWave; base < walkers; base += (uint32_t)THREADS) {
+      const uint32_t q = base + (uint32_t)lane;
+      if (q >= walkers) continue;
+      Walker<DM1> y;
+      uint32_t jA, jB;
+      if (q < C) {  // a region of the bucket, from its own bin
+        y.klo = KLO[q];
+        y.khi = KHI[q];
+        y.rid = RID[q];
+        y.pos = q;
+        y.upd = q < Cu;
+        y.after_key = y.upd ? y.klo : y.klo + 1u;
+        y.q = DM1 > 0 ? walker_from_entry<DM1>(Q[q]) : 0u;
+        const uint32_t fl = fine_of(decode_coord(y.klo), vmn, fscale, FINE);
+        const uint32_t other = y.upd ? (uint32_t)FINE : 0u;
+        jA = bin_begin(other + fl);
+        jB = BIN[other + fl];
+      } else {  // a boundary-state region: every lower endpoint of the bucket comes after it
+        const uint4 yr = reinterpret_cast<const uint4 *>(bs_rec)[bs_begin + (q - C)];
+        y.klo = yr.x;
+        y.khi = yr.y;
+        y.rid = yr.z;
+        y.pos = kNoPos;
+        y.upd = yr.z < n;
+        y.after_key = 0u;
+        y.q = DM1 > 0 ? walker_word<DM1>(yr.w) : 0u;
+        jA = jB = bin_begin(y.upd ? (uint32_t)FINE : 0u);
+      }
+      const uint32_t fh = fine_of(decode_coord(y.khi - I.closed), vmn, fscale, FINE);
+      const uint32_t last = (y.upd ? (uint32_t)FINE : 0u) + fh;
+      walk<DM1, MODE, GR>(KLO, RID, Q, y, jA, jB, bin_begin(last), BIN[last], hits, o);
     }
-    const uint32_t fh = fine_of(decode_coord(y.khi - I.closed), vmn, fscale, FINE);
-    const uint32_t last = (y.upd ? (uint32_t)FINE : 0u) + fh;
-    walk<DM1, MODE, GR>(KLO, RID, Q, y, jA, jB, bin_begin(last), BIN[last], hits, o);
-  }
-  if (DM1 == 0 && MODE == 1) {
-    // 4. d = 1: the pairs of each bucket update found here, by a prefix sum
-    //    of the difference array, into the per-update counts
-    __syncthreads();
-    constexpr int PER = CAP / THREADS;
-    const uint32_t j0 = (uint32_t)t * PER;
-    uint32_t v[PER], sum = 0;
+    if (DM1 == 0 && MODE == 1) {
+      // 4. d = 1: the pairs of each bucket update found here, by a prefix sum
+      //    of the difference array, into the per-update counts
+      __syncthreads();
+      constexpr int PER = CAP / THREADS;
+      const uint32_t j0 = (uint32_t)t * PER;
+      uint32_t v[PER], sum = 0;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      v[k] = DL[j0 + k];
-      sum += v[k];
-    }
-    uint32_t tot;
-    uint32_t run = block_exclusive_scan<uint32_t, THREADS>(sum, red, &tot);
+      for (int k = 0; k < PER; ++k) {
+        v[k] = DL[j0 + k];
+        sum += v[k];
+      }
+      uint32_t tot;
+      uint32_t run = block_exclusive_scan<uint32_t, THREADS>(sum, red, &tot);
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      run += v[k];
-      const uint32_t j = j0 + k;
-      if (j < Cu) {
-        if (run) atomicAdd(&per_update[RID[j]], (int)run);
-        if (own_cnt) own_cnt[RID[j]] = run;
+      for (int k = 0; k < PER; ++k) {
+        run += v[k];
+        const uint32_t j = j0 + k;
+        if (j < Cu) {
+          if (run) atomicAdd(&per_update[RID[j]], (int)run);
+          if (own_cnt) own_cnt[RID[j]] = run;
+        }
       }
     }
-  }
-  if (DM1 > 0) {  // 4. the exact test of the queued pairs, all at once
-    __syncthreads();
-    const uint32_t nq = min(queued, (uint32_t)kQueue);
-    for (uint32_t k = t; k < nq; k += THREADS) {
-      const uint2 pr = queue[k];
-      resolve<DM1, MODE, GR>(pr.x, pr.y, hits, o);
+    if (DM1 > 0) {  // 4. the exact test of the queued pairs, all at once
+      __syncthreads();
+      const uint32_t nq = min(queued, (uint32_t)kQueue);
+      for (uint32_t k = t; k < nq; k += THREADS) {
+        const uint2 pr = queue[k];
+        resolve<DM1, MODE, GR>(pr.x, pr.y, hits, o);
+      }
     }
-  }
   };
   if (DM1 > 0 && o.ny > 1)  // uniform
     walks(GridTag<true>{});
