@@ -365,38 +365,34 @@ def bench_resident(args, ddm, W, torch, np):
     }
 
 
-_BATCH_WORK = []  # the batched baseline's instances, shared with forked workers
-
-
-def _oracle_count(i):
-    """Worker of the batched CPU baseline: the oracle's count of instance i."""
+def _oracle_count(inst):
+    """The oracle's count of one instance (upd_lo, upd_hi, sub_lo, sub_hi)."""
     from oracle import oracle as O
-    k, _, _ = O.default().sbm(*_BATCH_WORK[i], pairs=False, per_update=False)
+    k, _, _ = O.default().sbm(*inst, pairs=False, per_update=False)
     return k
 
 
 def cpu_batched_baseline(args, W, np):
     """The oracle on a sample of the batched workload (every 8th instance), on
-    one core and over a process pool on the host cores.  Runs before the GPU
-    is first touched, so the pool's processes fork from a process without GPU
-    state."""
-    import multiprocessing as mp
+    one core and over a pool of threads on the host cores (the C oracle
+    releases the interpreter lock and keeps no global state, so instances
+    run in parallel without extra processes)."""
+    from concurrent.futures import ThreadPoolExecutor
     insts = W.batched_instances(args.batch_count, d=2, seed=0)
     picked = list(range(0, len(insts), 8))
-    _BATCH_WORK[:] = [(insts[b].upd_lo, insts[b].upd_hi, insts[b].sub_lo, insts[b].sub_hi)
-                      for b in picked]
+    work = [(insts[b].upd_lo, insts[b].upd_hi, insts[b].sub_lo, insts[b].sub_hi)
+            for b in picked]
     regions = sum(insts[b].n + insts[b].m for b in picked)
     t = time.perf_counter()
-    serial = [_oracle_count(i) for i in range(len(picked))]
+    serial = [_oracle_count(w) for w in work]
     t_serial = time.perf_counter() - t
     procs = max(1, min(16, os.cpu_count() or 1))
-    # largest instances first, one at a time; the workers read the instances
-    # from the memory they share with this process by fork
+    # largest instances first
     order = sorted(range(len(picked)), key=lambda i: -(insts[picked[i]].n + insts[picked[i]].m))
-    with mp.get_context("fork").Pool(procs) as pool:
-        pool.map(_oracle_count, order[-procs:], chunksize=1)  # workers up, oracle loaded
+    with ThreadPoolExecutor(procs) as pool:
+        list(pool.map(_oracle_count, [work[i] for i in order[-procs:]]))  # threads up
         t = time.perf_counter()
-        pooled = pool.map(_oracle_count, order, chunksize=1)
+        pooled = list(pool.map(_oracle_count, [work[i] for i in order]))
         t_pool = time.perf_counter() - t
     assert [pooled[order.index(i)] for i in range(len(picked))] == serial
     return {
@@ -407,7 +403,7 @@ def cpu_batched_baseline(args, W, np):
                       "kind": "oracle"},
         "sample": f"every 8th instance ({len(picked)} instances, {regions} regions), the C "
                   f"oracle per instance: {t_serial:.2f} s on one core, {t_pool:.2f} s over "
-                  f"{procs} processes",
+                  f"{procs} threads",
     }
 
 

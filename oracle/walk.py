@@ -24,9 +24,9 @@ IEEE float32 implementation):
 * step: lo <- lo + sigma * z, hi <- lo + side, in float32 with one rounding
   per operation.  Updates are regions 0 .. n-1, subscriptions n .. n+m-1.
 
-Parity of this module itself is pinned by a second, scalar implementation
-of the same definition in the tests and by distribution checks; no published
-known-answer vectors are used.  ``walk_fast`` runs the same motion through a
+Parity of this module itself is pinned by the known-answer vectors published
+with Philox4x32-10 (tests/golden/), by a second, scalar implementation of the
+same definition in the tests and by distribution checks.  ``walk_fast`` runs the same motion through a
 C implementation (``walk_oracle.c``, pinned bit for bit to this module by the
 tests) for full-size replays.
 """

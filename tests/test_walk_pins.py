@@ -1,9 +1,13 @@
 """Pins of the CPU reference of the serving motion (oracle/walk.py).
 
 The motion is the serving workload's, not the paper's method; its reference
-is pinned by a second, deliberately plain implementation of the published
-Philox4x32-10 definition (scalar Python integers, one round at a time) and
-by distribution properties of the Irwin-Hall normal it feeds."""
+is pinned by the published known-answer vectors of Philox4x32-10
+(tests/golden/philox4x32_10_kat.json), by a second, deliberately plain
+implementation of the same definition (scalar Python integers, one round at a
+time) and by distribution properties of the Irwin-Hall normal it feeds."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -24,6 +28,21 @@ def philox_scalar(c, k):
         k0 = (k0 + 0x9E3779B9) & mask
         k1 = (k1 + 0xBB67AE85) & mask
     return c
+
+
+def test_known_answer_vectors():
+    """The generator against the known-answer vectors published with the
+    Philox definition (counter, key, output), including all-zero and
+    all-ones inputs."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.json")
+    cases = json.load(open(path))["cases"]
+    assert len(cases) == 3
+    for c in cases:
+        ctr = np.array([[int(w, 16) for w in c["ctr"]]], dtype=np.uint32)
+        k0, k1 = (int(w, 16) for w in c["key"])
+        want = [int(w, 16) for w in c["out"]]
+        assert [int(v) for v in walk.philox4x32_10(ctr, k0, k1)[0]] == want
+        assert philox_scalar([int(w, 16) for w in c["ctr"]], (k0, k1)) == want
 
 
 def test_vectorised_equals_scalar():
