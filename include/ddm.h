@@ -48,6 +48,7 @@ extern "C" {
 #define DDM_E_WORKSPACE (-3) /* workspace smaller than ddm_workspace_bytes() */
 #define DDM_E_DEVICE (-4)    /* a HIP runtime call failed                    */
 #define DDM_E_UNSUPPORTED (-5) /* valid request outside the supported range   */
+#define DDM_E_SCRATCH (-6)   /* ddm_match_noalloc(): request beyond its array  */
 
 /* Output modes (exactly one). */
 #define DDM_COUNT 0      /* total number of intersecting pairs                */
@@ -135,6 +136,34 @@ int ddm_match_csr(const float *upd_lo, const float *upd_hi, int64_t n,
                   int d, int flags, void *workspace, size_t ws_bytes, void *stream,
                   uint64_t *count_host, int64_t *row_off, int32_t *sub_ids,
                   int64_t capacity);
+
+/*
+ * For callers that cannot allocate memory (code that must not call
+ * hipMalloc, such as tight serving loops or harnesses that forbid it):
+ * ddm_match() without a workspace argument.  The workspace is a static
+ * device array of DDM_NOALLOC_SCRATCH_BYTES inside the library; each device
+ * the library runs on holds its own copy from the first call on it until
+ * the process ends.  The call allocates nothing (no device, page-locked or
+ * graph memory; no profiling events) and never captures or replays a graph.
+ *
+ *   arguments   as for ddm_match(), minus workspace and ws_bytes; inputs and
+ *               outputs are still the caller's device buffers
+ *
+ * Errors: as ddm_match(); DDM_E_SCRATCH, before anything touches the GPU,
+ * if ddm_workspace_bytes(n, m, d, mode, pair_capacity) exceeds
+ * DDM_NOALLOC_SCRATCH_BYTES (64 MiB: n + m up to about 2.0e6 boxes for
+ * d = 2, 1.6e6 for d = 3, in count or per-update mode); DDM_E_UNSUPPORTED while ddm_profile(1) is on or
+ * on a device numbered 64 or above.  Sharing: every call on a device uses
+ * that device's one array, which keeps the last call's contents (each call
+ * clears what it needs).  Calls of one process on one device take turns (a
+ * lock held until the call has synchronised); work that bypasses this
+ * entry point and touches the array would race with them.
+ */
+#define DDM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int ddm_match_noalloc(const float *upd_lo, const float *upd_hi, int64_t n,
+                      const float *sub_lo, const float *sub_hi, int64_t m,
+                      int d, int mode, void *stream, uint64_t *count_host,
+                      int32_t *per_update, int32_t *pairs, int64_t pair_capacity);
 
 /*
  * Per-axis 1-D candidate counts (diagnostic).  counts_host[k] (host, [d])

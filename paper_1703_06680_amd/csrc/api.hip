@@ -505,6 +505,8 @@ extern "C" const char *ddm_strerror(int code) {
     case DDM_E_WORKSPACE: return "workspace smaller than ddm_workspace_bytes()";
     case DDM_E_DEVICE: return "HIP runtime error";
     case DDM_E_UNSUPPORTED: return "request outside the supported range";
+    case DDM_E_SCRATCH:
+      return "request needs more than the static scratch array of ddm_match_noalloc() holds";
     default: return "unknown error";
   }
 }
@@ -522,10 +524,12 @@ namespace {
 
 // ddm_match and ddm_match_csr: the pair list goes to ``pairs``, or, with
 // csr_off given, CSR rows to csr_off / csr_ids.
+// ``cached``: repeated count / per-update calls may be captured into a graph
+// (which allocates the graph and a page-locked header); false runs eagerly.
 int match_entry(const float *upd_lo, const float *upd_hi, int64_t n, const float *sub_lo,
                 const float *sub_hi, int64_t m, int d, int mode, void *workspace, size_t ws_bytes,
                 void *stream, uint64_t *count_host, int32_t *per_update, int32_t *pairs,
-                int64_t pair_capacity, int64_t *csr_off, int32_t *csr_ids) {
+                int64_t pair_capacity, int64_t *csr_off, int32_t *csr_ids, bool cached = true) {
   // host-side checks: nothing is launched when one fails
   const int mode_arg = mode;  // with the interval flag (the graph cache key)
   bool closed;
@@ -534,7 +538,7 @@ int match_entry(const float *upd_lo, const float *upd_hi, int64_t n, const float
   if ((n > 0 && (!upd_lo || !upd_hi)) || (m > 0 && (!sub_lo || !sub_hi))) return DDM_E_INVAL;
   if (mode == DDM_PER_UPDATE && n > 0 && !per_update) return DDM_E_INVAL;
   if (mode == DDM_PAIRS && pair_capacity > 0 && !(csr_off ? csr_ids : pairs)) return DDM_E_INVAL;
-  const bool graphable = mode != DDM_PAIRS && n + m > 0 && !prof::enabled() &&
+  const bool graphable = cached && mode != DDM_PAIRS && n + m > 0 && !prof::enabled() &&
                          g_path_request != DDM_PATH_GLOBAL && workspace &&
                          !(reinterpret_cast<uintptr_t>(workspace) & 255);
   const GraphKey key{upd_lo, upd_hi, sub_lo, sub_hi, n, m, d, mode_arg, workspace, ws_bytes,
@@ -653,4 +657,57 @@ extern "C" int ddm_match_csr(const float *upd_lo, const float *upd_hi, int64_t n
   if ((flags & ~DDM_CLOSED) != 0 || !row_off) return DDM_E_INVAL;
   return match_entry(upd_lo, upd_hi, n, sub_lo, sub_hi, m, d, DDM_PAIRS | flags, workspace,
                      ws_bytes, stream, count_host, nullptr, nullptr, capacity, row_off, sub_ids);
+}
+
+// ------------------------------------------------- no-allocation variant
+//
+// ddm_match() with the workspace taken from a file-scope device array
+// instead of the caller: for callers that cannot allocate device memory.
+// The array's name is a host-side stand-in in host code; its device address
+// is looked up once per device (hipGetSymbolAddress, with that device
+// current) and only that address is ever passed to kernels or copies.
+namespace {
+
+__device__ __align__(256) unsigned char scratch[DDM_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+
+struct ScratchSlot {
+  std::mutex mu;        // held for a whole call: calls on one device take turns
+  void *ptr = nullptr;  // device address of this device's copy of `scratch`
+};
+ScratchSlot g_scratch[kMaxDevices];
+
+}  // namespace
+
+extern "C" int ddm_match_noalloc(const float *upd_lo, const float *upd_hi, int64_t n,
+                                 const float *sub_lo, const float *sub_hi, int64_t m, int d,
+                                 int mode, void *stream, uint64_t *count_host,
+                                 int32_t *per_update, int32_t *pairs, int64_t pair_capacity) {
+  // the size check needs no device: requests beyond the array are refused
+  // before anything touches the GPU
+  int out;
+  bool closed;
+  if (!split_mode(mode, &out, &closed)) return DDM_E_INVAL;
+  if (!sizes_ok(n, m, d, out) || !count_host || pair_capacity < 0) return DDM_E_INVAL;
+  if (make_layout(n, m, d, out, pair_capacity).total > DDM_NOALLOC_SCRATCH_BYTES)
+    return DDM_E_SCRATCH;
+  if (prof::enabled()) return DDM_E_UNSUPPORTED;  // the recorder creates events
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return DDM_E_DEVICE;
+  if (dev < 0 || dev >= kMaxDevices) return DDM_E_UNSUPPORTED;
+  ScratchSlot &slot = g_scratch[dev];
+  std::lock_guard<std::mutex> hold(slot.mu);
+  if (!slot.ptr) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return DDM_E_DEVICE;
+    slot.ptr = p;
+  }
+  const int rc = match_entry(upd_lo, upd_hi, n, sub_lo, sub_hi, m, d, mode, slot.ptr,
+                             DDM_NOALLOC_SCRATCH_BYTES, stream, count_host, per_update, pairs,
+                             pair_capacity, nullptr, nullptr, false);
+  // every path has synchronised before it returns a result; an early error
+  // may not have, and the next call must not overlap this one's kernels
+  if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return DDM_E_DEVICE;
+  return rc;
 }

@@ -86,6 +86,26 @@ inline uint32_t bucket_cap(const BucketTuning &t) {
   return t.sweep_threads == 1024 ? kBigBucketCap : kBucketCap;
 }
 
+// Host copy of the per-instance plans, contiguous: a batch of one is held
+// inline (a single call touches no heap), larger batches on the heap.
+class PlanList {
+ public:
+  void resize(size_t count) {
+    count_ = count;
+    many_.assign(count > 1 ? count : 0, InstPlan{});
+  }
+  size_t size() const { return count_; }
+  InstPlan *data() { return count_ > 1 ? many_.data() : &one_; }
+  const InstPlan *data() const { return count_ > 1 ? many_.data() : &one_; }
+  InstPlan &operator[](size_t i) { return data()[i]; }
+  const InstPlan &operator[](size_t i) const { return data()[i]; }
+
+ private:
+  InstPlan one_{};
+  std::vector<InstPlan> many_;
+  size_t count_ = 0;
+};
+
 struct BucketLayout {
   uint32_t B;                          // instances
   uint32_t nb, nblk, nsmp;             // totals over the instances
@@ -100,7 +120,7 @@ struct BucketLayout {
   // byte offsets inside the bucket workspace
   size_t params, sample_part, sample_pts, counts, totals, offsets, block_offsets, scan_tmp, bs_cur,
       rec, bs_rec, plan, maps;
-  std::vector<InstPlan> inst;          // host copy of the per-instance plan
+  PlanList inst;                       // host copy of the per-instance plan
 };
 
 // Instances in order; output rows (per-update counts, pair rows) number the

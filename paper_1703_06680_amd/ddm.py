@@ -22,6 +22,8 @@ DDM_E_CAPACITY = -2
 DDM_E_WORKSPACE = -3
 DDM_E_DEVICE = -4
 DDM_E_UNSUPPORTED = -5
+DDM_E_SCRATCH = -6
+NOALLOC_SCRATCH_BYTES = 64 << 20  # DDM_NOALLOC_SCRATCH_BYTES
 
 MODES = {"count": 0, "per_update": 1, "pairs": 2}
 DDM_CLOSED = 16  # interval flag OR-ed into a mode: closed boxes [lo, hi]
@@ -66,6 +68,9 @@ def library() -> ctypes.CDLL:
                                       ctypes.c_size_t, vp, ctypes.POINTER(ctypes.c_uint64), vp, vp,
                                       i64]
         lib.ddm_match_csr.restype = ctypes.c_int
+        lib.ddm_match_noalloc.argtypes = [vp, vp, i64, vp, vp, i64, ctypes.c_int, ctypes.c_int,
+                                          vp, ctypes.POINTER(ctypes.c_uint64), vp, vp, i64]
+        lib.ddm_match_noalloc.restype = ctypes.c_int
         lib.ddm_strerror.argtypes = [ctypes.c_int]
         lib.ddm_strerror.restype = ctypes.c_char_p
         lib.ddm_set_path.argtypes = [ctypes.c_int]
@@ -171,6 +176,29 @@ def match_into(upd_lo, upd_hi, sub_lo, sub_hi, mode: str, workspace: torch.Tenso
                              _ptr(pairs) if pairs is not None else None, cap)
     if rc != DDM_OK:
         raise DDMError(rc)
+    return int(cnt.value)
+
+
+def match_noalloc_into(upd_lo, upd_hi, sub_lo, sub_hi, mode: str,
+                       per_update: torch.Tensor | None = None,
+                       pairs: torch.Tensor | None = None, stream=None,
+                       closed: bool = False) -> int:
+    """``ddm_match_noalloc``: the call of ``match_into`` without a workspace
+    (the library's static device array serves as one); returns K, raises
+    DDMError (code DDM_E_SCRATCH when the sizes need more than the array)."""
+    n, d = upd_lo.shape
+    m = sub_lo.shape[0]
+    if stream is None:
+        stream = torch.cuda.current_stream(upd_lo.device)
+    cnt = ctypes.c_uint64(0)
+    cap = pairs.shape[0] if pairs is not None else 0
+    rc = library().ddm_match_noalloc(_ptr(upd_lo), _ptr(upd_hi), n, _ptr(sub_lo), _ptr(sub_hi),
+                                     m, d, _code(mode, closed),
+                                     ctypes.c_void_p(stream.cuda_stream), ctypes.byref(cnt),
+                                     _ptr(per_update) if per_update is not None else None,
+                                     _ptr(pairs) if pairs is not None else None, cap)
+    if rc != DDM_OK:
+        raise DDMError(rc, "ddm_match_noalloc")
     return int(cnt.value)
 
 

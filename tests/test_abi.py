@@ -145,3 +145,33 @@ def test_resident_sizes_and_argument_errors(lib):
     lib.ddm_resident_destroy.argtypes = [vp]
     lib.ddm_resident_destroy.restype = ctypes.c_int
     assert lib.ddm_resident_destroy(None) == 0
+
+
+def test_noalloc_refuses_oversize_requests_before_touching_the_gpu(lib):
+    """ddm_match_noalloc checks the sizes against its static array first, so
+    these calls return without any HIP call (no GPU is needed here)."""
+    vp, i64 = ctypes.c_void_p, ctypes.c_int64
+    f = lib.ddm_match_noalloc
+    f.argtypes = [vp, vp, i64, vp, vp, i64, ctypes.c_int, ctypes.c_int, vp,
+                  ctypes.POINTER(ctypes.c_uint64), vp, vp, i64]
+    f.restype = ctypes.c_int
+    lib.ddm_workspace_bytes.argtypes = [i64, i64, ctypes.c_int, ctypes.c_int, i64]
+    lib.ddm_workspace_bytes.restype = ctypes.c_size_t
+    scratch = 64 << 20
+    fake = vp(256)  # never dereferenced: the calls below end on the host
+    cnt = ctypes.c_uint64(0)
+    for d, n in ((1, 1_400_000), (2, 1_100_000), (3, 900_000)):
+        assert lib.ddm_workspace_bytes(n, n, d, 0, 0) > scratch
+        assert f(fake, fake, n, fake, fake, n, d, 0, None, ctypes.byref(cnt), None, None, 0) == -6
+        assert f(fake, fake, n, fake, fake, n, d, 1, None, ctypes.byref(cnt), fake, None, 0) == -6
+    # a pair capacity beyond the array is refused the same way
+    assert lib.ddm_workspace_bytes(1000, 1000, 2, 2, 10**7) > scratch
+    assert f(fake, fake, 1000, fake, fake, 1000, 2, 2, None, ctypes.byref(cnt), None, fake,
+             10**7) == -6
+    # argument errors come first
+    assert f(fake, fake, -1, fake, fake, 10, 2, 0, None, ctypes.byref(cnt), None, None, 0) == -1
+    assert f(fake, fake, 10, fake, fake, 10, 2, 0, None, None, None, None, 0) == -1
+    assert f(fake, fake, 10, fake, fake, 10, 2, 7, None, ctypes.byref(cnt), None, None, 0) == -1
+    lib.ddm_strerror.argtypes = [ctypes.c_int]
+    lib.ddm_strerror.restype = ctypes.c_char_p
+    assert b"scratch" in lib.ddm_strerror(-6)
