@@ -476,8 +476,11 @@ const char *ddm_strerror(int code);
  * back to the global one when a bucket or the boundary state does not fit.
  * A forced DDM_PATH_BUCKETED call returns DDM_E_UNSUPPORTED instead of
  * falling back.  ddm_set_path() returns DDM_E_INVAL for an unknown value;
- * ddm_last_path() reports the path that produced the last successful result
- * of ddm_match() on any thread (0 if none).
+ * ddm_last_path() reports the path that served the calling thread's last
+ * ddm_match(), ddm_match_csr() or ddm_match_noalloc() call (0 if that call
+ * produced no result); the library's own nested calls (batch fallbacks,
+ * resident repairs, the server, per-axis counts) leave it unchanged.  The
+ * path request applies to every thread; both are safe to use concurrently.
  */
 #define DDM_PATH_AUTO 0
 #define DDM_PATH_BUCKETED 1

@@ -13,10 +13,12 @@
 // Both produce identical results; ddm_set_path() can force one of them.
 #include <string.h>
 
+#include <atomic>
 #include <mutex>
 #include <vector>
 
 #include "../../include/ddm.h"
+#include "internal.h"
 #include "bucket_path.h"
 #include "common.h"
 #include "match_global.h"
@@ -28,8 +30,11 @@ namespace {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-int g_path_request = DDM_PATH_AUTO;
-int g_last_path = 0;
+// The implementation requested (process-wide) and the one that produced the
+// calling thread's last result; the library's own nested calls (batches,
+// resident simulations, the server, per-axis counts) leave the latter alone.
+std::atomic<int> g_path_request{DDM_PATH_AUTO};
+thread_local int t_last_path = 0;
 
 // Byte offsets of every workspace buffer.  The buffers of the two paths share
 // one region (only one path runs at a time).
@@ -514,11 +519,11 @@ extern "C" const char *ddm_strerror(int code) {
 extern "C" int ddm_set_path(int path) {
   if (path != DDM_PATH_AUTO && path != DDM_PATH_BUCKETED && path != DDM_PATH_GLOBAL)
     return DDM_E_INVAL;
-  g_path_request = path;
+  g_path_request.store(path, std::memory_order_relaxed);
   return DDM_OK;
 }
 
-extern "C" int ddm_last_path(void) { return g_last_path; }
+extern "C" int ddm_last_path(void) { return t_last_path; }
 
 namespace {
 
@@ -529,7 +534,17 @@ namespace {
 int match_entry(const float *upd_lo, const float *upd_hi, int64_t n, const float *sub_lo,
                 const float *sub_hi, int64_t m, int d, int mode, void *workspace, size_t ws_bytes,
                 void *stream, uint64_t *count_host, int32_t *per_update, int32_t *pairs,
-                int64_t pair_capacity, int64_t *csr_off, int32_t *csr_ids, bool cached = true) {
+                int64_t pair_capacity, int64_t *csr_off, int32_t *csr_ids, bool cached = true,
+                bool record = true) {
+  int last_path = 0;
+  struct Record {  // reports the path on every return of a recorded call
+    bool on;
+    int &path;
+    ~Record() {
+      if (on) t_last_path = path;
+    }
+  } report{record, last_path};
+  const int path_request = g_path_request.load(std::memory_order_relaxed);
   // host-side checks: nothing is launched when one fails
   const int mode_arg = mode;  // with the interval flag (the graph cache key)
   bool closed;
@@ -539,12 +554,13 @@ int match_entry(const float *upd_lo, const float *upd_hi, int64_t n, const float
   if (mode == DDM_PER_UPDATE && n > 0 && !per_update) return DDM_E_INVAL;
   if (mode == DDM_PAIRS && pair_capacity > 0 && !(csr_off ? csr_ids : pairs)) return DDM_E_INVAL;
   const bool graphable = cached && mode != DDM_PAIRS && n + m > 0 && !prof::enabled() &&
-                         g_path_request != DDM_PATH_GLOBAL && workspace &&
+                         path_request != DDM_PATH_GLOBAL && workspace &&
                          !(reinterpret_cast<uintptr_t>(workspace) & 255);
   const GraphKey key{upd_lo, upd_hi, sub_lo, sub_hi, n, m, d, mode_arg, workspace, ws_bytes,
                      mode == DDM_COUNT ? nullptr : per_update};
   std::unique_lock<std::mutex> cache_lock(g_graph_mu, std::defer_lock);
   CachedGraph *entry = nullptr;
+  bool global_only = false;
   if (graphable) {
     cache_lock.lock();
     for (CachedGraph &e : g_graphs)
@@ -554,11 +570,12 @@ int match_entry(const float *upd_lo, const float *upd_hi, int64_t n, const float
       *count_host = 0;
       const int rc = replay(*entry, static_cast<hipStream_t>(stream), count_host);
       if (rc != kFallback) {
-        g_last_path = rc == DDM_OK ? DDM_PATH_BUCKETED : 0;
+        last_path = rc == DDM_OK ? DDM_PATH_BUCKETED : 0;
         return rc;
       }
-      if (g_path_request == DDM_PATH_BUCKETED) return DDM_E_UNSUPPORTED;
-      entry = nullptr;  // the device-wide path below
+      if (path_request == DDM_PATH_BUCKETED) return DDM_E_UNSUPPORTED;
+      entry = nullptr;
+      global_only = true;  // the replay did the bucketed attempt: the device-wide path below
     } else if (!entry) {  // first sighting: remember the call, run it eagerly
       if (g_graphs.size() >= kGraphCache) {
         size_t old = 0;
@@ -601,46 +618,56 @@ int match_entry(const float *upd_lo, const float *upd_hi, int64_t n, const float
                             : per_update;
   c.csr_off = csr_off;
   c.csr_ids = csr_ids;
-  g_last_path = 0;
+  last_path = 0;
   if (n + m == 0) {
     int rc = reset_outputs(c);
     if (rc == DDM_OK && hipStreamSynchronize(c.s) != hipSuccess) return DDM_E_DEVICE;
     if (rc == DDM_OK) rc = csr_zero(c);
     return rc;
   }
-  if (g_path_request == DDM_PATH_BUCKETED && !c.L.bucket_ok) return DDM_E_UNSUPPORTED;
+  if (path_request == DDM_PATH_BUCKETED && !c.L.bucket_ok) return DDM_E_UNSUPPORTED;
   int rc;
   if (entry && c.L.bucket_ok) {  // second sighting of a repeated call: capture and replay
     entry->used = ++g_graph_tick;
     if (capture(*entry, c)) {
       rc = replay(*entry, c.s, count_host);
       if (rc != kFallback) {
-        if (rc == DDM_OK) g_last_path = DDM_PATH_BUCKETED;
+        if (rc == DDM_OK) last_path = DDM_PATH_BUCKETED;
         return rc;
       }
-      if (g_path_request == DDM_PATH_BUCKETED) return DDM_E_UNSUPPORTED;
+      if (path_request == DDM_PATH_BUCKETED) return DDM_E_UNSUPPORTED;
       rc = run_global(c);
-      if (rc == DDM_OK || rc == DDM_E_CAPACITY) g_last_path = DDM_PATH_GLOBAL;
+      if (rc == DDM_OK || rc == DDM_E_CAPACITY) last_path = DDM_PATH_GLOBAL;
       return rc;
     }
     release(*entry);
     entry->failed = true;  // run eagerly from now on
     (void)hipGetLastError();
   }
-  if (g_path_request != DDM_PATH_GLOBAL && c.L.bucket_ok) {
+  if (path_request != DDM_PATH_GLOBAL && c.L.bucket_ok && !global_only) {
     rc = run_bucketed(c);
     if (rc != kFallback) {
-      if (rc == DDM_OK || rc == DDM_E_CAPACITY) g_last_path = DDM_PATH_BUCKETED;
+      if (rc == DDM_OK || rc == DDM_E_CAPACITY) last_path = DDM_PATH_BUCKETED;
       return rc;
     }
-    if (g_path_request == DDM_PATH_BUCKETED) return DDM_E_UNSUPPORTED;
+    if (path_request == DDM_PATH_BUCKETED) return DDM_E_UNSUPPORTED;
   }
   rc = run_global(c);
-  if (rc == DDM_OK || rc == DDM_E_CAPACITY) g_last_path = DDM_PATH_GLOBAL;
+  if (rc == DDM_OK || rc == DDM_E_CAPACITY) last_path = DDM_PATH_GLOBAL;
   return rc;
 }
 
 }  // namespace
+
+namespace ddm {
+int match_quiet(const float *upd_lo, const float *upd_hi, int64_t n, const float *sub_lo,
+                const float *sub_hi, int64_t m, int d, int mode, void *workspace, size_t ws_bytes,
+                void *stream, uint64_t *count_host, int32_t *per_update, int32_t *pairs,
+                int64_t pair_capacity) {
+  return match_entry(upd_lo, upd_hi, n, sub_lo, sub_hi, m, d, mode, workspace, ws_bytes, stream,
+                     count_host, per_update, pairs, pair_capacity, nullptr, nullptr, true, false);
+}
+}  // namespace ddm
 
 extern "C" int ddm_match(const float *upd_lo, const float *upd_hi, int64_t n, const float *sub_lo,
                          const float *sub_hi, int64_t m, int d, int mode, void *workspace,

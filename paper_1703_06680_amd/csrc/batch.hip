@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "../../include/ddm.h"
+#include "internal.h"
 #include "batch.h"
 #include "bucket_path.h"
 #include "common.h"
@@ -401,7 +402,7 @@ int enqueue(const Batch &c, hipStream_t s) {
   return DDM_OK;
 }
 
-// Instance by instance through ddm_match() (any d; the path it picks falls
+// Instance by instance through match_quiet() (any d; the path it picks falls
 // back by itself), writing the batch outputs.
 int run_each(const Batch &c, hipStream_t s, uint64_t *total_host) {
   const int64_t B = c.B;
@@ -415,7 +416,7 @@ int run_each(const Batch &c, hipStream_t s, uint64_t *total_host) {
     const int64_t u0 = c.uoff[(size_t)b], n = x.n, m = x.m;
     const int64_t room = full ? 0 : c.cap - used;
     uint64_t K = 0;
-    const int rc = ddm_match(x.ulo, x.uhi, n, x.slo, x.shi, m, c.d, c.match_mode(), c.ws,
+    const int rc = match_quiet(x.ulo, x.uhi, n, x.slo, x.shi, m, c.d, c.match_mode(), c.ws,
                              c.ws_bytes, s,
                              &K,
                              c.per_update && n > 0 ? c.per_update + u0 : nullptr,

@@ -452,11 +452,19 @@ __device__ __forceinline__ void load_group(const Group &q, bool vec, Box<D> (&bx
 
 // ------------------------------------------------------------ count pass
 
+// Boundary-state copies are admitted a wave at a time: each wave adds the
+// cells its regions reach in later columns to a 64-bit running total and
+// counts them only while the total stays within the buffer's capacity;
+// otherwise it sets the fallback flag and skips them.  So the per-cell
+// atomics stay bounded by the capacity (a few regions spanning the whole
+// swept axis would otherwise cost one per cell, twice, before the sweep saw
+// the overflow), and the 32-bit prefix sums over the sizes cannot wrap.
+// bs_size null (slab builds): no boundary state is counted.
 template <int D>
 __global__ __launch_bounds__(kThreads) void bk_count_kernel(
     uint32_t n_total, View V, const BucketParams *__restrict__ P, uint32_t *__restrict__ C,
-    uint32_t *__restrict__ bs_size, Header *__restrict__ hdr, int32_t *__restrict__ zero,
-    uint32_t zero_count) {
+    uint32_t *__restrict__ bs_size, uint32_t bs_cap, Header *__restrict__ hdr,
+    int32_t *__restrict__ zero, uint32_t zero_count) {
   extern __shared__ uint32_t hist[];
   const uint32_t inst = V.of_blk(blockIdx.x);
   const InstPlan I = V.get(inst);
@@ -471,22 +479,47 @@ __global__ __launch_bounds__(kThreads) void bk_count_kernel(
   uint32_t err = 0;
   auto count = [&](auto tag) {
     constexpr bool GR = decltype(tag)::value;
+    // rounds are uniform over the wave (the admission below is a wave sum)
+    const uint32_t lane0 = threadIdx.x & ~(uint32_t)(kWave - 1);
 #pragma unroll 2
-    for (uint32_t g = g0 + threadIdx.x; g < g1; g += kThreads) {
-      const Group q = group_of(g, I, n_total);
-      Box<D> bx[4];
-      load_group<D>(q, I.vec != 0, bx);
+    for (uint32_t gb = g0 + lane0; gb < g1; gb += kThreads) {
+      const uint32_t g = gb + (uint32_t)lane_id();
+      Cells<D> c[4];
+      uint32_t live = 0;             // rows of non-empty boxes
+      unsigned long long span = 0;   // their boundary-state cells
+      if (g < g1) {
+        const Group q = group_of(g, I, n_total);
+        Box<D> bx[4];
+        load_group<D>(q, I.vec != 0, bx);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if ((uint32_t)r >= q.rows) continue;
+          bool empty;
+          err |= box_errors<D>(bx[r], empty, I.closed);
+          if (empty) continue;
+          c[r] = cells_of<D, GR>(bx[r], p);
+          live |= 1u << r;
+          atomicAdd(&hist[cell_index<GR>(c[r].a0, c[r].c0, p)], 1u);
+          for (uint32_t y = c[r].c0 + 1; y <= c[r].c1; ++y)
+            atomicAdd(&hist[cell_index<GR>(c[r].a0, y, p)], 1u);
+          span += (unsigned long long)(c[r].a1 - c[r].a0) * (c[r].c1 - c[r].c0 + 1u);
+        }
+      }
+      if (!bs_size) continue;
+      const unsigned long long wspan = wave_sum(span);
+      if (wspan == 0ull) continue;  // uniform over the wave
+      int ok = 0;
+      if (lane_id() == 0) {
+        const unsigned long long before = atomicAdd(&hdr->bs_copies, wspan);
+        ok = before + wspan <= (unsigned long long)bs_cap;
+        if (!ok) atomicOr(&hdr->pad[0], 1u);
+      }
+      if (!__shfl(ok, 0, kWave)) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        if ((uint32_t)r >= q.rows) continue;
-        bool empty;
-        err |= box_errors<D>(bx[r], empty, I.closed);
-        if (empty) continue;
-        const Cells<D> c = cells_of<D, GR>(bx[r], p);
-        atomicAdd(&hist[cell_index<GR>(c.a0, c.c0, p)], 1u);
-        for (uint32_t y = c.c0 + 1; y <= c.c1; ++y) atomicAdd(&hist[cell_index<GR>(c.a0, y, p)], 1u);
-        for (uint32_t a = c.a0 + 1; a <= c.a1; ++a)
-          for (uint32_t y = c.c0; y <= c.c1; ++y)
+        if (!(live & (1u << r))) continue;
+        for (uint32_t a = c[r].a0 + 1; a <= c[r].a1; ++a)
+          for (uint32_t y = c[r].c0; y <= c[r].c1; ++y)
             atomicAdd(&bs_size[I.b0 + cell_index<GR>(a, y, p)], 1u);
       }
     }
@@ -578,9 +611,10 @@ __global__ __launch_bounds__(kThreads) void bk_scatter_kernel(
     uint32_t n_total, View V, const BucketParams *__restrict__ P, Offsets O,
     const uint32_t *__restrict__ SB,
     uint32_t *__restrict__ bs_cur, uint32_t bs_cap, uint32_t *__restrict__ rec,
-    uint32_t *__restrict__ bs_rec) {
+    uint32_t *__restrict__ bs_rec, const Header *__restrict__ hdr) {
   constexpr int RW = 4;
   extern __shared__ uint32_t cur[];
+  if (hdr->pad[0]) return;  // uniform: the count pass gave up (boundary state)
   const uint32_t inst = V.of_blk(blockIdx.x);
   const InstPlan I = V.get(inst);
   const BucketParams p = P[inst];
@@ -630,9 +664,10 @@ template <int D>
 __global__ __launch_bounds__(kThreads) void bk_scatter_pair_kernel(
     uint32_t n_total, View V, const BucketParams *__restrict__ P, Offsets O,
     const uint32_t *__restrict__ SB, uint32_t *__restrict__ bs_cur, uint32_t bs_cap,
-    uint32_t *__restrict__ rec, uint32_t *__restrict__ bs_rec) {
+    uint32_t *__restrict__ rec, uint32_t *__restrict__ bs_rec, const Header *__restrict__ hdr) {
   constexpr int RW = 4;
   extern __shared__ uint4 stash[];  // [max_nb] records, then tag[nb], cur[nb]
+  if (hdr->pad[0]) return;  // uniform: the count pass gave up (boundary state)
   const uint32_t inst = V.of_blk(blockIdx.x);
   const InstPlan I = V.get(inst);
   const BucketParams p = P[inst];
@@ -1315,6 +1350,9 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   const bool rows = kRows && R.cnt != nullptr && own_cnt != nullptr;
 
   if (MODE == 2 && gate && *gate == 0u) return;  // uniform over the grid
+  // the count pass gave up, or another bucket did not fit: the records may
+  // be incomplete and the host falls back (uniform over the workgroup)
+  if (!SLAB && hdr->pad[0]) return;
   const uint32_t b = blockIdx.x;
   const uint32_t inst = V.of_bucket(b);
   const InstPlan I = V.get(inst);
@@ -1594,8 +1632,8 @@ void prepare_impl(const BucketArgs &a, hipStream_t s) {
   const uint32_t grid = D >= 2 ? 1u : 0u;
   bk_plan_kernel<<<L.B, kPlanThreads, grid ? 2 * lds : 0, s>>>(p.part, p.pts, p.V, p.P, grid);
   prof::mark(s, "bucket.count");
-  bk_count_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.C, p.T + L.nb, a.hdr,
-                                                   a.zero, a.zero ? a.zero_count : 0u);
+  bk_count_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.C, p.T + L.nb, L.bs_cap,
+                                                   a.hdr, a.zero, a.zero ? a.zero_count : 0u);
   prof::mark(s, "bucket.offsets");
   bk_colscan_kernel<<<(L.nb + kColBuckets - 1) / kColBuckets, kColWaves * kWave, 0, s>>>(
       p.C, p.SB, p.T, p.V, L.nb);
@@ -1603,10 +1641,10 @@ void prepare_impl(const BucketArgs &a, hipStream_t s) {
   prof::mark(s, "bucket.scatter");
   if (L.max_nb <= kPairScatterMaxBuckets)
     bk_scatter_pair_kernel<D><<<L.nblk, kThreads, (size_t)L.max_nb * 24, s>>>(
-        L.n_total, p.V, p.P, p.O, p.SB, p.bs_cur, L.bs_cap, p.rec, p.bs_rec);
+        L.n_total, p.V, p.P, p.O, p.SB, p.bs_cur, L.bs_cap, p.rec, p.bs_rec, a.hdr);
   else
     bk_scatter_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.O, p.SB, p.bs_cur,
-                                                       L.bs_cap, p.rec, p.bs_rec);
+                                                       L.bs_cap, p.rec, p.bs_rec, a.hdr);
 }
 
 template <int DM1, int MODE>
@@ -1637,7 +1675,7 @@ void build_slabs_impl(const BucketArgs &a, const SlabBuild &sb, hipStream_t s) {
   const Clear clr{a.hdr, p.T + L.nb, p.bs_cur, L.nb, nullptr, L.B};
   bk_sample_kernel<D><<<L.nsmp, kSampleThreads, 0, s>>>(p.V, p.part, p.pts, clr);
   bk_plan_kernel<<<L.B, kPlanThreads, 0, s>>>(p.part, p.pts, p.V, p.P, 0u);  // slabs only
-  bk_count_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.C, p.T + L.nb, a.hdr,
+  bk_count_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.C, nullptr, 0u, a.hdr,
                                                    nullptr, 0u);
   bk_colscan_kernel<<<(L.nb + kColBuckets - 1) / kColBuckets, kColWaves * kWave, 0, s>>>(
       p.C, p.SB, p.T, p.V, L.nb);

@@ -21,9 +21,10 @@ struct Header {
   uint32_t nonempty;   // regions that are non-empty on every axis
   uint32_t kmin;       // min encoded lower key over non-empty regions
   uint32_t kmax;       // max encoded lower key over non-empty regions
-  uint32_t overflow;   // bucketed path: a bucket or the boundary state did not fit
-  uint32_t bs_total;   // bucketed path: boundary-state entries over all buckets
-  uint32_t pad[2];
+  // bucketed path: boundary-state copies claimed so far by the count pass
+  // (a 64-bit running total checked against the buffer's capacity)
+  unsigned long long bs_copies;
+  uint32_t pad[2];     // pad[0]: the bucketed path cannot finish (the host falls back)
   unsigned long long total;  // number of intersecting pairs
   unsigned long long aux[3];
 };

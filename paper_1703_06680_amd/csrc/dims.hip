@@ -11,6 +11,7 @@
 #include <stdint.h>
 
 #include "../../include/ddm.h"
+#include "internal.h"
 #include "common.h"
 
 namespace ddm {
@@ -81,7 +82,7 @@ extern "C" int ddm_dim_counts(const float *upd_lo, const float *upd_hi, int64_t 
     launch_column(sub_lo, sub_hi, m, d, k, sl, sh, s);
     if (hipGetLastError() != hipSuccess) return DDM_E_DEVICE;
     uint64_t K = 0;
-    const int rc = ddm_match(ul, uh, n, sl, sh, m, 1, DDM_COUNT, w, inner, stream, &K, nullptr,
+    const int rc = match_quiet(ul, uh, n, sl, sh, m, 1, DDM_COUNT, w, inner, stream, &K, nullptr,
                              nullptr, 0);
     if (rc != DDM_OK) return rc;
     counts_host[k] = K;

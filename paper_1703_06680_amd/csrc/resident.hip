@@ -34,6 +34,7 @@
 #include <new>
 
 #include "../../include/ddm.h"
+#include "internal.h"
 #include "bucket_dev.h"
 #include "bucket_path.h"
 #include "philox.h"
@@ -468,7 +469,7 @@ int build(ddm_resident &r, hipStream_t s) {
 
 // Count of the home rows by the full matching call.
 int full_match(ddm_resident &r, hipStream_t s, uint64_t *count) {
-  return ddm_match(r.home(0), r.home(1), r.n, r.home(2), r.home(3), r.m, r.d, DDM_COUNT,
+  return match_quiet(r.home(0), r.home(1), r.n, r.home(2), r.home(3), r.m, r.d, DDM_COUNT,
                    r.state + r.R.scratch, r.R.scratch_bytes, s, count, nullptr, nullptr, 0);
 }
 

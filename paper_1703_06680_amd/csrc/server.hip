@@ -20,7 +20,7 @@
 //     returned to the arena and their simulations become free.
 // Groups in different slots run on different streams and overlap on the
 // device.  The plain policy is the per-request baseline: one request at a
-// time in arrival order, each a step followed by ddm_match().  The incremental
+// time in arrival order, each a step followed by match_quiet().  The incremental
 // policy schedules like the batched one, but each simulation keeps a
 // resident state (ddm_resident_*, carved from the front of the arena when it
 // is registered) and a request is that state's step: no workspace is
@@ -38,6 +38,7 @@
 #include <vector>
 
 #include "../../include/ddm.h"
+#include "internal.h"
 #include "batch.h"
 #include "bucket_path.h"
 #include "sim.h"
@@ -307,7 +308,7 @@ extern "C" int ddm_server_run(ddm_server *sv, const int32_t *sim, const double *
       uint64_t K = 0;
       int e = launch_walk(sm.w, s.stream) == hipSuccess ? DDM_OK : DDM_E_DEVICE;
       if (e == DDM_OK)
-        e = ddm_match(sm.w.upd_lo, sm.w.upd_hi, sm.w.n, sm.w.sub_lo, sm.w.sub_hi, sm.w.m, sm.w.d,
+        e = match_quiet(sm.w.upd_lo, sm.w.upd_hi, sm.w.n, sm.w.sub_lo, sm.w.sub_hi, sm.w.m, sm.w.d,
                       DDM_COUNT, sv->arena, sv->arena_bytes, s.stream, &K, nullptr, nullptr, 0);
       if (e != DDM_OK) fail(e);
       counts[r] = K;

@@ -364,6 +364,35 @@ def test_skewed_distribution(ddm, oracle):
         check_all_modes(ddm, oracle, inst, expect_bucketed=False)
 
 
+def test_boundary_state_beyond_capacity_falls_back(ddm, oracle):
+    """2000 subscriptions reaching from a random point to past the end of
+    the swept axis and over the whole of axis 1 (d = 2, n = m = 5e5): copied
+    into the boundary state of every later bucket they would need about
+    6.5e5 entries, more than the buffer's 5.04e5.  The count pass stops
+    counting them once the total passes the capacity, the scatter and the
+    sweep stand down, and the call is answered by the device-wide path with
+    the oracle's counts.  With 1000 such subscriptions (about 3.3e5 copies)
+    the bucketed path holds them."""
+    for long_subs, path in ((2000, "global"), (1000, "bucketed")):
+        inst = W.uniform_instance(500_000, 500_000, 2, 1.0, seed=21)
+        rng = np.random.default_rng(22)
+        sel = rng.choice(inst.m, size=long_subs, replace=False)
+        inst.sub_hi[sel, 0] = 2.0e6
+        inst.sub_lo[sel, 1] = -1.0
+        inst.sub_hi[sel, 1] = 2.0e6
+        k_ref, per_ref, _ = oracle.sbm(*_host(inst), pairs=False)
+        assert k_ref >= long_subs * 100_000
+        g = _dev(inst)
+        _note(f"{long_subs} long subscriptions, per_update")
+        k, per = ddm.match(*g, mode="per_update")
+        assert (ddm.last_path(), k) == (path, k_ref)
+        assert np.array_equal(per.cpu().numpy(), per_ref)
+        _note(f"{long_subs} long subscriptions, count (graph replay)")
+        for _ in range(3):  # eager, captured, replayed
+            assert ddm.match(*g, mode="count") == k_ref
+            assert ddm.last_path() == path
+
+
 @pytest.mark.parametrize("mode", ["count", "per_update"])
 def test_repeated_call_replays_graph(ddm, oracle, mode):
     """Identical repeated calls are captured once and replayed: every replay
