@@ -119,7 +119,7 @@ struct BucketLayout {
   size_t bytes;                        // workspace bytes for all buffers below
   // byte offsets inside the bucket workspace
   size_t params, sample_part, sample_pts, counts, totals, offsets, block_offsets, scan_tmp, bs_cur,
-      rec, bs_rec, plan, maps;
+      rec, bs_rec, heavy, plan, maps;
   PlanList inst;                       // host copy of the per-instance plan
 };
 

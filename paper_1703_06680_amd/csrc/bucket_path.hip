@@ -117,6 +117,7 @@ struct Clear {
   uint32_t nb;
   unsigned long long *inst_total;
   uint32_t B;
+  uint32_t *heavy;  // the heavy-bucket list's two counters
 };
 
 template <int D>
@@ -128,6 +129,7 @@ __global__ __launch_bounds__(kSampleThreads) void bk_sample_kernel(View V,
     const uint32_t tid = blockIdx.x * kSampleThreads + threadIdx.x;
     const uint32_t stride = gridDim.x * kSampleThreads;
     if (tid < sizeof(Header) / sizeof(uint32_t)) reinterpret_cast<uint32_t *>(clr.hdr)[tid] = 0u;
+    if (tid < 2 && clr.heavy) clr.heavy[tid] = 0u;
     for (uint32_t i = tid; i <= clr.nb; i += stride) {
       clr.bs_size[i] = 0u;
       if (i < clr.nb) clr.bs_cur[i] = 0u;
@@ -452,14 +454,15 @@ __device__ __forceinline__ void load_group(const Group &q, bool vec, Box<D> (&bx
 
 // ------------------------------------------------------------ count pass
 
-// Boundary-state copies are admitted a wave at a time: each wave adds the
-// cells its regions reach in later columns to a 64-bit running total and
-// counts them only while the total stays within the buffer's capacity;
-// otherwise it sets the fallback flag and skips them.  So the per-cell
-// atomics stay bounded by the capacity (a few regions spanning the whole
-// swept axis would otherwise cost one per cell, twice, before the sweep saw
-// the overflow), and the 32-bit prefix sums over the sizes cannot wrap.
-// bs_size null (slab builds): no boundary state is counted.
+// Boundary-state copies are bounded before they are counted: a box that
+// reaches one later cell counts its copy at once (at most one per box); a
+// box that reaches more first claims them all on a 64-bit running total, and
+// counts them only while that total stays within the buffer's capacity,
+// otherwise it sets the fallback flag.  So a few boxes spanning the whole
+// swept axis cannot cost one device atomic per cell, twice, before the
+// sweep sees the overflow, and the 32-bit prefix sums over the sizes (at
+// most n + m + the capacity) cannot wrap.  bs_size null (slab builds): no
+// boundary state is counted.
 template <int D>
 __global__ __launch_bounds__(kThreads) void bk_count_kernel(
     uint32_t n_total, View V, const BucketParams *__restrict__ P, uint32_t *__restrict__ C,
@@ -479,47 +482,28 @@ __global__ __launch_bounds__(kThreads) void bk_count_kernel(
   uint32_t err = 0;
   auto count = [&](auto tag) {
     constexpr bool GR = decltype(tag)::value;
-    // rounds are uniform over the wave (the admission below is a wave sum)
-    const uint32_t lane0 = threadIdx.x & ~(uint32_t)(kWave - 1);
 #pragma unroll 2
-    for (uint32_t gb = g0 + lane0; gb < g1; gb += kThreads) {
-      const uint32_t g = gb + (uint32_t)lane_id();
-      Cells<D> c[4];
-      uint32_t live = 0;             // rows of non-empty boxes
-      unsigned long long span = 0;   // their boundary-state cells
-      if (g < g1) {
-        const Group q = group_of(g, I, n_total);
-        Box<D> bx[4];
-        load_group<D>(q, I.vec != 0, bx);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          if ((uint32_t)r >= q.rows) continue;
-          bool empty;
-          err |= box_errors<D>(bx[r], empty, I.closed);
-          if (empty) continue;
-          c[r] = cells_of<D, GR>(bx[r], p);
-          live |= 1u << r;
-          atomicAdd(&hist[cell_index<GR>(c[r].a0, c[r].c0, p)], 1u);
-          for (uint32_t y = c[r].c0 + 1; y <= c[r].c1; ++y)
-            atomicAdd(&hist[cell_index<GR>(c[r].a0, y, p)], 1u);
-          span += (unsigned long long)(c[r].a1 - c[r].a0) * (c[r].c1 - c[r].c0 + 1u);
-        }
-      }
-      if (!bs_size) continue;
-      const unsigned long long wspan = wave_sum(span);
-      if (wspan == 0ull) continue;  // uniform over the wave
-      int ok = 0;
-      if (lane_id() == 0) {
-        const unsigned long long before = atomicAdd(&hdr->bs_copies, wspan);
-        ok = before + wspan <= (unsigned long long)bs_cap;
-        if (!ok) atomicOr(&hdr->pad[0], 1u);
-      }
-      if (!__shfl(ok, 0, kWave)) continue;
+    for (uint32_t g = g0 + threadIdx.x; g < g1; g += kThreads) {
+      const Group q = group_of(g, I, n_total);
+      Box<D> bx[4];
+      load_group<D>(q, I.vec != 0, bx);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        if (!(live & (1u << r))) continue;
-        for (uint32_t a = c[r].a0 + 1; a <= c[r].a1; ++a)
-          for (uint32_t y = c[r].c0; y <= c[r].c1; ++y)
+        if ((uint32_t)r >= q.rows) continue;
+        bool empty;
+        err |= box_errors<D>(bx[r], empty, I.closed);
+        if (empty) continue;
+        const Cells<D> c = cells_of<D, GR>(bx[r], p);
+        atomicAdd(&hist[cell_index<GR>(c.a0, c.c0, p)], 1u);
+        for (uint32_t y = c.c0 + 1; y <= c.c1; ++y) atomicAdd(&hist[cell_index<GR>(c.a0, y, p)], 1u);
+        if (!bs_size || c.a1 == c.a0) continue;
+        const unsigned long long span = (unsigned long long)(c.a1 - c.a0) * (c.c1 - c.c0 + 1u);
+        if (span > 1ull && atomicAdd(&hdr->bs_copies, span) + span > (unsigned long long)bs_cap) {
+          atomicOr(&hdr->pad[0], 1u);
+          continue;
+        }
+        for (uint32_t a = c.a0 + 1; a <= c.a1; ++a)
+          for (uint32_t y = c.c0; y <= c.c1; ++y)
             atomicAdd(&bs_size[I.b0 + cell_index<GR>(a, y, p)], 1u);
       }
     }
@@ -923,6 +907,7 @@ struct Walker {
   uint32_t q;    // pre-filter walker word (d >= 2)
   uint32_t pos;  // LDS position of a bucket region, kNoPos for a boundary-state region
   bool upd;
+  float c[4];    // heavy sweep: exact lower / upper bounds of axes 1 and 2
 };
 constexpr uint32_t kNoPos = 0xFFFFFFFFu;
 
@@ -931,6 +916,18 @@ constexpr uint32_t kNoPos = 0xFFFFFFFFu;
 // latency of reading their coordinates overlaps; a full queue sends further
 // pairs through the exact test at once.
 constexpr int kQueue = 320;
+
+// The sweep comes in three kinds.  kSlabSweep: slabs of a resident
+// simulation; a pair beyond the queue's capacity gets its exact test at
+// once, on coordinates read from the rows.  kLightSweep: packed buckets; a
+// bucket whose pre-filter passes more pairs than the queue holds is not
+// counted, but listed as heavy.  kHeavySweep: the listed buckets again, with
+// the exact coordinates of their regions' axes 1 and 2 staged in LDS (one
+// row read per region instead of two per pair) and, for per-update counts,
+// the bucket's updates counted in LDS and flushed once each.
+constexpr int kSlabSweep = 0;
+constexpr int kLightSweep = 1;
+constexpr int kHeavySweep = 2;
 
 struct SweepCtx {
   InstPlan I;  // the bucket's instance: rows of its regions
@@ -954,6 +951,11 @@ struct SweepCtx {
   // rows they both reach)
   uint32_t ny = 1, row = 0;
   float vmin1 = 0.f, scale1 = 0.f;
+  // light sweep: set (LDS) once the bucket is found heavy; heavy sweep:
+  // exact bounds (lo1, hi1, lo2, hi2) and per-update counts by LDS position
+  uint32_t *heavy = nullptr;
+  const float4 *xc = nullptr;
+  uint32_t *cntl = nullptr;
 };
 
 // The row test of a pair whose axis-1 lower bounds are ly and lx; the sweep
@@ -1002,16 +1004,42 @@ __device__ __forceinline__ bool extra_axes(const SweepCtx &o, uint32_t ry, uint3
 
 // A pair of walker y and entry j that passed the key and pre-filter tests:
 // exact test on the other axes (d >= 2), then count or emit.
-template <int DM1, int MODE, bool GR>
+template <int DM1, int MODE, bool GR, int KIND>
 __device__ __forceinline__ void visit(const Walker<DM1> &y, bool &have_y, float (&ylo)[2],
                                       float (&yhi)[2], uint32_t j,
                                       const uint32_t *__restrict__ RID, unsigned long long &hits,
                                       uint32_t &own, const SweepCtx &o) {
+  if (KIND == kHeavySweep && DM1 > 0) {  // the exact test on staged coordinates
+    const float4 x = o.xc[j];
+    bool hit = before(y.c[0], x.y, o.I.closed) && before(x.x, y.c[1], o.I.closed);
+    if (DM1 >= 2) hit = hit && before(y.c[2], x.w, o.I.closed) && before(x.z, y.c[3], o.I.closed);
+    if (DM1 == 3 && hit) hit = extra_axes(o, y.rid, RID[j]);
+    if (!hit || !in_row<GR>(o, y.c[0], x.x)) return;
+    ++hits;
+    if (MODE == 1) {
+      if (y.upd)
+        ++own;
+      else
+        atomicAdd(&o.cntl[j], 1u);
+    } else if (MODE == 2) {
+      const uint32_t rx = RID[j];
+      const uint32_t uu = y.upd ? y.rid : rx;
+      const unsigned long long slot = o.pair_off[uu] + atomicAdd(&o.cursor[uu], 1u);
+      if (o.out_u) o.out_u[slot] = uu;  // null: rows are implied by the offsets
+      o.out_s[slot] = (y.upd ? rx : y.rid) - o.n;
+    }
+    return;
+  }
   const uint32_t rx = RID[j];
   if (DM1 > 0) {
+    if (KIND == kLightSweep && *o.heavy) return;  // the heavy sweep counts this bucket
     const uint32_t at = atomicAdd(o.queued, 1u);
     if (at < (uint32_t)kQueue) {
       o.queue[at] = make_uint2(y.rid, rx);
+      return;
+    }
+    if (KIND == kLightSweep) {
+      *o.heavy = 1u;
       return;
     }
     if (!have_y) {
@@ -1104,7 +1132,7 @@ __device__ __forceinline__ uint32_t min4(uint32_t a, uint32_t b, uint32_t c, uin
 // words at a time, masks the ones outside the interior and runs only the
 // pre-filter (skipping a chunk with one compare when none of the four
 // passes).
-template <int DM1, int MODE, bool GR>
+template <int DM1, int MODE, bool GR, int KIND>
 __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
                                      const uint32_t *__restrict__ RID,
                                      const uint32_t *__restrict__ Q, const Walker<DM1> &y,
@@ -1126,10 +1154,48 @@ __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
     const uint32_t k = KLO[j];
     const uint32_t fail = DM1 > 0 ? qfail<DM1>(Q[j], y.q) : 0u;
     if ((k >= y.after_key) & (k < y.khi) & (fail == 0u))
-      visit<DM1, MODE, GR>(y, have_y, ylo, yhi, j, RID, hits, own, o);
+      visit<DM1, MODE, GR, KIND>(y, have_y, ylo, yhi, j, RID, hits, own, o);
   }
   if (!split) {
     // first and last bin coincide: the edge loop has seen every entry
+  } else if (KIND == kHeavySweep && DM1 > 0 && DM1 <= 2 && MODE != 2 && !GR) {
+    // heavy bucket: the quantised pre-filter passes most entries, so every
+    // interior entry gets the exact test on its staged bounds, four at a
+    // time without branches; counts go to the walker (an update) or to the
+    // entries' LDS counters (a subscription walking updates)
+    const uint32_t closed = o.I.closed;
+    auto exact = [&](uint32_t j) {
+      const float4 x = o.xc[j];
+      bool h = before(y.c[0], x.y, closed) && before(x.x, y.c[1], closed);
+      if (DM1 >= 2) h = h && before(y.c[2], x.w, closed) && before(x.z, y.c[3], closed);
+      return h;
+    };
+    uint32_t j = jB;
+    for (; j + 4 <= jC; j += 4) {
+      const bool h0 = exact(j), h1 = exact(j + 1), h2 = exact(j + 2), h3 = exact(j + 3);
+      const uint32_t c = (uint32_t)h0 + (uint32_t)h1 + (uint32_t)h2 + (uint32_t)h3;
+      hits += c;
+      if (MODE == 1) {
+        if (y.upd) {
+          own += c;
+        } else if (c) {
+          if (h0) atomicAdd(&o.cntl[j], 1u);
+          if (h1) atomicAdd(&o.cntl[j + 1], 1u);
+          if (h2) atomicAdd(&o.cntl[j + 2], 1u);
+          if (h3) atomicAdd(&o.cntl[j + 3], 1u);
+        }
+      }
+    }
+    for (; j < jC; ++j) {
+      if (!exact(j)) continue;
+      ++hits;
+      if (MODE == 1) {
+        if (y.upd)
+          ++own;
+        else
+          atomicAdd(&o.cntl[j], 1u);
+      }
+    }
   } else if (DM1 == 0) {
     if (MODE == 0) {
       hits += jC - jB;
@@ -1142,7 +1208,7 @@ __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
         atomicAdd(&o.dl[jC], 0xFFFFFFFFu);
       }
     } else {
-      for (uint32_t j = jB; j < jC; ++j) visit<DM1, MODE, GR>(y, have_y, ylo, yhi, j, RID, hits, own, o);
+      for (uint32_t j = jB; j < jC; ++j) visit<DM1, MODE, GR, KIND>(y, have_y, ylo, yhi, j, RID, hits, own, o);
     }
   } else {
     // one aligned chunk of four: entries outside [jB, jC) get a non-zero
@@ -1158,10 +1224,10 @@ __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
         f3 |= (j + 3 < jB || j + 3 >= jC) ? 1u : 0u;
       }
       if (min4(f0, f1, f2, f3) == 0u) {
-        if (f0 == 0u) visit<DM1, MODE, GR>(y, have_y, ylo, yhi, j, RID, hits, own, o);
-        if (f1 == 0u) visit<DM1, MODE, GR>(y, have_y, ylo, yhi, j + 1, RID, hits, own, o);
-        if (f2 == 0u) visit<DM1, MODE, GR>(y, have_y, ylo, yhi, j + 2, RID, hits, own, o);
-        if (f3 == 0u) visit<DM1, MODE, GR>(y, have_y, ylo, yhi, j + 3, RID, hits, own, o);
+        if (f0 == 0u) visit<DM1, MODE, GR, KIND>(y, have_y, ylo, yhi, j, RID, hits, own, o);
+        if (f1 == 0u) visit<DM1, MODE, GR, KIND>(y, have_y, ylo, yhi, j + 1, RID, hits, own, o);
+        if (f2 == 0u) visit<DM1, MODE, GR, KIND>(y, have_y, ylo, yhi, j + 2, RID, hits, own, o);
+        if (f3 == 0u) visit<DM1, MODE, GR, KIND>(y, have_y, ylo, yhi, j + 3, RID, hits, own, o);
       }
     };
     uint32_t j = jB & ~3u;
@@ -1170,6 +1236,11 @@ __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
       j += 4;
     }
     for (; j + 8 <= jC; j += 8) {  // two chunks per step: both reads in flight
+      // a bucket found heavy is swept again by the heavy sweep: stop walking
+      if (KIND == kLightSweep && *(volatile const uint32_t *)o.heavy) {
+        j = jC;
+        break;
+      }
       const uint4 qa = reinterpret_cast<const uint4 *>(Q)[j >> 2];
       const uint4 qb = reinterpret_cast<const uint4 *>(Q)[(j >> 2) + 1];
       const uint32_t f0 = qfail<DM1>(qa.x, y.q), f1 = qfail<DM1>(qa.y, y.q);
@@ -1188,6 +1259,8 @@ __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
     if (DM1 == 0 && y.pos != kNoPos) {  // a bucket update: into its LDS entry
       atomicAdd(&o.dl[y.pos], own);
       atomicAdd(&o.dl[y.pos + 1], 0u - own);
+    } else if (KIND == kHeavySweep && y.pos != kNoPos) {
+      atomicAdd(&o.cntl[y.pos], own);
     } else {
       atomicAdd(&o.per_update[y.rid], (int)own);
     }
@@ -1305,18 +1378,25 @@ __device__ __forceinline__ void emit_rows(
     y.q = 0u;
     const uint32_t jA = bin_begin(FINE);
     const uint32_t fh = fine_of(decode_coord(y.khi - o.I.closed), vmn, fscale, FINE);
-    walk<0, 2, false>(KLO, RID, nullptr, y, jA, jA, bin_begin(FINE + fh), BIN[FINE + fh], hits, o);
+    walk<0, 2, false, kLightSweep>(KLO, RID, nullptr, y, jA, jA, bin_begin(FINE + fh),
+                                   BIN[FINE + fh], hits, o);
   }
 }
 
-template <int DM1, int MODE, int CAP, int THREADS, int FINE, bool SLAB = false>
-__global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
-    const uint32_t *__restrict__ rec, Offsets O, View V, const uint32_t *__restrict__ bs_rec,
-    uint32_t bs_cap, uint32_t n, Header *__restrict__ hdr, int32_t *__restrict__ per_update,
-    const unsigned long long *__restrict__ pair_off, uint32_t *__restrict__ cursor,
-    uint32_t *__restrict__ out_u, uint32_t *__restrict__ out_s,
+// The sweep of bucket b (every kind; see SweepCtx).  heavy: the heavy-bucket
+// list ([0] buckets listed by the count sweeps, [1] by the emitting ones,
+// then the list), filled by the light sweep.
+template <int DM1, int MODE, int CAP, int THREADS, int FINE, int KIND>
+__device__ __forceinline__ void sweep_bucket(
+    uint32_t b, const uint32_t *__restrict__ rec, const Offsets &O, const View &V,
+    const uint32_t *__restrict__ bs_rec, uint32_t bs_cap, uint32_t n, Header *__restrict__ hdr,
+    int32_t *__restrict__ per_update, const unsigned long long *__restrict__ pair_off,
+    uint32_t *__restrict__ cursor, uint32_t *__restrict__ out_u, uint32_t *__restrict__ out_s,
     unsigned long long *__restrict__ total, unsigned long long *__restrict__ inst_total,
-    const uint32_t *__restrict__ gate, uint32_t *__restrict__ own_cnt, RowEmit R) {
+    const uint32_t *__restrict__ gate, uint32_t *__restrict__ own_cnt, const RowEmit &R,
+    uint32_t *__restrict__ heavy) {
+  constexpr bool SLAB = KIND == kSlabSweep;
+  constexpr bool HV = KIND == kHeavySweep && DM1 > 0;
   constexpr int ITEMS = CAP / THREADS;
   constexpr int W = THREADS / kWave;
   constexpr int NBINS = 2 * FINE;
@@ -1332,8 +1412,10 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   __shared__ float redf[2 * W + 2];
   __shared__ uint32_t red[W + 2];
   __shared__ unsigned long long red64[W];
-  __shared__ uint2 queue[DM1 > 0 ? kQueue : 1];
-  __shared__ uint32_t queued;
+  __shared__ uint2 queue[DM1 > 0 && !HV ? kQueue : 1];
+  __shared__ uint32_t queued, heavy_flag;
+  __shared__ float4 XC[HV ? CAP + kPad : 1];
+  __shared__ uint32_t CNTL[HV && MODE == 1 ? CAP + kPad : 1];
   // d = 1: the per-position array DL of the count pass and of the
   // pair-by-pair emission, or, for the emission by rows, one row stage per
   // wave and the bucket's boundary-state subscriptions (upper key, region);
@@ -1353,7 +1435,6 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   // the count pass gave up, or another bucket did not fit: the records may
   // be incomplete and the host falls back (uniform over the workgroup)
   if (!SLAB && hdr->pad[0]) return;
-  const uint32_t b = blockIdx.x;
   const uint32_t inst = V.of_bucket(b);
   const InstPlan I = V.get(inst);
   uint32_t start, C, bs_begin, nbs;
@@ -1377,6 +1458,9 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   }
   const int t = threadIdx.x;
   SweepCtx o{I, n, per_update, pair_off, cursor, out_u, out_s, queue, &queued, DL, own_cnt};
+  o.heavy = &heavy_flag;
+  o.xc = XC;
+  o.cntl = CNTL;
   if (DM1 > 0 && !SLAB && O.P) {
     const BucketParams &bp = O.P[inst];
     if (bp.ny > 1) {
@@ -1412,10 +1496,13 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
     for (int k = t; k < CAP + kPad; k += THREADS) DL[k] = 0;
   if (t == 0) {
     queued = 0;
+    heavy_flag = 0;
     nbsub = 0;
     maxspan = 0;
     maxbsh = 0;
   }
+  if (HV && MODE == 1)
+    for (int k = t; k < CAP + kPad; k += THREADS) CNTL[k] = 0;
   if (t < kPad) {  // defined values in the padding (never counted)
     KLO[CAP + t] = 0;
     if (DM1 > 0) Q[CAP + t] = 0;
@@ -1473,6 +1560,18 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
       KHI[qpos] = rk[i].y;
       RID[qpos] = rk[i].z;
       if (DM1 > 0) Q[qpos] = entry_word<DM1>(rk[i].w);
+      key[i] = qpos;
+    }
+  }
+  if (HV) {  // the exact bounds of axes 1 and 2 of every region, one row read each
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const uint32_t s = t + i * THREADS;
+      if (s < C) {
+        float lo[2] = {0.f, 0.f}, hi[2] = {0.f, 0.f};
+        other_axes<DM1>(o, rk[i].z, lo, hi);
+        XC[key[i]] = make_float4(lo[0], hi[0], lo[1], hi[1]);
+      }
     }
   }
   __syncthreads();
@@ -1497,6 +1596,7 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
     for (uint32_t base = (uint32_t)w * kWave; base < walkers; base += (uint32_t)THREADS) {
       const uint32_t q = base + (uint32_t)lane;
       if (q >= walkers) continue;
+      if (KIND == kLightSweep && DM1 > 0 && *(volatile const uint32_t *)&heavy_flag) break;
       Walker<DM1> y;
       uint32_t jA, jB;
       if (q < C) {  // a region of the bucket, from its own bin
@@ -1507,6 +1607,13 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
         y.upd = q < Cu;
         y.after_key = y.upd ? y.klo : y.klo + 1u;
         y.q = DM1 > 0 ? walker_from_entry<DM1>(Q[q]) : 0u;
+        if (HV) {
+          const float4 x = XC[q];
+          y.c[0] = x.x;
+          y.c[1] = x.y;
+          y.c[2] = x.z;
+          y.c[3] = x.w;
+        }
         const uint32_t fl = fine_of(decode_coord(y.klo), vmn, fscale, FINE);
         const uint32_t other = y.upd ? (uint32_t)FINE : 0u;
         jA = bin_begin(other + fl);
@@ -1520,11 +1627,19 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
         y.upd = yr.z < n;
         y.after_key = 0u;
         y.q = DM1 > 0 ? walker_word<DM1>(yr.w) : 0u;
+        if (HV) {
+          float lo[2] = {0.f, 0.f}, hi[2] = {0.f, 0.f};
+          other_axes<DM1>(o, y.rid, lo, hi);
+          y.c[0] = lo[0];
+          y.c[1] = hi[0];
+          y.c[2] = lo[1];
+          y.c[3] = hi[1];
+        }
         jA = jB = bin_begin(y.upd ? (uint32_t)FINE : 0u);
       }
       const uint32_t fh = fine_of(decode_coord(y.khi - I.closed), vmn, fscale, FINE);
       const uint32_t last = (y.upd ? (uint32_t)FINE : 0u) + fh;
-      walk<DM1, MODE, GR>(KLO, RID, Q, y, jA, jB, bin_begin(last), BIN[last], hits, o);
+      walk<DM1, MODE, GR, KIND>(KLO, RID, Q, y, jA, jB, bin_begin(last), BIN[last], hits, o);
     }
     if (DM1 == 0 && MODE == 1) {
       // 4. d = 1: the pairs of each bucket update found here, by a prefix sum
@@ -1550,12 +1665,20 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
         }
       }
     }
-    if (DM1 > 0) {  // 4. the exact test of the queued pairs, all at once
+    if (HV && MODE == 1) {  // 4. the bucket's updates: their counts, once each
       __syncthreads();
-      const uint32_t nq = min(queued, (uint32_t)kQueue);
-      for (uint32_t k = t; k < nq; k += THREADS) {
-        const uint2 pr = queue[k];
-        resolve<DM1, MODE, GR>(pr.x, pr.y, hits, o);
+      for (uint32_t j = t; j < Cu; j += THREADS)
+        if (CNTL[j]) atomicAdd(&per_update[RID[j]], (int)CNTL[j]);
+    } else if (DM1 > 0 && !HV) {  // 4. the exact test of the queued pairs, all at once
+      __syncthreads();
+      if (KIND == kLightSweep && heavy_flag) {  // uniform: listed, counted by the heavy sweep
+        if (t == 0) heavy[2 + atomicAdd(&heavy[MODE == 2 ? 1 : 0], 1u)] = b;
+      } else {
+        const uint32_t nq = min(queued, (uint32_t)kQueue);
+        for (uint32_t k = t; k < nq; k += THREADS) {
+          const uint2 pr = queue[k];
+          resolve<DM1, MODE, GR>(pr.x, pr.y, hits, o);
+        }
       }
     }
   };
@@ -1576,11 +1699,43 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
   }
 }
 
+template <int DM1, int MODE, int CAP, int THREADS, int FINE, bool SLAB = false>
+__global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
+    const uint32_t *__restrict__ rec, Offsets O, View V, const uint32_t *__restrict__ bs_rec,
+    uint32_t bs_cap, uint32_t n, Header *__restrict__ hdr, int32_t *__restrict__ per_update,
+    const unsigned long long *__restrict__ pair_off, uint32_t *__restrict__ cursor,
+    uint32_t *__restrict__ out_u, uint32_t *__restrict__ out_s,
+    unsigned long long *__restrict__ total, unsigned long long *__restrict__ inst_total,
+    const uint32_t *__restrict__ gate, uint32_t *__restrict__ own_cnt, RowEmit R,
+    uint32_t *__restrict__ heavy) {
+  sweep_bucket<DM1, MODE, CAP, THREADS, FINE, SLAB ? kSlabSweep : kLightSweep>(
+      blockIdx.x, rec, O, V, bs_rec, bs_cap, n, hdr, per_update, pair_off, cursor, out_u, out_s,
+      total, inst_total, gate, own_cnt, R, heavy);
+}
+
+// The heavy buckets the light sweep listed, a workgroup at a time.
+template <int DM1, int MODE, int CAP, int THREADS, int FINE>
+__global__ __launch_bounds__(THREADS) void bk_heavy_sweep_kernel(
+    const uint32_t *__restrict__ rec, Offsets O, View V, const uint32_t *__restrict__ bs_rec,
+    uint32_t bs_cap, uint32_t n, Header *__restrict__ hdr, int32_t *__restrict__ per_update,
+    const unsigned long long *__restrict__ pair_off, uint32_t *__restrict__ cursor,
+    uint32_t *__restrict__ out_u, uint32_t *__restrict__ out_s,
+    unsigned long long *__restrict__ total, unsigned long long *__restrict__ inst_total,
+    const uint32_t *__restrict__ gate, uint32_t *__restrict__ heavy) {
+  const uint32_t listed = heavy[MODE == 2 ? 1 : 0];
+  for (uint32_t i = blockIdx.x; i < listed; i += gridDim.x) {  // uniform
+    sweep_bucket<DM1, MODE, CAP, THREADS, FINE, kHeavySweep>(
+        heavy[2 + i], rec, O, V, bs_rec, bs_cap, n, hdr, per_update, pair_off, cursor, out_u,
+        out_s, total, inst_total, gate, nullptr, RowEmit{}, heavy);
+    __syncthreads();  // LDS is reused by the next bucket
+  }
+}
+
 struct Ptrs {
   BucketParams *P;
   float *part;
   float2 *pts;
-  uint32_t *C, *T, *S, *SB, *bs_cur, *rec, *bs_rec;
+  uint32_t *C, *T, *S, *SB, *bs_cur, *rec, *bs_rec, *heavy;
   void *scan_tmp;
   Offsets O;
   View V;
@@ -1600,6 +1755,7 @@ Ptrs pointers(const BucketArgs &a) {
   p.bs_cur = reinterpret_cast<uint32_t *>(ws + L.bs_cur);
   p.rec = reinterpret_cast<uint32_t *>(ws + L.rec);
   p.bs_rec = reinterpret_cast<uint32_t *>(ws + L.bs_rec);
+  p.heavy = reinterpret_cast<uint32_t *>(ws + L.heavy);
   p.scan_tmp = ws + L.scan_tmp;
   p.O.S = p.S;
   p.O.nb = L.nb;
@@ -1627,7 +1783,7 @@ void prepare_impl(const BucketArgs &a, hipStream_t s) {
   Ptrs p = pointers(a);
   const size_t lds = (size_t)L.max_nb * sizeof(uint32_t);
   prof::mark(s, "bucket.sample");
-  const Clear clr{a.hdr, p.T + L.nb, p.bs_cur, L.nb, a.inst_total, L.B};
+  const Clear clr{a.hdr, p.T + L.nb, p.bs_cur, L.nb, a.inst_total, L.B, p.heavy};
   bk_sample_kernel<D><<<L.nsmp, kSampleThreads, 0, s>>>(p.V, p.part, p.pts, clr);
   const uint32_t grid = D >= 2 ? 1u : 0u;
   bk_plan_kernel<<<L.B, kPlanThreads, grid ? 2 * lds : 0, s>>>(p.part, p.pts, p.V, p.P, grid);
@@ -1653,18 +1809,37 @@ void sweep_impl(const BucketArgs &a, int32_t *per_update, const unsigned long lo
                 hipStream_t s, const uint32_t *gate) {
   const BucketLayout &L = *a.L;
   Ptrs p = pointers(a);
-  if (L.tune.sweep_threads == 1024)
+  // the light sweep of every bucket, then (d >= 2) the heavy sweep of those
+  // it listed: two workgroups per CU (one with 1024 threads), looping
+  const uint32_t hgrid = std::max<uint32_t>(1, std::min<uint32_t>(L.nb, 512));
+  if (L.tune.sweep_threads == 1024) {
     bk_sweep_kernel<DM1, MODE, kBigCap, 1024, 1024><<<L.nb, 1024, 0, s>>>(
         p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
-        out_u, out_s, total, a.inst_total, gate, a.own, a.rows);
-  else if (L.tune.sweep_threads == 256)
+        out_u, out_s, total, a.inst_total, gate, a.own, a.rows, p.heavy);
+    if (DM1 > 0) prof::mark(s, MODE == 2 ? "bucket.sweep.emit.heavy" : "bucket.sweep.heavy");
+    if (DM1 > 0)
+      bk_heavy_sweep_kernel<DM1, MODE, kBigCap, 1024, 1024><<<(hgrid + 1) / 2, 1024, 0, s>>>(
+          p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
+          out_u, out_s, total, a.inst_total, gate, p.heavy);
+  } else if (L.tune.sweep_threads == 256) {
     bk_sweep_kernel<DM1, MODE, kCap, 256, 512><<<L.nb, 256, 0, s>>>(
         p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
-        out_u, out_s, total, a.inst_total, gate, a.own, a.rows);
-  else
+        out_u, out_s, total, a.inst_total, gate, a.own, a.rows, p.heavy);
+    if (DM1 > 0) prof::mark(s, MODE == 2 ? "bucket.sweep.emit.heavy" : "bucket.sweep.heavy");
+    if (DM1 > 0)
+      bk_heavy_sweep_kernel<DM1, MODE, kCap, 256, 512><<<hgrid, 256, 0, s>>>(
+          p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
+          out_u, out_s, total, a.inst_total, gate, p.heavy);
+  } else {
     bk_sweep_kernel<DM1, MODE, kCap, 512, 512><<<L.nb, 512, 0, s>>>(
         p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
-        out_u, out_s, total, a.inst_total, gate, a.own, a.rows);
+        out_u, out_s, total, a.inst_total, gate, a.own, a.rows, p.heavy);
+    if (DM1 > 0) prof::mark(s, MODE == 2 ? "bucket.sweep.emit.heavy" : "bucket.sweep.heavy");
+    if (DM1 > 0)
+      bk_heavy_sweep_kernel<DM1, MODE, kCap, 512, 512><<<hgrid, 512, 0, s>>>(
+          p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
+          out_u, out_s, total, a.inst_total, gate, p.heavy);
+  }
 }
 
 template <int D>
@@ -1672,7 +1847,7 @@ void build_slabs_impl(const BucketArgs &a, const SlabBuild &sb, hipStream_t s) {
   const BucketLayout &L = *a.L;
   Ptrs p = pointers(a);
   const size_t lds = (size_t)L.max_nb * sizeof(uint32_t);
-  const Clear clr{a.hdr, p.T + L.nb, p.bs_cur, L.nb, nullptr, L.B};
+  const Clear clr{a.hdr, p.T + L.nb, p.bs_cur, L.nb, nullptr, L.B, nullptr};
   bk_sample_kernel<D><<<L.nsmp, kSampleThreads, 0, s>>>(p.V, p.part, p.pts, clr);
   bk_plan_kernel<<<L.B, kPlanThreads, 0, s>>>(p.part, p.pts, p.V, p.P, 0u);  // slabs only
   bk_count_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.C, nullptr, 0u, a.hdr,
@@ -1702,7 +1877,7 @@ void sweep_slabs_impl(const SlabSweep &w, hipStream_t s) {
   O.bs_slab = w.bs_slab;
   bk_sweep_kernel<DM1, 0, kCap, 512, 512, true><<<w.nb, 512, 0, s>>>(
       w.rec, O, V, w.bs_rec, 0u, w.nv, w.hdr, nullptr, nullptr, nullptr, nullptr, nullptr,
-      &w.hdr->total, nullptr, nullptr, nullptr, RowEmit{});
+      &w.hdr->total, nullptr, nullptr, nullptr, RowEmit{}, nullptr);
 }
 
 // Host-side plan of one instance; returns false if it does not fit.
@@ -1817,6 +1992,7 @@ BucketLayout bucket_layout(const InstSpec *inst, int64_t B, int d, const BucketT
   L.bs_cur = take((size_t)std::max<uint32_t>(L.nb, 1) * sizeof(uint32_t));
   L.rec = take((size_t)L.rec_cap * L.rec_words * sizeof(uint32_t));
   L.bs_rec = take((size_t)L.bs_cap * L.rec_words * sizeof(uint32_t));
+  L.heavy = take(((size_t)L.nb + 2) * sizeof(uint32_t));
   L.plan = take(B > 1 ? (size_t)B * sizeof(InstPlan) : 0);
   L.maps = take(B > 1 ? ((size_t)L.nblk + L.nsmp + L.nb) * sizeof(uint32_t) : 0);
   L.bytes = at;

@@ -238,6 +238,18 @@ def test_correlated_d3_stress(ddm, oracle, alpha):
     check_all_modes(ddm, oracle, inst)
 
 
+def test_heavy_buckets_grid_and_closed(ddm, oracle):
+    """Buckets whose quantised pre-filter passes more pairs than the sweep's
+    queue holds are listed and swept again with the exact bounds of axes 1
+    and 2 staged on chip (per-update counts from the updates' side): the
+    correlated boxes as closed boxes, and dense d = 2 boxes on a grid of
+    cells (thousands of true matches per cell, counted in one row)."""
+    inst = W.correlated_d3(150_000, 100.0, seed=4)
+    check_all_modes(ddm, oracle, inst, closed=True, expect_bucketed=True)
+    dense = W.uniform_instance(200_000, 200_000, 2, 2000.0, seed=6)
+    check_all_modes(ddm, oracle, dense, expect_bucketed=True)
+
+
 # ------------------------------------------------------------- edge cases
 
 def _t(a, d=1):
