@@ -463,6 +463,8 @@ def main():
                     help="skip the per-phase event timing (roofline becomes null)")
     ap.add_argument("--no-closed", action="store_true",
                     help="skip the closed-interval measurement of the headline workload")
+    ap.add_argument("--no-skewed", action="store_true",
+                    help="skip the skewed-placement (log-uniform, clustered) steps")
     ap.add_argument("--no-correlated", action="store_true",
                     help="skip the correlated d=3 stress measurement (many true matches)")
     ap.add_argument("--no-heavy", action="store_true",
@@ -649,6 +651,47 @@ def main():
                       "matches": kc, "path": path_c, "phases_ms": ph,
                       "counts_consistent": consistent}
         del gc
+    skewed = None
+    if not args.no_skewed:
+        # the headline shape with skewed lower corners (six decades of
+        # log-uniform placement; 16 normal clusters), same 1-D overlap degree:
+        # the overfull buckets of the sampled linear map are split by their
+        # exact totals; the per-update counts are checked against the pairs
+        # the d = 1 match of each axis bounds
+        skewed = {}
+        for kind, make in (("loguniform", W.loguniform_boxes), ("clustered", W.clustered_boxes)):
+            si = make(n, m, d, args.alpha, seed=0)
+            gs = [torch.from_numpy(x).to(dev) for x in (si.upd_lo, si.upd_hi, si.sub_lo, si.sub_hi)]
+            call = lambda: ddm.match_into(*gs, mode=args.mode, workspace=ws,  # noqa: E731
+                                          per_update=per if args.mode == "per_update" else None,
+                                          stream=stream)
+            for _ in range(args.warmup):
+                ks = call()
+            torch.cuda.synchronize()
+            tsk = time.perf_counter()
+            for _ in range(args.steps):
+                ks = call()
+            torch.cuda.synchronize()
+            dts = (time.perf_counter() - tsk) / args.steps
+            path_s = ddm.last_path()
+            ddm.profile(True)
+            call()
+            torch.cuda.synchronize()
+            ph = {p: round(v["ms"], 4) for p, v in sorted(ddm.profile_report().items())}
+            ddm.profile(False)
+            ok = ks <= min(ddm.dim_counts(*gs))
+            if args.mode == "per_update":
+                ok = ok and ks == int(per.sum())
+            skewed[kind] = {"workload": f"{si.name}: lower corners "
+                                        + ("log-uniform over six decades, sides proportional"
+                                           if kind == "loguniform" else
+                                           "in 16 normal clusters (sigma 2e4)")
+                                        + f", {args.mode} output",
+                            "ms_per_step": round(dts * 1e3, 4), "value": round(regions / dts, 1),
+                            "vs_uniform_step": round(dts * 1e3 / ms_per_step, 3),
+                            "matches": ks, "path": path_s, "phases_ms": ph,
+                            "counts_consistent": ok}
+            del gs
     closed = None
     if not args.no_closed:
         # the headline inputs as closed boxes [lo, hi]; checked against the
@@ -732,6 +775,7 @@ def main():
         "per_alpha": per_alpha,
         "closed": closed,
         "correlated": correlated,
+        "skewed": skewed,
         "served_p50_ms": served["levels"]["1x"]["batched"]["p50_ms"] if served else None,
         "served_p99_ms": served["levels"]["1x"]["batched"]["p99_ms"] if served else None,
         "served_incremental_p50_ms":

@@ -130,6 +130,7 @@ int bit_length(uint32_t x) { return x ? 32 - __builtin_clz(x) : 0; }
   } while (0)
 
 constexpr int kFallback = 1;  // internal: the bucketed path asks for the other one
+constexpr int kSplit = 2;     // internal: a replayed attempt overflowed buckets that can be split
 
 template <typename T>
 T *at(void *ws, size_t off) {
@@ -284,7 +285,9 @@ int finish_pairs(const Call &c, unsigned long long K, Emit emit, bool bucketed) 
 }
 
 // ------------------------------------------------------- bucketed path
-int run_bucketed(const Call &c) {
+// ``replayed``: the first attempt already ran (a replayed graph) and failed
+// with splittable buckets; only the split attempt is made.
+int run_bucketed(const Call &c, bool replayed = false) {
   BucketArgs a{};
   a.d = c.d;
   a.ws = at<void>(c.ws, c.L.region);
@@ -296,16 +299,39 @@ int run_bucketed(const Call &c) {
   // d = 1 pairs: the count pass records each update's own-bucket pairs, so
   // that the emitting pass needs device-wide cursors only for the rest
   a.own = c.mode == DDM_PAIRS && c.d == 1 ? at<uint32_t>(c.ws, c.L.own) : nullptr;
-  DDM_HIP(bucket_prepare(a, c.s));
   const int count_mode = c.mode == DDM_COUNT ? 0 : 1;
-  DDM_HIP(bucket_sweep(a, count_mode, c.cnt, nullptr, nullptr, nullptr, nullptr, &c.hdr->total,
-                       c.s));
   Header h{};
-  prof::end(c.s);
-  DDM_HIP(hipMemcpyAsync(&h, c.hdr, sizeof(Header), hipMemcpyDeviceToHost, c.s));
-  DDM_HIP(hipStreamSynchronize(c.s));
-  prof::flush();
+  auto header = [&]() -> int {
+    prof::end(c.s);
+    DDM_HIP(hipMemcpyAsync(&h, c.hdr, sizeof(Header), hipMemcpyDeviceToHost, c.s));
+    DDM_HIP(hipStreamSynchronize(c.s));
+    prof::flush();
+    return DDM_OK;
+  };
+  if (!replayed) {
+    DDM_HIP(bucket_prepare(a, c.s));
+    DDM_HIP(bucket_sweep(a, count_mode, c.cnt, nullptr, nullptr, nullptr, nullptr,
+                         &c.hdr->total, c.s));
+  }
+  int rc = header();
+  if (rc != DDM_OK) return rc;
   if (h.err) return DDM_E_INVAL;
+  // buckets that held more records than a sweep workgroup can: split them
+  // (their totals are known now) and count, scatter and sweep again
+  BucketLayout split;
+  if (h.pad[0] && h.pad[1] == kSplittable && c.L.B.nb_split > c.L.B.nb) {
+    DDM_HIP(bucket_split(a, c.s));
+    rc = header();
+    if (rc != DDM_OK) return rc;
+    if (h.split_nb == 0) return kFallback;
+    split = split_layout(c.L.B, h.split_nb);
+    a.L = &split;
+    DDM_HIP(bucket_prepare_split(a, c.s));
+    DDM_HIP(bucket_sweep(a, count_mode, c.cnt, nullptr, nullptr, nullptr, nullptr,
+                         &c.hdr->total, c.s));
+    rc = header();
+    if (rc != DDM_OK) return rc;
+  }
   if (h.pad[0]) return kFallback;
   *c.count_host = h.total;
   if (c.mode != DDM_PAIRS || (h.total == 0 && !c.csr_off)) return DDM_OK;
@@ -483,7 +509,7 @@ int replay(const CachedGraph &e, hipStream_t s, uint64_t *count_host) {
   Header h;
   memcpy(&h, e.hdr_host, sizeof(Header));  // written by the graph's copy, complete after the sync
   if (h.err) return DDM_E_INVAL;
-  if (h.pad[0]) return kFallback;
+  if (h.pad[0]) return h.pad[1] == kSplittable ? kSplit : kFallback;
   *count_host = h.total;
   return DDM_OK;
 }
@@ -560,7 +586,7 @@ int match_entry(const float *upd_lo, const float *upd_hi, int64_t n, const float
                      mode == DDM_COUNT ? nullptr : per_update};
   std::unique_lock<std::mutex> cache_lock(g_graph_mu, std::defer_lock);
   CachedGraph *entry = nullptr;
-  bool global_only = false;
+  bool global_only = false, replayed = false;
   if (graphable) {
     cache_lock.lock();
     for (CachedGraph &e : g_graphs)
@@ -569,13 +595,16 @@ int match_entry(const float *upd_lo, const float *upd_hi, int64_t n, const float
       entry->used = ++g_graph_tick;
       *count_host = 0;
       const int rc = replay(*entry, static_cast<hipStream_t>(stream), count_host);
-      if (rc != kFallback) {
+      if (rc != kFallback && rc != kSplit) {
         last_path = rc == DDM_OK ? DDM_PATH_BUCKETED : 0;
         return rc;
       }
-      if (path_request == DDM_PATH_BUCKETED) return DDM_E_UNSUPPORTED;
       entry = nullptr;
-      global_only = true;  // the replay did the bucketed attempt: the device-wide path below
+      // the replay made the first bucketed attempt: split its buckets below,
+      // or go to the device-wide path
+      replayed = rc == kSplit;
+      global_only = !replayed;
+      if (global_only && path_request == DDM_PATH_BUCKETED) return DDM_E_UNSUPPORTED;
     } else if (!entry) {  // first sighting: remember the call, run it eagerly
       if (g_graphs.size() >= kGraphCache) {
         size_t old = 0;
@@ -631,9 +660,16 @@ int match_entry(const float *upd_lo, const float *upd_hi, int64_t n, const float
     entry->used = ++g_graph_tick;
     if (capture(*entry, c)) {
       rc = replay(*entry, c.s, count_host);
-      if (rc != kFallback) {
+      if (rc != kFallback && rc != kSplit) {
         if (rc == DDM_OK) last_path = DDM_PATH_BUCKETED;
         return rc;
+      }
+      if (rc == kSplit) {
+        rc = run_bucketed(c, true);
+        if (rc != kFallback) {
+          if (rc == DDM_OK) last_path = DDM_PATH_BUCKETED;
+          return rc;
+        }
       }
       if (path_request == DDM_PATH_BUCKETED) return DDM_E_UNSUPPORTED;
       rc = run_global(c);
@@ -645,7 +681,7 @@ int match_entry(const float *upd_lo, const float *upd_hi, int64_t n, const float
     (void)hipGetLastError();
   }
   if (path_request != DDM_PATH_GLOBAL && c.L.bucket_ok && !global_only) {
-    rc = run_bucketed(c);
+    rc = run_bucketed(c, replayed);
     if (rc != kFallback) {
       if (rc == DDM_OK || rc == DDM_E_CAPACITY) last_path = DDM_PATH_BUCKETED;
       return rc;

@@ -26,6 +26,10 @@ struct BucketParams {
   uint32_t nx, ny;   // columns, rows per column
   float vmin1;       // row map of axis 1's lower coordinate (ny > 1)
   float scale1;
+  // split buckets (slabs only): if not null, column a of the map above became
+  // the buckets split[a].x .. split[a].x + split[a].y - 1, by a map linear in
+  // the encoded coordinate from split[a].z with scale __uint_as_float(split[a].w)
+  const uint4 *split;
 };
 
 // bucket(x) = clamp(floor((x - vmin) * scale), 0, nb - 1): monotone
@@ -35,6 +39,20 @@ __device__ __forceinline__ uint32_t bucket_of(float x, float vmin, float scale, 
   float t = (x - vmin) * scale;
   t = fminf(fmaxf(t, 0.0f), (float)(nb - 1));
   return (uint32_t)t;
+}
+
+// The bucket of swept-axis coordinate x in column a of a split map: the
+// column's first bucket plus floor((enc(x) - z) * scale), clamped to the
+// column's buckets.  Encoding, subtraction (clamped at 0), conversion to
+// float and scaling are all non-decreasing, so the map stays monotone and
+// the columns stay consecutive segments.
+__device__ __forceinline__ uint32_t split_of(float x, uint32_t a, const uint4 *__restrict__ split) {
+  const uint4 r = split[a];
+  if (r.y <= 1u) return r.x;
+  const long long off = (long long)encode_coord(x) - (long long)r.z;
+  float t = (float)(off > 0 ? off : 0ll) * __uint_as_float(r.w);
+  t = fminf(t, (float)(r.y - 1u));
+  return r.x + (uint32_t)t;
 }
 
 template <int D>
@@ -72,7 +90,8 @@ __device__ __forceinline__ uint32_t cell_index(uint32_t a, uint32_t c, const Buc
 // The cell of a box's record and its row: (a0 * ny + c0, c0).
 template <int D, bool GRID>
 __device__ __forceinline__ uint2 home_of(const Box<D> &b, const BucketParams &p) {
-  const uint32_t a = bucket_of(b.lo[0], p.vmin, p.scale, p.nx);
+  uint32_t a = bucket_of(b.lo[0], p.vmin, p.scale, p.nx);
+  if (p.split) a = split_of(b.lo[0], a, p.split);  // slabs only (ny = 1)
   uint32_t c = 0u;
   if (GRID && D >= 2) c = bucket_of(b.lo[1 % D], p.vmin1, p.scale1, p.ny);
   return make_uint2(cell_index<GRID>(a, c, p), c);
@@ -83,6 +102,10 @@ __device__ __forceinline__ Cells<D> cells_of(const Box<D> &b, const BucketParams
   Cells<D> c;
   c.a0 = bucket_of(b.lo[0], p.vmin, p.scale, p.nx);
   c.a1 = bucket_of(b.hi[0], p.vmin, p.scale, p.nx);
+  if (p.split) {  // slabs only (ny = 1)
+    c.a0 = split_of(b.lo[0], c.a0, p.split);
+    c.a1 = split_of(b.hi[0], c.a1, p.split);
+  }
   c.c0 = c.c1 = 0u;
   if (GRID && D >= 2) {
     c.c0 = bucket_of(b.lo[1 % D], p.vmin1, p.scale1, p.ny);

@@ -110,6 +110,7 @@ struct BucketLayout {
   uint32_t B;                          // instances
   uint32_t nb, nblk, nsmp;             // totals over the instances
   uint32_t max_nb;                     // most buckets of one instance
+  uint32_t nb_split;                   // room for buckets after a split (one instance)
   uint32_t n_total, m_total;           // updates, subscriptions over the instances
   uint32_t bs_cap;                     // capacity of the boundary-state record buffer
   uint32_t rec_cap;                    // capacity of the record buffer (even)
@@ -119,7 +120,7 @@ struct BucketLayout {
   size_t bytes;                        // workspace bytes for all buffers below
   // byte offsets inside the bucket workspace
   size_t params, sample_part, sample_pts, counts, totals, offsets, block_offsets, scan_tmp, bs_cur,
-      rec, bs_rec, heavy, plan, maps;
+      rec, bs_rec, heavy, split, plan, maps;
   PlanList inst;                       // host copy of the per-instance plan
 };
 
@@ -161,6 +162,20 @@ hipError_t bucket_upload_plan(const BucketArgs &a, hipStream_t s, void *pinned =
 // per-instance totals and a.zero itself (so the outputs need no clearing
 // beforehand).
 hipError_t bucket_prepare(const BucketArgs &a, hipStream_t s);
+
+// Splitting overfull buckets (one instance, slabs).  When an attempt fails
+// only because some buckets hold more records than a sweep workgroup can
+// (Header::pad[1] == kSplittable), bucket_split() enqueues the split plan:
+// every overfull column becomes several consecutive buckets under a map that
+// stays monotone, and Header::split_nb receives the new bucket count (0: no
+// split is possible; the caller falls back).  With split_layout(L, split_nb)
+// as the layout, bucket_prepare_split() then enqueues the count, offsets and
+// scatter of the split map, and bucket_sweep() the sweep, as for a first
+// attempt; the map, the validation and the cleared outputs of the first
+// attempt are reused.
+hipError_t bucket_split(const BucketArgs &a, hipStream_t s);
+BucketLayout split_layout(const BucketLayout &L, uint32_t nb);
+hipError_t bucket_prepare_split(const BucketArgs &a, hipStream_t s);
 
 // Enqueue the per-bucket sweep.  mode 0: totals only; 1: totals and
 // per-update counts (per_update zeroed beforehand, indexed by the update's

@@ -163,7 +163,7 @@ __global__ __launch_bounds__(kSampleThreads) void bk_sample_kernel(View V,
     if (D >= 2) v[3] = b.hi[1 % D] - b.lo[1 % D];
     v[8] = b.hi[0] - b.lo[0];
   }
-  if (D >= 2) {  // the sampled lower corner on the swept axis and axis 1, for the plan
+  {  // the sampled lower corner on the swept axis and axis 1, for the plan and bucket splits
     const float nan = __int_as_float(0x7fc00000);
     pts[i] = ok ? make_float2(b.lo[0], b.lo[1 % D]) : make_float2(nan, nan);
   }
@@ -265,6 +265,7 @@ __device__ void block_plan(const float *__restrict__ part, const InstPlan &I, bo
       ext0 += sred[j][8];
     }
     BucketParams q;
+    q.split = nullptr;
     q.nb = I.nb;
     q.vmin = 0.f;
     q.scale = 0.f;
@@ -334,7 +335,7 @@ __device__ void block_plan(const float *__restrict__ part, const InstPlan &I, bo
 // A grid (grid != 0, d >= 2) is kept if the sampled corners' sum of squared
 // cell counts, which grows as they crowd into fewer cells, is at most 5/4 of
 // the slab map's: inputs whose axis-1 corners follow their swept-axis ones
-// (which fill only a diagonal of the grid) keep the slabs.  LDS: 2 nb words
+// (which fill only a diagonal of the grid) keep the slabs...  LDS: 2 nb words
 // with grid != 0.
 __global__ __launch_bounds__(kPlanThreads) void bk_plan_kernel(const float *__restrict__ part,
                                                                const float2 *__restrict__ pts,
@@ -343,7 +344,7 @@ __global__ __launch_bounds__(kPlanThreads) void bk_plan_kernel(const float *__re
                                                                uint32_t grid) {
   __shared__ float sred[kPlanThreads / kWave][kPart];
   __shared__ BucketParams shp[2];
-  __shared__ unsigned long long ssq[2];
+  __shared__ unsigned long long ssq[3];
   extern __shared__ uint32_t hist[];
   const InstPlan I = V.get(blockIdx.x);
   const uint32_t t = threadIdx.x;
@@ -363,11 +364,13 @@ __global__ __launch_bounds__(kPlanThreads) void bk_plan_kernel(const float *__re
   if (g.ny > 1) {  // uniform over the workgroup
     const uint32_t nb = I.nb;
     for (uint32_t k = t; k < 2 * nb; k += kPlanThreads) hist[k] = 0u;
-    if (t < 2) ssq[t] = 0ull;
+    if (t < 3) ssq[t] = 0ull;
     __syncthreads();
+    uint32_t points = 0;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (x[u].x != x[u].x) continue;  // no valid box was sampled there
+      ++points;
       atomicAdd(&hist[bucket_of(x[u].x, q.vmin, q.scale, nb)], 1u);
       const uint32_t a = bucket_of(x[u].x, g.vmin, g.scale, g.nx);
       const uint32_t c = bucket_of(x[u].y, g.vmin1, g.scale1, g.ny);
@@ -381,12 +384,18 @@ __global__ __launch_bounds__(kPlanThreads) void bk_plan_kernel(const float *__re
     }
     s1 = wave_sum(s1);
     s2 = wave_sum(s2);
+    const unsigned long long pw = wave_sum((unsigned long long)points);
     if (lane_id() == 0) {
       atomicAdd(&ssq[0], s1);
       atomicAdd(&ssq[1], s2);
+      atomicAdd(&ssq[2], pw);
     }
     __syncthreads();
-    use_grid = 4ull * ssq[1] <= 5ull * ssq[0];
+    // ... and at most twice what S points spread evenly over nb cells give
+    // (S + S^2 / nb): a crowded grid would overflow cells, which cannot be
+    // split, where the slab buckets of a skewed input can
+    const unsigned long long S = ssq[2];
+    use_grid = 4ull * ssq[1] <= 5ull * ssq[0] && ssq[1] <= 2ull * (S + S * S / nb);
   }
   if (t == 0) P[blockIdx.x] = shp[use_grid ? 1 : 0];
 }
@@ -500,6 +509,7 @@ __global__ __launch_bounds__(kThreads) void bk_count_kernel(
         const unsigned long long span = (unsigned long long)(c.a1 - c.a0) * (c.c1 - c.c0 + 1u);
         if (span > 1ull && atomicAdd(&hdr->bs_copies, span) + span > (unsigned long long)bs_cap) {
           atomicOr(&hdr->pad[0], 1u);
+          atomicOr(&hdr->pad[1], kUnsplittable);
           continue;
         }
         for (uint32_t a = c.a0 + 1; a <= c.a1; ++a)
@@ -530,16 +540,22 @@ constexpr int kColWaves = 16;
 constexpr int kColBuckets = kWave / 2;
 constexpr int kColRanges = 2 * kColWaves;
 
+// A bucket whose total exceeds ``cap`` records cannot be swept on chip: it
+// sets the fallback flag, so that the scatter and the sweep stand down, and
+// says whether splitting slab buckets could cure it (bp: the instances'
+// bucket maps; a grid's cells are not split).
 __global__ __launch_bounds__(kColWaves * kWave) void bk_colscan_kernel(
     const uint32_t *__restrict__ C, uint32_t *__restrict__ P, uint32_t *__restrict__ tot,
-    View V, uint32_t nb_total) {
+    View V, uint32_t nb_total, uint32_t cap, const BucketParams *__restrict__ bp,
+    Header *__restrict__ hdr) {
   __shared__ uint32_t part[kColRanges][kColBuckets];
   const uint32_t col = threadIdx.x % kColBuckets, g = threadIdx.x / kColBuckets;  // g: range
   const uint32_t j = blockIdx.x * kColBuckets + col;
-  uint32_t k0 = 0, k1 = 0, stride = 0;
+  uint32_t k0 = 0, k1 = 0, stride = 0, inst = 0;
   size_t base = 0;
   if (j < nb_total) {
-    const InstPlan I = V.get(V.of_bucket(j));
+    inst = V.of_bucket(j);
+    const InstPlan I = V.get(inst);
     const uint32_t per = (I.nblk + kColRanges - 1) / kColRanges;
     k0 = min(I.nblk, g * per);
     k1 = min(I.nblk, k0 + per);
@@ -552,7 +568,13 @@ __global__ __launch_bounds__(kColWaves * kWave) void bk_colscan_kernel(
   __syncthreads();
   uint32_t run = 0;
   for (uint32_t v = 0; v < g; ++v) run += part[v][col];
-  if (j < nb_total && g == kColRanges - 1) tot[j] = run + sum;
+  if (j < nb_total && g == kColRanges - 1) {
+    tot[j] = run + sum;
+    if (run + sum > cap) {
+      atomicOr(&hdr->pad[0], 1u);
+      atomicOr(&hdr->pad[1], bp[inst].ny <= 1u ? kSplittable : kUnsplittable);
+    }
+  }
   for (uint32_t k = k0; k < k1; ++k) {
     const size_t at = base + (size_t)k * stride;
     const uint32_t c = C[at];
@@ -1453,7 +1475,10 @@ __device__ __forceinline__ void sweep_bucket(
     fits = O.bs_begin(O.nb) <= bs_cap && C <= (uint32_t)CAP && start + C <= O.rec_cap;
   }
   if (!fits) {  // uniform: the host falls back
-    if (threadIdx.x == 0) atomicOr(&hdr->pad[0], 1u);
+    if (threadIdx.x == 0) {
+      atomicOr(&hdr->pad[0], 1u);
+      atomicOr(&hdr->pad[1], kUnsplittable);
+    }
     return;
   }
   const int t = threadIdx.x;
@@ -1699,6 +1724,108 @@ __device__ __forceinline__ void sweep_bucket(
   }
 }
 
+// ------------------------------------------------------ split buckets
+
+// Mean records per bucket of a split column, and the split plan's workgroup.
+constexpr uint32_t kSplitTarget = 1024;
+constexpr int kSplitThreads = 1024;
+
+// After an attempt that failed only because slab buckets held more records
+// than a sweep workgroup can (one instance; its map, the totals of its
+// buckets and the input's validation are in the workspace): column a with
+// more than cap records becomes ceil(T[a] / kSplitTarget) consecutive
+// buckets, by a map linear in the encoded coordinate (see split_of), every
+// other column one bucket.  The encoded range a split column is cut over is
+// its nominal range under the map, narrowed to the sampled lower corners
+// that fell in it (widened by 1/64 of their spread), so that a column whose
+// boxes fill only part of it (the first one, stretched below the least
+// coordinate, above all) is still cut where its boxes are; corners beyond
+// the range land in its first or last bucket.  Writes the table and the new
+// bucket map, the new bucket count into hdr->split_nb (0 if the failure was
+// of another kind or more than max_nb buckets would be needed) and clears
+// the header and what the next count pass accumulates.  LDS: 2 nb words.
+__global__ __launch_bounds__(kSplitThreads) void bk_split_kernel(
+    uint32_t *__restrict__ T, uint32_t nb, uint32_t cap, uint32_t max_nb,
+    BucketParams *__restrict__ P, uint4 *__restrict__ split, Header *__restrict__ hdr,
+    uint32_t *__restrict__ bs_cur, uint32_t *__restrict__ heavy,
+    const float2 *__restrict__ pts, uint32_t sampled) {
+  constexpr int PER = (int)(kMaxBuckets / kSplitThreads);
+  __shared__ uint32_t red[kSplitThreads / kWave + 2];
+  extern __shared__ uint32_t kext[];  // least and greatest sampled key per column
+  const uint32_t t = threadIdx.x;
+  const BucketParams p = P[0];
+  const uint32_t why = hdr->pad[1];
+  const bool splittable = (why & kSplittable) && !(why & kUnsplittable) && p.ny <= 1u && !p.split;
+  uint32_t *kmin = kext, *kmax = kext + nb;
+  for (uint32_t b = t; b < nb; b += kSplitThreads) {
+    kmin[b] = 0xFFFFFFFFu;
+    kmax[b] = 0u;
+  }
+  uint32_t k[PER], sum = 0;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const uint32_t b = t * (uint32_t)PER + (uint32_t)i;
+    k[i] = 0u;
+    if (b < nb) {
+      const uint32_t tb = T[b];
+      k[i] = tb > cap ? (tb + kSplitTarget - 1u) / kSplitTarget : 1u;
+    }
+    sum += k[i];
+  }
+  uint32_t total;
+  uint32_t run = block_exclusive_scan<uint32_t, kSplitThreads>(sum, red, &total);
+  const bool ok = splittable && total <= max_nb;  // uniform
+  if (ok) {
+    for (uint32_t i = t; i < sampled; i += kSplitThreads) {
+      const float x = pts[i].x;
+      if (x != x) continue;  // no valid box was sampled there
+      const uint32_t a = bucket_of(x, p.vmin, p.scale, p.nx);
+      atomicMin(&kmin[a], encode_coord(x));
+      atomicMax(&kmax[a], encode_coord(x));
+    }
+  }
+  __syncthreads();  // every total of the failed attempt has been read
+  if (ok) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const uint32_t b = t * (uint32_t)PER + (uint32_t)i;
+      if (b >= nb) continue;
+      const float x0 = p.vmin + (float)b / p.scale, x1 = p.vmin + (float)(b + 1u) / p.scale;
+      uint32_t z = encode_coord(x0), z1 = encode_coord(x1);
+      if (k[i] > 1u && kmax[b] >= kmin[b]) {
+        const uint32_t w = (kmax[b] - kmin[b]) / 64u + 1u;
+        const uint32_t lo = kmin[b] > w ? kmin[b] - w : 0u;
+        const uint32_t hi = kmax[b] < 0xFFFFFFFFu - w ? kmax[b] + w : 0xFFFFFFFFu;
+        if (lo > z && lo < z1) z = lo;
+        if (hi < z1 && hi > z) z1 = hi;
+      }
+      const float sc = z1 > z ? (float)k[i] / (float)(z1 - z) : 0.f;
+      split[b] = make_uint4(run, k[i], z, __float_as_uint(sc));
+      run += k[i];
+    }
+    // the boundary-state sizes, the zero after them and the cursors of the
+    // split layout (its bucket totals come from the next column scan)
+    for (uint32_t j = t; j <= total; j += kSplitThreads) {
+      T[total + j] = 0u;
+      if (j < total) bs_cur[j] = 0u;
+    }
+    if (t < 2) heavy[t] = 0u;
+  }
+  if (t == 0) {
+    hdr->split_nb = ok ? total : 0u;
+    if (ok) {
+      hdr->pad[0] = 0u;
+      hdr->pad[1] = 0u;
+      hdr->bs_copies = 0ull;
+      hdr->total = 0ull;
+      BucketParams q = p;
+      q.split = split;
+      q.nb = total;
+      P[0] = q;
+    }
+  }
+}
+
 template <int DM1, int MODE, int CAP, int THREADS, int FINE, bool SLAB = false>
 __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
     const uint32_t *__restrict__ rec, Offsets O, View V, const uint32_t *__restrict__ bs_rec,
@@ -1736,6 +1863,7 @@ struct Ptrs {
   float *part;
   float2 *pts;
   uint32_t *C, *T, *S, *SB, *bs_cur, *rec, *bs_rec, *heavy;
+  uint4 *split;
   void *scan_tmp;
   Offsets O;
   View V;
@@ -1756,6 +1884,7 @@ Ptrs pointers(const BucketArgs &a) {
   p.rec = reinterpret_cast<uint32_t *>(ws + L.rec);
   p.bs_rec = reinterpret_cast<uint32_t *>(ws + L.bs_rec);
   p.heavy = reinterpret_cast<uint32_t *>(ws + L.heavy);
+  p.split = reinterpret_cast<uint4 *>(ws + L.split);
   p.scan_tmp = ws + L.scan_tmp;
   p.O.S = p.S;
   p.O.nb = L.nb;
@@ -1778,6 +1907,27 @@ Ptrs pointers(const BucketArgs &a) {
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 template <int D>
+void count_scatter_impl(const BucketArgs &a, hipStream_t s, int32_t *zero, uint32_t zero_count) {
+  const BucketLayout &L = *a.L;
+  Ptrs p = pointers(a);
+  const size_t lds = (size_t)L.max_nb * sizeof(uint32_t);
+  prof::mark(s, "bucket.count");
+  bk_count_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.C, p.T + L.nb, L.bs_cap,
+                                                   a.hdr, zero, zero ? zero_count : 0u);
+  prof::mark(s, "bucket.offsets");
+  bk_colscan_kernel<<<(L.nb + kColBuckets - 1) / kColBuckets, kColWaves * kWave, 0, s>>>(
+      p.C, p.SB, p.T, p.V, L.nb, bucket_cap(L.tune), p.P, a.hdr);
+  (void)exclusive_scan_u32(p.T, p.S, 2 * (size_t)L.nb + 1, p.scan_tmp, s);
+  prof::mark(s, "bucket.scatter");
+  if (L.max_nb <= kPairScatterMaxBuckets)
+    bk_scatter_pair_kernel<D><<<L.nblk, kThreads, (size_t)L.max_nb * 24, s>>>(
+        L.n_total, p.V, p.P, p.O, p.SB, p.bs_cur, L.bs_cap, p.rec, p.bs_rec, a.hdr);
+  else
+    bk_scatter_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.O, p.SB, p.bs_cur,
+                                                       L.bs_cap, p.rec, p.bs_rec, a.hdr);
+}
+
+template <int D>
 void prepare_impl(const BucketArgs &a, hipStream_t s) {
   const BucketLayout &L = *a.L;
   Ptrs p = pointers(a);
@@ -1787,20 +1937,7 @@ void prepare_impl(const BucketArgs &a, hipStream_t s) {
   bk_sample_kernel<D><<<L.nsmp, kSampleThreads, 0, s>>>(p.V, p.part, p.pts, clr);
   const uint32_t grid = D >= 2 ? 1u : 0u;
   bk_plan_kernel<<<L.B, kPlanThreads, grid ? 2 * lds : 0, s>>>(p.part, p.pts, p.V, p.P, grid);
-  prof::mark(s, "bucket.count");
-  bk_count_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.C, p.T + L.nb, L.bs_cap,
-                                                   a.hdr, a.zero, a.zero ? a.zero_count : 0u);
-  prof::mark(s, "bucket.offsets");
-  bk_colscan_kernel<<<(L.nb + kColBuckets - 1) / kColBuckets, kColWaves * kWave, 0, s>>>(
-      p.C, p.SB, p.T, p.V, L.nb);
-  (void)exclusive_scan_u32(p.T, p.S, 2 * (size_t)L.nb + 1, p.scan_tmp, s);
-  prof::mark(s, "bucket.scatter");
-  if (L.max_nb <= kPairScatterMaxBuckets)
-    bk_scatter_pair_kernel<D><<<L.nblk, kThreads, (size_t)L.max_nb * 24, s>>>(
-        L.n_total, p.V, p.P, p.O, p.SB, p.bs_cur, L.bs_cap, p.rec, p.bs_rec, a.hdr);
-  else
-    bk_scatter_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.O, p.SB, p.bs_cur,
-                                                       L.bs_cap, p.rec, p.bs_rec, a.hdr);
+  count_scatter_impl<D>(a, s, a.zero, a.zero_count);
 }
 
 template <int DM1, int MODE>
@@ -1853,7 +1990,7 @@ void build_slabs_impl(const BucketArgs &a, const SlabBuild &sb, hipStream_t s) {
   bk_count_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.C, nullptr, 0u, a.hdr,
                                                    nullptr, 0u);
   bk_colscan_kernel<<<(L.nb + kColBuckets - 1) / kColBuckets, kColWaves * kWave, 0, s>>>(
-      p.C, p.SB, p.T, p.V, L.nb);
+      p.C, p.SB, p.T, p.V, L.nb, 0xFFFFFFFFu, p.P, a.hdr);  // the slabs report their own overflow
   (void)fill_u32(sb.cnt + L.nb, 0u, 1, s);
   bk_slab_scatter_kernel<D><<<L.nblk, kThreads, lds, s>>>(p.V, p.P, p.SB, p.T, sb.ids, sb.lo,
                                                           sb.hi, sb.cnt, sb.cap, sb.overflow);
@@ -1980,19 +2117,26 @@ BucketLayout bucket_layout(const InstSpec *inst, int64_t B, int d, const BucketT
     at += align256(bytes);
     return o;
   };
-  const size_t scanned = 2 * (size_t)L.nb + 1;  // bucket sizes + boundary-state sizes + 0
+  // a single instance keeps room for its overfull buckets to be split: at
+  // most one more bucket per kSplitTarget records (bucket_split)
+  L.nb_split = L.nb;
+  if (B == 1 && L.nb > 0)
+    L.nb_split = (uint32_t)std::min<uint64_t>(kMaxBuckets, L.nb + (N + kSplitTarget - 1) / kSplitTarget);
+  const size_t cell_room = (size_t)L.nblk * L.nb_split;
+  const size_t scanned = 2 * (size_t)L.nb_split + 1;  // bucket sizes + boundary-state sizes + 0
   L.params = take((size_t)B * sizeof(BucketParams));
   L.sample_part = take((size_t)std::max<uint32_t>(L.nsmp, 1) * kPart * sizeof(float));
   L.sample_pts = take((size_t)std::max<uint32_t>(L.nsmp, 1) * kSampleThreads * 2 * sizeof(float));
-  L.counts = take(cell * sizeof(uint32_t));
+  L.counts = take(std::max(cell, cell_room) * sizeof(uint32_t));
   L.totals = take(scanned * sizeof(uint32_t));
   L.offsets = take(scanned * sizeof(uint32_t));
-  L.block_offsets = take(cell * sizeof(uint32_t));
+  L.block_offsets = take(std::max(cell, cell_room) * sizeof(uint32_t));
   L.scan_tmp = take(scan_temp_bytes(scanned));
-  L.bs_cur = take((size_t)std::max<uint32_t>(L.nb, 1) * sizeof(uint32_t));
+  L.bs_cur = take((size_t)std::max<uint32_t>(L.nb_split, 1) * sizeof(uint32_t));
   L.rec = take((size_t)L.rec_cap * L.rec_words * sizeof(uint32_t));
   L.bs_rec = take((size_t)L.bs_cap * L.rec_words * sizeof(uint32_t));
-  L.heavy = take(((size_t)L.nb + 2) * sizeof(uint32_t));
+  L.heavy = take(((size_t)L.nb_split + 2) * sizeof(uint32_t));
+  L.split = take((size_t)std::max<uint32_t>(L.nb, 1) * sizeof(uint4));
   L.plan = take(B > 1 ? (size_t)B * sizeof(InstPlan) : 0);
   L.maps = take(B > 1 ? ((size_t)L.nblk + L.nsmp + L.nb) * sizeof(uint32_t) : 0);
   L.bytes = at;
@@ -2037,6 +2181,40 @@ hipError_t bucket_prepare(const BucketArgs &a, hipStream_t s) {
     case 6: prepare_impl<6>(a, s); break;
     case 7: prepare_impl<7>(a, s); break;
     default: prepare_impl<8>(a, s); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t bucket_split(const BucketArgs &a, hipStream_t s) {
+  const BucketLayout &L = *a.L;
+  if (L.B != 1 || L.nb == 0 || L.nb_split <= L.nb) return hipErrorInvalidValue;
+  Ptrs p = pointers(a);
+  prof::mark(s, "bucket.split");
+  bk_split_kernel<<<1, kSplitThreads, 2 * (size_t)L.nb * sizeof(uint32_t), s>>>(
+      p.T, L.nb, bucket_cap(L.tune), L.nb_split, p.P, p.split, a.hdr, p.bs_cur, p.heavy, p.pts,
+      L.inst[0].nsmp * (uint32_t)kSampleThreads);
+  return hipGetLastError();
+}
+
+BucketLayout split_layout(const BucketLayout &L, uint32_t nb) {
+  BucketLayout R = L;
+  R.nb = nb;
+  R.max_nb = nb;
+  R.inst[0].nb = nb;
+  R.cells = (size_t)R.inst[0].nblk * nb;
+  return R;
+}
+
+hipError_t bucket_prepare_split(const BucketArgs &a, hipStream_t s) {
+  switch (a.d) {  // the output was cleared by the first attempt's count pass
+    case 1: count_scatter_impl<1>(a, s, nullptr, 0u); break;
+    case 2: count_scatter_impl<2>(a, s, nullptr, 0u); break;
+    case 3: count_scatter_impl<3>(a, s, nullptr, 0u); break;
+    case 4: count_scatter_impl<4>(a, s, nullptr, 0u); break;
+    case 5: count_scatter_impl<5>(a, s, nullptr, 0u); break;
+    case 6: count_scatter_impl<6>(a, s, nullptr, 0u); break;
+    case 7: count_scatter_impl<7>(a, s, nullptr, 0u); break;
+    default: count_scatter_impl<8>(a, s, nullptr, 0u); break;
   }
   return hipGetLastError();
 }

@@ -15,18 +15,25 @@ constexpr uint32_t kSentinel = 0xFFFFFFFFu;
 constexpr uint32_t kErrNaN = 1u;
 constexpr uint32_t kErrOrder = 2u;
 
+// Header::pad[1] bits of the bucketed path: why it could not finish.
+constexpr uint32_t kSplittable = 1u;    // slab buckets overflowed (their totals can split them)
+constexpr uint32_t kUnsplittable = 2u;  // something else overflowed
+
 // Small device-resident header at the start of every workspace.
 struct Header {
   uint32_t err;        // OR of kErr* flags
   uint32_t nonempty;   // regions that are non-empty on every axis
   uint32_t kmin;       // min encoded lower key over non-empty regions
   uint32_t kmax;       // max encoded lower key over non-empty regions
-  // bucketed path: boundary-state copies claimed so far by the count pass
-  // (a 64-bit running total checked against the buffer's capacity)
+  // bucketed path: boundary-state copies claimed so far by boxes reaching
+  // more than one later cell (checked against the buffer's capacity)
   unsigned long long bs_copies;
-  uint32_t pad[2];     // pad[0]: the bucketed path cannot finish (the host falls back)
+  uint32_t pad[2];     // pad[0]: the bucketed path cannot finish; pad[1]: kSplittable |
+                       // kUnsplittable, why
   unsigned long long total;  // number of intersecting pairs
   unsigned long long aux[3];
+  uint32_t split_nb;   // buckets after overfull ones were split (0: they cannot be)
+  uint32_t spare;
 };
 
 // Order-preserving map of a non-NaN float32 onto uint32: a < b (IEEE)

@@ -120,6 +120,53 @@ def correlated_d3(n: int, alpha: float, seed: int = 0) -> Instance:
     return Instance(ulo, uhi, slo, shi, alpha, f"correlated_d3_n{n}_a{alpha:g}")
 
 
+def loguniform_boxes(n: int, m: int, d: int, alpha: float, seed: int = 0,
+                     decades: float = 6.0) -> Instance:
+    """Skewed placement: lower corners log-uniform over ``decades`` decades
+    from 1 on every axis (half of them below 1e3 for six decades), each side
+    proportional to its lower corner, with the overlap degree alpha of the
+    uniform workload in logarithmic coordinates: side = lo * alpha *
+    ln(10^decades) / (n + m), rounded to float32, upper = lower + side in
+    float32."""
+    span = decades * math.log(10.0)
+    rel = np.float32(alpha * span / max(n + m, 1))
+    out = []
+    for stream, cnt in ((UPD_STREAM, n), (SUB_STREAM, m)):
+        rng = generator(seed, 200 + stream)
+        lo = np.exp(rng.random((cnt, d)) * span).astype(np.float32)
+        hi = (lo + (lo * rel).astype(np.float32)).astype(np.float32)
+        out.append((lo, hi))
+    (ulo, uhi), (slo, shi) = out
+    return Instance(ulo, uhi, slo, shi, alpha, f"loguniform_d{d}_n{n}_a{alpha:g}")
+
+
+def clustered_boxes(n: int, m: int, d: int, alpha: float, seed: int = 0, clusters: int = 16,
+                    sigma: float = 2.0e4) -> Instance:
+    """Clustered placement: lower corners drawn around ``clusters`` centres
+    (uniform on [2e5, 8e5)^d, shared by both sets) with a normal spread of
+    ``sigma`` per axis, clamped to [0, L).  The side on axis k is chosen so
+    that the expected number of 1-D overlaps per box is alpha, as in the
+    uniform workload: l_k = alpha / ((n + m) * integral of f_k^2), f_k the
+    mixture density of axis k (a sum of normal densities over centre pairs),
+    rounded once to float32."""
+    centres = 2.0e5 + generator(seed, 300).random((clusters, d)) * 6.0e5
+    sides = np.empty(d, dtype=np.float32)
+    for k in range(d):
+        diff = centres[:, None, k] - centres[None, :, k]
+        f2 = np.exp(-diff ** 2 / (4.0 * sigma ** 2)).sum() / (clusters ** 2 * 2.0 * sigma * math.sqrt(math.pi))
+        sides[k] = np.float32(alpha / (max(n + m, 1) * f2))
+    out = []
+    for stream, cnt in ((UPD_STREAM, n), (SUB_STREAM, m)):
+        rng = generator(seed, 300 + 1 + stream)
+        which = rng.integers(0, clusters, size=cnt)
+        lo = (centres[which] + rng.standard_normal((cnt, d)) * sigma).astype(np.float32)
+        np.clip(lo, np.float32(0.0), LO_MAX, out=lo)
+        hi = (lo + sides).astype(np.float32)
+        out.append((lo, hi))
+    (ulo, uhi), (slo, shi) = out
+    return Instance(ulo, uhi, slo, shi, alpha, f"clustered_d{d}_n{n}_a{alpha:g}")
+
+
 def tie_heavy(n: int, m: int, d: int, grid: int = 12, max_len: int = 4, seed: int = 0) -> Instance:
     """Small integer-grid boxes: lower corners in {0..grid}, side lengths in
     {0..max_len}.  Touching, nested, identical and empty intervals are all

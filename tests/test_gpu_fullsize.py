@@ -72,6 +72,31 @@ def test_correlated_d3_full_size(ddm, oracle, alpha):
     assert ddm.match(*g, mode="count") == k_ref
 
 
+@pytest.mark.parametrize("kind,d", [("loguniform", 3), ("clustered", 3), ("loguniform", 2),
+                                    ("clustered", 2)])
+def test_skewed_full_size(ddm, oracle, kind, d):
+    """n = m = 5e6, alpha = 100, lower corners log-uniform over six decades
+    or in 16 normal clusters: the overfull buckets of the linear map are
+    split by their exact totals and the call stays bucketed; total and
+    per-update counts equal to the oracle's (for d = 2 on a result with
+    thousands of pairs)."""
+    make = W.loguniform_boxes if kind == "loguniform" else W.clustered_boxes
+    inst = make(5_000_000, 5_000_000, d, 100.0, seed=0)
+    g = _dev(inst)
+    _note(f"{inst.name} per_update")
+    k, per = ddm.match(*g, mode="per_update")
+    assert ddm.last_path() == "bucketed"
+    k_ref, per_ref, _ = oracle.sbm(inst.upd_lo, inst.upd_hi, inst.sub_lo, inst.sub_hi, pairs=False)
+    if d == 2:
+        assert k_ref > 1000  # the comparison is not on an empty result
+    assert k == k_ref
+    assert np.array_equal(per.cpu().numpy(), per_ref)
+    _note(f"{inst.name} count, repeated (graph replay, then the split)")
+    for _ in range(3):
+        assert ddm.match(*g, mode="count") == k_ref
+        assert ddm.last_path() == "bucketed"
+
+
 def test_batched_workload_every_instance(ddm, oracle):
     """The 512-instance batch as one captured graph: every instance's count,
     per-update counts and pair list equal to the oracle's."""

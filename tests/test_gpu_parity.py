@@ -238,6 +238,21 @@ def test_correlated_d3_stress(ddm, oracle, alpha):
     check_all_modes(ddm, oracle, inst)
 
 
+@pytest.mark.parametrize("kind", ["loguniform", "clustered"])
+def test_skewed_inputs_split_buckets(ddm, oracle, kind):
+    """Lower corners spread over six decades (sides proportional to them) or
+    packed into 16 normal clusters: buckets of the sampled linear map hold
+    far more records than a sweep workgroup can; their exact totals split
+    them and the call stays on the bucketed path.  Every output mode on both
+    paths equal to the oracle, half-open and closed."""
+    make = W.loguniform_boxes if kind == "loguniform" else W.clustered_boxes
+    for d in (1, 2, 3):
+        inst = make(100_000, 90_000, d, 40.0, seed=d)
+        check_all_modes(ddm, oracle, inst, expect_bucketed=True)
+    inst = make(60_000, 70_000, 2, 40.0, seed=9)
+    check_all_modes(ddm, oracle, inst, closed=True, expect_bucketed=True)
+
+
 def test_heavy_buckets_grid_and_closed(ddm, oracle):
     """Buckets whose quantised pre-filter passes more pairs than the sweep's
     queue holds are listed and swept again with the exact bounds of axes 1
