@@ -463,6 +463,8 @@ def main():
                     help="skip the per-phase event timing (roofline becomes null)")
     ap.add_argument("--no-closed", action="store_true",
                     help="skip the closed-interval measurement of the headline workload")
+    ap.add_argument("--no-anisotropic", action="store_true",
+                    help="skip the anisotropic step (swept-axis choice against axis 0)")
     ap.add_argument("--no-skewed", action="store_true",
                     help="skip the skewed-placement (log-uniform, clustered) steps")
     ap.add_argument("--no-correlated", action="store_true",
@@ -692,6 +694,37 @@ def main():
                             "matches": ks, "path": path_s, "phases_ms": ph,
                             "counts_consistent": ok}
             del gs
+    anisotropic = None
+    if not args.no_anisotropic and d >= 2:
+        # boxes 100 times longer on axis 0 than on the others, alpha = 1 on
+        # the short axes: the plan sweeps another axis; the same step with
+        # axis 0 forced shows what the choice saves (counts must agree)
+        ai = W.anisotropic_boxes(n, m, d, 1.0, stretch=100.0, seed=0)
+        ga = [torch.from_numpy(x).to(dev) for x in (ai.upd_lo, ai.upd_hi, ai.sub_lo, ai.sub_hi)]
+        anisotropic = {"workload": f"{ai.name}: sides 100 l on axis 0, l = 1e6/N on the others, "
+                                   f"{args.mode} output"}
+        for label, axis in (("chosen_axis", None), ("axis_0", 0)):
+            ddm.set_sweep_axis(axis)
+            call = lambda: ddm.match_into(*ga, mode=args.mode, workspace=ws,  # noqa: E731
+                                          per_update=per if args.mode == "per_update" else None,
+                                          stream=stream)
+            for _ in range(args.warmup):
+                ka = call()
+            torch.cuda.synchronize()
+            tan = time.perf_counter()
+            for _ in range(args.steps):
+                ka = call()
+            torch.cuda.synchronize()
+            dta = (time.perf_counter() - tan) / args.steps
+            anisotropic[label] = {"ms_per_step": round(dta * 1e3, 4),
+                                  "value": round(regions / dta, 1), "matches": ka,
+                                  "path": ddm.last_path()}
+        ddm.set_sweep_axis(None)
+        anisotropic["counts_equal"] = (anisotropic["chosen_axis"]["matches"]
+                                       == anisotropic["axis_0"]["matches"])
+        anisotropic["speedup"] = round(anisotropic["axis_0"]["ms_per_step"]
+                                       / anisotropic["chosen_axis"]["ms_per_step"], 2)
+        del ga
     closed = None
     if not args.no_closed:
         # the headline inputs as closed boxes [lo, hi]; checked against the
@@ -776,6 +809,7 @@ def main():
         "closed": closed,
         "correlated": correlated,
         "skewed": skewed,
+        "anisotropic": anisotropic,
         "served_p50_ms": served["levels"]["1x"]["batched"]["p50_ms"] if served else None,
         "served_p99_ms": served["levels"]["1x"]["batched"]["p99_ms"] if served else None,
         "served_incremental_p50_ms":

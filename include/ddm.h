@@ -489,6 +489,20 @@ int ddm_set_path(int path);
 int ddm_last_path(void);
 
 /*
+ * The swept axis of the bucketed path (process-global, for tests and
+ * benchmarks).  Any axis gives the same pairs (Sec. 3: the d-dimensional
+ * test is the AND of the 1-D ones), but the work of a sweep grows with the
+ * 1-D candidates of its axis.  axis = -1 (default): every instance's plan
+ * sweeps the input axis with the fewest expected 1-D candidates estimated
+ * from its sample (mean extent over the range of lower bounds), unless that
+ * is not under half of axis 0's; axis = k (0 <= k < DDM_MAX_DIMS) sweeps
+ * axis k (axis 0 for instances with d <= k).  The device-wide path and
+ * resident simulations always sweep axis 0.  Returns DDM_E_INVAL for other
+ * values.
+ */
+int ddm_set_sweep_axis(int axis);
+
+/*
  * Per-phase GPU timing (diagnostic; not part of the method).
  *
  * ddm_profile(1) clears the totals and starts recording: every later call of

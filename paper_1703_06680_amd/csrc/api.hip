@@ -440,10 +440,11 @@ struct GraphKey {
   void *ws;
   size_t ws_bytes;
   int32_t *per_update;
+  int axis;  // the swept-axis setting the launches were captured under
   bool same(const GraphKey &o) const {
     return ulo == o.ulo && uhi == o.uhi && slo == o.slo && shi == o.shi && n == o.n &&
            m == o.m && d == o.d && mode == o.mode && ws == o.ws && ws_bytes == o.ws_bytes &&
-           per_update == o.per_update;
+           per_update == o.per_update && axis == o.axis;
   }
 };
 
@@ -551,6 +552,12 @@ extern "C" int ddm_set_path(int path) {
 
 extern "C" int ddm_last_path(void) { return t_last_path; }
 
+extern "C" int ddm_set_sweep_axis(int axis) {
+  if (axis < -1 || axis >= DDM_MAX_DIMS) return DDM_E_INVAL;
+  set_sweep_axis(axis);
+  return DDM_OK;
+}
+
 namespace {
 
 // ddm_match and ddm_match_csr: the pair list goes to ``pairs``, or, with
@@ -583,7 +590,7 @@ int match_entry(const float *upd_lo, const float *upd_hi, int64_t n, const float
                          path_request != DDM_PATH_GLOBAL && workspace &&
                          !(reinterpret_cast<uintptr_t>(workspace) & 255);
   const GraphKey key{upd_lo, upd_hi, sub_lo, sub_hi, n, m, d, mode_arg, workspace, ws_bytes,
-                     mode == DDM_COUNT ? nullptr : per_update};
+                     mode == DDM_COUNT ? nullptr : per_update, sweep_axis()};
   std::unique_lock<std::mutex> cache_lock(g_graph_mu, std::defer_lock);
   CachedGraph *entry = nullptr;
   bool global_only = false, replayed = false;

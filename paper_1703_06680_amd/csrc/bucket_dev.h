@@ -26,6 +26,11 @@ struct BucketParams {
   uint32_t nx, ny;   // columns, rows per column
   float vmin1;       // row map of axis 1's lower coordinate (ny > 1)
   float scale1;
+  // the input axis swept (axis 0 of the boxes as the kernels see them; the
+  // others follow in input order); kept in the first 64 bytes with the
+  // fields every sweep workgroup reads first
+  uint32_t axis;
+  uint32_t spare;
   // split buckets (slabs only): if not null, column a of the map above became
   // the buckets split[a].x .. split[a].x + split[a].y - 1, by a map linear in
   // the encoded coordinate from split[a].z with scale __uint_as_float(split[a].w)

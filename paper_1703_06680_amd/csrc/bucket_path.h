@@ -163,6 +163,12 @@ hipError_t bucket_upload_plan(const BucketArgs &a, hipStream_t s, void *pinned =
 // beforehand).
 hipError_t bucket_prepare(const BucketArgs &a, hipStream_t s);
 
+// The swept axis of later bucketed calls (process-wide): -1 lets every
+// instance's plan choose the axis with the fewest expected 1-D candidates
+// (the default); k >= 0 sweeps input axis k (axis 0 where k >= d).
+void set_sweep_axis(int axis);
+int sweep_axis();
+
 // Splitting overfull buckets (one instance, slabs).  When an attempt fails
 // only because some buckets hold more records than a sweep workgroup can
 // (Header::pad[1] == kSplittable), bucket_split() enqueues the split plan:

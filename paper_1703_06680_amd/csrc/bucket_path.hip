@@ -41,19 +41,100 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "bucket_dev.h"
 #include "primitives.h"
 #include "profile.h"
 
 namespace ddm {
+
+namespace {
+std::atomic<int> g_sweep_axis{-1};
+}  // namespace
+
+void set_sweep_axis(int axis) { g_sweep_axis.store(axis, std::memory_order_relaxed); }
+int sweep_axis() { return g_sweep_axis.load(std::memory_order_relaxed); }
+
 namespace {
 
 constexpr int kThreads = 1024;                 // count / scatter blocks
 constexpr int kSampleThreads = 256;
 constexpr uint32_t kSampleRows = 8192;         // rows per sample block (at most 256 blocks)
 constexpr uint32_t kMaxSampleBlocks = 256;
-constexpr int kPart = 10;                      // floats per sample block partial
+// Floats per sample block partial: the number of valid boxes sampled, then
+// for every axis k (input order) the least and greatest lower bound, the
+// greatest upper bound and the sum of the extents hi - lo.
+constexpr int kPartAxis = 4;
+constexpr int kPart = 1 + kPartAxis * kBucketMaxDims;
+
+// Combines partial b into a (slot 0 and the extents are sums, the others
+// extremes).
+__device__ __forceinline__ void part_merge(float (&a)[kPart], const float *b) {
+  a[0] += b[0];
+#pragma unroll
+  for (int k = 0; k < kBucketMaxDims; ++k) {
+    float *x = a + 1 + kPartAxis * k;
+    const float *y = b + 1 + kPartAxis * k;
+    x[0] = fminf(x[0], y[0]);
+    x[1] = fmaxf(x[1], y[1]);
+    x[2] = fmaxf(x[2], y[2]);
+    x[3] += y[3];
+  }
+}
+
+__device__ __forceinline__ void part_identity(float (&a)[kPart]) {
+  const float inf = __int_as_float(0x7f800000);
+  a[0] = 0.f;
+#pragma unroll
+  for (int k = 0; k < kBucketMaxDims; ++k) {
+    a[1 + kPartAxis * k] = inf;
+    a[2 + kPartAxis * k] = -inf;
+    a[3 + kPartAxis * k] = -inf;
+    a[4 + kPartAxis * k] = 0.f;
+  }
+}
+
+// The partial reduced over a wave (result in every lane); axes from D on
+// keep their identity values.
+template <int D = kBucketMaxDims>
+__device__ __forceinline__ void part_wave(float (&a)[kPart]) {
+  a[0] = wave_sum(a[0]);
+#pragma unroll
+  for (int k = 0; k < (D < kBucketMaxDims ? D : kBucketMaxDims); ++k) {
+    float *x = a + 1 + kPartAxis * k;
+    x[0] = wave_min(x[0]);
+    x[1] = wave_max(x[1]);
+    x[2] = wave_max(x[2]);
+    x[3] = wave_sum(x[3]);
+  }
+}
+
+// Axis k of the sweep order (the swept axis first, the others after it in
+// input order) as an input axis.
+__device__ __forceinline__ uint32_t input_axis(uint32_t k, uint32_t axis) {
+  return k == 0u ? axis : (k <= axis ? k - 1u : k);
+}
+
+// Puts input axis ``axis`` of a loaded box first and the others after it
+// in their order, so that every kernel after the plan sweeps axis 0 of its
+// boxes.
+template <int D>
+__device__ __forceinline__ void sweep_order(Box<D> &b, uint32_t axis) {
+  if (D == 1 || axis == 0u) return;
+  float l = b.lo[0], h = b.hi[0];
+#pragma unroll
+  for (int k = 1; k < D; ++k) {
+    if ((uint32_t)k > axis) continue;
+    const float tl = b.lo[k], th = b.hi[k];
+    b.lo[k] = l;
+    b.hi[k] = h;
+    l = tl;
+    h = th;
+  }
+  b.lo[0] = l;
+  b.hi[0] = h;
+}
 // Sampled lower corners (swept axis, axis 1) the plan tries a grid on, the
 // plan's workgroup size, and the mean slab walk (entries) from which rows
 // are tried.
@@ -123,7 +204,7 @@ struct Clear {
 template <int D>
 __global__ __launch_bounds__(kSampleThreads) void bk_sample_kernel(View V,
                                                                    float *__restrict__ part,
-                                                                   float2 *__restrict__ pts,
+                                                                   float *__restrict__ pts,
                                                                    Clear clr) {
   {
     const uint32_t tid = blockIdx.x * kSampleThreads + threadIdx.x;
@@ -138,15 +219,15 @@ __global__ __launch_bounds__(kSampleThreads) void bk_sample_kernel(View V,
       for (uint32_t i = tid; i < clr.B; i += stride) clr.inst_total[i] = 0ull;
   }
   // per block, over the sampled valid non-empty boxes of the block's
-  // instance: min/max of the swept lower coordinate (slots 0, 1), count (2),
-  // the sum of the axis-1 extents hi - lo (3), for axes 1 and 2 min(lo) /
-  // max(hi) (4 .. 7) and the sum of the swept-axis extents (8)
+  // instance, the partial described at kPart; the sampled lower corners of
+  // every axis (input order) go to pts[i * D ..] for the plan and for
+  // bucket splits
   constexpr int W = kSampleThreads / kWave;
   __shared__ float sred[W][kPart];
   const InstPlan I = V.get(V.of_smp(blockIdx.x));
   const uint32_t N = I.n + I.m;
-  const float inf = __int_as_float(0x7f800000);
-  float v[kPart] = {inf, -inf, 0.f, 0.f, inf, -inf, inf, -inf, 0.f, 0.f};
+  float v[kPart];
+  part_identity(v);
   const uint32_t i = blockIdx.x * kSampleThreads + threadIdx.x;
   const uint32_t r =
       (uint32_t)(((unsigned long long)mix32(i * 0x9E3779B9u + 0x632BE5ABu) * N) >> 32);
@@ -154,57 +235,29 @@ __global__ __launch_bounds__(kSampleThreads) void bk_sample_kernel(View V,
   const Box<D> b = load_row<D>(upd ? I.ulo : I.slo, upd ? I.uhi : I.shi, upd ? r : r - I.n);
   bool empty;
   const uint32_t err = box_errors<D>(b, empty, I.closed);
-  bool ok = !err && !empty && fabsf(b.lo[0]) <= 3.0e38f;
+  bool ok = !err && !empty;
 #pragma unroll
-  for (int k = 1; k < D; ++k) ok = ok && fabsf(b.lo[k]) <= 3.0e38f && fabsf(b.hi[k]) <= 3.0e38f;
+  for (int k = 0; k < D; ++k) ok = ok && fabsf(b.lo[k]) <= 3.0e38f && fabsf(b.hi[k]) <= 3.0e38f;
+  const float nan = __int_as_float(0x7fc00000);
   if (ok) {
-    v[0] = v[1] = b.lo[0];
-    v[2] = 1.f;
-    if (D >= 2) v[3] = b.hi[1 % D] - b.lo[1 % D];
-    v[8] = b.hi[0] - b.lo[0];
-  }
-  {  // the sampled lower corner on the swept axis and axis 1, for the plan and bucket splits
-    const float nan = __int_as_float(0x7fc00000);
-    pts[i] = ok ? make_float2(b.lo[0], b.lo[1 % D]) : make_float2(nan, nan);
-  }
-  if (ok) {
+    v[0] = 1.f;
 #pragma unroll
-    for (int k = 1; k < (D < 3 ? D : 3); ++k) {  // the quantised axes 1 and 2
-      v[4 + 2 * (k - 1)] = b.lo[k];
-      v[5 + 2 * (k - 1)] = b.hi[k];
+    for (int k = 0; k < D; ++k) {
+      v[1 + kPartAxis * k] = v[2 + kPartAxis * k] = b.lo[k];
+      v[3 + kPartAxis * k] = b.hi[k];
+      v[4 + kPartAxis * k] = b.hi[k] - b.lo[k];
     }
   }
 #pragma unroll
-  for (int k = 0; k < 8; k += 2) {
-    if (k == 2) continue;  // slots 2 and 3 are sums, below
-    v[k] = wave_min(v[k]);
-    v[k + 1] = wave_max(v[k + 1]);
-  }
-  v[2] = wave_sum(v[2]);
-  v[3] = wave_sum(v[3]);
-  v[8] = wave_sum(v[8]);
+  for (int k = 0; k < D; ++k) pts[(size_t)i * D + k] = ok ? b.lo[k] : nan;
+  part_wave<D>(v);
   const int w = threadIdx.x / kWave;
   if (lane_id() == 0)
 #pragma unroll
     for (int k = 0; k < kPart; ++k) sred[w][k] = v[k];
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int j = 1; j < W; ++j)
-#pragma unroll
-      for (int k = 0; k < 8; k += 2) {
-        if (k == 2) continue;
-        v[k] = fminf(v[k], sred[j][k]);
-        v[k + 1] = fmaxf(v[k + 1], sred[j][k + 1]);
-      }
-    float c = 0.f, e = 0.f, e0 = 0.f;
-    for (int j = 0; j < W; ++j) {
-      c += sred[j][2];
-      e += sred[j][3];
-      e0 += sred[j][8];
-    }
-    v[2] = c;
-    v[3] = e;
-    v[8] = e0;
+    for (int j = 1; j < W; ++j) part_merge(v, sred[j]);
 #pragma unroll
     for (int k = 0; k < kPart; ++k) part[blockIdx.x * kPart + k] = v[k];
   }
@@ -216,33 +269,25 @@ __global__ __launch_bounds__(kSampleThreads) void bk_sample_kernel(View V,
 // (out[1].ny = 1: none).  The grid's cells are about as long on axis 1 as
 // on the swept axis, and its rows are at least eight mean axis-1 extents
 // high, so that copies into later rows stay rare.
+//
+// The swept axis (axis < 0) is the input axis k with the fewest expected
+// 1-D candidates, N^2 * (mean extent) / (range of lower bounds) for boxes
+// spread over the range (Sec. 3: any axis gives the same pairs), unless that
+// is not under half of axis 0's; axis >= 0 forces that axis (0 if it is not
+// one of the instance's).  Axes 1, 2, ... of the plan are the other input
+// axes in order.
 template <int THREADS>
 __device__ void block_plan(const float *__restrict__ part, const InstPlan &I, bool grid,
-                           float (*sred)[kPart], BucketParams *out) {
+                           int force_axis, float (*sred)[kPart], BucketParams *out) {
   constexpr int W = THREADS / kWave;
-  const float inf = __int_as_float(0x7f800000);
-  float v[kPart] = {inf, -inf, 0.f, 0.f, inf, -inf, inf, -inf, 0.f, 0.f};
-  for (uint32_t i = threadIdx.x; i < I.nsmp; i += THREADS) {
-    const float *pp = part + (size_t)(I.smp0 + i) * kPart;
-#pragma unroll
-    for (int k = 0; k < 8; k += 2) {
-      if (k == 2) continue;
-      v[k] = fminf(v[k], pp[k]);
-      v[k + 1] = fmaxf(v[k + 1], pp[k + 1]);
-    }
-    v[2] += pp[2];
-    v[3] += pp[3];
-    v[8] += pp[8];
-  }
-#pragma unroll
-  for (int k = 0; k < 8; k += 2) {
-    if (k == 2) continue;  // slots 2 and 3 are sums, below
-    v[k] = wave_min(v[k]);
-    v[k + 1] = wave_max(v[k + 1]);
-  }
-  v[2] = wave_sum(v[2]);
-  v[3] = wave_sum(v[3]);
-  v[8] = wave_sum(v[8]);
+  float v[kPart];
+  part_identity(v);
+  for (uint32_t i = threadIdx.x; i < I.nsmp; i += THREADS)
+    part_merge(v, part + (size_t)(I.smp0 + i) * kPart);
+  if (I.d <= 3)  // uniform: the other axes hold identity values
+    part_wave<3>(v);
+  else
+    part_wave<kBucketMaxDims>(v);
   const int w = threadIdx.x / kWave;
   if (lane_id() == 0)
 #pragma unroll
@@ -250,22 +295,42 @@ __device__ void block_plan(const float *__restrict__ part, const InstPlan &I, bo
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll 1
-    for (int j = 1; j < W; ++j)
+    for (int j = 1; j < W; ++j) part_merge(v, sred[j]);
+    const float c = v[0];
+    const uint32_t d = I.d < (uint32_t)kBucketMaxDims ? I.d : (uint32_t)kBucketMaxDims;
+    // the partial of input axis k, through LDS (the reduced partial is
+    // indexed by axes chosen at run time)
 #pragma unroll
-      for (int k = 0; k < 8; k += 2) {
-        if (k == 2) continue;
-        v[k] = fminf(v[k], sred[j][k]);
-        v[k + 1] = fmaxf(v[k + 1], sred[j][k + 1]);
-      }
-    float c = 0.f, ext = 0.f, ext0 = 0.f;
+    for (int k = 0; k < kPart; ++k) sred[0][k] = v[k];
+    const float *st = sred[0];
+    auto lo_min = [&](uint32_t k) { return st[1 + kPartAxis * k]; };
+    auto lo_max = [&](uint32_t k) { return st[2 + kPartAxis * k]; };
+    auto hi_max = [&](uint32_t k) { return st[3 + kPartAxis * k]; };
+    auto ext_sum = [&](uint32_t k) { return st[4 + kPartAxis * k]; };
+    uint32_t axis = force_axis >= 0 && (uint32_t)force_axis < d ? (uint32_t)force_axis : 0u;
+    if (force_axis < 0 && c > 0.f) {
+      auto cost = [&](uint32_t k) {
+        const float range = lo_max(k) - lo_min(k);
+        return range > 0.f ? ext_sum(k) / range : __int_as_float(0x7f800000);
+      };
+      float best = cost(0);
 #pragma unroll 1
-    for (int j = 0; j < W; ++j) {
-      c += sred[j][2];
-      ext += sred[j][3];
-      ext0 += sred[j][8];
+      for (uint32_t k = 1; k < d; ++k)
+        if (cost(k) < 0.5f * best) {
+          best = cost(k);
+          axis = k;
+        }
     }
+    const uint32_t a0 = input_axis(0, axis), a1 = input_axis(1, axis), a2 = input_axis(2, axis);
+    // in sweep order: swept axis lower-bound range and extent sum; axis 1's
+    // range and extent sum; axes 1 and 2's ranges for the quantisation
+    const float v0 = lo_min(a0), v1 = lo_max(a0), ext0 = ext_sum(a0);
+    const float v4 = d >= 2 ? lo_min(a1) : 0.f, v5 = d >= 2 ? hi_max(a1) : 0.f;
+    const float ext = d >= 2 ? ext_sum(a1) : 0.f;
     BucketParams q;
     q.split = nullptr;
+    q.axis = axis;
+    q.spare = 0;
     q.nb = I.nb;
     q.vmin = 0.f;
     q.scale = 0.f;
@@ -274,10 +339,12 @@ __device__ void block_plan(const float *__restrict__ part, const InstPlan &I, bo
     q.ny = 1;
     q.vmin1 = 0.f;
     q.scale1 = 0.f;
-    for (int k = 0; k < 2; ++k) {
-      const float lo = v[4 + 2 * k], hi = v[5 + 2 * k];
+    for (uint32_t k = 0; k < 2; ++k) {
       q.qmin[k] = 0.f;
       q.qscale[k] = 0.f;  // every box quantises to 0: the pre-filter lets all pass
+      if (k + 1 >= d) continue;
+      const uint32_t ak = k == 0 ? a1 : a2;
+      const float lo = lo_min(ak), hi = hi_max(ak);
       if (c > 0.f && hi > lo) {
         const float qs = 65535.0f / (hi - lo);
         if (qs > 0.f && qs <= 3.0e38f) {
@@ -287,12 +354,12 @@ __device__ void block_plan(const float *__restrict__ part, const InstPlan &I, bo
       }
     }
     BucketParams g = q;
-    if (c > 0.f && v[1] > v[0] && I.nb > 0) {
+    if (c > 0.f && v1 > v0 && I.nb > 0) {
       // the sample's extremes lie about (max - min) / c inside the true ones;
       // widening the map by two such gaps keeps the regions beyond them from
       // piling into the first and last bucket
-      const float gap = 2.0f * (v[1] - v[0]) / c;
-      const float lo = v[0] - gap, hi = v[1] + gap;
+      const float gap = 2.0f * (v1 - v0) / c;
+      const float lo = v0 - gap, hi = v1 + gap;
       const float scale = (float)I.nb / (hi - lo);
       if (scale > 0.f && scale <= 3.0e38f && lo > -3.0e38f && hi < 3.0e38f) {
         q.vmin = lo;
@@ -303,9 +370,9 @@ __device__ void block_plan(const float *__restrict__ part, const InstPlan &I, bo
       // other kind (ext0 the mean swept-axis extent); rows pay for their
       // extra plan, count and copy work only when that is a few
       const float walk = (float)(I.n + I.m) * (ext0 / c) / (2.0f * (hi - lo));
-      if (q.valid && grid && I.d >= 2 && I.nb >= 4 && v[5] > v[4] && walk >= kGridWalk) {
-        const float gap1 = 2.0f * (v[5] - v[4]) / c;
-        const float lo1 = v[4] - gap1, hi1 = v[5] + gap1;
+      if (q.valid && grid && I.d >= 2 && I.nb >= 4 && v5 > v4 && walk >= kGridWalk) {
+        const float gap1 = 2.0f * (v5 - v4) / c;
+        const float lo1 = v4 - gap1, hi1 = v5 + gap1;
         float t = sqrtf((float)I.nb * ((hi1 - lo1) / (hi - lo)));
         if (ext > 0.f) t = fminf(t, (hi1 - lo1) / (8.0f * (ext / c)));
         if (t >= 2.0f) {  // false for NaN
@@ -337,29 +404,33 @@ __device__ void block_plan(const float *__restrict__ part, const InstPlan &I, bo
 // the slab map's: inputs whose axis-1 corners follow their swept-axis ones
 // (which fill only a diagonal of the grid) keep the slabs...  LDS: 2 nb words
 // with grid != 0.
+// force_axis: the swept axis, or -1 to let the plan choose (block_plan).
 __global__ __launch_bounds__(kPlanThreads) void bk_plan_kernel(const float *__restrict__ part,
-                                                               const float2 *__restrict__ pts,
+                                                               const float *__restrict__ pts,
                                                                View V,
                                                                BucketParams *__restrict__ P,
-                                                               uint32_t grid) {
+                                                               uint32_t grid, int force_axis) {
   __shared__ float sred[kPlanThreads / kWave][kPart];
   __shared__ BucketParams shp[2];
   __shared__ unsigned long long ssq[3];
   extern __shared__ uint32_t hist[];
   const InstPlan I = V.get(blockIdx.x);
   const uint32_t t = threadIdx.x;
-  // the sampled corners, loaded before the partials are reduced
+  block_plan<kPlanThreads>(part, I, grid != 0u, force_axis, sred, shp);
+  const BucketParams &q = shp[0], &g = shp[1];
+  // the sampled lower corners on the swept axis and axis 1 (sweep order)
   constexpr int U = (int)(kPlanPoints / kPlanThreads);
   const uint32_t cnt = min(I.nsmp * (uint32_t)kSampleThreads, kPlanPoints);
-  const float2 *pp = pts + (size_t)I.smp0 * kSampleThreads;
+  const uint32_t d = I.d;
+  const float *pp = pts + (size_t)I.smp0 * kSampleThreads * d;
+  const uint32_t s0 = input_axis(0, q.axis), s1 = input_axis(d >= 2 ? 1 : 0, q.axis);
   float2 x[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const uint32_t i = (uint32_t)u * kPlanThreads + t;
-    x[u] = grid && i < cnt ? pp[i] : make_float2(__int_as_float(0x7fc00000), 0.f);
+    x[u] = g.ny > 1 && i < cnt ? make_float2(pp[(size_t)i * d + s0], pp[(size_t)i * d + s1])
+                               : make_float2(__int_as_float(0x7fc00000), 0.f);
   }
-  block_plan<kPlanThreads>(part, I, grid != 0u, sred, shp);
-  const BucketParams &q = shp[0], &g = shp[1];
   bool use_grid = false;
   if (g.ny > 1) {  // uniform over the workgroup
     const uint32_t nb = I.nb;
@@ -499,6 +570,7 @@ __global__ __launch_bounds__(kThreads) void bk_count_kernel(
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         if ((uint32_t)r >= q.rows) continue;
+        sweep_order<D>(bx[r], p.axis);
         bool empty;
         err |= box_errors<D>(bx[r], empty, I.closed);
         if (empty) continue;
@@ -637,6 +709,7 @@ __global__ __launch_bounds__(kThreads) void bk_scatter_kernel(
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       if ((uint32_t)r >= q.rows) continue;
+      sweep_order<D>(bx[r], p.axis);
       bool empty;
       (void)box_errors<D>(bx[r], empty, I.closed);
       if (empty) continue;
@@ -700,6 +773,8 @@ __global__ __launch_bounds__(kThreads) void bk_scatter_pair_kernel(
         if (g < g1) {
           q[k] = group_of(g, I, n_total);
           load_group<D>(q[k], I.vec != 0, bx[k]);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) sweep_order<D>(bx[k][r], p.axis);
         }
       }
       uint32_t slot[G][4];  // odd slots still to collect, else ~0u
@@ -978,6 +1053,9 @@ struct SweepCtx {
   uint32_t *heavy = nullptr;
   const float4 *xc = nullptr;
   uint32_t *cntl = nullptr;
+  // the input axis swept, and where axes 1 and 2 of the sweep order sit in
+  // an input row
+  uint32_t axis = 0, k1 = 1, k2 = 2;
 };
 
 // The row test of a pair whose axis-1 lower bounds are ly and lx; the sweep
@@ -993,8 +1071,11 @@ __device__ __forceinline__ bool in_row(const SweepCtx &o, float ly, float lx) {
 template <int DM1>
 constexpr int kNearAxes = DM1 < 2 ? DM1 : 2;
 
-// Exact coordinates of axes 1 and 2 (at most) of region rid, from its row.
-template <int DM1>
+// Exact coordinates of axes 1 and 2 (at most, in sweep order) of region
+// rid, from its row.  PERM = false: the swept axis is input axis 0, so the
+// offsets are known at compile time (the only form on the hot paths of the
+// usual inputs); PERM = true reads them from the context.
+template <int DM1, bool PERM = false>
 __device__ __forceinline__ void other_axes(const SweepCtx &o, uint32_t rid, float (&lo)[2],
                                            float (&hi)[2]) {
   const bool upd = rid < o.n;
@@ -1004,8 +1085,9 @@ __device__ __forceinline__ void other_axes(const SweepCtx &o, uint32_t rid, floa
   const float *H = (upd ? o.I.uhi : o.I.shi) + row * D;
 #pragma unroll
   for (int c = 0; c < kNearAxes<DM1>; ++c) {
-    lo[c] = L[1 + c];
-    hi[c] = H[1 + c];
+    const uint32_t k = !PERM ? 1u + (uint32_t)c : (c == 0 ? o.k1 : o.k2);
+    lo[c] = L[k];
+    hi[c] = H[k];
   }
 }
 
@@ -1019,8 +1101,10 @@ __device__ __forceinline__ bool extra_axes(const SweepCtx &o, uint32_t ry, uint3
   const float *yl = (uy ? o.I.ulo : o.I.slo) + y * d, *yh = (uy ? o.I.uhi : o.I.shi) + y * d;
   const float *xl = (ux ? o.I.ulo : o.I.slo) + x * d, *xh = (ux ? o.I.uhi : o.I.shi) + x * d;
   bool hit = true;
-  for (uint32_t k = 3; k < d; ++k)
+  for (uint32_t j = 3; j < d; ++j) {
+    const uint32_t k = input_axis(j, o.axis);
     hit = hit && before(yl[k], xh[k], o.I.closed) && before(xl[k], yh[k], o.I.closed);
+  }
   return hit;
 }
 
@@ -1110,12 +1194,12 @@ __device__ __forceinline__ void visit(const Walker<DM1> &y, bool &have_y, float 
 
 // The exact test of a queued pair (ry walked, rx was met), then count or
 // emit as visit() does.
-template <int DM1, int MODE, bool GR>
+template <int DM1, int MODE, bool GR, bool PERM>
 __device__ __forceinline__ void resolve(uint32_t ry, uint32_t rx, unsigned long long &hits,
                                         const SweepCtx &o) {
   float ylo[2], yhi[2], xlo[2], xhi[2];
-  other_axes<DM1>(o, ry, ylo, yhi);
-  other_axes<DM1>(o, rx, xlo, xhi);
+  other_axes<DM1, PERM>(o, ry, ylo, yhi);
+  other_axes<DM1, PERM>(o, rx, xlo, xhi);
   bool hit = true;
 #pragma unroll
   for (int c = 0; c < kNearAxes<DM1>; ++c)
@@ -1451,6 +1535,10 @@ __device__ __forceinline__ void sweep_bucket(
                                               : (kDL ? kDLWords : 1)];
   uint32_t *DL = SCR;
   __shared__ uint32_t nbsub, maxspan, maxbsh;
+  // the swept input axis, read once at the start (a read of the instance's
+  // parameters near the end, where it is first needed, would stall every
+  // workgroup on its way out)
+  __shared__ uint32_t swept;
   const bool rows = kRows && R.cnt != nullptr && own_cnt != nullptr;
 
   if (MODE == 2 && gate && *gate == 0u) return;  // uniform over the grid
@@ -1525,6 +1613,7 @@ __device__ __forceinline__ void sweep_bucket(
     nbsub = 0;
     maxspan = 0;
     maxbsh = 0;
+    swept = DM1 > 0 && !SLAB && O.P ? O.P[inst].axis : 0u;
   }
   if (HV && MODE == 1)
     for (int k = t; k < CAP + kPad; k += THREADS) CNTL[k] = 0;
@@ -1589,12 +1678,18 @@ __device__ __forceinline__ void sweep_bucket(
     }
   }
   if (HV) {  // the exact bounds of axes 1 and 2 of every region, one row read each
+    o.axis = swept;
+    o.k1 = input_axis(1, o.axis);
+    o.k2 = input_axis(2, o.axis);
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
       const uint32_t s = t + i * THREADS;
       if (s < C) {
         float lo[2] = {0.f, 0.f}, hi[2] = {0.f, 0.f};
-        other_axes<DM1>(o, rk[i].z, lo, hi);
+        if (o.axis == 0u)
+          other_axes<DM1, false>(o, rk[i].z, lo, hi);
+        else
+          other_axes<DM1, true>(o, rk[i].z, lo, hi);
         XC[key[i]] = make_float4(lo[0], hi[0], lo[1], hi[1]);
       }
     }
@@ -1654,7 +1749,10 @@ __device__ __forceinline__ void sweep_bucket(
         y.q = DM1 > 0 ? walker_word<DM1>(yr.w) : 0u;
         if (HV) {
           float lo[2] = {0.f, 0.f}, hi[2] = {0.f, 0.f};
-          other_axes<DM1>(o, y.rid, lo, hi);
+          if (o.axis == 0u)
+            other_axes<DM1, false>(o, y.rid, lo, hi);
+          else
+            other_axes<DM1, true>(o, y.rid, lo, hi);
           y.c[0] = lo[0];
           y.c[1] = hi[0];
           y.c[2] = lo[1];
@@ -1700,9 +1798,20 @@ __device__ __forceinline__ void sweep_bucket(
         if (t == 0) heavy[2 + atomicAdd(&heavy[MODE == 2 ? 1 : 0], 1u)] = b;
       } else {
         const uint32_t nq = min(queued, (uint32_t)kQueue);
-        for (uint32_t k = t; k < nq; k += THREADS) {
-          const uint2 pr = queue[k];
-          resolve<DM1, MODE, GR>(pr.x, pr.y, hits, o);
+        // the swept axis is fetched here, not held through the walks
+        o.axis = swept;
+        o.k1 = input_axis(1, o.axis);
+        o.k2 = input_axis(2, o.axis);
+        if (o.axis == 0u) {  // uniform
+          for (uint32_t k = t; k < nq; k += THREADS) {
+            const uint2 pr = queue[k];
+            resolve<DM1, MODE, GR, false>(pr.x, pr.y, hits, o);
+          }
+        } else {
+          for (uint32_t k = t; k < nq; k += THREADS) {
+            const uint2 pr = queue[k];
+            resolve<DM1, MODE, GR, true>(pr.x, pr.y, hits, o);
+          }
         }
       }
     }
@@ -1748,7 +1857,7 @@ __global__ __launch_bounds__(kSplitThreads) void bk_split_kernel(
     uint32_t *__restrict__ T, uint32_t nb, uint32_t cap, uint32_t max_nb,
     BucketParams *__restrict__ P, uint4 *__restrict__ split, Header *__restrict__ hdr,
     uint32_t *__restrict__ bs_cur, uint32_t *__restrict__ heavy,
-    const float2 *__restrict__ pts, uint32_t sampled) {
+    const float *__restrict__ pts, uint32_t sampled, uint32_t d) {
   constexpr int PER = (int)(kMaxBuckets / kSplitThreads);
   __shared__ uint32_t red[kSplitThreads / kWave + 2];
   extern __shared__ uint32_t kext[];  // least and greatest sampled key per column
@@ -1777,7 +1886,7 @@ __global__ __launch_bounds__(kSplitThreads) void bk_split_kernel(
   const bool ok = splittable && total <= max_nb;  // uniform
   if (ok) {
     for (uint32_t i = t; i < sampled; i += kSplitThreads) {
-      const float x = pts[i].x;
+      const float x = pts[(size_t)i * d + p.axis];
       if (x != x) continue;  // no valid box was sampled there
       const uint32_t a = bucket_of(x, p.vmin, p.scale, p.nx);
       atomicMin(&kmin[a], encode_coord(x));
@@ -1861,7 +1970,7 @@ __global__ __launch_bounds__(THREADS) void bk_heavy_sweep_kernel(
 struct Ptrs {
   BucketParams *P;
   float *part;
-  float2 *pts;
+  float *pts;
   uint32_t *C, *T, *S, *SB, *bs_cur, *rec, *bs_rec, *heavy;
   uint4 *split;
   void *scan_tmp;
@@ -1875,7 +1984,7 @@ Ptrs pointers(const BucketArgs &a) {
   Ptrs p;
   p.P = reinterpret_cast<BucketParams *>(ws + L.params);
   p.part = reinterpret_cast<float *>(ws + L.sample_part);
-  p.pts = reinterpret_cast<float2 *>(ws + L.sample_pts);
+  p.pts = reinterpret_cast<float *>(ws + L.sample_pts);
   p.C = reinterpret_cast<uint32_t *>(ws + L.counts);
   p.T = reinterpret_cast<uint32_t *>(ws + L.totals);
   p.S = reinterpret_cast<uint32_t *>(ws + L.offsets);
@@ -1936,7 +2045,8 @@ void prepare_impl(const BucketArgs &a, hipStream_t s) {
   const Clear clr{a.hdr, p.T + L.nb, p.bs_cur, L.nb, a.inst_total, L.B, p.heavy};
   bk_sample_kernel<D><<<L.nsmp, kSampleThreads, 0, s>>>(p.V, p.part, p.pts, clr);
   const uint32_t grid = D >= 2 ? 1u : 0u;
-  bk_plan_kernel<<<L.B, kPlanThreads, grid ? 2 * lds : 0, s>>>(p.part, p.pts, p.V, p.P, grid);
+  bk_plan_kernel<<<L.B, kPlanThreads, grid ? 2 * lds : 0, s>>>(p.part, p.pts, p.V, p.P, grid,
+                                                               sweep_axis());
   count_scatter_impl<D>(a, s, a.zero, a.zero_count);
 }
 
@@ -1986,7 +2096,8 @@ void build_slabs_impl(const BucketArgs &a, const SlabBuild &sb, hipStream_t s) {
   const size_t lds = (size_t)L.max_nb * sizeof(uint32_t);
   const Clear clr{a.hdr, p.T + L.nb, p.bs_cur, L.nb, nullptr, L.B, nullptr};
   bk_sample_kernel<D><<<L.nsmp, kSampleThreads, 0, s>>>(p.V, p.part, p.pts, clr);
-  bk_plan_kernel<<<L.B, kPlanThreads, 0, s>>>(p.part, p.pts, p.V, p.P, 0u);  // slabs only
+  // slabs of the swept axis 0 only: resident simulations move regions by it
+  bk_plan_kernel<<<L.B, kPlanThreads, 0, s>>>(p.part, p.pts, p.V, p.P, 0u, 0);
   bk_count_kernel<D><<<L.nblk, kThreads, lds, s>>>(L.n_total, p.V, p.P, p.C, nullptr, 0u, a.hdr,
                                                    nullptr, 0u);
   bk_colscan_kernel<<<(L.nb + kColBuckets - 1) / kColBuckets, kColWaves * kWave, 0, s>>>(
@@ -2126,7 +2237,8 @@ BucketLayout bucket_layout(const InstSpec *inst, int64_t B, int d, const BucketT
   const size_t scanned = 2 * (size_t)L.nb_split + 1;  // bucket sizes + boundary-state sizes + 0
   L.params = take((size_t)B * sizeof(BucketParams));
   L.sample_part = take((size_t)std::max<uint32_t>(L.nsmp, 1) * kPart * sizeof(float));
-  L.sample_pts = take((size_t)std::max<uint32_t>(L.nsmp, 1) * kSampleThreads * 2 * sizeof(float));
+  L.sample_pts = take((size_t)std::max<uint32_t>(L.nsmp, 1) * kSampleThreads * (size_t)d *
+                      sizeof(float));
   L.counts = take(std::max(cell, cell_room) * sizeof(uint32_t));
   L.totals = take(scanned * sizeof(uint32_t));
   L.offsets = take(scanned * sizeof(uint32_t));
@@ -2192,7 +2304,7 @@ hipError_t bucket_split(const BucketArgs &a, hipStream_t s) {
   prof::mark(s, "bucket.split");
   bk_split_kernel<<<1, kSplitThreads, 2 * (size_t)L.nb * sizeof(uint32_t), s>>>(
       p.T, L.nb, bucket_cap(L.tune), L.nb_split, p.P, p.split, a.hdr, p.bs_cur, p.heavy, p.pts,
-      L.inst[0].nsmp * (uint32_t)kSampleThreads);
+      L.inst[0].nsmp * (uint32_t)kSampleThreads, (uint32_t)a.d);
   return hipGetLastError();
 }
 

@@ -75,6 +75,8 @@ def library() -> ctypes.CDLL:
         lib.ddm_strerror.restype = ctypes.c_char_p
         lib.ddm_set_path.argtypes = [ctypes.c_int]
         lib.ddm_set_path.restype = ctypes.c_int
+        lib.ddm_set_sweep_axis.argtypes = [ctypes.c_int]
+        lib.ddm_set_sweep_axis.restype = ctypes.c_int
         lib.ddm_last_path.argtypes = []
         lib.ddm_last_path.restype = ctypes.c_int
         lib.ddm_profile.argtypes = [ctypes.c_int]
@@ -127,6 +129,15 @@ def set_path(name: str) -> None:
     rc = library().ddm_set_path(PATHS[name])
     if rc != DDM_OK:
         raise DDMError(rc, "ddm_set_path")
+
+
+def set_sweep_axis(axis: int | None) -> None:
+    """Swept axis of later bucketed calls (process-global): None lets each
+    instance's plan choose the axis with the fewest expected 1-D candidates
+    (the default); an int forces that input axis."""
+    rc = library().ddm_set_sweep_axis(-1 if axis is None else int(axis))
+    if rc != DDM_OK:
+        raise DDMError(rc, "ddm_set_sweep_axis")
 
 
 def last_path():

@@ -167,6 +167,25 @@ def clustered_boxes(n: int, m: int, d: int, alpha: float, seed: int = 0, cluster
     return Instance(ulo, uhi, slo, shi, alpha, f"clustered_d{d}_n{n}_a{alpha:g}")
 
 
+def anisotropic_boxes(n: int, m: int, d: int, alpha: float, stretch: float = 100.0,
+                      seed: int = 0) -> Instance:
+    """The uniform workload with boxes ``stretch`` times longer on axis 0
+    than on the others (side l32 on axes 1 .. d-1, float32(stretch * l32) on
+    axis 0): axis 0 carries ``stretch`` times the 1-D candidates of any other
+    axis."""
+    side = side_length(alpha, n + m)
+    sides = np.full(d, side, dtype=np.float32)
+    sides[0] = np.float32(stretch * float(side))
+    out = []
+    for stream, cnt in ((UPD_STREAM, n), (SUB_STREAM, m)):
+        rng = generator(seed, 400 + stream)
+        lo = np.minimum((rng.random((cnt, d)) * L_SPACE).astype(np.float32), LO_MAX)
+        hi = (lo + sides).astype(np.float32)
+        out.append((lo, hi))
+    (ulo, uhi), (slo, shi) = out
+    return Instance(ulo, uhi, slo, shi, alpha, f"anisotropic_d{d}_n{n}_a{alpha:g}_x{stretch:g}")
+
+
 def tie_heavy(n: int, m: int, d: int, grid: int = 12, max_len: int = 4, seed: int = 0) -> Instance:
     """Small integer-grid boxes: lower corners in {0..grid}, side lengths in
     {0..max_len}.  Touching, nested, identical and empty intervals are all

@@ -97,6 +97,29 @@ def test_skewed_full_size(ddm, oracle, kind, d):
         assert ddm.last_path() == "bucketed"
 
 
+def test_anisotropic_full_size_swept_axis(ddm, oracle):
+    """n = m = 5e6, d = 2, boxes 100 times longer on axis 0 (sides 10 and
+    0.1): the plan sweeps axis 1 (5e6 1-D candidates instead of 5e8); the
+    per-update counts equal the oracle's (about a hundred pairs), and those of
+    a forced axis-0 sweep."""
+    inst = W.anisotropic_boxes(5_000_000, 5_000_000, 2, 1.0, seed=0)
+    g = _dev(inst)
+    _note(f"{inst.name} per_update, chosen axis")
+    k, per = ddm.match(*g, mode="per_update")
+    assert ddm.last_path() == "bucketed"
+    k_ref, per_ref, _ = oracle.sbm(inst.upd_lo, inst.upd_hi, inst.sub_lo, inst.sub_hi, pairs=False)
+    assert k_ref > 20  # the comparison is not on an empty result
+    assert k == k_ref
+    assert np.array_equal(per.cpu().numpy(), per_ref)
+    try:
+        ddm.set_sweep_axis(0)
+        _note(f"{inst.name} per_update, axis 0")
+        k0, per0 = ddm.match(*g, mode="per_update")
+    finally:
+        ddm.set_sweep_axis(None)
+    assert k0 == k_ref and np.array_equal(per0.cpu().numpy(), per_ref)
+
+
 def test_batched_workload_every_instance(ddm, oracle):
     """The 512-instance batch as one captured graph: every instance's count,
     per-update counts and pair list equal to the oracle's."""

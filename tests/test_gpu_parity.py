@@ -238,6 +238,26 @@ def test_correlated_d3_stress(ddm, oracle, alpha):
     check_all_modes(ddm, oracle, inst)
 
 
+def test_swept_axis_choice(ddm, oracle):
+    """Boxes 100 times longer on axis 0 than on axes 1 and 2: the plan sweeps
+    another axis; every forced axis gives the same result, equal to the
+    oracle in every output mode."""
+    inst = W.anisotropic_boxes(60_000, 50_000, 3, 30.0, seed=5)
+    try:
+        for axis in (None, 0, 1, 2):
+            ddm.set_sweep_axis(axis)
+            check_all_modes(ddm, oracle, inst, expect_bucketed=True)
+        ddm.set_sweep_axis(None)
+        closed = W.anisotropic_boxes(40_000, 45_000, 2, 20.0, seed=6)
+        check_all_modes(ddm, oracle, closed, closed=True, expect_bucketed=True)
+        ddm.set_sweep_axis(7)  # beyond d: axis 0
+        check_all_modes(ddm, oracle, closed, expect_bucketed=True)
+        with pytest.raises(ddm.DDMError):
+            ddm.set_sweep_axis(-2)
+    finally:
+        ddm.set_sweep_axis(None)
+
+
 @pytest.mark.parametrize("kind", ["loguniform", "clustered"])
 def test_skewed_inputs_split_buckets(ddm, oracle, kind):
     """Lower corners spread over six decades (sides proportional to them) or
