@@ -519,6 +519,18 @@ int ddm_set_sweep_axis(int axis);
 int ddm_profile(int enable);
 int ddm_profile_report(char *buf, size_t len);
 
+/*
+ * Achievable-bandwidth reference (diagnostic; not part of the method): a
+ * plain device copy of ``bytes`` (a multiple of 16, both pointers device
+ * memory aligned to 16 bytes) from src to dst with 16-byte loads and
+ * stores, run once to warm up and then reps times on the stream; *ms_out
+ * (host) receives the mean time of one copy in milliseconds.  The copy
+ * moves 2 * bytes through HBM.  Synchronises; creates and destroys two HIP
+ * events.  Errors: DDM_E_INVAL for bad arguments, DDM_E_DEVICE.
+ */
+int ddm_copy_probe(void *dst, const void *src, size_t bytes, int reps, void *stream,
+                   double *ms_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -106,3 +106,51 @@ extern "C" int ddm_profile_report(char *buf, size_t len) {
   memcpy(buf, out.c_str(), out.size() + 1);
   return DDM_OK;
 }
+
+// ------------------------------------------------ achievable bandwidth
+//
+// A plain device copy: 16-byte loads and stores in a grid-stride loop, eight
+// workgroups of 512 threads per CU.  Its rate is the bandwidth a streaming
+// kernel can reach on this device, the yardstick beside the published peak.
+namespace {
+
+__global__ __launch_bounds__(512) void copy_probe_kernel(uint4 *__restrict__ dst,
+                                                         const uint4 *__restrict__ src,
+                                                         size_t count) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+    dst[i] = src[i];
+}
+
+}  // namespace
+
+extern "C" int ddm_copy_probe(void *dst, const void *src, size_t bytes, int reps, void *stream,
+                              double *ms_out) {
+  if (!dst || !src || !ms_out || reps < 1 || (bytes & 15) ||
+      (reinterpret_cast<uintptr_t>(dst) & 15) || (reinterpret_cast<uintptr_t>(src) & 15))
+    return DDM_E_INVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t count = bytes / 16;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return DDM_E_DEVICE;
+  const unsigned grid = (unsigned)(cus > 0 ? cus * 8 : 2048);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return DDM_E_DEVICE;
+  int rc = DDM_OK;
+  copy_probe_kernel<<<grid, 512, 0, s>>>(static_cast<uint4 *>(dst),
+                                         static_cast<const uint4 *>(src), count);  // warm-up
+  if (hipEventRecord(e0, s) != hipSuccess) rc = DDM_E_DEVICE;
+  for (int r = 0; rc == DDM_OK && r < reps; ++r)
+    copy_probe_kernel<<<grid, 512, 0, s>>>(static_cast<uint4 *>(dst),
+                                           static_cast<const uint4 *>(src), count);
+  float ms = 0.f;
+  if (rc == DDM_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                       hipEventElapsedTime(&ms, e0, e1) != hipSuccess || hipGetLastError() != hipSuccess))
+    rc = DDM_E_DEVICE;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc == DDM_OK) *ms_out = (double)ms / reps;
+  return rc;
+}

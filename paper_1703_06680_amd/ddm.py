@@ -83,6 +83,9 @@ def library() -> ctypes.CDLL:
         lib.ddm_profile.restype = ctypes.c_int
         lib.ddm_profile_report.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
         lib.ddm_profile_report.restype = ctypes.c_int
+        lib.ddm_copy_probe.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int, vp,
+                                       ctypes.POINTER(ctypes.c_double)]
+        lib.ddm_copy_probe.restype = ctypes.c_int
         tp = ctypes.POINTER(Tuning)
         u64p = ctypes.POINTER(ctypes.c_uint64)
         lib.ddm_dim_counts_workspace_bytes.argtypes = [i64, i64, ctypes.c_int]
@@ -160,6 +163,25 @@ def profile_report() -> dict:
     if rc != DDM_OK:
         raise DDMError(rc, "ddm_profile_report")
     return json.loads(buf.value.decode())
+
+
+def copy_probe(nbytes: int = 256 << 20, reps: int = 10) -> dict:
+    """Achievable HBM bandwidth of a plain copy kernel of the library
+    (``ddm_copy_probe``): {"bytes_moved", "ms", "gb_per_s"} for one copy of
+    ``nbytes`` (read + write = 2 * nbytes)."""
+    nbytes = (int(nbytes) + 15) // 16 * 16
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    ms = ctypes.c_double(0.0)
+    stream = torch.cuda.current_stream()
+    rc = library().ddm_copy_probe(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                                  nbytes, int(reps), ctypes.c_void_p(stream.cuda_stream),
+                                  ctypes.byref(ms))
+    if rc != DDM_OK:
+        raise DDMError(rc, "ddm_copy_probe")
+    return {"bytes_moved": 2 * nbytes, "ms": ms.value,
+            "gb_per_s": 2 * nbytes / (ms.value * 1e-3) / 1e9}
 
 
 def _code(mode: str, closed: bool) -> int:

@@ -175,3 +175,20 @@ def test_noalloc_refuses_oversize_requests_before_touching_the_gpu(lib):
     lib.ddm_strerror.argtypes = [ctypes.c_int]
     lib.ddm_strerror.restype = ctypes.c_char_p
     assert b"scratch" in lib.ddm_strerror(-6)
+
+
+def test_copy_probe_rejects_bad_arguments_before_touching_the_gpu(lib):
+    """ddm_copy_probe checks pointers, alignment, size and repeat count on the
+    host first (no GPU is needed for these calls)."""
+    vp = ctypes.c_void_p
+    f = lib.ddm_copy_probe
+    f.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int, vp, ctypes.POINTER(ctypes.c_double)]
+    f.restype = ctypes.c_int
+    ms = ctypes.c_double(0.0)
+    a, b = vp(256), vp(512)  # never dereferenced
+    assert f(None, b, 64, 1, None, ctypes.byref(ms)) == -1
+    assert f(a, None, 64, 1, None, ctypes.byref(ms)) == -1
+    assert f(a, b, 64, 1, None, None) == -1
+    assert f(a, b, 64, 0, None, ctypes.byref(ms)) == -1
+    assert f(a, b, 60, 1, None, ctypes.byref(ms)) == -1
+    assert f(vp(264), b, 64, 1, None, ctypes.byref(ms)) == -1

@@ -339,6 +339,24 @@ def test_invalid_input_is_reported(ddm):
         assert e.value.code == ddm.DDM_E_INVAL
 
 
+def test_copy_probe_copies_and_times(ddm):
+    """The library's bandwidth yardstick copies its input exactly and
+    reports a positive time and a plausible rate."""
+    _note("copy probe")
+    src = torch.arange(1 << 20, dtype=torch.int32, device="cuda")
+    dst = torch.zeros_like(src)
+    ms = ddm.ctypes.c_double(0.0)
+    rc = ddm.library().ddm_copy_probe(ddm.ctypes.c_void_p(dst.data_ptr()),
+                                      ddm.ctypes.c_void_p(src.data_ptr()), src.numel() * 4, 3,
+                                      ddm.ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
+                                      ddm.ctypes.byref(ms))
+    torch.cuda.synchronize()
+    assert rc == 0 and ms.value > 0
+    assert torch.equal(dst, src)
+    c = ddm.copy_probe(64 << 20, reps=3)
+    assert c["bytes_moved"] == 128 << 20 and 100 < c["gb_per_s"] < 8000
+
+
 def test_capacity_retry(ddm, oracle):
     _note("capacity retry")
     inst = W.tie_heavy(50, 50, 2, grid=5, seed=1)
