@@ -21,8 +21,8 @@ struct BucketParams {
   float scale;
   uint32_t nb;
   uint32_t valid;
-  float qmin[2];     // 16-bit quantisation of the other axes (pre-filter)
-  float qscale[2];
+  float qmin[2];     // 16-bit quantisation of the other axes (pre-filter);
+  float qscale[2];   // see quant_t for the two forms of the map
   uint32_t nx, ny;   // columns, rows per column
   float vmin1;       // row map of axis 1's lower coordinate (ny > 1)
   float scale1;
@@ -30,7 +30,8 @@ struct BucketParams {
   // others follow in input order); kept in the first 64 bytes with the
   // fields every sweep workgroup reads first
   uint32_t axis;
-  uint32_t spare;
+  // bit k set: axis k + 1 is quantised on its encoded coordinate
+  uint32_t qenc;
   // split buckets (slabs only): if not null, column a of the map above became
   // the buckets split[a].x .. split[a].x + split[a].y - 1, by a map linear in
   // the encoded coordinate from split[a].z with scale __uint_as_float(split[a].w)
@@ -136,18 +137,31 @@ __device__ __forceinline__ uint32_t box_errors(const Box<D> &b, bool &empty, uin
 }
 
 // Conservative quantisation of a coordinate of another axis onto 16 bits by
-// the monotone map t = clamp((x - qmin) * qscale, 0, 65535): lower bounds
-// round down, upper bounds round up, so two boxes that overlap on that axis
-// also overlap after quantisation.  Quantised bounds only serve the
-// sweep's pre-filter; survivors are tested on the exact coordinates.
-__device__ __forceinline__ uint32_t quant_lo(float x, float qmin, float qs) {
-  float t = (x - qmin) * qs;
+// a monotone map t = clamp(quant_t(x), 0, 65535): lower bounds round down,
+// upper bounds round up, so two boxes that overlap on that axis also overlap
+// after quantisation.  Quantised bounds only serve the sweep's pre-filter;
+// survivors are tested on the exact coordinates.  The map is linear in the
+// coordinate, (x - qmin) * qscale, or, for an axis whose boxes spread over
+// many orders of magnitude, linear in its encoded coordinate (about
+// logarithmic in |x|): (enc(x) - e0) * qscale, e0 the bits held in qmin and
+// differences below 0 taken as 0.  Encoding, subtraction, conversion to
+// float and scaling are all non-decreasing, so either form is monotone.
+__device__ __forceinline__ float quant_t(float x, float qmin, float qs, bool enc) {
+  if (enc) {
+    const uint32_t e = encode_coord(x), e0 = __float_as_uint(qmin);
+    return (float)(e > e0 ? e - e0 : 0u) * qs;
+  }
+  return (x - qmin) * qs;
+}
+
+__device__ __forceinline__ uint32_t quant_lo(float x, float qmin, float qs, bool enc) {
+  float t = quant_t(x, qmin, qs, enc);
   t = fminf(fmaxf(t, 0.0f), 65535.0f);
   return (uint32_t)t;
 }
 
-__device__ __forceinline__ uint32_t quant_hi(float x, float qmin, float qs) {
-  float t = (x - qmin) * qs;
+__device__ __forceinline__ uint32_t quant_hi(float x, float qmin, float qs, bool enc) {
+  float t = quant_t(x, qmin, qs, enc);
   t = fminf(fmaxf(t, 0.0f), 65535.0f);
   return (uint32_t)ceilf(t);
 }
@@ -158,14 +172,14 @@ __device__ __forceinline__ uint32_t quant_hi(float x, float qmin, float qs) {
 // so the pre-filter stays conservative while keeping its resolution inside
 // a row (bounds beyond the row clamp to its ends).
 __device__ __forceinline__ uint32_t quant1_lo(float x, const BucketParams &p, uint32_t row) {
-  if (p.ny <= 1) return quant_lo(x, p.qmin[0], p.qscale[0]);
+  if (p.ny <= 1) return quant_lo(x, p.qmin[0], p.qscale[0], p.qenc & 1u);
   float t = ((x - p.vmin1) * p.scale1 - (float)row) * 65535.0f;
   t = fminf(fmaxf(t, 0.0f), 65535.0f);
   return (uint32_t)t;
 }
 
 __device__ __forceinline__ uint32_t quant1_hi(float x, const BucketParams &p, uint32_t row) {
-  if (p.ny <= 1) return quant_hi(x, p.qmin[0], p.qscale[0]);
+  if (p.ny <= 1) return quant_hi(x, p.qmin[0], p.qscale[0], p.qenc & 1u);
   float t = ((x - p.vmin1) * p.scale1 - (float)row) * 65535.0f;
   t = fminf(fmaxf(t, 0.0f), 65535.0f);
   return (uint32_t)ceilf(t);
@@ -184,8 +198,9 @@ __device__ __forceinline__ uint32_t qword_of(const Box<D> &b, const BucketParams
   if (D >= 3) {
     const uint32_t l1 = quant1_lo(b.lo[1 % D], p, row) >> 9;
     const uint32_t h1 = min(127u, (quant1_hi(b.hi[1 % D], p, row) + 511u) >> 9);
-    const uint32_t l2 = quant_lo(b.lo[2 % D], p.qmin[1], p.qscale[1]) >> 9;
-    const uint32_t h2 = min(127u, (quant_hi(b.hi[2 % D], p.qmin[1], p.qscale[1]) + 511u) >> 9);
+    const uint32_t l2 = quant_lo(b.lo[2 % D], p.qmin[1], p.qscale[1], p.qenc & 2u) >> 9;
+    const uint32_t h2 =
+        min(127u, (quant_hi(b.hi[2 % D], p.qmin[1], p.qscale[1], p.qenc & 2u) + 511u) >> 9);
     return l1 | (h1 << 8) | (l2 << 16) | (h2 << 24);
   }
   return 0u;

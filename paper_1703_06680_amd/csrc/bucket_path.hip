@@ -139,6 +139,9 @@ __device__ __forceinline__ void sweep_order(Box<D> &b, uint32_t axis) {
 // plan's workgroup size, and the mean slab walk (entries) from which rows
 // are tried.
 constexpr uint32_t kPlanPoints = 8192;
+constexpr uint32_t kQLevelBits = 8;  // levels of the plan's quantisation measure
+constexpr uint32_t kQLevels = 1u << kQLevelBits;
+constexpr uint32_t kQPoints = 512;  // sampled corners it is taken on (one per plan thread)
 constexpr int kPlanThreads = 512;
 constexpr float kGridWalk = 2.0f;
 
@@ -330,7 +333,7 @@ __device__ void block_plan(const float *__restrict__ part, const InstPlan &I, bo
     BucketParams q;
     q.split = nullptr;
     q.axis = axis;
-    q.spare = 0;
+    q.qenc = 0;
     q.nb = I.nb;
     q.vmin = 0.f;
     q.scale = 0.f;
@@ -398,12 +401,12 @@ __device__ void block_plan(const float *__restrict__ part, const InstPlan &I, bo
 }
 
 
-// One workgroup per instance: its bucket map and quantisation parameters.
-// A grid (grid != 0, d >= 2) is kept if the sampled corners' sum of squared
-// cell counts, which grows as they crowd into fewer cells, is at most 5/4 of
-// the slab map's: inputs whose axis-1 corners follow their swept-axis ones
-// (which fill only a diagonal of the grid) keep the slabs...  LDS: 2 nb words
-// with grid != 0.
+// One workgroup per instance: its bucket map and quantisation parameters,
+// from block_plan and two measures on the sampled corners (below).  A grid
+// (grid != 0, d >= 2) is kept if the corners' sum of squared cell counts,
+// which grows as they crowd into fewer cells, is small enough: inputs whose
+// axis-1 corners follow their swept-axis ones (which fill only a diagonal of
+// the grid) keep the slabs.  LDS: 2 nb words with grid != 0.
 // force_axis: the swept axis, or -1 to let the plan choose (block_plan).
 __global__ __launch_bounds__(kPlanThreads) void bk_plan_kernel(const float *__restrict__ part,
                                                                const float *__restrict__ pts,
@@ -413,6 +416,8 @@ __global__ __launch_bounds__(kPlanThreads) void bk_plan_kernel(const float *__re
   __shared__ float sred[kPlanThreads / kWave][kPart];
   __shared__ BucketParams shp[2];
   __shared__ unsigned long long ssq[3];
+  __shared__ uint32_t qh[4][kQLevels];  // [2 axis + map][level]
+  __shared__ uint32_t qsq[4];  // pairs of corners sharing a level, per map
   extern __shared__ uint32_t hist[];
   const InstPlan I = V.get(blockIdx.x);
   const uint32_t t = threadIdx.x;
@@ -423,21 +428,54 @@ __global__ __launch_bounds__(kPlanThreads) void bk_plan_kernel(const float *__re
   const uint32_t cnt = min(I.nsmp * (uint32_t)kSampleThreads, kPlanPoints);
   const uint32_t d = I.d;
   const float *pp = pts + (size_t)I.smp0 * kSampleThreads * d;
+  // (and axis 2): all loads issued before any is used
   const uint32_t s0 = input_axis(0, q.axis), s1 = input_axis(d >= 2 ? 1 : 0, q.axis);
+  const uint32_t s2 = input_axis(d >= 3 ? 2 : 0, q.axis);
+  const float nan = __int_as_float(0x7fc00000);
+  constexpr int UQ = (int)(kQPoints / kPlanThreads);
   float2 x[U];
+  float z[UQ];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const uint32_t i = (uint32_t)u * kPlanThreads + t;
-    x[u] = g.ny > 1 && i < cnt ? make_float2(pp[(size_t)i * d + s0], pp[(size_t)i * d + s1])
-                               : make_float2(__int_as_float(0x7fc00000), 0.f);
+    const bool in = d >= 2 && i < cnt;
+    x[u] = in ? make_float2(pp[(size_t)i * d + s0], pp[(size_t)i * d + s1]) : make_float2(nan, nan);
+    if (u < UQ) z[u] = in && d >= 3 ? pp[(size_t)i * d + s2] : nan;
   }
-  bool use_grid = false;
-  if (g.ny > 1) {  // uniform over the workgroup
-    const uint32_t nb = I.nb;
+  // Two measures on the sampled corners, in one pass:
+  // - the grid (g.ny > 1) is kept if its sum of squared cell counts is at
+  //   most 5/4 of the slabs' and at most twice what S points spread evenly
+  //   over nb cells give (S + S^2 / nb): a crowded grid would overflow cells,
+  //   which cannot be split, where the slab buckets of a skewed input can;
+  // - the other axes' quantisation is linear in the coordinate, unless the
+  //   encoded form (about logarithmic) spreads the sampled lower bounds much
+  //   better: the measure of a map is the number of pairs of kQPoints
+  //   sampled corners that share one of its kQLevels levels, proportional to
+  //   the chance that two boxes do, and the encoded map is taken where that
+  //   is under half the linear one's.
+  const bool try_grid = g.ny > 1;                    // uniform over the workgroup
+  const bool qmeasure = d >= 2 && sred[0][0] > 0.f;  // uniform over the workgroup
+  const uint32_t nb = I.nb;
+  const uint32_t na = d >= 3 ? 2u : 1u;
+  float e_min[2] = {0.f, 0.f}, e_scale[2] = {0.f, 0.f};
+  if (qmeasure)
+    for (uint32_t k = 0; k < 2; ++k) {
+      const uint32_t ak = k == 0 ? s1 : s2;
+      const uint32_t e0 = encode_coord(sred[0][1 + kPartAxis * ak]);
+      const uint32_t e1 = encode_coord(sred[0][3 + kPartAxis * ak]);
+      const float es = e1 > e0 ? 65535.0f / (float)(e1 - e0) : 0.f;
+      e_min[k] = __uint_as_float(e0);
+      e_scale[k] = es > 0.f && es <= 3.0e38f ? es : 0.f;
+    }
+  if (try_grid)
     for (uint32_t k = t; k < 2 * nb; k += kPlanThreads) hist[k] = 0u;
-    if (t < 3) ssq[t] = 0ull;
-    __syncthreads();
-    uint32_t points = 0;
+  if (qmeasure)
+    for (uint32_t k = t; k < 4 * kQLevels; k += kPlanThreads) qh[k / kQLevels][k % kQLevels] = 0u;
+  if (t < 3) ssq[t] = 0ull;
+  if (t < 4) qsq[t] = 0u;
+  __syncthreads();
+  uint32_t points = 0;
+  if (try_grid)
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (x[u].x != x[u].x) continue;  // no valid box was sampled there
@@ -447,28 +485,60 @@ __global__ __launch_bounds__(kPlanThreads) void bk_plan_kernel(const float *__re
       const uint32_t c = bucket_of(x[u].y, g.vmin1, g.scale1, g.ny);
       atomicAdd(&hist[nb + a * g.ny + c], 1u);
     }
-    __syncthreads();
-    unsigned long long s1 = 0, s2 = 0;
+  constexpr uint32_t kShift = 16 - kQLevelBits;
+  if (qmeasure)
+#pragma unroll
+    for (int u = 0; u < UQ; ++u)
+#pragma unroll
+      for (uint32_t k = 0; k < 2; ++k) {
+        const float y = k == 0 ? x[u].y : z[u];
+        if (k >= na || y != y) continue;  // no valid box was sampled there
+        atomicAdd(&qh[2 * k][quant_lo(y, q.qmin[k], q.qscale[k], false) >> kShift], 1u);
+        atomicAdd(&qh[2 * k + 1][quant_lo(y, e_min[k], e_scale[k], true) >> kShift], 1u);
+      }
+  __syncthreads();
+  if (try_grid) {
+    unsigned long long sq_slab = 0, sq_grid = 0;
     for (uint32_t k = t; k < nb; k += kPlanThreads) {
-      s1 += (unsigned long long)hist[k] * hist[k];
-      s2 += (unsigned long long)hist[nb + k] * hist[nb + k];
+      sq_slab += (unsigned long long)hist[k] * hist[k];
+      sq_grid += (unsigned long long)hist[nb + k] * hist[nb + k];
     }
-    s1 = wave_sum(s1);
-    s2 = wave_sum(s2);
+    sq_slab = wave_sum(sq_slab);
+    sq_grid = wave_sum(sq_grid);
     const unsigned long long pw = wave_sum((unsigned long long)points);
     if (lane_id() == 0) {
-      atomicAdd(&ssq[0], s1);
-      atomicAdd(&ssq[1], s2);
+      atomicAdd(&ssq[0], sq_slab);
+      atomicAdd(&ssq[1], sq_grid);
       atomicAdd(&ssq[2], pw);
     }
-    __syncthreads();
-    // ... and at most twice what S points spread evenly over nb cells give
-    // (S + S^2 / nb): a crowded grid would overflow cells, which cannot be
-    // split, where the slab buckets of a skewed input can
-    const unsigned long long S = ssq[2];
-    use_grid = 4ull * ssq[1] <= 5ull * ssq[0] && ssq[1] <= 2ull * (S + S * S / nb);
   }
-  if (t == 0) P[blockIdx.x] = shp[use_grid ? 1 : 0];
+  if (qmeasure) {  // wave w sums half of map w / 2 (maps beyond 2 na stay unused)
+    static_assert(kPlanThreads / kWave == 8 && kQLevels % (2 * kWave) == 0, "map halves");
+    const uint32_t m = (t / kWave) / 2u, k0 = (t / kWave) % 2u * (kQLevels / 2);
+    uint32_t sq = 0;
+    if (m < 2 * na)
+      for (uint32_t k = k0 + (uint32_t)lane_id(); k < k0 + kQLevels / 2; k += kWave) {
+        const uint32_t h = qh[m][k];
+        sq += h * (h ? h - 1u : 0u);
+      }
+    sq = wave_sum(sq);
+    if (lane_id() == 0 && m < 2 * na) atomicAdd(&qsq[m], sq);
+  }
+  __syncthreads();
+  if (t == 0) {
+    const unsigned long long S = ssq[2];
+    const bool use_grid =
+        try_grid && 4ull * ssq[1] <= 5ull * ssq[0] && ssq[1] <= 2ull * (S + S * S / nb);
+    BucketParams out = shp[use_grid ? 1 : 0];
+    if (qmeasure)
+      for (uint32_t k = 0; k < na; ++k)
+        if (e_scale[k] > 0.f && 2u * qsq[2 * k + 1] < qsq[2 * k]) {
+          out.qenc |= 1u << k;
+          out.qmin[k] = e_min[k];
+          out.qscale[k] = e_scale[k];
+        }
+    P[blockIdx.x] = out;
+  }
 }
 
 // ------------------------------------------------------ row groups
@@ -1417,9 +1487,25 @@ __device__ __forceinline__ void emit_rows(
     if (t == 0) atomicOr(R.flag, 1u);
     return;
   }
-  // (b) one wave per bucket update
+  // (b) one wave per bucket update.  The update's pair count and row offset
+  // are read one row ahead, so that their latency overlaps the walk of the
+  // row before.
+  int cnt_next = 0;
+  unsigned long long base_next = 0;
+  if ((uint32_t)w < Cu) {
+    const uint32_t r0 = RID[w];
+    cnt_next = R.cnt[r0];
+    base_next = o.pair_off[r0];
+  }
   for (uint32_t up = (uint32_t)w; up < Cu; up += W) {
     const uint32_t ku = KLO[up], hu = KHI[up], ru = RID[up];
+    const int cnt_u = cnt_next;
+    const unsigned long long base = base_next;
+    if (up + W < Cu) {
+      const uint32_t rn = RID[up + W];
+      cnt_next = R.cnt[rn];
+      base_next = o.pair_off[rn];
+    }
     const uint32_t fl = fine_of(decode_coord(ku), vmn, fscale, FINE);
     const uint32_t fh = fine_of(decode_coord(hu - o.I.closed), vmn, fscale, FINE);
     const uint32_t j0 = bin_begin(FINE + (fl > span ? fl - span : 0u));
@@ -1449,7 +1535,7 @@ __device__ __forceinline__ void emit_rows(
       append(hit, hit ? BSR[ii] - n : 0u);
     }
     if (L == 0) continue;
-    if (L > kRowStage || L > (uint32_t)R.cnt[ru]) {  // uniform over the wave; never expected
+    if (L > kRowStage || L > (uint32_t)cnt_u) {  // uniform over the wave; never expected
       if (lane == 0) atomicOr(R.flag, 1u);
       continue;
     }
@@ -1457,8 +1543,7 @@ __device__ __forceinline__ void emit_rows(
     const uint32_t L4 = (L + 3) & ~3u;
     if ((uint32_t)lane < L4 - L) stage[L + lane] = 0xFFFFFFFFu;
     __builtin_amdgcn_wave_barrier();
-    const unsigned long long base = o.pair_off[ru];
-    const bool full = (uint32_t)R.cnt[ru] == L;  // no pairs in later buckets
+    const bool full = (uint32_t)cnt_u == L;  // no pairs in later buckets
     uint32_t *ids = full ? R.ids : o.out_s;
     int2 *pairs = full ? reinterpret_cast<int2 *>(R.pairs) : nullptr;
     if (L <= kWave)

@@ -186,6 +186,41 @@ def anisotropic_boxes(n: int, m: int, d: int, alpha: float, stretch: float = 100
     return Instance(ulo, uhi, slo, shi, alpha, f"anisotropic_d{d}_n{n}_a{alpha:g}_x{stretch:g}")
 
 
+def signed_logscale_boxes(n: int, m: int, d: int, alpha: float, seed: int = 0,
+                          other_alpha: float | None = None, decades: float = 6.0,
+                          straddle: float = 0.01) -> Instance:
+    """Axis 0 as in the uniform workload (side alpha L / N); on axes 1 ..
+    d-1 lower corners of random sign with magnitudes log-uniform over
+    ``decades`` decades from 1, each side proportional to its magnitude
+    (side = |lo| * other_alpha * ln(10^decades) / N, other_alpha = alpha by
+    default); a fraction ``straddle`` of the boxes instead spans
+    [-u, v) with u, v uniform on [0, 1), across zero."""
+    oa = alpha if other_alpha is None else other_alpha
+    side0 = side_length(alpha, n + m)
+    rel = np.float32(oa * decades * math.log(10.0) / max(n + m, 1))
+    out = []
+    for stream, cnt in ((UPD_STREAM, n), (SUB_STREAM, m)):
+        rng = generator(seed, 500 + stream)
+        lo = np.empty((cnt, d), dtype=np.float32)
+        hi = np.empty((cnt, d), dtype=np.float32)
+        lo[:, 0] = np.minimum((rng.random(cnt) * L_SPACE).astype(np.float32), LO_MAX)
+        hi[:, 0] = (lo[:, 0] + side0).astype(np.float32)
+        for k in range(1, d):
+            mag = np.exp(rng.random(cnt) * decades * math.log(10.0)).astype(np.float32)
+            sign = np.where(rng.random(cnt) < 0.5, np.float32(-1.0), np.float32(1.0))
+            lk = (sign * mag).astype(np.float32)
+            lo[:, k] = lk
+            hi[:, k] = (lk + (mag * rel).astype(np.float32)).astype(np.float32)
+            cross = rng.random(cnt) < straddle
+            lo[cross, k] = -rng.random(int(cross.sum())).astype(np.float32)
+            hi[cross, k] = rng.random(int(cross.sum())).astype(np.float32)
+            fix = hi[:, k] < lo[:, k]
+            hi[fix, k] = lo[fix, k]
+        out.append((lo, hi))
+    (ulo, uhi), (slo, shi) = out
+    return Instance(ulo, uhi, slo, shi, alpha, f"signedlog_d{d}_n{n}_a{alpha:g}_o{oa:g}")
+
+
 def tie_heavy(n: int, m: int, d: int, grid: int = 12, max_len: int = 4, seed: int = 0) -> Instance:
     """Small integer-grid boxes: lower corners in {0..grid}, side lengths in
     {0..max_len}.  Touching, nested, identical and empty intervals are all

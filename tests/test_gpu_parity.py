@@ -273,6 +273,18 @@ def test_skewed_inputs_split_buckets(ddm, oracle, kind):
     check_all_modes(ddm, oracle, inst, closed=True, expect_bucketed=True)
 
 
+def test_other_axes_over_many_magnitudes(ddm, oracle):
+    """Axes 1 and 2 spread over six decades on both sides of zero (a few
+    boxes across it): the plan quantises them on the encoded coordinate.
+    Every output mode on both paths equal to the oracle, half-open and
+    closed."""
+    for d in (2, 3):
+        inst = W.signed_logscale_boxes(100_000, 90_000, d, 40.0, seed=d, other_alpha=2000.0)
+        check_all_modes(ddm, oracle, inst, expect_bucketed=True)
+    inst = W.signed_logscale_boxes(60_000, 70_000, 3, 40.0, seed=9, other_alpha=3000.0)
+    check_all_modes(ddm, oracle, inst, closed=True, expect_bucketed=True)
+
+
 def test_heavy_buckets_grid_and_closed(ddm, oracle):
     """Buckets whose quantised pre-filter passes more pairs than the sweep's
     queue holds are listed and swept again with the exact bounds of axes 1
