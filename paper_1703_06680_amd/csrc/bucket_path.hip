@@ -334,6 +334,7 @@ __device__ void block_plan(const float *__restrict__ part, const InstPlan &I, bo
     q.split = nullptr;
     q.axis = axis;
     q.qenc = 0;
+    q.qaxis = 1;
     q.nb = I.nb;
     q.vmin = 0.f;
     q.scale = 0.f;
@@ -530,13 +531,20 @@ __global__ __launch_bounds__(kPlanThreads) void bk_plan_kernel(const float *__re
     const bool use_grid =
         try_grid && 4ull * ssq[1] <= 5ull * ssq[0] && ssq[1] <= 2ull * (S + S * S / nb);
     BucketParams out = shp[use_grid ? 1 : 0];
+    uint32_t pairs_of[2] = {0u, 0u};  // the chosen map's measure per axis
     if (qmeasure)
-      for (uint32_t k = 0; k < na; ++k)
+      for (uint32_t k = 0; k < na; ++k) {
+        pairs_of[k] = qsq[2 * k];
         if (e_scale[k] > 0.f && 2u * qsq[2 * k + 1] < qsq[2 * k]) {
           out.qenc |= 1u << k;
           out.qmin[k] = e_min[k];
           out.qscale[k] = e_scale[k];
+          pairs_of[k] = qsq[2 * k + 1];
         }
+      }
+    // the pre-filter's axis (d >= 3): axis 2 on a grid, whose rows bound
+    // axis 1 already; on slabs the axis whose levels fewer sampled pairs share
+    out.qaxis = d >= 3 && (use_grid || pairs_of[1] < pairs_of[0]) ? 2u : 1u;
     P[blockIdx.x] = out;
   }
 }
@@ -1032,30 +1040,19 @@ __device__ __forceinline__ uint32_t qdiff(uint32_t entry, uint32_t walker) {
                                           __builtin_bit_cast(u16x2, walker)));
 }
 
-// Pre-filter words.  d = 2: the 16-bit bounds of axis 1 as above.  d >= 3:
-// one word of four 7-bit fields; the entry word holds, per axis, lo and
-// 127 - hi in consecutive bytes, the walker word hi and 127 - lo with the top
-// bit of every byte set.  walker - entry then borrows across no byte, and the
-// top bit of each byte survives exactly when that byte of the entry is not
-// above the walker's: both axes pass iff all four top bits survive.
+// Pre-filter words (d >= 2): the 16-bit bounds of one other axis (the
+// record word, qword_of) as above, the entry word lo | (65535 - hi) << 16
+// and the walker word hi | (65535 - lo) << 16.
 template <int DM1>
 __device__ __forceinline__ uint32_t entry_word(uint32_t w) {
-  if (DM1 == 1) return (w & 0xFFFFu) | ((65535u - (w >> 16)) << 16);
-  // bytes lo1, hi1, lo2, hi2 -> lo1, 127 - hi1, lo2, 127 - hi2
-  return (w & 0x00FF00FFu) | (0x7F007F00u - (w & 0xFF00FF00u));
+  return (w & 0xFFFFu) | ((65535u - (w >> 16)) << 16);
 }
 
 // The walker word of a region from its own entry word.
 template <int DM1>
 __device__ __forceinline__ uint32_t walker_from_entry(uint32_t e) {
-  if (DM1 == 1) {
-    const uint32_t lq = e & 0xFFFFu, hq = 65535u - (e >> 16);
-    return hq | ((65535u - lq) << 16);
-  }
-  // entry bytes a0, b0, a1, b1 (a = lo, b = 127 - hi) -> walker bytes
-  // hi, 127 - lo per axis = 127 - b, 127 - a, plus the top bits
-  const uint32_t swapped = ((e & 0x00FF00FFu) << 8) | ((e >> 8) & 0x00FF00FFu);
-  return (0x7F7F7F7Fu - swapped) | 0x80808080u;
+  const uint32_t lq = e & 0xFFFFu, hq = 65535u - (e >> 16);
+  return hq | ((65535u - lq) << 16);
 }
 
 template <int DM1>
@@ -1290,9 +1287,7 @@ __device__ __forceinline__ void resolve(uint32_t ry, uint32_t rx, unsigned long 
 // Zero iff entry word e passes the walker's pre-filter (d >= 2).
 template <int DM1>
 __device__ __forceinline__ uint32_t qfail(uint32_t e, uint32_t wq) {
-  if (DM1 >= 2) return ~(wq - e) & 0x80808080u;  // a cleared top bit: some byte failed
-  if (DM1 == 1) return qdiff(e, wq);
-  return 0u;
+  return DM1 > 0 ? qdiff(e, wq) : 0u;
 }
 
 __device__ __forceinline__ uint32_t min4(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
