@@ -1580,7 +1580,7 @@ __device__ __forceinline__ void sweep_bucket(
     uint32_t *__restrict__ cursor, uint32_t *__restrict__ out_u, uint32_t *__restrict__ out_s,
     unsigned long long *__restrict__ total, unsigned long long *__restrict__ inst_total,
     const uint32_t *__restrict__ gate, uint32_t *__restrict__ own_cnt, const RowEmit &R,
-    uint32_t *__restrict__ heavy) {
+    uint32_t *__restrict__ heavy, uint32_t *__restrict__ bucket_hits) {
   constexpr bool SLAB = KIND == kSlabSweep;
   constexpr bool HV = KIND == kHeavySweep && DM1 > 0;
   constexpr int ITEMS = CAP / THREADS;
@@ -1622,6 +1622,8 @@ __device__ __forceinline__ void sweep_bucket(
   const bool rows = kRows && R.cnt != nullptr && own_cnt != nullptr;
 
   if (MODE == 2 && gate && *gate == 0u) return;  // uniform over the grid
+  // the counting sweep found no pair here: the emitting one has nothing to do
+  if (MODE == 2 && bucket_hits && bucket_hits[b] == 0u) return;  // uniform
   // the count pass gave up, or another bucket did not fit: the records may
   // be incomplete and the host falls back (uniform over the workgroup)
   if (!SLAB && hdr->pad[0]) return;
@@ -1910,6 +1912,9 @@ __device__ __forceinline__ void sweep_bucket(
       atomicAdd(total, tot);
       if (inst_total) atomicAdd(&inst_total[inst], tot);
     }
+    // whether the bucket has pairs, for the emitting sweep (a bucket listed
+    // as heavy: counted later, so yes)
+    if (MODE != 2 && bucket_hits) bucket_hits[b] = tot != 0ull || heavy_flag ? 1u : 0u;
   }
 }
 
@@ -2023,10 +2028,10 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
     uint32_t *__restrict__ out_u, uint32_t *__restrict__ out_s,
     unsigned long long *__restrict__ total, unsigned long long *__restrict__ inst_total,
     const uint32_t *__restrict__ gate, uint32_t *__restrict__ own_cnt, RowEmit R,
-    uint32_t *__restrict__ heavy) {
+    uint32_t *__restrict__ heavy, uint32_t *__restrict__ bucket_hits) {
   sweep_bucket<DM1, MODE, CAP, THREADS, FINE, SLAB ? kSlabSweep : kLightSweep>(
       blockIdx.x, rec, O, V, bs_rec, bs_cap, n, hdr, per_update, pair_off, cursor, out_u, out_s,
-      total, inst_total, gate, own_cnt, R, heavy);
+      total, inst_total, gate, own_cnt, R, heavy, bucket_hits);
 }
 
 // The heavy buckets the light sweep listed, a workgroup at a time.
@@ -2037,12 +2042,13 @@ __global__ __launch_bounds__(THREADS) void bk_heavy_sweep_kernel(
     const unsigned long long *__restrict__ pair_off, uint32_t *__restrict__ cursor,
     uint32_t *__restrict__ out_u, uint32_t *__restrict__ out_s,
     unsigned long long *__restrict__ total, unsigned long long *__restrict__ inst_total,
-    const uint32_t *__restrict__ gate, uint32_t *__restrict__ heavy) {
+    const uint32_t *__restrict__ gate, uint32_t *__restrict__ heavy,
+    uint32_t *__restrict__ bucket_hits) {
   const uint32_t listed = heavy[MODE == 2 ? 1 : 0];
   for (uint32_t i = blockIdx.x; i < listed; i += gridDim.x) {  // uniform
     sweep_bucket<DM1, MODE, CAP, THREADS, FINE, kHeavySweep>(
         heavy[2 + i], rec, O, V, bs_rec, bs_cap, n, hdr, per_update, pair_off, cursor, out_u,
-        out_s, total, inst_total, gate, nullptr, RowEmit{}, heavy);
+        out_s, total, inst_total, gate, nullptr, RowEmit{}, heavy, bucket_hits);
     __syncthreads();  // LDS is reused by the next bucket
   }
 }
@@ -2142,30 +2148,30 @@ void sweep_impl(const BucketArgs &a, int32_t *per_update, const unsigned long lo
   if (L.tune.sweep_threads == 1024) {
     bk_sweep_kernel<DM1, MODE, kBigCap, 1024, 1024><<<L.nb, 1024, 0, s>>>(
         p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
-        out_u, out_s, total, a.inst_total, gate, a.own, a.rows, p.heavy);
+        out_u, out_s, total, a.inst_total, gate, a.own, a.rows, p.heavy, p.bs_cur);
     if (DM1 > 0) prof::mark(s, MODE == 2 ? "bucket.sweep.emit.heavy" : "bucket.sweep.heavy");
     if (DM1 > 0)
       bk_heavy_sweep_kernel<DM1, MODE, kBigCap, 1024, 1024><<<(hgrid + 1) / 2, 1024, 0, s>>>(
           p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
-          out_u, out_s, total, a.inst_total, gate, p.heavy);
+          out_u, out_s, total, a.inst_total, gate, p.heavy, p.bs_cur);
   } else if (L.tune.sweep_threads == 256) {
     bk_sweep_kernel<DM1, MODE, kCap, 256, 512><<<L.nb, 256, 0, s>>>(
         p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
-        out_u, out_s, total, a.inst_total, gate, a.own, a.rows, p.heavy);
+        out_u, out_s, total, a.inst_total, gate, a.own, a.rows, p.heavy, p.bs_cur);
     if (DM1 > 0) prof::mark(s, MODE == 2 ? "bucket.sweep.emit.heavy" : "bucket.sweep.heavy");
     if (DM1 > 0)
       bk_heavy_sweep_kernel<DM1, MODE, kCap, 256, 512><<<hgrid, 256, 0, s>>>(
           p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
-          out_u, out_s, total, a.inst_total, gate, p.heavy);
+          out_u, out_s, total, a.inst_total, gate, p.heavy, p.bs_cur);
   } else {
     bk_sweep_kernel<DM1, MODE, kCap, 512, 512><<<L.nb, 512, 0, s>>>(
         p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
-        out_u, out_s, total, a.inst_total, gate, a.own, a.rows, p.heavy);
+        out_u, out_s, total, a.inst_total, gate, a.own, a.rows, p.heavy, p.bs_cur);
     if (DM1 > 0) prof::mark(s, MODE == 2 ? "bucket.sweep.emit.heavy" : "bucket.sweep.heavy");
     if (DM1 > 0)
       bk_heavy_sweep_kernel<DM1, MODE, kCap, 512, 512><<<hgrid, 512, 0, s>>>(
           p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
-          out_u, out_s, total, a.inst_total, gate, p.heavy);
+          out_u, out_s, total, a.inst_total, gate, p.heavy, p.bs_cur);
   }
 }
 
@@ -2205,7 +2211,7 @@ void sweep_slabs_impl(const SlabSweep &w, hipStream_t s) {
   O.bs_slab = w.bs_slab;
   bk_sweep_kernel<DM1, 0, kCap, 512, 512, true><<<w.nb, 512, 0, s>>>(
       w.rec, O, V, w.bs_rec, 0u, w.nv, w.hdr, nullptr, nullptr, nullptr, nullptr, nullptr,
-      &w.hdr->total, nullptr, nullptr, nullptr, RowEmit{}, nullptr);
+      &w.hdr->total, nullptr, nullptr, nullptr, RowEmit{}, nullptr, nullptr);
 }
 
 // Host-side plan of one instance; returns false if it does not fit.
