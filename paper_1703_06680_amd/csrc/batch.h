@@ -16,7 +16,7 @@ namespace ddm {
 
 // Byte offsets of the batch workspace.
 struct BatchLayout {
-  size_t hdr, offs, gate, cnt, off, cur, pu, ps, pu2, ps2, scan_tmp, sort_tmp, region;
+  size_t hdr, offs, gate, cnt, off, cur, ps, scan_tmp, region;
   BucketLayout bk;
   size_t total;
 };

@@ -12,10 +12,11 @@
 //
 // Pairs are produced as in a single call: per-update counts, an exclusive
 // scan into per-update slots (the first pass of a two-pass compaction), an
-// emitting sweep, and two stable radix sorts (by subscription row, then by
-// update row) into lexicographic order; the rows in the concatenated arrays
-// are finally turned into instance-local ids, and each instance's first pair
-// is the slot of its first update.
+// emitting sweep that writes each update's subscriptions into its row, and
+// one wave per row that orders the row in LDS and writes it as
+// instance-local (update, subscription) ids; each instance's first pair is
+// the slot of its first update.  A row longer than the row sort holds sets
+// a flag, and the batch is then finished instance by instance.
 #include <string.h>
 
 #include <algorithm>
@@ -27,6 +28,7 @@
 #include "batch.h"
 #include "bucket_path.h"
 #include "common.h"
+#include "match_global.h"
 #include "primitives.h"
 #include "profile.h"
 
@@ -34,8 +36,6 @@ namespace ddm {
 namespace {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-int bit_length(uint32_t x) { return x ? 32 - __builtin_clz(x) : 0; }
 
 template <typename T>
 T *at(void *ws, size_t off) {
@@ -59,7 +59,8 @@ __global__ void bt_widen_kernel(const int32_t *__restrict__ cnt, unsigned long l
 
 // After the scan off[n_total] is the number of pairs K.  gate[0] = K if the
 // pairs fit the capacity, else 0 (nothing is emitted); gate[1] = 1 if they do
-// not fit.  pair_off[b] = off[first update row of instance b].
+// not fit; gate[2] = 0, set to 1 by the row sort if a row is longer than it
+// holds.  pair_off[b] = off[first update row of instance b].
 __global__ void bt_gate_kernel(const unsigned long long *__restrict__ off, uint32_t n_total,
                                uint64_t cap, const uint32_t *__restrict__ uoff, uint32_t B,
                                int64_t *__restrict__ pair_off, uint32_t *__restrict__ gate) {
@@ -69,6 +70,7 @@ __global__ void bt_gate_kernel(const unsigned long long *__restrict__ off, uint3
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     gate[0] = K <= cap ? (uint32_t)K : 0u;
     gate[1] = K > cap ? 1u : 0u;
+    gate[2] = 0u;
   }
 }
 
@@ -87,18 +89,53 @@ __device__ __forceinline__ uint32_t instance_of_row(const uint32_t *__restrict__
   return lo;
 }
 
-// Ordered (update row, subscription row) pairs -> instance-local int32 ids.
-__global__ void bt_pairs_out_kernel(const uint32_t *__restrict__ ru, const uint32_t *__restrict__ rs,
-                                    const uint32_t *__restrict__ gate,
-                                    const uint32_t *__restrict__ uoff,
-                                    const uint32_t *__restrict__ soff, uint32_t B,
-                                    int32_t *__restrict__ pairs) {
-  const uint32_t K = gate[0];
-  for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < K; p += gridDim.x * blockDim.x) {
-    const uint32_t u = ru[p], s = rs[p];
-    const uint32_t b = instance_of_row(uoff, B, u);
-    pairs[2 * (size_t)p] = (int32_t)(u - uoff[b]);
-    pairs[2 * (size_t)p + 1] = (int32_t)(s - soff[b]);
+// Orders every row of the emitted pairs: row u (an update row of the
+// concatenated arrays) holds the cnt[u] subscription rows it meets at
+// in[off[u] ..), in the order the sweep found them.  One wave per row stages
+// it in LDS as instance-local subscription ids and writes the pairs
+// (instance-local update id, subscription id) in order at pairs[off[u] ..):
+// up to 128 ids sorted across the wave in registers, longer rows by ranks
+// (ids in a row are distinct).  A row longer than kRowMax is left and sets
+// gate[2]; nothing runs if the pairs did not fit (gate[0] == 0).
+constexpr int kBtRowThreads = 512;
+constexpr int kBtRowWaves = kBtRowThreads / kWave;
+
+__global__ __launch_bounds__(kBtRowThreads) void bt_row_sort_kernel(
+    const unsigned long long *__restrict__ off, const int32_t *__restrict__ cnt,
+    const uint32_t *__restrict__ in, uint32_t n, const uint32_t *__restrict__ uoff,
+    const uint32_t *__restrict__ soff, uint32_t B, uint32_t *__restrict__ gate,
+    int2 *__restrict__ pairs) {
+  __shared__ __align__(16) uint32_t stage[kBtRowWaves][kRowMax];
+  if (gate[0] == 0u) return;  // uniform: no pairs, or they did not fit
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  uint32_t *row = stage[w];
+  // each wave takes 64 consecutive rows at a time, finds with one ballot the
+  // ones with work and orders those one after the other
+  const uint32_t step = gridDim.x * kBtRowWaves * kWave;
+  for (uint32_t u0 = (blockIdx.x * kBtRowWaves + w) * kWave; u0 < n; u0 += step) {
+    const uint32_t mine = u0 + (uint32_t)lane;
+    const uint32_t c = mine < n ? (uint32_t)cnt[mine] : 0u;
+    if (c > kRowMax) gate[2] = 1u;
+    uint64_t todo = __ballot(c != 0u && c <= kRowMax);
+    while (todo) {
+      const uint32_t u = u0 + (uint32_t)(__ffsll((unsigned long long)todo) - 1);
+      todo &= todo - 1;
+      const uint32_t L = (uint32_t)cnt[u];
+      const unsigned long long base = off[u];
+      const uint32_t b = instance_of_row(uoff, B, u);
+      const uint32_t ul = u - uoff[b], s0 = soff[b];
+      const uint32_t L4 = (L + 3) & ~3u;  // padded with ids above every real one
+      for (uint32_t i = lane; i < L4; i += kWave) row[i] = i < L ? in[base + i] - s0 : 0xFFFFFFFFu;
+      __builtin_amdgcn_wave_barrier();
+      if (L <= kWave)
+        sort_row<1>(row, L, lane, ul, base, nullptr, pairs);
+      else if (L <= 2 * kWave)
+        sort_row<2>(row, L, lane, ul, base, nullptr, pairs);
+      else
+        for (uint32_t i0 = 0; i0 < L; i0 += 4 * kWave)
+          rank_row<4>(row, L, L4, i0, lane, ul, base, nullptr, pairs);
+      __builtin_amdgcn_wave_barrier();  // every lane done with the row before the next one
+    }
   }
 }
 
@@ -183,12 +220,8 @@ BatchLayout batch_layout(const InstSpec *spec, int64_t B, int d, int mode, int64
   if (mode == DDM_PAIRS) {
     L.off = take((n_total + 1) * sizeof(unsigned long long));
     L.cur = take(n_total * sizeof(uint32_t));
-    L.pu = take(c * sizeof(uint32_t));
     L.ps = take(c * sizeof(uint32_t));
-    L.pu2 = take(c * sizeof(uint32_t));
-    L.ps2 = take(c * sizeof(uint32_t));
     L.scan_tmp = take(scan_temp_bytes(n_total + 1));
-    L.sort_tmp = take(radix_sort_temp_bytes((uint32_t)(c ? c : 1)));
   }
   L.region = at_;
   L.bk = bucket_layout(spec, B, d, t);
@@ -351,7 +384,6 @@ int upload(const Batch &c, hipStream_t s, std::vector<uint32_t> &staging, void *
 int enqueue(const Batch &c, hipStream_t s) {
   const BatchLayout &L = c.L;
   const uint32_t n_total = (uint32_t)c.uoff[(size_t)c.B];
-  const uint32_t m_total = (uint32_t)c.soff[(size_t)c.B];
   Header *hdr = at<Header>(c.ws, L.hdr);
   const uint32_t *uoff = at<uint32_t>(c.ws, L.offs);
   const uint32_t *soff = uoff + c.B + 1;
@@ -370,8 +402,7 @@ int enqueue(const Batch &c, hipStream_t s) {
   if (c.mode == DDM_PAIRS) {
     unsigned long long *off = at<unsigned long long>(c.ws, L.off);
     uint32_t *cur = at<uint32_t>(c.ws, L.cur);
-    uint32_t *pu = at<uint32_t>(c.ws, L.pu), *ps = at<uint32_t>(c.ws, L.ps);
-    uint32_t *pu2 = at<uint32_t>(c.ws, L.pu2), *ps2 = at<uint32_t>(c.ws, L.ps2);
+    uint32_t *ps = at<uint32_t>(c.ws, L.ps);
     prof::mark(s, "batch.pairs.scan");
     bt_widen_kernel<<<grid_for((size_t)n_total + 1), 256, 0, s>>>(cnt, off, n_total);
     DDM_HIP(exclusive_scan_u64(off, off, (size_t)n_total + 1, at<void>(c.ws, L.scan_tmp), s));
@@ -380,21 +411,16 @@ int enqueue(const Batch &c, hipStream_t s) {
     DDM_HIP(fill_u32(cur, 0u, n_total, s));
     BucketArgs emit = a;
     emit.inst_total = nullptr;  // the counting pass has set them
-    DDM_HIP(bucket_sweep(emit, 2, nullptr, off, cur, pu, ps, &hdr->aux[0], s, gate));
-    if (c.cap > 0) {
+    // rows are implied by the offsets: the sweep writes subscription rows only
+    DDM_HIP(bucket_sweep(emit, 2, nullptr, off, cur, nullptr, ps, &hdr->aux[0], s, gate));
+    if (c.cap > 0 && n_total > 0) {
       prof::mark(s, "batch.pairs.order");
-      KeyTransform raw{0, 0, 0};
-      const uint32_t cap = (uint32_t)c.cap;
-      int in_b = 0;
-      DDM_HIP(radix_sort_pairs(ps, pu, ps2, pu2, cap, bit_length(m_total ? m_total - 1 : 0), false,
-                               raw, at<void>(c.ws, L.sort_tmp), s, &in_b, gate));
-      uint32_t *sk = in_b ? ps2 : ps, *sv = in_b ? pu2 : pu;  // keys = s, vals = u
-      uint32_t *ok = in_b ? ps : ps2, *ov = in_b ? pu : pu2;
-      DDM_HIP(radix_sort_pairs(sv, sk, ok, ov, cap, bit_length(n_total ? n_total - 1 : 0), false,
-                               raw, at<void>(c.ws, L.sort_tmp), s, &in_b, gate));
-      const uint32_t *ru = in_b ? ok : sv, *rs = in_b ? ov : sk;
-      bt_pairs_out_kernel<<<grid_for(cap), 256, 0, s>>>(ru, rs, gate, uoff, soff, (uint32_t)c.B,
-                                                        c.pairs);
+      const unsigned rgrid =
+          (unsigned)std::max<size_t>(1, std::min<size_t>((n_total + kBtRowWaves * kWave - 1) /
+                                                             (kBtRowWaves * kWave), 4096));
+      bt_row_sort_kernel<<<rgrid, kBtRowThreads, 0, s>>>(off, cnt, ps, n_total, uoff, soff,
+                                                         (uint32_t)c.B, gate,
+                                                         reinterpret_cast<int2 *>(c.pairs));
     }
   }
   DDM_HIP(hipGetLastError());
@@ -462,7 +488,8 @@ int finish(const Batch &c, hipStream_t s, uint64_t *total_host, bool *fell_back)
   DDM_HIP(hipStreamSynchronize(s));
   prof::flush();
   if (h.err) return DDM_E_INVAL;
-  if (h.pad[0]) {
+  // a bucket overflowed, or a row was longer than the row sort holds
+  if (h.pad[0] || (c.mode == DDM_PAIRS && gate[0] != 0u && gate[2] != 0u)) {
     if (fell_back) *fell_back = true;
     return run_each(c, s, total_host);
   }
@@ -637,7 +664,19 @@ extern "C" int ddm_batch_graph_launch(ddm_batch_graph *g, void *stream) {
 extern "C" int ddm_batch_graph_result(ddm_batch_graph *g, void *stream, uint64_t *total_host) {
   if (!g || !g->exec || !total_host) return DDM_E_INVAL;
   *total_host = 0;
-  return batch_finish(g->c, static_cast<hipStream_t>(stream), total_host);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  bool fell_back = false;
+  const int rc = batch_finish(g->c, s, total_host, &fell_back);
+  if (fell_back) {
+    // the instance-by-instance fallback ran in the same workspace: put back
+    // the batch plan and offsets that the captured launches read, so that the
+    // next replay starts from them again
+    std::vector<uint32_t> staging;
+    const int up = upload(g->c, s, staging, nullptr);
+    if (up != DDM_OK) return up;
+    if (hipStreamSynchronize(s) != hipSuccess) return DDM_E_DEVICE;
+  }
+  return rc;
 }
 
 extern "C" int ddm_batch_graph_destroy(ddm_batch_graph *g) {

@@ -183,6 +183,56 @@ def test_batched_overflow_falls_back(ddm, oracle):
     graph.close()
 
 
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_batched_rows_beyond_the_row_sort(ddm, oracle, d):
+    """A batch whose rows all fit (1 to 2048 pairs) is ordered row by row;
+    updates that meet more subscriptions than one wave orders in LDS (rows
+    of 2049 and 3000 pairs) send the batch to instance-by-instance calls,
+    with identical results, in a plain call and in graph replays (twice
+    after such a fallback: it ran in the workspace the replays read)."""
+    rng = np.random.default_rng(11 + d)
+
+    def wide(n_wide, m, seed):
+        # subscriptions spread over the space (no bucket overflows); update i
+        # spans every other axis and, on axis 0, the first k subscriptions
+        t = W.uniform_instance(60, m, d, alpha=2.0, seed=seed)
+        ulo, uhi = t.upd_lo.copy(), t.upd_hi.copy()
+        slo = (rng.random((m, d)) * 1.0e6).astype(np.float32)
+        shi = (slo + 1.0).astype(np.float32)
+        order = np.argsort(slo[:, 0], kind="stable")
+        for i, k in enumerate(n_wide):
+            ulo[i] = -1.0
+            uhi[i] = 2.0e6
+            uhi[i, 0] = np.nextafter(slo[order[k - 1], 0], np.float32(1e9))
+        return W.Instance(ulo, uhi, slo, shi, float("nan"), f"wide{n_wide}")
+
+    def longest(refs):
+        return max(int(r[1].max()) for r in refs if r[1].size)
+
+    fits = [wide([2048, 1, 64, 65, 128, 129, 700], 2600, 1), _mixed(d, seed=4)[4]]
+    refs = _oracle_all(oracle, fits)
+    assert longest(refs) == 2048
+    K = sum(r[0] for r in refs)
+    batch, _ = _device_batch(ddm, fits, "pairs", cap=K)
+    _check(batch, fits, refs, "pairs", batch.run())
+    graph = batch.graph()
+    for _ in range(2):
+        graph.launch()
+        _check(batch, fits, refs, "pairs", graph.result())
+    graph.close()
+    long_rows = _mixed(d, seed=6)[:5] + [wide([2049, 3000, 5], 3100, 2)] + _mixed(d, seed=6)[5:]
+    refs = _oracle_all(oracle, long_rows)
+    assert longest(refs) == 3000
+    K = sum(r[0] for r in refs)
+    batch, _ = _device_batch(ddm, long_rows, "pairs", cap=K)
+    _check(batch, long_rows, refs, "pairs", batch.run())
+    graph = batch.graph()
+    for _ in range(2):
+        graph.launch()
+        _check(batch, long_rows, refs, "pairs", graph.result())
+    graph.close()
+
+
 @pytest.mark.parametrize("d", [5, 9])
 def test_batched_high_d(ddm, oracle, d):
     """d = 5 runs as one bucketed batch and replays as a graph; d = 9, beyond
