@@ -109,32 +109,44 @@ __global__ __launch_bounds__(kBtRowThreads) void bt_row_sort_kernel(
   if (gate[0] == 0u) return;  // uniform: no pairs, or they did not fit
   const int w = threadIdx.x / kWave, lane = lane_id();
   uint32_t *row = stage[w];
-  // each wave takes 64 consecutive rows at a time, finds with one ballot the
-  // ones with work and orders those one after the other
+  // each wave takes kGroups groups of 64 consecutive rows at a time (their
+  // counts loaded together: most rows of a sparse output are empty), finds
+  // with one ballot per group the rows with work and orders those one after
+  // the other
+  constexpr uint32_t kGroups = 4;
   const uint32_t step = gridDim.x * kBtRowWaves * kWave;
-  for (uint32_t u0 = (blockIdx.x * kBtRowWaves + w) * kWave; u0 < n; u0 += step) {
-    const uint32_t mine = u0 + (uint32_t)lane;
-    const uint32_t c = mine < n ? (uint32_t)cnt[mine] : 0u;
-    if (c > kRowMax) gate[2] = 1u;
-    uint64_t todo = __ballot(c != 0u && c <= kRowMax);
-    while (todo) {
-      const uint32_t u = u0 + (uint32_t)(__ffsll((unsigned long long)todo) - 1);
-      todo &= todo - 1;
-      const uint32_t L = (uint32_t)cnt[u];
-      const unsigned long long base = off[u];
-      const uint32_t b = instance_of_row(uoff, B, u);
-      const uint32_t ul = u - uoff[b], s0 = soff[b];
-      const uint32_t L4 = (L + 3) & ~3u;  // padded with ids above every real one
-      for (uint32_t i = lane; i < L4; i += kWave) row[i] = i < L ? in[base + i] - s0 : 0xFFFFFFFFu;
-      __builtin_amdgcn_wave_barrier();
-      if (L <= kWave)
-        sort_row<1>(row, L, lane, ul, base, nullptr, pairs);
-      else if (L <= 2 * kWave)
-        sort_row<2>(row, L, lane, ul, base, nullptr, pairs);
-      else
-        for (uint32_t i0 = 0; i0 < L; i0 += 4 * kWave)
-          rank_row<4>(row, L, L4, i0, lane, ul, base, nullptr, pairs);
-      __builtin_amdgcn_wave_barrier();  // every lane done with the row before the next one
+  for (uint32_t g0 = (blockIdx.x * kBtRowWaves + w) * kWave; g0 < n; g0 += kGroups * step) {
+    uint32_t cg[kGroups];
+#pragma unroll
+    for (uint32_t k = 0; k < kGroups; ++k) {
+      const uint32_t mine = g0 + k * step + (uint32_t)lane;
+      cg[k] = mine < n ? (uint32_t)cnt[mine] : 0u;
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kGroups; ++k) {
+      const uint32_t u0 = g0 + k * step;
+      const uint32_t c = cg[k];
+      if (c > kRowMax) gate[2] = 1u;
+      uint64_t todo = __ballot(c != 0u && c <= kRowMax);
+      while (todo) {
+        const uint32_t u = u0 + (uint32_t)(__ffsll((unsigned long long)todo) - 1);
+        todo &= todo - 1;
+        const uint32_t L = (uint32_t)cnt[u];
+        const unsigned long long base = off[u];
+        const uint32_t b = instance_of_row(uoff, B, u);
+        const uint32_t ul = u - uoff[b], s0 = soff[b];
+        const uint32_t L4 = (L + 3) & ~3u;  // padded with ids above every real one
+        for (uint32_t i = lane; i < L4; i += kWave) row[i] = i < L ? in[base + i] - s0 : 0xFFFFFFFFu;
+        __builtin_amdgcn_wave_barrier();
+        if (L <= kWave)
+          sort_row<1>(row, L, lane, ul, base, nullptr, pairs);
+        else if (L <= 2 * kWave)
+          sort_row<2>(row, L, lane, ul, base, nullptr, pairs);
+        else
+          for (uint32_t i0 = 0; i0 < L; i0 += 4 * kWave)
+            rank_row<4>(row, L, L4, i0, lane, ul, base, nullptr, pairs);
+        __builtin_amdgcn_wave_barrier();  // every lane done with the row before the next one
+      }
     }
   }
 }
