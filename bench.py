@@ -454,6 +454,10 @@ def main():
     ap.add_argument("--also-alphas", default="1,10",
                     help="comma-separated extra alphas reported under per_alpha ('' for none)")
     ap.add_argument("--mode", default="per_update", choices=["count", "per_update"])
+    ap.add_argument("--workload", default="uniform",
+                    choices=["uniform", "correlated", "loguniform", "clustered"],
+                    help="input of the timed steps: the uniform boxes the metric is quoted on "
+                         "(default), or a stress input of the same size, for kernel profiles")
     ap.add_argument("--n", type=int, default=5_000_000, help="n = m boxes per side")
     ap.add_argument("--d", type=int, default=3)
     ap.add_argument("--path", default="auto", choices=["auto", "bucketed", "global"],
@@ -522,7 +526,14 @@ def main():
     n = m = args.n
     d = args.d
     t0 = time.time()
-    inst = W.uniform_instance(n, m, d, args.alpha, seed=0)
+    if args.workload == "correlated" and d != 3:
+        print("bench.py: the correlated workload is three-dimensional (--d 3)", file=sys.stderr)
+        sys.exit(2)
+    make = {"uniform": lambda: W.uniform_instance(n, m, d, args.alpha, seed=0),
+            "correlated": lambda: W.correlated_d3(n, args.alpha, seed=0),
+            "loguniform": lambda: W.loguniform_boxes(n, m, d, args.alpha, seed=0),
+            "clustered": lambda: W.clustered_boxes(n, m, d, args.alpha, seed=0)}[args.workload]
+    inst = make()
     gen_s = time.time() - t0
     g = [torch.from_numpy(a).to(dev) for a in (inst.upd_lo, inst.upd_hi, inst.sub_lo, inst.sub_hi)]
     ws = torch.empty(ddm.workspace_bytes(n, m, d, args.mode), dtype=torch.uint8, device=dev)
@@ -798,8 +809,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"uniform boxes d={d}, n=m={n} (N={regions}), alpha={args.alpha:g}, "
-                               f"side=alpha*1e6/N on [0,1e6)^{d}, {args.mode} output",
+        "config": {"workload": (f"uniform boxes d={d}, n=m={n} (N={regions}), alpha={args.alpha:g}, "
+                                f"side=alpha*1e6/N on [0,1e6)^{d}, {args.mode} output"
+                                if args.workload == "uniform" else
+                                f"{inst.name} ({args.workload} stress input), {args.mode} output"),
                    "d": d, "n": n, "m": m, "alpha": args.alpha, "mode": args.mode,
                    "parallelism": "single GPU"},
         "matches": k,

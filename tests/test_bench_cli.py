@@ -22,7 +22,7 @@ def test_help_lists_the_measurements():
                        capture_output=True, text=True, timeout=120, cwd=ROOT)
     assert r.returncode == 0
     for flag in ("--steps", "--warmup", "--no-batched", "--no-served", "--no-heavy",
-                 "--no-correlated", "--no-closed", "--copy-probe", "--path"):
+                 "--no-correlated", "--no-closed", "--copy-probe", "--path", "--workload"):
         assert flag in r.stdout, flag
 
 
