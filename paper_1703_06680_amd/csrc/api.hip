@@ -311,7 +311,7 @@ int run_bucketed(const Call &c, bool replayed = false) {
   if (!replayed) {
     DDM_HIP(bucket_prepare(a, c.s));
     DDM_HIP(bucket_sweep(a, count_mode, c.cnt, nullptr, nullptr, nullptr, nullptr,
-                         &c.hdr->total, c.s));
+                         &c.hdr->total, c.s, nullptr, c.mode == DDM_PAIRS));
   }
   int rc = header();
   if (rc != DDM_OK) return rc;
@@ -328,7 +328,7 @@ int run_bucketed(const Call &c, bool replayed = false) {
     a.L = &split;
     DDM_HIP(bucket_prepare_split(a, c.s));
     DDM_HIP(bucket_sweep(a, count_mode, c.cnt, nullptr, nullptr, nullptr, nullptr,
-                         &c.hdr->total, c.s));
+                         &c.hdr->total, c.s, nullptr, c.mode == DDM_PAIRS));
     rc = header();
     if (rc != DDM_OK) return rc;
   }

@@ -410,7 +410,7 @@ int enqueue(const Batch &c, hipStream_t s) {
   prep.zero_count = cnt ? n_total : 0u;
   DDM_HIP(bucket_prepare(prep, s));
   DDM_HIP(bucket_sweep(a, c.mode == DDM_COUNT ? 0 : 1, cnt, nullptr, nullptr, nullptr, nullptr,
-                       &hdr->total, s));
+                       &hdr->total, s, nullptr, c.mode == DDM_PAIRS));
   if (c.mode == DDM_PAIRS) {
     unsigned long long *off = at<unsigned long long>(c.ws, L.off);
     uint32_t *cur = at<uint32_t>(c.ws, L.cur);

@@ -120,7 +120,7 @@ struct BucketLayout {
   size_t bytes;                        // workspace bytes for all buffers below
   // byte offsets inside the bucket workspace
   size_t params, sample_part, sample_pts, counts, totals, offsets, block_offsets, scan_tmp, bs_cur,
-      rec, bs_rec, heavy, split, plan, maps;
+      rec, bs_rec, heavy, split, plan, maps, hits;
   PlanList inst;                       // host copy of the per-instance plan
 };
 
@@ -189,10 +189,12 @@ hipError_t bucket_prepare_split(const BucketArgs &a, hipStream_t s);
 // the subscription) at pair_off[u] plus a per-update cursor (zeroed
 // beforehand).  In mode 2, if ``gate`` is not null and *gate is 0 on the
 // device, the launch writes nothing (the pairs did not fit their buffer).
+// A mode-2 sweep visits only the buckets in which the mode-1 sweep before it
+// found pairs, so that one must be made with ``mark`` (which marks them).
 hipError_t bucket_sweep(const BucketArgs &a, int mode, int32_t *per_update,
                         const unsigned long long *pair_off, uint32_t *cursor, uint32_t *out_u,
                         uint32_t *out_s, unsigned long long *total, hipStream_t s,
-                        const uint32_t *gate = nullptr);
+                        const uint32_t *gate = nullptr, bool mark = false);
 
 // Slab layout of one instance for a resident simulation (resident.hip):
 // bucket j's regions at slots [j * cap, j * cap + cnt[j]) of ids (region

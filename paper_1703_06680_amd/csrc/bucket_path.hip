@@ -198,6 +198,7 @@ struct View {
 struct Clear {
   Header *hdr;
   uint32_t *bs_size, *bs_cur;
+  uint32_t *hits;  // per bucket: whether the counting sweep found pairs there
   uint32_t nb;
   unsigned long long *inst_total;
   uint32_t B;
@@ -216,7 +217,10 @@ __global__ __launch_bounds__(kSampleThreads) void bk_sample_kernel(View V,
     if (tid < 2 && clr.heavy) clr.heavy[tid] = 0u;
     for (uint32_t i = tid; i <= clr.nb; i += stride) {
       clr.bs_size[i] = 0u;
-      if (i < clr.nb) clr.bs_cur[i] = 0u;
+      if (i < clr.nb) {
+        clr.bs_cur[i] = 0u;
+        if (clr.hits) clr.hits[i] = 0u;
+      }
     }
     if (clr.inst_total)
       for (uint32_t i = tid; i < clr.B; i += stride) clr.inst_total[i] = 0ull;
@@ -1572,7 +1576,7 @@ __device__ __forceinline__ void emit_rows(
 // The sweep of bucket b (every kind; see SweepCtx).  heavy: the heavy-bucket
 // list ([0] buckets listed by the count sweeps, [1] by the emitting ones,
 // then the list), filled by the light sweep.
-template <int DM1, int MODE, int CAP, int THREADS, int FINE, int KIND>
+template <int DM1, int MODE, int CAP, int THREADS, int FINE, int KIND, bool MARK = false>
 __device__ __forceinline__ void sweep_bucket(
     uint32_t b, const uint32_t *__restrict__ rec, const Offsets &O, const View &V,
     const uint32_t *__restrict__ bs_rec, uint32_t bs_cap, uint32_t n, Header *__restrict__ hdr,
@@ -1877,7 +1881,10 @@ __device__ __forceinline__ void sweep_bucket(
     } else if (DM1 > 0 && !HV) {  // 4. the exact test of the queued pairs, all at once
       __syncthreads();
       if (KIND == kLightSweep && heavy_flag) {  // uniform: listed, counted by the heavy sweep
-        if (t == 0) heavy[2 + atomicAdd(&heavy[MODE == 2 ? 1 : 0], 1u)] = b;
+        if (t == 0) {
+          heavy[2 + atomicAdd(&heavy[MODE == 2 ? 1 : 0], 1u)] = b;
+          if (MARK) bucket_hits[b] = 1u;  // it has pairs to emit
+        }
       } else {
         const uint32_t nq = min(queued, (uint32_t)kQueue);
         // the swept axis is fetched here, not held through the walks
@@ -1911,10 +1918,12 @@ __device__ __forceinline__ void sweep_bucket(
     if (tot) {
       atomicAdd(total, tot);
       if (inst_total) atomicAdd(&inst_total[inst], tot);
+      // the emitting sweep visits only the buckets marked here (the marks
+      // start cleared).  Only the counting sweeps of pair-mode calls mark
+      // (MARK): the store's mere presence in the kernel made the sweeps of
+      // the other calls a sixth slower.
+      if (MARK) bucket_hits[b] = 1u;
     }
-    // whether the bucket has pairs, for the emitting sweep (a bucket listed
-    // as heavy: counted later, so yes)
-    if (MODE != 2 && bucket_hits) bucket_hits[b] = tot != 0ull || heavy_flag ? 1u : 0u;
   }
 }
 
@@ -1941,7 +1950,7 @@ constexpr int kSplitThreads = 1024;
 __global__ __launch_bounds__(kSplitThreads) void bk_split_kernel(
     uint32_t *__restrict__ T, uint32_t nb, uint32_t cap, uint32_t max_nb,
     BucketParams *__restrict__ P, uint4 *__restrict__ split, Header *__restrict__ hdr,
-    uint32_t *__restrict__ bs_cur, uint32_t *__restrict__ heavy,
+    uint32_t *__restrict__ bs_cur, uint32_t *__restrict__ hits, uint32_t *__restrict__ heavy,
     const float *__restrict__ pts, uint32_t sampled, uint32_t d) {
   constexpr int PER = (int)(kMaxBuckets / kSplitThreads);
   __shared__ uint32_t red[kSplitThreads / kWave + 2];
@@ -1997,11 +2006,15 @@ __global__ __launch_bounds__(kSplitThreads) void bk_split_kernel(
       split[b] = make_uint4(run, k[i], z, __float_as_uint(sc));
       run += k[i];
     }
-    // the boundary-state sizes, the zero after them and the cursors of the
-    // split layout (its bucket totals come from the next column scan)
+    // the boundary-state sizes, the zero after them, the cursors and the
+    // pair marks of the split layout (its bucket totals come from the next
+    // column scan)
     for (uint32_t j = t; j <= total; j += kSplitThreads) {
       T[total + j] = 0u;
-      if (j < total) bs_cur[j] = 0u;
+      if (j < total) {
+        bs_cur[j] = 0u;
+        hits[j] = 0u;
+      }
     }
     if (t < 2) heavy[t] = 0u;
   }
@@ -2020,7 +2033,7 @@ __global__ __launch_bounds__(kSplitThreads) void bk_split_kernel(
   }
 }
 
-template <int DM1, int MODE, int CAP, int THREADS, int FINE, bool SLAB = false>
+template <int DM1, int MODE, int CAP, int THREADS, int FINE, bool SLAB = false, bool MARK = false>
 __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
     const uint32_t *__restrict__ rec, Offsets O, View V, const uint32_t *__restrict__ bs_rec,
     uint32_t bs_cap, uint32_t n, Header *__restrict__ hdr, int32_t *__restrict__ per_update,
@@ -2029,13 +2042,13 @@ __global__ __launch_bounds__(THREADS) void bk_sweep_kernel(
     unsigned long long *__restrict__ total, unsigned long long *__restrict__ inst_total,
     const uint32_t *__restrict__ gate, uint32_t *__restrict__ own_cnt, RowEmit R,
     uint32_t *__restrict__ heavy, uint32_t *__restrict__ bucket_hits) {
-  sweep_bucket<DM1, MODE, CAP, THREADS, FINE, SLAB ? kSlabSweep : kLightSweep>(
+  sweep_bucket<DM1, MODE, CAP, THREADS, FINE, SLAB ? kSlabSweep : kLightSweep, MARK>(
       blockIdx.x, rec, O, V, bs_rec, bs_cap, n, hdr, per_update, pair_off, cursor, out_u, out_s,
       total, inst_total, gate, own_cnt, R, heavy, bucket_hits);
 }
 
 // The heavy buckets the light sweep listed, a workgroup at a time.
-template <int DM1, int MODE, int CAP, int THREADS, int FINE>
+template <int DM1, int MODE, int CAP, int THREADS, int FINE, bool MARK = false>
 __global__ __launch_bounds__(THREADS) void bk_heavy_sweep_kernel(
     const uint32_t *__restrict__ rec, Offsets O, View V, const uint32_t *__restrict__ bs_rec,
     uint32_t bs_cap, uint32_t n, Header *__restrict__ hdr, int32_t *__restrict__ per_update,
@@ -2046,7 +2059,7 @@ __global__ __launch_bounds__(THREADS) void bk_heavy_sweep_kernel(
     uint32_t *__restrict__ bucket_hits) {
   const uint32_t listed = heavy[MODE == 2 ? 1 : 0];
   for (uint32_t i = blockIdx.x; i < listed; i += gridDim.x) {  // uniform
-    sweep_bucket<DM1, MODE, CAP, THREADS, FINE, kHeavySweep>(
+    sweep_bucket<DM1, MODE, CAP, THREADS, FINE, kHeavySweep, MARK>(
         heavy[2 + i], rec, O, V, bs_rec, bs_cap, n, hdr, per_update, pair_off, cursor, out_u,
         out_s, total, inst_total, gate, nullptr, RowEmit{}, heavy, bucket_hits);
     __syncthreads();  // LDS is reused by the next bucket
@@ -2057,7 +2070,7 @@ struct Ptrs {
   BucketParams *P;
   float *part;
   float *pts;
-  uint32_t *C, *T, *S, *SB, *bs_cur, *rec, *bs_rec, *heavy;
+  uint32_t *C, *T, *S, *SB, *bs_cur, *rec, *bs_rec, *heavy, *hits;
   uint4 *split;
   void *scan_tmp;
   Offsets O;
@@ -2079,6 +2092,7 @@ Ptrs pointers(const BucketArgs &a) {
   p.rec = reinterpret_cast<uint32_t *>(ws + L.rec);
   p.bs_rec = reinterpret_cast<uint32_t *>(ws + L.bs_rec);
   p.heavy = reinterpret_cast<uint32_t *>(ws + L.heavy);
+  p.hits = reinterpret_cast<uint32_t *>(ws + L.hits);
   p.split = reinterpret_cast<uint4 *>(ws + L.split);
   p.scan_tmp = ws + L.scan_tmp;
   p.O.S = p.S;
@@ -2128,7 +2142,7 @@ void prepare_impl(const BucketArgs &a, hipStream_t s) {
   Ptrs p = pointers(a);
   const size_t lds = (size_t)L.max_nb * sizeof(uint32_t);
   prof::mark(s, "bucket.sample");
-  const Clear clr{a.hdr, p.T + L.nb, p.bs_cur, L.nb, a.inst_total, L.B, p.heavy};
+  const Clear clr{a.hdr, p.T + L.nb, p.bs_cur, p.hits, L.nb, a.inst_total, L.B, p.heavy};
   bk_sample_kernel<D><<<L.nsmp, kSampleThreads, 0, s>>>(p.V, p.part, p.pts, clr);
   const uint32_t grid = D >= 2 ? 1u : 0u;
   bk_plan_kernel<<<L.B, kPlanThreads, grid ? 2 * lds : 0, s>>>(p.part, p.pts, p.V, p.P, grid,
@@ -2136,7 +2150,7 @@ void prepare_impl(const BucketArgs &a, hipStream_t s) {
   count_scatter_impl<D>(a, s, a.zero, a.zero_count);
 }
 
-template <int DM1, int MODE>
+template <int DM1, int MODE, bool MARK = false>
 void sweep_impl(const BucketArgs &a, int32_t *per_update, const unsigned long long *pair_off,
                 uint32_t *cursor, uint32_t *out_u, uint32_t *out_s, unsigned long long *total,
                 hipStream_t s, const uint32_t *gate) {
@@ -2146,32 +2160,32 @@ void sweep_impl(const BucketArgs &a, int32_t *per_update, const unsigned long lo
   // it listed: two workgroups per CU (one with 1024 threads), looping
   const uint32_t hgrid = std::max<uint32_t>(1, std::min<uint32_t>(L.nb, 512));
   if (L.tune.sweep_threads == 1024) {
-    bk_sweep_kernel<DM1, MODE, kBigCap, 1024, 1024><<<L.nb, 1024, 0, s>>>(
+    bk_sweep_kernel<DM1, MODE, kBigCap, 1024, 1024, false, MARK><<<L.nb, 1024, 0, s>>>(
         p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
-        out_u, out_s, total, a.inst_total, gate, a.own, a.rows, p.heavy, p.bs_cur);
+        out_u, out_s, total, a.inst_total, gate, a.own, a.rows, p.heavy, p.hits);
     if (DM1 > 0) prof::mark(s, MODE == 2 ? "bucket.sweep.emit.heavy" : "bucket.sweep.heavy");
     if (DM1 > 0)
-      bk_heavy_sweep_kernel<DM1, MODE, kBigCap, 1024, 1024><<<(hgrid + 1) / 2, 1024, 0, s>>>(
+      bk_heavy_sweep_kernel<DM1, MODE, kBigCap, 1024, 1024, MARK><<<(hgrid + 1) / 2, 1024, 0, s>>>(
           p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
-          out_u, out_s, total, a.inst_total, gate, p.heavy, p.bs_cur);
+          out_u, out_s, total, a.inst_total, gate, p.heavy, p.hits);
   } else if (L.tune.sweep_threads == 256) {
-    bk_sweep_kernel<DM1, MODE, kCap, 256, 512><<<L.nb, 256, 0, s>>>(
+    bk_sweep_kernel<DM1, MODE, kCap, 256, 512, false, MARK><<<L.nb, 256, 0, s>>>(
         p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
-        out_u, out_s, total, a.inst_total, gate, a.own, a.rows, p.heavy, p.bs_cur);
+        out_u, out_s, total, a.inst_total, gate, a.own, a.rows, p.heavy, p.hits);
     if (DM1 > 0) prof::mark(s, MODE == 2 ? "bucket.sweep.emit.heavy" : "bucket.sweep.heavy");
     if (DM1 > 0)
-      bk_heavy_sweep_kernel<DM1, MODE, kCap, 256, 512><<<hgrid, 256, 0, s>>>(
+      bk_heavy_sweep_kernel<DM1, MODE, kCap, 256, 512, MARK><<<hgrid, 256, 0, s>>>(
           p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
-          out_u, out_s, total, a.inst_total, gate, p.heavy, p.bs_cur);
+          out_u, out_s, total, a.inst_total, gate, p.heavy, p.hits);
   } else {
-    bk_sweep_kernel<DM1, MODE, kCap, 512, 512><<<L.nb, 512, 0, s>>>(
+    bk_sweep_kernel<DM1, MODE, kCap, 512, 512, false, MARK><<<L.nb, 512, 0, s>>>(
         p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
-        out_u, out_s, total, a.inst_total, gate, a.own, a.rows, p.heavy, p.bs_cur);
+        out_u, out_s, total, a.inst_total, gate, a.own, a.rows, p.heavy, p.hits);
     if (DM1 > 0) prof::mark(s, MODE == 2 ? "bucket.sweep.emit.heavy" : "bucket.sweep.heavy");
     if (DM1 > 0)
-      bk_heavy_sweep_kernel<DM1, MODE, kCap, 512, 512><<<hgrid, 512, 0, s>>>(
+      bk_heavy_sweep_kernel<DM1, MODE, kCap, 512, 512, MARK><<<hgrid, 512, 0, s>>>(
           p.rec, p.O, p.V, p.bs_rec, L.bs_cap, L.n_total, a.hdr, per_update, pair_off, cursor,
-          out_u, out_s, total, a.inst_total, gate, p.heavy, p.bs_cur);
+          out_u, out_s, total, a.inst_total, gate, p.heavy, p.hits);
   }
 }
 
@@ -2180,7 +2194,7 @@ void build_slabs_impl(const BucketArgs &a, const SlabBuild &sb, hipStream_t s) {
   const BucketLayout &L = *a.L;
   Ptrs p = pointers(a);
   const size_t lds = (size_t)L.max_nb * sizeof(uint32_t);
-  const Clear clr{a.hdr, p.T + L.nb, p.bs_cur, L.nb, nullptr, L.B, nullptr};
+  const Clear clr{a.hdr, p.T + L.nb, p.bs_cur, nullptr, L.nb, nullptr, L.B, nullptr};
   bk_sample_kernel<D><<<L.nsmp, kSampleThreads, 0, s>>>(p.V, p.part, p.pts, clr);
   // slabs of the swept axis 0 only: resident simulations move regions by it
   bk_plan_kernel<<<L.B, kPlanThreads, 0, s>>>(p.part, p.pts, p.V, p.P, 0u, 0);
@@ -2334,6 +2348,7 @@ BucketLayout bucket_layout(const InstSpec *inst, int64_t B, int d, const BucketT
   L.rec = take((size_t)L.rec_cap * L.rec_words * sizeof(uint32_t));
   L.bs_rec = take((size_t)L.bs_cap * L.rec_words * sizeof(uint32_t));
   L.heavy = take(((size_t)L.nb_split + 2) * sizeof(uint32_t));
+  L.hits = take((size_t)std::max<uint32_t>(L.nb_split, 1) * sizeof(uint32_t));
   L.split = take((size_t)std::max<uint32_t>(L.nb, 1) * sizeof(uint4));
   L.plan = take(B > 1 ? (size_t)B * sizeof(InstPlan) : 0);
   L.maps = take(B > 1 ? ((size_t)L.nblk + L.nsmp + L.nb) * sizeof(uint32_t) : 0);
@@ -2389,7 +2404,8 @@ hipError_t bucket_split(const BucketArgs &a, hipStream_t s) {
   Ptrs p = pointers(a);
   prof::mark(s, "bucket.split");
   bk_split_kernel<<<1, kSplitThreads, 2 * (size_t)L.nb * sizeof(uint32_t), s>>>(
-      p.T, L.nb, bucket_cap(L.tune), L.nb_split, p.P, p.split, a.hdr, p.bs_cur, p.heavy, p.pts,
+      p.T, L.nb, bucket_cap(L.tune), L.nb_split, p.P, p.split, a.hdr, p.bs_cur, p.hits, p.heavy,
+      p.pts,
       L.inst[0].nsmp * (uint32_t)kSampleThreads, (uint32_t)a.d);
   return hipGetLastError();
 }
@@ -2444,11 +2460,13 @@ hipError_t bucket_sweep_slabs(const SlabSweep &w, hipStream_t s) {
 hipError_t bucket_sweep(const BucketArgs &a, int mode, int32_t *per_update,
                         const unsigned long long *pair_off, uint32_t *cursor, uint32_t *out_u,
                         uint32_t *out_s, unsigned long long *total, hipStream_t s,
-                        const uint32_t *gate) {
+                        const uint32_t *gate, bool mark) {
   prof::mark(s, mode == 2 ? "bucket.sweep.emit" : "bucket.sweep");
 #define DDM_SWEEP(DM1)                                                                     \
   if (mode == 0)                                                                           \
     sweep_impl<DM1, 0>(a, per_update, pair_off, cursor, out_u, out_s, total, s, gate);    \
+  else if (mode == 1 && mark)                                                              \
+    sweep_impl<DM1, 1, true>(a, per_update, pair_off, cursor, out_u, out_s, total, s, gate); \
   else if (mode == 1)                                                                      \
     sweep_impl<DM1, 1>(a, per_update, pair_off, cursor, out_u, out_s, total, s, gate);    \
   else                                                                                     \
