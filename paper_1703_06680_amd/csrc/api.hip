@@ -206,9 +206,9 @@ int finish_pairs(const Call &c, unsigned long long K, Emit emit, bool bucketed) 
   // offsets, and the longest row into hdr->aux[1]
   auto offsets = [&]() -> int {
     DDM_HIP(fill_u64(&c.hdr->aux[1], 0ull, 1, c.s));
-    launch_widen(c.cnt, off, (size_t)c.n, c.s, &c.hdr->aux[1]);
     prof::mark(c.s, "pairs.scan");
-    DDM_HIP(exclusive_scan_u64(off, off, (size_t)c.n, at<void>(c.ws, L.scan_tmp), c.s));
+    DDM_HIP(exclusive_scan_widen(reinterpret_cast<const uint32_t *>(c.cnt), (size_t)c.n, off,
+                                 (size_t)c.n, at<void>(c.ws, L.scan_tmp), c.s, &c.hdr->aux[1]));
     return DDM_OK;
   };
   if (c.csr_off) {

@@ -49,14 +49,6 @@ T *at(void *ws, size_t off) {
 
 // ------------------------------------------------------------- kernels
 
-// off[i] = cnt[i] for i < count, off[count] = 0 (exclusive scan input).
-__global__ void bt_widen_kernel(const int32_t *__restrict__ cnt, unsigned long long *__restrict__ off,
-                                uint32_t count) {
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= count;
-       i += gridDim.x * blockDim.x)
-    off[i] = i < count ? (unsigned long long)(uint32_t)cnt[i] : 0ull;
-}
-
 // After the scan off[n_total] is the number of pairs K.  gate[0] = K if the
 // pairs fit the capacity, else 0 (nothing is emitted); gate[1] = 1 if they do
 // not fit; gate[2] = 0, set to 1 by the row sort if a row is longer than it
@@ -416,8 +408,8 @@ int enqueue(const Batch &c, hipStream_t s) {
     uint32_t *cur = at<uint32_t>(c.ws, L.cur);
     uint32_t *ps = at<uint32_t>(c.ws, L.ps);
     prof::mark(s, "batch.pairs.scan");
-    bt_widen_kernel<<<grid_for((size_t)n_total + 1), 256, 0, s>>>(cnt, off, n_total);
-    DDM_HIP(exclusive_scan_u64(off, off, (size_t)n_total + 1, at<void>(c.ws, L.scan_tmp), s));
+    DDM_HIP(exclusive_scan_widen(reinterpret_cast<const uint32_t *>(cnt), n_total, off,
+                                 (size_t)n_total + 1, at<void>(c.ws, L.scan_tmp), s));
     bt_gate_kernel<<<grid_for((size_t)c.B + 1), 256, 0, s>>>(off, n_total, (uint64_t)c.cap, uoff,
                                                              (uint32_t)c.B, c.pair_off, gate);
     DDM_HIP(fill_u32(cur, 0u, n_total, s));

@@ -41,9 +41,6 @@ void launch_gather(const uint32_t *sidx, uint32_t count, const uint32_t *khi, co
 void launch_sweep(int mode, const SweepArgs &a, hipStream_t s);
 void launch_interleave(const uint32_t *u, const uint32_t *sidx, int32_t *out, size_t count,
                        hipStream_t s);
-// out[i] = in[i] as uint64; with max_out, also atomicMax(*max_out, max in[i]).
-void launch_widen(const int32_t *in, unsigned long long *out, size_t count, hipStream_t s,
-                  unsigned long long *max_out = nullptr);
 // Rows of at most kRowMax pairs are ordered by launch_row_sort.
 constexpr uint32_t kRowMax = 2048;
 // Orders each row u (cnt[u] subscription ids at in[off[u] ..)) by id into

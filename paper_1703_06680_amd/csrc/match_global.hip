@@ -229,22 +229,6 @@ __global__ void interleave_kernel(const uint32_t *__restrict__ u, const uint32_t
   }
 }
 
-__global__ void widen_kernel(const int32_t *__restrict__ in, unsigned long long *__restrict__ out,
-                             size_t count, unsigned long long *__restrict__ max_out) {
-  unsigned long long most = 0;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-       i += (size_t)gridDim.x * blockDim.x) {
-    const unsigned long long v = (uint32_t)in[i];
-    out[i] = v;
-    most = v > most ? v : most;
-  }
-  if (max_out) {
-    most = wave_max(most);
-    // a read first: most waves see a larger maximum already and skip the atomic
-    if (lane_id() == 0 && most > *(volatile unsigned long long *)max_out) atomicMax(max_out, most);
-  }
-}
-
 // Orders every row of an emitted pair list: row u holds the cnt[u]
 // subscription ids of update u at in[off[u] ..), in the order the sweep found
 // them.  One wave per row: the row is staged in the wave's LDS slice and
@@ -378,13 +362,6 @@ void launch_interleave(const uint32_t *u, const uint32_t *sidx, int32_t *out, si
   if (!count) return;
   prof::mark(s, "pairs.interleave");
   interleave_kernel<<<grid_for(count), kThreads, 0, s>>>(u, sidx, out, count);
-}
-
-void launch_widen(const int32_t *in, unsigned long long *out, size_t count, hipStream_t s,
-                  unsigned long long *max_out) {
-  if (!count) return;
-  prof::mark(s, "pairs.widen");
-  widen_kernel<<<grid_for(count), kThreads, 0, s>>>(in, out, count, max_out);
 }
 
 void launch_row_sort(const unsigned long long *off, const int32_t *cnt, const uint32_t *in,

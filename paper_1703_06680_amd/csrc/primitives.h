@@ -16,6 +16,13 @@ hipError_t exclusive_scan_u32(const uint32_t *in, uint32_t *out, size_t count, v
                               hipStream_t s);
 hipError_t exclusive_scan_u64(const unsigned long long *in, unsigned long long *out,
                               size_t count, void *temp, hipStream_t s);
+// The same over count 32-bit inputs (zero past the end) into out_count
+// (count or count + 1) 64-bit outputs, without a separate widening pass; with
+// max_out (cleared beforehand), the largest input is folded into it.  temp
+// holds scan_temp_bytes(out_count) bytes.
+hipError_t exclusive_scan_widen(const uint32_t *in, size_t count, unsigned long long *out,
+                                size_t out_count, void *temp, hipStream_t s,
+                                unsigned long long *max_out = nullptr);
 
 // out[i] = value for i < count, by a kernel (so that it may be recorded into a
 // graph, unlike a memset node).

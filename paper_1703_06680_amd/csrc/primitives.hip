@@ -29,22 +29,34 @@ __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_
 
 // ------------------------------------------------------------------- scans
 
-template <typename T>
-__global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const T *__restrict__ in,
+// Inputs of type TI (count of them; zero past the end) summed as TO; with
+// max_out, the largest input is also folded into *max_out (atomic maximum).
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const TI *__restrict__ in,
                                                                    size_t count,
-                                                                   T *__restrict__ block_sums) {
-  __shared__ T part[kScanThreads / kWave];
+                                                                   TO *__restrict__ block_sums,
+                                                                   TO *__restrict__ max_out) {
+  __shared__ TO part[kScanThreads / kWave];
   const size_t base = (size_t)blockIdx.x * kScanChunk;
-  T acc = 0;
+  TO acc = 0, most = 0;
   for (int i = 0; i < kScanItems; ++i) {
     size_t idx = base + (size_t)i * kScanThreads + threadIdx.x;
-    if (idx < count) acc += in[idx];
+    if (idx < count) {
+      const TO v = (TO)in[idx];
+      acc += v;
+      most = v > most ? v : most;
+    }
   }
   acc = wave_sum(acc);
   if (lane_id() == 0) part[threadIdx.x / kWave] = acc;
+  if (max_out) {
+    most = wave_max(most);
+    // a read first: most waves see a larger maximum already and skip the atomic
+    if (lane_id() == 0 && most > *(volatile TO *)max_out) atomicMax(max_out, most);
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    T t = 0;
+    TO t = 0;
     for (int w = 0; w < kScanThreads / kWave; ++w) t += part[w];
     block_sums[blockIdx.x] = t;
   }
@@ -68,16 +80,20 @@ __global__ __launch_bounds__(kScanThreads) void scan_block_sums_kernel(T *__rest
 
 __device__ __forceinline__ int padded(int i) { return i + (i >> 5); }
 
-template <typename T>
-__global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const T *in, T *out, size_t count,
-                                                                  const T *__restrict__ block_sums) {
+// Inputs TI[count_in] (zero past the end), exclusive prefix written as
+// TO[count_out].
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const TI *in, TO *out,
+                                                                  size_t count_in, size_t count_out,
+                                                                  const TO *__restrict__ block_sums) {
+  using T = TO;
   __shared__ T tile[kScanChunk + kScanChunk / 32];
   __shared__ T lds[kScanThreads / kWave + 1];
   const size_t base = (size_t)blockIdx.x * kScanChunk;
   for (int i = 0; i < kScanItems; ++i) {
     int j = i * kScanThreads + threadIdx.x;
     size_t idx = base + j;
-    tile[padded(j)] = idx < count ? in[idx] : T(0);
+    tile[padded(j)] = idx < count_in ? (T)in[idx] : T(0);
   }
   __syncthreads();
   T loc[kScanItems];
@@ -96,7 +112,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const T *in, T
   for (int i = 0; i < kScanItems; ++i) {
     int j = i * kScanThreads + threadIdx.x;
     size_t idx = base + j;
-    if (idx < count) out[idx] = tile[padded(j)];
+    if (idx < count_out) out[idx] = tile[padded(j)];
   }
 }
 
@@ -109,41 +125,54 @@ constexpr int kSmallScanThreads = 1024;
 constexpr int kSmallItems = 16;
 constexpr size_t kSmallScan = (size_t)kSmallItems * kSmallScanThreads;
 
-template <typename T>
-__global__ __launch_bounds__(kSmallScanThreads) void scan_small_kernel(const T *in, T *out,
-                                                                       uint32_t count) {
-  __shared__ T lds[kSmallScanThreads / kWave + 1];
-  const uint32_t per = (count + kSmallScanThreads - 1) / kSmallScanThreads;
-  const uint32_t b0 = min(count, threadIdx.x * per);
-  T v[kSmallItems], sum = 0;
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kSmallScanThreads) void scan_small_kernel(const TI *in, TO *out,
+                                                                       uint32_t count_in,
+                                                                       uint32_t count_out,
+                                                                       TO *max_out) {
+  __shared__ TO lds[kSmallScanThreads / kWave + 1];
+  const uint32_t per = (count_out + kSmallScanThreads - 1) / kSmallScanThreads;
+  const uint32_t b0 = min(count_out, threadIdx.x * per);
+  TO v[kSmallItems], sum = 0, most = 0;
 #pragma unroll
   for (int q = 0; q < kSmallItems; ++q) {
     const uint32_t i = b0 + (uint32_t)q;
-    v[q] = (uint32_t)q < per && i < count ? in[i] : T(0);
+    v[q] = (uint32_t)q < per && i < count_in ? (TO)in[i] : TO(0);
     sum += v[q];
+    most = v[q] > most ? v[q] : most;
   }
-  T total;
-  T run = block_exclusive_scan<T, kSmallScanThreads>(sum, lds, &total);
+  TO total;
+  TO run = block_exclusive_scan<TO, kSmallScanThreads>(sum, lds, &total);
 #pragma unroll
   for (int q = 0; q < kSmallItems; ++q) {
     const uint32_t i = b0 + (uint32_t)q;
-    if ((uint32_t)q < per && i < count) out[i] = run;
+    if ((uint32_t)q < per && i < count_out) out[i] = run;
     run += v[q];
+  }
+  if (max_out) {
+    most = wave_max(most);
+    if (lane_id() == 0 && most > *(volatile TO *)max_out) atomicMax(max_out, most);
   }
 }
 
-template <typename T>
-hipError_t exclusive_scan_impl(const T *in, T *out, size_t count, void *temp, hipStream_t s) {
-  if (count == 0) return hipSuccess;
-  if (count <= kSmallScan) {
-    scan_small_kernel<T><<<dim3(1), dim3(kSmallScanThreads), 0, s>>>(in, out, (uint32_t)count);
+// Exclusive prefix of count_in inputs (zero past the end) into count_out
+// outputs, summed in TO; the largest input into *max_out if given.
+template <typename TI, typename TO>
+hipError_t exclusive_scan_impl(const TI *in, size_t count_in, TO *out, size_t count_out,
+                               void *temp, hipStream_t s, TO *max_out = nullptr) {
+  if (count_out == 0) return hipSuccess;
+  if (count_out <= kSmallScan) {
+    scan_small_kernel<TI, TO><<<dim3(1), dim3(kSmallScanThreads), 0, s>>>(
+        in, out, (uint32_t)count_in, (uint32_t)count_out, max_out);
     return hipGetLastError();
   }
-  size_t nb = div_up(count, kScanChunk);
-  T *sums = static_cast<T *>(temp);
-  scan_reduce_kernel<T><<<dim3((unsigned)nb), dim3(kScanThreads), 0, s>>>(in, count, sums);
-  scan_block_sums_kernel<T><<<dim3(1), dim3(kScanThreads), 0, s>>>(sums, nb);
-  scan_apply_kernel<T><<<dim3((unsigned)nb), dim3(kScanThreads), 0, s>>>(in, out, count, sums);
+  size_t nb = div_up(count_out, kScanChunk);
+  TO *sums = static_cast<TO *>(temp);
+  scan_reduce_kernel<TI, TO><<<dim3((unsigned)nb), dim3(kScanThreads), 0, s>>>(in, count_in, sums,
+                                                                               max_out);
+  scan_block_sums_kernel<TO><<<dim3(1), dim3(kScanThreads), 0, s>>>(sums, nb);
+  scan_apply_kernel<TI, TO><<<dim3((unsigned)nb), dim3(kScanThreads), 0, s>>>(
+      in, out, count_in, count_out, sums);
   return hipGetLastError();
 }
 
@@ -284,12 +313,20 @@ size_t scan_temp_bytes(size_t count) {
 
 hipError_t exclusive_scan_u32(const uint32_t *in, uint32_t *out, size_t count, void *temp,
                               hipStream_t s) {
-  return exclusive_scan_impl<uint32_t>(in, out, count, temp, s);
+  return exclusive_scan_impl<uint32_t, uint32_t>(in, count, out, count, temp, s);
 }
 
 hipError_t exclusive_scan_u64(const unsigned long long *in, unsigned long long *out, size_t count,
                               void *temp, hipStream_t s) {
-  return exclusive_scan_impl<unsigned long long>(in, out, count, temp, s);
+  return exclusive_scan_impl<unsigned long long, unsigned long long>(in, count, out, count, temp,
+                                                                     s);
+}
+
+hipError_t exclusive_scan_widen(const uint32_t *in, size_t count, unsigned long long *out,
+                                size_t out_count, void *temp, hipStream_t s,
+                                unsigned long long *max_out) {
+  return exclusive_scan_impl<uint32_t, unsigned long long>(in, count, out, out_count, temp, s,
+                                                           max_out);
 }
 
 size_t radix_sort_temp_bytes(uint32_t count) {
