@@ -1516,22 +1516,20 @@ __device__ __forceinline__ void emit_rows(
       if (hit && at < kRowStage) stage[at] = sid;
       L += (uint32_t)__popcll(m);
     };
+    // every lane reads (lanes past the end read the last entry and are
+    // masked off), so that the reads of a chunk go out together and nothing
+    // branches
     for (uint32_t j = j0; j < j1; j += kWave) {
-      const uint32_t jj = j + (uint32_t)lane;
-      bool hit = false;
-      uint32_t sid = 0;
-      if (jj < j1) {
-        const uint32_t k = KLO[jj];
-        hit = k < hu && (k >= ku || KHI[jj] > ku);
-        sid = RID[jj] - n;
-      }
-      append(hit, sid);
+      const uint32_t jj = min(j + (uint32_t)lane, j1 - 1u);
+      const uint32_t k = KLO[jj], kh = KHI[jj], r = RID[jj];
+      append(j + (uint32_t)lane < j1 && k < hu && (k >= ku || kh > ku), r - n);
     }
-    // boundary-state subscriptions reach only the start of the bucket
+    // boundary-state subscriptions reach only the start of the bucket (they
+    // start in an earlier one)
     for (uint32_t i = 0; ku < reach && i < nsb; i += kWave) {
-      const uint32_t ii = i + (uint32_t)lane;
-      const bool hit = ii < nsb && BSH[ii] > ku;  // it starts in an earlier bucket
-      append(hit, hit ? BSR[ii] - n : 0u);
+      const uint32_t ii = min(i + (uint32_t)lane, nsb - 1u);
+      const uint32_t bh = BSH[ii], br = BSR[ii];
+      append(i + (uint32_t)lane < nsb && bh > ku, br - n);
     }
     if (L == 0) continue;
     if (L > kRowStage || L > (uint32_t)cnt_u) {  // uniform over the wave; never expected
