@@ -344,6 +344,8 @@ def bench_resident(args, ddm, W, torch, np):
     exact = exact and all(torch.equal(a, b) for a, b in zip(state, full))
     info = res.info()
     res.close()
+    del full, state
+    degraded = _resident_burst(ddm, torch, g, side, seed, ws)
     step_ms = phases.get("resident.step")
     # algorithmic bytes of the step kernels per region: read its index and
     # lower corner (4 + 4d), write both corners and the 16-byte sweep record
@@ -362,6 +364,48 @@ def bench_resident(args, ddm, W, torch, np):
         "buckets": info["buckets"],
         "full_matches": info["full_matches"],
         "exact": bool(exact),
+        "burst": degraded,
+    }
+
+
+def _resident_burst(ddm, torch, g, side, seed, ws, steps=5, warmup=2):
+    """The same simulation in a lasting burst: a random walk whose sigma
+    (1e4) is about 65 slab widths, so that most regions leave their slab at
+    every step, the mover list and the boundary state overflow and the steps
+    run in full-match mode (the walk, then the full count).  Its step time
+    against sim_step + ddm_match at the same sigma, counts compared."""
+    sigma = 1.0e4
+    full = [x.clone() for x in g]
+    res = ddm.Resident(*g, side, sigma, seed)
+    got, want = [], []
+    for st in range(1, warmup + 1):
+        got.append(res.step(st))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for st in range(warmup + 1, warmup + steps + 1):
+        got.append(res.step(st))
+    t_res = (time.perf_counter() - t0) / steps
+    info = res.info()
+    res.close()
+    for st in range(1, warmup + 1):
+        ddm.sim_step(*full, side, sigma, seed, st)
+        want.append(ddm.match_into(*full, "count", ws))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for st in range(warmup + 1, warmup + steps + 1):
+        ddm.sim_step(*full, side, sigma, seed, st)
+        want.append(ddm.match_into(*full, "count", ws))
+    t_full = (time.perf_counter() - t0) / steps
+    del full
+    return {
+        "sigma": sigma,
+        "steps": steps,
+        "ms_per_step": round(1e3 * t_res, 4),
+        "full_ms_per_step": round(1e3 * t_full, 4),
+        "full_mode": info["full_mode"],
+        "full_matches": info["full_matches"],
+        "rebuilds": info["rebuilds"],
+        "exact": got == want,
     }
 
 
