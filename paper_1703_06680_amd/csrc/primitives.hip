@@ -117,38 +117,55 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const TI *in, 
 }
 
 // Arrays of at most kSmallScan elements are scanned by one workgroup in one
-// launch: thread t owns a run of at most kSmallItems consecutive elements,
-// loads it into registers at once, takes its offset from a workgroup scan of
-// the run sums and writes the run (every element is read before any is
-// written, so out may alias in).
+// launch.  The array passes through LDS so that every device read and write
+// is coalesced (consecutive lanes, consecutive elements): it is loaded
+// whole, thread t then scans a run of at most kSmallItems consecutive
+// elements in LDS, offset by a workgroup scan of the run sums, and the
+// result is stored whole.  Every element is read before any is written, so
+// out may alias in.  LDS: small_scan_lds(count_out, sizeof(TO)) bytes.
 constexpr int kSmallScanThreads = 1024;
 constexpr int kSmallItems = 16;
 constexpr size_t kSmallScan = (size_t)kSmallItems * kSmallScanThreads;
+
+// one pad element per 32, so that the runs of consecutive threads (a
+// stride of up to 16 elements) fall in different banks
+__device__ __forceinline__ uint32_t small_pad(uint32_t i) { return i + (i >> 5); }
+inline size_t small_scan_lds(size_t count, size_t elem) { return (count + (count >> 5) + 1) * elem; }
 
 template <typename TI, typename TO>
 __global__ __launch_bounds__(kSmallScanThreads) void scan_small_kernel(const TI *in, TO *out,
                                                                        uint32_t count_in,
                                                                        uint32_t count_out,
                                                                        TO *max_out) {
+  extern __shared__ __align__(16) unsigned char small_smem[];
+  TO *tile = reinterpret_cast<TO *>(small_smem);
   __shared__ TO lds[kSmallScanThreads / kWave + 1];
+  TO most = 0;
+  for (uint32_t i = threadIdx.x; i < count_out; i += kSmallScanThreads) {
+    const TO x = i < count_in ? (TO)in[i] : TO(0);
+    tile[small_pad(i)] = x;
+    most = x > most ? x : most;
+  }
+  __syncthreads();
   const uint32_t per = (count_out + kSmallScanThreads - 1) / kSmallScanThreads;
   const uint32_t b0 = min(count_out, threadIdx.x * per);
-  TO v[kSmallItems], sum = 0, most = 0;
+  TO v[kSmallItems], sum = 0;
 #pragma unroll
   for (int q = 0; q < kSmallItems; ++q) {
     const uint32_t i = b0 + (uint32_t)q;
-    v[q] = (uint32_t)q < per && i < count_in ? (TO)in[i] : TO(0);
+    v[q] = (uint32_t)q < per && i < count_out ? tile[small_pad(i)] : TO(0);
     sum += v[q];
-    most = v[q] > most ? v[q] : most;
   }
   TO total;
   TO run = block_exclusive_scan<TO, kSmallScanThreads>(sum, lds, &total);
 #pragma unroll
   for (int q = 0; q < kSmallItems; ++q) {
     const uint32_t i = b0 + (uint32_t)q;
-    if ((uint32_t)q < per && i < count_out) out[i] = run;
+    if ((uint32_t)q < per && i < count_out) tile[small_pad(i)] = run;
     run += v[q];
   }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < count_out; i += kSmallScanThreads) out[i] = tile[small_pad(i)];
   if (max_out) {
     most = wave_max(most);
     if (lane_id() == 0 && most > *(volatile TO *)max_out) atomicMax(max_out, most);
@@ -162,8 +179,9 @@ hipError_t exclusive_scan_impl(const TI *in, size_t count_in, TO *out, size_t co
                                void *temp, hipStream_t s, TO *max_out = nullptr) {
   if (count_out == 0) return hipSuccess;
   if (count_out <= kSmallScan) {
-    scan_small_kernel<TI, TO><<<dim3(1), dim3(kSmallScanThreads), 0, s>>>(
-        in, out, (uint32_t)count_in, (uint32_t)count_out, max_out);
+    scan_small_kernel<TI, TO>
+        <<<dim3(1), dim3(kSmallScanThreads), small_scan_lds(count_out, sizeof(TO)), s>>>(
+            in, out, (uint32_t)count_in, (uint32_t)count_out, max_out);
     return hipGetLastError();
   }
   size_t nb = div_up(count_out, kScanChunk);
