@@ -63,6 +63,16 @@ __device__ __forceinline__ uint32_t split_of(float x, uint32_t a, const uint4 *_
   return r.x + (uint32_t)t;
 }
 
+// A device pointer as a pointer into the global address space.  Row
+// pointers reach the kernels inside structures, where the compiler cannot
+// tell their address space and reads them with generic (flat) loads, which
+// also count against the LDS counter: every wait for an LDS result (the
+// cursor atomics of the scatter, say) would then wait for the rows in flight.
+template <typename T>
+__device__ __forceinline__ const T __attribute__((address_space(1))) *global_ptr(const T *p) {
+  return (const T __attribute__((address_space(1))) *)p;
+}
+
 template <int D>
 struct Box {
   float lo[D];

@@ -580,12 +580,13 @@ __device__ __forceinline__ Group group_of(uint32_t g, const InstPlan &I, uint32_
 template <int D>
 __device__ __forceinline__ void load_group(const Group &q, bool vec, Box<D> (&bx)[4]) {
   if (vec && q.rows == 4) {
-    const float4 *l4 = reinterpret_cast<const float4 *>(q.lo + (size_t)q.row0 * D);
-    const float4 *h4 = reinterpret_cast<const float4 *>(q.hi + (size_t)q.row0 * D);
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    const auto *l4 = global_ptr(reinterpret_cast<const v4f *>(q.lo + (size_t)q.row0 * D));
+    const auto *h4 = global_ptr(reinterpret_cast<const v4f *>(q.hi + (size_t)q.row0 * D));
     float lf[4 * D], hf[4 * D];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      const float4 a = l4[i], b = h4[i];
+      const v4f a = l4[i], b = h4[i];
       lf[4 * i] = a.x;
       lf[4 * i + 1] = a.y;
       lf[4 * i + 2] = a.z;
@@ -608,8 +609,8 @@ __device__ __forceinline__ void load_group(const Group &q, bool vec, Box<D> (&bx
 #pragma unroll
       for (int k = 0; k < D; ++k) {
         const bool ok = (uint32_t)r < q.rows;
-        bx[r].lo[k] = ok ? q.lo[(size_t)(q.row0 + r) * D + k] : 0.f;
-        bx[r].hi[k] = ok ? q.hi[(size_t)(q.row0 + r) * D + k] : 1.f;
+        bx[r].lo[k] = ok ? global_ptr(q.lo)[(size_t)(q.row0 + r) * D + k] : 0.f;
+        bx[r].hi[k] = ok ? global_ptr(q.hi)[(size_t)(q.row0 + r) * D + k] : 1.f;
       }
   }
 }
@@ -809,7 +810,7 @@ __global__ __launch_bounds__(kThreads) void bk_scatter_kernel(
 // Scatter with record pairs.  Random 16-byte stores are bound by their
 // number, so two records of one bucket in the same aligned 32 bytes of the
 // output are written together by one thread.  Records take their slots as
-// in bk_scatter_kernel, kPairGroups groups per thread per round.  A record
+// in bk_scatter_kernel, one group per thread per round.  A record
 // in an even slot s offers itself in its bucket's LDS mailbox (a tag, the
 // pair index s / 2, claimed by compare-and-swap, and the record; a busy
 // mailbox makes it a single store); after a barrier, the record in odd slot
@@ -819,7 +820,6 @@ __global__ __launch_bounds__(kThreads) void bk_scatter_kernel(
 // alone.  Every record is written exactly once.  LDS: 24 bytes per bucket.
 constexpr uint32_t kTagFree = 0xFFFFFFFFu;
 constexpr uint32_t kPairScatterMaxBuckets = 6656;
-constexpr int kPairGroups = 2;
 
 template <int D>
 __global__ __launch_bounds__(kThreads) void bk_scatter_pair_kernel(
@@ -842,22 +842,31 @@ __global__ __launch_bounds__(kThreads) void bk_scatter_pair_kernel(
   }
   __syncthreads();
   const uint32_t g0 = lb * I.gpb, g1 = min(I.g, g0 + I.gpb);
-  constexpr int G = D <= 3 ? kPairGroups : 1;  // wider rows: one group per round
+  // One group per thread and round; the rows of the thread's group of the
+  // next round are loaded at the start of this one, so that they are in
+  // flight while this round's records take their slots.
+  constexpr int G = 1;
   auto rounds = [&](auto mode) {
     constexpr bool GR = decltype(mode)::value;
+    Group qn = Group{};  // rows == 0: no group
+    Box<D> bn[4];
+    if (g0 + threadIdx.x < g1) {
+      qn = group_of(g0 + threadIdx.x, I, n_total);
+      load_group<D>(qn, I.vec != 0, bn);
+    }
     for (uint32_t base = g0; base < g1; base += G * kThreads) {  // uniform
       Group q[G];
       Box<D> bx[G][4];
+      q[0] = qn;
 #pragma unroll
-      for (int k = 0; k < G; ++k) {
-        const uint32_t g = base + (uint32_t)k * kThreads + threadIdx.x;
-        q[k] = Group{};
-        if (g < g1) {
-          q[k] = group_of(g, I, n_total);
-          load_group<D>(q[k], I.vec != 0, bx[k]);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) sweep_order<D>(bx[k][r], p.axis);
-        }
+      for (int r = 0; r < 4; ++r) {
+        bx[0][r] = bn[r];
+        sweep_order<D>(bx[0][r], p.axis);
+      }
+      qn = Group{};
+      if (base + kThreads + threadIdx.x < g1) {
+        qn = group_of(base + kThreads + threadIdx.x, I, n_total);
+        load_group<D>(qn, I.vec != 0, bn);
       }
       uint32_t slot[G][4];  // odd slots still to collect, else ~0u
 #pragma unroll
