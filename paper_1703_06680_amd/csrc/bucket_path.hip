@@ -645,11 +645,24 @@ __global__ __launch_bounds__(kThreads) void bk_count_kernel(
   uint32_t err = 0;
   auto count = [&](auto tag) {
     constexpr bool GR = decltype(tag)::value;
-#pragma unroll 2
-    for (uint32_t g = g0 + threadIdx.x; g < g1; g += kThreads) {
-      const Group q = group_of(g, I, n_total);
+    // the rows of a thread's next group are loaded before its current group
+    // is counted, so that they are in flight meanwhile
+    uint32_t g = g0 + threadIdx.x;
+    Group qn = Group{};
+    Box<D> bn[4];
+    if (g < g1) {
+      qn = group_of(g, I, n_total);
+      load_group<D>(qn, I.vec != 0, bn);
+    }
+    for (; g < g1; g += kThreads) {
+      const Group q = qn;
       Box<D> bx[4];
-      load_group<D>(q, I.vec != 0, bx);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) bx[r] = bn[r];
+      if (g + kThreads < g1) {
+        qn = group_of(g + kThreads, I, n_total);
+        load_group<D>(qn, I.vec != 0, bn);
+      }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         if ((uint32_t)r >= q.rows) continue;
