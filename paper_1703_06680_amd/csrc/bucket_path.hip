@@ -170,8 +170,8 @@ __device__ __forceinline__ Box<D> load_row(const float *__restrict__ lo,
   Box<D> b;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
-    b.lo[k] = lo[(size_t)row * D + k];
-    b.hi[k] = hi[(size_t)row * D + k];
+    b.lo[k] = global_ptr(lo)[(size_t)row * D + k];
+    b.hi[k] = global_ptr(hi)[(size_t)row * D + k];
   }
   return b;
 }
@@ -1174,8 +1174,8 @@ __device__ __forceinline__ void other_axes(const SweepCtx &o, uint32_t rid, floa
   const bool upd = rid < o.n;
   const size_t row = upd ? rid - o.I.u0 : rid - o.n - o.I.s0;
   const size_t D = DM1 == 3 ? (size_t)o.I.d : (size_t)(DM1 + 1);  // floats per row
-  const float *L = (upd ? o.I.ulo : o.I.slo) + row * D;
-  const float *H = (upd ? o.I.uhi : o.I.shi) + row * D;
+  const auto *L = global_ptr(upd ? o.I.ulo : o.I.slo) + row * D;
+  const auto *H = global_ptr(upd ? o.I.uhi : o.I.shi) + row * D;
 #pragma unroll
   for (int c = 0; c < kNearAxes<DM1>; ++c) {
     const uint32_t k = !PERM ? 1u + (uint32_t)c : (c == 0 ? o.k1 : o.k2);
@@ -1191,8 +1191,10 @@ __device__ __forceinline__ bool extra_axes(const SweepCtx &o, uint32_t ry, uint3
   const bool uy = ry < o.n, ux = rx < o.n;
   const size_t y = uy ? ry - o.I.u0 : ry - o.n - o.I.s0;
   const size_t x = ux ? rx - o.I.u0 : rx - o.n - o.I.s0;
-  const float *yl = (uy ? o.I.ulo : o.I.slo) + y * d, *yh = (uy ? o.I.uhi : o.I.shi) + y * d;
-  const float *xl = (ux ? o.I.ulo : o.I.slo) + x * d, *xh = (ux ? o.I.uhi : o.I.shi) + x * d;
+  const auto *yl = global_ptr(uy ? o.I.ulo : o.I.slo) + y * d;
+  const auto *yh = global_ptr(uy ? o.I.uhi : o.I.shi) + y * d;
+  const auto *xl = global_ptr(ux ? o.I.ulo : o.I.slo) + x * d;
+  const auto *xh = global_ptr(ux ? o.I.uhi : o.I.shi) + x * d;
   bool hit = true;
   for (uint32_t j = 3; j < d; ++j) {
     const uint32_t k = input_axis(j, o.axis);
