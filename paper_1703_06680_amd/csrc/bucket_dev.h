@@ -49,20 +49,6 @@ __device__ __forceinline__ uint32_t bucket_of(float x, float vmin, float scale, 
   return (uint32_t)t;
 }
 
-// The bucket of swept-axis coordinate x in column a of a split map: the
-// column's first bucket plus floor((enc(x) - z) * scale), clamped to the
-// column's buckets.  Encoding, subtraction (clamped at 0), conversion to
-// float and scaling are all non-decreasing, so the map stays monotone and
-// the columns stay consecutive segments.
-__device__ __forceinline__ uint32_t split_of(float x, uint32_t a, const uint4 *__restrict__ split) {
-  const uint4 r = split[a];
-  if (r.y <= 1u) return r.x;
-  const long long off = (long long)encode_coord(x) - (long long)r.z;
-  float t = (float)(off > 0 ? off : 0ll) * __uint_as_float(r.w);
-  t = fminf(t, (float)(r.y - 1u));
-  return r.x + (uint32_t)t;
-}
-
 // A device pointer as a pointer into the global address space.  Row
 // pointers reach the kernels inside structures, where the compiler cannot
 // tell their address space and reads them with generic (flat) loads, which
@@ -71,6 +57,21 @@ __device__ __forceinline__ uint32_t split_of(float x, uint32_t a, const uint4 *_
 template <typename T>
 __device__ __forceinline__ const T __attribute__((address_space(1))) *global_ptr(const T *p) {
   return (const T __attribute__((address_space(1))) *)p;
+}
+
+// The bucket of swept-axis coordinate x in column a of a split map: the
+// column's first bucket plus floor((enc(x) - z) * scale), clamped to the
+// column's buckets.  Encoding, subtraction (clamped at 0), conversion to
+// float and scaling are all non-decreasing, so the map stays monotone and
+// the columns stay consecutive segments.
+__device__ __forceinline__ uint32_t split_of(float x, uint32_t a, const uint4 *__restrict__ split) {
+  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  const v4u r = global_ptr(reinterpret_cast<const v4u *>(split))[a];
+  if (r.y <= 1u) return r.x;
+  const long long off = (long long)encode_coord(x) - (long long)r.z;
+  float t = (float)(off > 0 ? off : 0ll) * __uint_as_float(r.w);
+  t = fminf(t, (float)(r.y - 1u));
+  return r.x + (uint32_t)t;
 }
 
 template <int D>
