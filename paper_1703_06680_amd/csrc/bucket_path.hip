@@ -1362,39 +1362,52 @@ __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
     // interior entry gets the exact test on its staged bounds, four at a
     // time without branches; counts go to the walker (an update) or to the
     // entries' LDS counters (a subscription walking updates)
-    const uint32_t closed = o.I.closed;
-    auto exact = [&](uint32_t j) {
-      const float4 x = o.xc[j];
-      bool h = before(y.c[0], x.y, closed) && before(x.x, y.c[1], closed);
-      if (DM1 >= 2) h = h && before(y.c[2], x.w, closed) && before(x.z, y.c[3], closed);
-      return h;
-    };
-    uint32_t j = jB;
-    for (; j + 4 <= jC; j += 4) {
-      const bool h0 = exact(j), h1 = exact(j + 1), h2 = exact(j + 2), h3 = exact(j + 3);
-      const uint32_t c = (uint32_t)h0 + (uint32_t)h1 + (uint32_t)h2 + (uint32_t)h3;
-      hits += c;
-      if (MODE == 1) {
-        if (y.upd) {
-          own += c;
-        } else if (c) {
-          if (h0) atomicAdd(&o.cntl[j], 1u);
-          if (h1) atomicAdd(&o.cntl[j + 1], 1u);
-          if (h2) atomicAdd(&o.cntl[j + 2], 1u);
-          if (h3) atomicAdd(&o.cntl[j + 3], 1u);
+    // Both regions are non-empty on axes 1 and 2 (lower < upper, or <= for
+    // closed boxes), so each axis' two tests are one: the larger lower
+    // bound below the smaller upper bound.
+    auto interior = [&](auto cl) {
+      constexpr bool CL = decltype(cl)::value;
+      auto exact = [&](uint32_t j) {
+        const float4 x = o.xc[j];
+        const float a0 = fmaxf(y.c[0], x.x), b0 = fminf(y.c[1], x.y);
+        bool h = CL ? a0 <= b0 : a0 < b0;
+        if (DM1 >= 2) {
+          const float a1 = fmaxf(y.c[2], x.z), b1 = fminf(y.c[3], x.w);
+          h = h & (CL ? a1 <= b1 : a1 < b1);
+        }
+        return h;
+      };
+      uint32_t j = jB;
+      for (; j + 4 <= jC; j += 4) {
+        const bool h0 = exact(j), h1 = exact(j + 1), h2 = exact(j + 2), h3 = exact(j + 3);
+        const uint32_t c = (uint32_t)h0 + (uint32_t)h1 + (uint32_t)h2 + (uint32_t)h3;
+        hits += c;
+        if (MODE == 1) {
+          if (y.upd) {
+            own += c;
+          } else if (c) {
+            if (h0) atomicAdd(&o.cntl[j], 1u);
+            if (h1) atomicAdd(&o.cntl[j + 1], 1u);
+            if (h2) atomicAdd(&o.cntl[j + 2], 1u);
+            if (h3) atomicAdd(&o.cntl[j + 3], 1u);
+          }
         }
       }
-    }
-    for (; j < jC; ++j) {
-      if (!exact(j)) continue;
-      ++hits;
-      if (MODE == 1) {
-        if (y.upd)
-          ++own;
-        else
-          atomicAdd(&o.cntl[j], 1u);
+      for (; j < jC; ++j) {
+        if (!exact(j)) continue;
+        ++hits;
+        if (MODE == 1) {
+          if (y.upd)
+            ++own;
+          else
+            atomicAdd(&o.cntl[j], 1u);
+        }
       }
-    }
+    };
+    if (o.I.closed)  // uniform
+      interior(GridTag<true>{});
+    else
+      interior(GridTag<false>{});
   } else if (DM1 == 0) {
     if (MODE == 0) {
       hits += jC - jB;
