@@ -1041,9 +1041,14 @@ __device__ __forceinline__ float decode_coord(uint32_t k) {
   return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
 }
 
-// The strict test a < b of half-open intervals, a <= b for closed ones.
-__device__ __forceinline__ bool before(float a, float b, uint32_t closed) {
-  return a < b || (closed && a == b);
+// Whether intervals a = (al, ah) and b = (bl, bh), both non-empty, overlap:
+// the larger lower bound below the smaller upper bound (at most it, for
+// closed intervals).  For non-empty intervals this is the same as
+// al < bh and bl < ah (<= for closed ones), with one comparison on the
+// vector unit instead of four lane masks combined on the scalar unit.
+__device__ __forceinline__ bool overlap(float al, float ah, float bl, float bh, uint32_t closed) {
+  const float lo = fmaxf(al, bl), hi = fminf(ah, bh);
+  return closed ? lo <= hi : lo < hi;
 }
 
 __device__ __forceinline__ uint32_t fine_of(float x, float vmin, float fscale, int fine) {
@@ -1198,7 +1203,7 @@ __device__ __forceinline__ bool extra_axes(const SweepCtx &o, uint32_t ry, uint3
   bool hit = true;
   for (uint32_t j = 3; j < d; ++j) {
     const uint32_t k = input_axis(j, o.axis);
-    hit = hit && before(yl[k], xh[k], o.I.closed) && before(xl[k], yh[k], o.I.closed);
+    hit = hit && overlap(yl[k], yh[k], xl[k], xh[k], o.I.closed);
   }
   return hit;
 }
@@ -1212,8 +1217,8 @@ __device__ __forceinline__ void visit(const Walker<DM1> &y, bool &have_y, float 
                                       uint32_t &own, const SweepCtx &o) {
   if (KIND == kHeavySweep && DM1 > 0) {  // the exact test on staged coordinates
     const float4 x = o.xc[j];
-    bool hit = before(y.c[0], x.y, o.I.closed) && before(x.x, y.c[1], o.I.closed);
-    if (DM1 >= 2) hit = hit && before(y.c[2], x.w, o.I.closed) && before(x.z, y.c[3], o.I.closed);
+    bool hit = overlap(y.c[0], y.c[1], x.x, x.y, o.I.closed);
+    if (DM1 >= 2) hit = hit & overlap(y.c[2], y.c[3], x.z, x.w, o.I.closed);
     if (DM1 == 3 && hit) hit = extra_axes(o, y.rid, RID[j]);
     if (!hit || !in_row<GR>(o, y.c[0], x.x)) return;
     ++hits;
@@ -1252,7 +1257,7 @@ __device__ __forceinline__ void visit(const Walker<DM1> &y, bool &have_y, float 
     bool hit = true;
 #pragma unroll
     for (int c = 0; c < kNearAxes<DM1>; ++c)
-      hit = hit && before(ylo[c], xhi[c], o.I.closed) && before(xlo[c], yhi[c], o.I.closed);
+      hit = hit & overlap(ylo[c], yhi[c], xlo[c], xhi[c], o.I.closed);
     if (DM1 == 3 && hit) hit = extra_axes(o, y.rid, rx);
     if (!hit || !in_row<GR>(o, ylo[0], xlo[0])) return;
   }
@@ -1298,7 +1303,7 @@ __device__ __forceinline__ void resolve(uint32_t ry, uint32_t rx, unsigned long 
   bool hit = true;
 #pragma unroll
   for (int c = 0; c < kNearAxes<DM1>; ++c)
-    hit = hit && before(ylo[c], xhi[c], o.I.closed) && before(xlo[c], yhi[c], o.I.closed);
+    hit = hit & overlap(ylo[c], yhi[c], xlo[c], xhi[c], o.I.closed);
   if (DM1 == 3 && hit) hit = extra_axes(o, ry, rx);
   if (!hit || !in_row<GR>(o, ylo[0], xlo[0])) return;
   ++hits;
