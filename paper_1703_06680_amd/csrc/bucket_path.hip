@@ -1362,14 +1362,15 @@ __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
   }
   if (!split) {
     // first and last bin coincide: the edge loop has seen every entry
-  } else if (KIND == kHeavySweep && DM1 > 0 && DM1 <= 2 && MODE != 2 && !GR) {
+  } else if (KIND == kHeavySweep && DM1 > 0 && DM1 <= 2 && MODE != 2) {
     // heavy bucket: the quantised pre-filter passes most entries, so every
     // interior entry gets the exact test on its staged bounds, four at a
     // time without branches; counts go to the walker (an update) or to the
-    // entries' LDS counters (a subscription walking updates)
+    // entries' LDS counters (a subscription walking updates).
     // Both regions are non-empty on axes 1 and 2 (lower < upper, or <= for
     // closed boxes), so each axis' two tests are one: the larger lower
-    // bound below the smaller upper bound.
+    // bound below the smaller upper bound.  In a grid cell that larger
+    // axis-1 lower bound also decides the row the pair counts in.
     auto interior = [&](auto cl) {
       constexpr bool CL = decltype(cl)::value;
       auto exact = [&](uint32_t j) {
@@ -1380,6 +1381,7 @@ __device__ __forceinline__ void walk(const uint32_t *__restrict__ KLO,
           const float a1 = fmaxf(y.c[2], x.z), b1 = fminf(y.c[3], x.w);
           h = h & (CL ? a1 <= b1 : a1 < b1);
         }
+        if (GR) h = h & (bucket_of(a0, o.vmin1, o.scale1, o.ny) == o.row);
         return h;
       };
       uint32_t j = jB;
