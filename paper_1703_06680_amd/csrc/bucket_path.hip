@@ -2021,12 +2021,23 @@ __global__ __launch_bounds__(kSplitThreads) void bk_split_kernel(
   uint32_t run = block_exclusive_scan<uint32_t, kSplitThreads>(sum, red, &total);
   const bool ok = splittable && total <= max_nb;  // uniform
   if (ok) {
-    for (uint32_t i = t; i < sampled; i += kSplitThreads) {
-      const float x = pts[(size_t)i * d + p.axis];
-      if (x != x) continue;  // no valid box was sampled there
-      const uint32_t a = bucket_of(x, p.vmin, p.scale, p.nx);
-      atomicMin(&kmin[a], encode_coord(x));
-      atomicMax(&kmax[a], encode_coord(x));
+    // eight sampled corners per thread in flight at a time
+    constexpr uint32_t kLoads = 8;
+    for (uint32_t i0 = t; i0 < sampled; i0 += kLoads * kSplitThreads) {
+      float xs[kLoads];
+#pragma unroll
+      for (uint32_t u = 0; u < kLoads; ++u) {
+        const uint32_t i = i0 + u * kSplitThreads;
+        xs[u] = i < sampled ? pts[(size_t)i * d + p.axis] : __int_as_float(0x7fc00000);
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < kLoads; ++u) {
+        const float x = xs[u];
+        if (x != x) continue;  // no valid box was sampled there (or past the end)
+        const uint32_t a = bucket_of(x, p.vmin, p.scale, p.nx);
+        atomicMin(&kmin[a], encode_coord(x));
+        atomicMax(&kmax[a], encode_coord(x));
+      }
     }
   }
   __syncthreads();  // every total of the failed attempt has been read
