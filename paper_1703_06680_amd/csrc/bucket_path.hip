@@ -2030,13 +2030,31 @@ __global__ __launch_bounds__(kSplitThreads) void bk_split_kernel(
         const uint32_t i = i0 + u * kSplitThreads;
         xs[u] = i < sampled ? pts[(size_t)i * d + p.axis] : __int_as_float(0x7fc00000);
       }
+      // a run of corners in one column (most of them, where the corners
+      // crowd into a few columns) is folded in registers before its two
+      // LDS atomics
+      uint32_t col = 0xFFFFFFFFu, lo = 0xFFFFFFFFu, hi = 0u;
 #pragma unroll
       for (uint32_t u = 0; u < kLoads; ++u) {
         const float x = xs[u];
         if (x != x) continue;  // no valid box was sampled there (or past the end)
-        const uint32_t a = bucket_of(x, p.vmin, p.scale, p.nx);
-        atomicMin(&kmin[a], encode_coord(x));
-        atomicMax(&kmax[a], encode_coord(x));
+        const uint32_t a = bucket_of(x, p.vmin, p.scale, p.nx), e = encode_coord(x);
+        if (a != col) {
+          if (col != 0xFFFFFFFFu) {
+            atomicMin(&kmin[col], lo);
+            atomicMax(&kmax[col], hi);
+          }
+          col = a;
+          lo = e;
+          hi = e;
+        } else {
+          lo = min(lo, e);
+          hi = max(hi, e);
+        }
+      }
+      if (col != 0xFFFFFFFFu) {
+        atomicMin(&kmin[col], lo);
+        atomicMax(&kmax[col], hi);
       }
     }
   }
